@@ -1,0 +1,151 @@
+"""ORACLE -- test infrastructure, not part of the product.
+
+A plain CPU statement of what the device library computes, written from the
+paper (LAGraph, arXiv 2104.01661): triangle counting (Section IV-E,
+Algorithm 6), breadth-first search (Section IV-A, Algorithms 1-2), Brandes
+betweenness centrality (Section IV-B, Algorithm 3) in ``oracle.c``, and the
+GraphBLAS masked-product / accumulate / reduce semantics of Section III
+(Table I, Table II, "Masks") as a dense brute-force reference in
+``semantics.py``.
+
+Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the device path; the only
+common dependency is the seeded input generator ``graphgen``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle (plain -O2, single-threaded)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", _SRC, "-o", tmp])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int64
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        lib = ctypes.CDLL(_SO)
+        lib.orc_build.restype = _I
+        lib.orc_build.argtypes = [_I, _I, _P, _P, _P, _P]
+        lib.orc_tc.restype = _I
+        lib.orc_tc.argtypes = [_I, _P, _P]
+        lib.orc_tc_rows.restype = _I
+        lib.orc_tc_rows.argtypes = [_I, _P, _P, _I, _I]
+        lib.orc_tc_lower_counts.restype = _I
+        lib.orc_tc_lower_counts.argtypes = [_I, _P, _P, _P, _P, _P]
+        lib.orc_bfs.restype = ctypes.c_int
+        lib.orc_bfs.argtypes = [_I, _P, _P, _I, _P, _P]
+        lib.orc_bfs_min_parent.restype = None
+        lib.orc_bfs_min_parent.argtypes = [_I, _P, _P, _I, _P, _P]
+        lib.orc_brandes.restype = ctypes.c_int
+        lib.orc_brandes.argtypes = [_I, _P, _P, _I, _P, _P]
+        _lib = lib
+    return _lib
+
+
+def _c(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data
+
+
+def build_adjacency(n: int, src, dst):
+    """Undirected adjacency from raw edge draws: both directions, no
+    self-loops, rows sorted, duplicates removed.  -> (rowptr int64[n+1],
+    colidx int32[nnz])."""
+    src, ps = _c(src, np.int32)
+    dst, pd = _c(dst, np.int32)
+    rowptr = np.empty(n + 1, dtype=np.int64)
+    colidx = np.empty(max(2 * src.size, 1), dtype=np.int32)
+    nnz = _load().orc_build(n, src.size, ps, pd, rowptr.ctypes.data, colidx.ctypes.data)
+    if nnz < 0:
+        raise MemoryError("oracle: graph build failed")
+    return rowptr, colidx[:nnz].copy()
+
+
+def from_edges(n: int, pairs):
+    """Adjacency of a small graph given as an iterable of (u, v) pairs."""
+    pairs = list(pairs)
+    src = np.array([p[0] for p in pairs], dtype=np.int32)
+    dst = np.array([p[1] for p in pairs], dtype=np.int32)
+    return build_adjacency(n, src, dst)
+
+
+def triangle_count(rowptr, colidx) -> int:
+    rowptr, pr = _c(rowptr, np.int64)
+    colidx, pc = _c(colidx, np.int32)
+    return int(_load().orc_tc(rowptr.size - 1, pr, pc))
+
+
+def triangle_count_rows(rowptr, colidx, u0: int, u1: int) -> int:
+    rowptr, pr = _c(rowptr, np.int64)
+    colidx, pc = _c(colidx, np.int32)
+    return int(_load().orc_tc_rows(rowptr.size - 1, pr, pc, u0, u1))
+
+
+def lower_counts(rowptr, colidx):
+    """C<s(L)> = L plus.pair L' entry by entry -> (Lrowptr, Lcolidx, C values)."""
+    rowptr, pr = _c(rowptr, np.int64)
+    colidx, pc = _c(colidx, np.int32)
+    n = rowptr.size - 1
+    cap = max(colidx.size // 2 + 1, 1)
+    lrp = np.empty(n + 1, dtype=np.int64)
+    lci = np.empty(cap, dtype=np.int32)
+    cnt = np.empty(cap, dtype=np.int64)
+    q = _load().orc_tc_lower_counts(n, pr, pc, lrp.ctypes.data, lci.ctypes.data, cnt.ctypes.data)
+    return lrp, lci[:q].copy(), cnt[:q].copy()
+
+
+def bfs(rowptr, colidx, source: int):
+    """FIFO-queue BFS -> (level int32[n], parent int64[n]); -1 = unreached."""
+    rowptr, pr = _c(rowptr, np.int64)
+    colidx, pc = _c(colidx, np.int32)
+    n = rowptr.size - 1
+    level = np.empty(n, dtype=np.int32)
+    parent = np.empty(n, dtype=np.int64)
+    if _load().orc_bfs(n, pr, pc, int(source), level.ctypes.data, parent.ctypes.data) != 0:
+        raise MemoryError("oracle: bfs failed")
+    return level, parent
+
+
+def bfs_min_parent(rowptr, colidx, source: int, level):
+    """Deterministic parents: smallest neighbour one level closer."""
+    rowptr, pr = _c(rowptr, np.int64)
+    colidx, pc = _c(colidx, np.int32)
+    level, pl = _c(level, np.int32)
+    parent = np.empty(rowptr.size - 1, dtype=np.int64)
+    _load().orc_bfs_min_parent(rowptr.size - 1, pr, pc, int(source), pl, parent.ctypes.data)
+    return parent
+
+
+def brandes(rowptr, colidx, sources):
+    """Unnormalised betweenness summed over `sources` (FP64)."""
+    rowptr, pr = _c(rowptr, np.int64)
+    colidx, pc = _c(colidx, np.int32)
+    srcs, ps = _c(sources, np.int64)
+    out = np.empty(rowptr.size - 1, dtype=np.float64)
+    rc = _load().orc_brandes(rowptr.size - 1, pr, pc, srcs.size, ps, out.ctypes.data)
+    if rc == -2:
+        raise OverflowError("oracle: a shortest-path count reached 2^53")
+    if rc != 0:
+        raise MemoryError("oracle: brandes failed")
+    return out

@@ -1,0 +1,256 @@
+/*
+ * ORACLE -- test infrastructure, not part of the product.
+ *
+ * A plain, slow, single-threaded CPU statement of what the device path
+ * computes, written from the paper (LAGraph, arXiv 2104.01661).  Only the
+ * test suite, the smoke check and the benchmark's CPU-baseline leg may load
+ * it.  It shares no code, header, table or helper with the device library.
+ *
+ * Every function takes an undirected graph as a sorted, duplicate-free,
+ * self-loop-free adjacency (int64 row offsets, int32 neighbour ids) that
+ * orc_build makes from raw edge draws.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------------- */
+/* Graph construction (Table IV stands in as seeded R-MAT draws): add both
+ * directions of every draw, drop self-loops, sort each row, drop
+ * duplicates.  colidx must have room for 2*m entries.  Returns nnz.       */
+/* ---------------------------------------------------------------------- */
+
+static int cmp_i32(const void *a, const void *b)
+{
+    const int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+int64_t orc_build(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                  int64_t *rowptr, int32_t *colidx)
+{
+    int64_t *fill = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    if (!fill) return -1;
+    for (int64_t e = 0; e < m; e++) {
+        if (src[e] == dst[e]) continue;
+        fill[src[e]]++;
+        fill[dst[e]]++;
+    }
+    /* raw row starts (with duplicates) */
+    int64_t total = 0;
+    for (int64_t v = 0; v < n; v++) {
+        const int64_t c = fill[v];
+        fill[v] = total;
+        total += c;
+    }
+    fill[n] = total;
+    int64_t *start = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    if (!start) { free(fill); return -1; }
+    memcpy(start, fill, sizeof(int64_t) * ((size_t)n + 1));
+    for (int64_t e = 0; e < m; e++) {
+        const int32_t u = src[e], v = dst[e];
+        if (u == v) continue;
+        colidx[fill[u]++] = v;
+        colidx[fill[v]++] = u;
+    }
+    /* sort each row and squeeze out duplicates, compacting in place */
+    int64_t out = 0;
+    rowptr[0] = 0;
+    for (int64_t v = 0; v < n; v++) {
+        int32_t *row = colidx + start[v];
+        const int64_t len = start[v + 1] - start[v];
+        qsort(row, (size_t)len, sizeof(int32_t), cmp_i32);
+        for (int64_t p = 0; p < len; p++) {
+            if (p > 0 && row[p] == row[p - 1]) continue;
+            colidx[out++] = row[p];
+        }
+        rowptr[v + 1] = out;
+    }
+    free(start);
+    free(fill);
+    return out;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Triangle counting (Section IV-E, Algorithm 6): the number of 3-cliques.
+ * Written from the definition: every triangle u < v < w is counted once,
+ * at its smallest edge (u, v), by merging the neighbours of u that come
+ * after v with the neighbours of v that come after v.  No relabelling: the
+ * count does not depend on vertex order.                                   */
+/* ---------------------------------------------------------------------- */
+
+int64_t orc_tc(int64_t n, const int64_t *rp, const int32_t *ci)
+{
+    int64_t t = 0;
+    for (int64_t u = 0; u < n; u++) {
+        for (int64_t p = rp[u]; p < rp[u + 1]; p++) {
+            const int32_t v = ci[p];
+            if (v <= u) continue;
+            /* w in N(u) with w > v: the entries after position p */
+            int64_t a = p + 1, ae = rp[u + 1];
+            /* w in N(v) with w > v */
+            int64_t b = rp[v], be = rp[v + 1];
+            while (b < be && ci[b] <= v) b++;
+            while (a < ae && b < be) {
+                if (ci[a] < ci[b]) a++;
+                else if (ci[a] > ci[b]) b++;
+                else { t++; a++; b++; }
+            }
+        }
+    }
+    return t;
+}
+
+/* Same count restricted to the rows u in [u0, u1): used to time a bounded
+ * sample of the full workload. */
+int64_t orc_tc_rows(int64_t n, const int64_t *rp, const int32_t *ci, int64_t u0, int64_t u1)
+{
+    int64_t t = 0;
+    if (u1 > n) u1 = n;
+    for (int64_t u = u0; u < u1; u++) {
+        for (int64_t p = rp[u]; p < rp[u + 1]; p++) {
+            const int32_t v = ci[p];
+            if (v <= u) continue;
+            int64_t a = p + 1, ae = rp[u + 1];
+            int64_t b = rp[v], be = rp[v + 1];
+            while (b < be && ci[b] <= v) b++;
+            while (a < ae && b < be) {
+                if (ci[a] < ci[b]) a++;
+                else if (ci[a] > ci[b]) b++;
+                else { t++; a++; b++; }
+            }
+        }
+    }
+    return t;
+}
+
+/*
+ * The masked product of Algorithm 6 before its reduction, entry by entry:
+ * L is the strictly lower part of A (row i keeps neighbours j < i), and
+ * C(i,j) = sum over k of L(i,k) pair L(j,k) = |L_i intersect L_j| for every
+ * (i,j) in L.  Outputs L's row offsets (n+1), its column ids and the counts
+ * aligned with them; lci and cnt need room for nnz(A)/2 entries.
+ */
+int64_t orc_tc_lower_counts(int64_t n, const int64_t *rp, const int32_t *ci,
+                            int64_t *lrp, int32_t *lci, int64_t *cnt)
+{
+    int64_t q = 0;
+    lrp[0] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        for (int64_t p = rp[i]; p < rp[i + 1] && ci[p] < i; p++) lci[q++] = ci[p];
+        lrp[i + 1] = q;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        for (int64_t p = lrp[i]; p < lrp[i + 1]; p++) {
+            const int32_t j = lci[p];
+            int64_t a = lrp[i], ae = lrp[i + 1], b = lrp[j], be = lrp[j + 1], c = 0;
+            while (a < ae && b < be) {
+                if (lci[a] < lci[b]) a++;
+                else if (lci[a] > lci[b]) b++;
+                else { c++; a++; b++; }
+            }
+            cnt[p] = c;
+        }
+    }
+    return q;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Breadth-first search (Section IV-A, Algorithms 1 and 2).  A FIFO queue
+ * from the source, scanning neighbours in ascending order.  level(s) = 0,
+ * parent(s) = s; the first time v is seen from u, level(v) = level(u)+1 and
+ * parent(v) = u.  Unreached vertices get -1 in both.                       */
+/* ---------------------------------------------------------------------- */
+
+int orc_bfs(int64_t n, const int64_t *rp, const int32_t *ci, int64_t s,
+            int32_t *level, int64_t *parent)
+{
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!queue) return -1;
+    for (int64_t v = 0; v < n; v++) { level[v] = -1; parent[v] = -1; }
+    int64_t head = 0, tail = 0;
+    level[s] = 0;
+    parent[s] = s;
+    queue[tail++] = (int32_t)s;
+    while (head < tail) {
+        const int32_t u = queue[head++];
+        for (int64_t p = rp[u]; p < rp[u + 1]; p++) {
+            const int32_t v = ci[p];
+            if (level[v] < 0) {
+                level[v] = level[u] + 1;
+                parent[v] = u;
+                queue[tail++] = v;
+            }
+        }
+    }
+    free(queue);
+    return 0;
+}
+
+/* The deterministic reading of the `any` monoid: given the BFS levels, the
+ * parent of a reached v != s is the smallest neighbour one level closer. */
+void orc_bfs_min_parent(int64_t n, const int64_t *rp, const int32_t *ci, int64_t s,
+                        const int32_t *level, int64_t *parent)
+{
+    for (int64_t v = 0; v < n; v++) {
+        parent[v] = -1;
+        if (level[v] < 0) continue;
+        if (v == s) { parent[v] = s; continue; }
+        for (int64_t p = rp[v]; p < rp[v + 1]; p++) {
+            if (level[ci[p]] == level[v] - 1) { parent[v] = ci[p]; break; }
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Betweenness centrality (Section IV-B, Algorithm 3): Brandes' method in
+ * FP64, one source at a time.  A BFS counts shortest paths sigma; walking
+ * the BFS order backwards, every predecessor v of w gains
+ * sigma(v)/sigma(w) * (1 + delta(w)).  centrality(w) accumulates delta(w)
+ * for every w other than the source.  Sources are summed in the order
+ * given.  Returns -2 if a path count reaches 2^53 (it would no longer be an
+ * exact integer in FP64), -1 on allocation failure.                        */
+/* ---------------------------------------------------------------------- */
+
+int orc_brandes(int64_t n, const int64_t *rp, const int32_t *ci, int64_t ns,
+                const int64_t *sources, double *centrality)
+{
+    double *sigma = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *delta = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int64_t *dist = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!sigma || !delta || !dist || !order) {
+        free(sigma); free(delta); free(dist); free(order);
+        return -1;
+    }
+    int rc = 0;
+    for (int64_t v = 0; v < n; v++) centrality[v] = 0.0;
+    for (int64_t k = 0; k < ns; k++) {
+        const int64_t s = sources[k];
+        for (int64_t v = 0; v < n; v++) { sigma[v] = 0.0; delta[v] = 0.0; dist[v] = -1; }
+        int64_t head = 0, tail = 0;
+        sigma[s] = 1.0;
+        dist[s] = 0;
+        order[tail++] = (int32_t)s;
+        while (head < tail) {
+            const int32_t u = order[head++];
+            for (int64_t p = rp[u]; p < rp[u + 1]; p++) {
+                const int32_t v = ci[p];
+                if (dist[v] < 0) { dist[v] = dist[u] + 1; order[tail++] = v; }
+                if (dist[v] == dist[u] + 1) sigma[v] += sigma[u];
+            }
+        }
+        for (int64_t i = 0; i < tail; i++)
+            if (sigma[order[i]] >= 9007199254740992.0) rc = -2;
+        for (int64_t i = tail - 1; i >= 0; i--) {
+            const int32_t w = order[i];
+            for (int64_t p = rp[w]; p < rp[w + 1]; p++) {
+                const int32_t v = ci[p];
+                if (dist[v] == dist[w] - 1) delta[v] += sigma[v] / sigma[w] * (1.0 + delta[w]);
+            }
+            if (w != s) centrality[w] += delta[w];
+        }
+    }
+    free(sigma); free(delta); free(dist); free(order);
+    return rc;
+}
