@@ -1,0 +1,343 @@
+/*
+ * lagr.h -- C ABI of a masked-semiring sparse library for one AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The library computes the operations that LAGraph (Szarnyas et al.,
+ * arXiv 2104.01661) builds its algorithms from: masked products over a
+ * semiring, C<M> accum= A (+).(x) B  (Section III, Table I: mxm, vxm, mxv),
+ * with a mask that may be valued or structural and complemented, merge or
+ * replace semantics ("Masks"), an optional accumulator, transposes through
+ * a descriptor, plus reduce, assign, eWiseAdd/eWiseMult and a strictly
+ * lower select.  On top of them sit triangle counting (Section IV-E,
+ * Algorithm 6), direction-optimising BFS (Section IV-A, Algorithms 1-2) and
+ * batched betweenness centrality (Section IV-B, Algorithm 3), a batched
+ * many-graph triangle count and a continuous-batching query server.
+ *
+ * Conventions (Section II, "Algorithm calling conventions", "Error
+ * handling"):
+ *  - Every call returns int: 0 success, > 0 warning, < 0 error.
+ *  - The last argument `msg` is a caller-owned char[LAGR_MSG_LEN] (may be
+ *    NULL).  On error or warning it holds a reason; on success it is set to
+ *    the empty string.
+ *  - Outputs come first and are passed by pointer; the library allocates
+ *    them (through the allocator registered with lagr_set_allocator).  A
+ *    NULL output pointer means the output is not wanted.
+ *  - Input/output objects are passed by value and are modified.
+ *  - Inputs are never modified.  Arrays handed to the *_wrap_* calls are
+ *    BORROWED device pointers: the caller keeps them alive and unchanged
+ *    while the object that wraps them is in use.  When an operation writes
+ *    a wrapped object it replaces the borrowed arrays with library-owned
+ *    ones and never writes or frees the caller's memory.
+ *  - Arguments are validated on the host before any device work; a failed
+ *    validation leaves every object unchanged.
+ *  - Execution is non-blocking (the GraphBLAS non-blocking mode the paper
+ *    relies on for fusion, Section VI-B): device work is queued on the
+ *    context's stream.  Results held in device objects are valid once
+ *    lagr_wait(ctx) returns or the stream is synchronised; a call whose
+ *    output is a host scalar synchronises before it returns.
+ *  - One context per host thread.  Objects may be read by several calls at
+ *    once but not written by two at once.
+ *
+ * Storage:
+ *  - lagr_matrix: compressed sparse row (CSR) -- int64 row offsets
+ *    (nrows+1), int32 column ids sorted ascending and unique in each row,
+ *    optional values (one int64 or double per entry; none for LAGR_BOOL,
+ *    whose entries all have the value 1).
+ *  - lagr_vector: SPARSE (int32 ids sorted ascending + values), BITMAP
+ *    (uint8 presence[n] + dense values[n]) or FULL (dense values, every
+ *    entry present).
+ */
+#ifndef LAGR_H
+#define LAGR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LAGR_MSG_LEN 256
+
+/* ---------------------------------------------------------------- codes */
+enum {
+    LAGR_SUCCESS = 0,
+    LAGR_NO_VALUE = 1,            /* warning: a reduction had no entry     */
+    LAGR_NULL_POINTER = -1,
+    LAGR_INVALID_VALUE = -2,
+    LAGR_INVALID_INDEX = -3,
+    LAGR_DOMAIN_MISMATCH = -4,
+    LAGR_DIMENSION_MISMATCH = -5,
+    LAGR_INVALID_OBJECT = -6,     /* lagr_graph_check found a bad matrix   */
+    LAGR_OUT_OF_MEMORY = -7,
+    LAGR_PROPERTY_MISSING = -8,   /* an Advanced-mode call lacks a cached property */
+    LAGR_NOT_IMPLEMENTED = -9,
+    LAGR_DEVICE_ERROR = -10,      /* HIP error; its text is in msg         */
+    LAGR_BUDGET_EXCEEDED = -11    /* server: query larger than the budget  */
+};
+
+/* Run an lagr call; on error jump to the user-defined LAGR_CATCH (Section
+ * II, "Error handling").  Warnings (> 0) are not errors. */
+#define LAGR_TRY(call)                         \
+    do {                                       \
+        int lagr_status_ = (call);             \
+        if (lagr_status_ < 0) {                \
+            LAGR_CATCH(lagr_status_);          \
+        }                                      \
+    } while (0)
+
+/* ---------------------------------------------------------------- enums */
+typedef enum {
+    LAGR_BOOL = 0,   /* pattern only; every present entry has the value 1 */
+    LAGR_INT64 = 1,
+    LAGR_FP64 = 2
+} lagr_type;
+
+/* The semirings of Table II that the path uses.  Result domains:
+ *   PLUS_PAIR   plus monoid, pair(x,y) = 1         -> INT64 (a count)
+ *   ANY_SECONDI any monoid,  secondi(a_ik,b_kj) = k -> INT64 (an index)
+ *   PLUS_FIRST  plus monoid, first(x,y) = x         -> the type of A'
+ *               (LAGR_BOOL A' gives INT64)
+ *   MIN_PLUS    min monoid (identity +inf), x + y   -> FP64
+ * The additive identity is never stored: an output entry exists iff at
+ * least one k has both A'(i,k) and B'(k,j).  The `any` monoid returns one
+ * admissible k; this library always returns the smallest, so results are
+ * reproducible (LAGR_DESC_DETERMINISTIC states that guarantee).  FP64 sums
+ * are taken in ascending k order, except where a call documents otherwise. */
+typedef enum {
+    LAGR_PLUS_PAIR = 0,
+    LAGR_ANY_SECONDI = 1,
+    LAGR_PLUS_FIRST = 2,
+    LAGR_MIN_PLUS = 3
+} lagr_semiring;
+
+/* Binary operators for accumulators, eWise operations and reductions.
+ * LAGR_NOOP as an accumulator means "no accumulator". FIRST(c,t)=c,
+ * SECOND(c,t)=t, ANY(c,t)=c, DIV is FP64 only. */
+typedef enum {
+    LAGR_NOOP = 0,
+    LAGR_PLUS = 1,
+    LAGR_MIN = 2,
+    LAGR_FIRST = 3,
+    LAGR_SECOND = 4,
+    LAGR_TIMES = 5,
+    LAGR_DIV = 6,
+    LAGR_ANY = 7
+} lagr_binop;
+
+/* Descriptor bits (Table I caption; Section III "Masks"). */
+#define LAGR_DESC_DEFAULT 0u
+#define LAGR_DESC_COMP 1u          /* complement the mask                  */
+#define LAGR_DESC_STRUCT 2u        /* structural mask: presence only       */
+#define LAGR_DESC_REPLACE 4u       /* delete output entries outside mask   */
+#define LAGR_DESC_TRAN0 8u         /* use the transpose of the first input */
+#define LAGR_DESC_TRAN1 16u        /* use the transpose of the second input*/
+#define LAGR_DESC_DETERMINISTIC 32u/* any monoid returns the smallest k    */
+#define LAGR_DESC_ASSIGN_PARENT 64u/* vxm only: also p<s(w)> = w (fused)   */
+#define LAGR_DESC_S (LAGR_DESC_STRUCT)
+#define LAGR_DESC_RSC (LAGR_DESC_REPLACE | LAGR_DESC_STRUCT | LAGR_DESC_COMP)
+
+typedef enum { LAGR_VEC_SPARSE = 0, LAGR_VEC_BITMAP = 1, LAGR_VEC_FULL = 2 } lagr_vformat;
+
+/* Graph kinds (Listing 1, LAGraph_Kind). */
+typedef enum { LAGR_ADJACENCY_UNDIRECTED = 0, LAGR_ADJACENCY_DIRECTED = 1 } lagr_kind;
+
+typedef struct lagr_ctx_s *lagr_ctx;
+typedef struct lagr_matrix_s *lagr_matrix;
+typedef struct lagr_vector_s *lagr_vector;
+typedef struct lagr_graph_s *lagr_graph;
+
+/* ------------------------------------------------------ memory, context */
+
+/* Device allocator used for every library-owned array and workspace
+ * (Section V, memory-manager wrappers).  alloc returns NULL on failure,
+ * which surfaces as LAGR_OUT_OF_MEMORY.  Passing NULLs restores the
+ * built-in hipMalloc/hipFree.  Must be called while no object allocated by
+ * the previous allocator is still alive. */
+typedef void *(*lagr_alloc_fn)(size_t bytes, void *user);
+typedef void (*lagr_free_fn)(void *ptr, size_t bytes, void *user);
+int lagr_set_allocator(lagr_alloc_fn alloc, lagr_free_fn release, void *user, char *msg);
+
+/* A context binds a device and a stream (a hipStream_t, NULL = the null
+ * stream) and owns a reusable workspace, so repeated calls do not allocate
+ * (the per-call allocation cost the paper blames for the high-diameter
+ * Road graph, Section VI-B). */
+int lagr_ctx_new(lagr_ctx *ctx, int device, void *stream, char *msg);
+int lagr_ctx_set_stream(lagr_ctx ctx, void *stream, char *msg);
+int lagr_ctx_free(lagr_ctx *ctx);
+/* Wait for all work queued on the context's stream. */
+int lagr_wait(lagr_ctx ctx, char *msg);
+
+/* ------------------------------------------------------------ matrices */
+
+/* An empty nrows x ncols CSR matrix of the given type. */
+int lagr_matrix_new(lagr_matrix *A, lagr_type type, int64_t nrows, int64_t ncols,
+                    lagr_ctx ctx, char *msg);
+/* Wrap caller device arrays as a CSR matrix (borrowed; see above).
+ * rowptr: int64[nrows+1], rowptr[0] = 0, rowptr[nrows] = nvals;
+ * colidx: int32[nvals]; values: int64 or double [nvals], NULL for BOOL.
+ * Sortedness is the caller's promise; lagr_graph_check verifies it. */
+int lagr_matrix_wrap_csr(lagr_matrix *A, lagr_type type, int64_t nrows, int64_t ncols,
+                         int64_t nvals, const int64_t *rowptr, const int32_t *colidx,
+                         const void *values, lagr_ctx ctx, char *msg);
+/* Matrix build from tuples (Table I, build), on the device: nedges pairs
+ * (src[e], dst[e]) of int32 device arrays.  flags: LAGR_BUILD_SYMMETRIZE
+ * adds (dst, src) for every pair, LAGR_BUILD_DROP_LOOPS drops i == j.
+ * Duplicates collapse to one entry.  The result is a LAGR_BOOL CSR. */
+#define LAGR_BUILD_SYMMETRIZE 1u
+#define LAGR_BUILD_DROP_LOOPS 2u
+int lagr_matrix_build(lagr_matrix *A, int64_t nrows, int64_t ncols, int64_t nedges,
+                      const int32_t *src, const int32_t *dst, uint32_t flags,
+                      lagr_ctx ctx, char *msg);
+int lagr_matrix_info(const lagr_matrix A, lagr_type *type, int64_t *nrows, int64_t *ncols,
+                     int64_t *nvals, char *msg);
+/* Copy A's arrays into caller device buffers of sizes nrows+1 / nvals /
+ * nvals (any pointer may be NULL to skip that array). */
+int lagr_matrix_extract_csr(const lagr_matrix A, int64_t *rowptr, int32_t *colidx,
+                            void *values, lagr_ctx ctx, char *msg);
+/* C = strictly lower part of A: entries (i, j) with j < i (Table I,
+ * select; the reading of Algorithm 6's tril as strictly lower). */
+int lagr_select_tril(lagr_matrix *C, const lagr_matrix A, lagr_ctx ctx, char *msg);
+int lagr_matrix_free(lagr_matrix *A);
+
+/* ------------------------------------------------------------- vectors */
+int lagr_vector_new(lagr_vector *v, lagr_type type, int64_t n, lagr_ctx ctx, char *msg);
+/* Borrowed wraps.  idx int32[nvals] sorted ascending; present uint8[n]
+ * (0 / 1); values int64 or double arrays (NULL for BOOL). */
+int lagr_vector_wrap_sparse(lagr_vector *v, lagr_type type, int64_t n, int64_t nvals,
+                            const int32_t *idx, const void *values, lagr_ctx ctx, char *msg);
+int lagr_vector_wrap_bitmap(lagr_vector *v, lagr_type type, int64_t n, const uint8_t *present,
+                            const void *values, lagr_ctx ctx, char *msg);
+int lagr_vector_wrap_full(lagr_vector *v, lagr_type type, int64_t n, const void *values,
+                          lagr_ctx ctx, char *msg);
+int lagr_vector_info(const lagr_vector v, lagr_type *type, int64_t *n, lagr_vformat *format,
+                     char *msg);
+/* Number of entries (Table I, nvals); synchronises. */
+int lagr_vector_nvals(int64_t *nvals, const lagr_vector v, lagr_ctx ctx, char *msg);
+int lagr_matrix_nvals(int64_t *nvals, const lagr_matrix A, lagr_ctx ctx, char *msg);
+/* Tuples of v (Table I, extractTuples) into caller device buffers of
+ * length nvals (idx ascending). */
+int lagr_vector_extract_tuples(const lagr_vector v, int32_t *idx, void *values, lagr_ctx ctx,
+                               char *msg);
+/* Dense copy: present uint8[n] (may be NULL) and values[n] (absent
+ * entries are left as `fill`, a pointer to one element of v's type, or 0
+ * when fill is NULL). */
+int lagr_vector_extract_dense(const lagr_vector v, uint8_t *present, void *values,
+                              const void *fill, lagr_ctx ctx, char *msg);
+int lagr_vector_free(lagr_vector *v);
+
+/* --------------------------------------------------- core operations */
+
+/* C<M> accum= A' (+).(x) B'   (Table I, mxm; Section III "Masks").
+ * A' = A or A^T (LAGR_DESC_TRAN0), B' = B or B^T (LAGR_DESC_TRAN1).
+ * Dimensions: A' m x k, B' k x n, C and M m x n.  M may be NULL (no mask).
+ * accum: LAGR_NOOP or a binop on C's type.  C's type must equal the
+ * semiring's result type.  C may be the same object as A, B or M; the
+ * result is computed into new storage before C is replaced.
+ * The masked dot form (mask present, not complemented, LAGR_DESC_TRAN1) is
+ * computed entry by entry on the mask's pattern; plus.pair there uses a
+ * wavefront hash intersection (Algorithm 6's C<s(L)> = L plus.pair L^T). */
+int lagr_mxm(lagr_matrix C, const lagr_matrix M, lagr_binop accum, lagr_semiring semiring,
+             const lagr_matrix A, const lagr_matrix B, uint32_t desc, lagr_ctx ctx, char *msg);
+
+/* w'<m'> accum= u' (+).(x) A'  (Table I, vxm; with LAGR_DESC_TRAN1 it is
+ * the pull form w<m> accum= A (+).(x) u of mxv).  u length m, A' m x n,
+ * w and m length n.  With LAGR_DESC_ASSIGN_PARENT, `parent` (a vector of
+ * length n, INT64) additionally receives parent<s(w)> = w after the
+ * product -- the fused vxm + assign step of BFS (Section VI-B); pass NULL
+ * otherwise. */
+int lagr_vxm(lagr_vector w, const lagr_vector m, lagr_binop accum, lagr_semiring semiring,
+             const lagr_vector u, const lagr_matrix A, uint32_t desc, lagr_vector parent,
+             lagr_ctx ctx, char *msg);
+
+/* Fused product and reduction: *s = plus-reduce of (C<M> = A' (+).(x) B'),
+ * without forming C (Section VI-B, the mxm + reduce fusion proposed for
+ * triangle counting).  The result is written to the host scalar *s (int64
+ * or double by the semiring's result type); synchronises. */
+int lagr_mxm_reduce(void *s, const lagr_matrix M, lagr_semiring semiring, const lagr_matrix A,
+                    const lagr_matrix B, uint32_t desc, lagr_ctx ctx, char *msg);
+
+/* s accum= reduce of every entry of A with `monoid` (LAGR_PLUS or
+ * LAGR_MIN) (Table I, reduce to scalar).  s is a host scalar of A's type
+ * (INT64 for BOOL).  No entry: s is left unchanged and LAGR_NO_VALUE is
+ * returned.  Entries are combined in row-major order.  Synchronises. */
+int lagr_reduce_scalar(void *s, lagr_binop accum, lagr_binop monoid, const lagr_matrix A,
+                       lagr_ctx ctx, char *msg);
+int lagr_vector_reduce_scalar(void *s, lagr_binop accum, lagr_binop monoid, const lagr_vector u,
+                              lagr_ctx ctx, char *msg);
+/* w<m> accum= row-wise reduce of A' (Table I, reduce to vector); with
+ * LAGR_DESC_TRAN0, A' = A^T, i.e. column sums.  Empty rows give no entry. */
+int lagr_reduce_rows(lagr_vector w, const lagr_vector m, lagr_binop accum, lagr_binop monoid,
+                     const lagr_matrix A, uint32_t desc, lagr_ctx ctx, char *msg);
+
+/* w<m>(:) accum= u  and  w<m>(:) accum= s  (Table I, assign; all indices). */
+int lagr_assign_vector(lagr_vector w, const lagr_vector m, lagr_binop accum, const lagr_vector u,
+                       uint32_t desc, lagr_ctx ctx, char *msg);
+int lagr_assign_scalar(lagr_vector w, const lagr_vector m, lagr_binop accum, const void *s,
+                       uint32_t desc, lagr_ctx ctx, char *msg);
+
+/* C<M> accum= A op B on the union (eWiseAdd) or intersection (eWiseMult)
+ * of the patterns (Table I). */
+int lagr_ewise_add(lagr_matrix C, const lagr_matrix M, lagr_binop accum, lagr_binop op,
+                   const lagr_matrix A, const lagr_matrix B, uint32_t desc, lagr_ctx ctx,
+                   char *msg);
+int lagr_ewise_mult(lagr_matrix C, const lagr_matrix M, lagr_binop accum, lagr_binop op,
+                    const lagr_matrix A, const lagr_matrix B, uint32_t desc, lagr_ctx ctx,
+                    char *msg);
+
+/* -------------------------------------------------------------- graphs */
+
+/* Move constructor (Listing 1, LAGraph_New): G takes ownership of *A and
+ * *A becomes NULL.  A must be square. */
+int lagr_graph_new(lagr_graph *G, lagr_matrix *A, lagr_kind kind, lagr_ctx ctx, char *msg);
+/* CheckGraph (Section V): rows sorted and unique, ids in range, and for an
+ * undirected graph a symmetric pattern.  Records ndiag (Listing 1).
+ * LAGR_INVALID_OBJECT with the reason in msg when a check fails. */
+int lagr_graph_check(lagr_graph G, lagr_ctx ctx, char *msg);
+/* Cached properties (Section V, Property_*): computed and kept in G. */
+int lagr_property_row_degree(lagr_graph G, lagr_ctx ctx, char *msg);
+/* The triangle-count operand: A relabelled by descending degree and its
+ * strictly lower part (Algorithm 6, the degree sort and L = tril(A)). */
+int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg);
+/* Read access to G->A and the cached row degree (NULL if not cached). */
+int lagr_graph_matrix(lagr_matrix *A, const lagr_graph G, char *msg);
+int lagr_graph_ndiag(int64_t *ndiag, const lagr_graph G, char *msg);
+int lagr_graph_free(lagr_graph *G);
+
+/* ---------------------------------------------------------- algorithms */
+
+/* Triangle count (Section IV-E, Algorithm 6), Basic mode: computes any
+ * missing property (requires an undirected graph with no self-loops).  The
+ * count is the fused masked plus.pair product on the degree-ordered
+ * strictly lower part, reduced without forming C.  Synchronises. */
+int lagr_tc(int64_t *ntriangles, lagr_graph G, lagr_ctx ctx, char *msg);
+/* Advanced mode (Section II, "User modes"): LAGR_PROPERTY_MISSING when
+ * lagr_property_tc_lower has not been computed; never computes it. */
+int lagr_tc_adv(int64_t *ntriangles, const lagr_graph G, lagr_ctx ctx, char *msg);
+
+/* Breadth-first search (Section IV-A, Algorithms 1-2).  Outputs (either
+ * may be NULL): level, an INT64 FULL vector (source 0, -1 unreached) and
+ * parent, an INT64 FULL vector (parent(src) = src, -1 unreached).  Each
+ * level is a fused any.secondi step under the complemented structural mask
+ * of visited vertices, written straight into parent: push over the
+ * frontier list, or pull over unvisited vertices with a frontier bitmap
+ * when the frontier's edges outweigh the unexplored ones (Beamer's
+ * heuristic).  Parents are the smallest valid parent unless
+ * LAGR_BFS_ANY_PARENT allows any valid one. */
+#define LAGR_BFS_PUSH_ONLY 1u
+#define LAGR_BFS_ANY_PARENT 2u
+int lagr_bfs(lagr_vector *level, lagr_vector *parent, const lagr_graph G, int64_t source,
+             uint32_t flags, lagr_ctx ctx, char *msg);
+
+/* Batched betweenness centrality (Section IV-B, Algorithm 3): unnormalised
+ * sum over the given sources of the dependency of every vertex, where a
+ * source contributes nothing to itself.  `sources` is a HOST int64 array;
+ * they are processed in batches of 64 (one source per wavefront lane) and
+ * the batches are summed in order.  Output: FP64 FULL vector. */
+int lagr_bc(lagr_vector *centrality, const lagr_graph G, const int64_t *sources, int32_t ns,
+            lagr_ctx ctx, char *msg);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LAGR_H */

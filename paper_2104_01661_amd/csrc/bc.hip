@@ -1,0 +1,267 @@
+// Batched betweenness centrality (Section IV-B, Algorithm 3).
+//
+// Layout: a batch holds up to 64 sources, one per wavefront lane.  Path
+// counts sigma and the backward quantity W = (1 + delta) / sigma are
+// n x 64 FP64 arrays, vertex-major (the 64 lanes of a vertex are 512
+// contiguous bytes, so a wave reads a neighbour's row in one coalesced
+// load).  The frontier S[d] of Algorithm 3 is kept as one 64-bit lane mask
+// per vertex and level (bit k = vertex is at depth d from source k); the
+// visited mask P's pattern is the per-vertex mask of lanes not yet reached.
+//
+// Forward level d (F<!s(P), r> = F plus.first A, then P += F): a wave per
+// unreached vertex v gathers, in ascending neighbour order, sigma(u, k) of
+// the neighbours u at depth d in lane k.  Path counts are integers below
+// 2^53, so the FP64 sums are exact.
+// Backward level i (Algorithm 3's backtrack, read as i = d down to 1 so the
+// deepest level contributes): for v at depth i-1 in lane k,
+//   delta(v,k) = sigma(v,k) * sum over neighbours w at depth i in lane k of
+//                W(w,k),   W(w,k) = (1 + delta(w,k)) / sigma(w,k),
+// summed in ascending neighbour order; the kernel writes W(v,k) for the
+// next level and adds the lane sum of delta(v,.) to centrality(v).  A
+// source contributes nothing to itself (depth 0 is never a target).
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_bc_init(int64_t n, uint64_t lanes,
+                                                 uint64_t *__restrict__ unvis,
+                                                 uint64_t *__restrict__ mask0)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        unvis[v] = lanes;
+        mask0[v] = 0;
+    }
+}
+
+__global__ void k_bc_sources(const int64_t *__restrict__ src, int ns, uint64_t *__restrict__ unvis,
+                             uint64_t *__restrict__ mask0, double *__restrict__ sigma)
+{
+    const int k = threadIdx.x;
+    if (k < ns) {
+        const int64_t s = src[k];
+        atomicAnd((unsigned long long *)&unvis[s], ~(1ull << k));
+        atomicOr((unsigned long long *)&mask0[s], 1ull << k);
+        sigma[s * 64 + k] = 1.0;
+    }
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t x, int src)
+{
+    const unsigned lo = __shfl((unsigned)(x & 0xffffffffu), src, 64);
+    const unsigned hi = __shfl((unsigned)(x >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// One wave per vertex; returns through `next` the level-(d+1) lane mask.
+__global__ __launch_bounds__(256) void k_bc_forward(const int64_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ ci, int64_t n,
+                                                    const uint64_t *__restrict__ cur,
+                                                    uint64_t *__restrict__ next,
+                                                    uint64_t *__restrict__ unvis,
+                                                    double *__restrict__ sigma,
+                                                    unsigned *__restrict__ any_new)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t v = wave; v < n; v += nw) {
+        const uint64_t uv = unvis[v];
+        if (uv == 0) {
+            if (lane == 0) next[v] = 0;
+            continue;
+        }
+        double acc = 0.0;
+        const int64_t b = rp[v], e = rp[v + 1];
+        for (int64_t p0 = b; p0 < e; p0 += 64) {
+            const int64_t p = p0 + lane;
+            int32_t u = 0;
+            uint64_t fm = 0;
+            if (p < e) {
+                u = ci[p];
+                fm = cur[u] & uv;
+            }
+            uint64_t hits = __ballot(fm != 0);
+            while (hits) {
+                const int t = __ffsll((unsigned long long)hits) - 1;
+                hits &= hits - 1;
+                const int32_t uu = __shfl(u, t, 64);
+                const uint64_t m = shfl64(fm, t);
+                if ((m >> lane) & 1ull) acc += sigma[(int64_t)uu * 64 + lane];
+            }
+        }
+        const uint64_t nw_mask = __ballot(acc > 0.0) & uv;
+        if ((nw_mask >> lane) & 1ull) sigma[v * 64 + lane] = acc;
+        if (lane == 0) {
+            next[v] = nw_mask;
+            if (nw_mask) {
+                unvis[v] = uv & ~nw_mask;
+                atomicOr(any_new, 1u);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bc_backward(const int64_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ ci, int64_t n,
+                                                     const uint64_t *__restrict__ at_i,   // depth i
+                                                     const uint64_t *__restrict__ at_im1, // depth i-1
+                                                     int has_deeper, int add_centrality,
+                                                     const double *__restrict__ sigma,
+                                                     double *__restrict__ W,
+                                                     double *__restrict__ centrality)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t v = wave; v < n; v += nw) {
+        const uint64_t dm = at_im1[v];
+        if (dm == 0) continue;
+        double acc = 0.0;
+        if (has_deeper) {
+            const int64_t b = rp[v], e = rp[v + 1];
+            for (int64_t p0 = b; p0 < e; p0 += 64) {
+                const int64_t p = p0 + lane;
+                int32_t w = 0;
+                uint64_t fm = 0;
+                if (p < e) {
+                    w = ci[p];
+                    fm = at_i[w] & dm;
+                }
+                uint64_t hits = __ballot(fm != 0);
+                while (hits) {
+                    const int t = __ffsll((unsigned long long)hits) - 1;
+                    hits &= hits - 1;
+                    const int32_t ww = __shfl(w, t, 64);
+                    const uint64_t m = shfl64(fm, t);
+                    if ((m >> lane) & 1ull) acc += W[(int64_t)ww * 64 + lane];
+                }
+            }
+        }
+        const bool mine = (dm >> lane) & 1ull;
+        double delta = 0.0;
+        if (mine) {
+            const double s = sigma[v * 64 + lane];
+            delta = s * acc;
+            W[v * 64 + lane] = (1.0 + delta) / s;
+        }
+        if (add_centrality) {
+            double t = delta;
+            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+            if (lane == 0) centrality[v] += t;
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const int64_t *sources,
+                       int32_t ns, lagr_ctx ctx, char *msg)
+{
+    if (!centrality_out || !G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *centrality_out = nullptr;
+    if (ns < 0 || (ns > 0 && !sources)) return lagr_fail(msg, LAGR_INVALID_VALUE, "bad sources");
+    if (G->kind != LAGR_ADJACENCY_UNDIRECTED)
+        return lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "BC needs an undirected graph (A = A^T)");
+    const lagr_matrix A = G->A;
+    const int64_t n = A->nrows;
+    for (int32_t k = 0; k < ns; k++)
+        if (sources[k] < 0 || sources[k] >= n)
+            return lagr_fail(msg, LAGR_INVALID_INDEX, "source %lld out of range", (long long)sources[k]);
+
+    double *sigma = (double *)ws_get(ctx, WS_BC_SIGMA, sizeof(double) * 64 * (size_t)(n > 0 ? n : 1));
+    double *Wv = (double *)ws_get(ctx, WS_BC_W, sizeof(double) * 64 * (size_t)(n > 0 ? n : 1));
+    uint64_t *unvis = (uint64_t *)ws_get(ctx, WS_BC_UNVIS, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *dsrc = (int64_t *)ws_get(ctx, WS_BFS_D, sizeof(int64_t) * 64 + 64);
+    if (!sigma || !Wv || !unvis || !dsrc) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc workspace");
+    unsigned *flag = (unsigned *)(dsrc + 64);
+
+    lagr_vector cv = new (std::nothrow) lagr_vector_s();
+    if (!cv) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "vector");
+    cv->type = LAGR_FP64;
+    cv->n = n;
+    cv->fmt = LAGR_VEC_FULL;
+    cv->nvals = n;
+    cv->values_bytes = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    cv->values = dev_alloc(cv->values_bytes);
+    if (!cv->values) {
+        delete cv;
+        return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "centrality");
+    }
+    double *cent = (double *)cv->values;
+    int rc = LAGR_SUCCESS;
+    std::vector<uint64_t *> levels;   // levels[d]: lane masks of depth d
+    auto level_buf = [&](size_t d) -> uint64_t * {
+        while (levels.size() <= d) {
+            uint64_t *p = (uint64_t *)dev_alloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+            if (!p) return nullptr;
+            levels.push_back(p);
+        }
+        return levels[d];
+    };
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(ctx->stream);
+        for (uint64_t *p : levels) dev_free(p, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+        levels.clear();
+    };
+#define BC_TRY(expr)                   \
+    do {                               \
+        rc = (expr);                   \
+        if (rc < 0) {                  \
+            cleanup();                 \
+            lagr_vector_free(&cv);     \
+            return rc;                 \
+        }                              \
+    } while (0)
+#define BC_LAUNCHED()                                                               \
+    do {                                                                            \
+        if (hipGetLastError() != hipSuccess)                                        \
+            BC_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bc kernel launch failed"));   \
+    } while (0)
+
+    BC_TRY(fill_i64(ctx, (int64_t *)cent, n, 0, msg));   // 0.0 has all-zero bits
+    const unsigned gblocks = grid_for(n * 64, 256, 16384);
+    for (int32_t b0 = 0; b0 < ns; b0 += 64) {
+        const int nb = (ns - b0) < 64 ? (ns - b0) : 64;
+        const uint64_t lanes = nb == 64 ? ~0ull : ((1ull << nb) - 1);
+        uint64_t *m0 = level_buf(0);
+        if (!m0) BC_TRY(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc level masks"));
+        HIP_TRY(hipMemcpyAsync(dsrc, sources + b0, sizeof(int64_t) * nb, hipMemcpyHostToDevice,
+                               ctx->stream));
+        hipLaunchKernelGGL(k_bc_init, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, n,
+                           lanes, unvis, m0);
+        BC_LAUNCHED();
+        hipLaunchKernelGGL(k_bc_sources, dim3(1), dim3(64), 0, ctx->stream, dsrc, nb, unvis, m0,
+                           sigma);
+        BC_LAUNCHED();
+        // forward sweep: depth d -> d + 1 until no lane advances
+        size_t depth = 0;
+        while (true) {
+            uint64_t *next = level_buf(depth + 1);
+            if (!next) BC_TRY(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc level masks"));
+            BC_TRY(fill_u32(ctx, flag, 1, 0u, msg));
+            hipLaunchKernelGGL(k_bc_forward, dim3(gblocks), dim3(256), 0, ctx->stream, A->rowptr,
+                               A->colidx, n, levels[depth], next, unvis, sigma, flag);
+            BC_LAUNCHED();
+            unsigned h = 0;
+            BC_TRY(read_back(ctx, &h, flag, sizeof(h), msg));
+            if (!h) break;
+            depth++;
+        }
+        // backward sweep: targets at depth i-1 gather from depth i
+        for (size_t i = depth + 1; i >= 2; i--) {
+            const int has_deeper = i <= depth ? 1 : 0;
+            hipLaunchKernelGGL(k_bc_backward, dim3(gblocks), dim3(256), 0, ctx->stream, A->rowptr,
+                               A->colidx, n, has_deeper ? levels[i] : levels[i - 1], levels[i - 1],
+                               has_deeper, 1, sigma, Wv, cent);
+            BC_LAUNCHED();
+        }
+    }
+    cleanup();
+    *centrality_out = cv;
+#undef BC_TRY
+#undef BC_LAUNCHED
+    return lagr_ok(msg);
+}

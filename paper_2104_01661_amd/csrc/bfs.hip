@@ -1,0 +1,269 @@
+// Direction-optimising parents BFS (Section IV-A, Algorithms 1 and 2).
+//
+// One level is q<!s(p), r> = q any.secondi A, fused with p<s(q)> = q (the
+// vxm + assign fusion Section VI-B describes for GAP's bfs.cc): the kernel
+// that discovers v writes its parent, its level, the next frontier list
+// and the next frontier bitmap in the same pass.
+//   push: a wavefront per frontier vertex u scans N(u) with coalesced loads;
+//         a vertex is claimed by a 32-bit CAS on its level.  The parent is
+//         the smallest frontier neighbour (atomicMin on the unsigned
+//         parent, whose "absent" value -1 is the largest), or, with
+//         LAGR_BFS_ANY_PARENT, the CAS winner.
+//   pull: one lane per unvisited vertex v scans N(v) in ascending order
+//         and stops at the first neighbour in the frontier bitmap, which is
+//         the smallest valid parent.
+// Direction (Beamer, Asanovic and Patterson, SC 2012, the heuristic the
+// paper cites): pull when the frontier's edges exceed the unexplored edges
+// / ALPHA, back to push when the frontier has fewer than n / BETA vertices.
+#include "internal.h"
+
+namespace {
+
+constexpr int BFS_ALPHA = 14;
+constexpr int BFS_BETA = 24;
+
+struct BfsCounters {
+    unsigned long long nnext;   // vertices discovered this level
+    unsigned long long enext;   // sum of their degrees
+};
+
+__device__ __forceinline__ bool bit_test(const uint32_t *bm, int64_t v)
+{
+    return (bm[v >> 5] >> (v & 31)) & 1u;
+}
+
+// `visited` holds the vertices of earlier levels only; it absorbs the
+// level's discoveries after the level, so every frontier neighbour of a
+// vertex found in this level still reaches the parent update.
+__device__ __forceinline__ void discovered(int32_t v, int64_t deg_v, int32_t *next_list,
+                                           uint32_t *next_bm, BfsCounters *cnt)
+{
+    atomicOr(&next_bm[v >> 5], 1u << (v & 31));
+    const unsigned long long slot = atomicAdd(&cnt->nnext, 1ull);
+    next_list[slot] = v;
+    atomicAdd(&cnt->enext, (unsigned long long)deg_v);
+}
+
+__global__ __launch_bounds__(256) void k_bfs_init(int64_t src, int32_t *level, int64_t *parent,
+                                                  int32_t *list, uint32_t *visited, uint32_t *bm)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        level[src] = 0;
+        parent[src] = src;
+        list[0] = (int32_t)src;
+        visited[src >> 5] |= 1u << (src & 31);
+        bm[src >> 5] |= 1u << (src & 31);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bfs_push(const int64_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci,
+                                                  const int32_t *__restrict__ frontier, int64_t nq,
+                                                  int32_t lev, int any_parent,
+                                                  int32_t *__restrict__ level,
+                                                  unsigned long long *__restrict__ parent,
+                                                  const uint32_t *__restrict__ visited,
+                                                  int32_t *__restrict__ next_list,
+                                                  uint32_t *__restrict__ next_bm,
+                                                  BfsCounters *__restrict__ cnt)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t f = wave; f < nq; f += nw) {
+        const int32_t u = frontier[f];
+        const int64_t b = rp[u], e = rp[u + 1];
+        for (int64_t p = b + lane; p < e; p += 64) {
+            const int32_t v = ci[p];
+            if (bit_test(visited, v)) continue;
+            const int32_t old = atomicCAS(&level[v], -1, lev);
+            if (old == -1) {
+                if (any_parent) parent[v] = (unsigned long long)u;
+                else atomicMin(&parent[v], (unsigned long long)u);
+                discovered(v, rp[v + 1] - rp[v], next_list, next_bm, cnt);
+            } else if (old == lev && !any_parent) {
+                atomicMin(&parent[v], (unsigned long long)u);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bfs_pull(const int64_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci, int64_t n,
+                                                  int32_t lev, const uint32_t *__restrict__ cur_bm,
+                                                  int32_t *__restrict__ level,
+                                                  int64_t *__restrict__ parent,
+                                                  const uint32_t *__restrict__ visited,
+                                                  int32_t *__restrict__ next_list,
+                                                  uint32_t *__restrict__ next_bm,
+                                                  BfsCounters *__restrict__ cnt)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        if (bit_test(visited, v)) continue;
+        const int64_t b = rp[v], e = rp[v + 1];
+        for (int64_t p = b; p < e; p++) {
+            const int32_t u = ci[p];
+            if (bit_test(cur_bm, u)) {
+                parent[v] = u;
+                level[v] = lev;
+                discovered((int32_t)v, e - b, next_list, next_bm, cnt);
+                break;
+            }
+        }
+    }
+}
+
+__global__ void k_or_into(uint32_t *__restrict__ dst, const uint32_t *__restrict__ src, int64_t W)
+{
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < W;
+         w += (int64_t)gridDim.x * blockDim.x)
+        dst[w] |= src[w];
+}
+
+__global__ void k_level_to_i64(const int32_t *__restrict__ in, int64_t *__restrict__ out, int64_t n)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        out[v] = in[v];
+}
+
+}  // namespace
+
+static int new_full_i64(lagr_vector *out, int64_t n, int64_t **values, char *msg)
+{
+    lagr_vector v = new (std::nothrow) lagr_vector_s();
+    if (!v) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "vector");
+    v->type = LAGR_INT64;
+    v->n = n;
+    v->fmt = LAGR_VEC_FULL;
+    v->nvals = n;
+    v->values_bytes = sizeof(int64_t) * (size_t)(n > 0 ? n : 1);
+    v->values = dev_alloc(v->values_bytes);
+    if (!v->values) {
+        delete v;
+        return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "vector values");
+    }
+    *values = (int64_t *)v->values;
+    *out = v;
+    return LAGR_SUCCESS;
+}
+
+extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const lagr_graph G,
+                        int64_t source, uint32_t flags, lagr_ctx ctx, char *msg)
+{
+    if (!G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    if (level_out) *level_out = nullptr;
+    if (parent_out) *parent_out = nullptr;
+    const lagr_matrix A = G->A;
+    const int64_t n = A->nrows;
+    if (source < 0 || source >= n)
+        return lagr_fail(msg, LAGR_INVALID_INDEX, "source %lld out of range", (long long)source);
+    if (G->kind != LAGR_ADJACENCY_UNDIRECTED && !(flags & LAGR_BFS_PUSH_ONLY))
+        return lagr_fail(msg, LAGR_NOT_IMPLEMENTED,
+                         "pull steps on a directed graph need its transpose; use LAGR_BFS_PUSH_ONLY");
+    const int64_t W = (n + 31) / 32;
+    int32_t *lev32 = (int32_t *)ws_get(ctx, WS_BFS_A, sizeof(int32_t) * n);
+    int32_t *lists = (int32_t *)ws_get(ctx, WS_BFS_B, sizeof(int32_t) * 2 * n);
+    uint32_t *bms = (uint32_t *)ws_get(ctx, WS_BFS_C, sizeof(uint32_t) * 3 * W);
+    BfsCounters *cnt = (BfsCounters *)ws_get(ctx, WS_BFS_D, sizeof(BfsCounters));
+    int64_t *parent_scratch = nullptr;
+    if (!parent_out) parent_scratch = (int64_t *)ws_get(ctx, WS_BFS_E, sizeof(int64_t) * n);
+    if (!lev32 || !lists || !bms || !cnt || (!parent_out && !parent_scratch))
+        return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bfs workspace");
+    lagr_vector pv = nullptr, lv = nullptr;
+    int64_t *parent = parent_scratch;
+    if (parent_out) TRY(new_full_i64(&pv, n, &parent, msg));
+    uint32_t *visited = bms, *bm_cur = bms + W, *bm_next = bms + 2 * W;
+    int32_t *list_cur = lists, *list_next = lists + n;
+
+    int rc = LAGR_SUCCESS;
+    auto cleanup = [&]() {
+        if (pv) lagr_vector_free(&pv);
+        if (lv) lagr_vector_free(&lv);
+    };
+#define BFS_TRY(expr)            \
+    do {                         \
+        rc = (expr);             \
+        if (rc < 0) {            \
+            cleanup();           \
+            return rc;           \
+        }                        \
+    } while (0)
+
+    BFS_TRY(fill_u32(ctx, (uint32_t *)lev32, n, 0xFFFFFFFFu, msg));
+    BFS_TRY(fill_i64(ctx, parent, n, -1, msg));
+    BFS_TRY(fill_u32(ctx, bms, 3 * W, 0u, msg));
+    hipLaunchKernelGGL(k_bfs_init, dim3(1), dim3(64), 0, ctx->stream, source, lev32, parent,
+                       list_cur, visited, bm_cur);
+    if (hipGetLastError() != hipSuccess) {
+        cleanup();
+        return lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs init launch");
+    }
+    const int64_t *rp = A->rowptr;
+    const int32_t *ci = A->colidx;
+    // host copies of the per-level counters drive the direction choice
+    int64_t hdeg_src = 0;
+    {
+        int64_t two[2];
+        BFS_TRY(read_back(ctx, two, rp + source, 2 * sizeof(int64_t), msg));
+        hdeg_src = two[1] - two[0];
+    }
+    int64_t nq = 1, mf = hdeg_src, mu = A->nvals - hdeg_src;
+    bool pull = false;
+    const bool push_only = (flags & LAGR_BFS_PUSH_ONLY) != 0;
+    const int any_parent = (flags & LAGR_BFS_ANY_PARENT) ? 1 : 0;
+    for (int32_t lev = 1; nq > 0 && lev < INT32_MAX; lev++) {
+        if (!push_only) {
+            if (!pull && mf > mu / BFS_ALPHA) pull = true;
+            else if (pull && nq < n / BFS_BETA) pull = false;
+        }
+        BFS_TRY(fill_i64(ctx, (int64_t *)cnt, 2, 0, msg));
+        if (pull) {
+            hipLaunchKernelGGL(k_bfs_pull, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream,
+                               rp, ci, n, lev, bm_cur, lev32, parent, visited, list_next, bm_next,
+                               cnt);
+        } else {
+            hipLaunchKernelGGL(k_bfs_push, dim3(grid_for(nq * 64, 256, 8192)), dim3(256), 0,
+                               ctx->stream, rp, ci, list_cur, nq, lev, any_parent, lev32,
+                               (unsigned long long *)parent, visited, list_next, bm_next, cnt);
+        }
+        if (hipGetLastError() != hipSuccess) {
+            cleanup();
+            return lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs level launch");
+        }
+        hipLaunchKernelGGL(k_or_into, dim3(grid_for(W, 256, 4096)), dim3(256), 0, ctx->stream,
+                           visited, bm_next, W);
+        BfsCounters h;
+        BFS_TRY(read_back(ctx, &h, cnt, sizeof(h), msg));
+        nq = (int64_t)h.nnext;
+        mf = (int64_t)h.enext;
+        mu -= mf;
+        // the consumed frontier bitmap becomes the next level's output
+        BFS_TRY(fill_u32(ctx, bm_cur, W, 0u, msg));
+        uint32_t *tb = bm_cur;
+        bm_cur = bm_next;
+        bm_next = tb;
+        int32_t *tl = list_cur;
+        list_cur = list_next;
+        list_next = tl;
+    }
+    if (level_out) {
+        int64_t *lvals = nullptr;
+        BFS_TRY(new_full_i64(&lv, n, &lvals, msg));
+        hipLaunchKernelGGL(k_level_to_i64, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream,
+                           lev32, lvals, n);
+        if (hipGetLastError() != hipSuccess) {
+            cleanup();
+            return lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs level export");
+        }
+        *level_out = lv;
+        lv = nullptr;
+    }
+    if (parent_out) {
+        *parent_out = pv;
+        pv = nullptr;
+    }
+#undef BFS_TRY
+    return lagr_ok(msg);
+}

@@ -1,0 +1,385 @@
+// Context, allocator, messages and the matrix / vector / graph objects.
+#include <new>
+
+#include "internal.h"
+
+// ------------------------------------------------------------- messages
+
+int lagr_fail(char *msg, int code, const char *fmt, ...)
+{
+    if (msg) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(msg, LAGR_MSG_LEN, fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+// ------------------------------------------------------------- allocator
+
+static lagr_alloc_fn g_alloc = nullptr;
+static lagr_free_fn g_free = nullptr;
+static void *g_user = nullptr;
+
+void *dev_alloc(size_t bytes)
+{
+    if (bytes == 0) return nullptr;
+    if (g_alloc) return g_alloc(bytes, g_user);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void dev_free(void *p, size_t bytes)
+{
+    if (!p) return;
+    if (g_free) {
+        g_free(p, bytes, g_user);
+        return;
+    }
+    (void)hipFree(p);
+}
+
+extern "C" int lagr_set_allocator(lagr_alloc_fn alloc, lagr_free_fn release, void *user, char *msg)
+{
+    if ((alloc == nullptr) != (release == nullptr))
+        return lagr_fail(msg, LAGR_NULL_POINTER, "allocator and release must both be set or both NULL");
+    g_alloc = alloc;
+    g_free = release;
+    g_user = user;
+    return lagr_ok(msg);
+}
+
+// ------------------------------------------------------------- context
+
+extern "C" int lagr_ctx_new(lagr_ctx *ctx, int device, void *stream, char *msg)
+{
+    if (!ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "ctx is NULL");
+    *ctx = nullptr;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "device %d out of range (%d devices)", device, ndev);
+    HIP_TRY(hipSetDevice(device));
+    lagr_ctx c = new (std::nothrow) lagr_ctx_s();
+    if (!c) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "context");
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    if (hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "pinned staging buffer");
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cus = prop.multiProcessorCount;
+    *ctx = c;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_ctx_set_stream(lagr_ctx ctx, void *stream, char *msg)
+{
+    if (!ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "ctx is NULL");
+    ctx->stream = (hipStream_t)stream;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_ctx_free(lagr_ctx *ctx)
+{
+    if (!ctx || !*ctx) return LAGR_SUCCESS;
+    lagr_ctx c = *ctx;
+    (void)hipStreamSynchronize(c->stream);
+    for (int s = 0; s < WS_NSLOTS; s++) dev_free(c->ws[s], c->ws_bytes[s]);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+    *ctx = nullptr;
+    return LAGR_SUCCESS;
+}
+
+extern "C" int lagr_wait(lagr_ctx ctx, char *msg)
+{
+    if (!ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return lagr_ok(msg);
+}
+
+void *ws_get(lagr_ctx ctx, WsSlot slot, size_t bytes)
+{
+    if (bytes == 0) bytes = 8;
+    if (ctx->ws_bytes[slot] >= bytes) return ctx->ws[slot];
+    if (ctx->ws[slot]) {
+        // queued work may still read the old buffer
+        (void)hipStreamSynchronize(ctx->stream);
+        dev_free(ctx->ws[slot], ctx->ws_bytes[slot]);
+        ctx->ws[slot] = nullptr;
+        ctx->ws_bytes[slot] = 0;
+    }
+    size_t grow = bytes + bytes / 8;
+    grow = (grow + 255) & ~(size_t)255;
+    void *p = dev_alloc(grow);
+    if (!p) return nullptr;
+    ctx->ws[slot] = p;
+    ctx->ws_bytes[slot] = grow;
+    return p;
+}
+
+// ------------------------------------------------------------- matrices
+
+void matrix_release_arrays(lagr_matrix A)
+{
+    if (A->rowptr_bytes) dev_free(A->rowptr, A->rowptr_bytes);
+    if (A->colidx_bytes) dev_free(A->colidx, A->colidx_bytes);
+    if (A->values_bytes) dev_free(A->values, A->values_bytes);
+    A->rowptr = nullptr;
+    A->colidx = nullptr;
+    A->values = nullptr;
+    A->rowptr_bytes = A->colidx_bytes = A->values_bytes = 0;
+    A->nvals = 0;
+}
+
+int matrix_alloc(lagr_matrix A, int64_t nvals, char *msg)
+{
+    size_t rb = sizeof(int64_t) * (size_t)(A->nrows + 1);
+    size_t cb = sizeof(int32_t) * (size_t)(nvals > 0 ? nvals : 1);
+    size_t vb = type_size(A->type) * (size_t)(nvals > 0 ? nvals : 1);
+    int64_t *rp = (int64_t *)dev_alloc(rb);
+    int32_t *ci = (int32_t *)dev_alloc(cb);
+    void *va = vb ? dev_alloc(vb) : nullptr;
+    if (!rp || !ci || (vb && !va)) {
+        dev_free(rp, rb);
+        dev_free(ci, cb);
+        dev_free(va, vb);
+        return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "matrix arrays (%lld entries)", (long long)nvals);
+    }
+    A->rowptr = rp;
+    A->colidx = ci;
+    A->values = va;
+    A->rowptr_bytes = rb;
+    A->colidx_bytes = cb;
+    A->values_bytes = vb;
+    A->nvals = nvals;
+    return LAGR_SUCCESS;
+}
+
+static int check_type(lagr_type t, char *msg)
+{
+    if (t != LAGR_BOOL && t != LAGR_INT64 && t != LAGR_FP64)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "unknown type %d", (int)t);
+    return LAGR_SUCCESS;
+}
+
+extern "C" int lagr_matrix_new(lagr_matrix *A, lagr_type type, int64_t nrows, int64_t ncols,
+                               lagr_ctx ctx, char *msg)
+{
+    if (!A || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *A = nullptr;
+    TRY(check_type(type, msg));
+    if (nrows < 0 || ncols < 0 || nrows > INT32_MAX || ncols > INT32_MAX)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "dimensions %lld x %lld out of range",
+                         (long long)nrows, (long long)ncols);
+    lagr_matrix M = new (std::nothrow) lagr_matrix_s();
+    if (!M) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "matrix");
+    M->type = type;
+    M->nrows = nrows;
+    M->ncols = ncols;
+    int rc = matrix_alloc(M, 0, msg);
+    if (rc < 0) {
+        delete M;
+        return rc;
+    }
+    rc = fill_i64(ctx, M->rowptr, nrows + 1, 0, msg);
+    if (rc < 0) {
+        matrix_release_arrays(M);
+        delete M;
+        return rc;
+    }
+    *A = M;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_matrix_wrap_csr(lagr_matrix *A, lagr_type type, int64_t nrows, int64_t ncols,
+                                    int64_t nvals, const int64_t *rowptr, const int32_t *colidx,
+                                    const void *values, lagr_ctx ctx, char *msg)
+{
+    if (!A || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *A = nullptr;
+    TRY(check_type(type, msg));
+    if (nrows < 0 || ncols < 0 || nrows > INT32_MAX || ncols > INT32_MAX || nvals < 0)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "bad sizes");
+    if (!rowptr) return lagr_fail(msg, LAGR_NULL_POINTER, "rowptr is NULL");
+    if (nvals > 0 && !colidx) return lagr_fail(msg, LAGR_NULL_POINTER, "colidx is NULL");
+    if (type != LAGR_BOOL && nvals > 0 && !values)
+        return lagr_fail(msg, LAGR_NULL_POINTER, "values are NULL for a valued type");
+    lagr_matrix M = new (std::nothrow) lagr_matrix_s();
+    if (!M) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "matrix");
+    M->type = type;
+    M->nrows = nrows;
+    M->ncols = ncols;
+    M->nvals = nvals;
+    M->rowptr = const_cast<int64_t *>(rowptr);
+    M->colidx = const_cast<int32_t *>(colidx);
+    M->values = type == LAGR_BOOL ? nullptr : const_cast<void *>(values);
+    *A = M;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_matrix_info(const lagr_matrix A, lagr_type *type, int64_t *nrows,
+                                int64_t *ncols, int64_t *nvals, char *msg)
+{
+    if (!A) return lagr_fail(msg, LAGR_NULL_POINTER, "matrix is NULL");
+    if (type) *type = A->type;
+    if (nrows) *nrows = A->nrows;
+    if (ncols) *ncols = A->ncols;
+    if (nvals) *nvals = A->nvals;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_matrix_nvals(int64_t *nvals, const lagr_matrix A, lagr_ctx ctx, char *msg)
+{
+    if (!A || !nvals) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *nvals = A->nvals;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_matrix_extract_csr(const lagr_matrix A, int64_t *rowptr, int32_t *colidx,
+                                       void *values, lagr_ctx ctx, char *msg)
+{
+    if (!A || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    if (rowptr)
+        HIP_TRY(hipMemcpyAsync(rowptr, A->rowptr, sizeof(int64_t) * (A->nrows + 1),
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    if (colidx && A->nvals)
+        HIP_TRY(hipMemcpyAsync(colidx, A->colidx, sizeof(int32_t) * A->nvals,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    if (values && A->nvals && A->type != LAGR_BOOL)
+        HIP_TRY(hipMemcpyAsync(values, A->values, 8 * A->nvals, hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_matrix_free(lagr_matrix *A)
+{
+    if (!A || !*A) return LAGR_SUCCESS;
+    matrix_release_arrays(*A);
+    delete *A;
+    *A = nullptr;
+    return LAGR_SUCCESS;
+}
+
+// --------------------------------------------------------------- vectors
+
+void vector_release_arrays(lagr_vector v)
+{
+    if (v->idx_bytes) dev_free(v->idx, v->idx_bytes);
+    if (v->present_bytes) dev_free(v->present, v->present_bytes);
+    if (v->values_bytes) dev_free(v->values, v->values_bytes);
+    v->idx = nullptr;
+    v->present = nullptr;
+    v->values = nullptr;
+    v->idx_bytes = v->present_bytes = v->values_bytes = 0;
+    v->nvals = 0;
+}
+
+extern "C" int lagr_vector_new(lagr_vector *v, lagr_type type, int64_t n, lagr_ctx ctx, char *msg)
+{
+    if (!v || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *v = nullptr;
+    TRY(check_type(type, msg));
+    if (n < 0 || n > INT32_MAX) return lagr_fail(msg, LAGR_INVALID_VALUE, "bad length");
+    lagr_vector x = new (std::nothrow) lagr_vector_s();
+    if (!x) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "vector");
+    x->type = type;
+    x->n = n;
+    x->fmt = LAGR_VEC_SPARSE;
+    x->nvals = 0;
+    *v = x;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_vector_wrap_sparse(lagr_vector *v, lagr_type type, int64_t n, int64_t nvals,
+                                       const int32_t *idx, const void *values, lagr_ctx ctx,
+                                       char *msg)
+{
+    if (!v || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *v = nullptr;
+    TRY(check_type(type, msg));
+    if (n < 0 || n > INT32_MAX || nvals < 0 || nvals > n)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "bad sizes");
+    if (nvals > 0 && !idx) return lagr_fail(msg, LAGR_NULL_POINTER, "idx is NULL");
+    if (type != LAGR_BOOL && nvals > 0 && !values)
+        return lagr_fail(msg, LAGR_NULL_POINTER, "values are NULL for a valued type");
+    lagr_vector x = new (std::nothrow) lagr_vector_s();
+    if (!x) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "vector");
+    x->type = type;
+    x->n = n;
+    x->fmt = LAGR_VEC_SPARSE;
+    x->nvals = nvals;
+    x->idx = const_cast<int32_t *>(idx);
+    x->values = type == LAGR_BOOL ? nullptr : const_cast<void *>(values);
+    *v = x;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_vector_wrap_bitmap(lagr_vector *v, lagr_type type, int64_t n,
+                                       const uint8_t *present, const void *values, lagr_ctx ctx,
+                                       char *msg)
+{
+    if (!v || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *v = nullptr;
+    TRY(check_type(type, msg));
+    if (n < 0 || n > INT32_MAX) return lagr_fail(msg, LAGR_INVALID_VALUE, "bad length");
+    if (n > 0 && !present) return lagr_fail(msg, LAGR_NULL_POINTER, "present is NULL");
+    if (type != LAGR_BOOL && n > 0 && !values)
+        return lagr_fail(msg, LAGR_NULL_POINTER, "values are NULL for a valued type");
+    lagr_vector x = new (std::nothrow) lagr_vector_s();
+    if (!x) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "vector");
+    x->type = type;
+    x->n = n;
+    x->fmt = LAGR_VEC_BITMAP;
+    x->nvals = -1;
+    x->present = const_cast<uint8_t *>(present);
+    x->values = type == LAGR_BOOL ? nullptr : const_cast<void *>(values);
+    *v = x;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_vector_wrap_full(lagr_vector *v, lagr_type type, int64_t n, const void *values,
+                                     lagr_ctx ctx, char *msg)
+{
+    if (!v || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *v = nullptr;
+    TRY(check_type(type, msg));
+    if (type == LAGR_BOOL) return lagr_fail(msg, LAGR_DOMAIN_MISMATCH, "a FULL vector needs values");
+    if (n < 0 || n > INT32_MAX) return lagr_fail(msg, LAGR_INVALID_VALUE, "bad length");
+    if (n > 0 && !values) return lagr_fail(msg, LAGR_NULL_POINTER, "values are NULL");
+    lagr_vector x = new (std::nothrow) lagr_vector_s();
+    if (!x) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "vector");
+    x->type = type;
+    x->n = n;
+    x->fmt = LAGR_VEC_FULL;
+    x->nvals = n;
+    x->values = const_cast<void *>(values);
+    *v = x;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_vector_info(const lagr_vector v, lagr_type *type, int64_t *n,
+                                lagr_vformat *format, char *msg)
+{
+    if (!v) return lagr_fail(msg, LAGR_NULL_POINTER, "vector is NULL");
+    if (type) *type = v->type;
+    if (n) *n = v->n;
+    if (format) *format = v->fmt;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_vector_free(lagr_vector *v)
+{
+    if (!v || !*v) return LAGR_SUCCESS;
+    vector_release_arrays(*v);
+    delete *v;
+    *v = nullptr;
+    return LAGR_SUCCESS;
+}

@@ -1,0 +1,490 @@
+// Matrix build from tuples, strictly lower select, the graph object with
+// its cached properties (Listing 1; Section V), and CheckGraph.
+#include <new>
+
+#include "internal.h"
+
+namespace {
+
+__global__ void k_build_keys(const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
+                             int64_t nedges, int64_t nrows, int64_t ncols, int cbits, int sym,
+                             int drop, uint64_t *__restrict__ keys, unsigned *__restrict__ err)
+{
+    const uint64_t sent = (uint64_t)nrows << cbits;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nedges;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = src[e], v = dst[e];
+        const bool ok = u >= 0 && u < nrows && v >= 0 && v < ncols &&
+                        (!sym || (v < nrows && u < ncols));
+        if (!ok) atomicOr(err, 1u);
+        const bool dead = !ok || (drop && u == v);
+        if (sym) {
+            keys[2 * e] = dead ? sent : (((uint64_t)u << cbits) | (uint64_t)v);
+            keys[2 * e + 1] = dead ? sent : (((uint64_t)v << cbits) | (uint64_t)u);
+        } else {
+            keys[e] = dead ? sent : (((uint64_t)u << cbits) | (uint64_t)v);
+        }
+    }
+}
+
+// flag[p] = 1 if sorted key p is the first copy of a live entry.
+__global__ void k_unique_flags(const uint64_t *__restrict__ keys, int64_t n, uint64_t sent,
+                               int64_t *__restrict__ flag)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x)
+        flag[p] = (keys[p] < sent && (p == 0 || keys[p] != keys[p - 1])) ? 1 : 0;
+}
+
+__global__ void k_compact_keys(const uint64_t *__restrict__ keys, int64_t n, uint64_t sent,
+                               const int64_t *__restrict__ pos, uint64_t *__restrict__ out_keys,
+                               int32_t *__restrict__ colidx, uint64_t cmask)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = keys[p];
+        if (k < sent && (p == 0 || k != keys[p - 1])) {
+            out_keys[pos[p]] = k;
+            colidx[pos[p]] = (int32_t)(k & cmask);
+        }
+    }
+}
+
+__global__ void k_keys_to_cols(const uint64_t *__restrict__ keys, int64_t n, uint64_t cmask,
+                               int32_t *__restrict__ colidx)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x)
+        colidx[p] = (int32_t)(keys[p] & cmask);
+}
+
+// ------------------------------------------------ strictly lower select
+
+__global__ void k_count_lower(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                              int64_t n, int64_t *__restrict__ cnt)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        // columns are sorted: the lower part is a prefix of the row
+        int64_t lo = rp[i], hi = rp[i + 1];
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (ci[mid] < i) lo = mid + 1;
+            else hi = mid;
+        }
+        cnt[i] = lo - rp[i];
+    }
+}
+
+__global__ void k_copy_lower(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                             const void *__restrict__ va, int64_t n,
+                             const int64_t *__restrict__ orp, int32_t *__restrict__ oci,
+                             void *__restrict__ ova)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t i = wave; i < n; i += nw) {
+        const int64_t len = orp[i + 1] - orp[i];
+        for (int64_t t = lane; t < len; t += 64) {
+            oci[orp[i] + t] = ci[rp[i] + t];
+            if (va) ((uint64_t *)ova)[orp[i] + t] = ((const uint64_t *)va)[rp[i] + t];
+        }
+    }
+}
+
+// ------------------------------------------------------- CheckGraph
+
+__global__ void k_check(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                        int64_t nrows, int64_t ncols, int want_sym,
+                        unsigned *__restrict__ err, unsigned long long *__restrict__ ndiag)
+{
+    unsigned long long diag = 0;
+    unsigned e = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nrows;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = rp[i], b = rp[i + 1];
+        if (b < a) {
+            e |= 8u;
+            continue;
+        }
+        for (int64_t p = a; p < b; p++) {
+            const int64_t j = ci[p];
+            if (j < 0 || j >= ncols) {
+                e |= 1u;
+                continue;
+            }
+            if (p > a && ci[p - 1] >= j) e |= 2u;
+            if (j == i) diag++;
+            if (want_sym) {
+                if (j >= nrows) {
+                    e |= 4u;
+                    continue;
+                }
+                int64_t lo = rp[j], hi = rp[j + 1];
+                while (lo < hi) {
+                    int64_t mid = (lo + hi) >> 1;
+                    if (ci[mid] < i) lo = mid + 1;
+                    else hi = mid;
+                }
+                if (lo >= rp[j + 1] || ci[lo] != i) e |= 4u;
+            }
+        }
+    }
+    if (e) atomicOr(err, e);
+    if (diag) atomicAdd(ndiag, diag);
+}
+
+// ---------------------------------------- degree order and relabel (TC)
+
+__global__ void k_order_keys(const int64_t *__restrict__ deg, int64_t n, int64_t maxdeg, int vbits,
+                             uint64_t *__restrict__ keys)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        keys[v] = ((uint64_t)(maxdeg - deg[v]) << vbits) | (uint64_t)v;
+}
+
+__global__ void k_inverse_perm(const uint64_t *__restrict__ keys, int64_t n, uint64_t vmask,
+                               int32_t *__restrict__ inv)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x)
+        inv[keys[p] & vmask] = (int32_t)p;
+}
+
+// cnt[u] = number of neighbours v of u with inv[v] < inv[u]
+__global__ void k_count_relabel_lower(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                      const int32_t *__restrict__ inv, int64_t n,
+                                      int64_t *__restrict__ cnt)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t u = wave; u < n; u += nw) {
+        const int32_t iu = inv[u];
+        int64_t c = 0;
+        for (int64_t p = rp[u] + lane; p < rp[u + 1]; p += 64) c += inv[ci[p]] < iu ? 1 : 0;
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+        if (lane == 0) cnt[u] = c;
+    }
+}
+
+__global__ void k_emit_relabel_lower(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                     const int32_t *__restrict__ inv, int64_t n,
+                                     const int64_t *__restrict__ off, int vbits,
+                                     uint64_t *__restrict__ keys)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t u = wave; u < n; u += nw) {
+        const int32_t iu = inv[u];
+        int64_t out = off[u];
+        for (int64_t p0 = rp[u]; p0 < rp[u + 1]; p0 += 64) {
+            const int64_t p = p0 + lane;
+            int32_t iv = 0;
+            bool take = false;
+            if (p < rp[u + 1]) {
+                iv = inv[ci[p]];
+                take = iv < iu;
+            }
+            const uint64_t bal = __ballot(take);
+            if (take) keys[out + __popcll(bal & below)] = ((uint64_t)iu << vbits) | (uint64_t)iv;
+            out += __popcll(bal);
+        }
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ API
+
+extern "C" int lagr_matrix_build(lagr_matrix *A, int64_t nrows, int64_t ncols, int64_t nedges,
+                                 const int32_t *src, const int32_t *dst, uint32_t flags,
+                                 lagr_ctx ctx, char *msg)
+{
+    if (!A || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *A = nullptr;
+    if (nrows < 0 || ncols < 0 || nrows >= INT32_MAX || ncols >= INT32_MAX || nedges < 0)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "bad sizes");
+    if (nedges > 0 && (!src || !dst)) return lagr_fail(msg, LAGR_NULL_POINTER, "edge arrays");
+    const int sym = (flags & LAGR_BUILD_SYMMETRIZE) ? 1 : 0;
+    const int drop = (flags & LAGR_BUILD_DROP_LOOPS) ? 1 : 0;
+    if (sym && nrows != ncols)
+        return lagr_fail(msg, LAGR_DIMENSION_MISMATCH, "symmetrize needs a square matrix");
+    const int64_t nk = sym ? 2 * nedges : nedges;
+    const int cbits = bits_for((uint64_t)(ncols > 0 ? ncols - 1 : 0));
+    const int nbits = cbits + bits_for((uint64_t)nrows);
+    const uint64_t sent = (uint64_t)nrows << cbits;
+
+    lagr_matrix M = new (std::nothrow) lagr_matrix_s();
+    if (!M) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "matrix");
+    M->type = LAGR_BOOL;
+    M->nrows = nrows;
+    M->ncols = ncols;
+    int rc = LAGR_SUCCESS;
+    uint64_t *keys = (uint64_t *)ws_get(ctx, WS_KEYS, sizeof(uint64_t) * (nk > 0 ? nk : 1));
+    int64_t *pos = (int64_t *)ws_get(ctx, WS_FLAGS, sizeof(int64_t) * (nk > 0 ? nk : 1));
+    unsigned *err = (unsigned *)ws_get(ctx, WS_COUNTERS, 64);
+    int64_t nnz = 0;
+    unsigned herr = 0;
+    if (!keys || !pos || !err) {
+        delete M;
+        return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "build workspace");
+    }
+    HIP_TRY(hipMemsetAsync(err, 0, sizeof(unsigned), ctx->stream));
+    if (nedges > 0) {
+        hipLaunchKernelGGL(k_build_keys, dim3(grid_for(nedges, 256, 65536)), dim3(256), 0,
+                           ctx->stream, src, dst, nedges, nrows, ncols, cbits, sym, drop, keys, err);
+        LAUNCH_CHECK();
+    }
+    rc = read_back(ctx, &herr, err, sizeof(unsigned), msg);
+    if (rc < 0 || herr) {
+        delete M;
+        return rc < 0 ? rc : lagr_fail(msg, LAGR_INVALID_INDEX, "edge endpoint out of range");
+    }
+    if ((rc = radix_sort_u64(ctx, keys, nk, nbits, msg)) < 0) goto fail;
+    if (nk > 0) {
+        hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(nk, 256, 65536)), dim3(256), 0,
+                           ctx->stream, keys, nk, sent, pos);
+        LAUNCH_CHECK();
+    }
+    if ((rc = scan_exclusive_i64(ctx, pos, pos, nk, &nnz, msg)) < 0) goto fail;
+    if ((rc = matrix_alloc(M, nnz, msg)) < 0) goto fail;
+    {
+        uint64_t *ukeys = (uint64_t *)ws_get(ctx, WS_SORT_TMP, sizeof(uint64_t) * (nnz > 0 ? nnz : 1));
+        if (!ukeys) {
+            rc = lagr_fail(msg, LAGR_OUT_OF_MEMORY, "build workspace");
+            goto fail;
+        }
+        if (nk > 0) {
+            hipLaunchKernelGGL(k_compact_keys, dim3(grid_for(nk, 256, 65536)), dim3(256), 0,
+                               ctx->stream, keys, nk, sent, pos, ukeys, M->colidx,
+                               (cbits ? ((1ull << cbits) - 1) : 0ull));
+            LAUNCH_CHECK();
+        }
+        if ((rc = rowptr_from_sorted_keys(ctx, ukeys, nnz, cbits, nrows, M->rowptr, msg)) < 0)
+            goto fail;
+    }
+    *A = M;
+    return lagr_ok(msg);
+fail:
+    matrix_release_arrays(M);
+    delete M;
+    return rc;
+}
+
+extern "C" int lagr_select_tril(lagr_matrix *C, const lagr_matrix A, lagr_ctx ctx, char *msg)
+{
+    if (!C || !A || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *C = nullptr;
+    const int64_t n = A->nrows;
+    int64_t *cnt = (int64_t *)ws_get(ctx, WS_GEN_A, sizeof(int64_t) * (n + 1));
+    if (!cnt) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "select workspace");
+    if (n > 0) {
+        hipLaunchKernelGGL(k_count_lower, dim3(grid_for(n, 256, 65536)), dim3(256), 0, ctx->stream,
+                           A->rowptr, A->colidx, n, cnt);
+        LAUNCH_CHECK();
+    }
+    TRY(fill_i64(ctx, cnt + n, 1, 0, msg));
+    int64_t nnz = 0;
+    TRY(scan_exclusive_i64(ctx, cnt, cnt, n + 1, &nnz, msg));
+    lagr_matrix M = new (std::nothrow) lagr_matrix_s();
+    if (!M) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "matrix");
+    M->type = A->type;
+    M->nrows = A->nrows;
+    M->ncols = A->ncols;
+    int rc = matrix_alloc(M, nnz, msg);
+    if (rc < 0) {
+        delete M;
+        return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(M->rowptr, cnt, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice,
+                           ctx->stream));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_copy_lower, dim3(grid_for(n * 64, 256, 16384)), dim3(256), 0,
+                           ctx->stream, A->rowptr, A->colidx, A->values, n, M->rowptr, M->colidx,
+                           M->values);
+        LAUNCH_CHECK();
+    }
+    *C = M;
+    return lagr_ok(msg);
+}
+
+// ----------------------------------------------------------------- graph
+
+extern "C" int lagr_graph_new(lagr_graph *G, lagr_matrix *A, lagr_kind kind, lagr_ctx ctx,
+                              char *msg)
+{
+    if (!G || !A || !*A || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *G = nullptr;
+    if (kind != LAGR_ADJACENCY_UNDIRECTED && kind != LAGR_ADJACENCY_DIRECTED)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "unknown graph kind");
+    if ((*A)->nrows != (*A)->ncols)
+        return lagr_fail(msg, LAGR_DIMENSION_MISMATCH, "adjacency matrix must be square");
+    lagr_graph g = new (std::nothrow) lagr_graph_s();
+    if (!g) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "graph");
+    g->A = *A;
+    g->kind = kind;
+    *A = nullptr;
+    *G = g;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_graph_check(lagr_graph G, lagr_ctx ctx, char *msg)
+{
+    if (!G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    lagr_matrix A = G->A;
+    unsigned *err = (unsigned *)ws_get(ctx, WS_COUNTERS, 64);
+    if (!err) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "counters");
+    HIP_TRY(hipMemsetAsync(err, 0, 16, ctx->stream));
+    unsigned long long *nd = (unsigned long long *)(err + 2);
+    const int want_sym = G->kind == LAGR_ADJACENCY_UNDIRECTED;
+    if (A->nrows > 0) {
+        hipLaunchKernelGGL(k_check, dim3(grid_for(A->nrows, 256, 4096)), dim3(256), 0, ctx->stream,
+                           A->rowptr, A->colidx, A->nrows, A->ncols, want_sym, err, nd);
+        LAUNCH_CHECK();
+    }
+    unsigned h[4] = {0, 0, 0, 0};
+    TRY(read_back(ctx, h, err, 16, msg));
+    unsigned long long hd;
+    memcpy(&hd, &h[2], 8);
+    if (h[0] & 8u) return lagr_fail(msg, LAGR_INVALID_OBJECT, "row offsets decrease");
+    if (h[0] & 1u) return lagr_fail(msg, LAGR_INVALID_OBJECT, "column id out of range");
+    if (h[0] & 2u) return lagr_fail(msg, LAGR_INVALID_OBJECT, "row not sorted or has duplicates");
+    if (h[0] & 4u) return lagr_fail(msg, LAGR_INVALID_OBJECT, "undirected graph is not symmetric");
+    G->ndiag = (int64_t)hd;
+    if (want_sym) G->symmetric = 1;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_property_row_degree(lagr_graph G, lagr_ctx ctx, char *msg)
+{
+    if (!G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    if (G->row_degree) return lagr_ok(msg);
+    const int64_t n = G->A->nrows;
+    int64_t *deg = (int64_t *)dev_alloc(sizeof(int64_t) * (n > 0 ? n : 1));
+    if (!deg) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "row degree");
+    int64_t mx = 0;
+    int rc = row_degrees(ctx, G->A->rowptr, n, deg, &mx, msg);
+    if (rc < 0) {
+        dev_free(deg, sizeof(int64_t) * (n > 0 ? n : 1));
+        return rc;
+    }
+    G->row_degree = deg;
+    G->max_degree = mx;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
+{
+    if (!G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    if (G->L) return lagr_ok(msg);
+    if (G->kind != LAGR_ADJACENCY_UNDIRECTED)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "triangle counting needs an undirected graph");
+    if (G->ndiag < 0 || G->symmetric < 0) TRY(lagr_graph_check(G, ctx, msg));
+    if (G->ndiag != 0)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "graph has %lld self-loops", (long long)G->ndiag);
+    TRY(lagr_property_row_degree(G, ctx, msg));
+    lagr_matrix A = G->A;
+    const int64_t n = A->nrows;
+    const int vbits = bits_for((uint64_t)(n > 0 ? n - 1 : 0));
+    const uint64_t vmask = vbits ? ((1ull << vbits) - 1) : 0ull;
+
+    // 1. descending-degree order, ties by id (Algorithm 6 sorts by degree;
+    //    descending keeps the rows of L short for the row-by-row form)
+    uint64_t *okeys = (uint64_t *)ws_get(ctx, WS_PERM, sizeof(uint64_t) * (n > 0 ? n : 1));
+    int32_t *inv = (int32_t *)ws_get(ctx, WS_DEG, sizeof(int32_t) * (n > 0 ? n : 1));
+    int64_t *cnt = (int64_t *)ws_get(ctx, WS_FLAGS, sizeof(int64_t) * (n + 1));
+    if (!okeys || !inv || !cnt) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
+    if (n > 0) {
+        hipLaunchKernelGGL(k_order_keys, dim3(grid_for(n, 256, 65536)), dim3(256), 0, ctx->stream,
+                           G->row_degree, n, G->max_degree, vbits, okeys);
+        LAUNCH_CHECK();
+    }
+    TRY(radix_sort_u64(ctx, okeys, n, vbits + bits_for((uint64_t)G->max_degree), msg));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_inverse_perm, dim3(grid_for(n, 256, 65536)), dim3(256), 0, ctx->stream,
+                           okeys, n, vmask, inv);
+        LAUNCH_CHECK();
+        // 2. rows of the relabelled strictly lower part
+        hipLaunchKernelGGL(k_count_relabel_lower, dim3(grid_for(n * 64, 256, 16384)), dim3(256), 0,
+                           ctx->stream, A->rowptr, A->colidx, inv, n, cnt);
+        LAUNCH_CHECK();
+    }
+    TRY(fill_i64(ctx, cnt + n, 1, 0, msg));
+    int64_t nnz = 0;
+    TRY(scan_exclusive_i64(ctx, cnt, cnt, n + 1, &nnz, msg));
+    uint64_t *keys = (uint64_t *)ws_get(ctx, WS_KEYS, sizeof(uint64_t) * (nnz > 0 ? nnz : 1));
+    if (!keys) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
+    if (n > 0) {
+        hipLaunchKernelGGL(k_emit_relabel_lower, dim3(grid_for(n * 64, 256, 16384)), dim3(256), 0,
+                           ctx->stream, A->rowptr, A->colidx, inv, n, cnt, vbits, keys);
+        LAUNCH_CHECK();
+    }
+    TRY(radix_sort_u64(ctx, keys, nnz, 2 * vbits, msg));
+    lagr_matrix L = new (std::nothrow) lagr_matrix_s();
+    if (!L) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "matrix");
+    L->type = LAGR_BOOL;
+    L->nrows = n;
+    L->ncols = n;
+    int rc = matrix_alloc(L, nnz, msg);
+    if (rc < 0) {
+        delete L;
+        return rc;
+    }
+    if ((rc = rowptr_from_sorted_keys(ctx, keys, nnz, vbits, n, L->rowptr, msg)) < 0) goto fail;
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_keys_to_cols, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0,
+                           ctx->stream, keys, nnz, vmask, L->colidx);
+        if (hipGetLastError() != hipSuccess) {
+            rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "relabel launch failed");
+            goto fail;
+        }
+    }
+    {
+        int64_t *tmp = (int64_t *)ws_get(ctx, WS_FLAGS, sizeof(int64_t) * (n > 0 ? n : 1));
+        int64_t mx = 0;
+        if (!tmp) {
+            rc = lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
+            goto fail;
+        }
+        if ((rc = row_degrees(ctx, L->rowptr, n, tmp, &mx, msg)) < 0) goto fail;
+        G->L_maxrow = mx;
+    }
+    G->L = L;
+    return lagr_ok(msg);
+fail:
+    matrix_release_arrays(L);
+    delete L;
+    return rc;
+}
+
+extern "C" int lagr_graph_matrix(lagr_matrix *A, const lagr_graph G, char *msg)
+{
+    if (!A || !G) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *A = G->A;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_graph_ndiag(int64_t *ndiag, const lagr_graph G, char *msg)
+{
+    if (!ndiag || !G) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *ndiag = G->ndiag;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_graph_free(lagr_graph *G)
+{
+    if (!G || !*G) return LAGR_SUCCESS;
+    lagr_graph g = *G;
+    const int64_t n = g->A ? g->A->nrows : 0;
+    if (g->row_degree) dev_free(g->row_degree, sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    lagr_matrix_free(&g->A);
+    lagr_matrix_free(&g->L);
+    delete g;
+    *G = nullptr;
+    return LAGR_SUCCESS;
+}

@@ -1,0 +1,179 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+
+#include "../../include/lagr.h"
+
+// ------------------------------------------------------------------ errors
+
+int lagr_fail(char *msg, int code, const char *fmt, ...);
+static inline int lagr_ok(char *msg)
+{
+    if (msg) msg[0] = '\0';
+    return LAGR_SUCCESS;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return lagr_fail(msg, LAGR_DEVICE_ERROR, "%s failed: %s", #expr,            \
+                             hipGetErrorString(e_));                                    \
+    } while (0)
+
+#define LAUNCH_CHECK()                                                                  \
+    do {                                                                                \
+        hipError_t e_ = hipGetLastError();                                              \
+        if (e_ != hipSuccess)                                                           \
+            return lagr_fail(msg, LAGR_DEVICE_ERROR, "kernel launch failed at %s:%d: %s",\
+                             __FILE__, __LINE__, hipGetErrorString(e_));                \
+    } while (0)
+
+#define TRY(expr)                                                                       \
+    do {                                                                                \
+        int rc_ = (expr);                                                               \
+        if (rc_ < 0) return rc_;                                                        \
+    } while (0)
+
+// ------------------------------------------------------------------ memory
+
+void *dev_alloc(size_t bytes);
+void dev_free(void *p, size_t bytes);
+
+// Workspace slots: each slot is a grow-only device buffer owned by the
+// context, reused across calls.  A routine owns the slots listed for it.
+enum WsSlot {
+    WS_SCAN_L0 = 0,   // scan: block sums, 4 recursion levels
+    WS_SCAN_L1,
+    WS_SCAN_L2,
+    WS_SCAN_L3,
+    WS_SORT_TMP,      // radix sort ping-pong buffer
+    WS_SORT_HIST,     // radix sort digit histograms
+    WS_COUNTERS,      // small device counters
+    WS_KEYS,          // build/relabel: 64-bit keys
+    WS_FLAGS,         // build: dedup flags / positions
+    WS_DEG,           // degrees, ordering
+    WS_PERM,
+    WS_BFS_A,         // BFS state
+    WS_BFS_B,
+    WS_BFS_C,
+    WS_BFS_D,
+    WS_BFS_E,
+    WS_BC_SIGMA,      // BC state
+    WS_BC_W,
+    WS_BC_MASKS,
+    WS_BC_UNVIS,
+    WS_GEN_A,         // generic operations
+    WS_GEN_B,
+    WS_GEN_C,
+    WS_GEN_D,
+    WS_GEN_E,
+    WS_GEN_F,
+    WS_GEN_G,
+    WS_GEN_H,
+    WS_TC,            // triangle counting
+    WS_NSLOTS
+};
+
+struct lagr_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    void *ws[WS_NSLOTS] = {};
+    size_t ws_bytes[WS_NSLOTS] = {};
+    void *pinned = nullptr;          // 4 KiB pinned host staging for scalars
+    int num_cus = 256;
+};
+
+// Returns a device buffer of at least `bytes` for the slot (contents are
+// undefined).  nullptr on allocation failure.
+void *ws_get(lagr_ctx ctx, WsSlot slot, size_t bytes);
+
+struct lagr_matrix_s {
+    lagr_type type = LAGR_BOOL;
+    int64_t nrows = 0, ncols = 0, nvals = 0;
+    int64_t *rowptr = nullptr;
+    int32_t *colidx = nullptr;
+    void *values = nullptr;
+    size_t rowptr_bytes = 0, colidx_bytes = 0, values_bytes = 0;  // 0 = borrowed
+};
+
+struct lagr_vector_s {
+    lagr_type type = LAGR_BOOL;
+    int64_t n = 0;
+    lagr_vformat fmt = LAGR_VEC_SPARSE;
+    int64_t nvals = 0;              // exact for SPARSE and FULL; -1 = unknown (BITMAP)
+    int32_t *idx = nullptr;         // SPARSE
+    uint8_t *present = nullptr;     // BITMAP
+    void *values = nullptr;
+    size_t idx_bytes = 0, present_bytes = 0, values_bytes = 0;      // 0 = borrowed
+};
+
+struct lagr_graph_s {
+    lagr_matrix A = nullptr;
+    lagr_kind kind = LAGR_ADJACENCY_UNDIRECTED;
+    int64_t *row_degree = nullptr;  // cached property, int64[n]
+    int64_t max_degree = -1;
+    int64_t ndiag = -1;             // -1 unknown
+    int symmetric = -1;             // -1 unknown, 0 no, 1 yes
+    lagr_matrix L = nullptr;        // degree-ordered strictly lower part
+    int64_t L_maxrow = -1;
+};
+
+static inline size_t type_size(lagr_type t) { return t == LAGR_BOOL ? 0 : 8; }
+
+// Release a matrix's / vector's owned arrays and reset them to empty.
+void matrix_release_arrays(lagr_matrix A);
+void vector_release_arrays(lagr_vector v);
+// Allocate owned arrays for a CSR of the given size (rowptr always).
+int matrix_alloc(lagr_matrix A, int64_t nvals, char *msg);
+
+// ------------------------------------------------------------- primitives
+
+// Exclusive prefix sum of int64 in[0..n) into out (may alias in).  If
+// total != nullptr the grand total is copied to the host (synchronises).
+int scan_exclusive_i64(lagr_ctx ctx, const int64_t *in, int64_t *out, int64_t n,
+                       int64_t *total, char *msg);
+// Stable LSD radix sort of n 64-bit keys on bits [0, nbits), in place.
+int radix_sort_u64(lagr_ctx ctx, uint64_t *keys, int64_t n, int nbits, char *msg);
+// Fill helpers (graph-capture safe, no hipMemset).
+int fill_i64(lagr_ctx ctx, int64_t *p, int64_t n, int64_t value, char *msg);
+int fill_u32(lagr_ctx ctx, uint32_t *p, int64_t n, uint32_t value, char *msg);
+int fill_u8(lagr_ctx ctx, uint8_t *p, int64_t n, uint8_t value, char *msg);
+// Copy a few bytes device -> host through the context's pinned buffer and
+// wait for the stream.
+int read_back(lagr_ctx ctx, void *host, const void *dev, size_t bytes, char *msg);
+// Build CSR row offsets (n+1) from row ids of `nnz` sorted keys whose row
+// is key >> shift.
+int rowptr_from_sorted_keys(lagr_ctx ctx, const uint64_t *keys, int64_t nnz, int shift,
+                            int64_t nrows, int64_t *rowptr, char *msg);
+// Row degrees (rowptr differences) into deg[n] and their maximum (host).
+int row_degrees(lagr_ctx ctx, const int64_t *rowptr, int64_t n, int64_t *deg,
+                int64_t *maxdeg, char *msg);
+
+static inline int bits_for(uint64_t x)
+{
+    int b = 0;
+    while (b < 64 && (x >> b) != 0) b++;
+    return b;
+}
+
+static inline unsigned grid_for(int64_t work, int block, int64_t cap = 1 << 20)
+{
+    int64_t g = (work + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+// Device helpers ----------------------------------------------------------
+
+__device__ __forceinline__ unsigned lane_id()
+{
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}

@@ -1,0 +1,347 @@
+// Device-wide primitives: exclusive scan, LSD radix sort, fills, CSR row
+// offsets from sorted keys, row degrees.
+#include "internal.h"
+
+namespace {
+
+constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+
+// Block-wide exclusive scan of one int64 per thread; returns the block total.
+__device__ int64_t block_exclusive_scan(int64_t x, int64_t *lds_waves, int64_t &total)
+{
+    const unsigned lane = lane_id();
+    const unsigned wave = threadIdx.x / warpSize;
+    const unsigned nwaves = blockDim.x / warpSize;
+    int64_t incl = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int64_t y = __shfl_up(incl, d, 64);
+        if ((int)lane >= d) incl += y;
+    }
+    if (lane == 63) lds_waves[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t acc = 0;
+        for (unsigned w = 0; w < nwaves; w++) {
+            int64_t t = lds_waves[w];
+            lds_waves[w] = acc;
+            acc += t;
+        }
+        lds_waves[nwaves] = acc;
+    }
+    __syncthreads();
+    total = lds_waves[nwaves];
+    int64_t excl = incl - x + lds_waves[wave];
+    __syncthreads();
+    return excl;
+}
+
+__global__ void k_scan_tiles(const int64_t *__restrict__ in, int64_t *__restrict__ out,
+                             int64_t n, int64_t *__restrict__ tile_sums)
+{
+    __shared__ int64_t lds[SCAN_BLOCK / 64 + 1];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int64_t v[SCAN_ITEMS];
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        int64_t idx = base + i;
+        v[i] = idx < n ? in[idx] : 0;
+        s += v[i];
+    }
+    int64_t total;
+    int64_t run = block_exclusive_scan(s, lds, total);
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        int64_t idx = base + i;
+        if (idx < n) out[idx] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 0 && tile_sums) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_add(int64_t *__restrict__ out, int64_t n, const int64_t *__restrict__ tile_offs)
+{
+    const int64_t add = tile_offs[blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    for (int i = threadIdx.x; i < SCAN_TILE; i += blockDim.x) {
+        int64_t idx = base + i;
+        if (idx < n) out[idx] += add;
+    }
+}
+
+__global__ void k_total(const int64_t *__restrict__ in_last, const int64_t *__restrict__ out_last,
+                        int64_t *__restrict__ dst)
+{
+    *dst = *in_last + *out_last;
+}
+
+}  // namespace
+
+static int scan_level(lagr_ctx ctx, const int64_t *in, int64_t *out, int64_t n, int level,
+                      char *msg)
+{
+    const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (tiles <= 1) {
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(SCAN_BLOCK), 0, ctx->stream, in, out, n,
+                           (int64_t *)nullptr);
+        LAUNCH_CHECK();
+        return LAGR_SUCCESS;
+    }
+    if (level >= 4) return lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "scan: input too large");
+    int64_t *sums = (int64_t *)ws_get(ctx, (WsSlot)(WS_SCAN_L0 + level), sizeof(int64_t) * tiles);
+    if (!sums) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "scan workspace");
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, ctx->stream, in,
+                       out, n, sums);
+    LAUNCH_CHECK();
+    TRY(scan_level(ctx, sums, sums, tiles, level + 1, msg));
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, ctx->stream, out, n,
+                       sums);
+    LAUNCH_CHECK();
+    return LAGR_SUCCESS;
+}
+
+int scan_exclusive_i64(lagr_ctx ctx, const int64_t *in, int64_t *out, int64_t n, int64_t *total,
+                       char *msg)
+{
+    if (n <= 0) {
+        if (total) *total = 0;
+        return LAGR_SUCCESS;
+    }
+    int64_t last_in = 0;
+    if (total) {
+        // the last input is needed after an in-place scan overwrote it
+        HIP_TRY(hipMemcpyAsync(&((int64_t *)ctx->pinned)[1], in + n - 1, sizeof(int64_t),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    }
+    TRY(scan_level(ctx, in, out, n, 0, msg));
+    if (total) {
+        HIP_TRY(hipMemcpyAsync(&((int64_t *)ctx->pinned)[2], out + n - 1, sizeof(int64_t),
+                               hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        last_in = ((int64_t *)ctx->pinned)[1];
+        *total = last_in + ((int64_t *)ctx->pinned)[2];
+    }
+    return LAGR_SUCCESS;
+}
+
+// ------------------------------------------------------------ radix sort
+
+namespace {
+
+constexpr int RS_BLOCK = 256;
+constexpr int RS_ROUNDS = 16;
+constexpr int RS_TILE = RS_BLOCK * RS_ROUNDS;   // keys per block
+constexpr int RS_WAVES = RS_BLOCK / 64;
+
+__global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n,
+                                                      int shift, int64_t *__restrict__ hist,
+                                                      int64_t nblocks)
+{
+    __shared__ unsigned cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ROUNDS; r++) {
+        int64_t i = base + (int64_t)r * RS_BLOCK + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Stable scatter: keys keep their order inside each digit.  Each round
+// takes RS_BLOCK consecutive keys; inside a wave the lanes with an equal
+// digit find each other with eight ballots.
+__global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *__restrict__ in,
+                                                         uint64_t *__restrict__ out, int64_t n,
+                                                         int shift,
+                                                         const int64_t *__restrict__ offs,
+                                                         int64_t nblocks)
+{
+    __shared__ int64_t run[256];
+    __shared__ unsigned wcnt[RS_WAVES][256];
+    __shared__ int64_t wbase[RS_WAVES][256];
+    const unsigned lane = lane_id();
+    const unsigned wave = threadIdx.x / 64;
+    run[threadIdx.x] = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < RS_ROUNDS; r++) {
+        for (int w = 0; w < RS_WAVES; w++) wcnt[w][threadIdx.x] = 0;
+        __syncthreads();
+        const int64_t i = base + (int64_t)r * RS_BLOCK + threadIdx.x;
+        const bool valid = i < n;
+        uint64_t key = valid ? in[i] : 0;
+        unsigned digit = valid ? (unsigned)((key >> shift) & 255u) : 256u;
+        uint64_t same = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            uint64_t bal = __ballot((digit >> b) & 1u);
+            same &= ((digit >> b) & 1u) ? bal : ~bal;
+        }
+        const unsigned rank = __popcll(same & below);
+        if (valid && rank == 0) wcnt[wave][digit] = __popcll(same);
+        __syncthreads();
+        {
+            const unsigned d = threadIdx.x;
+            int64_t acc = run[d];
+            for (int w = 0; w < RS_WAVES; w++) {
+                wbase[w][d] = acc;
+                acc += wcnt[w][d];
+            }
+            run[d] = acc;
+        }
+        __syncthreads();
+        if (valid) out[wbase[wave][digit] + rank] = key;
+        __syncthreads();
+    }
+}
+
+__global__ void k_copy_u64(const uint64_t *__restrict__ in, uint64_t *__restrict__ out, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[i];
+}
+
+}  // namespace
+
+int radix_sort_u64(lagr_ctx ctx, uint64_t *keys, int64_t n, int nbits, char *msg)
+{
+    if (n <= 1 || nbits <= 0) return LAGR_SUCCESS;
+    const int64_t nblocks = (n + RS_TILE - 1) / RS_TILE;
+    uint64_t *tmp = (uint64_t *)ws_get(ctx, WS_SORT_TMP, sizeof(uint64_t) * n);
+    int64_t *hist = (int64_t *)ws_get(ctx, WS_SORT_HIST, sizeof(int64_t) * 256 * nblocks);
+    if (!tmp || !hist) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "radix sort workspace");
+    uint64_t *src = keys, *dst = tmp;
+    int passes = 0;
+    for (int shift = 0; shift < nbits; shift += 8, passes++) {
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, ctx->stream, src,
+                           n, shift, hist, nblocks);
+        LAUNCH_CHECK();
+        TRY(scan_exclusive_i64(ctx, hist, hist, 256 * nblocks, nullptr, msg));
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, ctx->stream,
+                           src, dst, n, shift, hist, nblocks);
+        LAUNCH_CHECK();
+        uint64_t *t = src;
+        src = dst;
+        dst = t;
+    }
+    if (src != keys) {
+        hipLaunchKernelGGL(k_copy_u64, dim3(grid_for(n, 256, 65536)), dim3(256), 0, ctx->stream,
+                           src, keys, n);
+        LAUNCH_CHECK();
+    }
+    return LAGR_SUCCESS;
+}
+
+// ----------------------------------------------------------------- fills
+
+namespace {
+template <class T>
+__global__ void k_fill(T *__restrict__ p, int64_t n, T v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+}  // namespace
+
+int fill_i64(lagr_ctx ctx, int64_t *p, int64_t n, int64_t value, char *msg)
+{
+    if (n <= 0) return LAGR_SUCCESS;
+    hipLaunchKernelGGL(k_fill<int64_t>, dim3(grid_for(n, 256, 16384)), dim3(256), 0, ctx->stream,
+                       p, n, value);
+    LAUNCH_CHECK();
+    return LAGR_SUCCESS;
+}
+
+int fill_u32(lagr_ctx ctx, uint32_t *p, int64_t n, uint32_t value, char *msg)
+{
+    if (n <= 0) return LAGR_SUCCESS;
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(n, 256, 16384)), dim3(256), 0, ctx->stream,
+                       p, n, value);
+    LAUNCH_CHECK();
+    return LAGR_SUCCESS;
+}
+
+int fill_u8(lagr_ctx ctx, uint8_t *p, int64_t n, uint8_t value, char *msg)
+{
+    if (n <= 0) return LAGR_SUCCESS;
+    hipLaunchKernelGGL(k_fill<uint8_t>, dim3(grid_for(n, 256, 16384)), dim3(256), 0, ctx->stream,
+                       p, n, value);
+    LAUNCH_CHECK();
+    return LAGR_SUCCESS;
+}
+
+int read_back(lagr_ctx ctx, void *host, const void *dev, size_t bytes, char *msg)
+{
+    if (bytes > 4096) return lagr_fail(msg, LAGR_INVALID_VALUE, "read_back: too large");
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    memcpy(host, ctx->pinned, bytes);
+    return LAGR_SUCCESS;
+}
+
+// ------------------------------------------------ CSR offsets from keys
+
+namespace {
+// rowptr[r] = first position whose row >= r.  Every position p writes the
+// offsets of the rows strictly between the previous key's row and its own.
+__global__ void k_rowptr_from_keys(const uint64_t *__restrict__ keys, int64_t nnz, int shift,
+                                   int64_t nrows, int64_t *__restrict__ rowptr)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= nnz;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t prev = p == 0 ? -1 : (int64_t)(keys[p - 1] >> shift);
+        const int64_t cur = p == nnz ? nrows : (int64_t)(keys[p] >> shift);
+        for (int64_t r = prev + 1; r <= cur && r <= nrows; r++) rowptr[r] = p;
+    }
+}
+
+__global__ void k_degrees(const int64_t *__restrict__ rowptr, int64_t n, int64_t *__restrict__ deg,
+                          unsigned long long *__restrict__ maxdeg)
+{
+    int64_t local = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = rowptr[v + 1] - rowptr[v];
+        deg[v] = d;
+        local = d > local ? d : local;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        int64_t y = __shfl_xor(local, o, 64);
+        local = y > local ? y : local;
+    }
+    if (lane_id() == 0) atomicMax(maxdeg, (unsigned long long)local);
+}
+}  // namespace
+
+int rowptr_from_sorted_keys(lagr_ctx ctx, const uint64_t *keys, int64_t nnz, int shift,
+                            int64_t nrows, int64_t *rowptr, char *msg)
+{
+    hipLaunchKernelGGL(k_rowptr_from_keys, dim3(grid_for(nnz + 1, 256, 65536)), dim3(256), 0,
+                       ctx->stream, keys, nnz, shift, nrows, rowptr);
+    LAUNCH_CHECK();
+    return LAGR_SUCCESS;
+}
+
+int row_degrees(lagr_ctx ctx, const int64_t *rowptr, int64_t n, int64_t *deg, int64_t *maxdeg,
+                char *msg)
+{
+    unsigned long long *m = (unsigned long long *)ws_get(ctx, WS_COUNTERS, 64);
+    if (!m) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "counters");
+    HIP_TRY(hipMemsetAsync(m, 0, sizeof(unsigned long long), ctx->stream));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_degrees, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream,
+                           rowptr, n, deg, m);
+        LAUNCH_CHECK();
+    }
+    unsigned long long h = 0;
+    TRY(read_back(ctx, &h, m, sizeof(h), msg));
+    if (maxdeg) *maxdeg = (int64_t)h;
+    return LAGR_SUCCESS;
+}

@@ -1,0 +1,468 @@
+"""Thin ctypes binding of liblagr.so (include/lagr.h).
+
+Argument marshalling only: every step of every operation runs in the HIP
+kernels of the shared library.  PyTorch supplies device memory (its caching
+allocator is registered as the library's allocator) and the stream.  There
+is no CPU fallback: importing this module without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblagr.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"liblagr.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MSG_LEN = 256
+
+# codes
+SUCCESS, NO_VALUE = 0, 1
+NULL_POINTER, INVALID_VALUE, INVALID_INDEX, DOMAIN_MISMATCH = -1, -2, -3, -4
+DIMENSION_MISMATCH, INVALID_OBJECT, OUT_OF_MEMORY, PROPERTY_MISSING = -5, -6, -7, -8
+NOT_IMPLEMENTED, DEVICE_ERROR, BUDGET_EXCEEDED = -9, -10, -11
+
+# types
+BOOL, INT64, FP64 = 0, 1, 2
+# semirings
+PLUS_PAIR, ANY_SECONDI, PLUS_FIRST, MIN_PLUS = 0, 1, 2, 3
+# binops
+NOOP, PLUS, MIN, FIRST, SECOND, TIMES, DIV, ANY = range(8)
+# descriptor bits
+DESC_DEFAULT, DESC_COMP, DESC_STRUCT, DESC_REPLACE = 0, 1, 2, 4
+DESC_TRAN0, DESC_TRAN1, DESC_DETERMINISTIC, DESC_ASSIGN_PARENT = 8, 16, 32, 64
+DESC_S = DESC_STRUCT
+DESC_RSC = DESC_REPLACE | DESC_STRUCT | DESC_COMP
+# vector formats
+VEC_SPARSE, VEC_BITMAP, VEC_FULL = 0, 1, 2
+# graph kinds
+ADJACENCY_UNDIRECTED, ADJACENCY_DIRECTED = 0, 1
+# build flags
+BUILD_SYMMETRIZE, BUILD_DROP_LOOPS = 1, 2
+# bfs flags
+BFS_PUSH_ONLY, BFS_ANY_PARENT = 1, 2
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_U32 = ctypes.c_uint32
+_INT = ctypes.c_int
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_C = ctypes.c_char_p
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+_PROTOS = {
+    "lagr_set_allocator": [ALLOC_FN, FREE_FN, _P, _C],
+    "lagr_ctx_new": [_PP, _INT, _P, _C],
+    "lagr_ctx_set_stream": [_P, _P, _C],
+    "lagr_ctx_free": [_PP],
+    "lagr_wait": [_P, _C],
+    "lagr_matrix_new": [_PP, _INT, _I64, _I64, _P, _C],
+    "lagr_matrix_wrap_csr": [_PP, _INT, _I64, _I64, _I64, _P, _P, _P, _P, _C],
+    "lagr_matrix_build": [_PP, _I64, _I64, _I64, _P, _P, _U32, _P, _C],
+    "lagr_matrix_info": [_P, _P, _P, _P, _P, _C],
+    "lagr_matrix_extract_csr": [_P, _P, _P, _P, _P, _C],
+    "lagr_matrix_nvals": [_P, _P, _P, _C],
+    "lagr_select_tril": [_PP, _P, _P, _C],
+    "lagr_matrix_free": [_PP],
+    "lagr_vector_new": [_PP, _INT, _I64, _P, _C],
+    "lagr_vector_wrap_sparse": [_PP, _INT, _I64, _I64, _P, _P, _P, _C],
+    "lagr_vector_wrap_bitmap": [_PP, _INT, _I64, _P, _P, _P, _C],
+    "lagr_vector_wrap_full": [_PP, _INT, _I64, _P, _P, _C],
+    "lagr_vector_info": [_P, _P, _P, _P, _C],
+    "lagr_vector_nvals": [_P, _P, _P, _C],
+    "lagr_vector_extract_tuples": [_P, _P, _P, _P, _C],
+    "lagr_vector_extract_dense": [_P, _P, _P, _P, _P, _C],
+    "lagr_vector_free": [_PP],
+    "lagr_mxm": [_P, _P, _INT, _INT, _P, _P, _U32, _P, _C],
+    "lagr_vxm": [_P, _P, _INT, _INT, _P, _P, _U32, _P, _P, _C],
+    "lagr_mxm_reduce": [_P, _P, _INT, _P, _P, _U32, _P, _C],
+    "lagr_reduce_scalar": [_P, _INT, _INT, _P, _P, _C],
+    "lagr_vector_reduce_scalar": [_P, _INT, _INT, _P, _P, _C],
+    "lagr_reduce_rows": [_P, _P, _INT, _INT, _P, _U32, _P, _C],
+    "lagr_assign_vector": [_P, _P, _INT, _P, _U32, _P, _C],
+    "lagr_assign_scalar": [_P, _P, _INT, _P, _U32, _P, _C],
+    "lagr_ewise_add": [_P, _P, _INT, _INT, _P, _P, _U32, _P, _C],
+    "lagr_ewise_mult": [_P, _P, _INT, _INT, _P, _P, _U32, _P, _C],
+    "lagr_graph_new": [_PP, _PP, _INT, _P, _C],
+    "lagr_graph_check": [_P, _P, _C],
+    "lagr_property_row_degree": [_P, _P, _C],
+    "lagr_property_tc_lower": [_P, _P, _C],
+    "lagr_graph_matrix": [_PP, _P, _C],
+    "lagr_graph_ndiag": [_P, _P, _C],
+    "lagr_graph_free": [_PP],
+    "lagr_tc": [_P, _P, _P, _C],
+    "lagr_tc_adv": [_P, _P, _P, _C],
+    "lagr_bfs": [_PP, _PP, _P, _I64, _U32, _P, _C],
+    "lagr_bc": [_PP, _P, _P, _I32, _P, _C],
+}
+
+_fns = {}
+for _name, _args in _PROTOS.items():
+    try:
+        _f = getattr(_lib, _name)
+    except AttributeError:
+        continue
+    _f.restype = ctypes.c_int
+    _f.argtypes = _args
+    _fns[_name] = _f
+
+
+def exported_symbols():
+    return set(_fns)
+
+
+class LagrError(RuntimeError):
+    def __init__(self, fn, code, text):
+        super().__init__(f"{fn} -> {code}: {text}")
+        self.code = code
+
+
+def call(name, *args):
+    """Call an exported function; raise LagrError on a negative code.
+    Returns the (non-negative) code."""
+    buf = ctypes.create_string_buffer(MSG_LEN)
+    rc = _fns[name](*args, buf)
+    if rc < 0:
+        raise LagrError(name, rc, buf.value.decode(errors="replace"))
+    return rc
+
+
+def call_nomsg(name, *args):
+    return _fns[name](*args)
+
+
+# ------------------------------------------------------------ allocator
+
+_alloc_refs = None
+
+
+def use_torch_allocator(enable: bool = True):
+    """Route the library's device allocations through PyTorch's caching
+    allocator on the current device and stream."""
+    global _alloc_refs
+    if not enable:
+        call("lagr_set_allocator", ALLOC_FN(), FREE_FN(), None)
+        _alloc_refs = None
+        return
+
+    def _alloc(nbytes, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:
+            return None
+
+    def _free(ptr, nbytes, user):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a, f = ALLOC_FN(_alloc), FREE_FN(_free)
+    call("lagr_set_allocator", a, f, None)
+    _alloc_refs = (a, f)
+
+
+# --------------------------------------------------------------- objects
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        torch.cuda.set_device(device)
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self.stream = s
+        self.h = ctypes.c_void_p()
+        call("lagr_ctx_new", ctypes.byref(self.h), device, ctypes.c_void_p(s.cuda_stream))
+
+    def wait(self):
+        call("lagr_wait", self.h)
+
+    def free(self):
+        if self.h:
+            call_nomsg("lagr_ctx_free", ctypes.byref(self.h))
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+_TORCH = {BOOL: None, INT64: torch.int64, FP64: torch.float64}
+
+
+class Matrix:
+    """Handle of a lagr_matrix.  Keeps wrapped tensors alive."""
+
+    def __init__(self, h, keep=()):
+        self.h = h
+        self._keep = keep
+
+    @classmethod
+    def new(cls, ctx, typ, nrows, ncols):
+        h = ctypes.c_void_p()
+        call("lagr_matrix_new", ctypes.byref(h), typ, nrows, ncols, ctx.h)
+        return cls(h)
+
+    @classmethod
+    def wrap_csr(cls, ctx, nrows, ncols, rowptr, colidx, values=None, typ=None):
+        if typ is None:
+            typ = BOOL if values is None else (FP64 if values.dtype == torch.float64 else INT64)
+        rowptr = rowptr.to(torch.int64).contiguous()
+        colidx = colidx.to(torch.int32).contiguous()
+        if values is not None:
+            values = values.to(_TORCH[typ]).contiguous()
+        h = ctypes.c_void_p()
+        call("lagr_matrix_wrap_csr", ctypes.byref(h), typ, nrows, ncols, colidx.numel(),
+             _ptr(rowptr), _ptr(colidx), _ptr(values), ctx.h)
+        return cls(h, (rowptr, colidx, values))
+
+    @classmethod
+    def build(cls, ctx, nrows, ncols, src, dst, flags):
+        src = src.to(torch.int32).contiguous()
+        dst = dst.to(torch.int32).contiguous()
+        h = ctypes.c_void_p()
+        call("lagr_matrix_build", ctypes.byref(h), nrows, ncols, src.numel(), _ptr(src), _ptr(dst),
+             flags, ctx.h)
+        return cls(h)
+
+    def info(self):
+        t, r, c, nv = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        call("lagr_matrix_info", self.h, ctypes.byref(t), ctypes.byref(r), ctypes.byref(c),
+             ctypes.byref(nv))
+        return t.value, r.value, c.value, nv.value
+
+    def to_csr(self, ctx):
+        typ, nrows, ncols, nvals = self.info()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        rp = torch.empty(nrows + 1, dtype=torch.int64, device=dev)
+        ci = torch.empty(nvals, dtype=torch.int32, device=dev)
+        va = None if typ == BOOL else torch.empty(nvals, dtype=_TORCH[typ], device=dev)
+        call("lagr_matrix_extract_csr", self.h, _ptr(rp), _ptr(ci), _ptr(va), ctx.h)
+        ctx.wait()
+        return rp, ci, va
+
+    def free(self):
+        if self.h:
+            call_nomsg("lagr_matrix_free", ctypes.byref(self.h))
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Vector:
+    def __init__(self, h, keep=()):
+        self.h = h
+        self._keep = keep
+
+    @classmethod
+    def new(cls, ctx, typ, n):
+        h = ctypes.c_void_p()
+        call("lagr_vector_new", ctypes.byref(h), typ, n, ctx.h)
+        return cls(h)
+
+    @classmethod
+    def wrap_sparse(cls, ctx, n, idx, values=None, typ=None):
+        if typ is None:
+            typ = BOOL if values is None else (FP64 if values.dtype == torch.float64 else INT64)
+        idx = idx.to(torch.int32).contiguous()
+        if values is not None:
+            values = values.to(_TORCH[typ]).contiguous()
+        h = ctypes.c_void_p()
+        call("lagr_vector_wrap_sparse", ctypes.byref(h), typ, n, idx.numel(), _ptr(idx),
+             _ptr(values), ctx.h)
+        return cls(h, (idx, values))
+
+    @classmethod
+    def wrap_bitmap(cls, ctx, present, values=None, typ=None):
+        if typ is None:
+            typ = BOOL if values is None else (FP64 if values.dtype == torch.float64 else INT64)
+        present = present.to(torch.uint8).contiguous()
+        if values is not None:
+            values = values.to(_TORCH[typ]).contiguous()
+        h = ctypes.c_void_p()
+        call("lagr_vector_wrap_bitmap", ctypes.byref(h), typ, present.numel(), _ptr(present),
+             _ptr(values), ctx.h)
+        return cls(h, (present, values))
+
+    @classmethod
+    def wrap_full(cls, ctx, values):
+        typ = FP64 if values.dtype == torch.float64 else INT64
+        values = values.to(_TORCH[typ]).contiguous()
+        h = ctypes.c_void_p()
+        call("lagr_vector_wrap_full", ctypes.byref(h), typ, values.numel(), _ptr(values), ctx.h)
+        return cls(h, (values,))
+
+    def info(self):
+        t, n, f = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int()
+        call("lagr_vector_info", self.h, ctypes.byref(t), ctypes.byref(n), ctypes.byref(f))
+        return t.value, n.value, f.value
+
+    def nvals(self, ctx):
+        nv = ctypes.c_int64()
+        call("lagr_vector_nvals", ctypes.byref(nv), self.h, ctx.h)
+        return nv.value
+
+    def to_dense(self, ctx, fill=0):
+        """-> (present uint8[n], values[n]) device tensors."""
+        typ, n, fmt = self.info()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        pres = torch.empty(n, dtype=torch.uint8, device=dev)
+        vt = _TORCH[typ] or torch.int64
+        vals = torch.empty(n, dtype=vt, device=dev)
+        f = ctypes.c_int64(fill) if vt == torch.int64 else ctypes.c_double(fill)
+        call("lagr_vector_extract_dense", self.h, _ptr(pres), None if typ == BOOL else _ptr(vals),
+             ctypes.byref(f), ctx.h)
+        ctx.wait()
+        return pres, vals
+
+    def values_full(self, ctx):
+        """Values of a FULL vector as a tensor (copy)."""
+        return self.to_dense(ctx)[1]
+
+    def to_tuples(self, ctx):
+        typ, n, fmt = self.info()
+        nv = self.nvals(ctx)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        idx = torch.empty(nv, dtype=torch.int32, device=dev)
+        vals = None if typ == BOOL else torch.empty(nv, dtype=_TORCH[typ], device=dev)
+        call("lagr_vector_extract_tuples", self.h, _ptr(idx), _ptr(vals), ctx.h)
+        ctx.wait()
+        return idx, vals
+
+    def free(self):
+        if self.h:
+            call_nomsg("lagr_vector_free", ctypes.byref(self.h))
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Graph:
+    def __init__(self, ctx, A: Matrix, kind=ADJACENCY_UNDIRECTED):
+        self.h = ctypes.c_void_p()
+        self._keep = A._keep
+        call("lagr_graph_new", ctypes.byref(self.h), ctypes.byref(A.h), kind, ctx.h)
+        A.h = ctypes.c_void_p()   # moved into the graph (Listing 1)
+
+    def check(self, ctx):
+        call("lagr_graph_check", self.h, ctx.h)
+
+    def ndiag(self):
+        v = ctypes.c_int64()
+        call("lagr_graph_ndiag", ctypes.byref(v), self.h)
+        return v.value
+
+    def free(self):
+        if self.h:
+            call_nomsg("lagr_graph_free", ctypes.byref(self.h))
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ algorithms
+
+def lagr_tc(G: Graph, ctx: Context) -> int:
+    t = ctypes.c_int64()
+    call("lagr_tc", ctypes.byref(t), G.h, ctx.h)
+    return t.value
+
+
+def lagr_tc_adv(G: Graph, ctx: Context) -> int:
+    t = ctypes.c_int64()
+    call("lagr_tc_adv", ctypes.byref(t), G.h, ctx.h)
+    return t.value
+
+
+def lagr_property_tc_lower(G: Graph, ctx: Context):
+    call("lagr_property_tc_lower", G.h, ctx.h)
+
+
+def lagr_bfs(G: Graph, source: int, ctx: Context, flags: int = 0, want_level=True, want_parent=True):
+    lv, pv = ctypes.c_void_p(), ctypes.c_void_p()
+    call("lagr_bfs", ctypes.byref(lv) if want_level else None,
+         ctypes.byref(pv) if want_parent else None, G.h, source, flags, ctx.h)
+    return (Vector(lv) if want_level else None), (Vector(pv) if want_parent else None)
+
+
+def lagr_bc(G: Graph, sources, ctx: Context) -> Vector:
+    import numpy as np
+    s = np.ascontiguousarray(np.asarray(sources, dtype=np.int64))
+    out = ctypes.c_void_p()
+    call("lagr_bc", ctypes.byref(out), G.h, ctypes.c_void_p(s.ctypes.data), s.size, ctx.h)
+    return Vector(out)
+
+
+# ----------------------------------------------------------- operations
+
+def lagr_mxm(C: Matrix, M, accum, semiring, A: Matrix, B: Matrix, desc, ctx: Context):
+    return call("lagr_mxm", C.h, None if M is None else M.h, accum, semiring, A.h, B.h, desc, ctx.h)
+
+
+def lagr_vxm(w: Vector, m, accum, semiring, u: Vector, A: Matrix, desc, ctx: Context, parent=None):
+    return call("lagr_vxm", w.h, None if m is None else m.h, accum, semiring, u.h, A.h, desc,
+                None if parent is None else parent.h, ctx.h)
+
+
+def lagr_mxm_reduce(M: Matrix, semiring, A: Matrix, B: Matrix, desc, ctx: Context, fp64=False):
+    s = ctypes.c_double() if fp64 else ctypes.c_int64()
+    call("lagr_mxm_reduce", ctypes.byref(s), M.h, semiring, A.h, B.h, desc, ctx.h)
+    return s.value
+
+
+def lagr_reduce_scalar(A: Matrix, monoid, ctx: Context, accum=NOOP, init=None, fp64=False):
+    s = ctypes.c_double(init or 0.0) if fp64 else ctypes.c_int64(init or 0)
+    rc = call("lagr_reduce_scalar", ctypes.byref(s), accum, monoid, A.h, ctx.h)
+    return None if rc == NO_VALUE and init is None else s.value
+
+
+def lagr_vector_reduce_scalar(u: Vector, monoid, ctx: Context, accum=NOOP, init=None, fp64=False):
+    s = ctypes.c_double(init or 0.0) if fp64 else ctypes.c_int64(init or 0)
+    rc = call("lagr_vector_reduce_scalar", ctypes.byref(s), accum, monoid, u.h, ctx.h)
+    return None if rc == NO_VALUE and init is None else s.value
+
+
+def lagr_reduce_rows(w: Vector, m, accum, monoid, A: Matrix, desc, ctx: Context):
+    return call("lagr_reduce_rows", w.h, None if m is None else m.h, accum, monoid, A.h, desc, ctx.h)
+
+
+def lagr_assign_vector(w: Vector, m, accum, u: Vector, desc, ctx: Context):
+    return call("lagr_assign_vector", w.h, None if m is None else m.h, accum, u.h, desc, ctx.h)
+
+
+def lagr_assign_scalar(w: Vector, m, accum, s, desc, ctx: Context, fp64=False):
+    x = ctypes.c_double(s) if fp64 else ctypes.c_int64(s)
+    return call("lagr_assign_scalar", w.h, None if m is None else m.h, accum, ctypes.byref(x), desc,
+                ctx.h)
+
+
+def lagr_ewise_add(C: Matrix, M, accum, op, A: Matrix, B: Matrix, desc, ctx: Context):
+    return call("lagr_ewise_add", C.h, None if M is None else M.h, accum, op, A.h, B.h, desc, ctx.h)
+
+
+def lagr_ewise_mult(C: Matrix, M, accum, op, A: Matrix, B: Matrix, desc, ctx: Context):
+    return call("lagr_ewise_mult", C.h, None if M is None else M.h, accum, op, A.h, B.h, desc, ctx.h)
+
+
+def lagr_select_tril(A: Matrix, ctx: Context) -> Matrix:
+    h = ctypes.c_void_p()
+    call("lagr_select_tril", ctypes.byref(h), A.h, ctx.h)
+    return Matrix(h)

@@ -1,0 +1,223 @@
+"""Parity of the device path (through the C ABI) with the CPU oracle:
+graph build, triangle counting, BFS and betweenness centrality."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+import graphs as Gs
+from gpu_util import (assert_bc_close, check_parents, ctx, device_graph, graph_csr,
+                      graph_from_edges, lagr, rmat)
+
+pytestmark = pytest.mark.gpu
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_values.json")))
+
+
+# --------------------------------------------------------------- build
+
+@pytest.mark.parametrize("scale,ef,seed", [(8, 4, 101), (10, 16, 1), (12, 8, 102)])
+def test_device_build_equals_oracle_adjacency(scale, ef, seed):
+    n, s, d = rmat(scale, ef, seed)
+    G = device_graph(n, s, d)
+    rp, ci = graph_csr(G)
+    orp, oci = oracle.build_adjacency(n, s, d)
+    assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
+
+
+def test_build_empty_and_all_loops():
+    G, (orp, oci) = graph_from_edges(5, [(1, 1), (3, 3)])
+    rp, ci = graph_csr(G)
+    assert rp.tolist() == [0] * 6 and ci.size == 0
+    L = lagr()
+    assert L.lagr_tc(G, ctx()) == 0
+
+
+def test_graph_check_rejects_malformed():
+    import torch
+    L = lagr()
+    c = ctx()
+    cases = {
+        "unsorted": ([0, 2, 3, 4], [2, 1, 0, 0]),
+        "duplicate": ([0, 2, 3, 4], [1, 1, 0, 0]),
+        "asymmetric": ([0, 1, 1, 1], [1]),
+        "out of range": ([0, 1, 2, 2], [5, 0]),
+    }
+    for name, (rp, ci) in cases.items():
+        rpt = torch.tensor(rp, dtype=torch.int64, device="cuda")
+        cit = torch.tensor(ci, dtype=torch.int32, device="cuda")
+        A = L.Matrix.wrap_csr(c, 3, 3, rpt, cit)
+        G = L.Graph(c, A)
+        with pytest.raises(L.LagrError) as e:
+            G.check(c)
+        assert e.value.code == L.INVALID_OBJECT, name
+
+
+# ------------------------------------------------------------------ TC
+
+@pytest.mark.parametrize("n", [3, 4, 7, 16, 40, 90])
+def test_tc_complete(n):
+    G, _ = graph_from_edges(*Gs.complete(n))
+    assert lagr().lagr_tc(G, ctx()) == math.comb(n, 3)
+
+
+@pytest.mark.parametrize("g,want", [(Gs.wheel(5), 5), (Gs.wheel(30), 30), (Gs.petersen(), 0),
+                                    (Gs.grid(6, 9), 0), (Gs.complete_bipartite(7, 9), 0),
+                                    (Gs.disjoint_union(Gs.complete(9), Gs.wheel(11)), 84 + 11)])
+def test_tc_closed_forms(g, want):
+    G, _ = graph_from_edges(*g)
+    assert lagr().lagr_tc(G, ctx()) == want
+
+
+def test_tc_hub_rows_longer_than_the_lds_table():
+    # a complete graph of 1500 vertices: rows of L reach 1499 > 1024 entries
+    n = 1500
+    G, _ = graph_from_edges(*Gs.complete(n))
+    assert lagr().lagr_tc(G, ctx()) == math.comb(n, 3)
+
+
+@pytest.mark.parametrize("entry", GOLD["graphs"], ids=lambda e: f"s{e['scale']}ef{e['edge_factor']}")
+def test_tc_rmat_golden(entry):
+    n, s, d = rmat(entry["scale"], entry["edge_factor"], entry["seed"])
+    G = device_graph(n, s, d)
+    assert lagr().lagr_tc(G, ctx()) == entry["triangles"]
+
+
+def test_tc_small_config_against_oracle_directly():
+    n, s, d = rmat(10, 16, 1)
+    G = device_graph(n, s, d)
+    rp, ci = oracle.build_adjacency(n, s, d)
+    assert lagr().lagr_tc(G, ctx()) == oracle.triangle_count(rp, ci)
+
+
+def test_tc_advanced_mode_requires_property():
+    L = lagr()
+    G, _ = graph_from_edges(*Gs.complete(6))
+    with pytest.raises(L.LagrError) as e:
+        L.lagr_tc_adv(G, ctx())
+    assert e.value.code == L.PROPERTY_MISSING
+    L.lagr_property_tc_lower(G, ctx())
+    assert L.lagr_tc_adv(G, ctx()) == 20
+
+
+@pytest.mark.skipif("large" not in GOLD, reason="large golden not generated")
+def test_tc_large_config():
+    e = GOLD["large"]
+    n, s, d = rmat(e["scale"], e["edge_factor"], e["seed"])
+    G = device_graph(n, s, d)
+    assert lagr().lagr_tc(G, ctx()) == e["triangles"]
+
+
+# ----------------------------------------------------------------- BFS
+
+def bfs_host(G, s, flags=0):
+    L = lagr()
+    c = ctx()
+    lv, pv = L.lagr_bfs(G, s, c, flags)
+    return lv.values_full(c).cpu().numpy(), pv.values_full(c).cpu().numpy()
+
+
+def test_bfs_closed_forms():
+    G, (rp, ci) = graph_from_edges(*Gs.path(50))
+    lv, pa = bfs_host(G, 0)
+    assert lv.tolist() == list(range(50)) and pa.tolist() == [0] + list(range(49))
+    r, c = 9, 13
+    G, (rp, ci) = graph_from_edges(*Gs.grid(r, c))
+    lv, pa = bfs_host(G, 0)
+    assert lv.tolist() == [i + j for i in range(r) for j in range(c)]
+    check_parents(rp, ci, 0, lv, pa)
+    G, _ = graph_from_edges(*Gs.disjoint_union(Gs.cycle(6), Gs.path(4)))
+    lv, pa = bfs_host(G, 7)
+    assert lv.tolist() == [-1] * 6 + [1, 0, 1, 2]
+    assert pa.tolist() == [-1] * 6 + [7, 7, 7, 8]
+
+
+@pytest.mark.parametrize("scale,ef,seed", [(10, 16, 1), (12, 8, 102), (14, 16, 103)])
+def test_bfs_rmat_levels_and_min_parents(scale, ef, seed):
+    L = lagr()
+    n, s, d = rmat(scale, ef, seed)
+    G = device_graph(n, s, d)
+    rp, ci = oracle.build_adjacency(n, s, d)
+    for src in graphgen.sources(n, s, d, 6, seed):
+        src = int(src)
+        lv_o, pa_o = oracle.bfs(rp, ci, src)
+        mp = oracle.bfs_min_parent(rp, ci, src, lv_o)
+        for flags in (0, L.BFS_PUSH_ONLY):
+            lv, pa = bfs_host(G, src, flags)
+            assert np.array_equal(lv, lv_o.astype(np.int64))
+            assert np.array_equal(pa, mp)
+        lv, pa = bfs_host(G, src, L.BFS_ANY_PARENT)
+        assert np.array_equal(lv, lv_o.astype(np.int64))
+        check_parents(rp, ci, src, lv, pa)
+
+
+def test_bfs_isolated_source_and_bad_source():
+    L = lagr()
+    G, _ = graph_from_edges(5, [(0, 1), (1, 2)])
+    lv, pa = bfs_host(G, 4)
+    assert lv.tolist() == [-1, -1, -1, -1, 0] and pa.tolist() == [-1, -1, -1, -1, 4]
+    with pytest.raises(L.LagrError) as e:
+        L.lagr_bfs(G, 5, ctx())
+    assert e.value.code == L.INVALID_INDEX
+
+
+def test_bfs_large_config_sampled_sources():
+    n, s, d = rmat(20, 16, 2)
+    G = device_graph(n, s, d)
+    rp, ci = oracle.build_adjacency(n, s, d)
+    srcs = graphgen.sources(n, s, d, 64, 2)
+    for src in srcs[:3]:
+        src = int(src)
+        lv_o, _ = oracle.bfs(rp, ci, src)
+        mp = oracle.bfs_min_parent(rp, ci, src, lv_o)
+        lv, pa = bfs_host(G, src)
+        assert np.array_equal(lv, lv_o.astype(np.int64))
+        assert np.array_equal(pa, mp)
+
+
+# ------------------------------------------------------------------ BC
+
+def bc_host(G, sources):
+    L = lagr()
+    c = ctx()
+    return L.lagr_bc(G, sources, c).values_full(c).cpu().numpy()
+
+
+def test_bc_closed_forms():
+    n = 40
+    G, _ = graph_from_edges(*Gs.path(n))
+    assert_bc_close(bc_host(G, list(range(n))), [2.0 * i * (n - 1 - i) for i in range(n)])
+    assert_bc_close(bc_host(G, [0]), [0.0] + [float(n - 1 - i) for i in range(1, n)])
+    G, _ = graph_from_edges(*Gs.star(30))
+    got = bc_host(G, list(range(30)))
+    assert got[0] == 29 * 28 and (got[1:] == 0).all()
+    G, _ = graph_from_edges(*Gs.complete(12))
+    assert (bc_host(G, list(range(12))) == 0).all()
+
+
+@pytest.mark.parametrize("scale,ef,seed,ns", [(10, 16, 1, 8), (10, 16, 1, 100), (12, 8, 102, 64),
+                                              (14, 16, 103, 64)])
+def test_bc_rmat_against_brandes(scale, ef, seed, ns):
+    n, s, d = rmat(scale, ef, seed)
+    G = device_graph(n, s, d)
+    rp, ci = oracle.build_adjacency(n, s, d)
+    srcs = graphgen.sources(n, s, d, ns, seed)
+    assert_bc_close(bc_host(G, srcs), oracle.brandes(rp, ci, srcs))
+
+
+def test_bc_duplicate_and_isolated_sources():
+    G, (rp, ci) = graph_from_edges(8, [(0, 1), (1, 2), (2, 3), (3, 0), (2, 4)])
+    srcs = [2, 2, 7, 0]
+    assert_bc_close(bc_host(G, srcs), oracle.brandes(rp, ci, srcs))
+
+
+def test_bc_large_config_one_batch():
+    n, s, d = rmat(18, 16, 3)
+    G = device_graph(n, s, d)
+    rp, ci = oracle.build_adjacency(n, s, d)
+    srcs = graphgen.sources(n, s, d, 256, 3)[:64]
+    assert_bc_close(bc_host(G, srcs), oracle.brandes(rp, ci, srcs))
