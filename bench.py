@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path on one MI355X.
+
+Workload (one step): on the seeded R-MAT graph of 2^20 vertices, edge
+factor 16 (a/b/c/d = .57/.19/.19/.05, symmetrised, no self-loops or
+duplicates, int64 row offsets, int32 column ids):
+  * triangle count from the adjacency matrix: degree order, relabel,
+    strictly lower part L, fused masked C<s(L)> = L plus.pair L^T + reduce
+    (Algorithm 6);
+  * direction-optimising BFS (Algorithm 2) from 64 seeded non-isolated
+    sources, parents written in the same pass.
+The primary number is TC edges/s = nnz(L) / (time of the whole triangle
+count).  BFS GTEPS (harmonic mean over the 64 sources of reached
+undirected edges / time), the prepared-graph TC rate and, on the 2^18
+graph, the betweenness seconds per 64-source batch (4 batches) are reported
+beside it.  Inputs are resident in device memory before timing starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-bc", action="store_true")
+    p.add_argument("--cpu-stride", type=int, default=4,
+                   help="oracle CPU sample: every stride-th row of the triangle count")
+    return p.parse_args()
+
+
+def kernel_source_sha(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+TC_KERNEL_FILES = ["paper_2104_01661_amd/csrc/tc.hip", "paper_2104_01661_amd/csrc/tc_device.h"]
+
+
+def load_counters(name, files):
+    """HBM traffic counters committed under profiles/, valid only while the
+    kernel's sources are unchanged."""
+    path = os.path.join(ROOT, "profiles", f"{name}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        c = json.load(f)
+    if c.get("kernel_source_sha") != kernel_source_sha(files):
+        return None
+    return c
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    from paper_2104_01661_amd import lagr as L
+
+    L.use_torch_allocator(True)
+    ctx = L.Context(0)
+    dev = torch.device("cuda", 0)
+
+    # ------------------------------------------------------------ inputs
+    cfg = graphgen.LARGE
+    n, src, dst = graphgen.rmat_edges(cfg["scale"], cfg["edge_factor"], cfg["seed"])
+    sources = [int(x) for x in graphgen.sources(n, src, dst, cfg["bfs_sources"], cfg["seed"])]
+    A = L.Matrix.build(ctx, n, n, torch.from_numpy(src).to(dev), torch.from_numpy(dst).to(dev),
+                       L.BUILD_SYMMETRIZE | L.BUILD_DROP_LOOPS)
+    G = L.Graph(ctx, A)
+    G.check(ctx)
+    Am = G.matrix()
+    _, _, _, nnzA = Am.info()
+    arp, aci, _ = Am.to_csr(ctx)
+    deg = torch.diff(arp).cpu().numpy()
+
+    # algorithmic byte model of the fused masked dot (one launch):
+    # stream L once (row offsets + column ids) and, per entry (i, j) of L,
+    # read the two offsets of row j (16 B) and its len(L_j) column ids.
+    L.lagr_property_tc_lower(G, ctx)
+    Lm = G.tc_lower()
+    lrp, lci, _ = Lm.to_csr(ctx)
+    nnzL = int(lci.numel())
+    llen = torch.diff(lrp)
+    gather = int(llen[lci.long()].sum().item())
+    tc_bytes = 8 * (n + 1) + 4 * nnzL + 16 * nnzL + 4 * gather
+
+    # per-source traversed edges for GTEPS: undirected edges in the reached set
+    reached_edges = []
+    for s in sources:
+        lv, _ = L.lagr_bfs(G, s, ctx, want_parent=False)
+        lvl = lv.values_full(ctx).cpu().numpy()
+        reached_edges.append(int(deg[lvl >= 0].sum()) // 2)
+    n_small_component = sum(1 for m in reached_edges if m < nnzA // 4)
+
+    # -------------------------------------------------------------- step
+    ev_tc = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev_bfs = [torch.cuda.Event(enable_timing=True) for _ in range(len(sources) + 1)]
+    tc_counts = []
+
+    def step(record):
+        G.delete_properties(ctx)
+        if record:
+            ev_tc[0].record()
+        t = L.lagr_tc(G, ctx)
+        if record:
+            ev_tc[1].record()
+            ev_bfs[0].record()
+        for k, s in enumerate(sources):
+            _, pv = L.lagr_bfs(G, s, ctx, want_level=False)
+            if record:
+                ev_bfs[k + 1].record()
+            del pv
+        tc_counts.append(t)
+
+    for _ in range(args.warmup):
+        step(False)
+    tc_ms, bfs_ms = [], []
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+        torch.cuda.synchronize()
+        tc_ms.append(ev_tc[0].elapsed_time(ev_tc[1]))
+        bfs_ms.append([ev_bfs[k].elapsed_time(ev_bfs[k + 1]) for k in range(len(sources))])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    kt = {k: ctx.kernel_time(k) for k in ("tc_rows", "bfs_push", "bfs_pull")}
+    ctx.timing(False)
+    assert len(set(tc_counts)) == 1, "triangle count changed between steps"
+
+    # prepared-graph triangle count (masked mxm + reduce only)
+    prep = []
+    for _ in range(max(3, args.steps)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        L.lagr_tc_adv(G, ctx)
+        e1.record()
+        torch.cuda.synchronize()
+        prep.append(e0.elapsed_time(e1))
+
+    tc_med = float(np.median(tc_ms))
+    tc_rate = nnzL / (tc_med * 1e-3)
+    bfs_arr = np.array(bfs_ms)                       # steps x sources
+    bfs_med_per_src = np.median(bfs_arr, axis=0)     # ms
+    teps = np.array(reached_edges) / (bfs_med_per_src * 1e-3)
+    gteps_hmean = float(len(teps) / np.sum(1.0 / teps)) / 1e9
+    gteps_aggr = float(np.sum(reached_edges) / (np.sum(bfs_med_per_src) * 1e-3)) / 1e9
+
+    tc_kernel_ms = kt["tc_rows"][0] / max(1, kt["tc_rows"][1])
+    achieved = tc_bytes / (tc_kernel_ms * 1e-3) / 1e9
+    counters = load_counters("tc_rows", TC_KERNEL_FILES)
+    traffic = None
+    if counters:
+        traffic = int((counters["fetch_kib"] * counters["fetch_scale"]
+                       + counters["write_kib"] * counters["write_scale"]) * 1024)
+    roofline = {"bound": "hbm", "kernel": "k_tc_rows (fused masked plus.pair + reduce)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes": tc_bytes, "kernel_ms": round(tc_kernel_ms, 4)}
+
+    out = {
+        "metric": "TC edges/s, BFS GTEPS (R-MAT s20)",
+        "value": round(tc_rate, 1),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "vertices": n, "entries_A": nnzA,
+                   "undirected_edges": nnzL, "triangles": tc_counts[0],
+                   "bfs_sources": len(sources)},
+        "tc": {"ms_median": round(tc_med, 4), "edges_per_s_prepared":
+               round(nnzL / (float(np.median(prep)) * 1e-3), 1),
+               "ms_prepared_median": round(float(np.median(prep)), 4)},
+        "bfs": {"gteps_hmean": round(gteps_hmean, 4), "gteps_aggregate": round(gteps_aggr, 4),
+                "ms_median": round(float(np.median(bfs_med_per_src)), 4),
+                "sources_outside_giant_component": n_small_component,
+                "push_ms_per_step": round(kt["bfs_push"][0] / args.steps, 4),
+                "pull_ms_per_step": round(kt["bfs_pull"][0] / args.steps, 4)},
+        "roofline": roofline,
+    }
+
+    # ------------------------------------------------ betweenness (2^18)
+    if not args.no_bc:
+        bcfg = graphgen.BC
+        bn, bs, bd = graphgen.rmat_edges(bcfg["scale"], bcfg["edge_factor"], bcfg["seed"])
+        bsrc = graphgen.sources(bn, bs, bd, bcfg["batches"] * bcfg["batch_size"], bcfg["seed"])
+        BA = L.Matrix.build(ctx, bn, bn, torch.from_numpy(bs).to(dev), torch.from_numpy(bd).to(dev),
+                            L.BUILD_SYMMETRIZE | L.BUILD_DROP_LOOPS)
+        BG = L.Graph(ctx, BA)
+        BG.check(ctx)
+        L.lagr_bc(BG, bsrc[:64], ctx)
+        bc_runs = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            c = L.lagr_bc(BG, bsrc, ctx)
+            e1.record()
+            torch.cuda.synchronize()
+            bc_runs.append(e0.elapsed_time(e1))
+            del c
+        out["bc"] = {"workload": bcfg["name"], "s_per_batch":
+                     round(float(np.median(bc_runs)) * 1e-3 / bcfg["batches"], 6),
+                     "batches": bcfg["batches"], "batch_size": bcfg["batch_size"], "dtype": "f64"}
+
+    # ------------------------------------------------ CPU oracle baseline
+    if not args.no_cpu_baseline:
+        import oracle
+        orp, oci = oracle.build_adjacency(n, src, dst)
+        stride = max(1, args.cpu_stride)
+        rows = np.arange(0, n, stride)
+        # edges the sample processes: (u, v) with v > u for the sampled rows u
+        up = np.zeros(n, dtype=np.int64)
+        idx = np.repeat(np.arange(n), np.diff(orp))
+        np.add.at(up, idx[oci > idx], 1)
+        edges = int(up[rows].sum())
+        c0 = time.perf_counter()
+        oracle.triangle_count_rows(orp, oci, 0, n, stride)
+        c1 = time.perf_counter()
+        out["cpu_baseline"] = {"value": round(edges / (c1 - c0), 1), "unit": "edges/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"triangle count of rows u = 0, {stride}, {2 * stride}, ... "
+                                         f"({edges} of {nnzL} undirected edges) of the same graph, "
+                                         f"single-threaded C, {c1 - c0:.1f} s"}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

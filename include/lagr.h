@@ -167,6 +167,15 @@ int lagr_ctx_set_stream(lagr_ctx ctx, void *stream, char *msg);
 int lagr_ctx_free(lagr_ctx *ctx);
 /* Wait for all work queued on the context's stream. */
 int lagr_wait(lagr_ctx ctx, char *msg);
+/* Kernel timing (Section V, Tic/Toc): while enabled, the library brackets
+ * each launch of its main kernels with HIP events on the context's stream.
+ * lagr_ctx_kernel_time synchronises and returns the summed duration (ms)
+ * and launch count of the kernel named `kernel` (e.g. "tc_rows",
+ * "bfs_push", "bfs_pull", "bc_forward", "bc_backward") since the timer was
+ * last enabled; enabling again clears the record. */
+int lagr_ctx_timing(lagr_ctx ctx, int enable, char *msg);
+int lagr_ctx_kernel_time(lagr_ctx ctx, const char *kernel, double *total_ms, int64_t *launches,
+                         char *msg);
 
 /* ------------------------------------------------------------ matrices */
 
@@ -299,8 +308,14 @@ int lagr_property_row_degree(lagr_graph G, lagr_ctx ctx, char *msg);
 /* The triangle-count operand: A relabelled by descending degree and its
  * strictly lower part (Algorithm 6, the degree sort and L = tril(A)). */
 int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg);
-/* Read access to G->A and the cached row degree (NULL if not cached). */
+/* Drop the cached property arrays -- row degree and the triangle-count
+ * operand (Section V, DeleteProperties).  The results of lagr_graph_check
+ * (ndiag, symmetry) describe A, which a graph never changes, and are kept. */
+int lagr_graph_delete_properties(lagr_graph G, lagr_ctx ctx, char *msg);
+/* Borrowed read access to G->A and to the cached triangle-count operand
+ * (NULL if not computed).  The handles stay owned by G: do not free them. */
 int lagr_graph_matrix(lagr_matrix *A, const lagr_graph G, char *msg);
+int lagr_graph_tc_lower(lagr_matrix *L, const lagr_graph G, char *msg);
 int lagr_graph_ndiag(int64_t *ndiag, const lagr_graph G, char *msg);
 int lagr_graph_free(lagr_graph *G);
 

@@ -50,7 +50,7 @@ def _load():
         lib.orc_tc.restype = _I
         lib.orc_tc.argtypes = [_I, _P, _P]
         lib.orc_tc_rows.restype = _I
-        lib.orc_tc_rows.argtypes = [_I, _P, _P, _I, _I]
+        lib.orc_tc_rows.argtypes = [_I, _P, _P, _I, _I, _I]
         lib.orc_tc_lower_counts.restype = _I
         lib.orc_tc_lower_counts.argtypes = [_I, _P, _P, _P, _P, _P]
         lib.orc_bfs.restype = ctypes.c_int
@@ -96,10 +96,11 @@ def triangle_count(rowptr, colidx) -> int:
     return int(_load().orc_tc(rowptr.size - 1, pr, pc))
 
 
-def triangle_count_rows(rowptr, colidx, u0: int, u1: int) -> int:
+def triangle_count_rows(rowptr, colidx, u0: int, u1: int, stride: int = 1) -> int:
+    """Triangles whose smallest vertex is one of u0, u0+stride, ... < u1."""
     rowptr, pr = _c(rowptr, np.int64)
     colidx, pc = _c(colidx, np.int32)
-    return int(_load().orc_tc_rows(rowptr.size - 1, pr, pc, u0, u1))
+    return int(_load().orc_tc_rows(rowptr.size - 1, pr, pc, u0, u1, stride))
 
 
 def lower_counts(rowptr, colidx):

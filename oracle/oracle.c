@@ -101,13 +101,15 @@ int64_t orc_tc(int64_t n, const int64_t *rp, const int32_t *ci)
     return t;
 }
 
-/* Same count restricted to the rows u in [u0, u1): used to time a bounded
- * sample of the full workload. */
-int64_t orc_tc_rows(int64_t n, const int64_t *rp, const int32_t *ci, int64_t u0, int64_t u1)
+/* Same count restricted to the rows u = u0, u0 + stride, ... below u1:
+ * used to time a bounded sample of the full workload. */
+int64_t orc_tc_rows(int64_t n, const int64_t *rp, const int32_t *ci, int64_t u0, int64_t u1,
+                    int64_t stride)
 {
     int64_t t = 0;
     if (u1 > n) u1 = n;
-    for (int64_t u = u0; u < u1; u++) {
+    if (stride < 1) stride = 1;
+    for (int64_t u = u0; u < u1; u += stride) {
         for (int64_t p = rp[u]; p < rp[u + 1]; p++) {
             const int32_t v = ci[p];
             if (v <= u) continue;

@@ -242,8 +242,10 @@ extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const in
             uint64_t *next = level_buf(depth + 1);
             if (!next) BC_TRY(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc level masks"));
             BC_TRY(fill_u32(ctx, flag, 1, 0u, msg));
-            hipLaunchKernelGGL(k_bc_forward, dim3(gblocks), dim3(256), 0, ctx->stream, A->rowptr,
-                               A->colidx, n, levels[depth], next, unvis, sigma, flag);
+            TIMED(ctx, "bc_forward",
+                  hipLaunchKernelGGL(k_bc_forward, dim3(gblocks), dim3(256), 0, ctx->stream,
+                                     A->rowptr, A->colidx, n, levels[depth], next, unvis, sigma,
+                                     flag));
             BC_LAUNCHED();
             unsigned h = 0;
             BC_TRY(read_back(ctx, &h, flag, sizeof(h), msg));
@@ -253,9 +255,11 @@ extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const in
         // backward sweep: targets at depth i-1 gather from depth i
         for (size_t i = depth + 1; i >= 2; i--) {
             const int has_deeper = i <= depth ? 1 : 0;
-            hipLaunchKernelGGL(k_bc_backward, dim3(gblocks), dim3(256), 0, ctx->stream, A->rowptr,
-                               A->colidx, n, has_deeper ? levels[i] : levels[i - 1], levels[i - 1],
-                               has_deeper, 1, sigma, Wv, cent);
+            TIMED(ctx, "bc_backward",
+                  hipLaunchKernelGGL(k_bc_backward, dim3(gblocks), dim3(256), 0, ctx->stream,
+                                     A->rowptr, A->colidx, n,
+                                     has_deeper ? levels[i] : levels[i - 1], levels[i - 1],
+                                     has_deeper, 1, sigma, Wv, cent));
             BC_LAUNCHED();
         }
     }

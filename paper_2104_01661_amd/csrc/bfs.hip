@@ -220,13 +220,16 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
         }
         BFS_TRY(fill_i64(ctx, (int64_t *)cnt, 2, 0, msg));
         if (pull) {
-            hipLaunchKernelGGL(k_bfs_pull, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream,
-                               rp, ci, n, lev, bm_cur, lev32, parent, visited, list_next, bm_next,
-                               cnt);
+            TIMED(ctx, "bfs_pull",
+                  hipLaunchKernelGGL(k_bfs_pull, dim3(grid_for(n, 256, 8192)), dim3(256), 0,
+                                     ctx->stream, rp, ci, n, lev, bm_cur, lev32, parent, visited,
+                                     list_next, bm_next, cnt));
         } else {
-            hipLaunchKernelGGL(k_bfs_push, dim3(grid_for(nq * 64, 256, 8192)), dim3(256), 0,
-                               ctx->stream, rp, ci, list_cur, nq, lev, any_parent, lev32,
-                               (unsigned long long *)parent, visited, list_next, bm_next, cnt);
+            TIMED(ctx, "bfs_push",
+                  hipLaunchKernelGGL(k_bfs_push, dim3(grid_for(nq * 64, 256, 8192)), dim3(256), 0,
+                                     ctx->stream, rp, ci, list_cur, nq, lev, any_parent, lev32,
+                                     (unsigned long long *)parent, visited, list_next, bm_next,
+                                     cnt));
         }
         if (hipGetLastError() != hipSuccess) {
             cleanup();

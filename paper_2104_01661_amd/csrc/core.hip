@@ -16,6 +16,8 @@ int lagr_fail(char *msg, int code, const char *fmt, ...)
     return code;
 }
 
+static void timers_clear(lagr_ctx ctx);
+
 // ------------------------------------------------------------- allocator
 
 static lagr_alloc_fn g_alloc = nullptr;
@@ -91,6 +93,7 @@ extern "C" int lagr_ctx_free(lagr_ctx *ctx)
     if (!ctx || !*ctx) return LAGR_SUCCESS;
     lagr_ctx c = *ctx;
     (void)hipStreamSynchronize(c->stream);
+    timers_clear(c);
     for (int s = 0; s < WS_NSLOTS; s++) dev_free(c->ws[s], c->ws_bytes[s]);
     if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
@@ -102,6 +105,61 @@ extern "C" int lagr_wait(lagr_ctx ctx, char *msg)
 {
     if (!ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "ctx is NULL");
     HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return lagr_ok(msg);
+}
+
+// ----------------------------------------------------------- kernel timing
+
+static void timers_clear(lagr_ctx ctx)
+{
+    for (auto &t : ctx->timers) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    ctx->timers.clear();
+}
+
+void timer_begin(lagr_ctx ctx, const char *name, hipEvent_t *stop)
+{
+    KernelTimer t;
+    t.name = name;
+    if (hipEventCreate(&t.start) != hipSuccess) return;
+    if (hipEventCreate(&t.stop) != hipSuccess) {
+        (void)hipEventDestroy(t.start);
+        return;
+    }
+    (void)hipEventRecord(t.start, ctx->stream);
+    *stop = t.stop;
+    ctx->timers.push_back(t);
+}
+
+void timer_end(lagr_ctx ctx, hipEvent_t stop) { (void)hipEventRecord(stop, ctx->stream); }
+
+extern "C" int lagr_ctx_timing(lagr_ctx ctx, int enable, char *msg)
+{
+    if (!ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    timers_clear(ctx);
+    ctx->timing = enable ? 1 : 0;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_ctx_kernel_time(lagr_ctx ctx, const char *kernel, double *total_ms,
+                                    int64_t *launches, char *msg)
+{
+    if (!ctx || !kernel) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (auto &t : ctx->timers) {
+        if (t.name != kernel) continue;
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, t.start, t.stop));
+        tot += ms;
+        cnt++;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = cnt;
     return lagr_ok(msg);
 }
 

@@ -469,6 +469,28 @@ extern "C" int lagr_graph_matrix(lagr_matrix *A, const lagr_graph G, char *msg)
     return lagr_ok(msg);
 }
 
+extern "C" int lagr_graph_tc_lower(lagr_matrix *L, const lagr_graph G, char *msg)
+{
+    if (!L || !G) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *L = G->L;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_graph_delete_properties(lagr_graph G, lagr_ctx ctx, char *msg)
+{
+    if (!G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    const int64_t n = G->A ? G->A->nrows : 0;
+    if (G->row_degree) dev_free(G->row_degree, sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    G->row_degree = nullptr;
+    G->max_degree = -1;
+    lagr_matrix_free(&G->L);
+    G->L_maxrow = -1;
+    // ndiag and the symmetry flag describe A, which a graph never changes:
+    // the results of lagr_graph_check stay valid and are kept
+    return lagr_ok(msg);
+}
+
 extern "C" int lagr_graph_ndiag(int64_t *ndiag, const lagr_graph G, char *msg)
 {
     if (!ndiag || !G) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");

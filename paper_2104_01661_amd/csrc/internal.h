@@ -10,6 +10,9 @@
 
 #include "../../include/lagr.h"
 
+#include <string>
+#include <vector>
+
 // ------------------------------------------------------------------ errors
 
 int lagr_fail(char *msg, int code, const char *fmt, ...);
@@ -81,7 +84,14 @@ enum WsSlot {
     WS_NSLOTS
 };
 
+struct KernelTimer {
+    std::string name;
+    hipEvent_t start, stop;
+};
+
 struct lagr_ctx_s {
+    int timing = 0;
+    std::vector<KernelTimer> timers;
     int device = 0;
     hipStream_t stream = nullptr;
     void *ws[WS_NSLOTS] = {};
@@ -132,6 +142,17 @@ void matrix_release_arrays(lagr_matrix A);
 void vector_release_arrays(lagr_vector v);
 // Allocate owned arrays for a CSR of the given size (rowptr always).
 int matrix_alloc(lagr_matrix A, int64_t nvals, char *msg);
+
+// Kernel timing: TIMED_LAUNCH(ctx, "name", launch-expression)
+void timer_begin(lagr_ctx ctx, const char *name, hipEvent_t *stop);
+void timer_end(lagr_ctx ctx, hipEvent_t stop);
+#define TIMED(ctx, name, ...)                                   \
+    do {                                                        \
+        hipEvent_t stop_ev_ = nullptr;                          \
+        if ((ctx)->timing) timer_begin((ctx), (name), &stop_ev_);\
+        __VA_ARGS__;                                            \
+        if (stop_ev_) timer_end((ctx), stop_ev_);               \
+    } while (0)
 
 // ------------------------------------------------------------- primitives
 

@@ -82,11 +82,13 @@ int tc_masked_dot(lagr_ctx ctx, const TcArgs &a, int64_t max_arow, bool per_entr
     // enough waves to fill 256 CUs several times over, each striding rows
     const int64_t blocks = grid_for(a.nrows, TC_WAVES, 2048L * 8);
     if (per_entry)
-        hipLaunchKernelGGL(k_tc_rows<true>, dim3((unsigned)blocks), dim3(TC_BLOCK), 0, ctx->stream,
-                           a, total_dev, entry_counts);
+        TIMED(ctx, "tc_rows_entries",
+              hipLaunchKernelGGL(k_tc_rows<true>, dim3((unsigned)blocks), dim3(TC_BLOCK), 0,
+                                 ctx->stream, a, total_dev, entry_counts));
     else
-        hipLaunchKernelGGL(k_tc_rows<false>, dim3((unsigned)blocks), dim3(TC_BLOCK), 0, ctx->stream,
-                           a, total_dev, entry_counts);
+        TIMED(ctx, "tc_rows",
+              hipLaunchKernelGGL(k_tc_rows<false>, dim3((unsigned)blocks), dim3(TC_BLOCK), 0,
+                                 ctx->stream, a, total_dev, entry_counts));
     LAUNCH_CHECK();
     if (max_arow > TC_HASH_MAX_ROW) {
         const unsigned g = grid_for(a.nrows, 1, 4096);

@@ -65,6 +65,8 @@ _PROTOS = {
     "lagr_ctx_set_stream": [_P, _P, _C],
     "lagr_ctx_free": [_PP],
     "lagr_wait": [_P, _C],
+    "lagr_ctx_timing": [_P, _INT, _C],
+    "lagr_ctx_kernel_time": [_P, _C, _P, _P, _C],
     "lagr_matrix_new": [_PP, _INT, _I64, _I64, _P, _C],
     "lagr_matrix_wrap_csr": [_PP, _INT, _I64, _I64, _I64, _P, _P, _P, _P, _C],
     "lagr_matrix_build": [_PP, _I64, _I64, _I64, _P, _P, _U32, _P, _C],
@@ -97,6 +99,8 @@ _PROTOS = {
     "lagr_property_row_degree": [_P, _P, _C],
     "lagr_property_tc_lower": [_P, _P, _C],
     "lagr_graph_matrix": [_PP, _P, _C],
+    "lagr_graph_tc_lower": [_PP, _P, _C],
+    "lagr_graph_delete_properties": [_P, _P, _C],
     "lagr_graph_ndiag": [_P, _P, _C],
     "lagr_graph_free": [_PP],
     "lagr_tc": [_P, _P, _P, _C],
@@ -185,6 +189,15 @@ class Context:
     def wait(self):
         call("lagr_wait", self.h)
 
+    def timing(self, enable: bool):
+        call("lagr_ctx_timing", self.h, 1 if enable else 0)
+
+    def kernel_time(self, kernel: str):
+        """(total ms, launches) of a library kernel since timing was enabled."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        call("lagr_ctx_kernel_time", self.h, kernel.encode(), ctypes.byref(ms), ctypes.byref(n))
+        return ms.value, n.value
+
     def free(self):
         if self.h:
             call_nomsg("lagr_ctx_free", ctypes.byref(self.h))
@@ -251,7 +264,7 @@ class Matrix:
         return rp, ci, va
 
     def free(self):
-        if self.h:
+        if self.h and not getattr(self, "_borrowed", False):
             call_nomsg("lagr_matrix_free", ctypes.byref(self.h))
 
     def __del__(self):
@@ -361,6 +374,26 @@ class Graph:
 
     def check(self, ctx):
         call("lagr_graph_check", self.h, ctx.h)
+
+    def delete_properties(self, ctx):
+        call("lagr_graph_delete_properties", self.h, ctx.h)
+
+    def _borrowed(self, fn):
+        h = ctypes.c_void_p()
+        call(fn, ctypes.byref(h), self.h)
+        if not h:
+            return None
+        M = Matrix(h)
+        M._borrowed = True
+        return M
+
+    def matrix(self):
+        """Borrowed handle of the adjacency matrix (owned by the graph)."""
+        return self._borrowed("lagr_graph_matrix")
+
+    def tc_lower(self):
+        """Borrowed handle of the cached triangle-count operand, or None."""
+        return self._borrowed("lagr_graph_tc_lower")
 
     def ndiag(self):
         v = ctypes.c_int64()

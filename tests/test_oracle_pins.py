@@ -95,6 +95,8 @@ def test_tc_rows_partition_sums_to_total():
     rp, ci = adj(g)
     parts = sum(oracle.triangle_count_rows(rp, ci, a, a + 17) for a in range(0, 80, 17))
     assert parts == oracle.triangle_count(rp, ci)
+    strided = sum(oracle.triangle_count_rows(rp, ci, r, 80, 3) for r in range(3))
+    assert strided == oracle.triangle_count(rp, ci)
 
 
 # ------------------------------------------------------------- BFS (Alg 1/2)
