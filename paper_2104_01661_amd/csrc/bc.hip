@@ -25,6 +25,11 @@
 
 namespace {
 
+// Vertices with more neighbours than BC_LONG are split into BC_CHUNK-long
+// pieces (hub vertices would otherwise hold one wave for the whole level).
+constexpr int64_t BC_LONG = GRAPH_LONG_ROW;
+constexpr int64_t BC_CHUNK = GRAPH_LONG_ROW;
+
 __global__ __launch_bounds__(256) void k_bc_init(int64_t n, uint64_t lanes,
                                                  uint64_t *__restrict__ unvis,
                                                  uint64_t *__restrict__ mask0)
@@ -68,13 +73,14 @@ __global__ __launch_bounds__(256) void k_bc_forward(const int64_t *__restrict__ 
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const unsigned lane = lane_id();
     for (int64_t v = wave; v < n; v += nw) {
+        const int64_t b = rp[v], e = rp[v + 1];
+        if (e - b > BC_LONG) continue;   // k_bc_forward_chunks
         const uint64_t uv = unvis[v];
         if (uv == 0) {
             if (lane == 0) next[v] = 0;
             continue;
         }
         double acc = 0.0;
-        const int64_t b = rp[v], e = rp[v + 1];
         for (int64_t p0 = b; p0 < e; p0 += 64) {
             const int64_t p = p0 + lane;
             int32_t u = 0;
@@ -117,11 +123,12 @@ __global__ __launch_bounds__(256) void k_bc_backward(const int64_t *__restrict__
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const unsigned lane = lane_id();
     for (int64_t v = wave; v < n; v += nw) {
+        const int64_t b = rp[v], e = rp[v + 1];
+        if (e - b > BC_LONG) continue;   // k_bc_backward_chunks
         const uint64_t dm = at_im1[v];
         if (dm == 0) continue;
         double acc = 0.0;
         if (has_deeper) {
-            const int64_t b = rp[v], e = rp[v + 1];
             for (int64_t p0 = b; p0 < e; p0 += 64) {
                 const int64_t p = p0 + lane;
                 int32_t w = 0;
@@ -155,7 +162,135 @@ __global__ __launch_bounds__(256) void k_bc_backward(const int64_t *__restrict__
     }
 }
 
+// Hub vertices (more than BC_LONG neighbours): every chunk of the neighbour
+// list is gathered by its own wave into partial[chunk][lane]; the combine
+// kernels add a vertex's chunk partials in chunk order and finish the
+// level exactly as the per-vertex kernels do.
+__device__ __forceinline__ double gather_lanes(const int32_t *__restrict__ ci, int64_t b, int64_t e,
+                                               const uint64_t *__restrict__ lvl, uint64_t want,
+                                               const double *__restrict__ val, unsigned lane)
+{
+    double acc = 0.0;
+    for (int64_t p0 = b; p0 < e; p0 += 64) {
+        const int64_t p = p0 + lane;
+        int32_t u = 0;
+        uint64_t fm = 0;
+        if (p < e) {
+            u = ci[p];
+            fm = lvl[u] & want;
+        }
+        uint64_t hits = __ballot(fm != 0);
+        while (hits) {
+            const int t = __ffsll((unsigned long long)hits) - 1;
+            hits &= hits - 1;
+            const int32_t uu = __shfl(u, t, 64);
+            const uint64_t m = shfl64(fm, t);
+            if ((m >> lane) & 1ull) acc += val[(int64_t)uu * 64 + lane];
+        }
+    }
+    return acc;
+}
+
+__global__ __launch_bounds__(256) void k_bc_forward_chunks(const int32_t *__restrict__ ci, RowChunks ch,
+                                                           const uint64_t *__restrict__ cur,
+                                                           const uint64_t *__restrict__ unvis,
+                                                           const double *__restrict__ sigma,
+                                                           double *__restrict__ partial)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t c = wave; c < ch.n; c += nw) {
+        const uint64_t uv = unvis[ch.row[c]];
+        if (uv == 0) continue;
+        partial[c * 64 + lane] = gather_lanes(ci, ch.beg[c], ch.end[c], cur, uv, sigma, lane);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bc_forward_combine(const int64_t *__restrict__ rp, RowChunks ch,
+                                                            const double *__restrict__ partial,
+                                                            uint64_t *__restrict__ next,
+                                                            uint64_t *__restrict__ unvis,
+                                                            double *__restrict__ sigma,
+                                                            unsigned *__restrict__ any_new)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t c = wave; c < ch.n; c += nw) {
+        const int64_t v = ch.row[c];
+        if (ch.beg[c] != rp[v]) continue;   // first chunk of its vertex only
+        const uint64_t uv = unvis[v];
+        if (uv == 0) {
+            if (lane == 0) next[v] = 0;
+            continue;
+        }
+        const int64_t k = (rp[v + 1] - rp[v] + BC_CHUNK - 1) / BC_CHUNK;
+        double acc = 0.0;
+        for (int64_t q = 0; q < k; q++) acc += partial[(c + q) * 64 + lane];
+        const uint64_t nw_mask = __ballot(acc > 0.0) & uv;
+        if ((nw_mask >> lane) & 1ull) sigma[v * 64 + lane] = acc;
+        if (lane == 0) {
+            next[v] = nw_mask;
+            if (nw_mask) {
+                unvis[v] = uv & ~nw_mask;
+                atomicOr(any_new, 1u);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bc_backward_chunks(const int32_t *__restrict__ ci, RowChunks ch,
+                                                            const uint64_t *__restrict__ at_i,
+                                                            const uint64_t *__restrict__ at_im1,
+                                                            const double *__restrict__ W,
+                                                            double *__restrict__ partial)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t c = wave; c < ch.n; c += nw) {
+        const uint64_t dm = at_im1[ch.row[c]];
+        if (dm == 0) continue;
+        partial[c * 64 + lane] = gather_lanes(ci, ch.beg[c], ch.end[c], at_i, dm, W, lane);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bc_backward_combine(const int64_t *__restrict__ rp, RowChunks ch,
+                                                             const uint64_t *__restrict__ at_im1,
+                                                             int has_deeper,
+                                                             const double *__restrict__ partial,
+                                                             const double *__restrict__ sigma,
+                                                             double *__restrict__ W,
+                                                             double *__restrict__ centrality)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t c = wave; c < ch.n; c += nw) {
+        const int64_t v = ch.row[c];
+        if (ch.beg[c] != rp[v]) continue;
+        const uint64_t dm = at_im1[v];
+        if (dm == 0) continue;
+        double acc = 0.0;
+        if (has_deeper) {
+            const int64_t k = (rp[v + 1] - rp[v] + BC_CHUNK - 1) / BC_CHUNK;
+            for (int64_t q = 0; q < k; q++) acc += partial[(c + q) * 64 + lane];
+        }
+        double delta = 0.0;
+        if ((dm >> lane) & 1ull) {
+            const double s = sigma[v * 64 + lane];
+            delta = s * acc;
+            W[v * 64 + lane] = (1.0 + delta) / s;
+        }
+        double t = delta;
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        if (lane == 0) centrality[v] += t;
+    }
+}
+
 }  // namespace
+
 
 extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const int64_t *sources,
                        int32_t ns, lagr_ctx ctx, char *msg)
@@ -223,6 +358,15 @@ extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const in
 
     BC_TRY(fill_i64(ctx, (int64_t *)cent, n, 0, msg));   // 0.0 has all-zero bits
     const unsigned gblocks = grid_for(n * 64, 256, 16384);
+    RowChunks ch;
+    BC_TRY(graph_chunks(G, ctx, &ch, msg));
+    double *partial = nullptr;
+    unsigned cblocks = 1;
+    if (ch.n > 0) {
+        partial = (double *)ws_get(ctx, WS_BC_MASKS, sizeof(double) * 64 * (size_t)ch.n);
+        if (!partial) BC_TRY(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc chunk partials"));
+        cblocks = grid_for(ch.n * 64, 256, 16384);
+    }
     for (int32_t b0 = 0; b0 < ns; b0 += 64) {
         const int nb = (ns - b0) < 64 ? (ns - b0) : 64;
         const uint64_t lanes = nb == 64 ? ~0ull : ((1ull << nb) - 1);
@@ -247,6 +391,16 @@ extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const in
                                      A->rowptr, A->colidx, n, levels[depth], next, unvis, sigma,
                                      flag));
             BC_LAUNCHED();
+            if (ch.n > 0) {
+                TIMED(ctx, "bc_forward_chunks",
+                      hipLaunchKernelGGL(k_bc_forward_chunks, dim3(cblocks), dim3(256), 0,
+                                         ctx->stream, A->colidx, ch, levels[depth], unvis, sigma,
+                                         partial));
+                BC_LAUNCHED();
+                hipLaunchKernelGGL(k_bc_forward_combine, dim3(cblocks), dim3(256), 0, ctx->stream,
+                                   A->rowptr, ch, partial, next, unvis, sigma, flag);
+                BC_LAUNCHED();
+            }
             unsigned h = 0;
             BC_TRY(read_back(ctx, &h, flag, sizeof(h), msg));
             if (!h) break;
@@ -255,12 +409,25 @@ extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const in
         // backward sweep: targets at depth i-1 gather from depth i
         for (size_t i = depth + 1; i >= 2; i--) {
             const int has_deeper = i <= depth ? 1 : 0;
+            const uint64_t *at_i = has_deeper ? levels[i] : levels[i - 1];
             TIMED(ctx, "bc_backward",
                   hipLaunchKernelGGL(k_bc_backward, dim3(gblocks), dim3(256), 0, ctx->stream,
-                                     A->rowptr, A->colidx, n,
-                                     has_deeper ? levels[i] : levels[i - 1], levels[i - 1],
-                                     has_deeper, 1, sigma, Wv, cent));
+                                     A->rowptr, A->colidx, n, at_i, levels[i - 1], has_deeper, 1,
+                                     sigma, Wv, cent));
             BC_LAUNCHED();
+            if (ch.n > 0) {
+                if (has_deeper) {
+                    TIMED(ctx, "bc_backward_chunks",
+                          hipLaunchKernelGGL(k_bc_backward_chunks, dim3(cblocks), dim3(256), 0,
+                                             ctx->stream, A->colidx, ch, at_i, levels[i - 1], Wv,
+                                             partial));
+                    BC_LAUNCHED();
+                }
+                hipLaunchKernelGGL(k_bc_backward_combine, dim3(cblocks), dim3(256), 0, ctx->stream,
+                                   A->rowptr, ch, levels[i - 1], has_deeper, partial, sigma, Wv,
+                                   cent);
+                BC_LAUNCHED();
+            }
         }
     }
     cleanup();

@@ -12,6 +12,8 @@
 //   pull: one lane per unvisited vertex v scans N(v) in ascending order
 //         and stops at the first neighbour in the frontier bitmap, which is
 //         the smallest valid parent.
+//   The frontier's hub vertices (rows longer than GRAPH_LONG_ROW) are
+//   pushed chunk by chunk by separate waves, so no wave walks a whole hub.
 // Direction (Beamer, Asanovic and Patterson, SC 2012, the heuristic the
 // paper cites): pull when the frontier's edges exceed the unexplored edges
 // / ALPHA, back to push when the frontier has fewer than n / BETA vertices.
@@ -56,6 +58,29 @@ __global__ __launch_bounds__(256) void k_bfs_init(int64_t src, int32_t *level, i
     }
 }
 
+// Push the neighbours rp-range [b, e) of frontier vertex u, one per lane.
+__device__ __forceinline__ void push_range(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                           int32_t u, int64_t b, int64_t e, unsigned lane, int32_t lev,
+                                           int any_parent, int32_t *__restrict__ level,
+                                           unsigned long long *__restrict__ parent,
+                                           const uint32_t *__restrict__ visited,
+                                           int32_t *__restrict__ next_list, uint32_t *__restrict__ next_bm,
+                                           BfsCounters *__restrict__ cnt)
+{
+    for (int64_t p = b + lane; p < e; p += 64) {
+        const int32_t v = ci[p];
+        if (bit_test(visited, v)) continue;
+        const int32_t old = atomicCAS(&level[v], -1, lev);
+        if (old == -1) {
+            if (any_parent) parent[v] = (unsigned long long)u;
+            else atomicMin(&parent[v], (unsigned long long)u);
+            discovered(v, rp[v + 1] - rp[v], next_list, next_bm, cnt);
+        } else if (old == lev && !any_parent) {
+            atomicMin(&parent[v], (unsigned long long)u);
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_bfs_push(const int64_t *__restrict__ rp,
                                                   const int32_t *__restrict__ ci,
                                                   const int32_t *__restrict__ frontier, int64_t nq,
@@ -73,21 +98,38 @@ __global__ __launch_bounds__(256) void k_bfs_push(const int64_t *__restrict__ rp
     for (int64_t f = wave; f < nq; f += nw) {
         const int32_t u = frontier[f];
         const int64_t b = rp[u], e = rp[u + 1];
-        for (int64_t p = b + lane; p < e; p += 64) {
-            const int32_t v = ci[p];
-            if (bit_test(visited, v)) continue;
-            const int32_t old = atomicCAS(&level[v], -1, lev);
-            if (old == -1) {
-                if (any_parent) parent[v] = (unsigned long long)u;
-                else atomicMin(&parent[v], (unsigned long long)u);
-                discovered(v, rp[v + 1] - rp[v], next_list, next_bm, cnt);
-            } else if (old == lev && !any_parent) {
-                atomicMin(&parent[v], (unsigned long long)u);
-            }
-        }
+        if (e - b > GRAPH_LONG_ROW) continue;   // k_bfs_push_chunks
+        push_range(rp, ci, u, b, e, lane, lev, any_parent, level, parent, visited, next_list,
+                   next_bm, cnt);
     }
 }
 
+// The frontier's hub vertices: every chunk of a long row whose vertex is in
+// the frontier bitmap is pushed by its own wave.
+__global__ __launch_bounds__(256) void k_bfs_push_chunks(const int64_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ ci, RowChunks ch,
+                                                         const uint32_t *__restrict__ cur_bm,
+                                                         int32_t lev, int any_parent,
+                                                         int32_t *__restrict__ level,
+                                                         unsigned long long *__restrict__ parent,
+                                                         const uint32_t *__restrict__ visited,
+                                                         int32_t *__restrict__ next_list,
+                                                         uint32_t *__restrict__ next_bm,
+                                                         BfsCounters *__restrict__ cnt)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t c = wave; c < ch.n; c += nw) {
+        const int32_t u = ch.row[c];
+        if (!bit_test(cur_bm, u)) continue;
+        push_range(rp, ci, u, ch.beg[c], ch.end[c], lane, lev, any_parent, level, parent, visited,
+                   next_list, next_bm, cnt);
+    }
+}
+
+// One lane per unvisited vertex: scan its neighbours in ascending order and
+// stop at the first one in the frontier bitmap, the smallest valid parent.
 __global__ __launch_bounds__(256) void k_bfs_pull(const int64_t *__restrict__ rp,
                                                   const int32_t *__restrict__ ci, int64_t n,
                                                   int32_t lev, const uint32_t *__restrict__ cur_bm,
@@ -202,6 +244,14 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
     }
     const int64_t *rp = A->rowptr;
     const int32_t *ci = A->colidx;
+    RowChunks ch;
+    {
+        int rc2 = graph_chunks(G, ctx, &ch, msg);
+        if (rc2 < 0) {
+            cleanup();
+            return rc2;
+        }
+    }
     // host copies of the per-level counters drive the direction choice
     int64_t hdeg_src = 0;
     {
@@ -230,6 +280,12 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
                                      ctx->stream, rp, ci, list_cur, nq, lev, any_parent, lev32,
                                      (unsigned long long *)parent, visited, list_next, bm_next,
                                      cnt));
+            if (ch.n > 0)
+                TIMED(ctx, "bfs_push",
+                      hipLaunchKernelGGL(k_bfs_push_chunks, dim3(grid_for(ch.n * 64, 256, 4096)),
+                                         dim3(256), 0, ctx->stream, rp, ci, ch, bm_cur, lev,
+                                         any_parent, lev32, (unsigned long long *)parent, visited,
+                                         list_next, bm_next, cnt));
         }
         if (hipGetLastError() != hipSuccess) {
             cleanup();

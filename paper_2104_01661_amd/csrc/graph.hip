@@ -6,6 +6,11 @@
 
 namespace {
 
+// Rows of at most this many entries are scanned by one thread; longer ones
+// are cut into chunks that whole wavefronts take (see row_chunks).
+constexpr int64_t LANE_ROW_MAX = 64;
+constexpr int64_t ROW_CHUNK = 2048;
+
 __global__ void k_build_keys(const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
                              int64_t nedges, int64_t nrows, int64_t ncols, int cbits, int sym,
                              int drop, uint64_t *__restrict__ keys, unsigned *__restrict__ err)
@@ -95,6 +100,36 @@ __global__ void k_copy_lower(const int64_t *__restrict__ rp, const int32_t *__re
 
 // ------------------------------------------------------- CheckGraph
 
+// One entry (i, p) of the check: in range, after its predecessor, on the
+// diagonal, mirrored.
+__device__ __forceinline__ void check_entry(const int64_t *rp, const int32_t *ci, int64_t nrows,
+                                            int64_t ncols, int want_sym, int64_t i, int64_t a,
+                                            int64_t p, unsigned &e, unsigned long long &diag)
+{
+    const int64_t j = ci[p];
+    if (j < 0 || j >= ncols) {
+        e |= 1u;
+        return;
+    }
+    if (p > a && ci[p - 1] >= j) e |= 2u;
+    if (j == i) diag++;
+    if (want_sym) {
+        if (j >= nrows) {
+            e |= 4u;
+            return;
+        }
+        int64_t lo = rp[j], hi = rp[j + 1];
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (ci[mid] < i) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo >= rp[j + 1] || ci[lo] != i) e |= 4u;
+    }
+}
+
+// Rows of at most LANE_ROW_MAX entries: one thread each; longer rows are
+// left to k_check_chunks.
 __global__ void k_check(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
                         int64_t nrows, int64_t ncols, int want_sym,
                         unsigned *__restrict__ err, unsigned long long *__restrict__ ndiag)
@@ -108,28 +143,26 @@ __global__ void k_check(const int64_t *__restrict__ rp, const int32_t *__restric
             e |= 8u;
             continue;
         }
-        for (int64_t p = a; p < b; p++) {
-            const int64_t j = ci[p];
-            if (j < 0 || j >= ncols) {
-                e |= 1u;
-                continue;
-            }
-            if (p > a && ci[p - 1] >= j) e |= 2u;
-            if (j == i) diag++;
-            if (want_sym) {
-                if (j >= nrows) {
-                    e |= 4u;
-                    continue;
-                }
-                int64_t lo = rp[j], hi = rp[j + 1];
-                while (lo < hi) {
-                    int64_t mid = (lo + hi) >> 1;
-                    if (ci[mid] < i) lo = mid + 1;
-                    else hi = mid;
-                }
-                if (lo >= rp[j + 1] || ci[lo] != i) e |= 4u;
-            }
-        }
+        if (b - a > LANE_ROW_MAX) continue;
+        for (int64_t p = a; p < b; p++) check_entry(rp, ci, nrows, ncols, want_sym, i, a, p, e, diag);
+    }
+    if (e) atomicOr(err, e);
+    if (diag) atomicAdd(ndiag, diag);
+}
+
+__global__ void k_check_chunks(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                               int64_t nrows, int64_t ncols, int want_sym, RowChunks ch,
+                               unsigned *__restrict__ err, unsigned long long *__restrict__ ndiag)
+{
+    unsigned long long diag = 0;
+    unsigned e = 0;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t c = wave; c < ch.n; c += nw) {
+        const int64_t i = ch.row[c];
+        for (int64_t p = ch.beg[c] + lane; p < ch.end[c]; p += 64)
+            check_entry(rp, ci, nrows, ncols, want_sym, i, rp[i], p, e, diag);
     }
     if (e) atomicOr(err, e);
     if (diag) atomicAdd(ndiag, diag);
@@ -153,46 +186,88 @@ __global__ void k_inverse_perm(const uint64_t *__restrict__ keys, int64_t n, uin
         inv[keys[p] & vmask] = (int32_t)p;
 }
 
-// cnt[u] = number of neighbours v of u with inv[v] < inv[u]
+// cnt[u] = number of neighbours v of u with inv[v] < inv[u], for rows of
+// at most LANE_ROW_MAX entries (one thread each; 0 for longer rows, which
+// k_count_relabel_chunks adds in).
 __global__ void k_count_relabel_lower(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                       const int32_t *__restrict__ inv, int64_t n,
                                       int64_t *__restrict__ cnt)
 {
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
-    const unsigned lane = lane_id();
-    for (int64_t u = wave; u < n; u += nw) {
-        const int32_t iu = inv[u];
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = rp[u], len = rp[u + 1] - b;
         int64_t c = 0;
-        for (int64_t p = rp[u] + lane; p < rp[u + 1]; p += 64) c += inv[ci[p]] < iu ? 1 : 0;
-        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-        if (lane == 0) cnt[u] = c;
+        if (len <= LANE_ROW_MAX) {
+            const int32_t iu = inv[u];
+            for (int64_t p = b; p < b + len; p++) c += inv[ci[p]] < iu ? 1 : 0;
+        }
+        cnt[u] = c;
     }
 }
 
+__global__ void k_count_relabel_chunks(const int32_t *__restrict__ ci, const int32_t *__restrict__ inv,
+                                       RowChunks ch, int64_t *__restrict__ cnt)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t c = wave; c < ch.n; c += nw) {
+        const int32_t u = ch.row[c];
+        const int32_t iu = inv[u];
+        unsigned long long k = 0;
+        for (int64_t p = ch.beg[c] + lane; p < ch.end[c]; p += 64) k += inv[ci[p]] < iu ? 1 : 0;
+        for (int o = 32; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
+        if (lane == 0 && k) atomicAdd((unsigned long long *)&cnt[u], k);
+    }
+}
+
+// Keys (inv[u] << vbits | inv[v]) of the relabelled strictly lower part.
+// cursor[u] starts at the row's output offset; the order inside a row does
+// not matter (the keys are sorted next).
 __global__ void k_emit_relabel_lower(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                      const int32_t *__restrict__ inv, int64_t n,
-                                     const int64_t *__restrict__ off, int vbits,
+                                     const int64_t *__restrict__ cursor, int vbits,
                                      uint64_t *__restrict__ keys)
+{
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = rp[u], len = rp[u + 1] - b;
+        if (len > LANE_ROW_MAX) continue;
+        const int32_t iu = inv[u];
+        int64_t o = cursor[u];
+        for (int64_t p = b; p < b + len; p++) {
+            const int32_t iv = inv[ci[p]];
+            if (iv < iu) keys[o++] = ((uint64_t)iu << vbits) | (uint64_t)iv;
+        }
+    }
+}
+
+__global__ void k_emit_relabel_chunks(const int32_t *__restrict__ ci, const int32_t *__restrict__ inv,
+                                      RowChunks ch, int vbits, unsigned long long *__restrict__ cursor,
+                                      uint64_t *__restrict__ keys)
 {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const unsigned lane = lane_id();
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    for (int64_t u = wave; u < n; u += nw) {
+    for (int64_t c = wave; c < ch.n; c += nw) {
+        const int32_t u = ch.row[c];
         const int32_t iu = inv[u];
-        int64_t out = off[u];
-        for (int64_t p0 = rp[u]; p0 < rp[u + 1]; p0 += 64) {
+        const int64_t e = ch.end[c];
+        for (int64_t p0 = ch.beg[c]; p0 < e; p0 += 64) {
             const int64_t p = p0 + lane;
             int32_t iv = 0;
             bool take = false;
-            if (p < rp[u + 1]) {
+            if (p < e) {
                 iv = inv[ci[p]];
                 take = iv < iu;
             }
             const uint64_t bal = __ballot(take);
-            if (take) keys[out + __popcll(bal & below)] = ((uint64_t)iu << vbits) | (uint64_t)iv;
-            out += __popcll(bal);
+            if (!bal) continue;
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(&cursor[u], (unsigned long long)__popcll(bal));
+            base = __shfl((long long)base, 0, 64);
+            if (take) keys[base + __popcll(bal & below)] = ((uint64_t)iu << vbits) | (uint64_t)iv;
         }
     }
 }
@@ -346,6 +421,15 @@ extern "C" int lagr_graph_check(lagr_graph G, lagr_ctx ctx, char *msg)
         hipLaunchKernelGGL(k_check, dim3(grid_for(A->nrows, 256, 4096)), dim3(256), 0, ctx->stream,
                            A->rowptr, A->colidx, A->nrows, A->ncols, want_sym, err, nd);
         LAUNCH_CHECK();
+        RowChunks ch;
+        TRY(row_chunks(ctx, A->rowptr, A->nrows, LANE_ROW_MAX, ROW_CHUNK, WS_CHUNK_A, WS_CHUNK_B, &ch,
+                       msg));
+        if (ch.n > 0) {
+            hipLaunchKernelGGL(k_check_chunks, dim3(grid_for(ch.n * 64, 256, 8192)), dim3(256), 0,
+                               ctx->stream, A->rowptr, A->colidx, A->nrows, A->ncols, want_sym, ch,
+                               err, nd);
+            LAUNCH_CHECK();
+        }
     }
     unsigned h[4] = {0, 0, 0, 0};
     TRY(read_back(ctx, h, err, 16, msg));
@@ -410,8 +494,15 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
                            okeys, n, vmask, inv);
         LAUNCH_CHECK();
         // 2. rows of the relabelled strictly lower part
-        hipLaunchKernelGGL(k_count_relabel_lower, dim3(grid_for(n * 64, 256, 16384)), dim3(256), 0,
+        hipLaunchKernelGGL(k_count_relabel_lower, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
                            ctx->stream, A->rowptr, A->colidx, inv, n, cnt);
+        LAUNCH_CHECK();
+    }
+    RowChunks ch;
+    TRY(row_chunks(ctx, A->rowptr, n, LANE_ROW_MAX, ROW_CHUNK, WS_CHUNK_A, WS_CHUNK_B, &ch, msg));
+    if (ch.n > 0) {
+        hipLaunchKernelGGL(k_count_relabel_chunks, dim3(grid_for(ch.n * 64, 256, 8192)), dim3(256), 0,
+                           ctx->stream, A->colidx, inv, ch, cnt);
         LAUNCH_CHECK();
     }
     TRY(fill_i64(ctx, cnt + n, 1, 0, msg));
@@ -420,8 +511,14 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
     uint64_t *keys = (uint64_t *)ws_get(ctx, WS_KEYS, sizeof(uint64_t) * (nnz > 0 ? nnz : 1));
     if (!keys) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
     if (n > 0) {
-        hipLaunchKernelGGL(k_emit_relabel_lower, dim3(grid_for(n * 64, 256, 16384)), dim3(256), 0,
+        hipLaunchKernelGGL(k_emit_relabel_lower, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
                            ctx->stream, A->rowptr, A->colidx, inv, n, cnt, vbits, keys);
+        LAUNCH_CHECK();
+    }
+    if (ch.n > 0) {
+        // the long rows' offsets serve as their output cursors
+        hipLaunchKernelGGL(k_emit_relabel_chunks, dim3(grid_for(ch.n * 64, 256, 8192)), dim3(256), 0,
+                           ctx->stream, A->colidx, inv, ch, vbits, (unsigned long long *)cnt, keys);
         LAUNCH_CHECK();
     }
     TRY(radix_sort_u64(ctx, keys, nnz, 2 * vbits, msg));
@@ -469,6 +566,39 @@ extern "C" int lagr_graph_matrix(lagr_matrix *A, const lagr_graph G, char *msg)
     return lagr_ok(msg);
 }
 
+int graph_chunks(lagr_graph G, lagr_ctx ctx, RowChunks *out, char *msg)
+{
+    if (G->nchunks < 0) {
+        RowChunks tmp;
+        TRY(row_chunks(ctx, G->A->rowptr, G->A->nrows, GRAPH_LONG_ROW, GRAPH_LONG_ROW, WS_CHUNK_A,
+                       WS_CHUNK_B, &tmp, msg));
+        const size_t nc = (size_t)(tmp.n > 0 ? tmp.n : 1);
+        int32_t *row = (int32_t *)dev_alloc(nc * 4);
+        int64_t *beg = (int64_t *)dev_alloc(nc * 8);
+        int64_t *end = (int64_t *)dev_alloc(nc * 8);
+        if (!row || !beg || !end) {
+            dev_free(row, nc * 4);
+            dev_free(beg, nc * 8);
+            dev_free(end, nc * 8);
+            return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "chunk list");
+        }
+        if (tmp.n > 0) {
+            HIP_TRY(hipMemcpyAsync(row, tmp.row, nc * 4, hipMemcpyDeviceToDevice, ctx->stream));
+            HIP_TRY(hipMemcpyAsync(beg, tmp.beg, nc * 8, hipMemcpyDeviceToDevice, ctx->stream));
+            HIP_TRY(hipMemcpyAsync(end, tmp.end, nc * 8, hipMemcpyDeviceToDevice, ctx->stream));
+        }
+        G->chunk_row = row;
+        G->chunk_beg = beg;
+        G->chunk_end = end;
+        G->nchunks = tmp.n;
+    }
+    out->n = G->nchunks;
+    out->row = G->chunk_row;
+    out->beg = G->chunk_beg;
+    out->end = G->chunk_end;
+    return LAGR_SUCCESS;
+}
+
 extern "C" int lagr_graph_tc_lower(lagr_matrix *L, const lagr_graph G, char *msg)
 {
     if (!L || !G) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
@@ -504,6 +634,12 @@ extern "C" int lagr_graph_free(lagr_graph *G)
     lagr_graph g = *G;
     const int64_t n = g->A ? g->A->nrows : 0;
     if (g->row_degree) dev_free(g->row_degree, sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (g->nchunks >= 0) {
+        const size_t nc = (size_t)(g->nchunks > 0 ? g->nchunks : 1);
+        dev_free(g->chunk_row, nc * 4);
+        dev_free(g->chunk_beg, nc * 8);
+        dev_free(g->chunk_end, nc * 8);
+    }
     lagr_matrix_free(&g->A);
     lagr_matrix_free(&g->L);
     delete g;

@@ -81,6 +81,9 @@ enum WsSlot {
     WS_GEN_G,
     WS_GEN_H,
     WS_TC,            // triangle counting
+    WS_TC_WORK,
+    WS_CHUNK_A,       // long-row chunk lists
+    WS_CHUNK_B,
     WS_NSLOTS
 };
 
@@ -133,7 +136,17 @@ struct lagr_graph_s {
     int symmetric = -1;             // -1 unknown, 0 no, 1 yes
     lagr_matrix L = nullptr;        // degree-ordered strictly lower part
     int64_t L_maxrow = -1;
+    // chunks of A's rows longer than GRAPH_LONG_ROW (owned arrays)
+    int64_t nchunks = -1;           // -1 not built
+    int32_t *chunk_row = nullptr;
+    int64_t *chunk_beg = nullptr;
+    int64_t *chunk_end = nullptr;
 };
+
+// Rows of A longer than this are cut into chunks of this many entries for
+// the BFS and BC kernels.
+constexpr int64_t GRAPH_LONG_ROW = 512;
+
 
 static inline size_t type_size(lagr_type t) { return t == LAGR_BOOL ? 0 : 8; }
 
@@ -173,6 +186,19 @@ int read_back(lagr_ctx ctx, void *host, const void *dev, size_t bytes, char *msg
 // is key >> shift.
 int rowptr_from_sorted_keys(lagr_ctx ctx, const uint64_t *keys, int64_t nnz, int shift,
                             int64_t nrows, int64_t *rowptr, char *msg);
+// Chunks of the rows longer than `min_len` entries, each at most `chunk`
+// entries, so that a hub row is spread over many wavefronts.  The arrays
+// live in the two workspace slots given; n is on the host (synchronises).
+struct RowChunks {
+    int64_t n;
+    const int32_t *row;
+    const int64_t *beg;
+    const int64_t *end;
+};
+int row_chunks(lagr_ctx ctx, const int64_t *rowptr, int64_t nrows, int64_t min_len, int64_t chunk,
+               WsSlot count_slot, WsSlot list_slot, RowChunks *out, char *msg);
+// The cached chunk list of G->A (built on first use).
+int graph_chunks(lagr_graph G, lagr_ctx ctx, RowChunks *out, char *msg);
 // Row degrees (rowptr differences) into deg[n] and their maximum (host).
 int row_degrees(lagr_ctx ctx, const int64_t *rowptr, int64_t n, int64_t *deg,
                 int64_t *maxdeg, char *msg);

@@ -289,16 +289,19 @@ int read_back(lagr_ctx ctx, void *host, const void *dev, size_t bytes, char *msg
 // ------------------------------------------------ CSR offsets from keys
 
 namespace {
-// rowptr[r] = first position whose row >= r.  Every position p writes the
-// offsets of the rows strictly between the previous key's row and its own.
+// rowptr[r] = first position whose row >= r (a lower bound per row).
 __global__ void k_rowptr_from_keys(const uint64_t *__restrict__ keys, int64_t nnz, int shift,
                                    int64_t nrows, int64_t *__restrict__ rowptr)
 {
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= nnz;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t prev = p == 0 ? -1 : (int64_t)(keys[p - 1] >> shift);
-        const int64_t cur = p == nnz ? nrows : (int64_t)(keys[p] >> shift);
-        for (int64_t r = prev + 1; r <= cur && r <= nrows; r++) rowptr[r] = p;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= nrows;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = nnz;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)(keys[mid] >> shift) < r) lo = mid + 1;
+            else hi = mid;
+        }
+        rowptr[r] = lo;
     }
 }
 
@@ -323,9 +326,66 @@ __global__ void k_degrees(const int64_t *__restrict__ rowptr, int64_t n, int64_t
 int rowptr_from_sorted_keys(lagr_ctx ctx, const uint64_t *keys, int64_t nnz, int shift,
                             int64_t nrows, int64_t *rowptr, char *msg)
 {
-    hipLaunchKernelGGL(k_rowptr_from_keys, dim3(grid_for(nnz + 1, 256, 65536)), dim3(256), 0,
+    hipLaunchKernelGGL(k_rowptr_from_keys, dim3(grid_for(nrows + 1, 256, 65536)), dim3(256), 0,
                        ctx->stream, keys, nnz, shift, nrows, rowptr);
     LAUNCH_CHECK();
+    return LAGR_SUCCESS;
+}
+
+namespace {
+__global__ void k_chunk_counts(const int64_t *__restrict__ rp, int64_t n, int64_t min_len,
+                               int64_t chunk, int64_t *__restrict__ cnt)
+{
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t len = rp[r + 1] - rp[r];
+        cnt[r] = len > min_len ? (len + chunk - 1) / chunk : 0;
+    }
+}
+
+__global__ void k_chunk_fill(const int64_t *__restrict__ rp, int64_t n, int64_t min_len, int64_t chunk,
+                             const int64_t *__restrict__ off, int32_t *__restrict__ row,
+                             int64_t *__restrict__ beg, int64_t *__restrict__ end)
+{
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = rp[r], e = rp[r + 1];
+        if (e - b <= min_len) continue;
+        int64_t o = off[r];
+        for (int64_t s = b; s < e; s += chunk, o++) {
+            row[o] = (int32_t)r;
+            beg[o] = s;
+            end[o] = s + chunk < e ? s + chunk : e;
+        }
+    }
+}
+}  // namespace
+
+int row_chunks(lagr_ctx ctx, const int64_t *rowptr, int64_t nrows, int64_t min_len, int64_t chunk,
+               WsSlot count_slot, WsSlot list_slot, RowChunks *out, char *msg)
+{
+    out->n = 0;
+    int64_t *cnt = (int64_t *)ws_get(ctx, count_slot, sizeof(int64_t) * (nrows + 1));
+    if (!cnt) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "chunk workspace");
+    if (nrows <= 0) return LAGR_SUCCESS;
+    hipLaunchKernelGGL(k_chunk_counts, dim3(grid_for(nrows, 256, 16384)), dim3(256), 0, ctx->stream,
+                       rowptr, nrows, min_len, chunk, cnt);
+    LAUNCH_CHECK();
+    int64_t total = 0;
+    TRY(scan_exclusive_i64(ctx, cnt, cnt, nrows, &total, msg));
+    if (total == 0) return LAGR_SUCCESS;
+    char *lst = (char *)ws_get(ctx, list_slot, (size_t)total * 24 + 64);
+    if (!lst) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "chunk list");
+    int64_t *beg = (int64_t *)lst;
+    int64_t *end = beg + total;
+    int32_t *row = (int32_t *)(end + total);
+    hipLaunchKernelGGL(k_chunk_fill, dim3(grid_for(nrows, 256, 16384)), dim3(256), 0, ctx->stream,
+                       rowptr, nrows, min_len, chunk, cnt, row, beg, end);
+    LAUNCH_CHECK();
+    out->n = total;
+    out->row = row;
+    out->beg = beg;
+    out->end = end;
     return LAGR_SUCCESS;
 }
 

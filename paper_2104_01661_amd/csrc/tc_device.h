@@ -1,33 +1,45 @@
-// Device side of the masked plus.pair dot product: one wavefront per row,
-// A_i hashed into LDS, the rows B_j of the mask row streamed as one
-// flattened, load-balanced sequence.  Shared by the single-graph and the
-// many-graph kernels.
+// Device side of the masked plus.pair dot product C<M> = A plus.pair B^T:
+// for every mask entry (i, j), C(i,j) = |A_i and B_j|.  Shared by the
+// single-graph and the many-graph kernels.
+//
+// One wavefront owns a row i.  It marks A_i in private LDS: a bitmap over
+// the ids below TC_BM_IDS and a small open-addressing table for larger
+// ids (a row with too many large ids falls back to a binary search of A_i
+// in memory).  The mask row is then taken 64 entries at a time: lane t
+// fetches the bounds of B_j for the t-th entry, the rows are cut into
+// 64-id units, and the wave walks the units in order, two at a time so
+// that two coalesced loads are in flight, testing every id against the
+// LDS sets.  In the triangle-count form (M = A = B = L, L strictly lower,
+// rows sorted) the first entry of each row is skipped: L_j holds ids
+// below j = L_i[0], which L_i does not.  After the descending-degree
+// relabel almost every probed id is a high-degree vertex with a small id,
+// so the bitmap answers nearly all probes with one LDS read.
 #pragma once
 
 #include "internal.h"
 
 constexpr int TC_BLOCK = 256;
 constexpr int TC_WAVES = TC_BLOCK / 64;
-constexpr int TC_HASH_LOG = 11;
-constexpr int TC_HASH_CAP = 1 << TC_HASH_LOG;    // int32 slots per wave
-constexpr int TC_HASH_MAX_ROW = TC_HASH_CAP / 2;  // longest A_i the table takes
+constexpr int TC_BM_IDS = 32768;              // ids covered by the LDS bitmap
+constexpr int TC_BM_WORDS = TC_BM_IDS / 32;   // 4 KiB per wave
+constexpr int TC_HS_LOG = 8;
+constexpr int TC_HS_SLOTS = 1 << TC_HS_LOG;   // 1 KiB per wave
+constexpr int TC_HS_MAX = TC_HS_SLOTS / 2;    // most large ids the table takes
 
 struct TcArgs {
     int64_t nrows;
     const int64_t *Mrp;   // mask pattern: which (i, j) to compute
     const int32_t *Mci;
-    const int64_t *Arp;   // hashed rows
+    const int64_t *Arp;   // rows tested for membership
     const int32_t *Aci;
-    const int64_t *Brp;   // streamed rows
+    const int64_t *Brp;   // rows streamed
     const int32_t *Bci;
-    int skip_short;       // M = A = B = L: rows with < 2 entries count nothing
+    int tc_form;          // M = A = B = L, strictly lower with sorted rows
 };
 
 struct TcWaveLds {
-    int32_t hash[TC_HASH_CAP];
-    int64_t off[64];      // exclusive offsets of the chunk's segments
-    int64_t start[64];    // where each segment starts in Bci
-    uint32_t cnt[64];     // per-segment counts (per-entry output)
+    uint32_t bm[TC_BM_WORDS];
+    int32_t hs[TC_HS_SLOTS];
 };
 
 __device__ __forceinline__ void wave_sync()
@@ -37,91 +49,224 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint32_t tc_hash(int32_t x, int shift)
+__device__ __forceinline__ int64_t bcast64(int64_t x, int src)
 {
-    return ((uint32_t)x * 0x9E3779B1u) >> shift;
+    const int lo = __shfl((int)(x & 0xffffffff), src, 64);
+    const int hi = __shfl((int)(x >> 32), src, 64);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-// Count |A_i and B_j| for the mask entries of row i.  Returns the row's
-// total; with PER_ENTRY also writes entry_counts[q] for each mask entry q.
+__device__ __forceinline__ uint32_t tc_hash(int32_t x)
+{
+    return ((uint32_t)x * 0x9E3779B1u) >> (32 - TC_HS_LOG);
+}
+
+// Is k in A_i?
+__device__ __forceinline__ unsigned tc_member(const TcWaveLds &L, bool use_hash, const int32_t *Arow,
+                                              int64_t alen, int32_t k)
+{
+    if (k < TC_BM_IDS) return (L.bm[k >> 5] >> (k & 31)) & 1u;
+    if (use_hash) {
+        uint32_t h = tc_hash(k);
+        while (true) {
+            const int32_t y = L.hs[h];
+            if (y == k) return 1u;
+            if (y < 0) return 0u;
+            h = (h + 1) & (TC_HS_SLOTS - 1);
+        }
+    }
+    int64_t lo = 0, hi = alen;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (Arow[mid] < k) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < alen && Arow[lo] == k) ? 1u : 0u;
+}
+
+// Row i by the whole wave.  Returns the row's total; with PER_ENTRY also
+// writes entry_counts[q] for each mask entry q of the row.
 template <bool PER_ENTRY>
 __device__ unsigned long long tc_row(const TcArgs &a, int64_t i, TcWaveLds &L,
-                                     int64_t *__restrict__ entry_counts)
+                                     int64_t *__restrict__ entry_counts, unsigned lane)
 {
-    const unsigned lane = lane_id();
     const int64_t a0 = a.Arp[i], alen = a.Arp[i + 1] - a0;
     const int64_t m0 = a.Mrp[i], mlen = a.Mrp[i + 1] - m0;
+    const int32_t *Arow = a.Aci + a0;
     if (mlen == 0) return 0;
-    if (alen > TC_HASH_MAX_ROW) return 0;   // the big-row kernel takes it
-    if (alen == 0 || (a.skip_short && alen < 2)) {
+    if (alen == 0 || (a.tc_form && alen < 2)) {
         if (PER_ENTRY)
             for (int64_t t = lane; t < mlen; t += 64) entry_counts[m0 + t] = 0;
         return 0;
     }
-    int logc = 6;
-    while ((int64_t(1) << logc) < 2 * alen) logc++;
-    const uint32_t cap = 1u << logc, mask = cap - 1;
-    const int shift = 32 - logc;
-    for (uint32_t s = lane; s < cap; s += 64) L.hash[s] = -1;
-    wave_sync();
-    for (int64_t t = lane; t < alen; t += 64) {
-        const int32_t x = a.Aci[a0 + t];
-        uint32_t h = tc_hash(x, shift);
-        while (atomicCAS(&L.hash[h], -1, x) != -1) h = (h + 1) & mask;
+    // mark A_i
+    // the trip count is the same for every lane, so each ballot sees the
+    // whole wave and nlarge (hence use_hash) is uniform
+    int64_t nlarge = 0;
+    for (int64_t t0 = 0; t0 < alen; t0 += 64) {
+        const int64_t t = t0 + lane;
+        const int32_t x = t < alen ? Arow[t] : 0;
+        if (t < alen && x < TC_BM_IDS) atomicOr(&L.bm[x >> 5], 1u << (x & 31));
+        nlarge += __popcll(__ballot(t < alen && x >= TC_BM_IDS));
+    }
+    const bool use_hash = nlarge > 0 && nlarge <= TC_HS_MAX;
+    if (use_hash) {
+        for (int s = lane; s < TC_HS_SLOTS; s += 64) L.hs[s] = -1;
+        wave_sync();
+        for (int64_t t = lane; t < alen; t += 64) {
+            const int32_t x = Arow[t];
+            if (x >= TC_BM_IDS) {
+                uint32_t h = tc_hash(x);
+                while (atomicCAS(&L.hs[h], -1, x) != -1) h = (h + 1) & (TC_HS_SLOTS - 1);
+            }
+        }
     }
     wave_sync();
+
     unsigned long long acc = 0;
-    for (int64_t t0 = 0; t0 < mlen; t0 += 64) {
-        const int nseg = (int)((mlen - t0) < 64 ? (mlen - t0) : 64);
-        int64_t wl = 0, st = 0;
+    for (int64_t q0 = 0; q0 < mlen; q0 += 64) {
+        const int nseg = (int)((mlen - q0) < 64 ? (mlen - q0) : 64);
+        int64_t s = 0;
+        int len = 0;
         if ((int)lane < nseg) {
-            const int32_t j = a.Mci[m0 + t0 + lane];
-            st = a.Brp[j];
-            wl = a.Brp[j + 1] - st;
+            const int64_t q = q0 + lane;
+            const int32_t j = a.Mci[m0 + q];
+            s = a.Brp[j];
+            len = (int)(a.Brp[j + 1] - s);
+            if (a.tc_form && q == 0) len = 0;
         }
-        int64_t incl = wl;
+        // units of 64 ids: exclusive and inclusive unit offsets per segment
+        const int nch = (len + 63) >> 6;
+        int incl = nch;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
-            const int64_t y = __shfl_up(incl, d, 64);
+            const int y = __shfl_up(incl, d, 64);
             if ((int)lane >= d) incl += y;
         }
-        L.off[lane] = incl - wl;
-        L.start[lane] = st;
-        if (PER_ENTRY) L.cnt[lane] = 0;
-        const int64_t tot = __shfl(incl, 63, 64);
-        wave_sync();
-        for (int64_t p = lane; p < tot; p += 64) {
-            int lo = 0, hi = nseg - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (L.off[mid] <= p) lo = mid;
-                else hi = mid - 1;
+        const int U = __shfl(incl, 63, 64);
+        const int excl = incl - nch;
+        unsigned segcnt = 0;
+        int t = 0;       // segment of the current unit (wave-uniform)
+        int tend = __shfl(incl, 0, 64);
+        for (int u = 0; u < U; u += 2) {
+            // unit u
+            while (u >= tend) {
+                t++;
+                tend = __shfl(incl, t, 64);
             }
-            const int32_t k = a.Bci[L.start[lo] + (p - L.off[lo])];
-            uint32_t h = tc_hash(k, shift);
-            bool hit = false;
-            while (true) {
-                const int32_t y = L.hash[h];
-                if (y == k) {
-                    hit = true;
-                    break;
+            const int t1 = t;
+            const int64_t base1 = bcast64(s, t1) + (int64_t)(u - __shfl(excl, t1, 64)) * 64;
+            const int lim1 = __shfl(len, t1, 64) - (u - __shfl(excl, t1, 64)) * 64;
+            // unit u + 1
+            int t2 = t1, lim2 = 0;
+            int64_t base2 = 0;
+            if (u + 1 < U) {
+                int tt = t1, te = tend;
+                while (u + 1 >= te) {
+                    tt++;
+                    te = __shfl(incl, tt, 64);
                 }
-                if (y == -1) break;
-                h = (h + 1) & mask;
+                t2 = tt;
+                base2 = bcast64(s, t2) + (int64_t)(u + 1 - __shfl(excl, t2, 64)) * 64;
+                lim2 = __shfl(len, t2, 64) - (u + 1 - __shfl(excl, t2, 64)) * 64;
             }
-            if (hit) {
-                if (PER_ENTRY) atomicAdd(&L.cnt[lo], 1u);
-                else acc++;
+            const bool v1 = (int)lane < lim1, v2 = (int)lane < lim2;
+            const int32_t k1 = v1 ? a.Bci[base1 + lane] : 0;
+            const int32_t k2 = v2 ? a.Bci[base2 + lane] : 0;
+            const unsigned h1 = v1 ? tc_member(L, use_hash, Arow, alen, k1) : 0u;
+            const unsigned h2 = v2 ? tc_member(L, use_hash, Arow, alen, k2) : 0u;
+            if (PER_ENTRY) {
+                const unsigned c1 = __popcll(__ballot(h1 != 0));
+                const unsigned c2 = __popcll(__ballot(h2 != 0));
+                if ((int)lane == t1) segcnt += c1;
+                if ((int)lane == t2) segcnt += c2;
+            } else {
+                acc += h1 + h2;
             }
         }
-        wave_sync();
-        if (PER_ENTRY) {
-            if ((int)lane < nseg) entry_counts[m0 + t0 + lane] = (int64_t)L.cnt[lane];
-            wave_sync();
-        }
+        if (PER_ENTRY && (int)lane < nseg) entry_counts[m0 + q0 + lane] = (int64_t)segcnt;
     }
+    wave_sync();
+    for (int64_t t = lane; t < alen; t += 64) {
+        const int32_t x = Arow[t];
+        if (x < TC_BM_IDS) L.bm[x >> 5] = 0u;
+    }
+    wave_sync();
     return acc;
 }
 
-int tc_masked_dot(lagr_ctx ctx, const TcArgs &a, int64_t max_arow, bool per_entry,
-                  unsigned long long *total_dev, int64_t *entry_counts, char *msg);
+// Estimated cost of a row: the ids it streams plus a fixed charge for
+// marking and clearing A_i.
+constexpr int64_t TC_ROW_CHARGE = 64;
+
+// First row r with prefix[r] >= target (prefix: n+1 ascending values).
+__device__ __forceinline__ int64_t tc_lower_bound(const int64_t *prefix, int64_t n, int64_t target)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (prefix[mid] < target) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Wave `w` of `nw` takes the rows whose work prefix starts in its equal
+// share [w*T/nw, (w+1)*T/nw) of the total T: a static partition balanced
+// by the streamed ids, so a run of heavy rows is spread over many waves.
+template <bool PER_ENTRY>
+__device__ unsigned long long tc_rows_balanced(const TcArgs &a, TcWaveLds &L,
+                                               int64_t *__restrict__ entry_counts,
+                                               const int64_t *__restrict__ prefix, int64_t w,
+                                               int64_t nw)
+{
+    const unsigned lane = lane_id();
+    for (int x = lane; x < TC_BM_WORDS; x += 64) L.bm[x] = 0u;
+    wave_sync();
+    const int64_t T = prefix[a.nrows];
+    const int64_t lo = (int64_t)((__int128)T * w / nw), hi = (int64_t)((__int128)T * (w + 1) / nw);
+    const int64_t r0 = tc_lower_bound(prefix, a.nrows, lo);
+    const int64_t r1 = tc_lower_bound(prefix, a.nrows, hi);
+    unsigned long long acc = 0;
+    for (int64_t r = r0; r < r1; r++)
+        if (a.Mrp[r + 1] > a.Mrp[r]) acc += tc_row<PER_ENTRY>(a, r, L, entry_counts, lane);
+    return acc;
+}
+
+// Work of each row (TC_ROW_CHARGE plus the ids it streams; 0 for an empty
+// mask row), for the balanced partition.  Rows with at most 64 mask
+// entries are summed by one lane, longer ones by the whole wave.
+__device__ __forceinline__ void tc_row_work_wave(const TcArgs &a, int64_t r0, int64_t *work)
+{
+    const unsigned lane = lane_id();
+    const int64_t r = r0 + lane;
+    int64_t m0 = 0, mlen = 0;
+    if (r < a.nrows) {
+        m0 = a.Mrp[r];
+        mlen = a.Mrp[r + 1] - m0;
+    }
+    int64_t w = 0;
+    if (mlen <= 64)
+        for (int64_t q = (a.tc_form ? 1 : 0); q < mlen; q++) {
+            const int32_t j = a.Mci[m0 + q];
+            w += a.Brp[j + 1] - a.Brp[j];
+        }
+    uint64_t big = __ballot(mlen > 64);
+    while (big) {
+        const int t = __ffsll((unsigned long long)big) - 1;
+        big &= big - 1;
+        const int64_t bm0 = bcast64(m0, t), bl = bcast64(mlen, t);
+        int64_t ww = 0;
+        for (int64_t q = lane; q < bl; q += 64) {
+            if (a.tc_form && q == 0) continue;
+            const int32_t j = a.Mci[bm0 + q];
+            ww += a.Brp[j + 1] - a.Brp[j];
+        }
+        for (int o = 32; o > 0; o >>= 1) ww += __shfl_xor(ww, o, 64);
+        if ((int)lane == t) w = ww;
+    }
+    if (r < a.nrows) work[r] = mlen > 0 ? w + TC_ROW_CHARGE : 0;
+}
+
+int tc_masked_dot(lagr_ctx ctx, const TcArgs &a, bool per_entry, unsigned long long *total_dev,
+                  int64_t *entry_counts, char *msg);
