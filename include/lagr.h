@@ -163,6 +163,10 @@ int lagr_set_allocator(lagr_alloc_fn alloc, lagr_free_fn release, void *user, ch
  * (the per-call allocation cost the paper blames for the high-diameter
  * Road graph, Section VI-B). */
 int lagr_ctx_new(lagr_ctx *ctx, int device, void *stream, char *msg);
+/* device = -1 makes a validation-only context: every call checks its
+ * arguments exactly as usual, but no device work can run on it (calls that
+ * pass their checks fail with LAGR_DEVICE_ERROR or LAGR_OUT_OF_MEMORY).  It
+ * needs no GPU, so host-side tests of the argument checks can use it. */
 int lagr_ctx_set_stream(lagr_ctx ctx, void *stream, char *msg);
 int lagr_ctx_free(lagr_ctx *ctx);
 /* Wait for all work queued on the context's stream. */

@@ -62,6 +62,15 @@ extern "C" int lagr_ctx_new(lagr_ctx *ctx, int device, void *stream, char *msg)
 {
     if (!ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "ctx is NULL");
     *ctx = nullptr;
+    if (device == -1) {
+        // validation-only context: no device work can be queued on it, but
+        // every argument check can run (it is what host-side tests use)
+        lagr_ctx c = new (std::nothrow) lagr_ctx_s();
+        if (!c) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "context");
+        c->device = -1;
+        *ctx = c;
+        return lagr_ok(msg);
+    }
     int ndev = 0;
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev)
@@ -92,7 +101,7 @@ extern "C" int lagr_ctx_free(lagr_ctx *ctx)
 {
     if (!ctx || !*ctx) return LAGR_SUCCESS;
     lagr_ctx c = *ctx;
-    (void)hipStreamSynchronize(c->stream);
+    if (c->device >= 0) (void)hipStreamSynchronize(c->stream);
     timers_clear(c);
     for (int s = 0; s < WS_NSLOTS; s++) dev_free(c->ws[s], c->ws_bytes[s]);
     if (c->pinned) (void)hipHostFree(c->pinned);
