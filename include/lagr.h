@@ -356,6 +356,33 @@ int lagr_bfs(lagr_vector *level, lagr_vector *parent, const lagr_graph G, int64_
 int lagr_bc(lagr_vector *centrality, const lagr_graph G, const int64_t *sources, int32_t ns,
             lagr_ctx ctx, char *msg);
 
+/* ------------------------------------------------- many-graph batching */
+
+/* Triangle counts of many independent graphs in one launch (an extension
+ * of Algorithm 6 beyond the paper: the per-call overhead it blames for
+ * small problems, Section VI-B, is paid once for the whole batch).
+ * lagr_batch_new computes each graph's missing triangle-count operand
+ * (Basic mode) and packs the operands back to back on the device (int32
+ * local column ids); the graphs may be freed afterwards. */
+typedef struct lagr_batch_s *lagr_batch;
+typedef struct {
+    int32_t blocks_per_cu; /* workgroups of 4 wavefronts per compute unit, 1..16 */
+    int32_t row_charge;    /* fixed cost per row in the work-balanced partition */
+    int32_t use_graph;     /* capture the launch once into a hipGraph and replay it */
+} lagr_tune;
+int lagr_batch_new(lagr_batch *B, const lagr_graph *graphs, int64_t ngraphs, lagr_ctx ctx,
+                   char *msg);
+int lagr_batch_info(const lagr_batch B, int64_t *ngraphs, int64_t *rows, int64_t *entries,
+                    char *msg);
+/* Times a grid of (blocks_per_cu, row_charge) candidates on this batch and
+ * stores the fastest (with use_graph = 1) as the batch's default. */
+int lagr_batch_autotune(lagr_tune *best, lagr_batch B, lagr_ctx ctx, char *msg);
+/* counts: HOST int64[ngraphs], graph order.  tune may be NULL (the batch's
+ * default).  Synchronises. */
+int lagr_tc_batched(int64_t *counts, lagr_batch B, const lagr_tune *tune, lagr_ctx ctx,
+                    char *msg);
+int lagr_batch_free(lagr_batch *B);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,7 +35,24 @@ struct TcArgs {
     const int64_t *Brp;   // rows streamed
     const int32_t *Bci;
     int tc_form;          // M = A = B = L, strictly lower with sorted rows
+    // Many graphs packed back to back: graph g owns rows [gbase[g],
+    // gbase[g+1]) and its column ids are local, so row j of graph g is
+    // row gbase[g] + j.  nullptr for a single matrix.
+    const int64_t *gbase = nullptr;
+    int64_t ngraphs = 0;
 };
+
+// Graph of packed row r (gbase ascending, ngraphs + 1 entries).
+__device__ __forceinline__ int64_t tc_graph_of(const TcArgs &a, int64_t r)
+{
+    int64_t lo = 0, hi = a.ngraphs;   // last g with gbase[g] <= r
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a.gbase[mid] <= r) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
 
 struct TcWaveLds {
     uint32_t bm[TC_BM_WORDS];
@@ -88,7 +105,8 @@ __device__ __forceinline__ unsigned tc_member(const TcWaveLds &L, bool use_hash,
 // writes entry_counts[q] for each mask entry q of the row.
 template <bool PER_ENTRY>
 __device__ unsigned long long tc_row(const TcArgs &a, int64_t i, TcWaveLds &L,
-                                     int64_t *__restrict__ entry_counts, unsigned lane)
+                                     int64_t *__restrict__ entry_counts, unsigned lane,
+                                     int64_t bbase = 0)
 {
     const int64_t a0 = a.Arp[i], alen = a.Arp[i + 1] - a0;
     const int64_t m0 = a.Mrp[i], mlen = a.Mrp[i + 1] - m0;
@@ -131,8 +149,8 @@ __device__ unsigned long long tc_row(const TcArgs &a, int64_t i, TcWaveLds &L,
         if ((int)lane < nseg) {
             const int64_t q = q0 + lane;
             const int32_t j = a.Mci[m0 + q];
-            s = a.Brp[j];
-            len = (int)(a.Brp[j + 1] - s);
+            s = a.Brp[bbase + j];
+            len = (int)(a.Brp[bbase + j + 1] - s);
             if (a.tc_form && q == 0) len = 0;
         }
         // units of 64 ids: exclusive and inclusive unit offsets per segment
@@ -214,11 +232,14 @@ __device__ __forceinline__ int64_t tc_lower_bound(const int64_t *prefix, int64_t
 // Wave `w` of `nw` takes the rows whose work prefix starts in its equal
 // share [w*T/nw, (w+1)*T/nw) of the total T: a static partition balanced
 // by the streamed ids, so a run of heavy rows is spread over many waves.
+// With per_graph (packed graphs), each graph's total is added to
+// per_graph[g]; the return value is then 0.
 template <bool PER_ENTRY>
 __device__ unsigned long long tc_rows_balanced(const TcArgs &a, TcWaveLds &L,
                                                int64_t *__restrict__ entry_counts,
                                                const int64_t *__restrict__ prefix, int64_t w,
-                                               int64_t nw)
+                                               int64_t nw,
+                                               unsigned long long *__restrict__ per_graph = nullptr)
 {
     const unsigned lane = lane_id();
     for (int x = lane; x < TC_BM_WORDS; x += 64) L.bm[x] = 0u;
@@ -228,44 +249,69 @@ __device__ unsigned long long tc_rows_balanced(const TcArgs &a, TcWaveLds &L,
     const int64_t r0 = tc_lower_bound(prefix, a.nrows, lo);
     const int64_t r1 = tc_lower_bound(prefix, a.nrows, hi);
     unsigned long long acc = 0;
-    for (int64_t r = r0; r < r1; r++)
-        if (a.Mrp[r + 1] > a.Mrp[r]) acc += tc_row<PER_ENTRY>(a, r, L, entry_counts, lane);
-    return acc;
+    if (!a.gbase) {
+        for (int64_t r = r0; r < r1; r++)
+            if (a.Mrp[r + 1] > a.Mrp[r]) acc += tc_row<PER_ENTRY>(a, r, L, entry_counts, lane);
+        return acc;
+    }
+    if (r0 >= r1) return 0;
+    // each lane holds a partial count: the flush sums the wave first (the
+    // graph changes at the same row for every lane, so all lanes take part)
+    auto flush = [&](int64_t gg) {
+        unsigned long long t = acc;
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        if (t && lane == 0 && per_graph) atomicAdd(&per_graph[gg], t);
+        acc = 0;
+    };
+    int64_t g = tc_graph_of(a, r0);
+    int64_t gend = a.gbase[g + 1];
+    for (int64_t r = r0; r < r1; r++) {
+        while (r >= gend) {
+            flush(g);
+            g++;
+            gend = a.gbase[g + 1];
+        }
+        if (a.Mrp[r + 1] > a.Mrp[r]) acc += tc_row<PER_ENTRY>(a, r, L, entry_counts, lane, a.gbase[g]);
+    }
+    flush(g);
+    return 0;
 }
 
-// Work of each row (TC_ROW_CHARGE plus the ids it streams; 0 for an empty
+// Work of each row (a fixed charge plus the ids it streams; 0 for an empty
 // mask row), for the balanced partition.  Rows with at most 64 mask
 // entries are summed by one lane, longer ones by the whole wave.
-__device__ __forceinline__ void tc_row_work_wave(const TcArgs &a, int64_t r0, int64_t *work)
+__device__ __forceinline__ void tc_row_work_wave(const TcArgs &a, int64_t r0, int64_t *work,
+                                                 int64_t charge = TC_ROW_CHARGE)
 {
     const unsigned lane = lane_id();
     const int64_t r = r0 + lane;
-    int64_t m0 = 0, mlen = 0;
+    int64_t m0 = 0, mlen = 0, base = 0;
     if (r < a.nrows) {
         m0 = a.Mrp[r];
         mlen = a.Mrp[r + 1] - m0;
+        if (a.gbase) base = a.gbase[tc_graph_of(a, r)];
     }
     int64_t w = 0;
     if (mlen <= 64)
         for (int64_t q = (a.tc_form ? 1 : 0); q < mlen; q++) {
-            const int32_t j = a.Mci[m0 + q];
+            const int64_t j = base + a.Mci[m0 + q];
             w += a.Brp[j + 1] - a.Brp[j];
         }
     uint64_t big = __ballot(mlen > 64);
     while (big) {
         const int t = __ffsll((unsigned long long)big) - 1;
         big &= big - 1;
-        const int64_t bm0 = bcast64(m0, t), bl = bcast64(mlen, t);
+        const int64_t bm0 = bcast64(m0, t), bl = bcast64(mlen, t), bb = bcast64(base, t);
         int64_t ww = 0;
         for (int64_t q = lane; q < bl; q += 64) {
             if (a.tc_form && q == 0) continue;
-            const int32_t j = a.Mci[bm0 + q];
+            const int64_t j = bb + a.Mci[bm0 + q];
             ww += a.Brp[j + 1] - a.Brp[j];
         }
         for (int o = 32; o > 0; o >>= 1) ww += __shfl_xor(ww, o, 64);
         if ((int)lane == t) w = ww;
     }
-    if (r < a.nrows) work[r] = mlen > 0 ? w + TC_ROW_CHARGE : 0;
+    if (r < a.nrows) work[r] = mlen > 0 ? w + charge : 0;
 }
 
 int tc_masked_dot(lagr_ctx ctx, const TcArgs &a, bool per_entry, unsigned long long *total_dev,

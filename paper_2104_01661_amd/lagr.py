@@ -499,3 +499,65 @@ def lagr_select_tril(A: Matrix, ctx: Context) -> Matrix:
     h = ctypes.c_void_p()
     call("lagr_select_tril", ctypes.byref(h), A.h, ctx.h)
     return Matrix(h)
+
+
+# ------------------------------------------------------ many-graph batch
+
+class Tune(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("row_charge", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"blocks_per_cu": self.blocks_per_cu, "row_charge": self.row_charge,
+                "use_graph": self.use_graph}
+
+
+for _name, _args in {
+    "lagr_batch_new": [_PP, _P, _I64, _P, _C],
+    "lagr_batch_info": [_P, _P, _P, _P, _C],
+    "lagr_batch_autotune": [ctypes.POINTER(Tune), _P, _P, _C],
+    "lagr_tc_batched": [_P, _P, ctypes.POINTER(Tune), _P, _C],
+    "lagr_batch_free": [_PP],
+}.items():
+    if hasattr(_lib, _name):
+        _f = getattr(_lib, _name)
+        _f.restype = ctypes.c_int
+        _f.argtypes = _args
+        _fns[_name] = _f
+
+
+class Batch:
+    """Packed triangle-count operands of many graphs (lagr_batch)."""
+
+    def __init__(self, ctx: Context, graphs):
+        arr = (ctypes.c_void_p * len(graphs))(*[g.h.value for g in graphs])
+        self.h = ctypes.c_void_p()
+        call("lagr_batch_new", ctypes.byref(self.h), arr, len(graphs), ctx.h)
+        self.n = len(graphs)
+
+    def info(self):
+        g, r, e = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        call("lagr_batch_info", self.h, ctypes.byref(g), ctypes.byref(r), ctypes.byref(e))
+        return g.value, r.value, e.value
+
+    def autotune(self, ctx: Context) -> Tune:
+        t = Tune()
+        call("lagr_batch_autotune", ctypes.byref(t), self.h, ctx.h)
+        return t
+
+    def tc(self, ctx: Context, tune: Tune = None):
+        import numpy as np
+        out = np.empty(self.n, dtype=np.int64)
+        call("lagr_tc_batched", ctypes.c_void_p(out.ctypes.data), self.h,
+             None if tune is None else ctypes.byref(tune), ctx.h)
+        return out
+
+    def free(self):
+        if self.h:
+            call_nomsg("lagr_batch_free", ctypes.byref(self.h))
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
