@@ -39,6 +39,13 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-bc", action="store_true")
+    p.add_argument("--no-batch", action="store_true")
+    p.add_argument("--batch-graphs", type=int, default=0,
+                   help="graphs in the many-graph leg (default: the full 2,000)")
+    p.add_argument("--no-serve", action="store_true")
+    p.add_argument("--serve-queries", type=int, default=2000,
+                   help="length of the served Poisson stream (5,000 queries/s)")
+    p.add_argument("--serve-workers", type=int, default=4)
     p.add_argument("--cpu-stride", type=int, default=4,
                    help="oracle CPU sample: every stride-th row of the triangle count")
     return p.parse_args()
@@ -66,6 +73,114 @@ def load_counters(name, files):
     if c.get("kernel_source_sha") != kernel_source_sha(files):
         return None
     return c
+
+
+def log(text):
+    print(f"[bench] {text}", file=sys.stderr, flush=True)
+
+
+def percentile_ms(x, q):
+    import numpy as np
+    return round(float(np.percentile(np.asarray(x), q)) * 1e3, 3) if len(x) else None
+
+
+def serve_leg(args, L, ctx, dev, graphgen, np, torch):
+    """Open-loop replay of the seeded Poisson query stream against the
+    continuous-batching server, then against plain per-query calls in
+    arrival order (one query at a time, FIFO).  Latency = time the result is
+    on the host - scheduled arrival."""
+    scfg = graphgen.SERVE
+    graphs, touched, sizes = [], [], []
+    for g in range(scfg["count"]):
+        sc, ef, sd = graphgen.serve_graph_params(g)
+        gn, gsrc, gdst = graphgen.rmat_edges(sc, ef, sd)
+        touched.append(graphgen.touched_vertices(gn, gsrc, gdst))
+        MA = L.Matrix.build(ctx, gn, gn, torch.from_numpy(gsrc).to(dev), torch.from_numpy(gdst).to(dev),
+                            L.BUILD_SYMMETRIZE | L.BUILD_DROP_LOOPS)
+        GG = L.Graph(ctx, MA)
+        graphs.append(GG)
+        sizes.append(gn)
+        del gsrc, gdst
+    log(f"serving: {len(graphs)} graphs resident, {sum(sizes)} vertices")
+    count = args.serve_queries
+    arr, kind, gid, qseed = graphgen.serve_queries(count)
+    queries = []
+    for i in range(count):
+        k, g = int(kind[i]), int(gid[i])
+        ns = 0 if k == 0 else (1 if k == 1 else scfg["bc_sources"])
+        srcs = graphgen.sample(touched[g], ns, int(qseed[i])) if ns else ()
+        queries.append((k, g, tuple(int(x) for x in srcs), float(arr[i])))
+    window = queries[-1][3]
+
+    def summarise(lat, done, starts_at, kinds):
+        lat = np.asarray(lat)
+        kinds = np.asarray(kinds)
+        end = max(done) - starts_at
+        backlog = int(sum(1 for (_, _, _, a), d in zip(queries, done) if d - starts_at > window))
+        r = {"p50_ms": percentile_ms(lat, 50), "p99_ms": percentile_ms(lat, 99),
+             "qps": round(count / end, 1), "makespan_s": round(end, 3),
+             "backlog_at_last_arrival": backlog}
+        for k, name in ((0, "tc"), (1, "bfs"), (2, "bc")):
+            r[name + "_p50_ms"] = percentile_ms(lat[kinds == k], 50)
+            r[name + "_p99_ms"] = percentile_ms(lat[kinds == k], 99)
+        return r
+
+    S = L.Server(ctx, graphs, workers=args.serve_workers, budget_bytes=scfg["budget_bytes"])
+    runs = []
+    for rep in range(2):             # the first replay sizes every worker's workspace
+        t_start = S.clock() + 0.25
+        tickets = [S.submit(L.make_query(k, g, s, t_start + a)) for k, g, s, a in queries]
+        assert S.wait(tickets[-1] + 1, 600.0), "server did not finish the stream"
+        res = {r.ticket: r for r in S.poll(count + 16)}
+        rs = [res[t] for t in tickets]
+        assert all(r.status == 0 for r in rs), "a served query failed"
+        runs.append((rs, t_start))
+        log(f"serving: replay {rep} done")
+    stats = S.stats()
+    S.free()
+    rs, t_start = runs[1]
+    served = summarise([r.done - r.arrival for r in rs], [r.done for r in rs], t_start,
+                       [r.kind for r in rs])
+    served.update({"workers": args.serve_workers,
+                   "mean_batch": {name: round(stats["queries"][k] / max(1, stats["batches"][k]), 2)
+                                  for k, name in ((0, "tc"), (1, "bfs"), (2, "bc"))},
+                   "peak_admitted_bytes": stats["peak_bytes"]})
+
+    # plain FIFO: each query alone, in arrival order, as soon as it has arrived
+    for G in graphs:
+        L.lagr_property_tc_lower(G, ctx)
+    lat, done, kinds = [], [], []
+    tc_plain = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter() + 0.25
+    for k, g, s, a in queries:
+        now = time.perf_counter()
+        if now < t0 + a:
+            time.sleep(t0 + a - now)
+        if k == 0:
+            tc_plain.setdefault(g, L.lagr_tc_adv(graphs[g], ctx))
+        elif k == 1:
+            lv, _ = L.lagr_bfs(graphs[g], s[0], ctx, want_parent=False)
+            ctx.wait()
+            del lv
+        else:
+            c = L.lagr_bc(graphs[g], list(s), ctx)
+            ctx.wait()
+            del c
+        t = time.perf_counter()
+        lat.append(t - (t0 + a))
+        done.append(t)
+        kinds.append(k)
+    plain = summarise(lat, done, t0, kinds)
+    log("serving: plain FIFO done")
+    for r in rs:
+        if r.kind == 0 and r.graph in tc_plain:
+            assert r.triangles == tc_plain[r.graph], "served and plain triangle counts differ"
+    return {"workload": scfg["name"], "queries": count, "rate_qps": scfg["rate"],
+            "arrival_window_s": round(window, 3), "mix_tc_bfs_bc": list(scfg["mix"]),
+            "resident_vertices": int(sum(sizes)), "budget_bytes": scfg["budget_bytes"],
+            "served": served, "plain_fifo": plain,
+            "p99_speedup_vs_plain": round(plain["p99_ms"] / served["p99_ms"], 2)}
 
 
 def main():
@@ -119,6 +234,7 @@ def main():
     n_small_component = sum(1 for m in reached_edges if m < nnzA // 4)
 
     # -------------------------------------------------------------- step
+    log("timed steps (TC + 64 BFS) on the s20 graph")
     ev_tc = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ev_bfs = [torch.cuda.Event(enable_timing=True) for _ in range(len(sources) + 1)]
     tc_counts = []
@@ -214,6 +330,7 @@ def main():
     }
 
     # ------------------------------------------------ betweenness (2^18)
+    log("betweenness leg")
     if not args.no_bc:
         bcfg = graphgen.BC
         bn, bs, bd = graphgen.rmat_edges(bcfg["scale"], bcfg["edge_factor"], bcfg["seed"])
@@ -237,7 +354,54 @@ def main():
                      round(float(np.median(bc_runs)) * 1e-3 / bcfg["batches"], 6),
                      "batches": bcfg["batches"], "batch_size": bcfg["batch_size"], "dtype": "f64"}
 
+    # ------------------------------------ many-graph batch (2,000 graphs)
+    log("many-graph batch leg")
+    if not args.no_batch:
+        mcfg = graphgen.MANY
+        count = args.batch_graphs or mcfg["count"]
+        gs = []
+        edges = 0
+        for g in range(count):
+            sc, ef, sd = graphgen.many_graph_params(g)
+            gn, gsrc, gdst = graphgen.rmat_edges(sc, ef, sd)
+            MA = L.Matrix.build(ctx, gn, gn, torch.from_numpy(gsrc).to(dev),
+                                torch.from_numpy(gdst).to(dev), L.BUILD_SYMMETRIZE | L.BUILD_DROP_LOOPS)
+            GG = L.Graph(ctx, MA)
+            L.lagr_property_tc_lower(GG, ctx)
+            gs.append(GG)
+        Bt = L.Batch(ctx, gs)
+        _, brows, bentries = Bt.info()
+        tune = Bt.autotune(ctx)
+        ref_counts = Bt.tc(ctx, L.Tune(tune.blocks_per_cu, tune.row_charge, 0))
+        reps = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0b = time.perf_counter()
+            cnts = Bt.tc(ctx)            # captured launch, replayed
+            reps.append(time.perf_counter() - t0b)
+            assert np.array_equal(cnts, ref_counts), "batched replay changed a count"
+        plain = []
+        torch.cuda.synchronize()
+        t0p = time.perf_counter()
+        for g, GG in enumerate(gs):
+            plain.append(L.lagr_tc_adv(GG, ctx))
+        t1p = time.perf_counter()
+        assert np.array_equal(np.array(plain), ref_counts), "batched and per-graph counts differ"
+        bt = float(np.median(reps))
+        out["batched"] = {"workload": mcfg["name"], "graphs": count, "undirected_edges": bentries,
+                          "graphs_per_s": round(count / bt, 1), "ms_per_batch": round(bt * 1e3, 3),
+                          "plain_graphs_per_s": round(count / (t1p - t0p), 1),
+                          "speedup_vs_plain": round((t1p - t0p) / bt, 2),
+                          "tune": tune.as_dict()}
+        del Bt, gs
+
+    # ------------------------------------------- serving (32 resident graphs)
+    log("serving leg")
+    if not args.no_serve:
+        out["serve"] = serve_leg(args, L, ctx, dev, graphgen, np, torch)
+
     # ------------------------------------------------ CPU oracle baseline
+    log("CPU oracle baseline")
     if not args.no_cpu_baseline:
         import oracle
         orp, oci = oracle.build_adjacency(n, src, dst)

@@ -383,6 +383,84 @@ int lagr_tc_batched(int64_t *counts, lagr_batch B, const lagr_tune *tune, lagr_c
                     char *msg);
 int lagr_batch_free(lagr_batch *B);
 
+/* ------------------------------------------------------------ serving */
+
+/* A continuous-batching query server over resident undirected graphs (an
+ * extension beyond the paper: the algorithms of Section IV-A/B and
+ * Algorithm 6 answered for a stream of queries).  Worker threads, each
+ * with its own HIP stream and workspace, take the oldest query whose
+ * arrival time has passed together with every other visible query of the
+ * same kind on the same graph: up to max_bfs_batch BFS queries run as one
+ * multi-source BFS (one wavefront lane each), up to max_bc_batch BC
+ * queries of up to 8 sources run as one 64-lane Algorithm 3 batch, and all
+ * visible counts of one graph share one count.  A batch is admitted only
+ * when its working-set estimate fits budget_bytes beside the running
+ * batches; one larger than the whole budget completes with status
+ * LAGR_BUDGET_EXCEEDED.  Every result is the same whatever the batch. */
+typedef struct lagr_server_s *lagr_server;
+enum { LAGR_QUERY_TC = 0, LAGR_QUERY_BFS = 1, LAGR_QUERY_BC = 2 };
+typedef struct {
+    int32_t workers;        /* worker threads, 1..16 */
+    int32_t max_bfs_batch;  /* 1..64 */
+    int32_t max_bc_batch;   /* 1..8 */
+    int32_t keep_vectors;   /* keep each BFS level / BC vector for lagr_server_result_vector */
+    int64_t budget_bytes;   /* device working-set budget over concurrent batches */
+} lagr_server_config;
+typedef struct {
+    int32_t kind;           /* LAGR_QUERY_* */
+    int32_t graph;          /* index into the server's graphs */
+    int32_t nsources;       /* TC 0, BFS 1, BC 1..8 */
+    int32_t pad_;
+    int64_t sources[8];
+    double arrival;         /* server clock (s) at which the query becomes visible */
+} lagr_query;
+typedef struct {
+    int64_t ticket;
+    int32_t kind, graph;
+    int32_t status;         /* LAGR_SUCCESS or the failing call's code */
+    int32_t batch_size;     /* queries answered by the same batch */
+    int64_t triangles;      /* TC */
+    int64_t reached;        /* BFS: vertices reached, the source included */
+    int64_t level_sum;      /* BFS: sum of the levels of reached vertices */
+    int64_t depth;          /* BFS: largest level */
+    double bc_sum;          /* BC: sum over vertices of the centrality */
+    double bc_max;          /* BC: largest centrality */
+    double arrival, start, done;   /* server clock (s) */
+} lagr_result;
+typedef struct {
+    int64_t completed;
+    int64_t batches[3], queries[3];   /* per LAGR_QUERY_* */
+    int64_t rejected;
+    int64_t peak_bytes;     /* largest admitted working-set estimate in flight */
+    int64_t pending;
+} lagr_server_counts;
+/* Builds every graph's cached triangle-count operand and long-row chunk
+ * list on ctx's stream (so workers never write a graph), then starts the
+ * workers on ctx's device.  The graphs must outlive the server and must
+ * not be changed while it runs.  Workers allocate with hipMalloc, never
+ * through a registered allocator. */
+int lagr_server_new(lagr_server *S, const lagr_graph *graphs, int32_t ngraphs,
+                    const lagr_server_config *cfg, lagr_ctx ctx, char *msg);
+/* Seconds since the server started. */
+int lagr_server_clock(const lagr_server S, double *now, char *msg);
+/* Copies the query in; ticket (may be NULL) numbers queries in submission
+ * order from 0.  Thread-safe. */
+int lagr_server_submit(lagr_server S, const lagr_query *q, int64_t *ticket, char *msg);
+/* Moves up to max completed results (completion order) into out. */
+int lagr_server_poll(lagr_server S, lagr_result *out, int32_t max, int32_t *n, char *msg);
+/* Waits until at least n_completed queries have completed in total, or
+ * timeout_s passes (then LAGR_NO_VALUE). */
+int lagr_server_wait(lagr_server S, int64_t n_completed, double timeout_s, char *msg);
+/* With keep_vectors: hands over the kept result of a completed query (BFS:
+ * INT64 FULL levels, -1 unreached; BC: FP64 FULL centrality), allocated
+ * through ctx; each ticket's vector can be taken once. */
+int lagr_server_result_vector(lagr_server S, int64_t ticket, lagr_vector *v, lagr_ctx ctx,
+                              char *msg);
+int lagr_server_stats(const lagr_server S, lagr_server_counts *stats, char *msg);
+/* Stops the workers after their running batches (queries still pending
+ * are dropped) and frees everything the server holds. */
+int lagr_server_free(lagr_server *S);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,16 +41,28 @@ __global__ __launch_bounds__(256) void k_bc_init(int64_t n, uint64_t lanes,
     }
 }
 
-__global__ void k_bc_sources(const int64_t *__restrict__ src, int ns, uint64_t *__restrict__ unvis,
+// src[k] is lane k's source, or -1 for an idle lane
+__global__ void k_bc_sources(const int64_t *__restrict__ src, uint64_t *__restrict__ unvis,
                              uint64_t *__restrict__ mask0, double *__restrict__ sigma)
 {
     const int k = threadIdx.x;
-    if (k < ns) {
+    if (k < 64 && src[k] >= 0) {
         const int64_t s = src[k];
         atomicAnd((unsigned long long *)&unvis[s], ~(1ull << k));
         atomicOr((unsigned long long *)&mask0[s], 1ull << k);
         sigma[s * 64 + k] = 1.0;
     }
+}
+
+// Add the sum of delta over each group of 2^gshift lanes (a fixed tree, so
+// a group's sum does not depend on the other lanes) to centrality
+// [v * groups + group]; gshift = 6 sums all 64 lanes into centrality[v].
+__device__ __forceinline__ void group_add(double delta, int gshift, unsigned lane,
+                                          double *__restrict__ centrality, int64_t v)
+{
+    double t = delta;
+    for (int o = (1 << gshift) >> 1; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if ((lane & ((1u << gshift) - 1)) == 0) centrality[v * (64 >> gshift) + (lane >> gshift)] += t;
 }
 
 __device__ __forceinline__ uint64_t shfl64(uint64_t x, int src)
@@ -114,7 +126,7 @@ __global__ __launch_bounds__(256) void k_bc_backward(const int64_t *__restrict__
                                                      const int32_t *__restrict__ ci, int64_t n,
                                                      const uint64_t *__restrict__ at_i,   // depth i
                                                      const uint64_t *__restrict__ at_im1, // depth i-1
-                                                     int has_deeper, int add_centrality,
+                                                     int has_deeper, int gshift,
                                                      const double *__restrict__ sigma,
                                                      double *__restrict__ W,
                                                      double *__restrict__ centrality)
@@ -154,11 +166,7 @@ __global__ __launch_bounds__(256) void k_bc_backward(const int64_t *__restrict__
             delta = s * acc;
             W[v * 64 + lane] = (1.0 + delta) / s;
         }
-        if (add_centrality) {
-            double t = delta;
-            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-            if (lane == 0) centrality[v] += t;
-        }
+        group_add(delta, gshift, lane, centrality, v);
     }
 }
 
@@ -258,7 +266,7 @@ __global__ __launch_bounds__(256) void k_bc_backward_chunks(const int32_t *__res
 
 __global__ __launch_bounds__(256) void k_bc_backward_combine(const int64_t *__restrict__ rp, RowChunks ch,
                                                              const uint64_t *__restrict__ at_im1,
-                                                             int has_deeper,
+                                                             int has_deeper, int gshift,
                                                              const double *__restrict__ partial,
                                                              const double *__restrict__ sigma,
                                                              double *__restrict__ W,
@@ -283,72 +291,58 @@ __global__ __launch_bounds__(256) void k_bc_backward_combine(const int64_t *__re
             delta = s * acc;
             W[v * 64 + lane] = (1.0 + delta) / s;
         }
-        double t = delta;
-        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-        if (lane == 0) centrality[v] += t;
+        group_add(delta, gshift, lane, centrality, v);
     }
 }
 
 }  // namespace
 
 
-extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const int64_t *sources,
-                       int32_t ns, lagr_ctx ctx, char *msg)
+// Betweenness of the 64-lane batches described by lane_src (HOST, 64
+// entries per batch, -1 = idle lane), summed into cent: with gshift = 6 one
+// value per vertex over every batch; with gshift = 3 one value per group of
+// 8 lanes (cent is n x 8) -- the serving path, where each group is one
+// query.  cent is zeroed here.
+int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nbatches, int gshift,
+               double *cent, char *msg)
 {
-    if (!centrality_out || !G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
-    *centrality_out = nullptr;
-    if (ns < 0 || (ns > 0 && !sources)) return lagr_fail(msg, LAGR_INVALID_VALUE, "bad sources");
-    if (G->kind != LAGR_ADJACENCY_UNDIRECTED)
-        return lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "BC needs an undirected graph (A = A^T)");
     const lagr_matrix A = G->A;
     const int64_t n = A->nrows;
-    for (int32_t k = 0; k < ns; k++)
-        if (sources[k] < 0 || sources[k] >= n)
-            return lagr_fail(msg, LAGR_INVALID_INDEX, "source %lld out of range", (long long)sources[k]);
-
+    const int groups = 64 >> gshift;
     double *sigma = (double *)ws_get(ctx, WS_BC_SIGMA, sizeof(double) * 64 * (size_t)(n > 0 ? n : 1));
     double *Wv = (double *)ws_get(ctx, WS_BC_W, sizeof(double) * 64 * (size_t)(n > 0 ? n : 1));
     uint64_t *unvis = (uint64_t *)ws_get(ctx, WS_BC_UNVIS, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     int64_t *dsrc = (int64_t *)ws_get(ctx, WS_BFS_D, sizeof(int64_t) * 64 + 64);
     if (!sigma || !Wv || !unvis || !dsrc) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc workspace");
     unsigned *flag = (unsigned *)(dsrc + 64);
-
-    lagr_vector cv = new (std::nothrow) lagr_vector_s();
-    if (!cv) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "vector");
-    cv->type = LAGR_FP64;
-    cv->n = n;
-    cv->fmt = LAGR_VEC_FULL;
-    cv->nvals = n;
-    cv->values_bytes = sizeof(double) * (size_t)(n > 0 ? n : 1);
-    cv->values = dev_alloc(cv->values_bytes);
-    if (!cv->values) {
-        delete cv;
-        return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "centrality");
-    }
-    double *cent = (double *)cv->values;
     int rc = LAGR_SUCCESS;
-    std::vector<uint64_t *> levels;   // levels[d]: lane masks of depth d
-    auto level_buf = [&](size_t d) -> uint64_t * {
-        while (levels.size() <= d) {
-            uint64_t *p = (uint64_t *)dev_alloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
-            if (!p) return nullptr;
-            levels.push_back(p);
-        }
-        return levels[d];
-    };
-    auto cleanup = [&]() {
+    // lane masks of depth d live in context-owned buffers reused across
+    // calls, so the steady state allocates nothing per level
+    const size_t lv_bytes = sizeof(uint64_t) * (size_t)(n > 0 ? n : 1);
+    if (ctx->lv_bytes < lv_bytes) {
         (void)hipStreamSynchronize(ctx->stream);
-        for (uint64_t *p : levels) dev_free(p, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
-        levels.clear();
+        for (void *p : ctx->lvpool) dev_free(p, ctx->lv_bytes);
+        ctx->lvpool.clear();
+        ctx->lv_bytes = lv_bytes;
+    }
+    std::vector<void *> &pool = ctx->lvpool;
+    auto level_buf = [&](size_t d) -> uint64_t * {
+        while (pool.size() <= d) {
+            void *p = dev_alloc(ctx->lv_bytes);
+            if (!p) return nullptr;
+            pool.push_back(p);
+        }
+        return (uint64_t *)pool[d];
     };
-#define BC_TRY(expr)                   \
-    do {                               \
-        rc = (expr);                   \
-        if (rc < 0) {                  \
-            cleanup();                 \
-            lagr_vector_free(&cv);     \
-            return rc;                 \
-        }                              \
+    auto levels = [&](size_t d) { return (uint64_t *)pool[d]; };
+    auto cleanup = [&]() { (void)hipStreamSynchronize(ctx->stream); };
+#define BC_TRY(expr)       \
+    do {                   \
+        rc = (expr);       \
+        if (rc < 0) {      \
+            cleanup();     \
+            return rc;     \
+        }                  \
     } while (0)
 #define BC_LAUNCHED()                                                               \
     do {                                                                            \
@@ -356,7 +350,7 @@ extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const in
             BC_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bc kernel launch failed"));   \
     } while (0)
 
-    BC_TRY(fill_i64(ctx, (int64_t *)cent, n, 0, msg));   // 0.0 has all-zero bits
+    BC_TRY(fill_i64(ctx, (int64_t *)cent, n * groups, 0, msg));   // 0.0 has all-zero bits
     const unsigned gblocks = grid_for(n * 64, 256, 16384);
     RowChunks ch;
     BC_TRY(graph_chunks(G, ctx, &ch, msg));
@@ -367,18 +361,21 @@ extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const in
         if (!partial) BC_TRY(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc chunk partials"));
         cblocks = grid_for(ch.n * 64, 256, 16384);
     }
-    for (int32_t b0 = 0; b0 < ns; b0 += 64) {
-        const int nb = (ns - b0) < 64 ? (ns - b0) : 64;
-        const uint64_t lanes = nb == 64 ? ~0ull : ((1ull << nb) - 1);
+    for (int b = 0; b < nbatches; b++) {
+        const int64_t *src = lane_src + 64 * b;
+        uint64_t lanes = 0;
+        for (int k = 0; k < 64; k++)
+            if (src[k] >= 0) lanes |= 1ull << k;
+        if (!lanes) continue;
         uint64_t *m0 = level_buf(0);
         if (!m0) BC_TRY(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc level masks"));
-        HIP_TRY(hipMemcpyAsync(dsrc, sources + b0, sizeof(int64_t) * nb, hipMemcpyHostToDevice,
-                               ctx->stream));
+        if (hipMemcpyAsync(dsrc, src, sizeof(int64_t) * 64, hipMemcpyHostToDevice, ctx->stream) !=
+            hipSuccess)
+            BC_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bc sources copy"));
         hipLaunchKernelGGL(k_bc_init, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, n,
                            lanes, unvis, m0);
         BC_LAUNCHED();
-        hipLaunchKernelGGL(k_bc_sources, dim3(1), dim3(64), 0, ctx->stream, dsrc, nb, unvis, m0,
-                           sigma);
+        hipLaunchKernelGGL(k_bc_sources, dim3(1), dim3(64), 0, ctx->stream, dsrc, unvis, m0, sigma);
         BC_LAUNCHED();
         // forward sweep: depth d -> d + 1 until no lane advances
         size_t depth = 0;
@@ -388,13 +385,13 @@ extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const in
             BC_TRY(fill_u32(ctx, flag, 1, 0u, msg));
             TIMED(ctx, "bc_forward",
                   hipLaunchKernelGGL(k_bc_forward, dim3(gblocks), dim3(256), 0, ctx->stream,
-                                     A->rowptr, A->colidx, n, levels[depth], next, unvis, sigma,
+                                     A->rowptr, A->colidx, n, levels(depth), next, unvis, sigma,
                                      flag));
             BC_LAUNCHED();
             if (ch.n > 0) {
                 TIMED(ctx, "bc_forward_chunks",
                       hipLaunchKernelGGL(k_bc_forward_chunks, dim3(cblocks), dim3(256), 0,
-                                         ctx->stream, A->colidx, ch, levels[depth], unvis, sigma,
+                                         ctx->stream, A->colidx, ch, levels(depth), unvis, sigma,
                                          partial));
                 BC_LAUNCHED();
                 hipLaunchKernelGGL(k_bc_forward_combine, dim3(cblocks), dim3(256), 0, ctx->stream,
@@ -409,30 +406,66 @@ extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const in
         // backward sweep: targets at depth i-1 gather from depth i
         for (size_t i = depth + 1; i >= 2; i--) {
             const int has_deeper = i <= depth ? 1 : 0;
-            const uint64_t *at_i = has_deeper ? levels[i] : levels[i - 1];
+            const uint64_t *at_i = has_deeper ? levels(i) : levels(i - 1);
             TIMED(ctx, "bc_backward",
                   hipLaunchKernelGGL(k_bc_backward, dim3(gblocks), dim3(256), 0, ctx->stream,
-                                     A->rowptr, A->colidx, n, at_i, levels[i - 1], has_deeper, 1,
-                                     sigma, Wv, cent));
+                                     A->rowptr, A->colidx, n, at_i, levels(i - 1), has_deeper,
+                                     gshift, sigma, Wv, cent));
             BC_LAUNCHED();
             if (ch.n > 0) {
                 if (has_deeper) {
                     TIMED(ctx, "bc_backward_chunks",
                           hipLaunchKernelGGL(k_bc_backward_chunks, dim3(cblocks), dim3(256), 0,
-                                             ctx->stream, A->colidx, ch, at_i, levels[i - 1], Wv,
+                                             ctx->stream, A->colidx, ch, at_i, levels(i - 1), Wv,
                                              partial));
                     BC_LAUNCHED();
                 }
                 hipLaunchKernelGGL(k_bc_backward_combine, dim3(cblocks), dim3(256), 0, ctx->stream,
-                                   A->rowptr, ch, levels[i - 1], has_deeper, partial, sigma, Wv,
-                                   cent);
+                                   A->rowptr, ch, levels(i - 1), has_deeper, gshift, partial, sigma,
+                                   Wv, cent);
                 BC_LAUNCHED();
             }
         }
     }
     cleanup();
-    *centrality_out = cv;
 #undef BC_TRY
 #undef BC_LAUNCHED
+    return LAGR_SUCCESS;
+}
+
+extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const int64_t *sources,
+                       int32_t ns, lagr_ctx ctx, char *msg)
+{
+    if (!centrality_out || !G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *centrality_out = nullptr;
+    if (ns < 0 || (ns > 0 && !sources)) return lagr_fail(msg, LAGR_INVALID_VALUE, "bad sources");
+    if (G->kind != LAGR_ADJACENCY_UNDIRECTED)
+        return lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "BC needs an undirected graph (A = A^T)");
+    const int64_t n = G->A->nrows;
+    for (int32_t k = 0; k < ns; k++)
+        if (sources[k] < 0 || sources[k] >= n)
+            return lagr_fail(msg, LAGR_INVALID_INDEX, "source %lld out of range", (long long)sources[k]);
+    // one source per lane, batches of 64 summed in order
+    const int nbatches = (ns + 63) / 64;
+    std::vector<int64_t> lane_src((size_t)64 * (nbatches > 0 ? nbatches : 1), -1);
+    for (int32_t k = 0; k < ns; k++) lane_src[k] = sources[k];
+    lagr_vector cv = new (std::nothrow) lagr_vector_s();
+    if (!cv) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "vector");
+    cv->type = LAGR_FP64;
+    cv->n = n;
+    cv->fmt = LAGR_VEC_FULL;
+    cv->nvals = n;
+    cv->values_bytes = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    cv->values = dev_alloc(cv->values_bytes);
+    if (!cv->values) {
+        delete cv;
+        return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "centrality");
+    }
+    const int rc = bc_compute(ctx, G, lane_src.data(), nbatches, 6, (double *)cv->values, msg);
+    if (rc < 0) {
+        lagr_vector_free(&cv);
+        return rc;
+    }
+    *centrality_out = cv;
     return lagr_ok(msg);
 }

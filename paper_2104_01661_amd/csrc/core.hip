@@ -24,10 +24,14 @@ static lagr_alloc_fn g_alloc = nullptr;
 static lagr_free_fn g_free = nullptr;
 static void *g_user = nullptr;
 
+static thread_local bool t_native_alloc = false;
+
+void set_thread_native_alloc(bool on) { t_native_alloc = on; }
+
 void *dev_alloc(size_t bytes)
 {
     if (bytes == 0) return nullptr;
-    if (g_alloc) return g_alloc(bytes, g_user);
+    if (g_alloc && !t_native_alloc) return g_alloc(bytes, g_user);
     void *p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -39,7 +43,7 @@ void *dev_alloc(size_t bytes)
 void dev_free(void *p, size_t bytes)
 {
     if (!p) return;
-    if (g_free) {
+    if (g_free && !t_native_alloc) {
         g_free(p, bytes, g_user);
         return;
     }
@@ -104,6 +108,7 @@ extern "C" int lagr_ctx_free(lagr_ctx *ctx)
     if (c->device >= 0) (void)hipStreamSynchronize(c->stream);
     timers_clear(c);
     for (int s = 0; s < WS_NSLOTS; s++) dev_free(c->ws[s], c->ws_bytes[s]);
+    for (void *p : c->lvpool) dev_free(p, c->lv_bytes);
     if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
     *ctx = nullptr;

@@ -48,6 +48,10 @@ static inline int lagr_ok(char *msg)
 
 void *dev_alloc(size_t bytes);
 void dev_free(void *p, size_t bytes);
+// While set on a thread, dev_alloc / dev_free use hipMalloc / hipFree even
+// when an allocator is registered (server worker threads, which must not
+// call back into the host application).
+void set_thread_native_alloc(bool on);
 
 // Workspace slots: each slot is a grow-only device buffer owned by the
 // context, reused across calls.  A routine owns the slots listed for it.
@@ -101,6 +105,8 @@ struct lagr_ctx_s {
     size_t ws_bytes[WS_NSLOTS] = {};
     void *pinned = nullptr;          // 4 KiB pinned host staging for scalars
     int num_cus = 256;
+    std::vector<void *> lvpool;      // per-level lane-mask buffers (BC)
+    size_t lv_bytes = 0;
 };
 
 // Returns a device buffer of at least `bytes` for the slot (contents are
@@ -199,6 +205,11 @@ int row_chunks(lagr_ctx ctx, const int64_t *rowptr, int64_t nrows, int64_t min_l
                WsSlot count_slot, WsSlot list_slot, RowChunks *out, char *msg);
 // The cached chunk list of G->A (built on first use).
 int graph_chunks(lagr_graph G, lagr_ctx ctx, RowChunks *out, char *msg);
+// Betweenness of 64-lane batches (lane_src: HOST, 64 per batch, -1 idle)
+// into cent: gshift 6 sums all lanes (n values), gshift 3 sums groups of 8
+// lanes (n x 8 values).
+int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nbatches, int gshift,
+               double *cent, char *msg);
 // Row degrees (rowptr differences) into deg[n] and their maximum (host).
 int row_degrees(lagr_ctx ctx, const int64_t *rowptr, int64_t n, int64_t *deg,
                 int64_t *maxdeg, char *msg);

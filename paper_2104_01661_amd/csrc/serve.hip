@@ -1,0 +1,762 @@
+// Continuous-batching query server over a resident set of graphs.
+//
+// Queries (triangle count, single-source BFS, up-to-8-source betweenness)
+// carry a scheduled arrival time on the server clock; a query becomes
+// visible to the workers once the clock passes it, so an open-loop arrival
+// stream is replayed exactly.  Each worker thread owns a HIP stream and a
+// context (its own workspace).  A free worker takes the oldest visible
+// query and every other visible query of the same kind on the same graph,
+// up to the batch limits:
+//   * BFS: up to 64 queries share one multi-source BFS, one wavefront lane
+//     per query (the lane-mask frontier of the betweenness kernels);
+//   * BC: up to 8 queries of up to 8 sources share one 64-lane batch of
+//     Algorithm 3, the dependencies summed per group of 8 lanes;
+//   * TC: every visible count on the graph is answered by one count.
+// A batch starts only if its working-set estimate fits the memory budget
+// next to the batches already running.  A lane's arithmetic does not
+// depend on the other lanes, so every result is the same alone and in a
+// mix (BC group sums use a fixed reduction tree).
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+
+#include "internal.h"
+
+namespace {
+
+// ----------------------------------------------------- multi-source BFS
+
+__device__ __forceinline__ uint64_t or_reduce64(uint64_t x)
+{
+    unsigned lo = (unsigned)x, hi = (unsigned)(x >> 32);
+    for (int o = 32; o > 0; o >>= 1) {
+        lo |= __shfl_xor(lo, o, 64);
+        hi |= __shfl_xor(hi, o, 64);
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__global__ void k_ms_sources(const int64_t *__restrict__ src, uint64_t *__restrict__ vis,
+                             uint64_t *__restrict__ cur, uint16_t *__restrict__ lev,
+                             int64_t *__restrict__ stats)
+{
+    const int k = threadIdx.x;
+    if (k < 64) {
+        stats[k] = src[k] >= 0 ? 1 : 0;   // reached (the source itself)
+        stats[64 + k] = 0;                // level sum
+        stats[128 + k] = 0;               // depth
+        if (src[k] >= 0) {
+            const int64_t s = src[k];
+            atomicOr((unsigned long long *)&vis[s], 1ull << k);
+            atomicOr((unsigned long long *)&cur[s], 1ull << k);
+            if (lev) lev[s * 64 + k] = 0;
+        }
+    }
+}
+
+// one wave per vertex of at most GRAPH_LONG_ROW neighbours; longer rows
+// only get next[v] = 0 here (their chunks OR into it afterwards)
+__global__ __launch_bounds__(256) void k_ms_level(const int64_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci, int64_t n,
+                                                  uint64_t lanes, const uint64_t *__restrict__ cur,
+                                                  uint64_t *__restrict__ next, uint64_t *__restrict__ vis,
+                                                  uint16_t *__restrict__ lev, int d,
+                                                  unsigned *__restrict__ flag)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t v = wave; v < n; v += nw) {
+        const int64_t b = rp[v], e = rp[v + 1];
+        const uint64_t uv = lanes & ~vis[v];
+        if (e - b > GRAPH_LONG_ROW || uv == 0) {
+            if (lane == 0) next[v] = 0;
+            continue;
+        }
+        uint64_t acc = 0;
+        for (int64_t p0 = b; p0 < e && acc != uv; p0 += 64) {
+            const int64_t p = p0 + lane;
+            const uint64_t m = p < e ? (cur[ci[p]] & uv) : 0;
+            acc |= or_reduce64(m);
+        }
+        if (lane == 0) {
+            next[v] = acc;
+            if (acc) {
+                vis[v] |= acc;
+                atomicOr(flag, 1u);
+            }
+        }
+        if (lev && ((acc >> lane) & 1ull)) lev[v * 64 + lane] = (uint16_t)d;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ms_chunks(const int32_t *__restrict__ ci, RowChunks ch,
+                                                   uint64_t lanes, const uint64_t *__restrict__ cur,
+                                                   const uint64_t *__restrict__ vis,
+                                                   uint64_t *__restrict__ next)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t c = wave; c < ch.n; c += nw) {
+        const int64_t v = ch.row[c];
+        const uint64_t uv = lanes & ~vis[v];
+        if (uv == 0) continue;
+        uint64_t acc = 0;
+        for (int64_t p0 = ch.beg[c]; p0 < ch.end[c] && acc != uv; p0 += 64) {
+            const int64_t p = p0 + lane;
+            const uint64_t m = p < ch.end[c] ? (cur[ci[p]] & uv) : 0;
+            acc |= or_reduce64(m);
+        }
+        if (lane == 0 && acc) atomicOr((unsigned long long *)&next[v], acc);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ms_long_final(const int64_t *__restrict__ rp, RowChunks ch,
+                                                       const uint64_t *__restrict__ next,
+                                                       uint64_t *__restrict__ vis,
+                                                       uint16_t *__restrict__ lev, int d,
+                                                       unsigned *__restrict__ flag)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t c = wave; c < ch.n; c += nw) {
+        const int64_t v = ch.row[c];
+        if (ch.beg[c] != rp[v]) continue;   // first chunk of its vertex
+        const uint64_t acc = next[v];
+        if (!acc) continue;
+        if (lane == 0) {
+            vis[v] |= acc;
+            atomicOr(flag, 1u);
+        }
+        if (lev && ((acc >> lane) & 1ull)) lev[v * 64 + lane] = (uint16_t)d;
+    }
+}
+
+// per-lane counts of the vertices reached at level d
+__global__ __launch_bounds__(256) void k_ms_count(const uint64_t *__restrict__ next, int64_t n, int64_t d,
+                                                  int64_t *__restrict__ stats)
+{
+    __shared__ unsigned long long cnt[64];
+    if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const unsigned lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    unsigned long long mine = 0;
+    for (int64_t v0 = wave * 64; v0 < n; v0 += nw * 64) {
+        const uint64_t x = v0 + lane < n ? next[v0 + lane] : 0;
+        if (!__ballot(x != 0)) continue;
+        for (int k = 0; k < 64; k++) {
+            const uint64_t b = __ballot((x >> k) & 1ull);
+            if ((int)lane == k) mine += __popcll(b);
+        }
+    }
+    if (mine) atomicAdd(&cnt[lane], mine);
+    __syncthreads();
+    if (threadIdx.x < 64 && cnt[threadIdx.x]) {
+        const unsigned long long c = cnt[threadIdx.x];
+        atomicAdd((unsigned long long *)&stats[threadIdx.x], c);
+        atomicAdd((unsigned long long *)&stats[64 + threadIdx.x], c * (unsigned long long)d);
+        atomicMax((unsigned long long *)&stats[128 + threadIdx.x], (unsigned long long)d);
+    }
+}
+
+__global__ void k_lane_levels(const uint16_t *__restrict__ lev, int64_t n, int k, int64_t *__restrict__ out)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const uint16_t x = lev[v * 64 + k];
+        out[v] = x == 0xFFFF ? -1 : (int64_t)x;
+    }
+}
+
+// ------------------------------------------------------ BC group digests
+
+constexpr int DG_BLOCK = 256;
+constexpr int DG_TILE = 4096;
+
+// per tile of vertices: sum and max of each of the 8 group columns, in a
+// fixed order (a column's result depends on that column alone)
+__global__ __launch_bounds__(DG_BLOCK) void k_group_tiles(const double *__restrict__ cent, int64_t n,
+                                                          double *__restrict__ psum,
+                                                          double *__restrict__ pmax)
+{
+    __shared__ double ss[8][DG_BLOCK];
+    __shared__ double sm[8][DG_BLOCK];
+    const int64_t base = (int64_t)blockIdx.x * DG_TILE;
+    double s[8], m[8];
+    for (int g = 0; g < 8; g++) {
+        s[g] = 0.0;
+        m[g] = 0.0;
+    }
+    for (int64_t v = base + threadIdx.x; v < base + DG_TILE && v < n; v += DG_BLOCK)
+        for (int g = 0; g < 8; g++) {
+            const double x = cent[v * 8 + g];
+            s[g] += x;
+            m[g] = x > m[g] ? x : m[g];
+        }
+    for (int g = 0; g < 8; g++) {
+        ss[g][threadIdx.x] = s[g];
+        sm[g][threadIdx.x] = m[g];
+    }
+    __syncthreads();
+    for (int w = DG_BLOCK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int g = 0; g < 8; g++) {
+                ss[g][threadIdx.x] += ss[g][threadIdx.x + w];
+                const double y = sm[g][threadIdx.x + w];
+                sm[g][threadIdx.x] = y > sm[g][threadIdx.x] ? y : sm[g][threadIdx.x];
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) {
+        psum[blockIdx.x * 8 + threadIdx.x] = ss[threadIdx.x][0];
+        pmax[blockIdx.x * 8 + threadIdx.x] = sm[threadIdx.x][0];
+    }
+}
+
+__global__ void k_group_final(const double *__restrict__ psum, const double *__restrict__ pmax,
+                              int64_t tiles, double *__restrict__ out)
+{
+    const int g = threadIdx.x;
+    if (g < 8) {
+        double s = 0.0, m = 0.0;
+        for (int64_t t = 0; t < tiles; t++) {
+            s += psum[t * 8 + g];
+            const double y = pmax[t * 8 + g];
+            m = y > m ? y : m;
+        }
+        out[g] = s;
+        out[8 + g] = m;
+    }
+}
+
+__global__ void k_group_col(const double *__restrict__ cent, int64_t n, int g, double *__restrict__ out)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        out[v] = cent[v * 8 + g];
+}
+
+}  // namespace
+
+// ============================================================ host side
+
+namespace {
+
+struct Slot {
+    lagr_query q;
+    int64_t ticket;
+};
+
+struct Kept {
+    void *p;
+    size_t bytes;
+    int64_t n;
+    lagr_type type;
+};
+
+// a context-owned scratch buffer that grows on demand
+struct Grow {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void *get(size_t want)
+    {
+        if (want <= bytes) return p;
+        if (p) dev_free(p, bytes);
+        p = dev_alloc(want);
+        bytes = p ? want : 0;
+        return p;
+    }
+    ~Grow()
+    {
+        if (p) dev_free(p, bytes);
+    }
+};
+
+}  // namespace
+
+struct lagr_server_s {
+    std::vector<lagr_graph> graphs;
+    int device = 0;
+    lagr_server_config cfg{};
+    std::chrono::steady_clock::time_point t0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Slot> pending;
+    std::vector<lagr_result> done;
+    size_t polled = 0;
+    std::unordered_map<int64_t, Kept> kept;
+    int64_t next_ticket = 0;
+    int64_t completed = 0;
+    int64_t in_use = 0, peak = 0;
+    int running = 0;
+    bool stop = false;
+    int64_t batches[3] = {0, 0, 0}, queries[3] = {0, 0, 0}, rejected = 0;
+    std::vector<std::thread> workers;
+
+    double now() const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+// Device working set of one batch, in bytes: the frontier / visited lane
+// masks of a multi-source BFS (3 x 8n) plus, when results are kept, the
+// 64 x 16-bit level lanes and one int64 vector per query; for BC the 64-lane
+// sigma and W arrays (2 x 512n), the lane masks (one 8n buffer per level,
+// counted as 16 levels), the 8 group sums and the kept vectors; for a count
+// its row-work prefix.
+int64_t footprint(const lagr_server_s *S, int kind, int graph, int nq)
+{
+    const int64_t n = S->graphs[graph]->A->nrows;
+    const bool keep = S->cfg.keep_vectors != 0;
+    if (kind == LAGR_QUERY_TC) return 16 * (n + 1);
+    if (kind == LAGR_QUERY_BFS) return 24 * n + (keep ? (128 + 8 * (int64_t)nq) * n : 0);
+    return (1024 + 16 * 8 + 64) * n + (keep ? 8 * (int64_t)nq * n : 0);
+}
+
+// multi-source BFS over the lanes of lane_src (HOST, 64, -1 idle); per-lane
+// reached count, level sum and depth into stats[3][64] (host)
+int msbfs_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, uint16_t *lev,
+                  int64_t *stats, char *msg)
+{
+    const lagr_matrix A = G->A;
+    const int64_t n = A->nrows;
+    uint64_t lanes = 0;
+    for (int k = 0; k < 64; k++)
+        if (lane_src[k] >= 0) lanes |= 1ull << k;
+    uint64_t *cur = (uint64_t *)ws_get(ctx, WS_BFS_A, 8 * (size_t)(n > 0 ? n : 1));
+    uint64_t *nxt = (uint64_t *)ws_get(ctx, WS_BFS_B, 8 * (size_t)(n > 0 ? n : 1));
+    uint64_t *vis = (uint64_t *)ws_get(ctx, WS_BFS_C, 8 * (size_t)(n > 0 ? n : 1));
+    int64_t *dsrc = (int64_t *)ws_get(ctx, WS_BFS_D, 8 * 64 + 64);
+    int64_t *dst = (int64_t *)ws_get(ctx, WS_BFS_E, 8 * 3 * 64);
+    if (!cur || !nxt || !vis || !dsrc || !dst) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "msbfs workspace");
+    unsigned *flag = (unsigned *)(dsrc + 64);
+    RowChunks ch;
+    TRY(graph_chunks(G, ctx, &ch, msg));
+    TRY(fill_i64(ctx, (int64_t *)cur, n, 0, msg));
+    TRY(fill_i64(ctx, (int64_t *)vis, n, 0, msg));
+    if (lev) TRY(fill_u32(ctx, (uint32_t *)lev, n * 32, 0xFFFFFFFFu, msg));
+    HIP_TRY(hipMemcpyAsync(dsrc, lane_src, 8 * 64, hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(k_ms_sources, dim3(1), dim3(64), 0, ctx->stream, dsrc, vis, cur, lev, dst);
+    LAUNCH_CHECK();
+    const unsigned gb = grid_for(n * 64, 256, 16384);
+    const unsigned cb = ch.n > 0 ? grid_for(ch.n * 64, 256, 16384) : 1;
+    for (int d = 1; d < 65535; d++) {
+        TRY(fill_u32(ctx, flag, 1, 0u, msg));
+        hipLaunchKernelGGL(k_ms_level, dim3(gb), dim3(256), 0, ctx->stream, A->rowptr, A->colidx, n, lanes,
+                           cur, nxt, vis, lev, d, flag);
+        LAUNCH_CHECK();
+        if (ch.n > 0) {
+            hipLaunchKernelGGL(k_ms_chunks, dim3(cb), dim3(256), 0, ctx->stream, A->colidx, ch, lanes, cur,
+                               vis, nxt);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_ms_long_final, dim3(cb), dim3(256), 0, ctx->stream, A->rowptr, ch, nxt, vis,
+                               lev, d, flag);
+            LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_ms_count, dim3(grid_for(n, 256, 4096)), dim3(256), 0, ctx->stream, nxt, n,
+                           (int64_t)d, dst);
+        LAUNCH_CHECK();
+        unsigned h = 0;
+        TRY(read_back(ctx, &h, flag, sizeof(h), msg));
+        if (!h) break;
+        std::swap(cur, nxt);
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, dst, 8 * 3 * 64, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    memcpy(stats, ctx->pinned, 8 * 3 * 64);
+    return LAGR_SUCCESS;
+}
+
+struct Worker {
+    lagr_server_s *S;
+    int device;
+    hipStream_t stream = nullptr;
+    lagr_ctx ctx = nullptr;
+    Grow lev, cent, digest;
+};
+
+// run one batch; fills res (same order as batch)
+int run_batch(Worker &W, const std::vector<Slot> &batch, std::vector<lagr_result> &res, char *msg)
+{
+    lagr_server_s *S = W.S;
+    const lagr_query &q0 = batch[0].q;
+    const lagr_graph G = S->graphs[q0.graph];
+    const int64_t n = G->A->nrows;
+    const bool keep = S->cfg.keep_vectors != 0;
+    std::vector<std::pair<int64_t, Kept>> kept;
+    if (q0.kind == LAGR_QUERY_TC) {
+        int64_t t = 0;
+        TRY(lagr_tc_adv(&t, G, W.ctx, msg));
+        for (auto &r : res) r.triangles = t;
+    } else if (q0.kind == LAGR_QUERY_BFS) {
+        int64_t src[64];
+        for (int k = 0; k < 64; k++) src[k] = k < (int)batch.size() ? batch[k].q.sources[0] : -1;
+        uint16_t *lev = nullptr;
+        if (keep) {
+            lev = (uint16_t *)W.lev.get(2 * 64 * (size_t)(n > 0 ? n : 1));
+            if (!lev) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "level lanes");
+        }
+        int64_t st[3 * 64];
+        TRY(msbfs_compute(W.ctx, G, src, lev, st, msg));
+        for (size_t k = 0; k < batch.size(); k++) {
+            res[k].reached = st[k];
+            res[k].level_sum = st[64 + k];
+            res[k].depth = st[128 + k];
+            if (keep) {
+                Kept kv{dev_alloc(8 * (size_t)(n > 0 ? n : 1)), 8 * (size_t)(n > 0 ? n : 1), n, LAGR_INT64};
+                if (!kv.p) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "result vector");
+                hipLaunchKernelGGL(k_lane_levels, dim3(grid_for(n, 256, 4096)), dim3(256), 0, W.ctx->stream,
+                                   lev, n, (int)k, (int64_t *)kv.p);
+                LAUNCH_CHECK();
+                kept.push_back({batch[k].ticket, kv});
+            }
+        }
+    } else {
+        int64_t src[64];
+        for (int k = 0; k < 64; k++) src[k] = -1;
+        for (size_t q = 0; q < batch.size(); q++)
+            for (int i = 0; i < batch[q].q.nsources; i++) src[8 * q + i] = batch[q].q.sources[i];
+        double *cent = (double *)W.cent.get(8 * 8 * (size_t)(n > 0 ? n : 1));
+        const int64_t tiles = (n + DG_TILE - 1) / DG_TILE;
+        double *dg = (double *)W.digest.get(8 * (16 * (size_t)(tiles > 0 ? tiles : 1) + 16));
+        if (!cent || !dg) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc buffers");
+        TRY(bc_compute(W.ctx, G, src, 1, 3, cent, msg));
+        double *psum = dg, *pmax = dg + 8 * (tiles > 0 ? tiles : 1), *fin = pmax + 8 * (tiles > 0 ? tiles : 1);
+        if (n > 0) {
+            hipLaunchKernelGGL(k_group_tiles, dim3((unsigned)tiles), dim3(DG_BLOCK), 0, W.ctx->stream, cent, n,
+                               psum, pmax);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_group_final, dim3(1), dim3(64), 0, W.ctx->stream, psum, pmax, tiles, fin);
+            LAUNCH_CHECK();
+        } else {
+            TRY(fill_i64(W.ctx, (int64_t *)fin, 16, 0, msg));
+        }
+        double h[16];
+        TRY(read_back(W.ctx, h, fin, sizeof(h), msg));
+        for (size_t q = 0; q < batch.size(); q++) {
+            res[q].bc_sum = h[q];
+            res[q].bc_max = h[8 + q];
+            if (keep) {
+                Kept kv{dev_alloc(8 * (size_t)(n > 0 ? n : 1)), 8 * (size_t)(n > 0 ? n : 1), n, LAGR_FP64};
+                if (!kv.p) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "result vector");
+                hipLaunchKernelGGL(k_group_col, dim3(grid_for(n, 256, 4096)), dim3(256), 0, W.ctx->stream, cent,
+                                   n, (int)q, (double *)kv.p);
+                LAUNCH_CHECK();
+                kept.push_back({batch[q].ticket, kv});
+            }
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(W.ctx->stream));
+    if (!kept.empty()) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (auto &kv : kept) S->kept[kv.first] = kv.second;
+    }
+    return LAGR_SUCCESS;
+}
+
+void worker_main(Worker *W)
+{
+    lagr_server_s *S = W->S;
+    char msg[LAGR_MSG_LEN];
+    (void)hipSetDevice(W->device);
+    set_thread_native_alloc(true);
+    for (;;) {
+        std::vector<Slot> batch;
+        int64_t fp = 0;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            for (;;) {
+                if (S->stop) return;
+                if (S->pending.empty()) {
+                    S->cv_work.wait(lk);
+                    continue;
+                }
+                const double t = S->now();
+                const Slot &head = S->pending.front();
+                if (head.q.arrival > t) {
+                    S->cv_work.wait_for(lk, std::chrono::duration<double>(head.q.arrival - t));
+                    continue;
+                }
+                // the oldest visible query and its visible companions
+                const int kind = head.q.kind, graph = head.q.graph;
+                const size_t cap = kind == LAGR_QUERY_BFS ? (size_t)S->cfg.max_bfs_batch
+                                 : kind == LAGR_QUERY_BC ? (size_t)S->cfg.max_bc_batch
+                                                         : (size_t)1 << 30;
+                std::vector<size_t> take;
+                for (size_t i = 0; i < S->pending.size() && take.size() < cap; i++) {
+                    const Slot &s = S->pending[i];
+                    if (s.q.arrival > t) break;
+                    if (s.q.kind == kind && s.q.graph == graph) take.push_back(i);
+                }
+                fp = footprint(S, kind, graph, (int)take.size());
+                if (fp > S->cfg.budget_bytes) {
+                    // larger than the whole budget: refuse these queries
+                    for (size_t j = take.size(); j-- > 0;) {
+                        lagr_result r{};
+                        r.ticket = S->pending[take[j]].ticket;
+                        r.kind = kind;
+                        r.graph = graph;
+                        r.status = LAGR_BUDGET_EXCEEDED;
+                        r.arrival = S->pending[take[j]].q.arrival;
+                        r.start = r.done = t;
+                        S->done.push_back(r);
+                        S->pending.erase(S->pending.begin() + (long)take[j]);
+                        S->completed++;
+                        S->rejected++;
+                    }
+                    S->cv_done.notify_all();
+                    continue;
+                }
+                if (S->in_use + fp > S->cfg.budget_bytes && S->running > 0) {
+                    S->cv_work.wait(lk);   // admitted again when memory frees up
+                    continue;
+                }
+                for (size_t j = take.size(); j-- > 0;) {
+                    batch.push_back(S->pending[take[j]]);
+                    S->pending.erase(S->pending.begin() + (long)take[j]);
+                }
+                std::reverse(batch.begin(), batch.end());
+                S->in_use += fp;
+                S->peak = std::max(S->peak, S->in_use);
+                S->running++;
+                S->batches[kind]++;
+                S->queries[kind] += (int64_t)batch.size();
+                break;
+            }
+        }
+        std::vector<lagr_result> res(batch.size());
+        const double start = S->now();
+        for (size_t k = 0; k < batch.size(); k++) {
+            res[k] = lagr_result{};
+            res[k].ticket = batch[k].ticket;
+            res[k].kind = batch[k].q.kind;
+            res[k].graph = batch[k].q.graph;
+            res[k].arrival = batch[k].q.arrival;
+            res[k].start = start;
+            res[k].batch_size = (int32_t)batch.size();
+        }
+        const int rc = run_batch(*W, batch, res, msg);
+        const double done = S->now();
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (auto &r : res) {
+                r.status = rc < 0 ? rc : LAGR_SUCCESS;
+                r.done = done;
+                S->done.push_back(r);
+            }
+            S->completed += (int64_t)res.size();
+            S->in_use -= fp;
+            S->running--;
+        }
+        S->cv_done.notify_all();
+        S->cv_work.notify_all();
+    }
+}
+
+}  // namespace
+
+// ================================================================= API
+
+extern "C" int lagr_server_new(lagr_server *Sp, const lagr_graph *graphs, int32_t ngraphs,
+                               const lagr_server_config *cfg, lagr_ctx ctx, char *msg)
+{
+    if (!Sp || !graphs || !cfg || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *Sp = nullptr;
+    if (ngraphs < 1) return lagr_fail(msg, LAGR_INVALID_VALUE, "the server needs at least one graph");
+    if (cfg->workers < 1 || cfg->workers > 16 || cfg->max_bfs_batch < 1 || cfg->max_bfs_batch > 64 ||
+        cfg->max_bc_batch < 1 || cfg->max_bc_batch > 8 || cfg->budget_bytes <= 0)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "server configuration out of range");
+    for (int32_t g = 0; g < ngraphs; g++) {
+        if (!graphs[g]) return lagr_fail(msg, LAGR_NULL_POINTER, "graph %d is NULL", g);
+        if (graphs[g]->kind != LAGR_ADJACENCY_UNDIRECTED)
+            return lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "served graphs must be undirected");
+    }
+    // every cached property the workers read is built now, on this thread
+    for (int32_t g = 0; g < ngraphs; g++) {
+        TRY(lagr_property_tc_lower(graphs[g], ctx, msg));
+        RowChunks ch;
+        TRY(graph_chunks(graphs[g], ctx, &ch, msg));
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    lagr_server_s *S = new (std::nothrow) lagr_server_s();
+    if (!S) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "server");
+    S->graphs.assign(graphs, graphs + ngraphs);
+    S->device = ctx->device;
+    S->cfg = *cfg;
+    S->t0 = std::chrono::steady_clock::now();
+    std::vector<Worker *> ws;
+    for (int w = 0; w < cfg->workers; w++) {
+        Worker *W = new (std::nothrow) Worker();
+        if (!W) break;
+        W->S = S;
+        W->device = ctx->device;
+        if (hipStreamCreateWithFlags(&W->stream, hipStreamNonBlocking) != hipSuccess ||
+            lagr_ctx_new(&W->ctx, ctx->device, W->stream, msg) < 0) {
+            delete W;
+            break;
+        }
+        ws.push_back(W);
+    }
+    if ((int)ws.size() != cfg->workers) {
+        for (Worker *W : ws) {
+            lagr_ctx_free(&W->ctx);
+            (void)hipStreamDestroy(W->stream);
+            delete W;
+        }
+        delete S;
+        return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "server workers");
+    }
+    for (Worker *W : ws) S->workers.emplace_back([W]() {
+        worker_main(W);
+        // still on the worker thread (native allocation), which took the
+        // worker's device memory with hipMalloc
+        lagr_ctx_free(&W->ctx);
+        (void)hipStreamDestroy(W->stream);
+        delete W;
+    });
+    *Sp = S;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_server_clock(const lagr_server S, double *now, char *msg)
+{
+    if (!S || !now) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *now = S->now();
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_server_submit(lagr_server S, const lagr_query *q, int64_t *ticket, char *msg)
+{
+    if (!S || !q) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    if (q->kind < LAGR_QUERY_TC || q->kind > LAGR_QUERY_BC)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "unknown query kind %d", q->kind);
+    if (q->graph < 0 || q->graph >= (int32_t)S->graphs.size())
+        return lagr_fail(msg, LAGR_INVALID_INDEX, "graph %d is not resident", q->graph);
+    const int64_t n = S->graphs[q->graph]->A->nrows;
+    const int need = q->kind == LAGR_QUERY_TC ? 0 : 1;
+    const int most = q->kind == LAGR_QUERY_BFS ? 1 : q->kind == LAGR_QUERY_BC ? 8 : 0;
+    if (q->nsources < need || q->nsources > most)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "%d sources for a query of kind %d", q->nsources, q->kind);
+    for (int i = 0; i < q->nsources; i++)
+        if (q->sources[i] < 0 || q->sources[i] >= n)
+            return lagr_fail(msg, LAGR_INVALID_INDEX, "source %lld out of range", (long long)q->sources[i]);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        Slot s{*q, S->next_ticket++};
+        // keep arrival order (a late-stamped query goes behind earlier ones)
+        auto it = S->pending.end();
+        while (it != S->pending.begin() && (it - 1)->q.arrival > q->arrival) --it;
+        S->pending.insert(it, s);
+        if (ticket) *ticket = s.ticket;
+    }
+    S->cv_work.notify_all();
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_server_poll(lagr_server S, lagr_result *out, int32_t max, int32_t *n, char *msg)
+{
+    if (!S || !n || (max > 0 && !out)) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    int32_t k = 0;
+    while (k < max && S->polled < S->done.size()) out[k++] = S->done[S->polled++];
+    *n = k;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_server_wait(lagr_server S, int64_t n_completed, double timeout_s, char *msg)
+{
+    if (!S) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    std::unique_lock<std::mutex> lk(S->mu);
+    const bool ok = S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s),
+                                        [&]() { return S->completed >= n_completed; });
+    if (!ok) {
+        if (msg) snprintf(msg, LAGR_MSG_LEN, "%lld of %lld queries completed", (long long)S->completed,
+                          (long long)n_completed);
+        return LAGR_NO_VALUE;
+    }
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_server_result_vector(lagr_server S, int64_t ticket, lagr_vector *v, lagr_ctx ctx,
+                                         char *msg)
+{
+    if (!S || !v || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *v = nullptr;
+    Kept kv;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->kept.find(ticket);
+        if (it == S->kept.end())
+            return lagr_fail(msg, LAGR_INVALID_INDEX, "no kept vector for ticket %lld", (long long)ticket);
+        kv = it->second;
+        S->kept.erase(it);
+    }
+    lagr_vector x = new (std::nothrow) lagr_vector_s();
+    void *p = x ? dev_alloc(kv.bytes) : nullptr;
+    int rc = LAGR_SUCCESS;
+    if (!x || !p) rc = lagr_fail(msg, LAGR_OUT_OF_MEMORY, "result vector");
+    else if (hipMemcpyAsync(p, kv.p, kv.bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
+             hipStreamSynchronize(ctx->stream) != hipSuccess)
+        rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "result copy");
+    set_thread_native_alloc(true);
+    dev_free(kv.p, kv.bytes);
+    set_thread_native_alloc(false);
+    if (rc < 0) {
+        if (p) dev_free(p, kv.bytes);
+        delete x;
+        return rc;
+    }
+    x->type = kv.type;
+    x->n = kv.n;
+    x->fmt = LAGR_VEC_FULL;
+    x->nvals = kv.n;
+    x->values = p;
+    x->values_bytes = kv.bytes;
+    *v = x;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_server_stats(const lagr_server S, lagr_server_counts *st, char *msg)
+{
+    if (!S || !st) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    st->completed = S->completed;
+    for (int k = 0; k < 3; k++) {
+        st->batches[k] = S->batches[k];
+        st->queries[k] = S->queries[k];
+    }
+    st->rejected = S->rejected;
+    st->peak_bytes = S->peak;
+    st->pending = (int64_t)S->pending.size();
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_server_free(lagr_server *Sp)
+{
+    if (!Sp || !*Sp) return LAGR_SUCCESS;
+    lagr_server_s *S = *Sp;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv_work.notify_all();
+    for (auto &t : S->workers) t.join();
+    set_thread_native_alloc(true);
+    for (auto &kv : S->kept) dev_free(kv.second.p, kv.second.bytes);
+    set_thread_native_alloc(false);
+    delete S;
+    *Sp = nullptr;
+    return LAGR_SUCCESS;
+}

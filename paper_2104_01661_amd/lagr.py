@@ -561,3 +561,123 @@ class Batch:
             self.free()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------ serving
+
+QUERY_TC, QUERY_BFS, QUERY_BC = 0, 1, 2
+BUDGET_EXCEEDED = -11
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int32), ("max_bfs_batch", ctypes.c_int32),
+                ("max_bc_batch", ctypes.c_int32), ("keep_vectors", ctypes.c_int32),
+                ("budget_bytes", ctypes.c_int64)]
+
+
+class Query(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("nsources", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("sources", ctypes.c_int64 * 8), ("arrival", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_int64), ("kind", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("triangles", ctypes.c_int64), ("reached", ctypes.c_int64),
+                ("level_sum", ctypes.c_int64), ("depth", ctypes.c_int64),
+                ("bc_sum", ctypes.c_double), ("bc_max", ctypes.c_double),
+                ("arrival", ctypes.c_double), ("start", ctypes.c_double),
+                ("done", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ServerCounts(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("batches", ctypes.c_int64 * 3),
+                ("queries", ctypes.c_int64 * 3), ("rejected", ctypes.c_int64),
+                ("peak_bytes", ctypes.c_int64), ("pending", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {"completed": self.completed, "batches": list(self.batches),
+                "queries": list(self.queries), "rejected": self.rejected,
+                "peak_bytes": self.peak_bytes, "pending": self.pending}
+
+
+for _name, _args in {
+    "lagr_server_new": [_PP, _P, _I32, ctypes.POINTER(ServerConfig), _P, _C],
+    "lagr_server_clock": [_P, ctypes.POINTER(ctypes.c_double), _C],
+    "lagr_server_submit": [_P, ctypes.POINTER(Query), _P, _C],
+    "lagr_server_poll": [_P, ctypes.POINTER(Result), _I32, _P, _C],
+    "lagr_server_wait": [_P, _I64, ctypes.c_double, _C],
+    "lagr_server_result_vector": [_P, _I64, _PP, _P, _C],
+    "lagr_server_stats": [_P, ctypes.POINTER(ServerCounts), _C],
+    "lagr_server_free": [_PP],
+}.items():
+    if hasattr(_lib, _name):
+        _f = getattr(_lib, _name)
+        _f.restype = ctypes.c_int
+        _f.argtypes = _args
+        _fns[_name] = _f
+
+
+def make_query(kind, graph, sources=(), arrival=0.0) -> Query:
+    q = Query()
+    q.kind, q.graph, q.nsources, q.arrival = kind, graph, len(sources), float(arrival)
+    for i, s in enumerate(sources):
+        q.sources[i] = int(s)
+    return q
+
+
+class Server:
+    """Continuous-batching query server (lagr_server).  The graphs must
+    outlive it; the binding keeps references to them."""
+
+    def __init__(self, ctx: Context, graphs, workers=2, max_bfs_batch=64, max_bc_batch=8,
+                 keep_vectors=False, budget_bytes=64 << 30):
+        self._graphs = list(graphs)
+        arr = (ctypes.c_void_p * len(graphs))(*[g.h.value for g in graphs])
+        cfg = ServerConfig(workers, max_bfs_batch, max_bc_batch, int(bool(keep_vectors)),
+                           int(budget_bytes))
+        self.h = ctypes.c_void_p()
+        call("lagr_server_new", ctypes.byref(self.h), arr, len(graphs), ctypes.byref(cfg), ctx.h)
+
+    def clock(self) -> float:
+        t = ctypes.c_double()
+        call("lagr_server_clock", self.h, ctypes.byref(t))
+        return t.value
+
+    def submit(self, q: Query) -> int:
+        t = ctypes.c_int64()
+        call("lagr_server_submit", self.h, ctypes.byref(q), ctypes.byref(t))
+        return t.value
+
+    def poll(self, max_results=4096):
+        buf = (Result * max_results)()
+        n = ctypes.c_int32()
+        call("lagr_server_poll", self.h, buf, max_results, ctypes.byref(n))
+        return [buf[i] for i in range(n.value)]
+
+    def wait(self, n_completed, timeout_s=60.0) -> bool:
+        return call("lagr_server_wait", self.h, n_completed, float(timeout_s)) == 0
+
+    def result_vector(self, ticket, ctx: Context) -> "Vector":
+        h = ctypes.c_void_p()
+        call("lagr_server_result_vector", self.h, ticket, ctypes.byref(h), ctx.h)
+        return Vector(h)
+
+    def stats(self):
+        s = ServerCounts()
+        call("lagr_server_stats", self.h, ctypes.byref(s))
+        return s.as_dict()
+
+    def free(self):
+        if self.h:
+            call_nomsg("lagr_server_free", ctypes.byref(self.h))
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

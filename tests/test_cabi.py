@@ -160,3 +160,30 @@ def test_message_cleared_on_success(api, ctx):
     assert api("lagr_matrix_info", A, ctypes.byref(t), ctypes.byref(r), ctypes.byref(c), ctypes.byref(nv)) == 0
     assert api.text == "" and (t.value, r.value, c.value) == (INT64, 2, 2)
     api.lib.lagr_matrix_free(ctypes.byref(A))
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int32), ("max_bfs_batch", ctypes.c_int32),
+                ("max_bc_batch", ctypes.c_int32), ("keep_vectors", ctypes.c_int32),
+                ("budget_bytes", ctypes.c_int64)]
+
+
+def test_server_checks(api, ctx):
+    S = ctypes.c_void_p()
+    good = ServerConfig(2, 64, 8, 0, 1 << 30)
+    none = (ctypes.c_void_p * 1)(None)
+    assert api("lagr_server_new", ctypes.byref(S), none, 1, ctypes.byref(good), ctx) == NULL_POINTER
+    assert api("lagr_server_new", ctypes.byref(S), none, 0, ctypes.byref(good), ctx) == INVALID_VALUE
+    for bad in (ServerConfig(0, 64, 8, 0, 1 << 30), ServerConfig(17, 64, 8, 0, 1 << 30),
+                ServerConfig(2, 65, 8, 0, 1 << 30), ServerConfig(2, 64, 9, 0, 1 << 30),
+                ServerConfig(2, 64, 8, 0, 0)):
+        assert api("lagr_server_new", ctypes.byref(S), none, 1, ctypes.byref(bad), ctx) == INVALID_VALUE
+    A = wrap(api, ctx, BOOL, 5, 5)
+    G = ctypes.c_void_p()
+    assert api("lagr_graph_new", ctypes.byref(G), ctypes.byref(A), 1, ctx) == 0   # directed
+    one = (ctypes.c_void_p * 1)(G.value)
+    assert api("lagr_server_new", ctypes.byref(S), one, 1, ctypes.byref(good), ctx) == -9
+    assert S.value is None
+    assert api("lagr_server_submit", None, None, None) == NULL_POINTER
+    assert api.lib.lagr_server_free(ctypes.byref(ctypes.c_void_p())) == 0
+    api.lib.lagr_graph_free(ctypes.byref(G))
