@@ -46,6 +46,9 @@ def parse():
     p.add_argument("--serve-queries", type=int, default=2000,
                    help="length of the served Poisson stream (5,000 queries/s)")
     p.add_argument("--serve-workers", type=int, default=4)
+    p.add_argument("--copy-probe-mib", type=int, default=0,
+                   help="first run a plain elementwise copy of this many MiB (calibrates HBM "
+                        "traffic counters: bytes read and written are known)")
     p.add_argument("--cpu-stride", type=int, default=4,
                    help="oracle CPU sample: every stride-th row of the triangle count")
     return p.parse_args()
@@ -200,6 +203,13 @@ def main():
     L.use_torch_allocator(True)
     ctx = L.Context(0)
     dev = torch.device("cuda", 0)
+    if args.copy_probe_mib > 0:
+        x = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.neg(x, out=y)       # reads and writes copy_probe_mib MiB each
+        torch.cuda.synchronize()
+        del x, y
 
     # ------------------------------------------------------------ inputs
     cfg = graphgen.LARGE
@@ -214,16 +224,34 @@ def main():
     arp, aci, _ = Am.to_csr(ctx)
     deg = torch.diff(arp).cpu().numpy()
 
-    # algorithmic byte model of the fused masked dot (one launch):
-    # stream L once (row offsets + column ids) and, per entry (i, j) of L,
-    # read the two offsets of row j (16 B) and its len(L_j) column ids.
+    # algorithmic byte model of the min-side count (one launch of k_tc_split):
+    # every pair (i, j) of L with p = position of j in row i >= 1 streams
+    # the shorter of L_j (len(L_j) <= p: "A side", row i marked) and
+    # L_i[0, p) ("B side", row j marked); per launch the kernel reads the
+    # work prefix and a 12-byte descriptor per item (64 pairs at most), one
+    # 8-byte segment descriptor per pair, the streamed ids (4 B each) and
+    # every marked row once (16 B of offsets + 4 B per id).
     L.lagr_property_tc_lower(G, ctx)
     Lm = G.tc_lower()
     lrp, lci, _ = Lm.to_csr(ctx)
     nnzL = int(lci.numel())
     llen = torch.diff(lrp)
-    gather = int(llen[lci.long()].sum().item())
-    tc_bytes = 8 * (n + 1) + 4 * nnzL + 16 * nnzL + 4 * gather
+    row_of = torch.repeat_interleave(torch.arange(n, device=dev), llen)
+    pos = torch.arange(nnzL, device=dev) - lrp[row_of]
+    lj = llen[lci.long()]
+    valid = (pos >= 1) & (lj > 0)
+    side_a = valid & (lj <= pos)
+    side_b = valid & (lj > pos)
+    streamed = int(lj[side_a].sum().item() + pos[side_b].sum().item())
+    nent = int(side_a.sum().item() + side_b.sum().item())
+    cnt_a = torch.bincount(row_of[side_a], minlength=n)
+    cnt_b = torch.bincount(lci.long()[side_b], minlength=n)
+    items = int(((cnt_a + 63) // 64).sum().item() + ((cnt_b + 63) // 64).sum().item())
+    marked = int((16 + 4 * llen[cnt_a > 0]).sum().item() + (16 + 4 * llen[cnt_b > 0]).sum().item())
+    tc_bytes = 8 * (items + 1) + 12 * items + 8 * nent + 4 * streamed + marked
+    tc_model = {"pairs": nent, "streamed_ids": streamed, "items": items,
+                "single_side_streamed_ids": int(lj[pos >= 1].sum().item())}
+    del row_of, pos, lj, valid, side_a, side_b, cnt_a, cnt_b
 
     # per-source traversed edges for GTEPS: undirected edges in the reached set
     reached_edges = []
@@ -268,7 +296,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    kt = {k: ctx.kernel_time(k) for k in ("tc_rows", "bfs_push", "bfs_pull")}
+    kt = {k: ctx.kernel_time(k) for k in ("tc_split", "bfs_push", "bfs_pull")}
     ctx.timing(False)
     assert len(set(tc_counts)) == 1, "triangle count changed between steps"
 
@@ -290,17 +318,18 @@ def main():
     gteps_hmean = float(len(teps) / np.sum(1.0 / teps)) / 1e9
     gteps_aggr = float(np.sum(reached_edges) / (np.sum(bfs_med_per_src) * 1e-3)) / 1e9
 
-    tc_kernel_ms = kt["tc_rows"][0] / max(1, kt["tc_rows"][1])
+    tc_kernel_ms = kt["tc_split"][0] / max(1, kt["tc_split"][1])
     achieved = tc_bytes / (tc_kernel_ms * 1e-3) / 1e9
-    counters = load_counters("tc_rows", TC_KERNEL_FILES)
+    counters = load_counters("tc_split", TC_KERNEL_FILES)
     traffic = None
     if counters:
         traffic = int((counters["fetch_kib"] * counters["fetch_scale"]
                        + counters["write_kib"] * counters["write_scale"]) * 1024)
-    roofline = {"bound": "hbm", "kernel": "k_tc_rows (fused masked plus.pair + reduce)",
+    roofline = {"bound": "hbm", "kernel": "k_tc_split (fused masked plus.pair + reduce, min-side)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "algorithmic_bytes": tc_bytes, "kernel_ms": round(tc_kernel_ms, 4)}
+                "algorithmic_bytes": tc_bytes, "kernel_ms": round(tc_kernel_ms, 4),
+                "model": tc_model}
 
     out = {
         "metric": "TC edges/s, BFS GTEPS (R-MAT s20)",

@@ -552,6 +552,10 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
         G->L_maxrow = mx;
     }
     G->L = L;
+    if ((rc = tc_plan_build(ctx, G, msg)) < 0) {
+        G->L = nullptr;
+        goto fail;
+    }
     return lagr_ok(msg);
 fail:
     matrix_release_arrays(L);
@@ -615,6 +619,7 @@ extern "C" int lagr_graph_delete_properties(lagr_graph G, lagr_ctx ctx, char *ms
     G->row_degree = nullptr;
     G->max_degree = -1;
     lagr_matrix_free(&G->L);
+    tc_plan_free(G);
     G->L_maxrow = -1;
     // ndiag and the symmetry flag describe A, which a graph never changes:
     // the results of lagr_graph_check stay valid and are kept
@@ -642,6 +647,7 @@ extern "C" int lagr_graph_free(lagr_graph *G)
     }
     lagr_matrix_free(&g->A);
     lagr_matrix_free(&g->L);
+    tc_plan_free(g);
     delete g;
     *G = nullptr;
     return LAGR_SUCCESS;

@@ -133,6 +133,8 @@ struct lagr_vector_s {
     size_t idx_bytes = 0, present_bytes = 0, values_bytes = 0;      // 0 = borrowed
 };
 
+struct TcPlan;
+
 struct lagr_graph_s {
     lagr_matrix A = nullptr;
     lagr_kind kind = LAGR_ADJACENCY_UNDIRECTED;
@@ -147,7 +149,13 @@ struct lagr_graph_s {
     int32_t *chunk_row = nullptr;
     int64_t *chunk_beg = nullptr;
     int64_t *chunk_end = nullptr;
+    // min-side triangle-count plan over L (built with L, owned)
+    TcPlan *tcplan = nullptr;
 };
+
+// Build / release G->tcplan from G->L.
+int tc_plan_build(lagr_ctx ctx, lagr_graph G, char *msg);
+void tc_plan_free(lagr_graph G);
 
 // Rows of A longer than this are cut into chunks of this many entries for
 // the BFS and BC kernels.

@@ -57,6 +57,8 @@ __device__ __forceinline__ int64_t tc_graph_of(const TcArgs &a, int64_t r)
 struct TcWaveLds {
     uint32_t bm[TC_BM_WORDS];
     int32_t hs[TC_HS_SLOTS];
+    int64_t seg_s[64];      // flattened streaming: segment starts
+    int32_t seg_x[65];      // and exclusive id offsets (seg_x[cnt] = total)
 };
 
 __device__ __forceinline__ void wave_sync()
@@ -101,26 +103,16 @@ __device__ __forceinline__ unsigned tc_member(const TcWaveLds &L, bool use_hash,
     return (lo < alen && Arow[lo] == k) ? 1u : 0u;
 }
 
-// Row i by the whole wave.  Returns the row's total; with PER_ENTRY also
-// writes entry_counts[q] for each mask entry q of the row.
-template <bool PER_ENTRY>
-__device__ unsigned long long tc_row(const TcArgs &a, int64_t i, TcWaveLds &L,
-                                     int64_t *__restrict__ entry_counts, unsigned lane,
-                                     int64_t bbase = 0)
+// Mark the ids of Arow in the wave's LDS sets; returns whether the hash
+// table holds the large ids (else membership of a large id is a binary
+// search of Arow).  The trip count is the same for every lane, so each
+// ballot sees the whole wave and the result is uniform.
+__device__ __forceinline__ bool tc_mark(TcWaveLds &L, const int32_t *__restrict__ Arow, int64_t alen,
+                                        unsigned lane, int32_t *first_id = nullptr)
 {
-    const int64_t a0 = a.Arp[i], alen = a.Arp[i + 1] - a0;
-    const int64_t m0 = a.Mrp[i], mlen = a.Mrp[i + 1] - m0;
-    const int32_t *Arow = a.Aci + a0;
-    if (mlen == 0) return 0;
-    if (alen == 0 || (a.tc_form && alen < 2)) {
-        if (PER_ENTRY)
-            for (int64_t t = lane; t < mlen; t += 64) entry_counts[m0 + t] = 0;
-        return 0;
-    }
-    // mark A_i
-    // the trip count is the same for every lane, so each ballot sees the
-    // whole wave and nlarge (hence use_hash) is uniform
     int64_t nlarge = 0;
+    if (first_id) *first_id = (int64_t)lane < alen ? Arow[lane] : -1;
+#pragma unroll 4
     for (int64_t t0 = 0; t0 < alen; t0 += 64) {
         const int64_t t = t0 + lane;
         const int32_t x = t < alen ? Arow[t] : 0;
@@ -140,6 +132,152 @@ __device__ unsigned long long tc_row(const TcArgs &a, int64_t i, TcWaveLds &L,
         }
     }
     wave_sync();
+    return use_hash;
+}
+
+// Clear the bitmap words tc_mark set (the hash table is reset by the next
+// tc_mark that uses it).
+__device__ __forceinline__ void tc_unmark(TcWaveLds &L, const int32_t *__restrict__ Arow, int64_t alen,
+                                          unsigned lane)
+{
+    wave_sync();
+    for (int64_t t = lane; t < alen; t += 64) {
+        const int32_t x = Arow[t];
+        if (x < TC_BM_IDS) L.bm[x >> 5] = 0u;
+    }
+    wave_sync();
+}
+
+// tc_unmark without reading the row again: a row of at most 64 ids clears
+// the words of the id each lane kept from tc_mark's first pass (first_id,
+// -1 for none); a longer row clears the whole bitmap.
+__device__ __forceinline__ void tc_unmark_kept(TcWaveLds &L, int32_t first_id, int64_t alen, unsigned lane)
+{
+    wave_sync();
+    if (alen <= 64) {
+        if (first_id >= 0 && first_id < TC_BM_IDS) L.bm[first_id >> 5] = 0u;
+    } else {
+        for (int x = lane; x < TC_BM_WORDS; x += 64) L.bm[x] = 0u;
+    }
+    wave_sync();
+}
+
+// Count, over up to 64 segments (lane t holds segment t: ids Bci[s, s+len)
+// or len = 0), the ids that are marked.  The segments are cut into units
+// of 64 ids and the wave walks the units in order, two at a time so that
+// two coalesced loads are in flight.  Returns this lane's partial count.
+__device__ __forceinline__ unsigned long long tc_stream(const TcWaveLds &L, bool use_hash,
+                                                        const int32_t *__restrict__ Arow, int64_t alen,
+                                                        const int32_t *__restrict__ Bci, int64_t s, int len,
+                                                        unsigned lane)
+{
+    const int nch = (len + 63) >> 6;
+    int incl = nch;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(incl, d, 64);
+        if ((int)lane >= d) incl += y;
+    }
+    const int U = __shfl(incl, 63, 64);
+    const int excl = incl - nch;
+    unsigned long long acc = 0;
+    int t = 0;   // segment of the current unit (wave-uniform)
+    int tend = __shfl(incl, 0, 64);
+    for (int u = 0; u < U; u += 2) {
+        while (u >= tend) {
+            t++;
+            tend = __shfl(incl, t, 64);
+        }
+        const int t1 = t;
+        const int off1 = (u - __shfl(excl, t1, 64)) * 64;
+        const int64_t base1 = bcast64(s, t1) + off1;
+        const int lim1 = __shfl(len, t1, 64) - off1;
+        int lim2 = 0;
+        int64_t base2 = 0;
+        if (u + 1 < U) {
+            int tt = t1, te = tend;
+            while (u + 1 >= te) {
+                tt++;
+                te = __shfl(incl, tt, 64);
+            }
+            const int off2 = (u + 1 - __shfl(excl, tt, 64)) * 64;
+            base2 = bcast64(s, tt) + off2;
+            lim2 = __shfl(len, tt, 64) - off2;
+        }
+        const bool v1 = (int)lane < lim1, v2 = (int)lane < lim2;
+        const int32_t k1 = v1 ? Bci[base1 + lane] : 0;
+        const int32_t k2 = v2 ? Bci[base2 + lane] : 0;
+        acc += (v1 ? tc_member(L, use_hash, Arow, alen, k1) : 0u) +
+               (v2 ? tc_member(L, use_hash, Arow, alen, k2) : 0u);
+    }
+    return acc;
+}
+
+// tc_stream over the concatenation of the segments: unit u holds ids
+// 64u .. 64u+63 of the concatenation, so short segments share units, and
+// TC_FLAT_INFLIGHT units are loaded before any is probed.  Each lane finds
+// the segment of its id by walking the wave's LDS copy of the segment
+// offsets forward (its ids only increase).
+constexpr int TC_FLAT_INFLIGHT = 4;
+
+__device__ __forceinline__ unsigned long long tc_stream_flat(TcWaveLds &L, bool use_hash,
+                                                             const int32_t *__restrict__ Arow, int64_t alen,
+                                                             const int32_t *__restrict__ Bci, int64_t s,
+                                                             int len, int cnt, unsigned lane)
+{
+    int incl = len;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(incl, d, 64);
+        if ((int)lane >= d) incl += y;
+    }
+    const int total = __shfl(incl, 63, 64);
+    if ((int)lane < cnt) {
+        L.seg_s[lane] = s;
+        L.seg_x[lane] = incl - len;
+    }
+    if (lane == 0) L.seg_x[cnt] = total;
+    wave_sync();
+    unsigned long long acc = 0;
+    int t = 0;
+    for (int g0 = 0; g0 < total; g0 += 64 * TC_FLAT_INFLIGHT) {
+        int32_t k[TC_FLAT_INFLIGHT];
+        bool v[TC_FLAT_INFLIGHT];
+#pragma unroll
+        for (int f = 0; f < TC_FLAT_INFLIGHT; f++) {
+            const int g = g0 + 64 * f + (int)lane;
+            v[f] = g < total;
+            k[f] = 0;
+            if (v[f]) {
+                while (L.seg_x[t + 1] <= g) t++;
+                k[f] = Bci[L.seg_s[t] + (g - L.seg_x[t])];
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < TC_FLAT_INFLIGHT; f++)
+            acc += v[f] ? tc_member(L, use_hash, Arow, alen, k[f]) : 0u;
+    }
+    wave_sync();
+    return acc;
+}
+
+// Row i by the whole wave.  Returns the row's total; with PER_ENTRY also
+// writes entry_counts[q] for each mask entry q of the row.
+template <bool PER_ENTRY>
+__device__ unsigned long long tc_row(const TcArgs &a, int64_t i, TcWaveLds &L,
+                                     int64_t *__restrict__ entry_counts, unsigned lane,
+                                     int64_t bbase = 0)
+{
+    const int64_t a0 = a.Arp[i], alen = a.Arp[i + 1] - a0;
+    const int64_t m0 = a.Mrp[i], mlen = a.Mrp[i + 1] - m0;
+    const int32_t *Arow = a.Aci + a0;
+    if (mlen == 0) return 0;
+    if (alen == 0 || (a.tc_form && alen < 2)) {
+        if (PER_ENTRY)
+            for (int64_t t = lane; t < mlen; t += 64) entry_counts[m0 + t] = 0;
+        return 0;
+    }
+    const bool use_hash = tc_mark(L, Arow, alen, lane);
 
     unsigned long long acc = 0;
     for (int64_t q0 = 0; q0 < mlen; q0 += 64) {
@@ -204,12 +342,7 @@ __device__ unsigned long long tc_row(const TcArgs &a, int64_t i, TcWaveLds &L,
         }
         if (PER_ENTRY && (int)lane < nseg) entry_counts[m0 + q0 + lane] = (int64_t)segcnt;
     }
-    wave_sync();
-    for (int64_t t = lane; t < alen; t += 64) {
-        const int32_t x = Arow[t];
-        if (x < TC_BM_IDS) L.bm[x >> 5] = 0u;
-    }
-    wave_sync();
+    tc_unmark(L, Arow, alen, lane);
     return acc;
 }
 
@@ -316,3 +449,40 @@ __device__ __forceinline__ void tc_row_work_wave(const TcArgs &a, int64_t r0, in
 
 int tc_masked_dot(lagr_ctx ctx, const TcArgs &a, bool per_entry, unsigned long long *total_dev,
                   int64_t *entry_counts, char *msg);
+
+// ------------------------------------------------- min-side count plan
+//
+// In the triangle-count form every pair (i, j) of L (j < i) contributes
+// |L_i and L_j|, and both sets only hold ids below j: L_j entirely, L_i in
+// its first p entries, where p is the position of j in row i.  The plan
+// streams the shorter of the two and probes it against LDS marks of the
+// other.  Virtual rows 0..n-1 ("A side", row i) mark L_i and stream whole
+// rows L_j (pairs with len(L_j) <= p); virtual rows n..2n-1 ("B side", row
+// j) mark L_j and stream the prefix L_i[0, p) (pairs with len(L_j) > p).
+// Pairs with p = 0 or an empty L_j contribute nothing and are dropped.  An
+// entry packs the streamed segment as (offset << TC_PLAN_LEN_BITS) |
+// length.  The virtual rows are cut into items of up to 64 entries; an
+// item records its first entry and count and the row it marks.
+//
+// Items are spread over the waves by a static partition of a work prefix
+// that counts dependent memory round trips, the latency that bounds this
+// kernel: the item's own loads, one per pair of 64-id units streamed, and
+// one per 64 ids marked on the first item of a row (later items of the
+// row usually follow in the same wave and keep the marks).
+constexpr int TC_PLAN_LEN_BITS = 24;
+constexpr int TC_PLAN_CNT_BITS = 7;
+constexpr int64_t TC_COST_ITEM = 2;
+constexpr int64_t TC_COST_BATCH = 1;   // per TC_FLAT_INFLIGHT units streamed
+constexpr int64_t TC_COST_MARK = 1;
+
+struct TcPlan {
+    int64_t n = 0;          // rows of L
+    int64_t nent = 0;       // entries over both sides
+    int64_t nitems = 0;
+    int64_t *trp = nullptr;      // 2n+1 entry offsets of the virtual rows
+    int64_t *irp = nullptr;      // 2n+1 item offsets of the virtual rows
+    int64_t *iprefix = nullptr;  // nitems+1 exclusive work prefix of the items
+    uint64_t *ent = nullptr;     // nent packed segments
+    uint64_t *item = nullptr;    // nitems: (first entry << TC_PLAN_CNT_BITS) | count
+    int32_t *item_row = nullptr; // nitems: row of L the item marks
+};
