@@ -193,7 +193,7 @@ struct PlanArgs {
     const int32_t *item_row;
 };
 
-__global__ __launch_bounds__(TC_BLOCK) void k_tc_split(PlanArgs a, unsigned long long *__restrict__ total)
+__global__ __launch_bounds__(TC_BLOCK, 8) void k_tc_split(PlanArgs a, unsigned long long *__restrict__ total)
 {
     __shared__ TcWaveLds lds[TC_WAVES];
     TcWaveLds &L = lds[threadIdx.x / 64];
@@ -350,8 +350,9 @@ static int tc_on_lower(lagr_ctx ctx, const lagr_graph G, int64_t *ntri, char *ms
     TRY(fill_i64(ctx, (int64_t *)tot, 1, 0, msg));
     if (P->nitems > 0) {
         PlanArgs a{P->nitems, L->rowptr, L->colidx, P->iprefix, P->ent, P->item, P->item_row};
-        // four resident waves per SIMD: the balanced partition needs no more
-        const unsigned blocks = (unsigned)(ctx->num_cus * 4);
+        // eight resident waves per SIMD (the LDS and register budgets of
+        // k_tc_split allow it): the static partition assumes all resident
+        const unsigned blocks = (unsigned)(ctx->num_cus * 8);
         TIMED(ctx, "tc_split",
               hipLaunchKernelGGL(k_tc_split, dim3(blocks), dim3(TC_BLOCK), 0, ctx->stream, a, tot));
         LAUNCH_CHECK();

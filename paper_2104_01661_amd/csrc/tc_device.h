@@ -20,8 +20,8 @@
 
 constexpr int TC_BLOCK = 256;
 constexpr int TC_WAVES = TC_BLOCK / 64;
-constexpr int TC_BM_IDS = 32768;              // ids covered by the LDS bitmap
-constexpr int TC_BM_WORDS = TC_BM_IDS / 32;   // 4 KiB per wave
+constexpr int TC_BM_IDS = 24576;              // ids covered by the LDS bitmap
+constexpr int TC_BM_WORDS = TC_BM_IDS / 32;   // 3 KiB per wave
 constexpr int TC_HS_LOG = 8;
 constexpr int TC_HS_SLOTS = 1 << TC_HS_LOG;   // 1 KiB per wave
 constexpr int TC_HS_MAX = TC_HS_SLOTS / 2;    // most large ids the table takes
@@ -218,7 +218,7 @@ __device__ __forceinline__ unsigned long long tc_stream(const TcWaveLds &L, bool
 // TC_FLAT_INFLIGHT units are loaded before any is probed.  Each lane finds
 // the segment of its id by walking the wave's LDS copy of the segment
 // offsets forward (its ids only increase).
-constexpr int TC_FLAT_INFLIGHT = 4;
+constexpr int TC_FLAT_INFLIGHT = 6;
 
 __device__ __forceinline__ unsigned long long tc_stream_flat(TcWaveLds &L, bool use_hash,
                                                              const int32_t *__restrict__ Arow, int64_t alen,
