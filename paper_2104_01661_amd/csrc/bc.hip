@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void k_bc_forward(const int64_t *__restrict__ 
             next[v] = nw_mask;
             if (nw_mask) {
                 unvis[v] = uv & ~nw_mask;
-                atomicOr(any_new, 1u);
+                *any_new = 1u;   // a flag: a plain store suffices (atomics on one address serialise)
             }
         }
     }
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(256) void k_bc_forward_combine(const int64_t *__res
             next[v] = nw_mask;
             if (nw_mask) {
                 unvis[v] = uv & ~nw_mask;
-                atomicOr(any_new, 1u);
+                *any_new = 1u;   // a flag: a plain store suffices (atomics on one address serialise)
             }
         }
     }

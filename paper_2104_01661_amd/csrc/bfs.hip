@@ -21,6 +21,13 @@
 
 namespace {
 
+__device__ __forceinline__ int64_t bcast64(int64_t x, int src)
+{
+    const int lo = __shfl((int)(x & 0xffffffff), src, 64);
+    const int hi = __shfl((int)(x >> 32), src, 64);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 constexpr int BFS_ALPHA = 14;
 constexpr int BFS_BETA = 24;
 
@@ -37,14 +44,11 @@ __device__ __forceinline__ bool bit_test(const uint32_t *bm, int64_t v)
 // `visited` holds the vertices of earlier levels only; it absorbs the
 // level's discoveries after the level, so every frontier neighbour of a
 // vertex found in this level still reaches the parent update.
-__device__ __forceinline__ void discovered(int32_t v, int64_t deg_v, int32_t *next_list,
-                                           uint32_t *next_bm, BfsCounters *cnt)
-{
-    atomicOr(&next_bm[v >> 5], 1u << (v & 31));
-    const unsigned long long slot = atomicAdd(&cnt->nnext, 1ull);
-    next_list[slot] = v;
-    atomicAdd(&cnt->enext, (unsigned long long)deg_v);
-}
+// The level kernels only write levels, parents and the next frontier's
+// bitmap.  k_bfs_compact then turns the bitmap into the next frontier list
+// (ascending within each workgroup's range), counts it and its degree sum,
+// and adds it to the visited set: one global atomic per workgroup, since
+// atomics on one address from every wavefront serialise.
 
 __global__ __launch_bounds__(256) void k_bfs_init(int64_t src, int32_t *level, int64_t *parent,
                                                   int32_t *list, uint32_t *visited, uint32_t *bm)
@@ -59,13 +63,10 @@ __global__ __launch_bounds__(256) void k_bfs_init(int64_t src, int32_t *level, i
 }
 
 // Push the neighbours rp-range [b, e) of frontier vertex u, one per lane.
-__device__ __forceinline__ void push_range(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                           int32_t u, int64_t b, int64_t e, unsigned lane, int32_t lev,
-                                           int any_parent, int32_t *__restrict__ level,
-                                           unsigned long long *__restrict__ parent,
-                                           const uint32_t *__restrict__ visited,
-                                           int32_t *__restrict__ next_list, uint32_t *__restrict__ next_bm,
-                                           BfsCounters *__restrict__ cnt)
+__device__ __forceinline__ void push_range(const int32_t *__restrict__ ci, int32_t u, int64_t b, int64_t e,
+                                           unsigned lane, int32_t lev, int any_parent,
+                                           int32_t *__restrict__ level, unsigned long long *__restrict__ parent,
+                                           const uint32_t *__restrict__ visited, uint32_t *__restrict__ next_bm)
 {
     for (int64_t p = b + lane; p < e; p += 64) {
         const int32_t v = ci[p];
@@ -74,7 +75,7 @@ __device__ __forceinline__ void push_range(const int64_t *__restrict__ rp, const
         if (old == -1) {
             if (any_parent) parent[v] = (unsigned long long)u;
             else atomicMin(&parent[v], (unsigned long long)u);
-            discovered(v, rp[v + 1] - rp[v], next_list, next_bm, cnt);
+            atomicOr(&next_bm[v >> 5], 1u << (v & 31));
         } else if (old == lev && !any_parent) {
             atomicMin(&parent[v], (unsigned long long)u);
         }
@@ -88,9 +89,7 @@ __global__ __launch_bounds__(256) void k_bfs_push(const int64_t *__restrict__ rp
                                                   int32_t *__restrict__ level,
                                                   unsigned long long *__restrict__ parent,
                                                   const uint32_t *__restrict__ visited,
-                                                  int32_t *__restrict__ next_list,
-                                                  uint32_t *__restrict__ next_bm,
-                                                  BfsCounters *__restrict__ cnt)
+                                                  uint32_t *__restrict__ next_bm)
 {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
@@ -99,23 +98,19 @@ __global__ __launch_bounds__(256) void k_bfs_push(const int64_t *__restrict__ rp
         const int32_t u = frontier[f];
         const int64_t b = rp[u], e = rp[u + 1];
         if (e - b > GRAPH_LONG_ROW) continue;   // k_bfs_push_chunks
-        push_range(rp, ci, u, b, e, lane, lev, any_parent, level, parent, visited, next_list,
-                   next_bm, cnt);
+        push_range(ci, u, b, e, lane, lev, any_parent, level, parent, visited, next_bm);
     }
 }
 
 // The frontier's hub vertices: every chunk of a long row whose vertex is in
 // the frontier bitmap is pushed by its own wave.
-__global__ __launch_bounds__(256) void k_bfs_push_chunks(const int64_t *__restrict__ rp,
-                                                         const int32_t *__restrict__ ci, RowChunks ch,
+__global__ __launch_bounds__(256) void k_bfs_push_chunks(const int32_t *__restrict__ ci, RowChunks ch,
                                                          const uint32_t *__restrict__ cur_bm,
                                                          int32_t lev, int any_parent,
                                                          int32_t *__restrict__ level,
                                                          unsigned long long *__restrict__ parent,
                                                          const uint32_t *__restrict__ visited,
-                                                         int32_t *__restrict__ next_list,
-                                                         uint32_t *__restrict__ next_bm,
-                                                         BfsCounters *__restrict__ cnt)
+                                                         uint32_t *__restrict__ next_bm)
 {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
@@ -123,44 +118,92 @@ __global__ __launch_bounds__(256) void k_bfs_push_chunks(const int64_t *__restri
     for (int64_t c = wave; c < ch.n; c += nw) {
         const int32_t u = ch.row[c];
         if (!bit_test(cur_bm, u)) continue;
-        push_range(rp, ci, u, ch.beg[c], ch.end[c], lane, lev, any_parent, level, parent, visited,
-                   next_list, next_bm, cnt);
+        push_range(ci, u, ch.beg[c], ch.end[c], lane, lev, any_parent, level, parent, visited, next_bm);
     }
 }
 
 // One lane per unvisited vertex: scan its neighbours in ascending order and
 // stop at the first one in the frontier bitmap, the smallest valid parent.
+// Neighbours are taken PULL_BATCH at a time (independent loads, then
+// independent bitmap probes) so a lane waits for two round trips per batch
+// rather than two per neighbour.
+constexpr int PULL_BATCH = 8;
+
 __global__ __launch_bounds__(256) void k_bfs_pull(const int64_t *__restrict__ rp,
                                                   const int32_t *__restrict__ ci, int64_t n,
                                                   int32_t lev, const uint32_t *__restrict__ cur_bm,
                                                   int32_t *__restrict__ level,
                                                   int64_t *__restrict__ parent,
                                                   const uint32_t *__restrict__ visited,
-                                                  int32_t *__restrict__ next_list,
-                                                  uint32_t *__restrict__ next_bm,
-                                                  BfsCounters *__restrict__ cnt)
+                                                  uint32_t *__restrict__ next_bm)
 {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * blockDim.x) {
-        if (bit_test(visited, v)) continue;
-        const int64_t b = rp[v], e = rp[v + 1];
-        for (int64_t p = b; p < e; p++) {
-            const int32_t u = ci[p];
-            if (bit_test(cur_bm, u)) {
-                parent[v] = u;
-                level[v] = lev;
-                discovered((int32_t)v, e - b, next_list, next_bm, cnt);
-                break;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // every lane runs the same trip count, so the ballot sees the whole wave
+    for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x; v0 < n; v0 += stride) {
+        const int64_t v = v0 + threadIdx.x;
+        int32_t par = -1;
+        if (v < n && !bit_test(visited, v)) {
+            const int64_t b = rp[v], e = rp[v + 1];
+            for (int64_t p0 = b; p0 < e && par < 0; p0 += PULL_BATCH) {
+                int32_t u[PULL_BATCH];
+#pragma unroll
+                for (int t = 0; t < PULL_BATCH; t++) u[t] = p0 + t < e ? ci[p0 + t] : -1;
+#pragma unroll
+                for (int t = PULL_BATCH - 1; t >= 0; t--)
+                    if (u[t] >= 0 && bit_test(cur_bm, u[t])) par = u[t];
             }
         }
+        if (par >= 0) {
+            parent[v] = par;
+            level[v] = lev;
+        }
+        // the wave's 64 vertices are 64-aligned: they own two bitmap words,
+        // which no other wave writes in this kernel
+        const uint64_t m = __ballot(par >= 0);
+        const unsigned lane = lane_id();
+        const int64_t w0 = (v - lane) >> 5;
+        if (lane == 0 && (uint32_t)m) next_bm[w0] = (uint32_t)m;
+        if (lane == 32 && (uint32_t)(m >> 32)) next_bm[w0 + 1] = (uint32_t)(m >> 32);
     }
 }
 
-__global__ void k_or_into(uint32_t *__restrict__ dst, const uint32_t *__restrict__ src, int64_t W)
+// Next frontier from its bitmap: a thread per 32-bit word.  Each workgroup
+// scans its words' popcounts, reserves its range of the list with one
+// atomic, writes its vertices in ascending order, adds its degree sum with
+// one more atomic and ORs its words into the visited set.
+__global__ __launch_bounds__(256) void k_bfs_compact(const int64_t *__restrict__ rp, int64_t n,
+                                                     const uint32_t *__restrict__ next_bm, int64_t W,
+                                                     uint32_t *__restrict__ visited,
+                                                     int32_t *__restrict__ next_list,
+                                                     BfsCounters *__restrict__ cnt)
 {
-    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < W;
-         w += (int64_t)gridDim.x * blockDim.x)
-        dst[w] |= src[w];
+    __shared__ unsigned scan[256];
+    __shared__ unsigned long long base_s, deg_s;
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t x = w < W ? next_bm[w] : 0u;
+    if (x) visited[w] |= x;
+    const unsigned c = (unsigned)__popc(x);
+    unsigned long long deg = 0;
+    for (uint32_t y = x; y; y &= y - 1) {
+        const int64_t v = w * 32 + __ffs(y) - 1;
+        deg += (unsigned long long)(rp[v + 1] - rp[v]);
+    }
+    scan[threadIdx.x] = c;
+    if (threadIdx.x == 0) deg_s = 0;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const unsigned y = (int)threadIdx.x >= o ? scan[threadIdx.x - o] : 0u;
+        __syncthreads();
+        scan[threadIdx.x] += y;
+        __syncthreads();
+    }
+    for (int o = 32; o > 0; o >>= 1) deg += __shfl_xor(deg, o, 64);
+    if (lane_id() == 0 && deg) atomicAdd(&deg_s, deg);
+    if (threadIdx.x == 255) base_s = scan[255] ? atomicAdd(&cnt->nnext, (unsigned long long)scan[255]) : 0;
+    __syncthreads();
+    if (threadIdx.x == 0 && deg_s) atomicAdd(&cnt->enext, deg_s);
+    unsigned long long pos = base_s + scan[threadIdx.x] - c;
+    for (uint32_t y = x; y; y &= y - 1) next_list[pos++] = (int32_t)(w * 32 + __ffs(y) - 1);
 }
 
 __global__ void k_level_to_i64(const int32_t *__restrict__ in, int64_t *__restrict__ out, int64_t n)
@@ -273,26 +316,25 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
             TIMED(ctx, "bfs_pull",
                   hipLaunchKernelGGL(k_bfs_pull, dim3(grid_for(n, 256, 8192)), dim3(256), 0,
                                      ctx->stream, rp, ci, n, lev, bm_cur, lev32, parent, visited,
-                                     list_next, bm_next, cnt));
+                                     bm_next));
         } else {
             TIMED(ctx, "bfs_push",
                   hipLaunchKernelGGL(k_bfs_push, dim3(grid_for(nq * 64, 256, 8192)), dim3(256), 0,
                                      ctx->stream, rp, ci, list_cur, nq, lev, any_parent, lev32,
-                                     (unsigned long long *)parent, visited, list_next, bm_next,
-                                     cnt));
+                                     (unsigned long long *)parent, visited, bm_next));
             if (ch.n > 0)
                 TIMED(ctx, "bfs_push",
                       hipLaunchKernelGGL(k_bfs_push_chunks, dim3(grid_for(ch.n * 64, 256, 4096)),
-                                         dim3(256), 0, ctx->stream, rp, ci, ch, bm_cur, lev,
-                                         any_parent, lev32, (unsigned long long *)parent, visited,
-                                         list_next, bm_next, cnt));
+                                         dim3(256), 0, ctx->stream, ci, ch, bm_cur, lev, any_parent,
+                                         lev32, (unsigned long long *)parent, visited, bm_next));
         }
         if (hipGetLastError() != hipSuccess) {
             cleanup();
             return lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs level launch");
         }
-        hipLaunchKernelGGL(k_or_into, dim3(grid_for(W, 256, 4096)), dim3(256), 0, ctx->stream,
-                           visited, bm_next, W);
+        TIMED(ctx, "bfs_compact",
+              hipLaunchKernelGGL(k_bfs_compact, dim3(grid_for(W, 256, 1 << 30)), dim3(256), 0, ctx->stream,
+                                 rp, n, bm_next, W, visited, list_next, cnt));
         BfsCounters h;
         BFS_TRY(read_back(ctx, &h, cnt, sizeof(h), msg));
         nq = (int64_t)h.nnext;

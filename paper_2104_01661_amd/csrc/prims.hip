@@ -319,7 +319,13 @@ __global__ void k_degrees(const int64_t *__restrict__ rowptr, int64_t n, int64_t
         int64_t y = __shfl_xor(local, o, 64);
         local = y > local ? y : local;
     }
-    if (lane_id() == 0) atomicMax(maxdeg, (unsigned long long)local);
+    // one atomic per workgroup (atomics on one address serialise)
+    __shared__ unsigned long long wmax;
+    if (threadIdx.x == 0) wmax = 0;
+    __syncthreads();
+    if (lane_id() == 0) atomicMax(&wmax, (unsigned long long)local);
+    __syncthreads();
+    if (threadIdx.x == 0 && wmax) atomicMax(maxdeg, wmax);
 }
 }  // namespace
 
@@ -396,7 +402,7 @@ int row_degrees(lagr_ctx ctx, const int64_t *rowptr, int64_t n, int64_t *deg, in
     if (!m) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "counters");
     HIP_TRY(hipMemsetAsync(m, 0, sizeof(unsigned long long), ctx->stream));
     if (n > 0) {
-        hipLaunchKernelGGL(k_degrees, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream,
+        hipLaunchKernelGGL(k_degrees, dim3(grid_for(n, 256, 1024)), dim3(256), 0, ctx->stream,
                            rowptr, n, deg, m);
         LAUNCH_CHECK();
     }

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_ms_level(const int64_t *__restrict__ rp
             next[v] = acc;
             if (acc) {
                 vis[v] |= acc;
-                atomicOr(flag, 1u);
+                *flag = 1u;   // a flag: a plain store suffices (atomics on one address serialise)
             }
         }
         if (lev && ((acc >> lane) & 1ull)) lev[v * 64 + lane] = (uint16_t)d;
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void k_ms_long_final(const int64_t *__restrict
         if (!acc) continue;
         if (lane == 0) {
             vis[v] |= acc;
-            atomicOr(flag, 1u);
+            *flag = 1u;   // a flag: a plain store suffices (atomics on one address serialise)
         }
         if (lev && ((acc >> lane) & 1ull)) lev[v * 64 + lane] = (uint16_t)d;
     }
@@ -365,7 +365,7 @@ int msbfs_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, uin
                                lev, d, flag);
             LAUNCH_CHECK();
         }
-        hipLaunchKernelGGL(k_ms_count, dim3(grid_for(n, 256, 4096)), dim3(256), 0, ctx->stream, nxt, n,
+        hipLaunchKernelGGL(k_ms_count, dim3(grid_for(n, 256, 256)), dim3(256), 0, ctx->stream, nxt, n,
                            (int64_t)d, dst);
         LAUNCH_CHECK();
         unsigned h = 0;

@@ -25,8 +25,16 @@ __global__ __launch_bounds__(TC_BLOCK) void k_tc_rows(TcArgs a, const int64_t *_
     unsigned long long acc = tc_rows_balanced<PER_ENTRY>(a, lds[wave], entry_counts, prefix, w,
                                                          (int64_t)gridDim.x * TC_WAVES);
     if (!PER_ENTRY) {
+        // one atomic per workgroup (atomics on one address serialise)
         for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        if (lane_id() == 0 && acc) atomicAdd(total, acc);
+        __shared__ unsigned long long wsum[TC_WAVES];
+        if (lane_id() == 0) wsum[wave] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0;
+            for (int i = 0; i < TC_WAVES; i++) t += wsum[i];
+            if (t) atomicAdd(total, t);
+        }
     }
 }
 
@@ -193,7 +201,9 @@ struct PlanArgs {
     const int32_t *item_row;
 };
 
-__global__ __launch_bounds__(TC_BLOCK, 8) void k_tc_split(PlanArgs a, unsigned long long *__restrict__ total)
+// Each workgroup writes its count to partial[blockIdx.x]; k_sum_partials
+// adds them (atomics on one address from every wavefront would serialise).
+__global__ __launch_bounds__(TC_BLOCK, 8) void k_tc_split(PlanArgs a, unsigned long long *__restrict__ partial)
 {
     __shared__ TcWaveLds lds[TC_WAVES];
     TcWaveLds &L = lds[threadIdx.x / 64];
@@ -234,7 +244,29 @@ __global__ __launch_bounds__(TC_BLOCK, 8) void k_tc_split(PlanArgs a, unsigned l
         acc += tc_stream_flat(L, use_hash, Arow, alen, a.Lci, s, len, cnt, lane);
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0 && acc) atomicAdd(total, acc);
+    __shared__ unsigned long long wsum[TC_WAVES];
+    if (lane == 0) wsum[threadIdx.x / 64] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < TC_WAVES; i++) t += wsum[i];
+        partial[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const unsigned long long *__restrict__ partial, int64_t n,
+                                                      unsigned long long *__restrict__ out)
+{
+    __shared__ unsigned long long s[256];
+    unsigned long long t = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) t += partial[i];
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = s[0];
 }
 
 }  // namespace
@@ -345,17 +377,20 @@ static int tc_on_lower(lagr_ctx ctx, const lagr_graph G, int64_t *ntri, char *ms
 {
     const lagr_matrix L = G->L;
     const TcPlan *P = G->tcplan;
-    unsigned long long *tot = (unsigned long long *)ws_get(ctx, WS_TC, 64);
+    // eight resident waves per SIMD (the LDS and register budgets of
+    // k_tc_split allow it): the static partition assumes all resident
+    const unsigned blocks = (unsigned)(ctx->num_cus * 8);
+    unsigned long long *tot = (unsigned long long *)ws_get(ctx, WS_TC, 8 * ((size_t)blocks + 1));
     if (!tot) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc counter");
-    TRY(fill_i64(ctx, (int64_t *)tot, 1, 0, msg));
     if (P->nitems > 0) {
         PlanArgs a{P->nitems, L->rowptr, L->colidx, P->iprefix, P->ent, P->item, P->item_row};
-        // eight resident waves per SIMD (the LDS and register budgets of
-        // k_tc_split allow it): the static partition assumes all resident
-        const unsigned blocks = (unsigned)(ctx->num_cus * 8);
         TIMED(ctx, "tc_split",
-              hipLaunchKernelGGL(k_tc_split, dim3(blocks), dim3(TC_BLOCK), 0, ctx->stream, a, tot));
+              hipLaunchKernelGGL(k_tc_split, dim3(blocks), dim3(TC_BLOCK), 0, ctx->stream, a, tot + 1));
         LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, ctx->stream, tot + 1, (int64_t)blocks, tot);
+        LAUNCH_CHECK();
+    } else {
+        TRY(fill_i64(ctx, (int64_t *)tot, 1, 0, msg));
     }
     unsigned long long h = 0;
     TRY(read_back(ctx, &h, tot, sizeof(h), msg));
