@@ -361,13 +361,15 @@ int lagr_bc(lagr_vector *centrality, const lagr_graph G, const int64_t *sources,
 /* Triangle counts of many independent graphs in one launch (an extension
  * of Algorithm 6 beyond the paper: the per-call overhead it blames for
  * small problems, Section VI-B, is paid once for the whole batch).
- * lagr_batch_new computes each graph's missing triangle-count operand
- * (Basic mode) and packs the operands back to back on the device (int32
- * local column ids); the graphs may be freed afterwards. */
+ * lagr_batch_new computes each graph's missing triangle-count operand and
+ * count plan (Basic mode) and packs them back to back on the device (int32
+ * local column ids); the graphs may be freed afterwards.  A batch holds
+ * fewer than 2^31 rows in total. */
 typedef struct lagr_batch_s *lagr_batch;
 typedef struct {
     int32_t blocks_per_cu; /* workgroups of 4 wavefronts per compute unit, 1..16 */
-    int32_t row_charge;    /* fixed cost per row in the work-balanced partition */
+    int32_t row_charge;    /* fixed cost per work item in the balanced partition, >= 1
+                              (one unit = one round of streamed loads) */
     int32_t use_graph;     /* capture the launch once into a hipGraph and replay it */
 } lagr_tune;
 int lagr_batch_new(lagr_batch *B, const lagr_graph *graphs, int64_t ngraphs, lagr_ctx ctx,

@@ -1,14 +1,16 @@
 // Many-graph triangle counting in one launch.
 //
-// The degree-ordered strictly lower parts L_g of many graphs are packed
-// back to back: local int32 column ids, int64 row offsets into one shared
-// id array, and a table of each graph's first row.  One work-balanced
-// kernel (the row kernel of tc_device.h) covers every row of every graph
-// and adds each graph's count to its own counter.  The launch -- counter
-// reset and count kernel -- is captured once into a hipGraph on a stream
-// the batch owns and replayed on every call; the grid size and the fixed
-// per-row charge of the balanced partition are picked by timing a small
-// grid of candidates (lagr_batch_autotune).
+// Each graph's degree-ordered strictly lower part L_g and its min-side
+// count plan (tc_device.h) are packed back to back: local int32 column
+// ids, int64 row offsets into one shared id array, segment descriptors
+// re-based onto that array, work items re-based onto the packed
+// descriptors and onto global rows, and the graph of every item.  One
+// kernel (the plan's wave loop) covers every item of every graph and adds
+// each graph's count to its own counter.  The launch -- counter reset and
+// count kernel -- is captured once into a hipGraph on a stream the batch
+// owns and replayed on every call; the grid size and the fixed per-item
+// charge of the balanced partition are picked by timing a small grid of
+// candidates (lagr_batch_autotune).
 #include <new>
 #include <vector>
 
@@ -18,11 +20,14 @@
 struct lagr_batch_s {
     int device = 0;
     int num_cus = 256;
-    int64_t ng = 0, R = 0, E = 0;
-    int64_t *gbase = nullptr;      // ng + 1
-    int64_t *rp = nullptr;         // R + 1
-    int32_t *ci = nullptr;         // E
-    int64_t *prefix = nullptr;     // R + 1, work prefix for prefix_charge
+    int64_t ng = 0, R = 0, E = 0, NE = 0, K = 0;
+    int64_t *rp = nullptr;          // R + 1 packed row offsets
+    int32_t *ci = nullptr;          // E packed local column ids
+    uint64_t *ent = nullptr;        // NE packed segment descriptors
+    uint64_t *item = nullptr;       // K packed items
+    int32_t *item_row = nullptr;    // K global rows
+    int32_t *item_graph = nullptr;  // K graph ids
+    int64_t *prefix = nullptr;      // K + 1 work prefix for prefix_charge
     int64_t prefix_charge = -1;
     unsigned long long *counts = nullptr;   // ng
     int64_t *host_counts = nullptr;         // pinned, ng
@@ -30,7 +35,7 @@ struct lagr_batch_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     lagr_tune exec_tune{};
-    lagr_tune tune{4, 64, 1};
+    lagr_tune tune{8, (int32_t)TC_COST_ITEM, 1};
     hipEvent_t ready = nullptr;
 };
 
@@ -52,53 +57,90 @@ __global__ void k_pack_rowptr(const int64_t *__restrict__ rp, int64_t n, int64_t
         out[r] = rp[r] + ebase;
 }
 
-__global__ __launch_bounds__(256) void k_batch_work(TcArgs a, int64_t charge, int64_t *__restrict__ work)
+// out[i] = in[i] + add (re-bases packed descriptors: the offset fields sit
+// in the high bits, so adding a shifted base moves them)
+__global__ void k_pack_add_u64(const uint64_t *__restrict__ in, int64_t n, uint64_t add,
+                               uint64_t *__restrict__ out)
 {
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
-    for (int64_t r0 = wave * 64; r0 < a.nrows; r0 += nw * 64) tc_row_work_wave(a, r0, work, charge);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[i] + add;
 }
 
-__global__ __launch_bounds__(TC_BLOCK) void k_tc_batched(TcArgs a, const int64_t *__restrict__ prefix,
-                                                         unsigned long long *__restrict__ per_graph)
+__global__ void k_pack_items(const int32_t *__restrict__ row, int64_t n, int32_t rbase, int32_t g,
+                             int32_t *__restrict__ row_out, int32_t *__restrict__ graph_out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        row_out[i] = row[i] + rbase;
+        graph_out[i] = g;
+    }
+}
+
+// Cost of each packed item (the round-trip model of the single-graph
+// plan, with `charge` as the fixed cost per item): the marked row's cost
+// goes to the first item of the row.
+__global__ void k_batch_item_work(const uint64_t *__restrict__ item, const int32_t *__restrict__ item_row,
+                                  const uint64_t *__restrict__ ent, const int64_t *__restrict__ rp, int64_t K,
+                                  int64_t charge, int64_t *__restrict__ work)
+{
+    const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t it = item[k];
+        const int64_t e0 = (int64_t)(it >> TC_PLAN_CNT_BITS);
+        const int cnt = (int)(it & ((1u << TC_PLAN_CNT_BITS) - 1));
+        int64_t ids = 0;
+        for (int c = 0; c < cnt; c++) ids += (int64_t)(ent[e0 + c] & lmask);
+        const int64_t units = (ids + 63) >> 6;
+        int64_t w = charge + TC_COST_BATCH * ((units + TC_FLAT_INFLIGHT - 1) / TC_FLAT_INFLIGHT);
+        const int32_t m = item_row[k];
+        if (k == 0 || item_row[k - 1] != m) w += TC_COST_MARK * ((rp[m + 1] - rp[m] + 63) >> 6);
+        work[k] = w;
+    }
+}
+
+__global__ __launch_bounds__(TC_BLOCK, 8) void k_tc_batched(PlanArgs a)
 {
     __shared__ TcWaveLds lds[TC_WAVES];
-    const unsigned wave = threadIdx.x / 64;
-    const int64_t w = (int64_t)blockIdx.x * TC_WAVES + wave;
-    tc_rows_balanced<false>(a, lds[wave], nullptr, prefix, w, (int64_t)gridDim.x * TC_WAVES, per_graph);
+    const int64_t w = (int64_t)blockIdx.x * TC_WAVES + threadIdx.x / 64;
+    tc_split_wave<true>(a, lds[threadIdx.x / 64], w, (int64_t)gridDim.x * TC_WAVES);
 }
 
-TcArgs batch_args(const lagr_batch B)
+PlanArgs batch_args(const lagr_batch B)
 {
-    TcArgs a;
-    a.nrows = B->R;
-    a.Mrp = a.Arp = a.Brp = B->rp;
-    a.Mci = a.Aci = a.Bci = B->ci;
-    a.tc_form = 1;
-    a.gbase = B->gbase;
-    a.ngraphs = B->ng;
+    PlanArgs a;
+    a.nitems = B->K;
+    a.Lrp = B->rp;
+    a.Lci = B->ci;
+    a.iprefix = B->prefix;
+    a.ent = B->ent;
+    a.item = B->item;
+    a.item_row = B->item_row;
+    a.item_graph = B->item_graph;
+    a.per_graph = B->counts;
     return a;
 }
 
 int check_tune(const lagr_tune &t, char *msg)
 {
-    if (t.blocks_per_cu < 1 || t.blocks_per_cu > 16 || t.row_charge < 0 || t.row_charge > (1 << 20))
+    if (t.blocks_per_cu < 1 || t.blocks_per_cu > 16 || t.row_charge < 1 || t.row_charge > (1 << 20))
         return lagr_fail(msg, LAGR_INVALID_VALUE, "tune out of range (blocks_per_cu %d, row_charge %d)",
                          t.blocks_per_cu, t.row_charge);
     return LAGR_SUCCESS;
 }
 
-// work prefix for the given charge, on stream s
+// work prefix for the given per-item charge
 int batch_prefix(lagr_ctx ctx, lagr_batch B, int64_t charge, char *msg)
 {
     if (B->prefix_charge == charge) return LAGR_SUCCESS;
-    TRY(fill_i64(ctx, B->prefix + B->R, 1, 0, msg));
-    if (B->R > 0) {
-        hipLaunchKernelGGL(k_batch_work, dim3(grid_for(B->R, 256, 16384)), dim3(256), 0, ctx->stream,
-                           batch_args(B), charge, B->prefix);
+    TRY(fill_i64(ctx, B->prefix + B->K, 1, 0, msg));
+    if (B->K > 0) {
+        hipLaunchKernelGGL(k_batch_item_work, dim3(grid_for(B->K, 256, 16384)), dim3(256), 0, ctx->stream, B->item,
+                           B->item_row, B->ent, B->rp, B->K, charge, B->prefix);
         LAUNCH_CHECK();
     }
-    TRY(scan_exclusive_i64(ctx, B->prefix, B->prefix, B->R + 1, nullptr, msg));
+    TRY(scan_exclusive_i64(ctx, B->prefix, B->prefix, B->K + 1, nullptr, msg));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     B->prefix_charge = charge;
     return LAGR_SUCCESS;
@@ -110,9 +152,9 @@ int enqueue_count(lagr_batch B, hipStream_t s, const lagr_tune &t, char *msg)
     hipLaunchKernelGGL(k_fill_u64_batch, dim3(grid_for(B->ng, 256, 1024)), dim3(256), 0, s, B->counts,
                        B->ng);
     LAUNCH_CHECK();
-    if (B->R > 0) {
+    if (B->K > 0) {
         hipLaunchKernelGGL(k_tc_batched, dim3((unsigned)(B->num_cus * t.blocks_per_cu)), dim3(TC_BLOCK), 0,
-                           s, batch_args(B), (const int64_t *)B->prefix, B->counts);
+                           s, batch_args(B));
         LAUNCH_CHECK();
     }
     return LAGR_SUCCESS;
@@ -137,13 +179,20 @@ extern "C" int lagr_batch_new(lagr_batch *Bout, const lagr_graph *graphs, int64_
     for (int64_t g = 0; g < ngraphs; g++)
         if (!graphs[g]) return lagr_fail(msg, LAGR_NULL_POINTER, "graph %lld is NULL", (long long)g);
     // Basic mode: compute every missing triangle-count operand
-    std::vector<int64_t> gb(ngraphs + 1), eb(ngraphs + 1);
-    gb[0] = eb[0] = 0;
+    std::vector<int64_t> gb(ngraphs + 1), eb(ngraphs + 1), nb(ngraphs + 1), kb(ngraphs + 1);
+    gb[0] = eb[0] = nb[0] = kb[0] = 0;
     for (int64_t g = 0; g < ngraphs; g++) {
         TRY(lagr_property_tc_lower(graphs[g], ctx, msg));
         gb[g + 1] = gb[g] + graphs[g]->L->nrows;
         eb[g + 1] = eb[g] + graphs[g]->L->nvals;
+        nb[g + 1] = nb[g] + graphs[g]->tcplan->nent;
+        kb[g + 1] = kb[g] + graphs[g]->tcplan->nitems;
     }
+    if (gb[ngraphs] >= ((int64_t)1 << 31))
+        return lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "a batch holds fewer than 2^31 rows");
+    if (eb[ngraphs] >= ((int64_t)1 << (64 - TC_PLAN_LEN_BITS)) ||
+        nb[ngraphs] >= ((int64_t)1 << (64 - TC_PLAN_CNT_BITS)))
+        return lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "batch too large for the packed plan");
     lagr_batch B = new (std::nothrow) lagr_batch_s();
     if (!B) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "batch");
     B->device = ctx->device;
@@ -151,29 +200,42 @@ extern "C" int lagr_batch_new(lagr_batch *Bout, const lagr_graph *graphs, int64_
     B->ng = ngraphs;
     B->R = gb[ngraphs];
     B->E = eb[ngraphs];
-    B->gbase = (int64_t *)dev_alloc(8 * (ngraphs + 1));
+    B->NE = nb[ngraphs];
+    B->K = kb[ngraphs];
+    auto one = [](int64_t x) { return (size_t)(x > 0 ? x : 1); };
     B->rp = (int64_t *)dev_alloc(8 * (B->R + 1));
-    B->ci = (int32_t *)dev_alloc(4 * (B->E > 0 ? B->E : 1));
-    B->prefix = (int64_t *)dev_alloc(8 * (B->R + 1));
+    B->ci = (int32_t *)dev_alloc(4 * one(B->E));
+    B->ent = (uint64_t *)dev_alloc(8 * one(B->NE));
+    B->item = (uint64_t *)dev_alloc(8 * one(B->K));
+    B->item_row = (int32_t *)dev_alloc(4 * one(B->K));
+    B->item_graph = (int32_t *)dev_alloc(4 * one(B->K));
+    B->prefix = (int64_t *)dev_alloc(8 * (B->K + 1));
     B->counts = (unsigned long long *)dev_alloc(8 * ngraphs);
     int rc = LAGR_SUCCESS;
-    if (!B->gbase || !B->rp || !B->ci || !B->prefix || !B->counts ||
+    if (!B->rp || !B->ci || !B->ent || !B->item || !B->item_row || !B->item_graph || !B->prefix || !B->counts ||
         hipHostMalloc(&B->host_counts, 8 * ngraphs, hipHostMallocDefault) != hipSuccess ||
         hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&B->ready, hipEventDisableTiming) != hipSuccess) {
         lagr_batch_free(&B);
         return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "batch arrays");
     }
-    if (hipMemcpyAsync(B->gbase, gb.data(), 8 * (ngraphs + 1), hipMemcpyHostToDevice, ctx->stream) !=
-        hipSuccess)
-        rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "batch table copy");
     for (int64_t g = 0; g < ngraphs && rc >= 0; g++) {
         const lagr_matrix L = graphs[g]->L;
-        if (L->nrows > 0) {
+        const TcPlan *P = graphs[g]->tcplan;
+        if (L->nrows > 0)
             hipLaunchKernelGGL(k_pack_rowptr, dim3(grid_for(L->nrows, 256, 4096)), dim3(256), 0, ctx->stream,
                                L->rowptr, L->nrows, eb[g], B->rp + gb[g]);
-            if (hipGetLastError() != hipSuccess) rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "pack launch");
+        if (P->nent > 0)
+            hipLaunchKernelGGL(k_pack_add_u64, dim3(grid_for(P->nent, 256, 4096)), dim3(256), 0, ctx->stream,
+                               P->ent, P->nent, (uint64_t)eb[g] << TC_PLAN_LEN_BITS, B->ent + nb[g]);
+        if (P->nitems > 0) {
+            hipLaunchKernelGGL(k_pack_add_u64, dim3(grid_for(P->nitems, 256, 4096)), dim3(256), 0, ctx->stream,
+                               P->item, P->nitems, (uint64_t)nb[g] << TC_PLAN_CNT_BITS, B->item + kb[g]);
+            hipLaunchKernelGGL(k_pack_items, dim3(grid_for(P->nitems, 256, 4096)), dim3(256), 0, ctx->stream,
+                               P->item_row, P->nitems, (int32_t)gb[g], (int32_t)g, B->item_row + kb[g],
+                               B->item_graph + kb[g]);
         }
+        if (hipGetLastError() != hipSuccess) rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "pack launch");
         if (rc >= 0 && L->nvals > 0 &&
             hipMemcpyAsync(B->ci + eb[g], L->colidx, 4 * L->nvals, hipMemcpyDeviceToDevice, ctx->stream) !=
                 hipSuccess)
@@ -241,8 +303,8 @@ extern "C" int lagr_tc_batched(int64_t *counts, lagr_batch B, const lagr_tune *t
 extern "C" int lagr_batch_autotune(lagr_tune *best, lagr_batch B, lagr_ctx ctx, char *msg)
 {
     if (!best || !B || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
-    static const int bpc[] = {1, 2, 4, 8};
-    static const int charge[] = {16, 64, 256};
+    static const int bpc[] = {2, 4, 8};
+    static const int charge[] = {1, 2, 4};
     std::vector<int64_t> scratch(B->ng);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
@@ -288,10 +350,14 @@ extern "C" int lagr_batch_free(lagr_batch *Bp)
     lagr_batch B = *Bp;
     if (B->stream) (void)hipStreamSynchronize(B->stream);
     drop_graph(B);
-    dev_free(B->gbase, 8 * (B->ng + 1));
+    auto one = [](int64_t x) { return (size_t)(x > 0 ? x : 1); };
     dev_free(B->rp, 8 * (B->R + 1));
-    dev_free(B->ci, 4 * (B->E > 0 ? B->E : 1));
-    dev_free(B->prefix, 8 * (B->R + 1));
+    dev_free(B->ci, 4 * one(B->E));
+    dev_free(B->ent, 8 * one(B->NE));
+    dev_free(B->item, 8 * one(B->K));
+    dev_free(B->item_row, 4 * one(B->K));
+    dev_free(B->item_graph, 4 * one(B->K));
+    dev_free(B->prefix, 8 * (B->K + 1));
     dev_free(B->counts, 8 * B->ng);
     if (B->host_counts) (void)hipHostFree(B->host_counts);
     if (B->ready) (void)hipEventDestroy(B->ready);

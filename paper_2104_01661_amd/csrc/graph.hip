@@ -552,7 +552,7 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
         G->L_maxrow = mx;
     }
     G->L = L;
-    if ((rc = tc_plan_build(ctx, G, msg)) < 0) {
+    if ((rc = tc_plan_build(ctx, G, keys, vbits, msg)) < 0) {
         G->L = nullptr;
         goto fail;
     }

@@ -153,8 +153,9 @@ struct lagr_graph_s {
     TcPlan *tcplan = nullptr;
 };
 
-// Build / release G->tcplan from G->L.
-int tc_plan_build(lagr_ctx ctx, lagr_graph G, char *msg);
+// Build / release G->tcplan from G->L and L's sorted (row << vbits |
+// column) keys.
+int tc_plan_build(lagr_ctx ctx, lagr_graph G, const uint64_t *keys, int vbits, char *msg);
 void tc_plan_free(lagr_graph G);
 
 // Rows of A longer than this are cut into chunks of this many entries for

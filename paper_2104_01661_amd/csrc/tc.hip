@@ -45,66 +45,55 @@ __device__ __forceinline__ uint64_t plan_pack(int64_t off, int64_t len)
     return ((uint64_t)off << TC_PLAN_LEN_BITS) | (uint64_t)len;
 }
 
-// The entries of rows [r0, r0 + 64) of L, flattened over the wave: f(i,
-// p, start of row i, e) for entry e at position p of row i.  The row of an
-// entry is found by a binary search over the 64 row starts held one per
-// lane.  Every lane runs the same trip count (the shuffles need the whole
-// wave); lanes past the end pass valid = false.
-template <class F>
-__device__ __forceinline__ void plan_walk_rows(const int64_t *__restrict__ rp, int64_t n, int64_t r0,
-                                               unsigned lane, F f)
-{
-    const int64_t rl = r0 + lane;
-    const int64_t st = rp[rl < n ? rl : n];
-    const int64_t first = bcast64(st, 0);
-    const int64_t last = rp[r0 + 64 < n ? r0 + 64 : n];
-    for (int64_t base = first; base < last; base += 64) {
-        const int64_t e = base + lane;
-        int t = 0;
-#pragma unroll
-        for (int b = 32; b > 0; b >>= 1) {
-            const int c = t + b;
-            const int lo = __shfl((int)(st & 0xffffffff), c, 64);
-            const int hi = __shfl((int)(st >> 32), c, 64);
-            const int64_t sc = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-            if (sc <= e) t = c;
-        }
-        const int lo = __shfl((int)(st & 0xffffffff), t, 64);
-        const int hi = __shfl((int)(st >> 32), t, 64);
-        const int64_t si = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-        if (e < last) f(r0 + t, e - si, si, e);
-    }
-}
-
 // B-side rows j below PLAN_HOT (the highest-degree vertices after the
 // relabel) receive most B entries; a workgroup first gathers their counts
 // in LDS, so each takes one global atomic per workgroup instead of one per
-// entry (same-address atomics serialise).  A workgroup owns PLAN_ROWS
-// consecutive rows of L, 64 per wavefront.
+// entry (same-address atomics serialise).  The kernels read L's sorted
+// (row << vbits | column) keys, so every thread knows its entry's row and
+// column directly; workgroup g takes the g-th contiguous share of the
+// entries, which keeps its hot counts dense.
 constexpr int PLAN_HOT = 8192;
-constexpr int PLAN_ROWS = 256;
+constexpr int PLAN_BLOCK = 256;
+constexpr unsigned PLAN_GRID = 1024;
+
+struct PlanEntry {
+    int64_t i, j, p, si;   // row, column, position in row i, start of row i
+};
+
+__device__ __forceinline__ PlanEntry plan_entry(const uint64_t *__restrict__ keys, const int64_t *__restrict__ rp,
+                                                int vbits, uint64_t vmask, int64_t e)
+{
+    const uint64_t k = keys[e];
+    PlanEntry x;
+    x.i = (int64_t)(k >> vbits);
+    x.j = (int64_t)(k & vmask);
+    x.si = rp[x.i];
+    x.p = e - x.si;
+    return x;
+}
 
 // Entries per virtual row (cnt: 2n+1 entries, zero on entry).
-__global__ __launch_bounds__(PLAN_ROWS) void k_plan_count(const int64_t *__restrict__ rp,
-                                                          const int32_t *__restrict__ ci, int64_t n,
-                                                          unsigned long long *__restrict__ cnt)
+__global__ __launch_bounds__(PLAN_BLOCK) void k_plan_count(const uint64_t *__restrict__ keys, int64_t nnz,
+                                                           int vbits, uint64_t vmask,
+                                                           const int64_t *__restrict__ rp, int64_t n,
+                                                           unsigned long long *__restrict__ cnt)
 {
     __shared__ unsigned hot[PLAN_HOT];
-    for (int x = threadIdx.x; x < PLAN_HOT; x += PLAN_ROWS) hot[x] = 0u;
+    for (int x = threadIdx.x; x < PLAN_HOT; x += PLAN_BLOCK) hot[x] = 0u;
     __syncthreads();
-    const int64_t r0 = (int64_t)blockIdx.x * PLAN_ROWS + (threadIdx.x / 64) * 64;
-    if (r0 < n)
-        plan_walk_rows(rp, n, r0, lane_id(), [&](int64_t i, int64_t p, int64_t, int64_t e) {
-            if (p == 0) return;
-            const int32_t j = ci[e];
-            const int64_t lj = rp[j + 1] - rp[j];
-            if (lj == 0) return;
-            if (lj <= p) atomicAdd(&cnt[i], 1ull);
-            else if (j < PLAN_HOT) atomicAdd(&hot[j], 1u);
-            else atomicAdd(&cnt[n + j], 1ull);
-        });
+    const int64_t share = (nnz + gridDim.x - 1) / gridDim.x;
+    const int64_t e0 = (int64_t)blockIdx.x * share, e1 = min(nnz, e0 + share);
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += PLAN_BLOCK) {
+        const PlanEntry x = plan_entry(keys, rp, vbits, vmask, e);
+        if (x.p == 0) continue;
+        const int64_t lj = rp[x.j + 1] - rp[x.j];
+        if (lj == 0) continue;
+        if (lj <= x.p) atomicAdd(&cnt[x.i], 1ull);
+        else if (x.j < PLAN_HOT) atomicAdd(&hot[x.j], 1u);
+        else atomicAdd(&cnt[n + x.j], 1ull);
+    }
     __syncthreads();
-    for (int x = threadIdx.x; x < PLAN_HOT && x < n; x += PLAN_ROWS)
+    for (int x = threadIdx.x; x < PLAN_HOT && x < n; x += PLAN_BLOCK)
         if (hot[x]) atomicAdd(&cnt[n + x], (unsigned long long)hot[x]);
 }
 
@@ -113,38 +102,38 @@ __global__ __launch_bounds__(PLAN_ROWS) void k_plan_count(const int64_t *__restr
 // B rows reserve one range per workgroup and hand out positions from LDS
 // as offsets from bstart, the first B-side offset (the host checks that
 // the B side spans fewer than 2^32 entries).
-__global__ __launch_bounds__(PLAN_ROWS) void k_plan_fill(const int64_t *__restrict__ rp,
-                                                         const int32_t *__restrict__ ci, int64_t n,
-                                                         int64_t bstart, unsigned long long *__restrict__ cur,
-                                                         uint64_t *__restrict__ ent)
+__global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const uint64_t *__restrict__ keys, int64_t nnz,
+                                                          int vbits, uint64_t vmask,
+                                                          const int64_t *__restrict__ rp, int64_t n,
+                                                          int64_t bstart, unsigned long long *__restrict__ cur,
+                                                          uint64_t *__restrict__ ent)
 {
     __shared__ unsigned hot[PLAN_HOT];
-    for (int x = threadIdx.x; x < PLAN_HOT; x += PLAN_ROWS) hot[x] = 0u;
+    for (int x = threadIdx.x; x < PLAN_HOT; x += PLAN_BLOCK) hot[x] = 0u;
     __syncthreads();
-    const int64_t r0 = (int64_t)blockIdx.x * PLAN_ROWS + (threadIdx.x / 64) * 64;
-    const unsigned lane = lane_id();
-    if (r0 < n)
-        plan_walk_rows(rp, n, r0, lane, [&](int64_t, int64_t p, int64_t, int64_t e) {
-            if (p == 0) return;
-            const int32_t j = ci[e];
-            if (j >= PLAN_HOT) return;
-            const int64_t lj = rp[j + 1] - rp[j];
-            if (lj > p) atomicAdd(&hot[j], 1u);
-        });
+    const int64_t share = (nnz + gridDim.x - 1) / gridDim.x;
+    const int64_t e0 = (int64_t)blockIdx.x * share, e1 = min(nnz, e0 + share);
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += PLAN_BLOCK) {
+        const uint64_t k = keys[e];
+        const int64_t j = (int64_t)(k & vmask);
+        if (j >= PLAN_HOT) continue;
+        const int64_t i = (int64_t)(k >> vbits), p = e - rp[i];
+        const int64_t lj = rp[j + 1] - rp[j];
+        if (p > 0 && lj > p) atomicAdd(&hot[j], 1u);
+    }
     __syncthreads();
-    for (int x = threadIdx.x; x < PLAN_HOT && x < n; x += PLAN_ROWS)
+    for (int x = threadIdx.x; x < PLAN_HOT && x < n; x += PLAN_BLOCK)
         if (hot[x]) hot[x] = (unsigned)((int64_t)atomicAdd(&cur[n + x], (unsigned long long)hot[x]) - bstart);
     __syncthreads();
-    if (r0 < n)
-        plan_walk_rows(rp, n, r0, lane, [&](int64_t i, int64_t p, int64_t si, int64_t e) {
-            if (p == 0) return;
-            const int32_t j = ci[e];
-            const int64_t sj = rp[j], lj = rp[j + 1] - sj;
-            if (lj == 0) return;
-            if (lj <= p) ent[atomicAdd(&cur[i], 1ull)] = plan_pack(sj, lj);
-            else if (j < PLAN_HOT) ent[bstart + atomicAdd(&hot[j], 1u)] = plan_pack(si, p);
-            else ent[atomicAdd(&cur[n + j], 1ull)] = plan_pack(si, p);
-        });
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += PLAN_BLOCK) {
+        const PlanEntry x = plan_entry(keys, rp, vbits, vmask, e);
+        if (x.p == 0) continue;
+        const int64_t sj = rp[x.j], lj = rp[x.j + 1] - sj;
+        if (lj == 0) continue;
+        if (lj <= x.p) ent[atomicAdd(&cur[x.i], 1ull)] = plan_pack(sj, lj);
+        else if (x.j < PLAN_HOT) ent[bstart + atomicAdd(&hot[x.j], 1u)] = plan_pack(x.si, x.p);
+        else ent[atomicAdd(&cur[n + x.j], 1ull)] = plan_pack(x.si, x.p);
+    }
 }
 
 __global__ void k_plan_items(const int64_t *__restrict__ trp, int64_t nv, int64_t *__restrict__ irp)
@@ -191,61 +180,15 @@ __global__ void k_plan_item_work(const int64_t *__restrict__ Lrp, int64_t n,
     }
 }
 
-struct PlanArgs {
-    int64_t nitems;
-    const int64_t *Lrp;
-    const int32_t *Lci;
-    const int64_t *iprefix;
-    const uint64_t *ent;
-    const uint64_t *item;
-    const int32_t *item_row;
-};
-
 // Each workgroup writes its count to partial[blockIdx.x]; k_sum_partials
 // adds them (atomics on one address from every wavefront would serialise).
 __global__ __launch_bounds__(TC_BLOCK, 8) void k_tc_split(PlanArgs a, unsigned long long *__restrict__ partial)
 {
     __shared__ TcWaveLds lds[TC_WAVES];
-    TcWaveLds &L = lds[threadIdx.x / 64];
-    const unsigned lane = lane_id();
     const int64_t w = (int64_t)blockIdx.x * TC_WAVES + threadIdx.x / 64;
-    const int64_t nw = (int64_t)gridDim.x * TC_WAVES;
-    for (int x = lane; x < TC_BM_WORDS; x += 64) L.bm[x] = 0u;
-    wave_sync();
-    const int64_t T = a.iprefix[a.nitems];
-    const int64_t lo = (int64_t)((__int128)T * w / nw), hi = (int64_t)((__int128)T * (w + 1) / nw);
-    const int64_t k0 = tc_lower_bound(a.iprefix, a.nitems, lo);
-    const int64_t k1 = tc_lower_bound(a.iprefix, a.nitems, hi);
-    const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
-    unsigned long long acc = 0;
-    int32_t marked = -1, first_id = -1;
-    int64_t alen = 0;
-    const int32_t *Arow = nullptr;
-    bool use_hash = false;
-    for (int64_t k = k0; k < k1; k++) {
-        const uint64_t it = a.item[k];
-        const int32_t m = a.item_row[k];
-        const int64_t e0 = (int64_t)(it >> TC_PLAN_CNT_BITS);
-        const int cnt = (int)(it & ((1u << TC_PLAN_CNT_BITS) - 1));
-        int64_t s = 0;
-        int len = 0;
-        if ((int)lane < cnt) {
-            const uint64_t x = a.ent[e0 + lane];
-            s = (int64_t)(x >> TC_PLAN_LEN_BITS);
-            len = (int)(x & lmask);
-        }
-        if (m != marked) {
-            if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
-            Arow = a.Lci + a.Lrp[m];
-            alen = a.Lrp[m + 1] - a.Lrp[m];
-            use_hash = tc_mark(L, Arow, alen, lane, &first_id);
-            marked = m;
-        }
-        acc += tc_stream_flat(L, use_hash, Arow, alen, a.Lci, s, len, cnt, lane);
-    }
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    unsigned long long acc = tc_split_wave<false>(a, lds[threadIdx.x / 64], w, (int64_t)gridDim.x * TC_WAVES);
     __shared__ unsigned long long wsum[TC_WAVES];
-    if (lane == 0) wsum[threadIdx.x / 64] = acc;
+    if (lane_id() == 0) wsum[threadIdx.x / 64] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
@@ -286,7 +229,7 @@ void tc_plan_free(lagr_graph G)
     G->tcplan = nullptr;
 }
 
-int tc_plan_build(lagr_ctx ctx, lagr_graph G, char *msg)
+int tc_plan_build(lagr_ctx ctx, lagr_graph G, const uint64_t *keys, int vbits, char *msg)
 {
     const lagr_matrix Lm = G->L;
     const int64_t n = Lm->nrows, nv = 2 * n;
@@ -305,10 +248,11 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, char *msg)
     if (!P->trp || !P->irp) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
     int rc;
     if ((rc = fill_i64(ctx, P->trp, nv + 1, 0, msg)) < 0) return fail(rc);
-    const unsigned wgrid = (unsigned)((n + PLAN_ROWS - 1) / PLAN_ROWS);
-    if (n > 0) {
-        hipLaunchKernelGGL(k_plan_count, dim3(wgrid), dim3(PLAN_ROWS), 0, ctx->stream, Lm->rowptr, Lm->colidx, n,
-                           (unsigned long long *)P->trp);
+    const uint64_t vmask = vbits ? ((1ull << vbits) - 1) : 0ull;
+    const int64_t nnz = Lm->nvals;
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_plan_count, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, keys, nnz, vbits, vmask,
+                           Lm->rowptr, n, (unsigned long long *)P->trp);
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
     }
     if ((rc = scan_exclusive_i64(ctx, P->trp, P->trp, nv + 1, &P->nent, msg)) < 0) return fail(rc);
@@ -322,8 +266,9 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, char *msg)
     if (n > 0) {
         if (hipMemcpyAsync(cur, P->trp, 8 * (size_t)nv, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
             return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan copy"));
-        hipLaunchKernelGGL(k_plan_fill, dim3(wgrid), dim3(PLAN_ROWS), 0, ctx->stream, Lm->rowptr, Lm->colidx, n,
-                           bstart, cur, P->ent);
+        if (nnz > 0)
+            hipLaunchKernelGGL(k_plan_fill, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, keys, nnz, vbits,
+                               vmask, Lm->rowptr, n, bstart, cur, P->ent);
         hipLaunchKernelGGL(k_plan_items, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, ctx->stream, P->trp,
                            nv, P->irp);
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));

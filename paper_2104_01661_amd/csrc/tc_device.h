@@ -162,58 +162,8 @@ __device__ __forceinline__ void tc_unmark_kept(TcWaveLds &L, int32_t first_id, i
     wave_sync();
 }
 
-// Count, over up to 64 segments (lane t holds segment t: ids Bci[s, s+len)
-// or len = 0), the ids that are marked.  The segments are cut into units
-// of 64 ids and the wave walks the units in order, two at a time so that
-// two coalesced loads are in flight.  Returns this lane's partial count.
-__device__ __forceinline__ unsigned long long tc_stream(const TcWaveLds &L, bool use_hash,
-                                                        const int32_t *__restrict__ Arow, int64_t alen,
-                                                        const int32_t *__restrict__ Bci, int64_t s, int len,
-                                                        unsigned lane)
-{
-    const int nch = (len + 63) >> 6;
-    int incl = nch;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(incl, d, 64);
-        if ((int)lane >= d) incl += y;
-    }
-    const int U = __shfl(incl, 63, 64);
-    const int excl = incl - nch;
-    unsigned long long acc = 0;
-    int t = 0;   // segment of the current unit (wave-uniform)
-    int tend = __shfl(incl, 0, 64);
-    for (int u = 0; u < U; u += 2) {
-        while (u >= tend) {
-            t++;
-            tend = __shfl(incl, t, 64);
-        }
-        const int t1 = t;
-        const int off1 = (u - __shfl(excl, t1, 64)) * 64;
-        const int64_t base1 = bcast64(s, t1) + off1;
-        const int lim1 = __shfl(len, t1, 64) - off1;
-        int lim2 = 0;
-        int64_t base2 = 0;
-        if (u + 1 < U) {
-            int tt = t1, te = tend;
-            while (u + 1 >= te) {
-                tt++;
-                te = __shfl(incl, tt, 64);
-            }
-            const int off2 = (u + 1 - __shfl(excl, tt, 64)) * 64;
-            base2 = bcast64(s, tt) + off2;
-            lim2 = __shfl(len, tt, 64) - off2;
-        }
-        const bool v1 = (int)lane < lim1, v2 = (int)lane < lim2;
-        const int32_t k1 = v1 ? Bci[base1 + lane] : 0;
-        const int32_t k2 = v2 ? Bci[base2 + lane] : 0;
-        acc += (v1 ? tc_member(L, use_hash, Arow, alen, k1) : 0u) +
-               (v2 ? tc_member(L, use_hash, Arow, alen, k2) : 0u);
-    }
-    return acc;
-}
-
-// tc_stream over the concatenation of the segments: unit u holds ids
+// Count, over up to 64 segments (lane t < cnt holds segment t: ids
+// Bci[s, s+len)), the ids that are marked: unit u holds ids
 // 64u .. 64u+63 of the concatenation, so short segments share units, and
 // TC_FLAT_INFLIGHT units are loaded before any is probed.  Each lane finds
 // the segment of its id by walking the wave's LDS copy of the segment
@@ -486,3 +436,80 @@ struct TcPlan {
     uint64_t *item = nullptr;    // nitems: (first entry << TC_PLAN_CNT_BITS) | count
     int32_t *item_row = nullptr; // nitems: row of L the item marks
 };
+
+struct PlanArgs {
+    int64_t nitems;
+    const int64_t *Lrp;
+    const int32_t *Lci;
+    const int64_t *iprefix;
+    const uint64_t *ent;
+    const uint64_t *item;
+    const int32_t *item_row;
+    // many packed graphs: the graph of each item and its counter (else null)
+    const int32_t *item_graph = nullptr;
+    unsigned long long *per_graph = nullptr;
+};
+
+// Wave w of nw takes the items whose work prefix starts in its equal share
+// of the total, marks each item's row (again only when the row changes)
+// and streams its segments.  Returns this wave's count, summed over the
+// wave; with BATCHED each graph's part is added to per_graph[g] instead
+// (the items of one graph are contiguous) and the result is 0.
+template <bool BATCHED>
+__device__ unsigned long long tc_split_wave(const PlanArgs &a, TcWaveLds &L, int64_t w, int64_t nw)
+{
+    const unsigned lane = lane_id();
+    for (int x = lane; x < TC_BM_WORDS; x += 64) L.bm[x] = 0u;
+    wave_sync();
+    const int64_t T = a.iprefix[a.nitems];
+    const int64_t lo = (int64_t)((__int128)T * w / nw), hi = (int64_t)((__int128)T * (w + 1) / nw);
+    const int64_t k0 = tc_lower_bound(a.iprefix, a.nitems, lo);
+    const int64_t k1 = tc_lower_bound(a.iprefix, a.nitems, hi);
+    const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
+    unsigned long long acc = 0;
+    int32_t marked = -1, first_id = -1, g = -1;
+    int64_t alen = 0;
+    const int32_t *Arow = nullptr;
+    bool use_hash = false;
+    auto flush = [&]() {
+        unsigned long long t = acc;
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        if (lane == 0 && t && g >= 0) atomicAdd(&a.per_graph[g], t);
+        acc = 0;
+    };
+    for (int64_t k = k0; k < k1; k++) {
+        if (BATCHED) {
+            const int32_t gk = a.item_graph[k];
+            if (gk != g) {
+                flush();
+                g = gk;
+            }
+        }
+        const uint64_t it = a.item[k];
+        const int32_t m = a.item_row[k];
+        const int64_t e0 = (int64_t)(it >> TC_PLAN_CNT_BITS);
+        const int cnt = (int)(it & ((1u << TC_PLAN_CNT_BITS) - 1));
+        int64_t s = 0;
+        int len = 0;
+        if ((int)lane < cnt) {
+            const uint64_t x = a.ent[e0 + lane];
+            s = (int64_t)(x >> TC_PLAN_LEN_BITS);
+            len = (int)(x & lmask);
+        }
+        if (m != marked) {
+            if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
+            Arow = a.Lci + a.Lrp[m];
+            alen = a.Lrp[m + 1] - a.Lrp[m];
+            use_hash = tc_mark(L, Arow, alen, lane, &first_id);
+            marked = m;
+        }
+        acc += tc_stream_flat(L, use_hash, Arow, alen, a.Lci, s, len, cnt, lane);
+    }
+    if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
+    if (BATCHED) {
+        flush();
+        return 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    return acc;
+}

@@ -36,12 +36,12 @@ def test_batched_counts_equal_oracle_and_replays():
     B = L.Batch(c, gs)
     ng, rows, entries = B.info()
     assert ng == len(gs)
-    eager = B.tc(c, L.Tune(4, 64, 0))
+    eager = B.tc(c, L.Tune(4, 2, 0))
     assert np.array_equal(eager, want)
-    for t in (L.Tune(1, 16, 0), L.Tune(8, 256, 0), L.Tune(2, 0, 0)):
+    for t in (L.Tune(1, 1, 0), L.Tune(8, 4, 0), L.Tune(2, 64, 0), L.Tune(16, 2, 0)):
         assert np.array_equal(B.tc(c, t), want)
     # replays of the captured launch, with other device work in between
-    graph_tune = L.Tune(4, 64, 1)
+    graph_tune = L.Tune(8, 2, 1)
     for rep in range(4):
         assert np.array_equal(B.tc(c, graph_tune), want), rep
         assert L.lagr_tc(gs[rep], c) == want[rep]
@@ -59,5 +59,8 @@ def test_single_graph_batch_and_bad_tune():
     B = L.Batch(c, [G])
     assert B.tc(c).tolist() == [oracle.triangle_count(*oracle.build_adjacency(n, s, d))]
     with pytest.raises(L.LagrError) as e:
-        B.tc(c, L.Tune(0, 64, 0))
+        B.tc(c, L.Tune(0, 2, 0))
+    assert e.value.code == L.INVALID_VALUE
+    with pytest.raises(L.LagrError) as e:
+        B.tc(c, L.Tune(4, 0, 0))
     assert e.value.code == L.INVALID_VALUE
