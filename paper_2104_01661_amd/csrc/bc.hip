@@ -5,15 +5,25 @@
 // n x 64 FP64 arrays, vertex-major (the 64 lanes of a vertex are 512
 // contiguous bytes, so a wave reads a neighbour's row in one coalesced
 // load).  The frontier S[d] of Algorithm 3 is kept as one 64-bit lane mask
-// per vertex and level (bit k = vertex is at depth d from source k); the
-// visited mask P's pattern is the per-vertex mask of lanes not yet reached.
+// per vertex and level (bit k = vertex is at depth d from source k) plus
+// the list of vertices whose mask is not empty; the visited mask P's
+// pattern is the per-vertex mask of lanes not yet reached, with a list of
+// the vertices that still have such lanes ("active").
 //
-// Forward level d (F<!s(P), r> = F plus.first A, then P += F): a wave per
-// unreached vertex v gathers, in ascending neighbour order, sigma(u, k) of
-// the neighbours u at depth d in lane k.  Path counts are integers below
-// 2^53, so the FP64 sums are exact.
+// Forward level d (F<!s(P), r> = F plus.first A, then P += F), in the
+// direction that touches fewer edges (the choice the paper describes for
+// BC, after Beamer):
+//   pull: a wave per active vertex v gathers, in ascending neighbour order,
+//         sigma(u, k) of the neighbours u at depth d in lane k;
+//   push: a wave per frontier vertex u adds sigma(u, k) to every neighbour
+//         v still unreached in lane k (FP64 atomics).
+// Path counts are integers below 2^53, so every FP64 sum is exact and the
+// result does not depend on the order of the additions.  A compaction pass
+// then folds the new masks into the unreached masks and lists the next
+// frontier and the active vertices.
 // Backward level i (Algorithm 3's backtrack, read as i = d down to 1 so the
-// deepest level contributes): for v at depth i-1 in lane k,
+// deepest level contributes): for v at depth i-1 in lane k (the level's
+// list),
 //   delta(v,k) = sigma(v,k) * sum over neighbours w at depth i in lane k of
 //                W(w,k),   W(w,k) = (1 + delta(w,k)) / sigma(w,k),
 // summed in ascending neighbour order; the kernel writes W(v,k) for the
@@ -29,6 +39,9 @@ namespace {
 // pieces (hub vertices would otherwise hold one wave for the whole level).
 constexpr int64_t BC_LONG = GRAPH_LONG_ROW;
 constexpr int64_t BC_CHUNK = GRAPH_LONG_ROW;
+// push a forward level when the frontier's edges are fewer than the active
+// vertices' edges / BC_PUSH_RATIO
+constexpr int64_t BC_PUSH_RATIO = 10;
 
 __global__ __launch_bounds__(256) void k_bc_init(int64_t n, uint64_t lanes,
                                                  uint64_t *__restrict__ unvis,
@@ -72,26 +85,55 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t x, int src)
     return ((uint64_t)hi << 32) | lo;
 }
 
-// One wave per vertex; returns through `next` the level-(d+1) lane mask.
-__global__ __launch_bounds__(256) void k_bc_forward(const int64_t *__restrict__ rp,
-                                                    const int32_t *__restrict__ ci, int64_t n,
-                                                    const uint64_t *__restrict__ cur,
-                                                    uint64_t *__restrict__ next,
-                                                    uint64_t *__restrict__ unvis,
-                                                    double *__restrict__ sigma,
-                                                    unsigned *__restrict__ any_new)
+// acc += val[u_t * 64 + lane] for every hit t of the ballot `hits` (in
+// ascending t) whose mask m_t has this lane, where u_t and m_t are lane t's
+// neighbour and mask.  Eight rows are loaded before any is added, and the
+// additions keep the ascending order (adding 0.0 for a lane without the bit
+// leaves the sum unchanged), so the result is that of the one-at-a-time
+// loop.
+constexpr int BC_GATHER = 8;
+
+__device__ __forceinline__ double gather_hits(uint64_t hits, int32_t u, uint64_t m, const double *__restrict__ val,
+                                              unsigned lane, double acc)
+{
+    while (hits) {
+        int32_t uu[BC_GATHER];
+        bool on[BC_GATHER];
+#pragma unroll
+        for (int j = 0; j < BC_GATHER; j++) {
+            on[j] = false;
+            uu[j] = 0;
+            if (hits) {
+                const int t = __ffsll((unsigned long long)hits) - 1;
+                hits &= hits - 1;
+                uu[j] = __shfl(u, t, 64);
+                on[j] = (shfl64(m, t) >> lane) & 1ull;
+            }
+        }
+        double x[BC_GATHER];
+#pragma unroll
+        for (int j = 0; j < BC_GATHER; j++) x[j] = on[j] ? val[(int64_t)uu[j] * 64 + lane] : 0.0;
+#pragma unroll
+        for (int j = 0; j < BC_GATHER; j++) acc += x[j];
+    }
+    return acc;
+}
+
+// Pull: one wave per active vertex (rows of at most BC_LONG neighbours);
+// writes next[v] (zero on entry) and sigma of the lanes it reaches.
+__global__ __launch_bounds__(256) void k_bc_pull(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                 const int32_t *__restrict__ act, int64_t na,
+                                                 const uint64_t *__restrict__ cur, uint64_t *__restrict__ next,
+                                                 const uint64_t *__restrict__ unvis, double *__restrict__ sigma)
 {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const unsigned lane = lane_id();
-    for (int64_t v = wave; v < n; v += nw) {
+    for (int64_t q = wave; q < na; q += nw) {
+        const int64_t v = act[q];
         const int64_t b = rp[v], e = rp[v + 1];
         if (e - b > BC_LONG) continue;   // k_bc_forward_chunks
         const uint64_t uv = unvis[v];
-        if (uv == 0) {
-            if (lane == 0) next[v] = 0;
-            continue;
-        }
         double acc = 0.0;
         for (int64_t p0 = b; p0 < e; p0 += 64) {
             const int64_t p = p0 + lane;
@@ -101,29 +143,153 @@ __global__ __launch_bounds__(256) void k_bc_forward(const int64_t *__restrict__ 
                 u = ci[p];
                 fm = cur[u] & uv;
             }
-            uint64_t hits = __ballot(fm != 0);
-            while (hits) {
-                const int t = __ffsll((unsigned long long)hits) - 1;
-                hits &= hits - 1;
-                const int32_t uu = __shfl(u, t, 64);
-                const uint64_t m = shfl64(fm, t);
-                if ((m >> lane) & 1ull) acc += sigma[(int64_t)uu * 64 + lane];
-            }
+            acc = gather_hits(__ballot(fm != 0), u, fm, sigma, lane, acc);
         }
         const uint64_t nw_mask = __ballot(acc > 0.0) & uv;
         if ((nw_mask >> lane) & 1ull) sigma[v * 64 + lane] = acc;
-        if (lane == 0) {
-            next[v] = nw_mask;
-            if (nw_mask) {
-                unvis[v] = uv & ~nw_mask;
-                *any_new = 1u;   // a flag: a plain store suffices (atomics on one address serialise)
-            }
+        if (lane == 0 && nw_mask) next[v] = nw_mask;
+    }
+}
+
+// Push from frontier vertex u (lanes fm, this lane's sigma su) over the
+// neighbour range [b, e), 64 neighbours per step.
+__device__ __forceinline__ void bc_push_range(const int32_t *__restrict__ ci, int64_t b, int64_t e, uint64_t fm,
+                                              double su, const uint64_t *__restrict__ unvis,
+                                              double *__restrict__ sigma, uint64_t *__restrict__ next,
+                                              unsigned lane)
+{
+    for (int64_t p0 = b; p0 < e; p0 += 64) {
+        const int64_t p = p0 + lane;
+        int32_t v = 0;
+        uint64_t m = 0;
+        if (p < e) {
+            v = ci[p];
+            m = unvis[v] & fm;
+        }
+        uint64_t hits = __ballot(m != 0);
+        while (hits) {
+            const int t = __ffsll((unsigned long long)hits) - 1;
+            hits &= hits - 1;
+            const int32_t vv = __shfl(v, t, 64);
+            const uint64_t mm = shfl64(m, t);
+            if ((mm >> lane) & 1ull) unsafeAtomicAdd(&sigma[(int64_t)vv * 64 + lane], su);
+            if (lane == 0) atomicOr((unsigned long long *)&next[vv], (unsigned long long)mm);
         }
     }
 }
 
+// Push: one wave per frontier vertex (rows of at most BC_LONG neighbours).
+__global__ __launch_bounds__(256) void k_bc_push(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                 const int32_t *__restrict__ front, int64_t nf,
+                                                 const uint64_t *__restrict__ cur, uint64_t *__restrict__ next,
+                                                 const uint64_t *__restrict__ unvis, double *__restrict__ sigma)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t q = wave; q < nf; q += nw) {
+        const int64_t u = front[q];
+        const int64_t b = rp[u], e = rp[u + 1];
+        if (e - b > BC_LONG) continue;   // k_bc_push_chunks
+        bc_push_range(ci, b, e, cur[u], sigma[u * 64 + lane], unvis, sigma, next, lane);
+    }
+}
+
+// Push for the frontier's hub vertices, one wave per chunk.
+__global__ __launch_bounds__(256) void k_bc_push_chunks(const int32_t *__restrict__ ci, RowChunks ch,
+                                                        const uint64_t *__restrict__ cur,
+                                                        uint64_t *__restrict__ next,
+                                                        const uint64_t *__restrict__ unvis,
+                                                        double *__restrict__ sigma)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t c = wave; c < ch.n; c += nw) {
+        const int64_t u = ch.row[c];
+        const uint64_t fm = cur[u];
+        if (fm == 0) continue;
+        bc_push_range(ci, ch.beg[c], ch.end[c], fm, sigma[u * 64 + lane], unvis, sigma, next, lane);
+    }
+}
+
+// After a level: unvis &= ~next; the vertices with a new mask form the next
+// frontier list and those with unreached lanes (and neighbours) the active
+// list; cnt[0..3] += frontier size, its degree sum, active size, its degree
+// sum.  Workgroup g owns the g-th contiguous share of the vertices: it
+// counts, reserves its ranges with one atomic per counter and writes its
+// vertices in ascending order.
+__global__ __launch_bounds__(256) void k_bc_compact(const int64_t *__restrict__ rp, int64_t n,
+                                                    const uint64_t *__restrict__ next, uint64_t *__restrict__ unvis,
+                                                    int32_t *__restrict__ flist, int32_t *__restrict__ alist,
+                                                    unsigned long long *__restrict__ cnt)
+{
+    __shared__ unsigned sf[256], sa[256];
+    __shared__ unsigned long long base_f, base_a, sum_ef, sum_ea;
+    const int64_t share = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t v0 = (int64_t)blockIdx.x * share, v1 = min(n, v0 + share);
+    unsigned cf = 0, ca = 0;
+    unsigned long long ef = 0, ea = 0;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += 256) {
+        const uint64_t nm = next[v];
+        uint64_t uv = unvis[v];
+        if (nm) {
+            uv &= ~nm;
+            unvis[v] = uv;
+        }
+        const int64_t deg = rp[v + 1] - rp[v];
+        if (nm) {
+            cf++;
+            ef += (unsigned long long)deg;
+        }
+        if (uv && deg) {
+            ca++;
+            ea += (unsigned long long)deg;
+        }
+    }
+    sf[threadIdx.x] = cf;
+    sa[threadIdx.x] = ca;
+    if (threadIdx.x == 0) sum_ef = sum_ea = 0;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const unsigned yf = (int)threadIdx.x >= o ? sf[threadIdx.x - o] : 0u;
+        const unsigned ya = (int)threadIdx.x >= o ? sa[threadIdx.x - o] : 0u;
+        __syncthreads();
+        sf[threadIdx.x] += yf;
+        sa[threadIdx.x] += ya;
+        __syncthreads();
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        ef += __shfl_xor(ef, o, 64);
+        ea += __shfl_xor(ea, o, 64);
+    }
+    if (lane_id() == 0) {
+        if (ef) atomicAdd(&sum_ef, ef);
+        if (ea) atomicAdd(&sum_ea, ea);
+    }
+    if (threadIdx.x == 255) {
+        base_f = sf[255] ? atomicAdd(&cnt[0], (unsigned long long)sf[255]) : 0;
+        base_a = sa[255] ? atomicAdd(&cnt[2], (unsigned long long)sa[255]) : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (sum_ef) atomicAdd(&cnt[1], sum_ef);
+        if (sum_ea) atomicAdd(&cnt[3], sum_ea);
+    }
+    unsigned long long pf = base_f + sf[threadIdx.x] - cf, pa = base_a + sa[threadIdx.x] - ca;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += 256) {
+        const uint64_t nm = next[v], uv = unvis[v];
+        const int64_t deg = rp[v + 1] - rp[v];
+        if (nm) flist[pf++] = (int32_t)v;
+        if (uv && deg) alist[pa++] = (int32_t)v;
+    }
+}
+
+// Backward targets: one wave per vertex of level i-1's list (rows of at
+// most BC_LONG neighbours).
 __global__ __launch_bounds__(256) void k_bc_backward(const int64_t *__restrict__ rp,
-                                                     const int32_t *__restrict__ ci, int64_t n,
+                                                     const int32_t *__restrict__ ci,
+                                                     const int32_t *__restrict__ tlist, int64_t nt,
                                                      const uint64_t *__restrict__ at_i,   // depth i
                                                      const uint64_t *__restrict__ at_im1, // depth i-1
                                                      int has_deeper, int gshift,
@@ -134,11 +300,11 @@ __global__ __launch_bounds__(256) void k_bc_backward(const int64_t *__restrict__
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const unsigned lane = lane_id();
-    for (int64_t v = wave; v < n; v += nw) {
+    for (int64_t q = wave; q < nt; q += nw) {
+        const int64_t v = tlist[q];
         const int64_t b = rp[v], e = rp[v + 1];
         if (e - b > BC_LONG) continue;   // k_bc_backward_chunks
         const uint64_t dm = at_im1[v];
-        if (dm == 0) continue;
         double acc = 0.0;
         if (has_deeper) {
             for (int64_t p0 = b; p0 < e; p0 += 64) {
@@ -149,14 +315,7 @@ __global__ __launch_bounds__(256) void k_bc_backward(const int64_t *__restrict__
                     w = ci[p];
                     fm = at_i[w] & dm;
                 }
-                uint64_t hits = __ballot(fm != 0);
-                while (hits) {
-                    const int t = __ffsll((unsigned long long)hits) - 1;
-                    hits &= hits - 1;
-                    const int32_t ww = __shfl(w, t, 64);
-                    const uint64_t m = shfl64(fm, t);
-                    if ((m >> lane) & 1ull) acc += W[(int64_t)ww * 64 + lane];
-                }
+                acc = gather_hits(__ballot(fm != 0), w, fm, W, lane, acc);
             }
         }
         const bool mine = (dm >> lane) & 1ull;
@@ -187,14 +346,7 @@ __device__ __forceinline__ double gather_lanes(const int32_t *__restrict__ ci, i
             u = ci[p];
             fm = lvl[u] & want;
         }
-        uint64_t hits = __ballot(fm != 0);
-        while (hits) {
-            const int t = __ffsll((unsigned long long)hits) - 1;
-            hits &= hits - 1;
-            const int32_t uu = __shfl(u, t, 64);
-            const uint64_t m = shfl64(fm, t);
-            if ((m >> lane) & 1ull) acc += val[(int64_t)uu * 64 + lane];
-        }
+        acc = gather_hits(__ballot(fm != 0), u, fm, val, lane, acc);
     }
     return acc;
 }
@@ -218,9 +370,8 @@ __global__ __launch_bounds__(256) void k_bc_forward_chunks(const int32_t *__rest
 __global__ __launch_bounds__(256) void k_bc_forward_combine(const int64_t *__restrict__ rp, RowChunks ch,
                                                             const double *__restrict__ partial,
                                                             uint64_t *__restrict__ next,
-                                                            uint64_t *__restrict__ unvis,
-                                                            double *__restrict__ sigma,
-                                                            unsigned *__restrict__ any_new)
+                                                            const uint64_t *__restrict__ unvis,
+                                                            double *__restrict__ sigma)
 {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
@@ -229,22 +380,13 @@ __global__ __launch_bounds__(256) void k_bc_forward_combine(const int64_t *__res
         const int64_t v = ch.row[c];
         if (ch.beg[c] != rp[v]) continue;   // first chunk of its vertex only
         const uint64_t uv = unvis[v];
-        if (uv == 0) {
-            if (lane == 0) next[v] = 0;
-            continue;
-        }
+        if (uv == 0) continue;
         const int64_t k = (rp[v + 1] - rp[v] + BC_CHUNK - 1) / BC_CHUNK;
         double acc = 0.0;
         for (int64_t q = 0; q < k; q++) acc += partial[(c + q) * 64 + lane];
         const uint64_t nw_mask = __ballot(acc > 0.0) & uv;
         if ((nw_mask >> lane) & 1ull) sigma[v * 64 + lane] = acc;
-        if (lane == 0) {
-            next[v] = nw_mask;
-            if (nw_mask) {
-                unvis[v] = uv & ~nw_mask;
-                *any_new = 1u;   // a flag: a plain store suffices (atomics on one address serialise)
-            }
-        }
+        if (lane == 0 && nw_mask) next[v] = nw_mask;
     }
 }
 
@@ -308,17 +450,21 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
 {
     const lagr_matrix A = G->A;
     const int64_t n = A->nrows;
+    const size_t n1 = (size_t)(n > 0 ? n : 1);
     const int groups = 64 >> gshift;
-    double *sigma = (double *)ws_get(ctx, WS_BC_SIGMA, sizeof(double) * 64 * (size_t)(n > 0 ? n : 1));
-    double *Wv = (double *)ws_get(ctx, WS_BC_W, sizeof(double) * 64 * (size_t)(n > 0 ? n : 1));
-    uint64_t *unvis = (uint64_t *)ws_get(ctx, WS_BC_UNVIS, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    double *sigma = (double *)ws_get(ctx, WS_BC_SIGMA, sizeof(double) * 64 * n1);
+    double *Wv = (double *)ws_get(ctx, WS_BC_W, sizeof(double) * 64 * n1);
+    uint64_t *unvis = (uint64_t *)ws_get(ctx, WS_BC_UNVIS, sizeof(uint64_t) * n1);
+    int32_t *acts = (int32_t *)ws_get(ctx, WS_BC_ACT, sizeof(int32_t) * 2 * n1);
+    unsigned long long *cnt = (unsigned long long *)ws_get(ctx, WS_BC_CNT, 64);
     int64_t *dsrc = (int64_t *)ws_get(ctx, WS_BFS_D, sizeof(int64_t) * 64 + 64);
-    if (!sigma || !Wv || !unvis || !dsrc) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc workspace");
-    unsigned *flag = (unsigned *)(dsrc + 64);
+    if (!sigma || !Wv || !unvis || !acts || !cnt || !dsrc) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc workspace");
     int rc = LAGR_SUCCESS;
-    // lane masks of depth d live in context-owned buffers reused across
-    // calls, so the steady state allocates nothing per level
-    const size_t lv_bytes = sizeof(uint64_t) * (size_t)(n > 0 ? n : 1);
+    // level d's lane masks (8 bytes per vertex) and vertex list (4 bytes per
+    // vertex) share one context-owned buffer, reused across calls, so the
+    // steady state allocates nothing per level
+    const size_t mask_bytes = sizeof(uint64_t) * n1;
+    const size_t lv_bytes = mask_bytes + sizeof(int32_t) * n1;
     if (ctx->lv_bytes < lv_bytes) {
         (void)hipStreamSynchronize(ctx->stream);
         for (void *p : ctx->lvpool) dev_free(p, ctx->lv_bytes);
@@ -335,6 +481,7 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
         return (uint64_t *)pool[d];
     };
     auto levels = [&](size_t d) { return (uint64_t *)pool[d]; };
+    auto lists = [&](size_t d) { return (int32_t *)((char *)pool[d] + mask_bytes); };
     auto cleanup = [&]() { (void)hipStreamSynchronize(ctx->stream); };
 #define BC_TRY(expr)       \
     do {                   \
@@ -351,7 +498,6 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
     } while (0)
 
     BC_TRY(fill_i64(ctx, (int64_t *)cent, n * groups, 0, msg));   // 0.0 has all-zero bits
-    const unsigned gblocks = grid_for(n * 64, 256, 16384);
     RowChunks ch;
     BC_TRY(graph_chunks(G, ctx, &ch, msg));
     double *partial = nullptr;
@@ -361,6 +507,24 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
         if (!partial) BC_TRY(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc chunk partials"));
         cblocks = grid_for(ch.n * 64, 256, 16384);
     }
+    const unsigned compact_blocks = (unsigned)(n > 0 ? (ctx->num_cus < n ? ctx->num_cus : n) : 1);
+    int32_t *act_cur = acts, *act_next = acts + n1;
+    // compaction after a level: returns frontier size / degree sum, active
+    // size / degree sum
+    unsigned long long h[4];
+    auto compact = [&](const uint64_t *next, int32_t *flist) -> int {
+        TRY(fill_i64(ctx, (int64_t *)cnt, 4, 0, msg));
+        if (n > 0) {
+            hipLaunchKernelGGL(k_bc_compact, dim3(compact_blocks), dim3(256), 0, ctx->stream, A->rowptr, n, next,
+                               unvis, flist, act_next, cnt);
+            LAUNCH_CHECK();
+        }
+        TRY(read_back(ctx, h, cnt, sizeof(h), msg));
+        std::swap(act_cur, act_next);
+        return LAGR_SUCCESS;
+    };
+    auto wgrid = [](int64_t items) { return grid_for(items * 64, 256, 16384); };
+    std::vector<int64_t> nlev;
     for (int b = 0; b < nbatches; b++) {
         const int64_t *src = lane_src + 64 * b;
         uint64_t lanes = 0;
@@ -368,49 +532,67 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
             if (src[k] >= 0) lanes |= 1ull << k;
         if (!lanes) continue;
         uint64_t *m0 = level_buf(0);
-        if (!m0) BC_TRY(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc level masks"));
+        if (!m0) BC_TRY(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc level buffers"));
         if (hipMemcpyAsync(dsrc, src, sizeof(int64_t) * 64, hipMemcpyHostToDevice, ctx->stream) !=
             hipSuccess)
             BC_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bc sources copy"));
+        // push adds into sigma, so every unreached (vertex, lane) starts at 0
+        BC_TRY(fill_i64(ctx, (int64_t *)sigma, n * 64, 0, msg));
         hipLaunchKernelGGL(k_bc_init, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, n,
                            lanes, unvis, m0);
         BC_LAUNCHED();
         hipLaunchKernelGGL(k_bc_sources, dim3(1), dim3(64), 0, ctx->stream, dsrc, unvis, m0, sigma);
         BC_LAUNCHED();
+        BC_TRY(compact(m0, lists(0)));
+        nlev.assign(1, (int64_t)h[0]);
         // forward sweep: depth d -> d + 1 until no lane advances
         size_t depth = 0;
         while (true) {
+            const int64_t nf = (int64_t)h[0], ef = (int64_t)h[1], na = (int64_t)h[2], ea = (int64_t)h[3];
             uint64_t *next = level_buf(depth + 1);
-            if (!next) BC_TRY(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc level masks"));
-            BC_TRY(fill_u32(ctx, flag, 1, 0u, msg));
-            TIMED(ctx, "bc_forward",
-                  hipLaunchKernelGGL(k_bc_forward, dim3(gblocks), dim3(256), 0, ctx->stream,
-                                     A->rowptr, A->colidx, n, levels(depth), next, unvis, sigma,
-                                     flag));
-            BC_LAUNCHED();
-            if (ch.n > 0) {
-                TIMED(ctx, "bc_forward_chunks",
-                      hipLaunchKernelGGL(k_bc_forward_chunks, dim3(cblocks), dim3(256), 0,
-                                         ctx->stream, A->colidx, ch, levels(depth), unvis, sigma,
-                                         partial));
+            if (!next) BC_TRY(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc level buffers"));
+            BC_TRY(fill_i64(ctx, (int64_t *)next, n, 0, msg));
+            const bool push = ef * BC_PUSH_RATIO < ea;
+            if (push) {
+                TIMED(ctx, "bc_forward",
+                      hipLaunchKernelGGL(k_bc_push, dim3(wgrid(nf)), dim3(256), 0, ctx->stream, A->rowptr,
+                                         A->colidx, lists(depth), nf, levels(depth), next, unvis, sigma));
                 BC_LAUNCHED();
-                hipLaunchKernelGGL(k_bc_forward_combine, dim3(cblocks), dim3(256), 0, ctx->stream,
-                                   A->rowptr, ch, partial, next, unvis, sigma, flag);
+                if (ch.n > 0) {
+                    TIMED(ctx, "bc_forward_chunks",
+                          hipLaunchKernelGGL(k_bc_push_chunks, dim3(cblocks), dim3(256), 0, ctx->stream,
+                                             A->colidx, ch, levels(depth), next, unvis, sigma));
+                    BC_LAUNCHED();
+                }
+            } else if (na > 0) {
+                TIMED(ctx, "bc_forward",
+                      hipLaunchKernelGGL(k_bc_pull, dim3(wgrid(na)), dim3(256), 0, ctx->stream, A->rowptr,
+                                         A->colidx, act_cur, na, levels(depth), next, unvis, sigma));
                 BC_LAUNCHED();
+                if (ch.n > 0) {
+                    TIMED(ctx, "bc_forward_chunks",
+                          hipLaunchKernelGGL(k_bc_forward_chunks, dim3(cblocks), dim3(256), 0, ctx->stream,
+                                             A->colidx, ch, levels(depth), unvis, sigma, partial));
+                    BC_LAUNCHED();
+                    hipLaunchKernelGGL(k_bc_forward_combine, dim3(cblocks), dim3(256), 0, ctx->stream,
+                                       A->rowptr, ch, partial, next, unvis, sigma);
+                    BC_LAUNCHED();
+                }
             }
-            unsigned h = 0;
-            BC_TRY(read_back(ctx, &h, flag, sizeof(h), msg));
-            if (!h) break;
+            BC_TRY(compact(next, lists(depth + 1)));
+            if (h[0] == 0) break;
             depth++;
+            nlev.push_back((int64_t)h[0]);
         }
         // backward sweep: targets at depth i-1 gather from depth i
         for (size_t i = depth + 1; i >= 2; i--) {
             const int has_deeper = i <= depth ? 1 : 0;
             const uint64_t *at_i = has_deeper ? levels(i) : levels(i - 1);
+            const int64_t nt = nlev[i - 1];
             TIMED(ctx, "bc_backward",
-                  hipLaunchKernelGGL(k_bc_backward, dim3(gblocks), dim3(256), 0, ctx->stream,
-                                     A->rowptr, A->colidx, n, at_i, levels(i - 1), has_deeper,
-                                     gshift, sigma, Wv, cent));
+                  hipLaunchKernelGGL(k_bc_backward, dim3(wgrid(nt)), dim3(256), 0, ctx->stream, A->rowptr,
+                                     A->colidx, lists(i - 1), nt, at_i, levels(i - 1), has_deeper, gshift,
+                                     sigma, Wv, cent));
             BC_LAUNCHED();
             if (ch.n > 0) {
                 if (has_deeper) {

@@ -76,6 +76,8 @@ enum WsSlot {
     WS_BC_W,
     WS_BC_MASKS,
     WS_BC_UNVIS,
+    WS_BC_ACT,        // BC active-vertex lists (two)
+    WS_BC_CNT,        // BC per-level counters
     WS_GEN_A,         // generic operations
     WS_GEN_B,
     WS_GEN_C,
@@ -105,7 +107,7 @@ struct lagr_ctx_s {
     size_t ws_bytes[WS_NSLOTS] = {};
     void *pinned = nullptr;          // 4 KiB pinned host staging for scalars
     int num_cus = 256;
-    std::vector<void *> lvpool;      // per-level lane-mask buffers (BC)
+    std::vector<void *> lvpool;      // per-level lane masks + vertex lists (BC)
     size_t lv_bytes = 0;
 };
 
