@@ -43,8 +43,10 @@ def parse():
     p.add_argument("--batch-graphs", type=int, default=0,
                    help="graphs in the many-graph leg (default: the full 2,000)")
     p.add_argument("--no-serve", action="store_true")
-    p.add_argument("--serve-queries", type=int, default=2000,
-                   help="length of the served Poisson stream (5,000 queries/s)")
+    p.add_argument("--serve-queries", type=int, default=10000,
+                   help="length of the measured Poisson stream (5,000 queries/s)")
+    p.add_argument("--serve-warmup", type=int, default=2000,
+                   help="queries of the stream replayed first, unmeasured")
     p.add_argument("--serve-workers", type=int, default=4)
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="first run a plain elementwise copy of this many MiB (calibrates HBM "
@@ -129,23 +131,27 @@ def serve_leg(args, L, ctx, dev, graphgen, np, torch):
         return r
 
     S = L.Server(ctx, graphs, workers=args.serve_workers, budget_bytes=scfg["budget_bytes"])
-    runs = []
-    for rep in range(2):             # the first replay sizes every worker's workspace
+    # a warm-up replay of the stream's first queries sizes every worker's
+    # workspace; the measured replay is the whole stream
+    warm = queries[:min(args.serve_warmup, count)]
+    stats0 = None
+    for rep, qs in enumerate((warm, queries)):
         t_start = S.clock() + 0.25
-        tickets = [S.submit(L.make_query(k, g, s, t_start + a)) for k, g, s, a in queries]
+        tickets = [S.submit(L.make_query(k, g, s, t_start + a)) for k, g, s, a in qs]
         assert S.wait(tickets[-1] + 1, 600.0), "server did not finish the stream"
-        res = {r.ticket: r for r in S.poll(count + 16)}
+        res = {r.ticket: r for r in S.poll(len(qs) + 16)}
         rs = [res[t] for t in tickets]
         assert all(r.status == 0 for r in rs), "a served query failed"
-        runs.append((rs, t_start))
-        log(f"serving: replay {rep} done")
+        if rep == 0:
+            stats0 = S.stats()
+        log(f"serving: {'warm-up' if rep == 0 else 'measured'} replay of {len(qs)} queries done")
     stats = S.stats()
     S.free()
-    rs, t_start = runs[1]
     served = summarise([r.done - r.arrival for r in rs], [r.done for r in rs], t_start,
                        [r.kind for r in rs])
     served.update({"workers": args.serve_workers,
-                   "mean_batch": {name: round(stats["queries"][k] / max(1, stats["batches"][k]), 2)
+                   "mean_batch": {name: round((stats["queries"][k] - stats0["queries"][k]) /
+                                              max(1, stats["batches"][k] - stats0["batches"][k]), 2)
                                   for k, name in ((0, "tc"), (1, "bfs"), (2, "bc"))},
                    "peak_admitted_bytes": stats["peak_bytes"]})
 
@@ -179,7 +185,7 @@ def serve_leg(args, L, ctx, dev, graphgen, np, torch):
     for r in rs:
         if r.kind == 0 and r.graph in tc_plain:
             assert r.triangles == tc_plain[r.graph], "served and plain triangle counts differ"
-    return {"workload": scfg["name"], "queries": count, "rate_qps": scfg["rate"],
+    return {"workload": scfg["name"], "queries": count, "warmup_queries": len(warm), "rate_qps": scfg["rate"],
             "arrival_window_s": round(window, 3), "mix_tc_bfs_bc": list(scfg["mix"]),
             "resident_vertices": int(sum(sizes)), "budget_bytes": scfg["budget_bytes"],
             "served": served, "plain_fifo": plain,
@@ -296,7 +302,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    kt = {k: ctx.kernel_time(k) for k in ("tc_split", "bfs_push", "bfs_pull")}
+    kt = {k: ctx.kernel_time(k) for k in ("tc_split",)}
     ctx.timing(False)
     assert len(set(tc_counts)) == 1, "triangle count changed between steps"
 
@@ -352,9 +358,7 @@ def main():
                "ms_prepared_median": round(float(np.median(prep)), 4)},
         "bfs": {"gteps_hmean": round(gteps_hmean, 4), "gteps_aggregate": round(gteps_aggr, 4),
                 "ms_median": round(float(np.median(bfs_med_per_src)), 4),
-                "sources_outside_giant_component": n_small_component,
-                "push_ms_per_step": round(kt["bfs_push"][0] / args.steps, 4),
-                "pull_ms_per_step": round(kt["bfs_pull"][0] / args.steps, 4)},
+                "sources_outside_giant_component": n_small_component},
         "roofline": roofline,
     }
 

@@ -2,164 +2,193 @@
 //
 // One level is q<!s(p), r> = q any.secondi A, fused with p<s(q)> = q (the
 // vxm + assign fusion Section VI-B describes for GAP's bfs.cc): the kernel
-// that discovers v writes its parent, its level, the next frontier list
-// and the next frontier bitmap in the same pass.
-//   push: a wavefront per frontier vertex u scans N(u) with coalesced loads;
-//         a vertex is claimed by a 32-bit CAS on its level.  The parent is
-//         the smallest frontier neighbour (atomicMin on the unsigned
-//         parent, whose "absent" value -1 is the largest), or, with
-//         LAGR_BFS_ANY_PARENT, the CAS winner.
+// that discovers v writes its parent, its level and its bit in the next
+// frontier bitmap in the same pass.
+//   push: a wavefront per frontier vertex u scans N(u) with coalesced loads
+//         (hub rows, longer than GRAPH_LONG_ROW, chunk by chunk);
 //   pull: one lane per unvisited vertex v scans N(v) in ascending order
-//         and stops at the first neighbour in the frontier bitmap, which is
-//         the smallest valid parent.
-//   The frontier's hub vertices (rows longer than GRAPH_LONG_ROW) are
-//   pushed chunk by chunk by separate waves, so no wave walks a whole hub.
-// Direction (Beamer, Asanovic and Patterson, SC 2012, the heuristic the
-// paper cites): pull when the frontier's edges exceed the unexplored edges
-// / ALPHA, back to push when the frontier has fewer than n / BETA vertices.
+//         and stops at the first neighbour in the frontier bitmap.
+// A compaction pass then lists the next frontier, counts it and its degree
+// sum and adds it to the visited set.  The level loop runs on the device:
+// a one-thread kernel folds the counters into the level state and picks
+// the direction, and every kernel of a level returns at once when the
+// search is done or the other direction was picked.  Two levels (the two
+// buffer parities) are captured once into a hipGraph per context and
+// replayed; the host looks at the done flag only every few levels.
 #include "internal.h"
 
 namespace {
 
-__device__ __forceinline__ int64_t bcast64(int64_t x, int src)
-{
-    const int lo = __shfl((int)(x & 0xffffffff), src, 64);
-    const int hi = __shfl((int)(x >> 32), src, 64);
-    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-
 constexpr int BFS_ALPHA = 14;
 constexpr int BFS_BETA = 24;
-
-struct BfsCounters {
-    unsigned long long nnext;   // vertices discovered this level
-    unsigned long long enext;   // sum of their degrees
-};
 
 __device__ __forceinline__ bool bit_test(const uint32_t *bm, int64_t v)
 {
     return (bm[v >> 5] >> (v & 31)) & 1u;
 }
 
-// `visited` holds the vertices of earlier levels only; it absorbs the
-// level's discoveries after the level, so every frontier neighbour of a
-// vertex found in this level still reaches the parent update.
-// The level kernels only write levels, parents and the next frontier's
-// bitmap.  k_bfs_compact then turns the bitmap into the next frontier list
-// (ascending within each workgroup's range), counts it and its degree sum,
-// and adds it to the visited set: one global atomic per workgroup, since
-// atomics on one address from every wavefront serialise.
+}  // namespace
 
-__global__ __launch_bounds__(256) void k_bfs_init(int64_t src, int32_t *level, int64_t *parent,
-                                                  int32_t *list, uint32_t *visited, uint32_t *bm)
+// Everything a level needs, in device memory: the kernels of a level take
+// only this struct's address and the buffer parity, so one captured
+// hipGraph of two levels serves every call (the host refreshes the
+// struct before each search).  Buffers [par] hold the current frontier,
+// [par ^ 1] the next one.
+struct BfsDev {
+    const int64_t *rp;
+    const int32_t *ci;
+    int64_t n, W;
+    int32_t *level;
+    unsigned long long *parent;
+    uint32_t *visited;
+    uint32_t *bm[2];
+    int32_t *list[2];
+    RowChunks ch;
+    int32_t any_parent, push_only;
+    // level state: lev, direction, termination, frontier size / degree sum,
+    // unexplored degree sum, and the compaction counters of the last level
+    int32_t lev, pull, done, pad_;
+    int64_t nq, mf, mu;
+    unsigned long long nnext, enext;
+};
+
+namespace {
+
+__global__ void k_bfs_init(BfsDev *d, int64_t src)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        level[src] = 0;
-        parent[src] = src;
-        list[0] = (int32_t)src;
-        visited[src >> 5] |= 1u << (src & 31);
-        bm[src >> 5] |= 1u << (src & 31);
+        d->level[src] = 0;
+        d->parent[src] = (unsigned long long)src;
+        d->list[0][0] = (int32_t)src;
+        d->visited[src >> 5] |= 1u << (src & 31);
+        d->bm[0][src >> 5] |= 1u << (src & 31);
+        d->enext = (unsigned long long)(d->rp[src + 1] - d->rp[src]);
     }
 }
 
+// Start of a level: fold the last compaction's counters into the state,
+// stop when the frontier is empty, and pick the direction (Beamer, Asanovic
+// and Patterson, SC 2012, the heuristic the paper cites): pull when the
+// frontier's edges exceed the unexplored edges / BFS_ALPHA, back to push
+// when the frontier has fewer than n / BFS_BETA vertices.
+__global__ void k_bfs_decide(BfsDev *d)
+{
+    if (threadIdx.x != 0 || d->done) return;
+    const int64_t nq = (int64_t)d->nnext, mf = (int64_t)d->enext;
+    d->nq = nq;
+    d->mf = mf;
+    d->mu -= mf;
+    d->lev += 1;
+    if (nq == 0 || d->lev == INT32_MAX) {
+        d->done = 1;
+        return;
+    }
+    if (!d->push_only) {
+        if (!d->pull && mf > d->mu / BFS_ALPHA) d->pull = 1;
+        else if (d->pull && nq < d->n / BFS_BETA) d->pull = 0;
+    }
+    d->nnext = 0;
+    d->enext = 0;
+}
+
 // Push the neighbours rp-range [b, e) of frontier vertex u, one per lane.
-__device__ __forceinline__ void push_range(const int32_t *__restrict__ ci, int32_t u, int64_t b, int64_t e,
-                                           unsigned lane, int32_t lev, int any_parent,
-                                           int32_t *__restrict__ level, unsigned long long *__restrict__ parent,
-                                           const uint32_t *__restrict__ visited, uint32_t *__restrict__ next_bm)
+__device__ __forceinline__ void push_range(const BfsDev &d, int32_t u, int64_t b, int64_t e, unsigned lane,
+                                           int32_t lev, uint32_t *__restrict__ next_bm)
 {
     for (int64_t p = b + lane; p < e; p += 64) {
-        const int32_t v = ci[p];
-        if (bit_test(visited, v)) continue;
-        const int32_t old = atomicCAS(&level[v], -1, lev);
+        const int32_t v = d.ci[p];
+        if (bit_test(d.visited, v)) continue;
+        const int32_t old = atomicCAS(&d.level[v], -1, lev);
         if (old == -1) {
-            if (any_parent) parent[v] = (unsigned long long)u;
-            else atomicMin(&parent[v], (unsigned long long)u);
+            if (d.any_parent) d.parent[v] = (unsigned long long)u;
+            else atomicMin(&d.parent[v], (unsigned long long)u);
             atomicOr(&next_bm[v >> 5], 1u << (v & 31));
-        } else if (old == lev && !any_parent) {
-            atomicMin(&parent[v], (unsigned long long)u);
+        } else if (old == lev && !d.any_parent) {
+            atomicMin(&d.parent[v], (unsigned long long)u);
         }
     }
 }
 
-__global__ __launch_bounds__(256) void k_bfs_push(const int64_t *__restrict__ rp,
-                                                  const int32_t *__restrict__ ci,
-                                                  const int32_t *__restrict__ frontier, int64_t nq,
-                                                  int32_t lev, int any_parent,
-                                                  int32_t *__restrict__ level,
-                                                  unsigned long long *__restrict__ parent,
-                                                  const uint32_t *__restrict__ visited,
-                                                  uint32_t *__restrict__ next_bm)
+// Push: a wavefront per frontier vertex u (rows of at most GRAPH_LONG_ROW)
+// scans N(u) with coalesced loads; a vertex is claimed by a 32-bit CAS on
+// its level.  The parent is the smallest frontier neighbour (atomicMin on
+// the unsigned parent, whose "absent" value -1 is the largest), or, with
+// LAGR_BFS_ANY_PARENT, the CAS winner.
+__global__ __launch_bounds__(256) void k_bfs_push(BfsDev *dp, int par)
 {
+    const BfsDev &d = *dp;
+    if (d.done || d.pull) return;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const unsigned lane = lane_id();
-    for (int64_t f = wave; f < nq; f += nw) {
+    const int32_t lev = d.lev;
+    const int32_t *frontier = d.list[par];
+    uint32_t *next_bm = d.bm[par ^ 1];
+    for (int64_t f = wave; f < d.nq; f += nw) {
         const int32_t u = frontier[f];
-        const int64_t b = rp[u], e = rp[u + 1];
+        const int64_t b = d.rp[u], e = d.rp[u + 1];
         if (e - b > GRAPH_LONG_ROW) continue;   // k_bfs_push_chunks
-        push_range(ci, u, b, e, lane, lev, any_parent, level, parent, visited, next_bm);
+        push_range(d, u, b, e, lane, lev, next_bm);
     }
 }
 
 // The frontier's hub vertices: every chunk of a long row whose vertex is in
 // the frontier bitmap is pushed by its own wave.
-__global__ __launch_bounds__(256) void k_bfs_push_chunks(const int32_t *__restrict__ ci, RowChunks ch,
-                                                         const uint32_t *__restrict__ cur_bm,
-                                                         int32_t lev, int any_parent,
-                                                         int32_t *__restrict__ level,
-                                                         unsigned long long *__restrict__ parent,
-                                                         const uint32_t *__restrict__ visited,
-                                                         uint32_t *__restrict__ next_bm)
+__global__ __launch_bounds__(256) void k_bfs_push_chunks(BfsDev *dp, int par)
 {
+    const BfsDev &d = *dp;
+    if (d.done || d.pull) return;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const unsigned lane = lane_id();
-    for (int64_t c = wave; c < ch.n; c += nw) {
-        const int32_t u = ch.row[c];
+    const uint32_t *cur_bm = d.bm[par];
+    uint32_t *next_bm = d.bm[par ^ 1];
+    for (int64_t c = wave; c < d.ch.n; c += nw) {
+        const int32_t u = d.ch.row[c];
         if (!bit_test(cur_bm, u)) continue;
-        push_range(ci, u, ch.beg[c], ch.end[c], lane, lev, any_parent, level, parent, visited, next_bm);
+        push_range(d, u, d.ch.beg[c], d.ch.end[c], lane, d.lev, next_bm);
     }
 }
 
-// One lane per unvisited vertex: scan its neighbours in ascending order and
-// stop at the first one in the frontier bitmap, the smallest valid parent.
-// Neighbours are taken PULL_BATCH at a time (independent loads, then
-// independent bitmap probes) so a lane waits for two round trips per batch
-// rather than two per neighbour.
+// Pull: one lane per unvisited vertex scans its neighbours in ascending
+// order and stops at the first one in the frontier bitmap, the smallest
+// valid parent.  Neighbours are taken PULL_BATCH at a time (independent
+// loads, then independent bitmap probes) so a lane waits for two round
+// trips per batch rather than two per neighbour.
 constexpr int PULL_BATCH = 8;
 
-__global__ __launch_bounds__(256) void k_bfs_pull(const int64_t *__restrict__ rp,
-                                                  const int32_t *__restrict__ ci, int64_t n,
-                                                  int32_t lev, const uint32_t *__restrict__ cur_bm,
-                                                  int32_t *__restrict__ level,
-                                                  int64_t *__restrict__ parent,
-                                                  const uint32_t *__restrict__ visited,
-                                                  uint32_t *__restrict__ next_bm)
+__global__ __launch_bounds__(256) void k_bfs_pull(BfsDev *dp, int par)
 {
+    const BfsDev &d = *dp;
+    if (d.done || !d.pull) return;
+    const int64_t n = d.n;
+    const int32_t lev = d.lev;
+    const uint32_t *cur_bm = d.bm[par];
+    uint32_t *next_bm = d.bm[par ^ 1];
+    int64_t *parent = (int64_t *)d.parent;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     // every lane runs the same trip count, so the ballot sees the whole wave
     for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x; v0 < n; v0 += stride) {
         const int64_t v = v0 + threadIdx.x;
-        int32_t par = -1;
-        if (v < n && !bit_test(visited, v)) {
-            const int64_t b = rp[v], e = rp[v + 1];
-            for (int64_t p0 = b; p0 < e && par < 0; p0 += PULL_BATCH) {
+        int32_t par_v = -1;
+        if (v < n && !bit_test(d.visited, v)) {
+            const int64_t b = d.rp[v], e = d.rp[v + 1];
+            for (int64_t p0 = b; p0 < e && par_v < 0; p0 += PULL_BATCH) {
                 int32_t u[PULL_BATCH];
 #pragma unroll
-                for (int t = 0; t < PULL_BATCH; t++) u[t] = p0 + t < e ? ci[p0 + t] : -1;
+                for (int t = 0; t < PULL_BATCH; t++) u[t] = p0 + t < e ? d.ci[p0 + t] : -1;
 #pragma unroll
                 for (int t = PULL_BATCH - 1; t >= 0; t--)
-                    if (u[t] >= 0 && bit_test(cur_bm, u[t])) par = u[t];
+                    if (u[t] >= 0 && bit_test(cur_bm, u[t])) par_v = u[t];
             }
         }
-        if (par >= 0) {
-            parent[v] = par;
-            level[v] = lev;
+        if (par_v >= 0) {
+            parent[v] = par_v;
+            d.level[v] = lev;
         }
         // the wave's 64 vertices are 64-aligned: they own two bitmap words,
         // which no other wave writes in this kernel
-        const uint64_t m = __ballot(par >= 0);
+        const uint64_t m = __ballot(par_v >= 0);
         const unsigned lane = lane_id();
         const int64_t w0 = (v - lane) >> 5;
         if (lane == 0 && (uint32_t)m) next_bm[w0] = (uint32_t)m;
@@ -167,26 +196,29 @@ __global__ __launch_bounds__(256) void k_bfs_pull(const int64_t *__restrict__ rp
     }
 }
 
-// Next frontier from its bitmap: a thread per 32-bit word.  Each workgroup
-// scans its words' popcounts, reserves its range of the list with one
-// atomic, writes its vertices in ascending order, adds its degree sum with
-// one more atomic and ORs its words into the visited set.
-__global__ __launch_bounds__(256) void k_bfs_compact(const int64_t *__restrict__ rp, int64_t n,
-                                                     const uint32_t *__restrict__ next_bm, int64_t W,
-                                                     uint32_t *__restrict__ visited,
-                                                     int32_t *__restrict__ next_list,
-                                                     BfsCounters *__restrict__ cnt)
+// End of a level: the next frontier from its bitmap, a thread per 32-bit
+// word.  Each workgroup scans its words' popcounts, reserves its range of
+// the list with one atomic (atomics on one address from every wavefront
+// would serialise), writes its vertices in ascending order, adds its
+// degree sum with one more atomic, ORs its words into the visited set and
+// clears the words of the consumed frontier bitmap.
+__global__ __launch_bounds__(256) void k_bfs_compact(BfsDev *dp, int par)
 {
+    const BfsDev &d = *dp;
+    if (d.done) return;
     __shared__ unsigned scan[256];
     __shared__ unsigned long long base_s, deg_s;
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t x = w < W ? next_bm[w] : 0u;
-    if (x) visited[w] |= x;
+    const uint32_t *next_bm = d.bm[par ^ 1];
+    int32_t *next_list = d.list[par ^ 1];
+    const uint32_t x = w < d.W ? next_bm[w] : 0u;
+    if (w < d.W) d.bm[par][w] = 0u;
+    if (x) d.visited[w] |= x;
     const unsigned c = (unsigned)__popc(x);
     unsigned long long deg = 0;
     for (uint32_t y = x; y; y &= y - 1) {
         const int64_t v = w * 32 + __ffs(y) - 1;
-        deg += (unsigned long long)(rp[v + 1] - rp[v]);
+        deg += (unsigned long long)(d.rp[v + 1] - d.rp[v]);
     }
     scan[threadIdx.x] = c;
     if (threadIdx.x == 0) deg_s = 0;
@@ -199,9 +231,9 @@ __global__ __launch_bounds__(256) void k_bfs_compact(const int64_t *__restrict__
     }
     for (int o = 32; o > 0; o >>= 1) deg += __shfl_xor(deg, o, 64);
     if (lane_id() == 0 && deg) atomicAdd(&deg_s, deg);
-    if (threadIdx.x == 255) base_s = scan[255] ? atomicAdd(&cnt->nnext, (unsigned long long)scan[255]) : 0;
+    if (threadIdx.x == 255) base_s = scan[255] ? atomicAdd(&dp->nnext, (unsigned long long)scan[255]) : 0;
     __syncthreads();
-    if (threadIdx.x == 0 && deg_s) atomicAdd(&cnt->enext, deg_s);
+    if (threadIdx.x == 0 && deg_s) atomicAdd(&dp->enext, deg_s);
     unsigned long long pos = base_s + scan[threadIdx.x] - c;
     for (uint32_t y = x; y; y &= y - 1) next_list[pos++] = (int32_t)(w * 32 + __ffs(y) - 1);
 }
@@ -213,7 +245,50 @@ __global__ void k_level_to_i64(const int32_t *__restrict__ in, int64_t *__restri
         out[v] = in[v];
 }
 
+// One level on stream s with buffer parity par.
+int enqueue_level(BfsDev *d, int par, int64_t n, int64_t W, int num_cus, hipStream_t s, char *msg)
+{
+    hipLaunchKernelGGL(k_bfs_decide, dim3(1), dim3(64), 0, s, d);
+    hipLaunchKernelGGL(k_bfs_push, dim3((unsigned)(num_cus * 8)), dim3(256), 0, s, d, par);
+    hipLaunchKernelGGL(k_bfs_push_chunks, dim3((unsigned)(num_cus * 2)), dim3(256), 0, s, d, par);
+    hipLaunchKernelGGL(k_bfs_pull, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, d, par);
+    hipLaunchKernelGGL(k_bfs_compact, dim3(grid_for(W, 256, 1 << 30)), dim3(256), 0, s, d, par);
+    LAUNCH_CHECK();
+    return LAGR_SUCCESS;
+}
+
 }  // namespace
+
+// The context's captured two-level graph for graphs of n vertices.
+static int bfs_graph(lagr_ctx ctx, BfsDev *d, int64_t n, int64_t W, hipGraphExec_t *exec, char *msg)
+{
+    if (ctx->bfs_exec && ctx->bfs_key == n && ctx->bfs_state == (void *)d) {
+        *exec = ctx->bfs_exec;
+        return LAGR_SUCCESS;
+    }
+    if (ctx->bfs_exec) (void)hipGraphExecDestroy(ctx->bfs_exec);
+    ctx->bfs_exec = nullptr;
+    if (!ctx->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_level(d, 0, n, W, ctx->num_cus, ctx->capture_stream, msg);
+    if (rc >= 0) rc = enqueue_level(d, 1, n, W, ctx->num_cus, ctx->capture_stream, msg);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->capture_stream, &g);
+    if (rc < 0 || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc < 0 ? rc : lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs capture: %s", hipGetErrorString(e));
+    }
+    const hipError_t ei = hipGraphInstantiate(&ctx->bfs_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        ctx->bfs_exec = nullptr;
+        return lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs graph: %s", hipGetErrorString(ei));
+    }
+    ctx->bfs_key = n;
+    ctx->bfs_state = (void *)d;
+    *exec = ctx->bfs_exec;
+    return LAGR_SUCCESS;
+}
 
 static int new_full_i64(lagr_vector *out, int64_t n, int64_t **values, char *msg)
 {
@@ -251,16 +326,16 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
     int32_t *lev32 = (int32_t *)ws_get(ctx, WS_BFS_A, sizeof(int32_t) * n);
     int32_t *lists = (int32_t *)ws_get(ctx, WS_BFS_B, sizeof(int32_t) * 2 * n);
     uint32_t *bms = (uint32_t *)ws_get(ctx, WS_BFS_C, sizeof(uint32_t) * 3 * W);
-    BfsCounters *cnt = (BfsCounters *)ws_get(ctx, WS_BFS_D, sizeof(BfsCounters));
+    BfsDev *d = (BfsDev *)ws_get(ctx, WS_BFS_D, sizeof(BfsDev));
     int64_t *parent_scratch = nullptr;
     if (!parent_out) parent_scratch = (int64_t *)ws_get(ctx, WS_BFS_E, sizeof(int64_t) * n);
-    if (!lev32 || !lists || !bms || !cnt || (!parent_out && !parent_scratch))
+    if (!lev32 || !lists || !bms || !d || (!parent_out && !parent_scratch))
         return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bfs workspace");
+    RowChunks ch;
+    TRY(graph_chunks(G, ctx, &ch, msg));
     lagr_vector pv = nullptr, lv = nullptr;
     int64_t *parent = parent_scratch;
     if (parent_out) TRY(new_full_i64(&pv, n, &parent, msg));
-    uint32_t *visited = bms, *bm_cur = bms + W, *bm_next = bms + 2 * W;
-    int32_t *list_cur = lists, *list_next = lists + n;
 
     int rc = LAGR_SUCCESS;
     auto cleanup = [&]() {
@@ -276,88 +351,56 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
         }                        \
     } while (0)
 
+    // the struct goes through the context's pinned staging buffer; the copy
+    // is ordered before everything below on the stream
+    BfsDev h{};
+    h.rp = A->rowptr;
+    h.ci = A->colidx;
+    h.n = n;
+    h.W = W;
+    h.level = lev32;
+    h.parent = (unsigned long long *)parent;
+    h.visited = bms;
+    h.bm[0] = bms + W;
+    h.bm[1] = bms + 2 * W;
+    h.list[0] = lists;
+    h.list[1] = lists + n;
+    h.ch = ch;
+    h.any_parent = (flags & LAGR_BFS_ANY_PARENT) ? 1 : 0;
+    h.push_only = (flags & LAGR_BFS_PUSH_ONLY) ? 1 : 0;
+    h.lev = 0;
+    h.mu = A->nvals;
+    h.nnext = 1;   // the source (k_bfs_init sets enext to its degree)
+    static_assert(sizeof(BfsDev) <= 4096, "BfsDev must fit the pinned staging buffer");
+    memcpy(ctx->pinned, &h, sizeof(h));
+    if (hipMemcpyAsync(d, ctx->pinned, sizeof(h), hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+        BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs state copy"));
     BFS_TRY(fill_u32(ctx, (uint32_t *)lev32, n, 0xFFFFFFFFu, msg));
     BFS_TRY(fill_i64(ctx, parent, n, -1, msg));
     BFS_TRY(fill_u32(ctx, bms, 3 * W, 0u, msg));
-    hipLaunchKernelGGL(k_bfs_init, dim3(1), dim3(64), 0, ctx->stream, source, lev32, parent,
-                       list_cur, visited, bm_cur);
-    if (hipGetLastError() != hipSuccess) {
-        cleanup();
-        return lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs init launch");
-    }
-    const int64_t *rp = A->rowptr;
-    const int32_t *ci = A->colidx;
-    RowChunks ch;
-    {
-        int rc2 = graph_chunks(G, ctx, &ch, msg);
-        if (rc2 < 0) {
-            cleanup();
-            return rc2;
-        }
-    }
-    // host copies of the per-level counters drive the direction choice
-    int64_t hdeg_src = 0;
-    {
-        int64_t two[2];
-        BFS_TRY(read_back(ctx, two, rp + source, 2 * sizeof(int64_t), msg));
-        hdeg_src = two[1] - two[0];
-    }
-    int64_t nq = 1, mf = hdeg_src, mu = A->nvals - hdeg_src;
-    bool pull = false;
-    const bool push_only = (flags & LAGR_BFS_PUSH_ONLY) != 0;
-    const int any_parent = (flags & LAGR_BFS_ANY_PARENT) ? 1 : 0;
-    for (int32_t lev = 1; nq > 0 && lev < INT32_MAX; lev++) {
-        if (!push_only) {
-            if (!pull && mf > mu / BFS_ALPHA) pull = true;
-            else if (pull && nq < n / BFS_BETA) pull = false;
-        }
-        BFS_TRY(fill_i64(ctx, (int64_t *)cnt, 2, 0, msg));
-        if (pull) {
-            TIMED(ctx, "bfs_pull",
-                  hipLaunchKernelGGL(k_bfs_pull, dim3(grid_for(n, 256, 8192)), dim3(256), 0,
-                                     ctx->stream, rp, ci, n, lev, bm_cur, lev32, parent, visited,
-                                     bm_next));
-        } else {
-            TIMED(ctx, "bfs_push",
-                  hipLaunchKernelGGL(k_bfs_push, dim3(grid_for(nq * 64, 256, 8192)), dim3(256), 0,
-                                     ctx->stream, rp, ci, list_cur, nq, lev, any_parent, lev32,
-                                     (unsigned long long *)parent, visited, bm_next));
-            if (ch.n > 0)
-                TIMED(ctx, "bfs_push",
-                      hipLaunchKernelGGL(k_bfs_push_chunks, dim3(grid_for(ch.n * 64, 256, 4096)),
-                                         dim3(256), 0, ctx->stream, ci, ch, bm_cur, lev, any_parent,
-                                         lev32, (unsigned long long *)parent, visited, bm_next));
-        }
-        if (hipGetLastError() != hipSuccess) {
-            cleanup();
-            return lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs level launch");
-        }
-        TIMED(ctx, "bfs_compact",
-              hipLaunchKernelGGL(k_bfs_compact, dim3(grid_for(W, 256, 1 << 30)), dim3(256), 0, ctx->stream,
-                                 rp, n, bm_next, W, visited, list_next, cnt));
-        BfsCounters h;
-        BFS_TRY(read_back(ctx, &h, cnt, sizeof(h), msg));
-        nq = (int64_t)h.nnext;
-        mf = (int64_t)h.enext;
-        mu -= mf;
-        // the consumed frontier bitmap becomes the next level's output
-        BFS_TRY(fill_u32(ctx, bm_cur, W, 0u, msg));
-        uint32_t *tb = bm_cur;
-        bm_cur = bm_next;
-        bm_next = tb;
-        int32_t *tl = list_cur;
-        list_cur = list_next;
-        list_next = tl;
+    hipLaunchKernelGGL(k_bfs_init, dim3(1), dim3(64), 0, ctx->stream, d, source);
+    if (hipGetLastError() != hipSuccess) BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs init launch"));
+    hipGraphExec_t exec = nullptr;
+    BFS_TRY(bfs_graph(ctx, d, n, W, &exec, msg));
+    // replay two levels at a time; look at the done flag after 6 levels and
+    // then after every 2 (each look is a host round trip)
+    int64_t levels = 0;
+    for (int64_t replays = 3;; replays = 1) {
+        for (int64_t r = 0; r < replays; r++)
+            if (hipGraphLaunch(exec, ctx->stream) != hipSuccess)
+                BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs graph launch"));
+        levels += 2 * replays;
+        int32_t done = 0;
+        BFS_TRY(read_back(ctx, &done, &d->done, sizeof(done), msg));
+        if (done) break;
+        if (levels > n + 2) BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs did not terminate"));
     }
     if (level_out) {
         int64_t *lvals = nullptr;
         BFS_TRY(new_full_i64(&lv, n, &lvals, msg));
         hipLaunchKernelGGL(k_level_to_i64, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream,
                            lev32, lvals, n);
-        if (hipGetLastError() != hipSuccess) {
-            cleanup();
-            return lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs level export");
-        }
+        if (hipGetLastError() != hipSuccess) BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs level export"));
         *level_out = lv;
         lv = nullptr;
     }

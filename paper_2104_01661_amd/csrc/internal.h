@@ -109,6 +109,12 @@ struct lagr_ctx_s {
     int num_cus = 256;
     std::vector<void *> lvpool;      // per-level lane masks + vertex lists (BC)
     size_t lv_bytes = 0;
+    // BFS: captured two-level graph (valid for bfs_key vertices and the
+    // state struct at bfs_state) and the stream it is captured on
+    hipGraphExec_t bfs_exec = nullptr;
+    int64_t bfs_key = -1;
+    void *bfs_state = nullptr;
+    hipStream_t capture_stream = nullptr;
 };
 
 // Returns a device buffer of at least `bytes` for the slot (contents are
