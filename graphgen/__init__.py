@@ -27,6 +27,7 @@ TAG_EDGES = 0
 TAG_SOURCES = 0x737263          # "src"
 TAG_PARAMS = 0x70726d           # "prm"
 TAG_QUERIES = 0x717279          # "qry"
+TAG_WEIGHTS = 0x777467          # "wtg"
 
 
 def build(force: bool = False) -> str:
@@ -59,6 +60,9 @@ def _load():
         lib.gg_sample.restype = ctypes.c_int
         lib.gg_sample.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
                                   ctypes.c_uint64, ctypes.c_void_p]
+        lib.gg_edge_weights.restype = None
+        lib.gg_edge_weights.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                        ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p]
         lib.gg_uniforms.restype = None
         lib.gg_uniforms.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
                                     ctypes.c_int64, ctypes.c_void_p]
@@ -103,6 +107,17 @@ def sample(candidates: np.ndarray, k: int, seed: int, tag: int = TAG_SOURCES) ->
 def uniforms(seed: int, tag: int, count: int, start: int = 0) -> np.ndarray:
     out = np.empty(count, dtype=np.float64)
     _load().gg_uniforms(seed, tag, start, count, out.ctypes.data)
+    return out
+
+
+def edge_weights(rowptr, colidx, seed: int, wmax: int = 255) -> np.ndarray:
+    """Symmetric seeded integer weights in [1, wmax] (as float64), one per
+    CSR entry: w(u, v) = w(v, u)."""
+    rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+    ci = np.ascontiguousarray(colidx, dtype=np.int32)
+    out = np.empty(ci.size, dtype=np.float64)
+    _load().gg_edge_weights(rp.size - 1, rp.ctypes.data, ci.ctypes.data, seed, TAG_WEIGHTS, wmax,
+                            out.ctypes.data)
     return out
 
 

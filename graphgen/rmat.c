@@ -124,3 +124,19 @@ void gg_uniforms(uint64_t seed, uint64_t tag, int64_t i0, int64_t count, double 
     const uint64_t key = gg_key(seed, tag);
     for (int64_t i = 0; i < count; i++) out[i] = gg_u01(gg_nth(key, (uint64_t)(i0 + i)));
 }
+
+/* Symmetric integer edge weights in [1, wmax] for an adjacency in CSR form:
+ * entry (u, v) gets 1 + (x mod wmax) where x is output number
+ * min(u,v) * 2^32 + max(u,v) of stream (seed, tag), so w(u,v) = w(v,u). */
+void gg_edge_weights(int64_t n, const int64_t *rp, const int32_t *ci, uint64_t seed, uint64_t tag,
+                     int64_t wmax, double *out)
+{
+    const uint64_t key = gg_key(seed, tag);
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t u = 0; u < n; u++)
+        for (int64_t p = rp[u]; p < rp[u + 1]; p++) {
+            const uint64_t v = (uint64_t)ci[p];
+            const uint64_t a = (uint64_t)u < v ? (uint64_t)u : v, b = (uint64_t)u < v ? v : (uint64_t)u;
+            out[p] = (double)(1 + gg_nth(key, (a << 32) | b) % (uint64_t)wmax);
+        }
+}

@@ -3,7 +3,9 @@
 A plain CPU statement of what the device library computes, written from the
 paper (LAGraph, arXiv 2104.01661): triangle counting (Section IV-E,
 Algorithm 6), breadth-first search (Section IV-A, Algorithms 1-2), Brandes
-betweenness centrality (Section IV-B, Algorithm 3) in ``oracle.c``, and the
+betweenness centrality (Section IV-B, Algorithm 3), and the shortest-path
+distances of delta-stepping (Section IV-D, Algorithm 5) by Dijkstra's
+algorithm in ``oracle.c``, and the
 GraphBLAS masked-product / accumulate / reduce semantics of Section III
 (Table I, Table II, "Masks") as a dense brute-force reference in
 ``semantics.py``.
@@ -59,6 +61,8 @@ def _load():
         lib.orc_bfs_min_parent.argtypes = [_I, _P, _P, _I, _P, _P]
         lib.orc_brandes.restype = ctypes.c_int
         lib.orc_brandes.argtypes = [_I, _P, _P, _I, _P, _P]
+        lib.orc_dijkstra.restype = ctypes.c_int
+        lib.orc_dijkstra.argtypes = [_I, _P, _P, _P, _I, _P]
         _lib = lib
     return _lib
 
@@ -149,4 +153,16 @@ def brandes(rowptr, colidx, sources):
         raise OverflowError("oracle: a shortest-path count reached 2^53")
     if rc != 0:
         raise MemoryError("oracle: brandes failed")
+    return out
+
+
+def dijkstra(rowptr, colidx, weights, source: int):
+    """Shortest-path distances from source (float64[n], +inf unreached);
+    weights: one non-negative float64 per CSR entry."""
+    rowptr, pr = _c(rowptr, np.int64)
+    colidx, pc = _c(colidx, np.int32)
+    weights, pw = _c(weights, np.float64)
+    out = np.empty(rowptr.size - 1, dtype=np.float64)
+    if _load().orc_dijkstra(rowptr.size - 1, pr, pc, pw, int(source), out.ctypes.data) != 0:
+        raise MemoryError("oracle: dijkstra failed")
     return out

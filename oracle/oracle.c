@@ -256,3 +256,78 @@ int orc_brandes(int64_t n, const int64_t *rp, const int32_t *ci, int64_t ns,
     free(sigma); free(delta); free(dist); free(order);
     return rc;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Single-source shortest paths (Section IV-D): the distances that the
+ * delta-stepping method of Algorithm 5 computes, here by Dijkstra's
+ * algorithm with a binary heap of (distance, vertex) pairs (stale pairs are
+ * skipped).  Weights w[p] >= 0 belong to CSR entry p.  dist = +inf for
+ * unreachable vertices.  Returns 0, or -1 if memory runs out.            */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    double d;
+    int64_t v;
+} orc_hnode;
+
+static void orc_heap_push(orc_hnode *h, int64_t *sz, double d, int64_t v)
+{
+    int64_t i = (*sz)++;
+    while (i > 0) {
+        const int64_t parent = (i - 1) / 2;
+        if (h[parent].d <= d) break;
+        h[i] = h[parent];
+        i = parent;
+    }
+    h[i].d = d;
+    h[i].v = v;
+}
+
+static orc_hnode orc_heap_pop(orc_hnode *h, int64_t *sz)
+{
+    const orc_hnode top = h[0];
+    const orc_hnode last = h[--(*sz)];
+    int64_t i = 0;
+    while (1) {
+        int64_t c = 2 * i + 1;
+        if (c >= *sz) break;
+        if (c + 1 < *sz && h[c + 1].d < h[c].d) c++;
+        if (h[c].d >= last.d) break;
+        h[i] = h[c];
+        i = c;
+    }
+    if (*sz > 0) h[i] = last;
+    return top;
+}
+
+int orc_dijkstra(int64_t n, const int64_t *rp, const int32_t *ci, const double *w, int64_t s, double *dist)
+{
+    const int64_t cap = rp[n] + 1;
+    orc_hnode *h = (orc_hnode *)malloc(sizeof(orc_hnode) * (size_t)cap);
+    char *done = (char *)calloc((size_t)n + 1, 1);
+    if (!h || !done) {
+        free(h);
+        free(done);
+        return -1;
+    }
+    for (int64_t v = 0; v < n; v++) dist[v] = 1.0 / 0.0;
+    int64_t sz = 0;
+    dist[s] = 0.0;
+    orc_heap_push(h, &sz, 0.0, s);
+    while (sz > 0) {
+        const orc_hnode x = orc_heap_pop(h, &sz);
+        if (done[x.v]) continue;
+        done[x.v] = 1;
+        for (int64_t p = rp[x.v]; p < rp[x.v + 1]; p++) {
+            const int64_t v = ci[p];
+            const double nd = x.d + w[p];
+            if (nd < dist[v]) {
+                dist[v] = nd;
+                orc_heap_push(h, &sz, nd, v);
+            }
+        }
+    }
+    free(h);
+    free(done);
+    return 0;
+}

@@ -269,3 +269,73 @@ def test_build_symmetric_sorted_unique_no_loops():
     for v in range(n):
         row = ci[rp[v]:rp[v + 1]]
         assert (np.diff(row) > 0).all() and v not in row
+
+
+# ------------------------------------------------------------- SSSP (Alg 5)
+
+def weighted(n, edges, seed=7, wmax=255):
+    import graphgen
+    rp, ci = oracle.from_edges(n, edges)
+    return rp, ci, graphgen.edge_weights(rp, ci, seed, wmax)
+
+
+def test_edge_weights_are_symmetric_integers():
+    import graphgen
+    n, s, d = graphgen.rmat_edges(9, 8, 12)
+    rp, ci = oracle.build_adjacency(n, s, d)
+    w = graphgen.edge_weights(rp, ci, 3)
+    M = sp.csr_matrix((w, ci, rp), shape=(n, n))
+    assert (M != M.T).nnz == 0
+    assert w.min() >= 1 and w.max() <= 255 and np.array_equal(w, np.round(w))
+
+
+def test_sssp_unit_weights_are_bfs_levels():
+    import graphgen
+    n, s, d = graphgen.rmat_edges(10, 16, 1)
+    rp, ci = oracle.build_adjacency(n, s, d)
+    src = int(graphgen.sources(n, s, d, 1, 1)[0])
+    dist = oracle.dijkstra(rp, ci, np.ones(ci.size), src)
+    lev = oracle.bfs(rp, ci, src)[0]
+    assert np.array_equal(np.where(lev >= 0, lev.astype(float), np.inf), dist)
+
+
+def test_sssp_path_prefix_sums_and_grid():
+    n = 40
+    rp, ci, w = weighted(*G.path(n))
+    dist = oracle.dijkstra(rp, ci, w, 0)
+    step = [w[rp[i]:rp[i + 1]][ci[rp[i]:rp[i + 1]] == i + 1][0] for i in range(n - 1)]
+    assert np.array_equal(dist, np.concatenate([[0.0], np.cumsum(step)]))
+    rp, ci = adj(G.grid(7, 9))
+    dist = oracle.dijkstra(rp, ci, np.ones(ci.size), 0)
+    assert np.array_equal(dist, np.array([i + j for i in range(7) for j in range(9)], dtype=float))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_sssp_against_scipy_and_floyd_warshall(seed):
+    rng = np.random.default_rng(seed)
+    n = 24
+    rp, ci, w = weighted(*G.random_graph(n, 0.15, rng), seed=seed)
+    M = sp.csr_matrix((w, ci, rp), shape=(n, n))
+    FW = csg.floyd_warshall(M, directed=True)
+    # textbook Floyd-Warshall by hand as well (integer weights: every sum exact)
+    D = np.full((n, n), np.inf)
+    np.fill_diagonal(D, 0.0)
+    for u in range(n):
+        for p in range(rp[u], rp[u + 1]):
+            D[u, ci[p]] = min(D[u, ci[p]], w[p])
+    for k in range(n):
+        D = np.minimum(D, D[:, k:k + 1] + D[k:k + 1, :])
+    assert np.array_equal(D, FW)
+    for s in range(n):
+        assert np.array_equal(oracle.dijkstra(rp, ci, w, s), D[s])
+
+
+def test_sssp_rmat_against_scipy_dijkstra():
+    import graphgen
+    n, s, d = graphgen.rmat_edges(11, 8, 21)
+    rp, ci = oracle.build_adjacency(n, s, d)
+    w = graphgen.edge_weights(rp, ci, 21)
+    M = sp.csr_matrix((w, ci, rp), shape=(n, n))
+    for src in graphgen.sources(n, s, d, 4, 21):
+        want = csg.dijkstra(M, directed=True, indices=int(src))
+        assert np.array_equal(oracle.dijkstra(rp, ci, w, int(src)), want)

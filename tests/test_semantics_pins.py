@@ -241,3 +241,24 @@ def test_algorithm6_through_semantics_matches_oracle():
     lrp, lci, cnt = oracle.lower_counts(*oracle.from_edges(*g))
     rows = np.repeat(np.arange(A.nrows), np.diff(lrp))
     assert C2.e == {(int(i), int(j)): int(c) for i, j, c in zip(rows, lci, cnt) if c > 0}
+
+
+def test_algorithm5_fixpoint_through_semantics_matches_dijkstra():
+    """min.plus relaxation to a fixpoint (what delta-stepping computes, bucket
+    by bucket) through the brute-force semantics equals the Dijkstra oracle."""
+    import graphgen
+    rng = np.random.default_rng(8)
+    n = 14
+    rp, ci = oracle.from_edges(n, G.random_graph(n, 0.3, rng)[1])
+    w = graphgen.edge_weights(rp, ci, 8, 20)
+    W = np.zeros((n, n))
+    for u in range(n):
+        W[u, ci[rp[u]:rp[u + 1]]] = w[rp[u]:rp[u + 1]]
+    A = mat_from_dense(W, kind="fp64")
+    t = S.Vec(n, {0: 0.0}, "fp64")
+    for _ in range(n):
+        t = S.vxm(t, None, "min", "min.plus", t, A)
+    got = np.full(n, np.inf)
+    for j, x in t.e.items():
+        got[j] = x
+    assert np.array_equal(got, oracle.dijkstra(rp, ci, w, 0))
