@@ -78,6 +78,13 @@ __device__ __forceinline__ void group_add(double delta, int gshift, unsigned lan
     if ((lane & ((1u << gshift) - 1)) == 0) centrality[v * (64 >> gshift) + (lane >> gshift)] += t;
 }
 
+__device__ __forceinline__ int64_t bcast64(int64_t x, int src)
+{
+    const int lo = __shfl((int)(x & 0xffffffff), src, 64);
+    const int hi = __shfl((int)(x >> 32), src, 64);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 __device__ __forceinline__ uint64_t shfl64(uint64_t x, int src)
 {
     const unsigned lo = __shfl((unsigned)(x & 0xffffffffu), src, 64);
@@ -437,6 +444,162 @@ __global__ __launch_bounds__(256) void k_bc_backward_combine(const int64_t *__re
     }
 }
 
+
+// ------------------------------------------------ multi-source BFS lanes
+//
+// Up to 64 breadth-first searches at once, one per lane, with the forward
+// machinery of the betweenness batches but no path counts: a vertex
+// reaches lane k at depth d + 1 when a neighbour is at depth d in lane k.
+
+// Pull over the active list (rows of at most BC_LONG neighbours): OR of the
+// neighbours' depth-d masks within the vertex's unreached lanes, stopping
+// once every unreached lane is found.
+__global__ __launch_bounds__(256) void k_ms_pull(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                 const int32_t *__restrict__ act, int64_t na,
+                                                 const uint64_t *__restrict__ cur, uint64_t *__restrict__ next,
+                                                 const uint64_t *__restrict__ unvis)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t q = wave; q < na; q += nw) {
+        const int64_t v = act[q];
+        const int64_t b = rp[v], e = rp[v + 1];
+        if (e - b > BC_LONG) continue;   // k_ms_pull_chunks
+        const uint64_t uv = unvis[v];
+        uint64_t acc = 0;
+        for (int64_t p0 = b; p0 < e && acc != uv; p0 += 64) {
+            const int64_t p = p0 + lane;
+            uint64_t m = p < e ? (cur[ci[p]] & uv) : 0;
+            for (int o = 32; o > 0; o >>= 1) m |= shfl64(m, (int)(lane ^ o));
+            acc |= m;
+        }
+        if (lane == 0 && acc) next[v] = acc;
+    }
+}
+
+// Pull for hub vertices with unreached lanes, one wave per chunk (OR-ed in).
+__global__ __launch_bounds__(256) void k_ms_pull_chunks(const int32_t *__restrict__ ci, RowChunks ch,
+                                                        const uint64_t *__restrict__ cur,
+                                                        uint64_t *__restrict__ next,
+                                                        const uint64_t *__restrict__ unvis)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t c = wave; c < ch.n; c += nw) {
+        const int64_t v = ch.row[c];
+        const uint64_t uv = unvis[v];
+        if (uv == 0) continue;
+        uint64_t acc = 0;
+        for (int64_t p0 = ch.beg[c]; p0 < ch.end[c] && acc != uv; p0 += 64) {
+            const int64_t p = p0 + lane;
+            uint64_t m = p < ch.end[c] ? (cur[ci[p]] & uv) : 0;
+            for (int o = 32; o > 0; o >>= 1) m |= shfl64(m, (int)(lane ^ o));
+            acc |= m;
+        }
+        if (lane == 0 && acc) atomicOr((unsigned long long *)&next[v], (unsigned long long)acc);
+    }
+}
+
+// Push from the frontier over the neighbour range [b, e) of u (lanes fm).
+__device__ __forceinline__ void ms_push_range(const int32_t *__restrict__ ci, int64_t b, int64_t e, uint64_t fm,
+                                              const uint64_t *__restrict__ unvis, uint64_t *__restrict__ next,
+                                              unsigned lane)
+{
+    for (int64_t p = b + lane; p < e; p += 64) {
+        const int32_t v = ci[p];
+        const uint64_t m = unvis[v] & fm;
+        if (m) atomicOr((unsigned long long *)&next[v], (unsigned long long)m);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ms_push(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                 const int32_t *__restrict__ front, int64_t nf,
+                                                 const uint64_t *__restrict__ cur, uint64_t *__restrict__ next,
+                                                 const uint64_t *__restrict__ unvis)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t q = wave; q < nf; q += nw) {
+        const int64_t u = front[q];
+        const int64_t b = rp[u], e = rp[u + 1];
+        if (e - b > BC_LONG) continue;   // k_ms_push_chunks
+        ms_push_range(ci, b, e, cur[u], unvis, next, lane);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ms_push_chunks(const int32_t *__restrict__ ci, RowChunks ch,
+                                                        const uint64_t *__restrict__ cur,
+                                                        uint64_t *__restrict__ next,
+                                                        const uint64_t *__restrict__ unvis)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t c = wave; c < ch.n; c += nw) {
+        const uint64_t fm = cur[ch.row[c]];
+        if (fm) ms_push_range(ci, ch.beg[c], ch.end[c], fm, unvis, next, lane);
+    }
+}
+
+// Per lane k, over the vertices reached at depth d (the frontier list and
+// their masks): stats[k] += count, stats[64 + k] += count * d, stats[128 +
+// k] = max depth; with lev, lev[v * 64 + k] = d.  64 list entries per
+// wave step; one set of atomics per workgroup.
+__global__ __launch_bounds__(256) void k_ms_stats(const int32_t *__restrict__ front, int64_t nf,
+                                                  const uint64_t *__restrict__ mask, int64_t d,
+                                                  uint16_t *__restrict__ lev, unsigned long long *__restrict__ stats)
+{
+    __shared__ unsigned long long cnt[64];
+    if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const unsigned lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    unsigned long long mine = 0;
+    for (int64_t q0 = wave * 64; q0 < nf; q0 += nw * 64) {
+        const int64_t q = q0 + lane;
+        const int64_t v = q < nf ? front[q] : -1;
+        const uint64_t x = v >= 0 ? mask[v] : 0;
+        for (int k = 0; k < 64; k++) {
+            const uint64_t bal = __ballot((x >> k) & 1ull);
+            if ((int)lane == k) mine += (unsigned long long)__popcll(bal);
+        }
+        if (lev)
+            for (int t = 0; t < 64; t++) {
+                const int64_t vt = bcast64(v, t);
+                if (vt < 0) break;
+                const uint64_t xt = shfl64(x, t);
+                if ((xt >> lane) & 1ull) lev[vt * 64 + lane] = (uint16_t)d;
+            }
+    }
+    if (mine) atomicAdd(&cnt[lane], mine);
+    __syncthreads();
+    if (threadIdx.x < 64 && cnt[threadIdx.x]) {
+        const unsigned long long c = cnt[threadIdx.x];
+        atomicAdd(&stats[threadIdx.x], c);
+        atomicAdd(&stats[64 + threadIdx.x], c * (unsigned long long)d);
+        atomicMax(&stats[128 + threadIdx.x], (unsigned long long)d);
+    }
+}
+
+__global__ void k_ms_sources(const int64_t *__restrict__ src, uint64_t *__restrict__ unvis,
+                             uint64_t *__restrict__ mask0, unsigned long long *__restrict__ stats)
+{
+    const int k = threadIdx.x;
+    if (k < 64) {
+        stats[k] = 0;
+        stats[64 + k] = 0;
+        stats[128 + k] = 0;
+        if (src[k] >= 0) {
+            atomicAnd((unsigned long long *)&unvis[src[k]], ~(1ull << k));
+            atomicOr((unsigned long long *)&mask0[src[k]], 1ull << k);
+        }
+    }
+}
+
 }  // namespace
 
 
@@ -612,6 +775,107 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
     cleanup();
 #undef BC_TRY
 #undef BC_LAUNCHED
+    return LAGR_SUCCESS;
+}
+
+
+// Multi-source BFS over the lanes of lane_src (HOST, 64, -1 idle): per lane
+// the number of reached vertices (the source included), the sum of their
+// levels and the largest level into stats[3][64] (host); with lev
+// (n x 64 uint16), every reached (vertex, lane)'s level, 0xFFFF elsewhere.
+int msbfs_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, uint16_t *lev, int64_t *stats,
+                  char *msg)
+{
+    const lagr_matrix A = G->A;
+    const int64_t n = A->nrows;
+    const size_t n1 = (size_t)(n > 0 ? n : 1);
+    uint64_t *unvis = (uint64_t *)ws_get(ctx, WS_BC_UNVIS, sizeof(uint64_t) * n1);
+    int32_t *acts = (int32_t *)ws_get(ctx, WS_BC_ACT, sizeof(int32_t) * 2 * n1);
+    unsigned long long *cnt = (unsigned long long *)ws_get(ctx, WS_BC_CNT, 64);
+    int64_t *dsrc = (int64_t *)ws_get(ctx, WS_BFS_D, sizeof(int64_t) * 64 + 64);
+    unsigned long long *dstats = (unsigned long long *)ws_get(ctx, WS_BFS_E, sizeof(int64_t) * 3 * 64);
+    if (!unvis || !acts || !cnt || !dsrc || !dstats) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "msbfs workspace");
+    // two (mask, list) buffers of the context's level pool, used in turn
+    const size_t mask_bytes = sizeof(uint64_t) * n1;
+    const size_t lv_bytes = mask_bytes + sizeof(int32_t) * n1;
+    if (ctx->lv_bytes < lv_bytes) {
+        TRY(hipStreamSynchronize(ctx->stream) == hipSuccess ? LAGR_SUCCESS
+                                                            : lagr_fail(msg, LAGR_DEVICE_ERROR, "sync"));
+        for (void *p : ctx->lvpool) dev_free(p, ctx->lv_bytes);
+        ctx->lvpool.clear();
+        ctx->lv_bytes = lv_bytes;
+    }
+    while (ctx->lvpool.size() < 2) {
+        void *p = dev_alloc(ctx->lv_bytes);
+        if (!p) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "msbfs level buffers");
+        ctx->lvpool.push_back(p);
+    }
+    auto mask_of = [&](int b) { return (uint64_t *)ctx->lvpool[b]; };
+    auto list_of = [&](int b) { return (int32_t *)((char *)ctx->lvpool[b] + mask_bytes); };
+    uint64_t lanes = 0;
+    for (int k = 0; k < 64; k++)
+        if (lane_src[k] >= 0) lanes |= 1ull << k;
+    RowChunks ch;
+    TRY(graph_chunks(G, ctx, &ch, msg));
+    const unsigned cblocks = ch.n > 0 ? grid_for(ch.n * 64, 256, 16384) : 1;
+    const unsigned compact_blocks = (unsigned)(n > 0 ? (ctx->num_cus < n ? ctx->num_cus : n) : 1);
+    int32_t *act_cur = acts, *act_next = acts + n1;
+    unsigned long long h[4];
+    auto compact = [&](const uint64_t *next, int32_t *flist) -> int {
+        TRY(fill_i64(ctx, (int64_t *)cnt, 4, 0, msg));
+        if (n > 0) {
+            hipLaunchKernelGGL(k_bc_compact, dim3(compact_blocks), dim3(256), 0, ctx->stream, A->rowptr, n, next,
+                               unvis, flist, act_next, cnt);
+            LAUNCH_CHECK();
+        }
+        TRY(read_back(ctx, h, cnt, sizeof(h), msg));
+        std::swap(act_cur, act_next);
+        return LAGR_SUCCESS;
+    };
+    auto wgrid = [](int64_t items) { return grid_for(items * 64, 256, 16384); };
+    auto stats_of = [&](const int32_t *flist, int64_t nf, const uint64_t *mask, int64_t d) -> int {
+        if (nf > 0) {
+            hipLaunchKernelGGL(k_ms_stats, dim3(grid_for(nf, 256, 256)), dim3(256), 0, ctx->stream, flist, nf, mask,
+                               d, lev, dstats);
+            LAUNCH_CHECK();
+        }
+        return LAGR_SUCCESS;
+    };
+    HIP_TRY(hipMemcpyAsync(dsrc, lane_src, sizeof(int64_t) * 64, hipMemcpyHostToDevice, ctx->stream));
+    if (lev) TRY(fill_u32(ctx, (uint32_t *)lev, n * 32, 0xFFFFFFFFu, msg));
+    uint64_t *m0 = mask_of(0);
+    hipLaunchKernelGGL(k_bc_init, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, n, lanes, unvis, m0);
+    hipLaunchKernelGGL(k_ms_sources, dim3(1), dim3(64), 0, ctx->stream, dsrc, unvis, m0, dstats);
+    LAUNCH_CHECK();
+    TRY(compact(m0, list_of(0)));
+    TRY(stats_of(list_of(0), (int64_t)h[0], m0, 0));
+    int b = 0;
+    for (int64_t d = 1; d < 65535; d++) {
+        const int64_t nf = (int64_t)h[0], ef = (int64_t)h[1], na = (int64_t)h[2], ea = (int64_t)h[3];
+        uint64_t *cur = mask_of(b), *next = mask_of(b ^ 1);
+        TRY(fill_i64(ctx, (int64_t *)next, n, 0, msg));
+        if (ef * BC_PUSH_RATIO < ea) {
+            hipLaunchKernelGGL(k_ms_push, dim3(wgrid(nf)), dim3(256), 0, ctx->stream, A->rowptr, A->colidx,
+                               list_of(b), nf, cur, next, unvis);
+            if (ch.n > 0)
+                hipLaunchKernelGGL(k_ms_push_chunks, dim3(cblocks), dim3(256), 0, ctx->stream, A->colidx, ch, cur,
+                                   next, unvis);
+        } else if (na > 0) {
+            hipLaunchKernelGGL(k_ms_pull, dim3(wgrid(na)), dim3(256), 0, ctx->stream, A->rowptr, A->colidx,
+                               act_cur, na, cur, next, unvis);
+            if (ch.n > 0)
+                hipLaunchKernelGGL(k_ms_pull_chunks, dim3(cblocks), dim3(256), 0, ctx->stream, A->colidx, ch, cur,
+                                   next, unvis);
+        }
+        LAUNCH_CHECK();
+        TRY(compact(next, list_of(b ^ 1)));
+        if (h[0] == 0) break;
+        TRY(stats_of(list_of(b ^ 1), (int64_t)h[0], next, d));
+        b ^= 1;
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, dstats, 8 * 3 * 64, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    memcpy(stats, ctx->pinned, 8 * 3 * 64);
     return LAGR_SUCCESS;
 }
 

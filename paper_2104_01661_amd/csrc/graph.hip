@@ -6,6 +6,14 @@
 
 namespace {
 
+// Make a wave's LDS writes visible to the whole wave.
+__device__ __forceinline__ void wave_barrier_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Rows of at most this many entries are scanned by one thread; longer ones
 // are cut into chunks that whole wavefronts take (see row_chunks).
 constexpr int64_t LANE_ROW_MAX = 64;
@@ -186,9 +194,9 @@ __global__ void k_inverse_perm(const uint64_t *__restrict__ keys, int64_t n, uin
         inv[keys[p] & vmask] = (int32_t)p;
 }
 
-// cnt[u] = number of neighbours v of u with inv[v] < inv[u], for rows of
-// at most LANE_ROW_MAX entries (one thread each; 0 for longer rows, which
-// k_count_relabel_chunks adds in).
+// cnt[inv[u]] = number of neighbours v of u with inv[v] < inv[u] (the
+// length of row inv[u] of L), for rows of at most LANE_ROW_MAX entries
+// (one thread each; 0 for longer rows, which k_count_relabel_chunks adds).
 __global__ void k_count_relabel_lower(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                       const int32_t *__restrict__ inv, int64_t n,
                                       int64_t *__restrict__ cnt)
@@ -196,12 +204,11 @@ __global__ void k_count_relabel_lower(const int64_t *__restrict__ rp, const int3
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
          u += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = rp[u], len = rp[u + 1] - b;
+        const int32_t iu = inv[u];
         int64_t c = 0;
-        if (len <= LANE_ROW_MAX) {
-            const int32_t iu = inv[u];
+        if (len <= LANE_ROW_MAX)
             for (int64_t p = b; p < b + len; p++) c += inv[ci[p]] < iu ? 1 : 0;
-        }
-        cnt[u] = c;
+        cnt[iu] = c;
     }
 }
 
@@ -217,34 +224,39 @@ __global__ void k_count_relabel_chunks(const int32_t *__restrict__ ci, const int
         unsigned long long k = 0;
         for (int64_t p = ch.beg[c] + lane; p < ch.end[c]; p += 64) k += inv[ci[p]] < iu ? 1 : 0;
         for (int o = 32; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
-        if (lane == 0 && k) atomicAdd((unsigned long long *)&cnt[u], k);
+        if (lane == 0 && k) atomicAdd((unsigned long long *)&cnt[iu], k);
     }
 }
 
-// Keys (inv[u] << vbits | inv[v]) of the relabelled strictly lower part.
-// cursor[u] starts at the row's output offset; the order inside a row does
-// not matter (the keys are sorted next).
+// Column ids of the relabelled strictly lower part, written unsorted into
+// row inv[u] of L (buffer U, from the row's offset Lrp[inv[u]]), with the
+// row of every entry (rowid; the sort below only moves ids within a row).
 __global__ void k_emit_relabel_lower(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                      const int32_t *__restrict__ inv, int64_t n,
-                                     const int64_t *__restrict__ cursor, int vbits,
-                                     uint64_t *__restrict__ keys)
+                                     const int64_t *__restrict__ Lrp, int32_t *__restrict__ U,
+                                     int32_t *__restrict__ rowid)
 {
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
          u += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = rp[u], len = rp[u + 1] - b;
         if (len > LANE_ROW_MAX) continue;
         const int32_t iu = inv[u];
-        int64_t o = cursor[u];
+        int64_t o = Lrp[iu];
         for (int64_t p = b; p < b + len; p++) {
             const int32_t iv = inv[ci[p]];
-            if (iv < iu) keys[o++] = ((uint64_t)iu << vbits) | (uint64_t)iv;
+            if (iv < iu) {
+                U[o] = iv;
+                rowid[o++] = iu;
+            }
         }
     }
 }
 
+// The long rows of A, chunk by chunk; cursor[inv[u]] starts at the row's
+// offset in L.
 __global__ void k_emit_relabel_chunks(const int32_t *__restrict__ ci, const int32_t *__restrict__ inv,
-                                      RowChunks ch, int vbits, unsigned long long *__restrict__ cursor,
-                                      uint64_t *__restrict__ keys)
+                                      RowChunks ch, unsigned long long *__restrict__ cursor,
+                                      int32_t *__restrict__ U, int32_t *__restrict__ rowid)
 {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
@@ -265,10 +277,88 @@ __global__ void k_emit_relabel_chunks(const int32_t *__restrict__ ci, const int3
             const uint64_t bal = __ballot(take);
             if (!bal) continue;
             unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(&cursor[u], (unsigned long long)__popcll(bal));
+            if (lane == 0) base = atomicAdd(&cursor[iu], (unsigned long long)__popcll(bal));
             base = __shfl((long long)base, 0, 64);
-            if (take) keys[base + __popcll(bal & below)] = ((uint64_t)iu << vbits) | (uint64_t)iv;
+            if (take) {
+                const unsigned long long o = base + __popcll(bal & below);
+                U[o] = iv;
+                rowid[o] = iu;
+            }
         }
+    }
+}
+
+// Rows of at most SORT_SHORT ids: each entry's place in its row of the
+// sorted output Lci is the number of smaller ids in the row (the ids of a
+// row are distinct), read from the unsorted copy U.
+constexpr int64_t SORT_SHORT = 64;
+
+__global__ void k_sort_short(const int64_t *__restrict__ Lrp, const int32_t *__restrict__ U,
+                             const int32_t *__restrict__ rowid, int64_t nnz, int32_t *__restrict__ Lci)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = rowid[e], b = Lrp[r], len = Lrp[r + 1] - b;
+        if (len > SORT_SHORT) continue;   // k_sort_long
+        const int32_t x = U[e];
+        int64_t rank = 0;
+        for (int64_t q = b; q < b + len; q++) rank += U[q] < x ? 1 : 0;
+        Lci[b + rank] = x;
+    }
+}
+
+// Rows of SORT_SHORT + 1 .. SORT_LONG ids: one wave per row, a bitonic
+// network over the row in the wave's LDS.
+constexpr int SORT_LONG = 2048;
+
+__global__ __launch_bounds__(256) void k_sort_long(const int64_t *__restrict__ Lrp, int64_t n,
+                                                   const int32_t *__restrict__ U, int32_t *__restrict__ Lci)
+{
+    __shared__ int32_t buf[4][SORT_LONG];
+    int32_t *x = buf[threadIdx.x / 64];
+    const unsigned lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    for (int64_t r = wave; r < n; r += nw) {
+        const int64_t b = Lrp[r], len = Lrp[r + 1] - b;
+        if (len <= SORT_SHORT) continue;
+        int N = 1;
+        while (N < len) N <<= 1;
+        for (int i = lane; i < N; i += 64) x[i] = i < len ? U[b + i] : INT32_MAX;
+        wave_barrier_lds();
+        for (int k = 2; k <= N; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = lane; t < N / 2; t += 64) {
+                    const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1)), ij = i | j;
+                    const int32_t a = x[i], c = x[ij];
+                    if ((a > c) == ((i & k) == 0)) {
+                        x[i] = c;
+                        x[ij] = a;
+                    }
+                }
+                wave_barrier_lds();
+            }
+        for (int i = lane; i < len; i += 64) Lci[b + i] = x[i];
+        wave_barrier_lds();
+    }
+}
+
+// Rows longer than SORT_LONG: keys of every entry, then a global radix sort.
+__global__ void k_row_keys(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci, int64_t n, int vbits,
+                           uint64_t *__restrict__ keys)
+{
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t e = rp[r]; e < rp[r + 1]; e++) keys[e] = ((uint64_t)r << vbits) | (uint64_t)ci[e];
+}
+
+__global__ void k_keys_split(const uint64_t *__restrict__ keys, int64_t nnz, int vbits, uint64_t vmask,
+                             int32_t *__restrict__ ci, int32_t *__restrict__ rowid)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        ci[e] = (int32_t)(keys[e] & vmask);
+        rowid[e] = (int32_t)(keys[e] >> vbits);
     }
 }
 
@@ -508,20 +598,6 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
     TRY(fill_i64(ctx, cnt + n, 1, 0, msg));
     int64_t nnz = 0;
     TRY(scan_exclusive_i64(ctx, cnt, cnt, n + 1, &nnz, msg));
-    uint64_t *keys = (uint64_t *)ws_get(ctx, WS_KEYS, sizeof(uint64_t) * (nnz > 0 ? nnz : 1));
-    if (!keys) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
-    if (n > 0) {
-        hipLaunchKernelGGL(k_emit_relabel_lower, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
-                           ctx->stream, A->rowptr, A->colidx, inv, n, cnt, vbits, keys);
-        LAUNCH_CHECK();
-    }
-    if (ch.n > 0) {
-        // the long rows' offsets serve as their output cursors
-        hipLaunchKernelGGL(k_emit_relabel_chunks, dim3(grid_for(ch.n * 64, 256, 8192)), dim3(256), 0,
-                           ctx->stream, A->colidx, inv, ch, vbits, (unsigned long long *)cnt, keys);
-        LAUNCH_CHECK();
-    }
-    TRY(radix_sort_u64(ctx, keys, nnz, 2 * vbits, msg));
     lagr_matrix L = new (std::nothrow) lagr_matrix_s();
     if (!L) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "matrix");
     L->type = LAGR_BOOL;
@@ -532,14 +608,31 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
         delete L;
         return rc;
     }
-    if ((rc = rowptr_from_sorted_keys(ctx, keys, nnz, vbits, n, L->rowptr, msg)) < 0) goto fail;
-    if (nnz > 0) {
-        hipLaunchKernelGGL(k_keys_to_cols, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0,
-                           ctx->stream, keys, nnz, vmask, L->colidx);
-        if (hipGetLastError() != hipSuccess) {
-            rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "relabel launch failed");
-            goto fail;
-        }
+    int32_t *rowid = (int32_t *)ws_get(ctx, WS_GEN_A, sizeof(int32_t) * (nnz > 0 ? nnz : 1));
+    int32_t *U = (int32_t *)ws_get(ctx, WS_GEN_C, sizeof(int32_t) * (nnz > 0 ? nnz : 1));
+    unsigned long long *cursor = (unsigned long long *)ws_get(ctx, WS_GEN_B, sizeof(int64_t) * (n > 0 ? n : 1));
+    if (!rowid || !U || !cursor) {
+        rc = lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
+        goto fail;
+    }
+    // 3. each row's ids land unsorted in U, with their rows; then the rows
+    //    are sorted into L
+    if (hipMemcpyAsync(L->rowptr, cnt, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, ctx->stream) !=
+            hipSuccess ||
+        (n > 0 && hipMemcpyAsync(cursor, cnt, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, ctx->stream) !=
+                      hipSuccess)) {
+        rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "relabel copy");
+        goto fail;
+    }
+    if (n > 0)
+        hipLaunchKernelGGL(k_emit_relabel_lower, dim3(grid_for(n, 256, 16384)), dim3(256), 0, ctx->stream,
+                           A->rowptr, A->colidx, inv, n, L->rowptr, U, rowid);
+    if (ch.n > 0)
+        hipLaunchKernelGGL(k_emit_relabel_chunks, dim3(grid_for(ch.n * 64, 256, 8192)), dim3(256), 0,
+                           ctx->stream, A->colidx, inv, ch, cursor, U, rowid);
+    if (hipGetLastError() != hipSuccess) {
+        rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "relabel launch failed");
+        goto fail;
     }
     {
         int64_t *tmp = (int64_t *)ws_get(ctx, WS_FLAGS, sizeof(int64_t) * (n > 0 ? n : 1));
@@ -551,8 +644,38 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
         if ((rc = row_degrees(ctx, L->rowptr, n, tmp, &mx, msg)) < 0) goto fail;
         G->L_maxrow = mx;
     }
+    if (nnz > 0 && G->L_maxrow <= SORT_LONG) {
+        hipLaunchKernelGGL(k_sort_short, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, ctx->stream, L->rowptr, U,
+                           rowid, nnz, L->colidx);
+        if (G->L_maxrow > SORT_SHORT)
+            hipLaunchKernelGGL(k_sort_long, dim3(grid_for(n * 64, 256, 16384)), dim3(256), 0, ctx->stream, L->rowptr,
+                               n, U, L->colidx);
+        if (hipGetLastError() != hipSuccess) {
+            rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
+            goto fail;
+        }
+    } else if (nnz > 0) {
+        uint64_t *keys = (uint64_t *)ws_get(ctx, WS_KEYS, sizeof(uint64_t) * nnz);
+        if (!keys) {
+            rc = lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
+            goto fail;
+        }
+        hipLaunchKernelGGL(k_row_keys, dim3(grid_for(n, 256, 16384)), dim3(256), 0, ctx->stream, L->rowptr,
+                           U, n, vbits, keys);
+        if (hipGetLastError() != hipSuccess) {
+            rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
+            goto fail;
+        }
+        if ((rc = radix_sort_u64(ctx, keys, nnz, 2 * vbits, msg)) < 0) goto fail;
+        hipLaunchKernelGGL(k_keys_split, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, ctx->stream, keys, nnz,
+                           vbits, vmask, L->colidx, rowid);
+        if (hipGetLastError() != hipSuccess) {
+            rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
+            goto fail;
+        }
+    }
     G->L = L;
-    if ((rc = tc_plan_build(ctx, G, keys, vbits, msg)) < 0) {
+    if ((rc = tc_plan_build(ctx, G, rowid, msg)) < 0) {
         G->L = nullptr;
         goto fail;
     }

@@ -161,9 +161,8 @@ struct lagr_graph_s {
     TcPlan *tcplan = nullptr;
 };
 
-// Build / release G->tcplan from G->L and L's sorted (row << vbits |
-// column) keys.
-int tc_plan_build(lagr_ctx ctx, lagr_graph G, const uint64_t *keys, int vbits, char *msg);
+// Build / release G->tcplan from G->L and the row of each entry of L.
+int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, char *msg);
 void tc_plan_free(lagr_graph G);
 
 // Rows of A longer than this are cut into chunks of this many entries for
@@ -227,6 +226,12 @@ int graph_chunks(lagr_graph G, lagr_ctx ctx, RowChunks *out, char *msg);
 // lanes (n x 8 values).
 int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nbatches, int gshift,
                double *cent, char *msg);
+// Multi-source BFS of up to 64 lanes (lane_src: HOST, 64, -1 idle): per
+// lane reached count, level sum and depth into stats[3][64] (host); with
+// lev (n x 64 uint16), the level of every reached (vertex, lane), 0xFFFF
+// elsewhere.
+int msbfs_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, uint16_t *lev, int64_t *stats,
+                  char *msg);
 // Row degrees (rowptr differences) into deg[n] and their maximum (host).
 int row_degrees(lagr_ctx ctx, const int64_t *rowptr, int64_t n, int64_t *deg,
                 int64_t *maxdeg, char *msg);

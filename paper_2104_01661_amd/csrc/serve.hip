@@ -29,145 +29,6 @@
 
 namespace {
 
-// ----------------------------------------------------- multi-source BFS
-
-__device__ __forceinline__ uint64_t or_reduce64(uint64_t x)
-{
-    unsigned lo = (unsigned)x, hi = (unsigned)(x >> 32);
-    for (int o = 32; o > 0; o >>= 1) {
-        lo |= __shfl_xor(lo, o, 64);
-        hi |= __shfl_xor(hi, o, 64);
-    }
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__global__ void k_ms_sources(const int64_t *__restrict__ src, uint64_t *__restrict__ vis,
-                             uint64_t *__restrict__ cur, uint16_t *__restrict__ lev,
-                             int64_t *__restrict__ stats)
-{
-    const int k = threadIdx.x;
-    if (k < 64) {
-        stats[k] = src[k] >= 0 ? 1 : 0;   // reached (the source itself)
-        stats[64 + k] = 0;                // level sum
-        stats[128 + k] = 0;               // depth
-        if (src[k] >= 0) {
-            const int64_t s = src[k];
-            atomicOr((unsigned long long *)&vis[s], 1ull << k);
-            atomicOr((unsigned long long *)&cur[s], 1ull << k);
-            if (lev) lev[s * 64 + k] = 0;
-        }
-    }
-}
-
-// one wave per vertex of at most GRAPH_LONG_ROW neighbours; longer rows
-// only get next[v] = 0 here (their chunks OR into it afterwards)
-__global__ __launch_bounds__(256) void k_ms_level(const int64_t *__restrict__ rp,
-                                                  const int32_t *__restrict__ ci, int64_t n,
-                                                  uint64_t lanes, const uint64_t *__restrict__ cur,
-                                                  uint64_t *__restrict__ next, uint64_t *__restrict__ vis,
-                                                  uint16_t *__restrict__ lev, int d,
-                                                  unsigned *__restrict__ flag)
-{
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
-    const unsigned lane = lane_id();
-    for (int64_t v = wave; v < n; v += nw) {
-        const int64_t b = rp[v], e = rp[v + 1];
-        const uint64_t uv = lanes & ~vis[v];
-        if (e - b > GRAPH_LONG_ROW || uv == 0) {
-            if (lane == 0) next[v] = 0;
-            continue;
-        }
-        uint64_t acc = 0;
-        for (int64_t p0 = b; p0 < e && acc != uv; p0 += 64) {
-            const int64_t p = p0 + lane;
-            const uint64_t m = p < e ? (cur[ci[p]] & uv) : 0;
-            acc |= or_reduce64(m);
-        }
-        if (lane == 0) {
-            next[v] = acc;
-            if (acc) {
-                vis[v] |= acc;
-                *flag = 1u;   // a flag: a plain store suffices (atomics on one address serialise)
-            }
-        }
-        if (lev && ((acc >> lane) & 1ull)) lev[v * 64 + lane] = (uint16_t)d;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_ms_chunks(const int32_t *__restrict__ ci, RowChunks ch,
-                                                   uint64_t lanes, const uint64_t *__restrict__ cur,
-                                                   const uint64_t *__restrict__ vis,
-                                                   uint64_t *__restrict__ next)
-{
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
-    const unsigned lane = lane_id();
-    for (int64_t c = wave; c < ch.n; c += nw) {
-        const int64_t v = ch.row[c];
-        const uint64_t uv = lanes & ~vis[v];
-        if (uv == 0) continue;
-        uint64_t acc = 0;
-        for (int64_t p0 = ch.beg[c]; p0 < ch.end[c] && acc != uv; p0 += 64) {
-            const int64_t p = p0 + lane;
-            const uint64_t m = p < ch.end[c] ? (cur[ci[p]] & uv) : 0;
-            acc |= or_reduce64(m);
-        }
-        if (lane == 0 && acc) atomicOr((unsigned long long *)&next[v], acc);
-    }
-}
-
-__global__ __launch_bounds__(256) void k_ms_long_final(const int64_t *__restrict__ rp, RowChunks ch,
-                                                       const uint64_t *__restrict__ next,
-                                                       uint64_t *__restrict__ vis,
-                                                       uint16_t *__restrict__ lev, int d,
-                                                       unsigned *__restrict__ flag)
-{
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
-    const unsigned lane = lane_id();
-    for (int64_t c = wave; c < ch.n; c += nw) {
-        const int64_t v = ch.row[c];
-        if (ch.beg[c] != rp[v]) continue;   // first chunk of its vertex
-        const uint64_t acc = next[v];
-        if (!acc) continue;
-        if (lane == 0) {
-            vis[v] |= acc;
-            *flag = 1u;   // a flag: a plain store suffices (atomics on one address serialise)
-        }
-        if (lev && ((acc >> lane) & 1ull)) lev[v * 64 + lane] = (uint16_t)d;
-    }
-}
-
-// per-lane counts of the vertices reached at level d
-__global__ __launch_bounds__(256) void k_ms_count(const uint64_t *__restrict__ next, int64_t n, int64_t d,
-                                                  int64_t *__restrict__ stats)
-{
-    __shared__ unsigned long long cnt[64];
-    if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
-    __syncthreads();
-    const unsigned lane = lane_id();
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
-    unsigned long long mine = 0;
-    for (int64_t v0 = wave * 64; v0 < n; v0 += nw * 64) {
-        const uint64_t x = v0 + lane < n ? next[v0 + lane] : 0;
-        if (!__ballot(x != 0)) continue;
-        for (int k = 0; k < 64; k++) {
-            const uint64_t b = __ballot((x >> k) & 1ull);
-            if ((int)lane == k) mine += __popcll(b);
-        }
-    }
-    if (mine) atomicAdd(&cnt[lane], mine);
-    __syncthreads();
-    if (threadIdx.x < 64 && cnt[threadIdx.x]) {
-        const unsigned long long c = cnt[threadIdx.x];
-        atomicAdd((unsigned long long *)&stats[threadIdx.x], c);
-        atomicAdd((unsigned long long *)&stats[64 + threadIdx.x], c * (unsigned long long)d);
-        atomicMax((unsigned long long *)&stats[128 + threadIdx.x], (unsigned long long)d);
-    }
-}
-
 __global__ void k_lane_levels(const uint16_t *__restrict__ lev, int64_t n, int k, int64_t *__restrict__ out)
 {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
@@ -310,73 +171,20 @@ struct lagr_server_s {
 
 namespace {
 
-// Device working set of one batch, in bytes: the frontier / visited lane
-// masks of a multi-source BFS (3 x 8n) plus, when results are kept, the
-// 64 x 16-bit level lanes and one int64 vector per query; for BC the 64-lane
-// sigma and W arrays (2 x 512n), the lane masks (one 8n buffer per level,
-// counted as 16 levels), the 8 group sums and the kept vectors; for a count
-// its row-work prefix.
+// Device working set of one batch, in bytes: for a multi-source BFS the
+// unreached masks and two active lists (16n) and two level buffers of lane
+// masks and vertex lists (24n), plus, when results are kept, the 64 x
+// 16-bit level lanes and one int64 vector per query; for BC the 64-lane
+// sigma and W arrays (2 x 512n), the level buffers (12n per level, counted
+// as 8 levels), the unreached masks and lists, the 8 group sums and the
+// kept vectors; for a count the work partials.
 int64_t footprint(const lagr_server_s *S, int kind, int graph, int nq)
 {
     const int64_t n = S->graphs[graph]->A->nrows;
     const bool keep = S->cfg.keep_vectors != 0;
     if (kind == LAGR_QUERY_TC) return 16 * (n + 1);
-    if (kind == LAGR_QUERY_BFS) return 24 * n + (keep ? (128 + 8 * (int64_t)nq) * n : 0);
-    return (1024 + 16 * 8 + 64) * n + (keep ? 8 * (int64_t)nq * n : 0);
-}
-
-// multi-source BFS over the lanes of lane_src (HOST, 64, -1 idle); per-lane
-// reached count, level sum and depth into stats[3][64] (host)
-int msbfs_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, uint16_t *lev,
-                  int64_t *stats, char *msg)
-{
-    const lagr_matrix A = G->A;
-    const int64_t n = A->nrows;
-    uint64_t lanes = 0;
-    for (int k = 0; k < 64; k++)
-        if (lane_src[k] >= 0) lanes |= 1ull << k;
-    uint64_t *cur = (uint64_t *)ws_get(ctx, WS_BFS_A, 8 * (size_t)(n > 0 ? n : 1));
-    uint64_t *nxt = (uint64_t *)ws_get(ctx, WS_BFS_B, 8 * (size_t)(n > 0 ? n : 1));
-    uint64_t *vis = (uint64_t *)ws_get(ctx, WS_BFS_C, 8 * (size_t)(n > 0 ? n : 1));
-    int64_t *dsrc = (int64_t *)ws_get(ctx, WS_BFS_D, 8 * 64 + 64);
-    int64_t *dst = (int64_t *)ws_get(ctx, WS_BFS_E, 8 * 3 * 64);
-    if (!cur || !nxt || !vis || !dsrc || !dst) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "msbfs workspace");
-    unsigned *flag = (unsigned *)(dsrc + 64);
-    RowChunks ch;
-    TRY(graph_chunks(G, ctx, &ch, msg));
-    TRY(fill_i64(ctx, (int64_t *)cur, n, 0, msg));
-    TRY(fill_i64(ctx, (int64_t *)vis, n, 0, msg));
-    if (lev) TRY(fill_u32(ctx, (uint32_t *)lev, n * 32, 0xFFFFFFFFu, msg));
-    HIP_TRY(hipMemcpyAsync(dsrc, lane_src, 8 * 64, hipMemcpyHostToDevice, ctx->stream));
-    hipLaunchKernelGGL(k_ms_sources, dim3(1), dim3(64), 0, ctx->stream, dsrc, vis, cur, lev, dst);
-    LAUNCH_CHECK();
-    const unsigned gb = grid_for(n * 64, 256, 16384);
-    const unsigned cb = ch.n > 0 ? grid_for(ch.n * 64, 256, 16384) : 1;
-    for (int d = 1; d < 65535; d++) {
-        TRY(fill_u32(ctx, flag, 1, 0u, msg));
-        hipLaunchKernelGGL(k_ms_level, dim3(gb), dim3(256), 0, ctx->stream, A->rowptr, A->colidx, n, lanes,
-                           cur, nxt, vis, lev, d, flag);
-        LAUNCH_CHECK();
-        if (ch.n > 0) {
-            hipLaunchKernelGGL(k_ms_chunks, dim3(cb), dim3(256), 0, ctx->stream, A->colidx, ch, lanes, cur,
-                               vis, nxt);
-            LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_ms_long_final, dim3(cb), dim3(256), 0, ctx->stream, A->rowptr, ch, nxt, vis,
-                               lev, d, flag);
-            LAUNCH_CHECK();
-        }
-        hipLaunchKernelGGL(k_ms_count, dim3(grid_for(n, 256, 256)), dim3(256), 0, ctx->stream, nxt, n,
-                           (int64_t)d, dst);
-        LAUNCH_CHECK();
-        unsigned h = 0;
-        TRY(read_back(ctx, &h, flag, sizeof(h), msg));
-        if (!h) break;
-        std::swap(cur, nxt);
-    }
-    HIP_TRY(hipMemcpyAsync(ctx->pinned, dst, 8 * 3 * 64, hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    memcpy(stats, ctx->pinned, 8 * 3 * 64);
-    return LAGR_SUCCESS;
+    if (kind == LAGR_QUERY_BFS) return 40 * n + (keep ? (128 + 8 * (int64_t)nq) * n : 0);
+    return (1024 + 12 * 8 + 16 + 64) * n + (keep ? 8 * (int64_t)nq * n : 0);
 }
 
 struct Worker {

@@ -48,8 +48,8 @@ __device__ __forceinline__ uint64_t plan_pack(int64_t off, int64_t len)
 // B-side rows j below PLAN_HOT (the highest-degree vertices after the
 // relabel) receive most B entries; a workgroup first gathers their counts
 // in LDS, so each takes one global atomic per workgroup instead of one per
-// entry (same-address atomics serialise).  The kernels read L's sorted
-// (row << vbits | column) keys, so every thread knows its entry's row and
+// entry (same-address atomics serialise).  The kernels read the row of
+// every entry of L (rowid), so every thread knows its entry's row and
 // column directly; workgroup g takes the g-th contiguous share of the
 // entries, which keeps its hot counts dense.
 constexpr int PLAN_HOT = 8192;
@@ -60,21 +60,20 @@ struct PlanEntry {
     int64_t i, j, p, si;   // row, column, position in row i, start of row i
 };
 
-__device__ __forceinline__ PlanEntry plan_entry(const uint64_t *__restrict__ keys, const int64_t *__restrict__ rp,
-                                                int vbits, uint64_t vmask, int64_t e)
+__device__ __forceinline__ PlanEntry plan_entry(const int32_t *__restrict__ rowid, const int32_t *__restrict__ ci,
+                                                const int64_t *__restrict__ rp, int64_t e)
 {
-    const uint64_t k = keys[e];
     PlanEntry x;
-    x.i = (int64_t)(k >> vbits);
-    x.j = (int64_t)(k & vmask);
+    x.i = rowid[e];
+    x.j = ci[e];
     x.si = rp[x.i];
     x.p = e - x.si;
     return x;
 }
 
 // Entries per virtual row (cnt: 2n+1 entries, zero on entry).
-__global__ __launch_bounds__(PLAN_BLOCK) void k_plan_count(const uint64_t *__restrict__ keys, int64_t nnz,
-                                                           int vbits, uint64_t vmask,
+__global__ __launch_bounds__(PLAN_BLOCK) void k_plan_count(const int32_t *__restrict__ rowid,
+                                                           const int32_t *__restrict__ ci, int64_t nnz,
                                                            const int64_t *__restrict__ rp, int64_t n,
                                                            unsigned long long *__restrict__ cnt)
 {
@@ -84,7 +83,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_count(const uint64_t *__res
     const int64_t share = (nnz + gridDim.x - 1) / gridDim.x;
     const int64_t e0 = (int64_t)blockIdx.x * share, e1 = min(nnz, e0 + share);
     for (int64_t e = e0 + threadIdx.x; e < e1; e += PLAN_BLOCK) {
-        const PlanEntry x = plan_entry(keys, rp, vbits, vmask, e);
+        const PlanEntry x = plan_entry(rowid, ci, rp, e);
         if (x.p == 0) continue;
         const int64_t lj = rp[x.j + 1] - rp[x.j];
         if (lj == 0) continue;
@@ -102,8 +101,8 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_count(const uint64_t *__res
 // B rows reserve one range per workgroup and hand out positions from LDS
 // as offsets from bstart, the first B-side offset (the host checks that
 // the B side spans fewer than 2^32 entries).
-__global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const uint64_t *__restrict__ keys, int64_t nnz,
-                                                          int vbits, uint64_t vmask,
+__global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restrict__ rowid,
+                                                          const int32_t *__restrict__ ci, int64_t nnz,
                                                           const int64_t *__restrict__ rp, int64_t n,
                                                           int64_t bstart, unsigned long long *__restrict__ cur,
                                                           uint64_t *__restrict__ ent)
@@ -114,10 +113,9 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const uint64_t *__rest
     const int64_t share = (nnz + gridDim.x - 1) / gridDim.x;
     const int64_t e0 = (int64_t)blockIdx.x * share, e1 = min(nnz, e0 + share);
     for (int64_t e = e0 + threadIdx.x; e < e1; e += PLAN_BLOCK) {
-        const uint64_t k = keys[e];
-        const int64_t j = (int64_t)(k & vmask);
+        const int64_t j = ci[e];
         if (j >= PLAN_HOT) continue;
-        const int64_t i = (int64_t)(k >> vbits), p = e - rp[i];
+        const int64_t i = rowid[e], p = e - rp[i];
         const int64_t lj = rp[j + 1] - rp[j];
         if (p > 0 && lj > p) atomicAdd(&hot[j], 1u);
     }
@@ -126,7 +124,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const uint64_t *__rest
         if (hot[x]) hot[x] = (unsigned)((int64_t)atomicAdd(&cur[n + x], (unsigned long long)hot[x]) - bstart);
     __syncthreads();
     for (int64_t e = e0 + threadIdx.x; e < e1; e += PLAN_BLOCK) {
-        const PlanEntry x = plan_entry(keys, rp, vbits, vmask, e);
+        const PlanEntry x = plan_entry(rowid, ci, rp, e);
         if (x.p == 0) continue;
         const int64_t sj = rp[x.j], lj = rp[x.j + 1] - sj;
         if (lj == 0) continue;
@@ -229,7 +227,7 @@ void tc_plan_free(lagr_graph G)
     G->tcplan = nullptr;
 }
 
-int tc_plan_build(lagr_ctx ctx, lagr_graph G, const uint64_t *keys, int vbits, char *msg)
+int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, char *msg)
 {
     const lagr_matrix Lm = G->L;
     const int64_t n = Lm->nrows, nv = 2 * n;
@@ -248,10 +246,9 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const uint64_t *keys, int vbits, c
     if (!P->trp || !P->irp) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
     int rc;
     if ((rc = fill_i64(ctx, P->trp, nv + 1, 0, msg)) < 0) return fail(rc);
-    const uint64_t vmask = vbits ? ((1ull << vbits) - 1) : 0ull;
     const int64_t nnz = Lm->nvals;
     if (nnz > 0) {
-        hipLaunchKernelGGL(k_plan_count, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, keys, nnz, vbits, vmask,
+        hipLaunchKernelGGL(k_plan_count, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx, nnz,
                            Lm->rowptr, n, (unsigned long long *)P->trp);
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
     }
@@ -267,8 +264,8 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const uint64_t *keys, int vbits, c
         if (hipMemcpyAsync(cur, P->trp, 8 * (size_t)nv, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
             return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan copy"));
         if (nnz > 0)
-            hipLaunchKernelGGL(k_plan_fill, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, keys, nnz, vbits,
-                               vmask, Lm->rowptr, n, bstart, cur, P->ent);
+            hipLaunchKernelGGL(k_plan_fill, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx,
+                               nnz, Lm->rowptr, n, bstart, cur, P->ent);
         hipLaunchKernelGGL(k_plan_items, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, ctx->stream, P->trp,
                            nv, P->irp);
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));

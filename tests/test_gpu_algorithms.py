@@ -80,6 +80,47 @@ def test_tc_hub_rows_longer_than_the_lds_table():
     assert lagr().lagr_tc(G, ctx()) == math.comb(n, 3)
 
 
+def test_tc_rows_longer_than_the_sort_tile():
+    # K_2100: rows of L reach 2099 entries, past the LDS row sort (2048), so
+    # L is sorted by the global radix sort instead
+    n = 2100
+    G, _ = graph_from_edges(*Gs.complete(n))
+    assert lagr().lagr_tc(G, ctx()) == math.comb(n, 3)
+    lrp, lci = lower_csr(G)
+    assert lrp[-1] == n * (n - 1) // 2
+    for r in (0, 1, 1000, n - 1):
+        assert np.array_equal(lci[lrp[r]:lrp[r + 1]], np.arange(r))
+
+
+def lower_csr(G):
+    """(rowptr, colidx) of the graph's cached strictly lower part, on the host."""
+    rp, ci, _ = G.tc_lower().to_csr(ctx())
+    return rp.cpu().numpy(), ci.cpu().numpy()
+
+
+@pytest.mark.parametrize("scale,ef,seed", [(10, 16, 1), (11, 8, 5), (9, 32, 6)])
+def test_tc_lower_is_the_degree_relabelled_lower_part(scale, ef, seed):
+    """L = strict lower part of A after relabelling by descending degree
+    (ties by id), rows sorted; rebuilt here with numpy from the oracle's
+    adjacency."""
+    n, s, d = rmat(scale, ef, seed)
+    G = device_graph(n, s, d)
+    lagr().lagr_property_tc_lower(G, ctx())
+    lrp, lci = lower_csr(G)
+    rp, ci = oracle.build_adjacency(n, s, d)
+    deg = np.diff(rp)
+    order = np.lexsort((np.arange(n), -deg))
+    inv = np.empty(n, dtype=np.int64)
+    inv[order] = np.arange(n)
+    rows = np.repeat(np.arange(n), deg)
+    ni, nj = inv[rows], inv[ci]
+    keep = nj < ni
+    key = np.sort(ni[keep] * n + nj[keep])
+    want_rp = np.searchsorted(key // n, np.arange(n + 1), side="left")
+    assert np.array_equal(lrp, want_rp)
+    assert np.array_equal(lci, key % n)
+
+
 @pytest.mark.parametrize("entry", GOLD["graphs"], ids=lambda e: f"s{e['scale']}ef{e['edge_factor']}")
 def test_tc_rmat_golden(entry):
     n, s, d = rmat(entry["scale"], entry["edge_factor"], entry["seed"])
