@@ -194,96 +194,90 @@ __global__ void k_inverse_perm(const uint64_t *__restrict__ keys, int64_t n, uin
         inv[keys[p] & vmask] = (int32_t)p;
 }
 
-// cnt[inv[u]] = number of neighbours v of u with inv[v] < inv[u] (the
-// length of row inv[u] of L), for rows of at most LANE_ROW_MAX entries
-// (one thread each; 0 for longer rows, which k_count_relabel_chunks adds).
-__global__ void k_count_relabel_lower(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                      const int32_t *__restrict__ inv, int64_t n,
-                                      int64_t *__restrict__ cnt)
+// rowA[e] = the row of entry e of A.  A wave takes 64 consecutive rows
+// and writes them one after the other, its lanes over the row's entries
+// (coalesced stores; a lane per row would scatter every store).  Rows of
+// more than GRAPH_LONG_ROW entries are left to k_row_ids_chunks, so that
+// no wave writes a hub row alone.
+__global__ void k_row_ids(const int64_t *__restrict__ rp, int64_t n, int32_t *__restrict__ rowA)
 {
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
-         u += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = rp[u], len = rp[u + 1] - b;
-        const int32_t iu = inv[u];
-        int64_t c = 0;
-        if (len <= LANE_ROW_MAX)
-            for (int64_t p = b; p < b + len; p++) c += inv[ci[p]] < iu ? 1 : 0;
-        cnt[iu] = c;
-    }
-}
-
-__global__ void k_count_relabel_chunks(const int32_t *__restrict__ ci, const int32_t *__restrict__ inv,
-                                       RowChunks ch, int64_t *__restrict__ cnt)
-{
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const unsigned lane = lane_id();
-    for (int64_t c = wave; c < ch.n; c += nw) {
-        const int32_t u = ch.row[c];
-        const int32_t iu = inv[u];
-        unsigned long long k = 0;
-        for (int64_t p = ch.beg[c] + lane; p < ch.end[c]; p += 64) k += inv[ci[p]] < iu ? 1 : 0;
-        for (int o = 32; o > 0; o >>= 1) k += __shfl_xor(k, o, 64);
-        if (lane == 0 && k) atomicAdd((unsigned long long *)&cnt[iu], k);
-    }
-}
-
-// Column ids of the relabelled strictly lower part, written unsorted into
-// row inv[u] of L (buffer U, from the row's offset Lrp[inv[u]]), with the
-// row of every entry (rowid; the sort below only moves ids within a row).
-__global__ void k_emit_relabel_lower(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                     const int32_t *__restrict__ inv, int64_t n,
-                                     const int64_t *__restrict__ Lrp, int32_t *__restrict__ U,
-                                     int32_t *__restrict__ rowid)
-{
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
-         u += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = rp[u], len = rp[u + 1] - b;
-        if (len > LANE_ROW_MAX) continue;
-        const int32_t iu = inv[u];
-        int64_t o = Lrp[iu];
-        for (int64_t p = b; p < b + len; p++) {
-            const int32_t iv = inv[ci[p]];
-            if (iv < iu) {
-                U[o] = iv;
-                rowid[o++] = iu;
-            }
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); r0 < n; r0 += step) {
+        const int64_t r = r0 + lane;
+        const int64_t mb = r < n ? rp[r] : 0, me = r < n ? rp[r + 1] : 0;
+        const int rows = (int)min((int64_t)64, n - r0);
+        for (int k = 0; k < rows; k++) {
+            const int64_t b = __shfl(mb, k, 64), e = __shfl(me, k, 64);
+            if (e - b > GRAPH_LONG_ROW) continue;
+            for (int64_t p = b + lane; p < e; p += 64) rowA[p] = (int32_t)(r0 + k);
         }
     }
 }
 
-// The long rows of A, chunk by chunk; cursor[inv[u]] starts at the row's
-// offset in L.
-__global__ void k_emit_relabel_chunks(const int32_t *__restrict__ ci, const int32_t *__restrict__ inv,
-                                      RowChunks ch, unsigned long long *__restrict__ cursor,
-                                      int32_t *__restrict__ U, int32_t *__restrict__ rowid)
+__global__ void k_row_ids_chunks(RowChunks ch, int32_t *__restrict__ rowA)
 {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const unsigned lane = lane_id();
-    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    for (int64_t c = wave; c < ch.n; c += nw) {
-        const int32_t u = ch.row[c];
-        const int32_t iu = inv[u];
-        const int64_t e = ch.end[c];
-        for (int64_t p0 = ch.beg[c]; p0 < e; p0 += 64) {
-            const int64_t p = p0 + lane;
-            int32_t iv = 0;
-            bool take = false;
-            if (p < e) {
-                iv = inv[ci[p]];
-                take = iv < iu;
-            }
-            const uint64_t bal = __ballot(take);
-            if (!bal) continue;
-            unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(&cursor[iu], (unsigned long long)__popcll(bal));
-            base = __shfl((long long)base, 0, 64);
-            if (take) {
-                const unsigned long long o = base + __popcll(bal & below);
-                U[o] = iv;
-                rowid[o] = iu;
-            }
+    for (int64_t c = wave; c < ch.n; c += nw)
+        for (int64_t p = ch.beg[c] + lane; p < ch.end[c]; p += 64) rowA[p] = ch.row[c];
+}
+
+// cnt[inv[u]] (zero on entry) += number of neighbours v of u with
+// inv[v] < inv[u]: the length of row inv[u] of L.  One lane per entry of A;
+// the loop steps whole wavefronts (wave_run needs every lane).
+__global__ void k_count_relabel(const int32_t *__restrict__ rowA, const int32_t *__restrict__ ci,
+                                const int32_t *__restrict__ inv, int64_t nnz,
+                                unsigned long long *__restrict__ cnt)
+{
+    const unsigned lane = lane_id();
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t w0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); w0 < nnz; w0 += step) {
+        const int64_t e = w0 + lane;
+        int32_t u = -1, iu = 0;
+        bool take = false;
+        if (e < nnz) {
+            u = rowA[e];
+            iu = inv[u];
+            take = inv[ci[e]] < iu;
+        }
+        const WaveRun w = wave_run(u);
+        const uint64_t t = __ballot(take) & w.run;
+        if (lane == w.head && t) atomicAdd(&cnt[iu], (unsigned long long)__popcll(t));
+    }
+}
+
+// Column ids of the relabelled strictly lower part, written unsorted into
+// row inv[u] of L (buffer U; cursor[inv[u]] starts at the row's offset in
+// L), with the row of every entry (rowL; the sort below only moves ids
+// within a row).
+__global__ void k_emit_relabel(const int32_t *__restrict__ rowA, const int32_t *__restrict__ ci,
+                               const int32_t *__restrict__ inv, int64_t nnz,
+                               unsigned long long *__restrict__ cursor, int32_t *__restrict__ U,
+                               int32_t *__restrict__ rowL)
+{
+    const unsigned lane = lane_id();
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t w0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); w0 < nnz; w0 += step) {
+        const int64_t e = w0 + lane;
+        int32_t u = -1, iu = 0, iv = 0;
+        bool take = false;
+        if (e < nnz) {
+            u = rowA[e];
+            iu = inv[u];
+            iv = inv[ci[e]];
+            take = iv < iu;
+        }
+        const WaveRun w = wave_run(u);
+        const uint64_t t = __ballot(take) & w.run;
+        unsigned long long base = 0;
+        if (lane == w.head && t) base = atomicAdd(&cursor[iu], (unsigned long long)__popcll(t));
+        base = (unsigned long long)__shfl((long long)base, (int)w.head, 64);
+        if (take) {
+            const unsigned long long o = base + __popcll(t & w.before);
+            U[o] = iv;
+            rowL[o] = iu;
         }
     }
 }
@@ -307,21 +301,21 @@ __global__ void k_sort_short(const int64_t *__restrict__ Lrp, const int32_t *__r
     }
 }
 
-// Rows of SORT_SHORT + 1 .. SORT_LONG ids: one wave per row, a bitonic
-// network over the row in the wave's LDS.
+// Rows of SORT_SHORT + 1 .. SORT_LONG ids (one chunk each in ch): one wave
+// per row, a bitonic network over the row in the wave's LDS.
 constexpr int SORT_LONG = 2048;
 
-__global__ __launch_bounds__(256) void k_sort_long(const int64_t *__restrict__ Lrp, int64_t n,
-                                                   const int32_t *__restrict__ U, int32_t *__restrict__ Lci)
+__global__ __launch_bounds__(256) void k_sort_long(RowChunks ch, const int32_t *__restrict__ U,
+                                                   int32_t *__restrict__ Lci)
 {
     __shared__ int32_t buf[4][SORT_LONG];
     int32_t *x = buf[threadIdx.x / 64];
     const unsigned lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
-    for (int64_t r = wave; r < n; r += nw) {
-        const int64_t b = Lrp[r], len = Lrp[r + 1] - b;
-        if (len <= SORT_SHORT) continue;
+    for (int64_t c = wave; c < ch.n; c += nw) {
+        const int64_t b = ch.beg[c];
+        const int len = (int)(ch.end[c] - b);
         int N = 1;
         while (N < len) N <<= 1;
         for (int i = lane; i < N; i += 64) x[i] = i < len ? U[b + i] : INT32_MAX;
@@ -330,9 +324,9 @@ __global__ __launch_bounds__(256) void k_sort_long(const int64_t *__restrict__ L
             for (int j = k >> 1; j > 0; j >>= 1) {
                 for (int t = lane; t < N / 2; t += 64) {
                     const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1)), ij = i | j;
-                    const int32_t a = x[i], c = x[ij];
-                    if ((a > c) == ((i & k) == 0)) {
-                        x[i] = c;
+                    const int32_t a = x[i], c2 = x[ij];
+                    if ((a > c2) == ((i & k) == 0)) {
+                        x[i] = c2;
                         x[ij] = a;
                     }
                 }
@@ -572,30 +566,36 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
     uint64_t *okeys = (uint64_t *)ws_get(ctx, WS_PERM, sizeof(uint64_t) * (n > 0 ? n : 1));
     int32_t *inv = (int32_t *)ws_get(ctx, WS_DEG, sizeof(int32_t) * (n > 0 ? n : 1));
     int64_t *cnt = (int64_t *)ws_get(ctx, WS_FLAGS, sizeof(int64_t) * (n + 1));
-    if (!okeys || !inv || !cnt) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
+    const int64_t nnzA = A->nvals;
+    int32_t *rowA = (int32_t *)ws_get(ctx, WS_GEN_D, sizeof(int32_t) * (nnzA > 0 ? nnzA : 1));
+    if (!okeys || !inv || !cnt || !rowA) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
     if (n > 0) {
         hipLaunchKernelGGL(k_order_keys, dim3(grid_for(n, 256, 65536)), dim3(256), 0, ctx->stream,
                            G->row_degree, n, G->max_degree, vbits, okeys);
         LAUNCH_CHECK();
     }
     TRY(radix_sort_u64(ctx, okeys, n, vbits + bits_for((uint64_t)G->max_degree), msg));
+    TRY(fill_i64(ctx, cnt, n + 1, 0, msg));
     if (n > 0) {
         hipLaunchKernelGGL(k_inverse_perm, dim3(grid_for(n, 256, 65536)), dim3(256), 0, ctx->stream,
                            okeys, n, vmask, inv);
         LAUNCH_CHECK();
-        // 2. rows of the relabelled strictly lower part
-        hipLaunchKernelGGL(k_count_relabel_lower, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
-                           ctx->stream, A->rowptr, A->colidx, inv, n, cnt);
+        // 2. the row of every entry of A, then the row lengths of the
+        //    relabelled strictly lower part
+        RowChunks ch;
+        TRY(graph_chunks(G, ctx, &ch, msg));
+        hipLaunchKernelGGL(k_row_ids, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, A->rowptr, n,
+                           rowA);
+        if (ch.n > 0)
+            hipLaunchKernelGGL(k_row_ids_chunks, dim3(grid_for(ch.n * 64, 256, 8192)), dim3(256), 0,
+                               ctx->stream, ch, rowA);
         LAUNCH_CHECK();
+        if (nnzA > 0) {
+            hipLaunchKernelGGL(k_count_relabel, dim3(grid_for(nnzA, 256, 8192)), dim3(256), 0, ctx->stream,
+                               rowA, A->colidx, inv, nnzA, (unsigned long long *)cnt);
+            LAUNCH_CHECK();
+        }
     }
-    RowChunks ch;
-    TRY(row_chunks(ctx, A->rowptr, n, LANE_ROW_MAX, ROW_CHUNK, WS_CHUNK_A, WS_CHUNK_B, &ch, msg));
-    if (ch.n > 0) {
-        hipLaunchKernelGGL(k_count_relabel_chunks, dim3(grid_for(ch.n * 64, 256, 8192)), dim3(256), 0,
-                           ctx->stream, A->colidx, inv, ch, cnt);
-        LAUNCH_CHECK();
-    }
-    TRY(fill_i64(ctx, cnt + n, 1, 0, msg));
     int64_t nnz = 0;
     TRY(scan_exclusive_i64(ctx, cnt, cnt, n + 1, &nnz, msg));
     lagr_matrix L = new (std::nothrow) lagr_matrix_s();
@@ -624,12 +624,9 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
         rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "relabel copy");
         goto fail;
     }
-    if (n > 0)
-        hipLaunchKernelGGL(k_emit_relabel_lower, dim3(grid_for(n, 256, 16384)), dim3(256), 0, ctx->stream,
-                           A->rowptr, A->colidx, inv, n, L->rowptr, U, rowid);
-    if (ch.n > 0)
-        hipLaunchKernelGGL(k_emit_relabel_chunks, dim3(grid_for(ch.n * 64, 256, 8192)), dim3(256), 0,
-                           ctx->stream, A->colidx, inv, ch, cursor, U, rowid);
+    if (nnzA > 0)
+        hipLaunchKernelGGL(k_emit_relabel, dim3(grid_for(nnzA, 256, 8192)), dim3(256), 0, ctx->stream, rowA,
+                           A->colidx, inv, nnzA, cursor, U, rowid);
     if (hipGetLastError() != hipSuccess) {
         rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "relabel launch failed");
         goto fail;
@@ -647,12 +644,21 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
     if (nnz > 0 && G->L_maxrow <= SORT_LONG) {
         hipLaunchKernelGGL(k_sort_short, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, ctx->stream, L->rowptr, U,
                            rowid, nnz, L->colidx);
-        if (G->L_maxrow > SORT_SHORT)
-            hipLaunchKernelGGL(k_sort_long, dim3(grid_for(n * 64, 256, 16384)), dim3(256), 0, ctx->stream, L->rowptr,
-                               n, U, L->colidx);
         if (hipGetLastError() != hipSuccess) {
             rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
             goto fail;
+        }
+        if (G->L_maxrow > SORT_SHORT) {
+            RowChunks lc;
+            if ((rc = row_chunks(ctx, L->rowptr, n, SORT_SHORT, SORT_LONG, WS_CHUNK_A, WS_CHUNK_B, &lc, msg)) < 0)
+                goto fail;
+            if (lc.n > 0)
+                hipLaunchKernelGGL(k_sort_long, dim3(grid_for(lc.n * 64, 256, 16384)), dim3(256), 0, ctx->stream,
+                                   lc, U, L->colidx);
+            if (hipGetLastError() != hipSuccess) {
+                rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
+                goto fail;
+            }
         }
     } else if (nnz > 0) {
         uint64_t *keys = (uint64_t *)ws_get(ctx, WS_KEYS, sizeof(uint64_t) * nnz);

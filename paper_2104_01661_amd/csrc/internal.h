@@ -257,3 +257,29 @@ __device__ __forceinline__ unsigned lane_id()
 {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
+
+// For entries in row order, one per lane: the lanes of the wave whose key
+// (row) equals this lane's form one contiguous run.  The run's first lane
+// (head) can make one atomic on the row's counter for the whole run (atomics
+// from many lanes on one address are serialised).  run: the lanes of the
+// run; before: those of them below this lane.  Every lane of the wave must
+// call it.
+struct WaveRun {
+    unsigned head;
+    uint64_t run, before;
+};
+
+__device__ __forceinline__ WaveRun wave_run(int32_t key)
+{
+    const unsigned lane = lane_id();
+    const int32_t prev = __shfl_up(key, 1, 64);
+    const uint64_t H = __ballot(lane == 0 || prev != key);
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    WaveRun w;
+    w.head = 63 - __clzll((unsigned long long)(H & upto));
+    const uint64_t after = H & ~upto;
+    const uint64_t hi = after ? ((1ull << (__ffsll((unsigned long long)after) - 1)) - 1) : ~0ull;
+    w.run = hi & ~((1ull << w.head) - 1);
+    w.before = w.run & ((1ull << lane) - 1);
+    return w;
+}

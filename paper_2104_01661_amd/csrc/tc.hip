@@ -51,86 +51,128 @@ __device__ __forceinline__ uint64_t plan_pack(int64_t off, int64_t len)
 // entry (same-address atomics serialise).  The kernels read the row of
 // every entry of L (rowid), so every thread knows its entry's row and
 // column directly; workgroup g takes the g-th contiguous share of the
-// entries, which keeps its hot counts dense.
+// entries, which keeps its hot counts dense.  The count kernel's atomic
+// returns the workgroup's offset inside each hot row (boff, PLAN_GRID x
+// PLAN_HOT), which the fill kernel, run on the same partition, starts from.
+// The kernels chain dependent loads (row, row start, column, column's row),
+// so they run 512-thread workgroups, four per CU (the 32 KiB LDS table
+// allows it), for more loads in flight.
 constexpr int PLAN_HOT = 8192;
-constexpr int PLAN_BLOCK = 256;
+constexpr int PLAN_BLOCK = 512;
 constexpr unsigned PLAN_GRID = 1024;
 
 struct PlanEntry {
     int64_t i, j, p, si;   // row, column, position in row i, start of row i
 };
 
+// rowpk[r] = plan_pack(start of row r, length of row r): one gather gives
+// both (the plan kernels gather it for the row and for the column of every
+// entry, at random columns).
 __device__ __forceinline__ PlanEntry plan_entry(const int32_t *__restrict__ rowid, const int32_t *__restrict__ ci,
-                                                const int64_t *__restrict__ rp, int64_t e)
+                                                const uint64_t *__restrict__ rowpk, int64_t e)
 {
     PlanEntry x;
     x.i = rowid[e];
     x.j = ci[e];
-    x.si = rp[x.i];
+    x.si = (int64_t)(rowpk[x.i] >> TC_PLAN_LEN_BITS);
     x.p = e - x.si;
     return x;
 }
 
-// Entries per virtual row (cnt: 2n+1 entries, zero on entry).
+__global__ void k_row_pack(const int64_t *__restrict__ rp, int64_t n, uint64_t *__restrict__ rowpk)
+{
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x)
+        rowpk[r] = plan_pack(rp[r], rp[r + 1] - rp[r]);
+}
+
+// Entries per virtual row (cnt: 2n+1 entries, zero on entry).  The loops
+// step whole wavefronts, so every lane of a wave takes part in each
+// iteration's ballots and shuffles.
 __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_count(const int32_t *__restrict__ rowid,
                                                            const int32_t *__restrict__ ci, int64_t nnz,
-                                                           const int64_t *__restrict__ rp, int64_t n,
-                                                           unsigned long long *__restrict__ cnt)
+                                                           const uint64_t *__restrict__ rowpk, int64_t n,
+                                                           unsigned long long *__restrict__ cnt,
+                                                           unsigned *__restrict__ boff)
 {
     __shared__ unsigned hot[PLAN_HOT];
     for (int x = threadIdx.x; x < PLAN_HOT; x += PLAN_BLOCK) hot[x] = 0u;
     __syncthreads();
     const int64_t share = (nnz + gridDim.x - 1) / gridDim.x;
     const int64_t e0 = (int64_t)blockIdx.x * share, e1 = min(nnz, e0 + share);
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += PLAN_BLOCK) {
-        const PlanEntry x = plan_entry(rowid, ci, rp, e);
-        if (x.p == 0) continue;
-        const int64_t lj = rp[x.j + 1] - rp[x.j];
-        if (lj == 0) continue;
-        if (lj <= x.p) atomicAdd(&cnt[x.i], 1ull);
-        else if (x.j < PLAN_HOT) atomicAdd(&hot[x.j], 1u);
-        else atomicAdd(&cnt[n + x.j], 1ull);
+    const unsigned lane = lane_id();
+    for (int64_t w0 = e0 + (threadIdx.x & ~63u); w0 < e1; w0 += PLAN_BLOCK) {
+        const int64_t e = w0 + lane;
+        bool a_side = false;
+        int32_t key = -1;
+        if (e < e1) {
+            const PlanEntry x = plan_entry(rowid, ci, rowpk, e);
+            key = (int32_t)x.i;
+            const int64_t lj = (int64_t)(rowpk[x.j] & ((1ull << TC_PLAN_LEN_BITS) - 1));
+            if (x.p > 0 && lj > 0) {
+                if (lj <= x.p) a_side = true;
+                else if (x.j < PLAN_HOT) atomicAdd(&hot[x.j], 1u);
+                else atomicAdd(&cnt[n + x.j], 1ull);
+            }
+        }
+        const WaveRun w = wave_run(key);
+        const uint64_t take = __ballot(a_side) & w.run;
+        if (lane == w.head && take) atomicAdd(&cnt[key], (unsigned long long)__popcll(take));
     }
     __syncthreads();
+    unsigned *mine = boff + (size_t)blockIdx.x * PLAN_HOT;
     for (int x = threadIdx.x; x < PLAN_HOT && x < n; x += PLAN_BLOCK)
-        if (hot[x]) atomicAdd(&cnt[n + x], (unsigned long long)hot[x]);
+        mine[x] = hot[x] ? (unsigned)atomicAdd(&cnt[n + x], (unsigned long long)hot[x]) : 0u;
 }
 
 // cur (a copy of the first 2n offsets) holds the write cursor of each
 // virtual row; the order of the entries within a row is immaterial.  Hot
-// B rows reserve one range per workgroup and hand out positions from LDS
-// as offsets from bstart, the first B-side offset (the host checks that
-// the B side spans fewer than 2^32 entries).
+// B rows hand out positions from LDS as offsets from bstart, the first
+// B-side offset (the host checks that the B side spans fewer than 2^32
+// entries), starting at the workgroup's range from the count kernel.
 __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restrict__ rowid,
                                                           const int32_t *__restrict__ ci, int64_t nnz,
-                                                          const int64_t *__restrict__ rp, int64_t n,
-                                                          int64_t bstart, unsigned long long *__restrict__ cur,
+                                                          const uint64_t *__restrict__ rowpk, int64_t n,
+                                                          const int64_t *__restrict__ trp, int64_t bstart,
+                                                          const unsigned *__restrict__ boff,
+                                                          unsigned long long *__restrict__ cur,
                                                           uint64_t *__restrict__ ent)
 {
     __shared__ unsigned hot[PLAN_HOT];
-    for (int x = threadIdx.x; x < PLAN_HOT; x += PLAN_BLOCK) hot[x] = 0u;
+    const unsigned *mine = boff + (size_t)blockIdx.x * PLAN_HOT;
+    for (int x = threadIdx.x; x < PLAN_HOT && x < n; x += PLAN_BLOCK)
+        hot[x] = (unsigned)(trp[n + x] - bstart) + mine[x];
     __syncthreads();
     const int64_t share = (nnz + gridDim.x - 1) / gridDim.x;
     const int64_t e0 = (int64_t)blockIdx.x * share, e1 = min(nnz, e0 + share);
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += PLAN_BLOCK) {
-        const int64_t j = ci[e];
-        if (j >= PLAN_HOT) continue;
-        const int64_t i = rowid[e], p = e - rp[i];
-        const int64_t lj = rp[j + 1] - rp[j];
-        if (p > 0 && lj > p) atomicAdd(&hot[j], 1u);
-    }
-    __syncthreads();
-    for (int x = threadIdx.x; x < PLAN_HOT && x < n; x += PLAN_BLOCK)
-        if (hot[x]) hot[x] = (unsigned)((int64_t)atomicAdd(&cur[n + x], (unsigned long long)hot[x]) - bstart);
-    __syncthreads();
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += PLAN_BLOCK) {
-        const PlanEntry x = plan_entry(rowid, ci, rp, e);
-        if (x.p == 0) continue;
-        const int64_t sj = rp[x.j], lj = rp[x.j + 1] - sj;
-        if (lj == 0) continue;
-        if (lj <= x.p) ent[atomicAdd(&cur[x.i], 1ull)] = plan_pack(sj, lj);
-        else if (x.j < PLAN_HOT) ent[bstart + atomicAdd(&hot[x.j], 1u)] = plan_pack(x.si, x.p);
-        else ent[atomicAdd(&cur[n + x.j], 1ull)] = plan_pack(x.si, x.p);
+    const unsigned lane = lane_id();
+    for (int64_t w0 = e0 + (threadIdx.x & ~63u); w0 < e1; w0 += PLAN_BLOCK) {
+        const int64_t e = w0 + lane;
+        bool a_side = false;
+        int32_t key = -1;
+        uint64_t packed = 0;
+        if (e < e1) {
+            const PlanEntry x = plan_entry(rowid, ci, rowpk, e);
+            key = (int32_t)x.i;
+            const uint64_t pj = rowpk[x.j];
+            const int64_t lj = (int64_t)(pj & ((1ull << TC_PLAN_LEN_BITS) - 1));
+            if (x.p > 0 && lj > 0) {
+                if (lj <= x.p) {
+                    a_side = true;
+                    packed = pj;
+                } else if (x.j < PLAN_HOT) {
+                    ent[bstart + atomicAdd(&hot[x.j], 1u)] = plan_pack(x.si, x.p);
+                } else {
+                    ent[atomicAdd(&cur[n + x.j], 1ull)] = plan_pack(x.si, x.p);
+                }
+            }
+        }
+        const WaveRun w = wave_run(key);
+        const uint64_t take = __ballot(a_side) & w.run;
+        unsigned long long base = 0;
+        if (lane == w.head && take) base = atomicAdd(&cur[key], (unsigned long long)__popcll(take));
+        base = (unsigned long long)__shfl((long long)base, (int)w.head, 64);
+        if (a_side) ent[base + __popcll(take & w.before)] = packed;
     }
 }
 
@@ -247,9 +289,19 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, char *msg)
     int rc;
     if ((rc = fill_i64(ctx, P->trp, nv + 1, 0, msg)) < 0) return fail(rc);
     const int64_t nnz = Lm->nvals;
+    if (G->L_maxrow >= ((int64_t)1 << TC_PLAN_LEN_BITS))
+        return fail(lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "rows of L too long for the count plan"));
+    unsigned *boff = (unsigned *)ws_get(ctx, WS_GEN_H, sizeof(unsigned) * (size_t)PLAN_GRID * PLAN_HOT);
+    uint64_t *rowpk = (uint64_t *)ws_get(ctx, WS_GEN_E, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    if (!boff || !rowpk) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_row_pack, dim3(grid_for(n, 256, 16384)), dim3(256), 0, ctx->stream, Lm->rowptr, n,
+                           rowpk);
+        if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
+    }
     if (nnz > 0) {
         hipLaunchKernelGGL(k_plan_count, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx, nnz,
-                           Lm->rowptr, n, (unsigned long long *)P->trp);
+                           rowpk, n, (unsigned long long *)P->trp, boff);
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
     }
     if ((rc = scan_exclusive_i64(ctx, P->trp, P->trp, nv + 1, &P->nent, msg)) < 0) return fail(rc);
@@ -265,7 +317,7 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, char *msg)
             return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan copy"));
         if (nnz > 0)
             hipLaunchKernelGGL(k_plan_fill, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx,
-                               nnz, Lm->rowptr, n, bstart, cur, P->ent);
+                               nnz, rowpk, n, P->trp, bstart, boff, cur, P->ent);
         hipLaunchKernelGGL(k_plan_items, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, ctx->stream, P->trp,
                            nv, P->irp);
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
