@@ -39,6 +39,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-bc", action="store_true")
+    p.add_argument("--no-sssp", action="store_true")
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--batch-graphs", type=int, default=0,
                    help="graphs in the many-graph leg (default: the full 2,000)")
@@ -386,6 +387,47 @@ def main():
         out["bc"] = {"workload": bcfg["name"], "s_per_batch":
                      round(float(np.median(bc_runs)) * 1e-3 / bcfg["batches"], 6),
                      "batches": bcfg["batches"], "batch_size": bcfg["batch_size"], "dtype": "f64"}
+
+    # ------------------------------------- delta-stepping SSSP (2^20)
+    log("sssp leg")
+    if not args.no_sssp:
+        scfg = graphgen.SSSP
+        wts = graphgen.edge_weights(arp.cpu().numpy(), aci.cpu().numpy(), scfg["weight_seed"], scfg["wmax"])
+        SG = L.Graph(ctx, L.Matrix.wrap_csr(ctx, n, n, arp, aci, torch.from_numpy(wts).to(dev)))
+        ssrc = [int(x) for x in graphgen.sources(n, src, dst, scfg["sources"], scfg["source_seed"])]
+
+        def sssp_ms(s, delta):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            dv = L.lagr_sssp(SG, s, delta, ctx)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1), dv
+
+        # delta: the fastest of a few on the first source (untimed choice)
+        sweep = {}
+        for delta in scfg["deltas"]:
+            sssp_ms(ssrc[0], delta)
+            sweep[delta] = float(np.median([sssp_ms(ssrc[0], delta)[0] for _ in range(3)]))
+        best = min(sweep, key=sweep.get)
+        s_ms, s_edges = [], []
+        for s in ssrc:
+            runs = []
+            for _ in range(3):
+                ms, dv = sssp_ms(s, best)
+                runs.append(ms)
+            dist = dv.values_full(ctx).cpu().numpy()
+            s_edges.append(int(deg[np.isfinite(dist)].sum()) // 2)
+            s_ms.append(float(np.median(runs)))
+            del dv
+        out["sssp"] = {"workload": scfg["name"], "delta": best, "sources": len(ssrc),
+                       "ms_median": round(float(np.median(s_ms)), 4),
+                       "gteps_hmean": round(len(s_ms) / sum(ms * 1e-3 / max(m, 1) * 1e9
+                                                            for ms, m in zip(s_ms, s_edges)), 4),
+                       "delta_sweep_ms": {str(k): round(v, 4) for k, v in sweep.items()},
+                       "dtype": "f64"}
+        del SG
 
     # ------------------------------------ many-graph batch (2,000 graphs)
     log("many-graph batch leg")

@@ -133,6 +133,9 @@ def sources(n: int, src: np.ndarray, dst: np.ndarray, k: int, seed: int) -> np.n
 TC_SMALL = dict(name="rmat-s10-ef16-tc", scale=10, edge_factor=16, seed=1)
 LARGE = dict(name="rmat-s20-ef16-tc+dobfs64", scale=20, edge_factor=16, seed=2, bfs_sources=64)
 BC = dict(name="rmat-s18-ef16-bc4x64", scale=18, edge_factor=16, seed=3, batches=4, batch_size=64)
+# delta-stepping SSSP on the LARGE graph with symmetric integer weights 1..255
+SSSP = dict(name="rmat-s20-ef16-sssp8-w1..255", weight_seed=20, wmax=255, sources=8, source_seed=21,
+            deltas=(16.0, 32.0, 64.0, 128.0))
 MANY = dict(name="rmat-2000-graphs-s8..16", count=2000, base=4 << 32)
 SERVE = dict(name="serve-32-graphs-s12..22", count=32, base=5 << 32, rate=5000.0,
              mix=(0.3, 0.5, 0.2), bc_sources=8, budget_bytes=64 << 30, stream_seed=55)

@@ -356,6 +356,21 @@ int lagr_bfs(lagr_vector *level, lagr_vector *parent, const lagr_graph G, int64_
 int lagr_bc(lagr_vector *centrality, const lagr_graph G, const int64_t *sources, int32_t ns,
             lagr_ctx ctx, char *msg);
 
+/* Single-source shortest paths by delta-stepping (Section IV-E, Algorithm
+ * 5) over the min.plus semiring.  G->A must be LAGR_FP64: A(u, v) is the
+ * weight of the edge u -> v (rows are out-edges; any graph kind), and every
+ * weight must be positive and finite (Algorithm 5's split into light edges,
+ * 0 < w <= delta, and heavy edges, w > delta, has no place for others):
+ * LAGR_DOMAIN_MISMATCH for another type, LAGR_INVALID_VALUE for a bad
+ * weight or a delta that is not positive and finite, LAGR_INVALID_INDEX
+ * for a source outside [0, n).  Output: dist, a new FP64 FULL vector of
+ * shortest-path lengths (0 at the source, +inf where unreachable).  Each
+ * distance is the minimum over the relaxations made of dist(u) + w(u, v)
+ * with the final dist(u) among them, so it equals Dijkstra's result bit for
+ * bit for any positive weights. */
+int lagr_sssp(lagr_vector *dist, const lagr_graph G, int64_t source, double delta, lagr_ctx ctx,
+              char *msg);
+
 /* ------------------------------------------------- many-graph batching */
 
 /* Triangle counts of many independent graphs in one launch (an extension

@@ -133,21 +133,17 @@ __global__ __launch_bounds__(256) void k_bfs_push(BfsDev *dp, int par)
 }
 
 // The frontier's hub vertices: every chunk of a long row whose vertex is in
-// the frontier bitmap is pushed by its own wave.
+// the frontier bitmap is pushed by a whole wave.
 __global__ __launch_bounds__(256) void k_bfs_push_chunks(BfsDev *dp, int par)
 {
     const BfsDev &d = *dp;
     if (d.done || d.pull) return;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const unsigned lane = lane_id();
-    const uint32_t *cur_bm = d.bm[par];
+    const int32_t lev = d.lev;
     uint32_t *next_bm = d.bm[par ^ 1];
-    for (int64_t c = wave; c < d.ch.n; c += nw) {
-        const int32_t u = d.ch.row[c];
-        if (!bit_test(cur_bm, u)) continue;
-        push_range(d, u, d.ch.beg[c], d.ch.end[c], lane, d.lev, next_bm);
-    }
+    for_marked_chunks(d.ch, d.bm[par], [&](int32_t u, int64_t b, int64_t e) {
+        push_range(d, u, b, e, lane, lev, next_bm);
+    });
 }
 
 // Pull: one lane per unvisited vertex scans its neighbours in ascending

@@ -107,6 +107,7 @@ extern "C" int lagr_ctx_free(lagr_ctx *ctx)
     lagr_ctx c = *ctx;
     if (c->device >= 0) (void)hipStreamSynchronize(c->stream);
     if (c->bfs_exec) (void)hipGraphExecDestroy(c->bfs_exec);
+    if (c->sssp_exec) (void)hipGraphExecDestroy(c->sssp_exec);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     timers_clear(c);
     for (int s = 0; s < WS_NSLOTS; s++) dev_free(c->ws[s], c->ws_bytes[s]);

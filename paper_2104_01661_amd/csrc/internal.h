@@ -88,6 +88,7 @@ enum WsSlot {
     WS_GEN_H,
     WS_TC,            // triangle counting
     WS_TC_WORK,
+    WS_SSSP,          // SSSP device state
     WS_CHUNK_A,       // long-row chunk lists
     WS_CHUNK_B,
     WS_NSLOTS
@@ -114,6 +115,10 @@ struct lagr_ctx_s {
     hipGraphExec_t bfs_exec = nullptr;
     int64_t bfs_key = -1;
     void *bfs_state = nullptr;
+    // SSSP: captured two-step graph, keyed the same way
+    hipGraphExec_t sssp_exec = nullptr;
+    int64_t sssp_key = -1;
+    void *sssp_state = nullptr;
     hipStream_t capture_stream = nullptr;
 };
 
@@ -256,6 +261,34 @@ static inline unsigned grid_for(int64_t work, int block, int64_t cap = 1 << 20)
 __device__ __forceinline__ unsigned lane_id()
 {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// Chunks of the rows whose vertex is set in bitmap bm, for a kernel whose
+// wavefronts share the chunk list: each lane tests one chunk (64 tests in
+// flight per wave instead of one dependent test per chunk), and chunk
+// indices interleave across wavefronts (lane l of wave w tests chunk
+// w + (l + 64 k) nw), so the consecutive chunks of one hub row spread over
+// many wavefronts.  body(u, beg, end) runs with the whole wave for each
+// hit.
+template <typename Body>
+__device__ __forceinline__ void for_marked_chunks(const RowChunks &ch, const uint32_t *__restrict__ bm,
+                                                  Body body)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t k0 = 0; wave + k0 * nw < ch.n; k0 += 64) {
+        const int64_t c = wave + (k0 + lane) * nw;
+        bool hit = false;
+        if (c < ch.n) {
+            const int32_t u = ch.row[c];
+            hit = (bm[u >> 5] >> (u & 31)) & 1u;
+        }
+        for (uint64_t m = __ballot(hit); m; m &= m - 1) {
+            const int64_t cc = wave + (k0 + (int64_t)__ffsll((unsigned long long)m) - 1) * nw;
+            body(ch.row[cc], ch.beg[cc], ch.end[cc]);
+        }
+    }
 }
 
 // For entries in row order, one per lane: the lanes of the wave whose key

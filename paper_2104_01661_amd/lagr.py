@@ -107,6 +107,7 @@ _PROTOS = {
     "lagr_tc_adv": [_P, _P, _P, _C],
     "lagr_bfs": [_PP, _PP, _P, _I64, _U32, _P, _C],
     "lagr_bc": [_PP, _P, _P, _I32, _P, _C],
+    "lagr_sssp": [_PP, _P, _I64, ctypes.c_double, _P, _C],
 }
 
 _fns = {}
@@ -434,6 +435,12 @@ def lagr_bfs(G: Graph, source: int, ctx: Context, flags: int = 0, want_level=Tru
     call("lagr_bfs", ctypes.byref(lv) if want_level else None,
          ctypes.byref(pv) if want_parent else None, G.h, source, flags, ctx.h)
     return (Vector(lv) if want_level else None), (Vector(pv) if want_parent else None)
+
+
+def lagr_sssp(G: Graph, source: int, delta: float, ctx: Context) -> Vector:
+    out = ctypes.c_void_p()
+    call("lagr_sssp", ctypes.byref(out), G.h, int(source), float(delta), ctx.h)
+    return Vector(out)
 
 
 def lagr_bc(G: Graph, sources, ctx: Context) -> Vector:
