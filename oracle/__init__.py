@@ -5,7 +5,8 @@ paper (LAGraph, arXiv 2104.01661): triangle counting (Section IV-E,
 Algorithm 6), breadth-first search (Section IV-A, Algorithms 1-2), Brandes
 betweenness centrality (Section IV-B, Algorithm 3), and the shortest-path
 distances of delta-stepping (Section IV-D, Algorithm 5) by Dijkstra's
-algorithm in ``oracle.c``, and the
+algorithm, and directed graphs (the transpose property AT, BFS parents
+and Brandes over in-edges) in ``oracle.c``, and the
 GraphBLAS masked-product / accumulate / reduce semantics of Section III
 (Table I, Table II, "Masks") as a dense brute-force reference in
 ``semantics.py``.
@@ -63,6 +64,12 @@ def _load():
         lib.orc_brandes.argtypes = [_I, _P, _P, _I, _P, _P]
         lib.orc_dijkstra.restype = ctypes.c_int
         lib.orc_dijkstra.argtypes = [_I, _P, _P, _P, _I, _P]
+        lib.orc_build_directed.restype = _I
+        lib.orc_build_directed.argtypes = [_I, _I, _P, _P, _P, _P]
+        lib.orc_transpose.restype = ctypes.c_int
+        lib.orc_transpose.argtypes = [_I, _I, _P, _P, _P, _P, _P]
+        lib.orc_brandes_directed.restype = ctypes.c_int
+        lib.orc_brandes_directed.argtypes = [_I, _P, _P, _P, _P, _I, _P, _P]
         _lib = lib
     return _lib
 
@@ -149,6 +156,55 @@ def brandes(rowptr, colidx, sources):
     srcs, ps = _c(sources, np.int64)
     out = np.empty(rowptr.size - 1, dtype=np.float64)
     rc = _load().orc_brandes(rowptr.size - 1, pr, pc, srcs.size, ps, out.ctypes.data)
+    if rc == -2:
+        raise OverflowError("oracle: a shortest-path count reached 2^53")
+    if rc != 0:
+        raise MemoryError("oracle: brandes failed")
+    return out
+
+
+def build_directed(n: int, src, dst):
+    """Directed adjacency from raw edge draws: (src[e], dst[e]) is the edge
+    src -> dst; no self-loops, rows sorted, duplicates removed."""
+    src, ps = _c(src, np.int32)
+    dst, pd = _c(dst, np.int32)
+    rowptr = np.empty(n + 1, dtype=np.int64)
+    colidx = np.empty(max(src.size, 1), dtype=np.int32)
+    nnz = _load().orc_build_directed(n, src.size, ps, pd, rowptr.ctypes.data, colidx.ctypes.data)
+    if nnz < 0:
+        raise MemoryError("oracle: graph build failed")
+    return rowptr, colidx[:nnz].copy()
+
+
+def transpose(rowptr, colidx, ncols=None, values=None):
+    """Transpose of a CSR (rows sorted) -> (rowptr, colidx) or, with values,
+    (rowptr, colidx, values)."""
+    rowptr, pr = _c(rowptr, np.int64)
+    colidx, pc = _c(colidx, np.int32)
+    nrows = rowptr.size - 1
+    ncols = nrows if ncols is None else int(ncols)
+    rpT = np.empty(ncols + 1, dtype=np.int64)
+    ciT = np.empty(max(colidx.size, 1), dtype=np.int32)
+    perm = np.empty(max(colidx.size, 1), dtype=np.int64)
+    if _load().orc_transpose(nrows, ncols, pr, pc, rpT.ctypes.data, ciT.ctypes.data, perm.ctypes.data) != 0:
+        raise MemoryError("oracle: transpose failed")
+    ciT, perm = ciT[:colidx.size].copy(), perm[:colidx.size]
+    if values is None:
+        return rpT, ciT
+    return rpT, ciT, np.asarray(values)[perm]
+
+
+def brandes_directed(rowptr, colidx, sources):
+    """Unnormalised betweenness of a directed graph summed over `sources`:
+    paths follow out-edges, the backward sweep reads in-edges (FP64)."""
+    rowptr, pr = _c(rowptr, np.int64)
+    colidx, pc = _c(colidx, np.int32)
+    rpT, ciT = transpose(rowptr, colidx)
+    rpT, prT = _c(rpT, np.int64)
+    ciT, pcT = _c(ciT, np.int32)
+    srcs, ps = _c(sources, np.int64)
+    out = np.empty(rowptr.size - 1, dtype=np.float64)
+    rc = _load().orc_brandes_directed(rowptr.size - 1, pr, pc, prT, pcT, srcs.size, ps, out.ctypes.data)
     if rc == -2:
         raise OverflowError("oracle: a shortest-path count reached 2^53")
     if rc != 0:

@@ -9,6 +9,7 @@ import pytest
 import scipy.sparse as sp
 import scipy.sparse.csgraph as csg
 
+import graphgen
 import oracle
 import graphs as G
 
@@ -339,3 +340,126 @@ def test_sssp_rmat_against_scipy_dijkstra():
     for src in graphgen.sources(n, s, d, 4, 21):
         want = csg.dijkstra(M, directed=True, indices=int(src))
         assert np.array_equal(oracle.dijkstra(rp, ci, w, int(src)), want)
+
+
+# ------------------------------------------------------ directed graphs
+# A(u, v) is the edge u -> v (Section II, LAGRAPH_ADJACENCY_DIRECTED); pull
+# steps and the BC predecessor sweep read in-edges, the rows of AT.
+
+def _digraph(scale, ef, seed):
+    n, s, d = graphgen.rmat_edges(scale, ef, seed)
+    rp, ci = oracle.build_directed(n, s, d)
+    return n, s, d, rp, ci
+
+
+def _dense(n, rp, ci, vals=None):
+    M = np.zeros((n, n))
+    for u in range(n):
+        M[u, ci[rp[u]:rp[u + 1]]] = 1.0 if vals is None else vals[rp[u]:rp[u + 1]]
+    return M
+
+
+def test_build_directed_is_the_set_of_draws():
+    n, s, d = graphgen.rmat_edges(8, 8, 61)
+    rp, ci = oracle.build_directed(n, s, d)
+    want = sorted(set((int(a), int(b)) for a, b in zip(s, d) if a != b))
+    got = [(u, int(v)) for u in range(n) for v in ci[rp[u]:rp[u + 1]]]
+    assert got == want
+
+
+def test_transpose_is_the_dense_transpose():
+    for seed in (71, 72, 73):
+        n, _, _, rp, ci = _digraph(7, 6, seed)
+        w = np.arange(1, ci.size + 1, dtype=np.float64)
+        rpT, ciT, wT = oracle.transpose(rp, ci, values=w)
+        assert np.array_equal(_dense(n, rpT, ciT, wT), _dense(n, rp, ci, w).T)
+        assert all(np.all(np.diff(ciT[rpT[u]:rpT[u + 1]]) > 0) for u in range(n))
+        r2, c2 = oracle.transpose(rpT, ciT)
+        assert np.array_equal(r2, rp) and np.array_equal(c2, ci)
+    rpT, ciT = oracle.transpose(np.array([0, 2, 3]), np.array([1, 4, 0], np.int32), ncols=5)
+    assert rpT.tolist() == [0, 1, 2, 2, 2, 3] and ciT.tolist() == [1, 0, 0]
+
+
+def test_directed_bfs_levels_and_in_neighbour_parents():
+    n, s, d, rp, ci = _digraph(7, 8, 75)
+    D = _dense(n, rp, ci) > 0
+    rpT, ciT = oracle.transpose(rp, ci)
+    for src in graphgen.sources(n, s, d, 4, 3):
+        src = int(src)
+        level, _ = oracle.bfs(rp, ci, src)
+        # levels: first k with v in the k-step reach set (boolean powers of A)
+        want = np.full(n, -1)
+        reach = np.zeros(n, bool)
+        reach[src] = True
+        want[src] = 0
+        k = 0
+        while True:
+            k += 1
+            nxt = (reach[:, None] & D).any(axis=0) & ~reach
+            if not nxt.any():
+                break
+            want[nxt] = k
+            reach |= nxt
+        assert np.array_equal(level, want)
+        par = oracle.bfs_min_parent(rpT, ciT, src, level)
+        assert par[src] == src
+        for v in range(n):
+            if v == src:
+                continue
+            cands = [u for u in range(n) if D[u, v] and level[v] > 0 and level[u] == level[v] - 1]
+            assert par[v] == (min(cands) if cands else -1), v
+
+
+def _bc_by_definition(n, rp, ci, sources):
+    """Sum over s in sources, t != s, v not in {s, t} of sigma_st(v) /
+    sigma_st, from exact all-pairs shortest-path counts."""
+    from fractions import Fraction
+    dist = [[-1] * n for _ in range(n)]
+    sig = [[0] * n for _ in range(n)]
+    for a in range(n):
+        dist[a][a], sig[a][a] = 0, 1
+        frontier = [a]
+        while frontier:
+            nxt = []
+            for u in frontier:
+                for v in ci[rp[u]:rp[u + 1]]:
+                    v = int(v)
+                    if dist[a][v] < 0:
+                        dist[a][v] = dist[a][u] + 1
+                        nxt.append(v)
+                    if dist[a][v] == dist[a][u] + 1:
+                        sig[a][v] += sig[a][u]
+            frontier = nxt
+    bc = [Fraction(0)] * n
+    for s_ in sources:
+        for t in range(n):
+            if t == s_ or dist[s_][t] < 0:
+                continue
+            for v in range(n):
+                if v in (s_, t) or dist[s_][v] < 0 or dist[v][t] < 0:
+                    continue
+                if dist[s_][v] + dist[v][t] == dist[s_][t]:
+                    bc[v] += Fraction(sig[s_][v] * sig[v][t], sig[s_][t])
+    return np.array([float(x) for x in bc])
+
+
+@pytest.mark.parametrize("scale,ef,seed", [(4, 6, 81), (5, 4, 82), (5, 8, 83)])
+def test_brandes_directed_matches_the_definition(scale, ef, seed):
+    n, _, _, rp, ci = _digraph(scale, ef, seed)
+    srcs = np.arange(n)
+    got = oracle.brandes_directed(rp, ci, srcs)
+    want = _bc_by_definition(n, rp, ci, srcs)
+    assert np.allclose(got, want, rtol=1e-12, atol=0) and np.array_equal(got == 0, want == 0)
+
+
+def test_brandes_directed_closed_forms_and_symmetric_case():
+    n = 9
+    rp, ci = oracle.build_directed(n, np.arange(n - 1), np.arange(1, n))       # path 0 -> ... -> 8
+    k = np.arange(n)
+    assert np.array_equal(oracle.brandes_directed(rp, ci, k), (k * (n - 1 - k)).astype(np.float64))
+    rp, ci = oracle.build_directed(n, np.arange(n), (np.arange(n) + 1) % n)    # directed cycle
+    assert np.array_equal(oracle.brandes_directed(rp, ci, k), np.full(n, (n - 1) * (n - 2) / 2))
+    n, s, d = graphgen.rmat_edges(8, 8, 84)
+    rp, ci = oracle.build_adjacency(n, s, d)                                  # symmetric: A = AT
+    srcs = graphgen.sources(n, s, d, 16, 5)
+    assert np.allclose(oracle.brandes_directed(rp, ci, srcs), oracle.brandes(rp, ci, srcs), rtol=1e-12, atol=0)
