@@ -312,6 +312,12 @@ int lagr_property_row_degree(lagr_graph G, lagr_ctx ctx, char *msg);
 /* The triangle-count operand: A relabelled by descending degree and its
  * strictly lower part (Algorithm 6, the degree sort and L = tril(A)). */
 int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg);
+/* Cached transpose AT of a directed graph's adjacency matrix (Section II,
+ * the AT property that pull steps need: row v of AT lists the in-edges of
+ * v, with their values).  A no-op for an undirected graph, whose A is its
+ * own transpose.  lagr_bfs and lagr_bc compute it on first use for a
+ * directed graph; lagr_graph_delete_properties frees it. */
+int lagr_property_at(lagr_graph G, lagr_ctx ctx, char *msg);
 /* Drop the cached property arrays -- row degree and the triangle-count
  * operand (Section V, DeleteProperties).  The results of lagr_graph_check
  * (ndiag, symmetry) describe A, which a graph never changes, and are kept. */
@@ -320,6 +326,9 @@ int lagr_graph_delete_properties(lagr_graph G, lagr_ctx ctx, char *msg);
  * (NULL if not computed).  The handles stay owned by G: do not free them. */
 int lagr_graph_matrix(lagr_matrix *A, const lagr_graph G, char *msg);
 int lagr_graph_tc_lower(lagr_matrix *L, const lagr_graph G, char *msg);
+/* Borrowed handle of AT (G's own A for an undirected graph);
+ * LAGR_PROPERTY_MISSING for a directed graph before lagr_property_at. */
+int lagr_graph_at(lagr_matrix *AT, const lagr_graph G, char *msg);
 int lagr_graph_ndiag(int64_t *ndiag, const lagr_graph G, char *msg);
 int lagr_graph_free(lagr_graph *G);
 
@@ -342,7 +351,10 @@ int lagr_tc_adv(int64_t *ntriangles, const lagr_graph G, lagr_ctx ctx, char *msg
  * frontier list, or pull over unvisited vertices with a frontier bitmap
  * when the frontier's edges outweigh the unexplored ones (Beamer's
  * heuristic).  Parents are the smallest valid parent unless
- * LAGR_BFS_ANY_PARENT allows any valid one. */
+ * LAGR_BFS_ANY_PARENT allows any valid one.  On a directed graph the search
+ * follows out-edges (A(u, v) is u -> v) and the parent of v is an
+ * in-neighbour; pull steps read AT, which is computed and cached on first
+ * use unless LAGR_BFS_PUSH_ONLY is given. */
 #define LAGR_BFS_PUSH_ONLY 1u
 #define LAGR_BFS_ANY_PARENT 2u
 int lagr_bfs(lagr_vector *level, lagr_vector *parent, const lagr_graph G, int64_t source,
@@ -352,7 +364,9 @@ int lagr_bfs(lagr_vector *level, lagr_vector *parent, const lagr_graph G, int64_
  * sum over the given sources of the dependency of every vertex, where a
  * source contributes nothing to itself.  `sources` is a HOST int64 array;
  * they are processed in batches of 64 (one source per wavefront lane) and
- * the batches are summed in order.  Output: FP64 FULL vector. */
+ * the batches are summed in order.  Output: FP64 FULL vector.  On a directed
+ * graph shortest paths follow out-edges; pull steps read AT, which is
+ * computed and cached on first use. */
 int lagr_bc(lagr_vector *centrality, const lagr_graph G, const int64_t *sources, int32_t ns,
             lagr_ctx ctx, char *msg);
 

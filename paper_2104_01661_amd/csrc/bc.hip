@@ -221,12 +221,13 @@ __global__ __launch_bounds__(256) void k_bc_push_chunks(const int32_t *__restric
 }
 
 // After a level: unvis &= ~next; the vertices with a new mask form the next
-// frontier list and those with unreached lanes (and neighbours) the active
-// list; cnt[0..3] += frontier size, its degree sum, active size, its degree
-// sum.  Workgroup g owns the g-th contiguous share of the vertices: it
+// frontier list and those with unreached lanes and in-edges (rows of rpT,
+// the pull side) the active list; cnt[0..3] += frontier size, its
+// out-degree sum (rp), active size, its in-degree sum.  Workgroup g owns the g-th contiguous share of the vertices: it
 // counts, reserves its ranges with one atomic per counter and writes its
 // vertices in ascending order.
-__global__ __launch_bounds__(256) void k_bc_compact(const int64_t *__restrict__ rp, int64_t n,
+__global__ __launch_bounds__(256) void k_bc_compact(const int64_t *__restrict__ rp,
+                                                    const int64_t *__restrict__ rpT, int64_t n,
                                                     const uint64_t *__restrict__ next, uint64_t *__restrict__ unvis,
                                                     int32_t *__restrict__ flist, int32_t *__restrict__ alist,
                                                     unsigned long long *__restrict__ cnt)
@@ -244,14 +245,14 @@ __global__ __launch_bounds__(256) void k_bc_compact(const int64_t *__restrict__ 
             uv &= ~nm;
             unvis[v] = uv;
         }
-        const int64_t deg = rp[v + 1] - rp[v];
+        const int64_t deg = rp[v + 1] - rp[v], din = rpT[v + 1] - rpT[v];
         if (nm) {
             cf++;
             ef += (unsigned long long)deg;
         }
-        if (uv && deg) {
+        if (uv && din) {
             ca++;
-            ea += (unsigned long long)deg;
+            ea += (unsigned long long)din;
         }
     }
     sf[threadIdx.x] = cf;
@@ -286,9 +287,8 @@ __global__ __launch_bounds__(256) void k_bc_compact(const int64_t *__restrict__ 
     unsigned long long pf = base_f + sf[threadIdx.x] - cf, pa = base_a + sa[threadIdx.x] - ca;
     for (int64_t v = v0 + threadIdx.x; v < v1; v += 256) {
         const uint64_t nm = next[v], uv = unvis[v];
-        const int64_t deg = rp[v + 1] - rp[v];
         if (nm) flist[pf++] = (int32_t)v;
-        if (uv && deg) alist[pa++] = (int32_t)v;
+        if (uv && rpT[v + 1] > rpT[v]) alist[pa++] = (int32_t)v;
     }
 }
 
@@ -661,14 +661,21 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
     } while (0)
 
     BC_TRY(fill_i64(ctx, (int64_t *)cent, n * groups, 0, msg));   // 0.0 has all-zero bits
-    RowChunks ch;
+    // push and the backward sweep read out-edges (A); pull reads in-edges
+    // (AT, which is A itself for an undirected graph)
+    const lagr_matrix AT = graph_in_edges(G);
+    if (!AT) BC_TRY(lagr_fail(msg, LAGR_PROPERTY_MISSING, "the transpose of a directed graph is missing"));
+    RowChunks ch, chT;
     BC_TRY(graph_chunks(G, ctx, &ch, msg));
+    BC_TRY(graph_chunks_in(G, ctx, &chT, msg));
     double *partial = nullptr;
-    unsigned cblocks = 1;
-    if (ch.n > 0) {
-        partial = (double *)ws_get(ctx, WS_BC_MASKS, sizeof(double) * 64 * (size_t)ch.n);
+    unsigned cblocks = 1, cblocksT = 1;
+    if (ch.n > 0 || chT.n > 0) {
+        const int64_t most = ch.n > chT.n ? ch.n : chT.n;
+        partial = (double *)ws_get(ctx, WS_BC_MASKS, sizeof(double) * 64 * (size_t)most);
         if (!partial) BC_TRY(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc chunk partials"));
         cblocks = grid_for(ch.n * 64, 256, 16384);
+        cblocksT = grid_for(chT.n * 64, 256, 16384);
     }
     const unsigned compact_blocks = (unsigned)(n > 0 ? (ctx->num_cus < n ? ctx->num_cus : n) : 1);
     int32_t *act_cur = acts, *act_next = acts + n1;
@@ -678,7 +685,7 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
     auto compact = [&](const uint64_t *next, int32_t *flist) -> int {
         TRY(fill_i64(ctx, (int64_t *)cnt, 4, 0, msg));
         if (n > 0) {
-            hipLaunchKernelGGL(k_bc_compact, dim3(compact_blocks), dim3(256), 0, ctx->stream, A->rowptr, n, next,
+            hipLaunchKernelGGL(k_bc_compact, dim3(compact_blocks), dim3(256), 0, ctx->stream, A->rowptr, AT->rowptr, n, next,
                                unvis, flist, act_next, cnt);
             LAUNCH_CHECK();
         }
@@ -729,16 +736,16 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
                 }
             } else if (na > 0) {
                 TIMED(ctx, "bc_forward",
-                      hipLaunchKernelGGL(k_bc_pull, dim3(wgrid(na)), dim3(256), 0, ctx->stream, A->rowptr,
-                                         A->colidx, act_cur, na, levels(depth), next, unvis, sigma));
+                      hipLaunchKernelGGL(k_bc_pull, dim3(wgrid(na)), dim3(256), 0, ctx->stream, AT->rowptr,
+                                         AT->colidx, act_cur, na, levels(depth), next, unvis, sigma));
                 BC_LAUNCHED();
-                if (ch.n > 0) {
+                if (chT.n > 0) {
                     TIMED(ctx, "bc_forward_chunks",
-                          hipLaunchKernelGGL(k_bc_forward_chunks, dim3(cblocks), dim3(256), 0, ctx->stream,
-                                             A->colidx, ch, levels(depth), unvis, sigma, partial));
+                          hipLaunchKernelGGL(k_bc_forward_chunks, dim3(cblocksT), dim3(256), 0, ctx->stream,
+                                             AT->colidx, chT, levels(depth), unvis, sigma, partial));
                     BC_LAUNCHED();
-                    hipLaunchKernelGGL(k_bc_forward_combine, dim3(cblocks), dim3(256), 0, ctx->stream,
-                                       A->rowptr, ch, partial, next, unvis, sigma);
+                    hipLaunchKernelGGL(k_bc_forward_combine, dim3(cblocksT), dim3(256), 0, ctx->stream,
+                                       AT->rowptr, chT, partial, next, unvis, sigma);
                     BC_LAUNCHED();
                 }
             }
@@ -824,7 +831,7 @@ int msbfs_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, uin
     auto compact = [&](const uint64_t *next, int32_t *flist) -> int {
         TRY(fill_i64(ctx, (int64_t *)cnt, 4, 0, msg));
         if (n > 0) {
-            hipLaunchKernelGGL(k_bc_compact, dim3(compact_blocks), dim3(256), 0, ctx->stream, A->rowptr, n, next,
+            hipLaunchKernelGGL(k_bc_compact, dim3(compact_blocks), dim3(256), 0, ctx->stream, A->rowptr, A->rowptr, n, next,
                                unvis, flist, act_next, cnt);
             LAUNCH_CHECK();
         }
@@ -885,12 +892,12 @@ extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const in
     if (!centrality_out || !G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
     *centrality_out = nullptr;
     if (ns < 0 || (ns > 0 && !sources)) return lagr_fail(msg, LAGR_INVALID_VALUE, "bad sources");
-    if (G->kind != LAGR_ADJACENCY_UNDIRECTED)
-        return lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "BC needs an undirected graph (A = A^T)");
     const int64_t n = G->A->nrows;
     for (int32_t k = 0; k < ns; k++)
         if (sources[k] < 0 || sources[k] >= n)
             return lagr_fail(msg, LAGR_INVALID_INDEX, "source %lld out of range", (long long)sources[k]);
+    // pull steps of a directed graph read its transpose
+    TRY(graph_ensure_at(G, ctx, msg));
     // one source per lane, batches of 64 summed in order
     const int nbatches = (ns + 63) / 64;
     std::vector<int64_t> lane_src((size_t)64 * (nbatches > 0 ? nbatches : 1), -1);

@@ -6,8 +6,9 @@
 // frontier bitmap in the same pass.
 //   push: a wavefront per frontier vertex u scans N(u) with coalesced loads
 //         (hub rows, longer than GRAPH_LONG_ROW, chunk by chunk);
-//   pull: one lane per unvisited vertex v scans N(v) in ascending order
-//         and stops at the first neighbour in the frontier bitmap.
+//   pull: one lane per unvisited vertex v scans its in-neighbours (row v
+//         of AT; of A itself for an undirected graph) in ascending order
+//         and stops at the first one in the frontier bitmap.
 // A compaction pass then lists the next frontier, counts it and its degree
 // sum and adds it to the visited set.  The level loop runs on the device:
 // a one-thread kernel folds the counters into the level state and picks
@@ -35,8 +36,10 @@ __device__ __forceinline__ bool bit_test(const uint32_t *bm, int64_t v)
 // struct before each search).  Buffers [par] hold the current frontier,
 // [par ^ 1] the next one.
 struct BfsDev {
-    const int64_t *rp;
+    const int64_t *rp;        // out-edges (push)
     const int32_t *ci;
+    const int64_t *rpT;       // in-edges (pull): AT, or A when undirected
+    const int32_t *ciT;
     int64_t n, W;
     int32_t *level;
     unsigned long long *parent;
@@ -146,9 +149,9 @@ __global__ __launch_bounds__(256) void k_bfs_push_chunks(BfsDev *dp, int par)
     });
 }
 
-// Pull: one lane per unvisited vertex scans its neighbours in ascending
-// order and stops at the first one in the frontier bitmap, the smallest
-// valid parent.  Neighbours are taken PULL_BATCH at a time (independent
+// Pull: one lane per unvisited vertex scans its in-neighbours (row v of AT)
+// in ascending order and stops at the first one in the frontier bitmap,
+// the smallest valid parent.  Neighbours are taken PULL_BATCH at a time (independent
 // loads, then independent bitmap probes) so a lane waits for two round
 // trips per batch rather than two per neighbour.
 constexpr int PULL_BATCH = 8;
@@ -168,11 +171,11 @@ __global__ __launch_bounds__(256) void k_bfs_pull(BfsDev *dp, int par)
         const int64_t v = v0 + threadIdx.x;
         int32_t par_v = -1;
         if (v < n && !bit_test(d.visited, v)) {
-            const int64_t b = d.rp[v], e = d.rp[v + 1];
+            const int64_t b = d.rpT[v], e = d.rpT[v + 1];
             for (int64_t p0 = b; p0 < e && par_v < 0; p0 += PULL_BATCH) {
                 int32_t u[PULL_BATCH];
 #pragma unroll
-                for (int t = 0; t < PULL_BATCH; t++) u[t] = p0 + t < e ? d.ci[p0 + t] : -1;
+                for (int t = 0; t < PULL_BATCH; t++) u[t] = p0 + t < e ? d.ciT[p0 + t] : -1;
 #pragma unroll
                 for (int t = PULL_BATCH - 1; t >= 0; t--)
                     if (u[t] >= 0 && bit_test(cur_bm, u[t])) par_v = u[t];
@@ -315,9 +318,9 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
     const int64_t n = A->nrows;
     if (source < 0 || source >= n)
         return lagr_fail(msg, LAGR_INVALID_INDEX, "source %lld out of range", (long long)source);
-    if (G->kind != LAGR_ADJACENCY_UNDIRECTED && !(flags & LAGR_BFS_PUSH_ONLY))
-        return lagr_fail(msg, LAGR_NOT_IMPLEMENTED,
-                         "pull steps on a directed graph need its transpose; use LAGR_BFS_PUSH_ONLY");
+    // pull steps read in-edges: a directed graph needs its transpose
+    if (!(flags & LAGR_BFS_PUSH_ONLY)) TRY(graph_ensure_at(G, ctx, msg));
+    const lagr_matrix AT = (flags & LAGR_BFS_PUSH_ONLY) ? A : graph_in_edges(G);
     const int64_t W = (n + 31) / 32;
     int32_t *lev32 = (int32_t *)ws_get(ctx, WS_BFS_A, sizeof(int32_t) * n);
     int32_t *lists = (int32_t *)ws_get(ctx, WS_BFS_B, sizeof(int32_t) * 2 * n);
@@ -352,6 +355,8 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
     BfsDev h{};
     h.rp = A->rowptr;
     h.ci = A->colidx;
+    h.rpT = AT->rowptr;
+    h.ciT = AT->colidx;
     h.n = n;
     h.W = W;
     h.level = lev32;

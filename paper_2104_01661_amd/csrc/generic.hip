@@ -1006,6 +1006,37 @@ int check_semiring(lagr_semiring s, char *msg)
 
 }  // namespace
 
+int matrix_transpose(lagr_ctx ctx, const lagr_matrix A, lagr_matrix *out, char *msg)
+{
+    *out = nullptr;
+    Pool pool;
+    Csr T;
+    TRY(transpose(ctx, view(A), pool, &T, msg));
+    lagr_matrix M = new (std::nothrow) lagr_matrix_s();
+    if (!M) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "matrix");
+    M->type = A->type;
+    M->nrows = A->ncols;
+    M->ncols = A->nrows;
+    M->nvals = A->nvals;
+    M->rowptr = (int64_t *)T.rp;
+    M->colidx = (int32_t *)T.ci;
+    M->values = (void *)T.val;
+    M->rowptr_bytes = sizeof(int64_t) * (size_t)(M->nrows + 1);
+    M->colidx_bytes = sizeof(int32_t) * (size_t)(M->nvals > 0 ? M->nvals : 1);
+    M->values_bytes = T.val ? 8 * (size_t)(M->nvals > 0 ? M->nvals : 1) : 0;
+    pool.release((void *)T.rp);
+    pool.release((void *)T.ci);
+    if (T.val) pool.release((void *)T.val);
+    // the pool frees the sort keys when it goes: finish using them first
+    const hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        lagr_matrix_free(&M);
+        return lagr_fail(msg, LAGR_DEVICE_ERROR, "transpose: %s", hipGetErrorString(e));
+    }
+    *out = M;
+    return LAGR_SUCCESS;
+}
+
 // =================================================================== API
 
 extern "C" int lagr_mxm(lagr_matrix C, const lagr_matrix M, lagr_binop accum, lagr_semiring semiring,

@@ -699,12 +699,12 @@ extern "C" int lagr_graph_matrix(lagr_matrix *A, const lagr_graph G, char *msg)
     return lagr_ok(msg);
 }
 
-int graph_chunks(lagr_graph G, lagr_ctx ctx, RowChunks *out, char *msg)
+static int cached_chunks(ChunkCache &cc, const lagr_matrix M, lagr_ctx ctx, RowChunks *out, char *msg)
 {
-    if (G->nchunks < 0) {
+    if (cc.n < 0) {
         RowChunks tmp;
-        TRY(row_chunks(ctx, G->A->rowptr, G->A->nrows, GRAPH_LONG_ROW, GRAPH_LONG_ROW, WS_CHUNK_A,
-                       WS_CHUNK_B, &tmp, msg));
+        TRY(row_chunks(ctx, M->rowptr, M->nrows, GRAPH_LONG_ROW, GRAPH_LONG_ROW, WS_CHUNK_A, WS_CHUNK_B, &tmp,
+                       msg));
         const size_t nc = (size_t)(tmp.n > 0 ? tmp.n : 1);
         int32_t *row = (int32_t *)dev_alloc(nc * 4);
         int64_t *beg = (int64_t *)dev_alloc(nc * 8);
@@ -720,16 +720,60 @@ int graph_chunks(lagr_graph G, lagr_ctx ctx, RowChunks *out, char *msg)
             HIP_TRY(hipMemcpyAsync(beg, tmp.beg, nc * 8, hipMemcpyDeviceToDevice, ctx->stream));
             HIP_TRY(hipMemcpyAsync(end, tmp.end, nc * 8, hipMemcpyDeviceToDevice, ctx->stream));
         }
-        G->chunk_row = row;
-        G->chunk_beg = beg;
-        G->chunk_end = end;
-        G->nchunks = tmp.n;
+        cc.row = row;
+        cc.beg = beg;
+        cc.end = end;
+        cc.n = tmp.n;
     }
-    out->n = G->nchunks;
-    out->row = G->chunk_row;
-    out->beg = G->chunk_beg;
-    out->end = G->chunk_end;
+    out->n = cc.n;
+    out->row = cc.row;
+    out->beg = cc.beg;
+    out->end = cc.end;
     return LAGR_SUCCESS;
+}
+
+static void free_chunks(ChunkCache &cc)
+{
+    if (cc.n >= 0) {
+        const size_t nc = (size_t)(cc.n > 0 ? cc.n : 1);
+        dev_free(cc.row, nc * 4);
+        dev_free(cc.beg, nc * 8);
+        dev_free(cc.end, nc * 8);
+    }
+    cc = ChunkCache();
+}
+
+int graph_chunks(lagr_graph G, lagr_ctx ctx, RowChunks *out, char *msg)
+{
+    return cached_chunks(G->chunks, G->A, ctx, out, msg);
+}
+
+int graph_chunks_in(lagr_graph G, lagr_ctx ctx, RowChunks *out, char *msg)
+{
+    if (G->kind != LAGR_ADJACENCY_DIRECTED) return graph_chunks(G, ctx, out, msg);
+    if (!G->AT) return lagr_fail(msg, LAGR_PROPERTY_MISSING, "the transpose of a directed graph is missing");
+    return cached_chunks(G->chunks_t, G->AT, ctx, out, msg);
+}
+
+int graph_ensure_at(lagr_graph G, lagr_ctx ctx, char *msg)
+{
+    if (G->kind != LAGR_ADJACENCY_DIRECTED || G->AT) return LAGR_SUCCESS;
+    return matrix_transpose(ctx, G->A, &G->AT, msg);
+}
+
+extern "C" int lagr_property_at(lagr_graph G, lagr_ctx ctx, char *msg)
+{
+    if (!G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    TRY(graph_ensure_at(G, ctx, msg));
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_graph_at(lagr_matrix *AT, const lagr_graph G, char *msg)
+{
+    if (!AT || !G) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    *AT = graph_in_edges(G);
+    if (!*AT) return lagr_fail(msg, LAGR_PROPERTY_MISSING, "the transpose has not been computed");
+    return lagr_ok(msg);
 }
 
 extern "C" int lagr_graph_tc_lower(lagr_matrix *L, const lagr_graph G, char *msg)
@@ -750,6 +794,8 @@ extern "C" int lagr_graph_delete_properties(lagr_graph G, lagr_ctx ctx, char *ms
     lagr_matrix_free(&G->L);
     tc_plan_free(G);
     G->L_maxrow = -1;
+    lagr_matrix_free(&G->AT);
+    free_chunks(G->chunks_t);
     // ndiag and the symmetry flag describe A, which a graph never changes:
     // the results of lagr_graph_check stay valid and are kept
     return lagr_ok(msg);
@@ -768,13 +814,10 @@ extern "C" int lagr_graph_free(lagr_graph *G)
     lagr_graph g = *G;
     const int64_t n = g->A ? g->A->nrows : 0;
     if (g->row_degree) dev_free(g->row_degree, sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
-    if (g->nchunks >= 0) {
-        const size_t nc = (size_t)(g->nchunks > 0 ? g->nchunks : 1);
-        dev_free(g->chunk_row, nc * 4);
-        dev_free(g->chunk_beg, nc * 8);
-        dev_free(g->chunk_end, nc * 8);
-    }
+    free_chunks(g->chunks);
+    free_chunks(g->chunks_t);
     lagr_matrix_free(&g->A);
+    lagr_matrix_free(&g->AT);
     lagr_matrix_free(&g->L);
     tc_plan_free(g);
     delete g;

@@ -148,6 +148,14 @@ struct lagr_vector_s {
 
 struct TcPlan;
 
+// Owned chunk list of a matrix's long rows (n = -1: not built).
+struct ChunkCache {
+    int64_t n = -1;
+    int32_t *row = nullptr;
+    int64_t *beg = nullptr;
+    int64_t *end = nullptr;
+};
+
 struct lagr_graph_s {
     lagr_matrix A = nullptr;
     lagr_kind kind = LAGR_ADJACENCY_UNDIRECTED;
@@ -158,13 +166,21 @@ struct lagr_graph_s {
     lagr_matrix L = nullptr;        // degree-ordered strictly lower part
     int64_t L_maxrow = -1;
     // chunks of A's rows longer than GRAPH_LONG_ROW (owned arrays)
-    int64_t nchunks = -1;           // -1 not built
-    int32_t *chunk_row = nullptr;
-    int64_t *chunk_beg = nullptr;
-    int64_t *chunk_end = nullptr;
+    ChunkCache chunks;
     // min-side triangle-count plan over L (built with L, owned)
     TcPlan *tcplan = nullptr;
+    // transpose of A for a directed graph (the AT property, owned; an
+    // undirected graph uses A itself) and the chunks of its long rows
+    lagr_matrix AT = nullptr;
+    ChunkCache chunks_t;
 };
+
+// The pull side of G: AT for a directed graph (nullptr if not computed),
+// A for an undirected one.
+static inline lagr_matrix graph_in_edges(const lagr_graph G)
+{
+    return G->kind == LAGR_ADJACENCY_DIRECTED ? G->AT : G->A;
+}
 
 // Build / release G->tcplan from G->L and the row of each entry of L.
 int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, char *msg);
@@ -226,6 +242,14 @@ int row_chunks(lagr_ctx ctx, const int64_t *rowptr, int64_t nrows, int64_t min_l
                WsSlot count_slot, WsSlot list_slot, RowChunks *out, char *msg);
 // The cached chunk list of G->A (built on first use).
 int graph_chunks(lagr_graph G, lagr_ctx ctx, RowChunks *out, char *msg);
+// The cached chunk list of the pull side, graph_in_edges(G) (which must
+// exist).
+int graph_chunks_in(lagr_graph G, lagr_ctx ctx, RowChunks *out, char *msg);
+// A new matrix holding the transpose of A (values carried), owned by the
+// caller.
+int matrix_transpose(lagr_ctx ctx, const lagr_matrix A, lagr_matrix *out, char *msg);
+// Compute G->AT for a directed graph if it is missing (no-op otherwise).
+int graph_ensure_at(lagr_graph G, lagr_ctx ctx, char *msg);
 // Betweenness of 64-lane batches (lane_src: HOST, 64 per batch, -1 idle)
 // into cent: gshift 6 sums all lanes (n values), gshift 3 sums groups of 8
 // lanes (n x 8 values).

@@ -98,6 +98,8 @@ _PROTOS = {
     "lagr_graph_check": [_P, _P, _C],
     "lagr_property_row_degree": [_P, _P, _C],
     "lagr_property_tc_lower": [_P, _P, _C],
+    "lagr_property_at": [_P, _P, _C],
+    "lagr_graph_at": [_PP, _P, _C],
     "lagr_graph_matrix": [_PP, _P, _C],
     "lagr_graph_tc_lower": [_PP, _P, _C],
     "lagr_graph_delete_properties": [_P, _P, _C],
@@ -395,6 +397,13 @@ class Graph:
     def tc_lower(self):
         """Borrowed handle of the cached triangle-count operand, or None."""
         return self._borrowed("lagr_graph_tc_lower")
+
+    def property_at(self, ctx):
+        call("lagr_property_at", self.h, ctx.h)
+
+    def at(self):
+        """Borrowed handle of the transpose (A itself when undirected)."""
+        return self._borrowed("lagr_graph_at")
 
     def ndiag(self):
         v = ctypes.c_int64()
