@@ -5,8 +5,9 @@ paper (LAGraph, arXiv 2104.01661): triangle counting (Section IV-E,
 Algorithm 6), breadth-first search (Section IV-A, Algorithms 1-2), Brandes
 betweenness centrality (Section IV-B, Algorithm 3), and the shortest-path
 distances of delta-stepping (Section IV-D, Algorithm 5) by Dijkstra's
-algorithm, and directed graphs (the transpose property AT, BFS parents
-and Brandes over in-edges) in ``oracle.c``, and the
+algorithm, directed graphs (the transpose property AT, BFS parents and
+Brandes over in-edges), PageRank (Section IV-C, Algorithm 4) and connected
+components (Section IV-F, Algorithm 7) in ``oracle.c``, and the
 GraphBLAS masked-product / accumulate / reduce semantics of Section III
 (Table I, Table II, "Masks") as a dense brute-force reference in
 ``semantics.py``.
@@ -70,6 +71,10 @@ def _load():
         lib.orc_transpose.argtypes = [_I, _I, _P, _P, _P, _P, _P]
         lib.orc_brandes_directed.restype = ctypes.c_int
         lib.orc_brandes_directed.argtypes = [_I, _P, _P, _P, _P, _I, _P, _P]
+        lib.orc_pagerank.restype = _I
+        lib.orc_pagerank.argtypes = [_I, _P, _P, _P, ctypes.c_double, ctypes.c_double, _I, _P]
+        lib.orc_components.restype = ctypes.c_int
+        lib.orc_components.argtypes = [_I, _P, _P, _P, _P, _P]
         _lib = lib
     return _lib
 
@@ -210,6 +215,40 @@ def brandes_directed(rowptr, colidx, sources):
     if rc != 0:
         raise MemoryError("oracle: brandes failed")
     return out
+
+
+def pagerank(rowptr, colidx, damping=0.85, tol=1e-4, itermax=100):
+    """PageRank as Algorithm 4 (GAP) states it -> (rank float64[n],
+    iterations).  Rows of (rowptr, colidx) are out-edges."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    colidx = np.ascontiguousarray(colidx, dtype=np.int32)
+    n = rowptr.size - 1
+    rpT, ciT = transpose(rowptr, colidx)
+    rpT, prT = _c(rpT, np.int64)
+    ciT, pcT = _c(ciT, np.int32)
+    dout, pd = _c(np.diff(rowptr), np.int64)
+    r = np.empty(n, dtype=np.float64)
+    k = _load().orc_pagerank(n, prT, pcT, pd, float(damping), float(tol), int(itermax), r.ctypes.data)
+    if k < 0:
+        raise MemoryError("oracle: pagerank failed")
+    return r, int(k)
+
+
+def components(rowptr, colidx, directed=False):
+    """Label of every vertex = the smallest vertex id of its (weakly)
+    connected component (int64[n])."""
+    rowptr, pr = _c(rowptr, np.int64)
+    colidx, pc = _c(colidx, np.int32)
+    if directed:
+        rpT, ciT = transpose(rowptr, colidx)
+        rpT, prT = _c(rpT, np.int64)
+        ciT, pcT = _c(ciT, np.int32)
+    else:
+        prT, pcT = pr, pc
+    label = np.empty(rowptr.size - 1, dtype=np.int64)
+    if _load().orc_components(rowptr.size - 1, pr, pc, prT, pcT, label.ctypes.data) != 0:
+        raise MemoryError("oracle: components failed")
+    return label
 
 
 def dijkstra(rowptr, colidx, weights, source: int):

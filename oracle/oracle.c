@@ -11,6 +11,7 @@
  * orc_build makes from raw edge draws.
  */
 #include <stdint.h>
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -371,6 +372,89 @@ int orc_brandes_directed(int64_t n, const int64_t *rp, const int32_t *ci, const 
     }
     free(sigma); free(delta); free(dist); free(order);
     return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* PageRank as GAP specifies it (Section IV-C, Algorithm 4), in FP64, the
+ * steps in the listing's order:
+ *   teleport = (1 - damping) / n;  r = 1/n;  d = d_out / damping
+ *   repeat: t = r;  w = t / d (only where d_out > 0: a vertex without
+ *   out-edges sends nothing);  r = teleport;  r += AT plus.second w, i.e.
+ *   r(j) += w(i) for every edge i -> j, summed over i in ascending order;
+ *   t = |t - r|;  stop when sum(t), summed over j in ascending order, is
+ *   below tol, or after itermax iterations.
+ * rpT/ciT: the transpose (row j lists the in-neighbours i of j); dout[i]:
+ * out-degree.  Returns the number of iterations done, -1 on allocation
+ * failure.                                                                 */
+/* ---------------------------------------------------------------------- */
+
+int64_t orc_pagerank(int64_t n, const int64_t *rpT, const int32_t *ciT, const int64_t *dout, double damping,
+                     double tol, int64_t itermax, double *r)
+{
+    double *t = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *w = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *d = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!t || !w || !d) { free(t); free(w); free(d); return -1; }
+    const double teleport = (1.0 - damping) / (double)n;
+    for (int64_t v = 0; v < n; v++) {
+        r[v] = 1.0 / (double)n;
+        d[v] = (double)dout[v] / damping;
+    }
+    int64_t k = 0;
+    while (k < itermax) {
+        k++;
+        for (int64_t v = 0; v < n; v++) t[v] = r[v];
+        for (int64_t v = 0; v < n; v++) w[v] = dout[v] > 0 ? t[v] / d[v] : 0.0;
+        for (int64_t j = 0; j < n; j++) {
+            double s = 0.0;
+            for (int64_t p = rpT[j]; p < rpT[j + 1]; p++)
+                if (dout[ciT[p]] > 0) s += w[ciT[p]];
+            r[j] = teleport + s;
+        }
+        double sum = 0.0;
+        for (int64_t j = 0; j < n; j++) sum += fabs(t[j] - r[j]);
+        if (sum < tol) break;
+    }
+    free(t); free(w); free(d);
+    return k;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Connected components (Section IV-F, Algorithm 7).  FastSV only ever
+ * lowers a parent to a smaller id and stops when no grandparent changes,
+ * which leaves every vertex pointing at the smallest vertex id of its
+ * component; that labelling is written out here directly, by a BFS from
+ * each not yet labelled vertex in ascending order.  Edges are taken in both
+ * directions (rp/ci and the transpose rpT/ciT; pass A twice for an
+ * undirected graph).  Returns 0, -1 on allocation failure.                */
+/* ---------------------------------------------------------------------- */
+
+int orc_components(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t *rpT, const int32_t *ciT,
+                   int64_t *label)
+{
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!queue) return -1;
+    for (int64_t v = 0; v < n; v++) label[v] = -1;
+    for (int64_t s = 0; s < n; s++) {
+        if (label[s] >= 0) continue;
+        int64_t head = 0, tail = 0;
+        label[s] = s;
+        queue[tail++] = (int32_t)s;
+        while (head < tail) {
+            const int32_t u = queue[head++];
+            for (int side = 0; side < 2; side++) {
+                const int64_t *R = side ? rpT : rp;
+                const int32_t *C = side ? ciT : ci;
+                for (int64_t p = R[u]; p < R[u + 1]; p++)
+                    if (label[C[p]] < 0) {
+                        label[C[p]] = s;
+                        queue[tail++] = C[p];
+                    }
+            }
+        }
+    }
+    free(queue);
+    return 0;
 }
 
 /* ---------------------------------------------------------------------- */

@@ -463,3 +463,85 @@ def test_brandes_directed_closed_forms_and_symmetric_case():
     rp, ci = oracle.build_adjacency(n, s, d)                                  # symmetric: A = AT
     srcs = graphgen.sources(n, s, d, 16, 5)
     assert np.allclose(oracle.brandes_directed(rp, ci, srcs), oracle.brandes(rp, ci, srcs), rtol=1e-12, atol=0)
+
+
+# ------------------------------------------------------------- PageRank
+# Algorithm 4 (GAP): r <- (1 - a)/n + a * AT D+ r, where D+ = diag(1/d_out)
+# on vertices with out-edges and 0 on the others (they send nothing).
+
+def _pagerank_dense(rp, ci, damping, iters):
+    n = rp.size - 1
+    A = _dense(n, rp, ci)
+    dout = A.sum(axis=1)
+    dplus = np.where(dout > 0, 1.0 / np.where(dout > 0, dout, 1.0), 0.0)
+    r = np.full(n, 1.0 / n)
+    hist = []
+    for _ in range(iters):
+        t = r
+        r = (1.0 - damping) / n + damping * (A.T @ (dplus * t))
+        hist.append(np.abs(t - r).sum())
+    return r, hist
+
+
+@pytest.mark.parametrize("directed,seed", [(False, 91), (True, 92), (False, 93)])
+def test_pagerank_is_the_dense_power_iteration(directed, seed):
+    n, s, d = graphgen.rmat_edges(7, 6, seed)
+    rp, ci = (oracle.build_directed if directed else oracle.build_adjacency)(n, s, d)
+    for iters in (1, 2, 7, 30):
+        got, k = oracle.pagerank(rp, ci, 0.85, 0.0, iters)
+        want, _ = _pagerank_dense(rp, ci, 0.85, iters)
+        assert k == iters
+        assert np.allclose(got, want, rtol=1e-12, atol=0)
+    # the stopping rule: the first iteration whose change has 1-norm < tol
+    _, hist = _pagerank_dense(rp, ci, 0.85, 100)
+    for tol in (1e-2, 1e-4, 1e-7):
+        first = next(i + 1 for i, h in enumerate(hist) if h < tol)
+        if min(abs(h - tol) for h in hist) > 1e-9 * tol:
+            assert oracle.pagerank(rp, ci, 0.85, tol, 100)[1] == first
+
+
+def test_pagerank_closed_forms():
+    a = 0.85
+    for n, e in (G.complete(12), G.cycle(10)):
+        rp, ci = oracle.from_edges(n, e)
+        r, k = oracle.pagerank(rp, ci, a, 1e-12, 100)
+        assert np.allclose(r, 1.0 / n, rtol=1e-14, atol=0) and k == 1
+    rp, ci = oracle.build_directed(7, np.arange(7), (np.arange(7) + 1) % 7)    # directed cycle
+    r, _ = oracle.pagerank(rp, ci, a, 1e-12, 100)
+    assert np.allclose(r, 1.0 / 7, rtol=1e-14, atol=0)
+    n, e = G.star(9)                                  # centre 0, eight leaves
+    rp, ci = oracle.from_edges(n, e)
+    r, _ = oracle.pagerank(rp, ci, a, 1e-15, 1000)
+    b = (1 - a) / n
+    rc = b * (1 + (n - 1) * a) / (1 - a * a)
+    rl = b + a * rc / (n - 1)
+    assert np.allclose(r, [rc] + [rl] * (n - 1), rtol=1e-12, atol=0)
+    assert abs(rc + (n - 1) * rl - 1.0) < 1e-12
+    # an isolated vertex keeps only the teleport share and sends nothing
+    rp, ci = oracle.from_edges(4, [(0, 1), (1, 2)])
+    r, _ = oracle.pagerank(rp, ci, a, 1e-14, 1000)
+    assert r[3] == (1 - a) / 4 and r.sum() < 1.0
+
+
+# ---------------------------------------------------- connected components
+
+@pytest.mark.parametrize("directed,seed", [(False, 95), (True, 96), (False, 97)])
+def test_components_are_min_ids_of_scipy_components(directed, seed):
+    n, s, d = graphgen.rmat_edges(11, 2, seed)
+    rp, ci = (oracle.build_directed if directed else oracle.build_adjacency)(n, s, d)
+    lab = oracle.components(rp, ci, directed=directed)
+    M = sp.csr_matrix((np.ones(ci.size), ci, rp), shape=(n, n))
+    k, comp = csg.connected_components(M, directed=directed, connection="weak")
+    assert len(set(lab.tolist())) == k > 1
+    for c in range(k):
+        members = np.nonzero(comp == c)[0]
+        assert (lab[members] == members.min()).all()
+
+
+def test_components_closed_forms():
+    n, e = G.disjoint_union(G.path(5), G.disjoint_union(G.petersen(), G.star(4)))
+    rp, ci = oracle.from_edges(n + 2, e)              # two isolated vertices at the end
+    want = [0] * 5 + [5] * 10 + [15] * 4 + [19, 20]
+    assert oracle.components(rp, ci).tolist() == want
+    rp, ci = oracle.build_directed(4, np.array([3, 2, 1]), np.array([2, 1, 0]))   # 3 -> 2 -> 1 -> 0
+    assert oracle.components(rp, ci, directed=True).tolist() == [0, 0, 0, 0]
