@@ -40,6 +40,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-bc", action="store_true")
     p.add_argument("--no-sssp", action="store_true")
+    p.add_argument("--no-prcc", action="store_true")
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--batch-graphs", type=int, default=0,
                    help="graphs in the many-graph leg (default: the full 2,000)")
@@ -428,6 +429,34 @@ def main():
                        "delta_sweep_ms": {str(k): round(v, 4) for k, v in sweep.items()},
                        "dtype": "f64"}
         del SG
+
+    # ------------------------------- PageRank and FastSV components (2^20)
+    log("pagerank and components leg")
+    if not args.no_prcc:
+        def timed(fn, reps=5):
+            out_ms, res = [], None
+            fn()
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                res = fn()
+                e1.record()
+                torch.cuda.synchronize()
+                out_ms.append(e0.elapsed_time(e1))
+            return float(np.median(out_ms)), res
+
+        und_edges = nnzA // 2
+        pr_ms, (_, pr_iters) = timed(lambda: L.lagr_pagerank(G, ctx, 0.85, 1e-4, 20))
+        cc_ms, (cc_lab, cc_iters) = timed(lambda: L.lagr_cc(G, ctx))
+        ncomp = int(torch.unique(cc_lab.values_full(ctx)).numel())
+        out["pagerank"] = {"workload": "rmat-s20-ef16-pr (damping 0.85, tol 1e-4, itermax 20)",
+                           "ms": round(pr_ms, 4), "iterations": pr_iters,
+                           "ms_per_iteration": round(pr_ms / max(pr_iters, 1), 4),
+                           "edges_per_s_per_iteration": round(und_edges * 2 * pr_iters / (pr_ms * 1e-3), 1),
+                           "dtype": "f64"}
+        out["cc"] = {"workload": "rmat-s20-ef16-cc (FastSV)", "ms": round(cc_ms, 4), "iterations": cc_iters,
+                     "components": ncomp, "dtype": "int32"}
 
     # ------------------------------------ many-graph batch (2,000 graphs)
     log("many-graph batch leg")

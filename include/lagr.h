@@ -385,6 +385,28 @@ int lagr_bc(lagr_vector *centrality, const lagr_graph G, const int64_t *sources,
 int lagr_sssp(lagr_vector *dist, const lagr_graph G, int64_t source, double delta, lagr_ctx ctx,
               char *msg);
 
+/* PageRank as GAP specifies it (Section IV-C, Algorithm 4), in FP64:
+ * teleport = (1 - damping)/n, r = 1/n, and each iteration
+ * r = teleport + sum over the in-edges i -> j of r_prev(i) / (d_out(i) /
+ * damping), where a vertex without out-edges sends nothing (GAP's variant:
+ * their rank leaks).  Stops after the first iteration whose change has
+ * 1-norm below tol, or after itermax iterations.  damping in [0, 1], tol
+ * finite and >= 0, itermax >= 0, else LAGR_INVALID_VALUE.  A directed
+ * graph's in-edges are the rows of AT (computed and cached on first use).
+ * Output: rank, a new FP64 FULL vector; iters (may be NULL): the
+ * iterations run.  Sums over at most 32 in-edges run in ascending order as
+ * the listing adds them; longer ones in a fixed order of their own, so a
+ * run is reproducible bit for bit. */
+int lagr_pagerank(lagr_vector *rank, int64_t *iters, const lagr_graph G, double damping, double tol,
+                  int64_t itermax, lagr_ctx ctx, char *msg);
+
+/* Connected components by FastSV (Section IV-F, Algorithm 7): component,
+ * a new INT64 FULL vector holding for every vertex the smallest vertex id of
+ * its component (weakly connected for a directed graph, whose AT is
+ * computed and cached on first use); iters (may be NULL): the FastSV
+ * iterations run. */
+int lagr_cc(lagr_vector *component, int64_t *iters, const lagr_graph G, lagr_ctx ctx, char *msg);
+
 /* ------------------------------------------------- many-graph batching */
 
 /* Triangle counts of many independent graphs in one launch (an extension

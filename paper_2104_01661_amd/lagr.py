@@ -110,6 +110,8 @@ _PROTOS = {
     "lagr_bfs": [_PP, _PP, _P, _I64, _U32, _P, _C],
     "lagr_bc": [_PP, _P, _P, _I32, _P, _C],
     "lagr_sssp": [_PP, _P, _I64, ctypes.c_double, _P, _C],
+    "lagr_pagerank": [_PP, _P, _P, ctypes.c_double, ctypes.c_double, _I64, _P, _C],
+    "lagr_cc": [_PP, _P, _P, _P, _C],
 }
 
 _fns = {}
@@ -450,6 +452,21 @@ def lagr_sssp(G: Graph, source: int, delta: float, ctx: Context) -> Vector:
     out = ctypes.c_void_p()
     call("lagr_sssp", ctypes.byref(out), G.h, int(source), float(delta), ctx.h)
     return Vector(out)
+
+
+def lagr_pagerank(G: Graph, ctx: Context, damping=0.85, tol=1e-4, itermax=100):
+    """-> (rank Vector, iterations run)."""
+    out, it = ctypes.c_void_p(), ctypes.c_int64()
+    call("lagr_pagerank", ctypes.byref(out), ctypes.byref(it), G.h, float(damping), float(tol), int(itermax),
+         ctx.h)
+    return Vector(out), it.value
+
+
+def lagr_cc(G: Graph, ctx: Context):
+    """-> (component label Vector, FastSV iterations run)."""
+    out, it = ctypes.c_void_p(), ctypes.c_int64()
+    call("lagr_cc", ctypes.byref(out), ctypes.byref(it), G.h, ctx.h)
+    return Vector(out), it.value
 
 
 def lagr_bc(G: Graph, sources, ctx: Context) -> Vector:
