@@ -222,11 +222,15 @@ __global__ void k_plan_item_work(const int64_t *__restrict__ Lrp, int64_t n,
 
 // Each workgroup writes its count to partial[blockIdx.x]; k_sum_partials
 // adds them (atomics on one address from every wavefront would serialise).
-__global__ __launch_bounds__(TC_BLOCK, 8) void k_tc_split(PlanArgs a, unsigned long long *__restrict__ partial)
+// Workgroups are dispatched to the 8 XCDs in turn (workgroup b runs on XCD
+// b mod 8), and each XCD has its own L2: the waves of workgroup b take their
+// items from the counter of eighth b mod 8 first (tc_dyn_wave).  Each
+// workgroup writes its count to partial[blockIdx.x].
+__global__ __launch_bounds__(TC_BLOCK, 8) void k_tc_split(PlanArgs a, unsigned long long *__restrict__ partial,
+                                                          unsigned long long *__restrict__ ctr)
 {
     __shared__ TcWaveLds lds[TC_WAVES];
-    const int64_t w = (int64_t)blockIdx.x * TC_WAVES + threadIdx.x / 64;
-    unsigned long long acc = tc_split_wave<false>(a, lds[threadIdx.x / 64], w, (int64_t)gridDim.x * TC_WAVES);
+    unsigned long long acc = tc_dyn_wave(a, lds[threadIdx.x / 64], ctr, (int)(blockIdx.x % TC_DYN_PARTS));
     __shared__ unsigned long long wsum[TC_WAVES];
     if (lane_id() == 0) wsum[threadIdx.x / 64] = acc;
     __syncthreads();
@@ -372,14 +376,17 @@ static int tc_on_lower(lagr_ctx ctx, const lagr_graph G, int64_t *ntri, char *ms
     const lagr_matrix L = G->L;
     const TcPlan *P = G->tcplan;
     // eight resident waves per SIMD (the LDS and register budgets of
-    // k_tc_split allow it): the static partition assumes all resident
+    // k_tc_split allow it); the work counters follow the partials
     const unsigned blocks = (unsigned)(ctx->num_cus * 8);
-    unsigned long long *tot = (unsigned long long *)ws_get(ctx, WS_TC, 8 * ((size_t)blocks + 1));
+    const size_t nctr = (size_t)TC_DYN_STRIDE * TC_DYN_PARTS;
+    unsigned long long *tot = (unsigned long long *)ws_get(ctx, WS_TC, 8 * ((size_t)blocks + 1 + nctr));
     if (!tot) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc counter");
     if (P->nitems > 0) {
+        unsigned long long *ctr = tot + 1 + blocks;
+        TRY(fill_i64(ctx, (int64_t *)ctr, (int64_t)nctr, 0, msg));
         PlanArgs a{P->nitems, L->rowptr, L->colidx, P->iprefix, P->ent, P->item, P->item_row};
         TIMED(ctx, "tc_split",
-              hipLaunchKernelGGL(k_tc_split, dim3(blocks), dim3(TC_BLOCK), 0, ctx->stream, a, tot + 1));
+              hipLaunchKernelGGL(k_tc_split, dim3(blocks), dim3(TC_BLOCK), 0, ctx->stream, a, tot + 1, ctr));
         LAUNCH_CHECK();
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, ctx->stream, tot + 1, (int64_t)blocks, tot);
         LAUNCH_CHECK();

@@ -513,3 +513,67 @@ __device__ unsigned long long tc_split_wave(const PlanArgs &a, TcWaveLds &L, int
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     return acc;
 }
+
+// Dynamic form of the same loop.  The static split leaves waves busy for
+// about 60% of the launch at 2^20 (the cost model misjudges some items),
+// so each wave instead takes TC_DYN_ITEMS consecutive items at a time from
+// a counter.  There is one counter per XCD (ctr[TC_DYN_STRIDE * x], one
+// cache line each), covering one contiguous eighth of the items, so the
+// waves of an XCD keep working through neighbouring items (their streamed
+// rows stay in that XCD's L2); a wave whose eighth is used up moves on to
+// the next eighth in turn.  The counters must be zero at launch.
+constexpr int64_t TC_DYN_ITEMS = 4;
+constexpr int TC_DYN_STRIDE = 16;   // 128 bytes between counters
+constexpr int TC_DYN_PARTS = 8;
+
+__device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsigned long long *ctr, int part)
+{
+    const unsigned lane = lane_id();
+    for (int x = lane; x < TC_BM_WORDS; x += 64) L.bm[x] = 0u;
+    wave_sync();
+    const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
+    const int64_t N = a.nitems;
+    unsigned long long acc = 0;
+    int32_t marked = -1, first_id = -1;
+    int64_t alen = 0;
+    const int32_t *Arow = nullptr;
+    bool use_hash = false;
+    for (int tries = 0; tries < TC_DYN_PARTS;) {
+        const int p = (part + tries) % TC_DYN_PARTS;
+        const int64_t r0 = N * p / TC_DYN_PARTS, r1 = N * (p + 1) / TC_DYN_PARTS;
+        unsigned long long c = 0;
+        if (lane == 0) c = atomicAdd(&ctr[TC_DYN_STRIDE * p], 1ull);
+        c = (unsigned long long)__shfl((long long)c, 0, 64);
+        const int64_t k0 = r0 + (int64_t)c * TC_DYN_ITEMS;
+        if (k0 >= r1) {
+            tries++;
+            continue;
+        }
+        const int64_t k1 = k0 + TC_DYN_ITEMS < r1 ? k0 + TC_DYN_ITEMS : r1;
+        for (int64_t k = k0; k < k1; k++) {
+            const uint64_t it = a.item[k];
+            const int32_t m = a.item_row[k];
+            const int64_t e0 = (int64_t)(it >> TC_PLAN_CNT_BITS);
+            const int cnt = (int)(it & ((1u << TC_PLAN_CNT_BITS) - 1));
+            int64_t s = 0;
+            int len = 0;
+            if ((int)lane < cnt) {
+                const uint64_t x = a.ent[e0 + lane];
+                s = (int64_t)(x >> TC_PLAN_LEN_BITS);
+                len = (int)(x & lmask);
+            }
+            if (m != marked) {
+                if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
+                Arow = a.Lci + a.Lrp[m];
+                alen = a.Lrp[m + 1] - a.Lrp[m];
+                use_hash = tc_mark(L, Arow, alen, lane, &first_id);
+                marked = m;
+            }
+            acc += tc_stream_flat(L, use_hash, Arow, alen, a.Lci, s, len, cnt, lane);
+        }
+    }
+    if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    return acc;
+}
+
