@@ -178,28 +178,34 @@ __global__ void k_check_chunks(const int64_t *__restrict__ rp, const int32_t *__
 
 // ---------------------------------------- degree order and relabel (TC)
 
-__global__ void k_order_keys(const int64_t *__restrict__ deg, int64_t n, int64_t maxdeg, int vbits,
+// key of vertex v: (v << dbits) | (maxdeg - deg(v)), dbits a multiple of 8
+// (the radix passes take whole 8-bit digits, which must not reach v).  A
+// stable sort on the low dbits bits alone orders by descending degree and,
+// since the keys start in ascending v, keeps ties in ascending id: two
+// passes at 2^20 instead of five over (degree, id).  The vertex with new
+// label p is order[p] >> dbits.
+__global__ void k_order_keys(const int64_t *__restrict__ deg, int64_t n, int64_t maxdeg, int dbits,
                              uint64_t *__restrict__ keys)
 {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x)
-        keys[v] = ((uint64_t)(maxdeg - deg[v]) << vbits) | (uint64_t)v;
+        keys[v] = ((uint64_t)v << dbits) | (uint64_t)(maxdeg - deg[v]);
 }
 
-__global__ void k_inverse_perm(const uint64_t *__restrict__ keys, int64_t n, uint64_t vmask,
-                               int32_t *__restrict__ inv)
+__global__ void k_inverse_perm(const uint64_t *__restrict__ keys, int64_t n, int dbits, int32_t *__restrict__ inv)
 {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * blockDim.x)
-        inv[keys[p] & vmask] = (int32_t)p;
+        inv[keys[p] >> dbits] = (int32_t)p;
 }
 
-// rowA[e] = the row of entry e of A.  A wave takes 64 consecutive rows
-// and writes them one after the other, its lanes over the row's entries
-// (coalesced stores; a lane per row would scatter every store).  Rows of
-// more than GRAPH_LONG_ROW entries are left to k_row_ids_chunks, so that
-// no wave writes a hub row alone.
-__global__ void k_row_ids(const int64_t *__restrict__ rp, int64_t n, int32_t *__restrict__ rowA)
+// rowA[e] = the row of entry e of a matrix with row offsets rp (A, and L
+// for the plan).  A wave takes 64 consecutive rows and writes them one
+// after the other, its lanes over the row's entries (coalesced stores; a
+// lane per row would scatter every store).  Rows of more than long_row
+// entries are left to k_row_ids_chunks, so that no wave writes a hub row
+// alone.
+__global__ void k_row_ids(const int64_t *__restrict__ rp, int64_t n, int64_t long_row, int32_t *__restrict__ rowA)
 {
     const unsigned lane = lane_id();
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
@@ -209,7 +215,7 @@ __global__ void k_row_ids(const int64_t *__restrict__ rp, int64_t n, int32_t *__
         const int rows = (int)min((int64_t)64, n - r0);
         for (int k = 0; k < rows; k++) {
             const int64_t b = __shfl(mb, k, 64), e = __shfl(me, k, 64);
-            if (e - b > GRAPH_LONG_ROW) continue;
+            if (e - b > long_row) continue;
             for (int64_t p = b + lane; p < e; p += 64) rowA[p] = (int32_t)(r0 + k);
         }
     }
@@ -224,101 +230,120 @@ __global__ void k_row_ids_chunks(RowChunks ch, int32_t *__restrict__ rowA)
         for (int64_t p = ch.beg[c] + lane; p < ch.end[c]; p += 64) rowA[p] = ch.row[c];
 }
 
-// cnt[inv[u]] (zero on entry) += number of neighbours v of u with
-// inv[v] < inv[u]: the length of row inv[u] of L.  One lane per entry of A;
-// the loop steps whole wavefronts (wave_run needs every lane).
-__global__ void k_count_relabel(const int32_t *__restrict__ rowA, const int32_t *__restrict__ ci,
-                                const int32_t *__restrict__ inv, int64_t nnz,
-                                unsigned long long *__restrict__ cnt)
+// The strictly lower part of the relabelled A, written in A's own layout:
+// the ids inv[v] < inv[u] of row u go, unsorted, to P[rpA[u] ..), and
+// cur[u] (zero on entry) ends as their number, the length of row inv[u] of
+// L.  Emitting into the space of the source row needs no counting pass
+// first.  One lane per entry of A; the loop steps whole wavefronts
+// (wave_run needs every lane), and the lanes of one row make one atomic.
+__global__ void k_emit_padded(const int32_t *__restrict__ rowA, const int32_t *__restrict__ ci,
+                              const int64_t *__restrict__ rpA, const int32_t *__restrict__ inv, int64_t nnz,
+                              unsigned long long *__restrict__ cur, int32_t *__restrict__ P)
 {
     const unsigned lane = lane_id();
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
     for (int64_t w0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); w0 < nnz; w0 += step) {
         const int64_t e = w0 + lane;
-        int32_t u = -1, iu = 0;
+        int32_t u = -1, iv = 0;
         bool take = false;
         if (e < nnz) {
             u = rowA[e];
-            iu = inv[u];
-            take = inv[ci[e]] < iu;
-        }
-        const WaveRun w = wave_run(u);
-        const uint64_t t = __ballot(take) & w.run;
-        if (lane == w.head && t) atomicAdd(&cnt[iu], (unsigned long long)__popcll(t));
-    }
-}
-
-// Column ids of the relabelled strictly lower part, written unsorted into
-// row inv[u] of L (buffer U; cursor[inv[u]] starts at the row's offset in
-// L), with the row of every entry (rowL; the sort below only moves ids
-// within a row).
-__global__ void k_emit_relabel(const int32_t *__restrict__ rowA, const int32_t *__restrict__ ci,
-                               const int32_t *__restrict__ inv, int64_t nnz,
-                               unsigned long long *__restrict__ cursor, int32_t *__restrict__ U,
-                               int32_t *__restrict__ rowL)
-{
-    const unsigned lane = lane_id();
-    const int64_t step = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t w0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); w0 < nnz; w0 += step) {
-        const int64_t e = w0 + lane;
-        int32_t u = -1, iu = 0, iv = 0;
-        bool take = false;
-        if (e < nnz) {
-            u = rowA[e];
-            iu = inv[u];
             iv = inv[ci[e]];
-            take = iv < iu;
+            take = iv < inv[u];
         }
         const WaveRun w = wave_run(u);
         const uint64_t t = __ballot(take) & w.run;
         unsigned long long base = 0;
-        if (lane == w.head && t) base = atomicAdd(&cursor[iu], (unsigned long long)__popcll(t));
+        if (lane == w.head && t) base = atomicAdd(&cur[u], (unsigned long long)__popcll(t));
         base = (unsigned long long)__shfl((long long)base, (int)w.head, 64);
-        if (take) {
-            const unsigned long long o = base + __popcll(t & w.before);
-            U[o] = iv;
-            rowL[o] = iu;
-        }
+        if (take) P[rpA[u] + (int64_t)base + __popcll(t & w.before)] = iv;
     }
 }
 
-// Rows of at most SORT_SHORT ids: each entry's place in its row of the
-// sorted output Lci is the number of smaller ids in the row (the ids of a
-// row are distinct), read from the unsorted copy U.
+// cnt[inv[u]] = cur[u]: the row lengths of L, by new label.
+__global__ void k_lower_lengths(const unsigned long long *__restrict__ cur, const int32_t *__restrict__ inv,
+                                int64_t n, int64_t *__restrict__ cnt)
+{
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x)
+        cnt[inv[u]] = (int64_t)cur[u];
+}
+
+// Rows of at most SORT_SHORT ids: each entry's place in its row of L is the
+// number of smaller ids in the row (the ids of a row are distinct), read
+// from the row's unsorted copy in P, at the offset in A of the row's vertex
+// (order[r] >> oshift is the vertex with new label r).  One thread per entry
+// of L; rowL, the row of every entry of L, is already written.
 constexpr int64_t SORT_SHORT = 64;
 
-__global__ void k_sort_short(const int64_t *__restrict__ Lrp, const int32_t *__restrict__ U,
-                             const int32_t *__restrict__ rowid, int64_t nnz, int32_t *__restrict__ Lci)
+__global__ void k_sort_short(const int32_t *__restrict__ rowL, const int64_t *__restrict__ Lrp,
+                             const uint64_t *__restrict__ order, int oshift, const int64_t *__restrict__ rpA,
+                             const int32_t *__restrict__ P, int64_t nnz, int32_t *__restrict__ Lci)
 {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = rowid[e], b = Lrp[r], len = Lrp[r + 1] - b;
-        if (len > SORT_SHORT) continue;   // k_sort_long
-        const int32_t x = U[e];
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < nnz;
+         o += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = rowL[o];
+        const int64_t b = Lrp[r], c = Lrp[r + 1] - b;
+        if (c > SORT_SHORT) continue;   // k_sort_long
+        const int32_t *src = P + rpA[order[r] >> oshift];
+        const int32_t x = src[o - b];
         int64_t rank = 0;
-        for (int64_t q = b; q < b + len; q++) rank += U[q] < x ? 1 : 0;
+        for (int64_t t = 0; t < c; t++) rank += src[t] < x ? 1 : 0;
         Lci[b + rank] = x;
     }
 }
 
-// Rows of SORT_SHORT + 1 .. SORT_LONG ids (one chunk each in ch): one wave
-// per row, a bitonic network over the row in the wave's LDS.
+// Rows of SORT_SHORT + 1 .. SORT_LONG ids (listed in rows[0 .. *count)):
+// one wave per row, a bitonic network over the row in the wave's LDS.  The row's source is P at the offset of its vertex in A
+// (order[r] >> oshift is the vertex with new label r).
 constexpr int SORT_LONG = 2048;
 
-__global__ __launch_bounds__(256) void k_sort_long(RowChunks ch, const int32_t *__restrict__ U,
-                                                   int32_t *__restrict__ Lci)
+// Rows of L longer than min_len, listed in rows[0 .. *count) (count zero on
+// entry): each workgroup reserves its range with one atomic.
+__global__ __launch_bounds__(256) void k_list_long_rows(const int64_t *__restrict__ Lrp, int64_t n, int64_t min_len,
+                                                        int32_t *__restrict__ rows, unsigned long long *count)
+{
+    __shared__ unsigned sc[256];
+    __shared__ unsigned long long base_s;
+    const int64_t share = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t v0 = (int64_t)blockIdx.x * share, v1 = min(n, v0 + share);
+    unsigned c = 0;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += 256) c += Lrp[v + 1] - Lrp[v] > min_len ? 1u : 0u;
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const unsigned y = (int)threadIdx.x >= o ? sc[threadIdx.x - o] : 0u;
+        __syncthreads();
+        sc[threadIdx.x] += y;
+        __syncthreads();
+    }
+    if (threadIdx.x == 255) base_s = sc[255] ? atomicAdd(count, (unsigned long long)sc[255]) : 0;
+    __syncthreads();
+    unsigned long long pos = base_s + sc[threadIdx.x] - c;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += 256)
+        if (Lrp[v + 1] - Lrp[v] > min_len) rows[pos++] = (int32_t)v;
+}
+
+__global__ __launch_bounds__(256) void k_sort_long(const int32_t *__restrict__ rows,
+                                                   const unsigned long long *__restrict__ count,
+                                                   const int64_t *__restrict__ Lrp, const uint64_t *__restrict__ order,
+                                                   int oshift, const int64_t *__restrict__ rpA,
+                                                   const int32_t *__restrict__ P, int32_t *__restrict__ Lci)
 {
     __shared__ int32_t buf[4][SORT_LONG];
     int32_t *x = buf[threadIdx.x / 64];
     const unsigned lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
-    for (int64_t c = wave; c < ch.n; c += nw) {
-        const int64_t b = ch.beg[c];
-        const int len = (int)(ch.end[c] - b);
+    const int64_t nrows = (int64_t)*count;
+    for (int64_t c = wave; c < nrows; c += nw) {
+        const int32_t r = rows[c];
+        const int64_t b = Lrp[r];
+        const int len = (int)(Lrp[r + 1] - b);
+        const int32_t *src = P + rpA[order[r] >> oshift];
         int N = 1;
         while (N < len) N <<= 1;
-        for (int i = lane; i < N; i += 64) x[i] = i < len ? U[b + i] : INT32_MAX;
+        for (int i = lane; i < N; i += 64) x[i] = i < len ? src[i] : INT32_MAX;
         wave_barrier_lds();
         for (int k = 2; k <= N; k <<= 1)
             for (int j = k >> 1; j > 0; j >>= 1) {
@@ -337,13 +362,18 @@ __global__ __launch_bounds__(256) void k_sort_long(RowChunks ch, const int32_t *
     }
 }
 
-// Rows longer than SORT_LONG: keys of every entry, then a global radix sort.
-__global__ void k_row_keys(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci, int64_t n, int vbits,
-                           uint64_t *__restrict__ keys)
+// Rows longer than SORT_LONG: a (row, id) key for every entry of L, then a
+// global radix sort.
+__global__ void k_row_keys(const int32_t *__restrict__ rowL, const int64_t *__restrict__ Lrp,
+                           const uint64_t *__restrict__ order, int oshift, const int64_t *__restrict__ rpA,
+                           const int32_t *__restrict__ P, int64_t nnz, int vbits, uint64_t *__restrict__ keys)
 {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
-         r += (int64_t)gridDim.x * blockDim.x)
-        for (int64_t e = rp[r]; e < rp[r + 1]; e++) keys[e] = ((uint64_t)r << vbits) | (uint64_t)ci[e];
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < nnz;
+         o += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = rowL[o];
+        const int32_t x = P[rpA[order[r] >> oshift] + (o - Lrp[r])];
+        keys[o] = ((uint64_t)r << vbits) | (uint64_t)x;
+    }
 }
 
 __global__ void k_keys_split(const uint64_t *__restrict__ keys, int64_t nnz, int vbits, uint64_t vmask,
@@ -569,32 +599,42 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
     const int64_t nnzA = A->nvals;
     int32_t *rowA = (int32_t *)ws_get(ctx, WS_GEN_D, sizeof(int32_t) * (nnzA > 0 ? nnzA : 1));
     if (!okeys || !inv || !cnt || !rowA) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
+    const int dbits = (bits_for((uint64_t)G->max_degree) + 7) / 8 * 8;
     if (n > 0) {
         hipLaunchKernelGGL(k_order_keys, dim3(grid_for(n, 256, 65536)), dim3(256), 0, ctx->stream,
-                           G->row_degree, n, G->max_degree, vbits, okeys);
+                           G->row_degree, n, G->max_degree, dbits, okeys);
         LAUNCH_CHECK();
     }
-    TRY(radix_sort_u64(ctx, okeys, n, vbits + bits_for((uint64_t)G->max_degree), msg));
+    TRY(radix_sort_u64(ctx, okeys, n, dbits, msg));
     TRY(fill_i64(ctx, cnt, n + 1, 0, msg));
     if (n > 0) {
         hipLaunchKernelGGL(k_inverse_perm, dim3(grid_for(n, 256, 65536)), dim3(256), 0, ctx->stream,
-                           okeys, n, vmask, inv);
+                           okeys, n, dbits, inv);
         LAUNCH_CHECK();
-        // 2. the row of every entry of A, then the row lengths of the
-        //    relabelled strictly lower part
+        // 2. the row of every entry of A; the relabelled strictly lower part
+        //    lands unsorted in A's layout, counting its row lengths
         RowChunks ch;
         TRY(graph_chunks(G, ctx, &ch, msg));
         hipLaunchKernelGGL(k_row_ids, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, A->rowptr, n,
-                           rowA);
+                           GRAPH_LONG_ROW, rowA);
         if (ch.n > 0)
             hipLaunchKernelGGL(k_row_ids_chunks, dim3(grid_for(ch.n * 64, 256, 8192)), dim3(256), 0,
                                ctx->stream, ch, rowA);
         LAUNCH_CHECK();
-        if (nnzA > 0) {
-            hipLaunchKernelGGL(k_count_relabel, dim3(grid_for(nnzA, 256, 8192)), dim3(256), 0, ctx->stream,
-                               rowA, A->colidx, inv, nnzA, (unsigned long long *)cnt);
-            LAUNCH_CHECK();
-        }
+    }
+    int32_t *P = (int32_t *)ws_get(ctx, WS_GEN_C, sizeof(int32_t) * (nnzA > 0 ? nnzA : 1));
+    unsigned long long *cur = (unsigned long long *)ws_get(ctx, WS_GEN_B, sizeof(int64_t) * (n > 0 ? n : 1));
+    if (!P || !cur) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
+    TRY(fill_i64(ctx, (int64_t *)cur, n, 0, msg));
+    if (nnzA > 0) {
+        hipLaunchKernelGGL(k_emit_padded, dim3(grid_for(nnzA, 256, 8192)), dim3(256), 0, ctx->stream, rowA,
+                           A->colidx, A->rowptr, inv, nnzA, cur, P);
+        LAUNCH_CHECK();
+    }
+    if (n > 0) {
+        hipLaunchKernelGGL(k_lower_lengths, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, cur, inv, n,
+                           cnt);
+        LAUNCH_CHECK();
     }
     int64_t nnz = 0;
     TRY(scan_exclusive_i64(ctx, cnt, cnt, n + 1, &nnz, msg));
@@ -609,26 +649,14 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
         return rc;
     }
     int32_t *rowid = (int32_t *)ws_get(ctx, WS_GEN_A, sizeof(int32_t) * (nnz > 0 ? nnz : 1));
-    int32_t *U = (int32_t *)ws_get(ctx, WS_GEN_C, sizeof(int32_t) * (nnz > 0 ? nnz : 1));
-    unsigned long long *cursor = (unsigned long long *)ws_get(ctx, WS_GEN_B, sizeof(int64_t) * (n > 0 ? n : 1));
-    if (!rowid || !U || !cursor) {
+    if (!rowid) {
         rc = lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
         goto fail;
     }
-    // 3. each row's ids land unsorted in U, with their rows; then the rows
-    //    are sorted into L
+    // 3. the rows are sorted from P into L
     if (hipMemcpyAsync(L->rowptr, cnt, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, ctx->stream) !=
-            hipSuccess ||
-        (n > 0 && hipMemcpyAsync(cursor, cnt, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, ctx->stream) !=
-                      hipSuccess)) {
+        hipSuccess) {
         rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "relabel copy");
-        goto fail;
-    }
-    if (nnzA > 0)
-        hipLaunchKernelGGL(k_emit_relabel, dim3(grid_for(nnzA, 256, 8192)), dim3(256), 0, ctx->stream, rowA,
-                           A->colidx, inv, nnzA, cursor, U, rowid);
-    if (hipGetLastError() != hipSuccess) {
-        rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "relabel launch failed");
         goto fail;
     }
     {
@@ -641,20 +669,36 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
         if ((rc = row_degrees(ctx, L->rowptr, n, tmp, &mx, msg)) < 0) goto fail;
         G->L_maxrow = mx;
     }
+    // the row of every entry of L (the plan reads it too); rows of L are
+    // short (the longest is L_maxrow), so no chunk list is needed
+    if (n > 0) {
+        hipLaunchKernelGGL(k_row_ids, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, L->rowptr, n,
+                           (int64_t)INT64_MAX, rowid);
+        if (hipGetLastError() != hipSuccess) {
+            rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row id launch failed");
+            goto fail;
+        }
+    }
     if (nnz > 0 && G->L_maxrow <= SORT_LONG) {
-        hipLaunchKernelGGL(k_sort_short, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, ctx->stream, L->rowptr, U,
-                           rowid, nnz, L->colidx);
+        hipLaunchKernelGGL(k_sort_short, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, ctx->stream, rowid,
+                           L->rowptr, okeys, dbits, A->rowptr, P, nnz, L->colidx);
         if (hipGetLastError() != hipSuccess) {
             rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
             goto fail;
         }
         if (G->L_maxrow > SORT_SHORT) {
-            RowChunks lc;
-            if ((rc = row_chunks(ctx, L->rowptr, n, SORT_SHORT, SORT_LONG, WS_CHUNK_A, WS_CHUNK_B, &lc, msg)) < 0)
+            // the rows over SORT_SHORT, listed and counted on the device
+            int32_t *lrows = (int32_t *)ws_get(ctx, WS_CHUNK_A, sizeof(int32_t) * (size_t)n);
+            unsigned long long *nlong = (unsigned long long *)ws_get(ctx, WS_CHUNK_B, 64);
+            if (!lrows || !nlong) {
+                rc = lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
                 goto fail;
-            if (lc.n > 0)
-                hipLaunchKernelGGL(k_sort_long, dim3(grid_for(lc.n * 64, 256, 16384)), dim3(256), 0, ctx->stream,
-                                   lc, U, L->colidx);
+            }
+            if ((rc = fill_i64(ctx, (int64_t *)nlong, 1, 0, msg)) < 0) goto fail;
+            hipLaunchKernelGGL(k_list_long_rows, dim3(grid_for(n, 256, 1024)), dim3(256), 0, ctx->stream, L->rowptr,
+                               n, SORT_SHORT, lrows, nlong);
+            hipLaunchKernelGGL(k_sort_long, dim3((unsigned)(ctx->num_cus * 16)), dim3(256), 0, ctx->stream, lrows,
+                               nlong, L->rowptr, okeys, dbits, A->rowptr, P, L->colidx);
             if (hipGetLastError() != hipSuccess) {
                 rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
                 goto fail;
@@ -666,8 +710,8 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
             rc = lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
             goto fail;
         }
-        hipLaunchKernelGGL(k_row_keys, dim3(grid_for(n, 256, 16384)), dim3(256), 0, ctx->stream, L->rowptr,
-                           U, n, vbits, keys);
+        hipLaunchKernelGGL(k_row_keys, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, ctx->stream, rowid,
+                           L->rowptr, okeys, dbits, A->rowptr, P, nnz, vbits, keys);
         if (hipGetLastError() != hipSuccess) {
             rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
             goto fail;

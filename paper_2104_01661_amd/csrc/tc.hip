@@ -61,24 +61,9 @@ constexpr int PLAN_HOT = 8192;
 constexpr int PLAN_BLOCK = 512;
 constexpr unsigned PLAN_GRID = 1024;
 
-struct PlanEntry {
-    int64_t i, j, p, si;   // row, column, position in row i, start of row i
-};
-
 // rowpk[r] = plan_pack(start of row r, length of row r): one gather gives
 // both (the plan kernels gather it for the row and for the column of every
 // entry, at random columns).
-__device__ __forceinline__ PlanEntry plan_entry(const int32_t *__restrict__ rowid, const int32_t *__restrict__ ci,
-                                                const uint64_t *__restrict__ rowpk, int64_t e)
-{
-    PlanEntry x;
-    x.i = rowid[e];
-    x.j = ci[e];
-    x.si = (int64_t)(rowpk[x.i] >> TC_PLAN_LEN_BITS);
-    x.p = e - x.si;
-    return x;
-}
-
 __global__ void k_row_pack(const int64_t *__restrict__ rp, int64_t n, uint64_t *__restrict__ rowpk)
 {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
@@ -86,9 +71,15 @@ __global__ void k_row_pack(const int64_t *__restrict__ rp, int64_t n, uint64_t *
         rowpk[r] = plan_pack(rp[r], rp[r + 1] - rp[r]);
 }
 
-// Entries per virtual row (cnt: 2n+1 entries, zero on entry).  The loops
-// step whole wavefronts, so every lane of a wave takes part in each
-// iteration's ballots and shuffles.
+// Entries per virtual row (cnt: 2n+1 entries, zero on entry).  Each wave
+// takes PLAN_ILP windows of 64 consecutive entries per iteration and runs
+// them stage by stage (their loads, then their gathers, then their
+// atomics), so a wave waits for each round trip once per PLAN_ILP windows:
+// the kernels are bound by the latency of gathers and atomics that miss
+// L2.  Every lane of a wave runs every iteration (the loop bound is
+// uniform), as wave_run's ballots and shuffles need.
+constexpr int PLAN_ILP = 2;
+
 __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_count(const int32_t *__restrict__ rowid,
                                                            const int32_t *__restrict__ ci, int64_t nnz,
                                                            const uint64_t *__restrict__ rowpk, int64_t n,
@@ -101,23 +92,36 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_count(const int32_t *__rest
     const int64_t share = (nnz + gridDim.x - 1) / gridDim.x;
     const int64_t e0 = (int64_t)blockIdx.x * share, e1 = min(nnz, e0 + share);
     const unsigned lane = lane_id();
-    for (int64_t w0 = e0 + (threadIdx.x & ~63u); w0 < e1; w0 += PLAN_BLOCK) {
-        const int64_t e = w0 + lane;
-        bool a_side = false;
-        int32_t key = -1;
-        if (e < e1) {
-            const PlanEntry x = plan_entry(rowid, ci, rowpk, e);
-            key = (int32_t)x.i;
-            const int64_t lj = (int64_t)(rowpk[x.j] & ((1ull << TC_PLAN_LEN_BITS) - 1));
-            if (x.p > 0 && lj > 0) {
-                if (lj <= x.p) a_side = true;
-                else if (x.j < PLAN_HOT) atomicAdd(&hot[x.j], 1u);
-                else atomicAdd(&cnt[n + x.j], 1ull);
-            }
+    const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
+    const int64_t first = (int64_t)(threadIdx.x / 64) * PLAN_ILP * 64 + lane;
+    for (int64_t base = e0; base < e1; base += (int64_t)PLAN_BLOCK * PLAN_ILP) {
+        int32_t i[PLAN_ILP], j[PLAN_ILP];
+        uint64_t pi[PLAN_ILP], pj[PLAN_ILP];
+#pragma unroll
+        for (int k = 0; k < PLAN_ILP; k++) {
+            const int64_t e = base + first + 64 * k;
+            i[k] = e < e1 ? rowid[e] : -1;
+            j[k] = e < e1 ? ci[e] : 0;
         }
-        const WaveRun w = wave_run(key);
-        const uint64_t take = __ballot(a_side) & w.run;
-        if (lane == w.head && take) atomicAdd(&cnt[key], (unsigned long long)__popcll(take));
+#pragma unroll
+        for (int k = 0; k < PLAN_ILP; k++) {
+            pi[k] = i[k] >= 0 ? rowpk[i[k]] : 0ull;
+            pj[k] = i[k] >= 0 ? rowpk[j[k]] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < PLAN_ILP; k++) {
+            const int64_t e = base + first + 64 * k;
+            const int64_t p = e - (int64_t)(pi[k] >> TC_PLAN_LEN_BITS), lj = (int64_t)(pj[k] & lmask);
+            const bool valid = i[k] >= 0 && p > 0 && lj > 0;
+            const bool a_side = valid && lj <= p;
+            if (valid && !a_side) {
+                if (j[k] < PLAN_HOT) atomicAdd(&hot[j[k]], 1u);
+                else atomicAdd(&cnt[n + j[k]], 1ull);
+            }
+            const WaveRun w = wave_run(i[k]);
+            const uint64_t take = __ballot(a_side) & w.run;
+            if (lane == w.head && take) atomicAdd(&cnt[i[k]], (unsigned long long)__popcll(take));
+        }
     }
     __syncthreads();
     unsigned *mine = boff + (size_t)blockIdx.x * PLAN_HOT;
@@ -127,18 +131,19 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_count(const int32_t *__rest
 
 // cur (a copy of the first 2n offsets) holds the write cursor of each
 // virtual row; the order of the entries within a row is immaterial.  Hot
-// B rows hand out positions from LDS as offsets from bstart, the first
-// B-side offset (the host checks that the B side spans fewer than 2^32
+// B rows hand out positions from LDS as offsets from bstart = trp[n], the
+// first B-side offset (the host checks that the plan has fewer than 2^32
 // entries), starting at the workgroup's range from the count kernel.
 __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restrict__ rowid,
                                                           const int32_t *__restrict__ ci, int64_t nnz,
                                                           const uint64_t *__restrict__ rowpk, int64_t n,
-                                                          const int64_t *__restrict__ trp, int64_t bstart,
+                                                          const int64_t *__restrict__ trp,
                                                           const unsigned *__restrict__ boff,
                                                           unsigned long long *__restrict__ cur,
                                                           uint64_t *__restrict__ ent)
 {
     __shared__ unsigned hot[PLAN_HOT];
+    const int64_t bstart = trp[n];
     const unsigned *mine = boff + (size_t)blockIdx.x * PLAN_HOT;
     for (int x = threadIdx.x; x < PLAN_HOT && x < n; x += PLAN_BLOCK)
         hot[x] = (unsigned)(trp[n + x] - bstart) + mine[x];
@@ -146,33 +151,50 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restr
     const int64_t share = (nnz + gridDim.x - 1) / gridDim.x;
     const int64_t e0 = (int64_t)blockIdx.x * share, e1 = min(nnz, e0 + share);
     const unsigned lane = lane_id();
-    for (int64_t w0 = e0 + (threadIdx.x & ~63u); w0 < e1; w0 += PLAN_BLOCK) {
-        const int64_t e = w0 + lane;
-        bool a_side = false;
-        int32_t key = -1;
-        uint64_t packed = 0;
-        if (e < e1) {
-            const PlanEntry x = plan_entry(rowid, ci, rowpk, e);
-            key = (int32_t)x.i;
-            const uint64_t pj = rowpk[x.j];
-            const int64_t lj = (int64_t)(pj & ((1ull << TC_PLAN_LEN_BITS) - 1));
-            if (x.p > 0 && lj > 0) {
-                if (lj <= x.p) {
-                    a_side = true;
-                    packed = pj;
-                } else if (x.j < PLAN_HOT) {
-                    ent[bstart + atomicAdd(&hot[x.j], 1u)] = plan_pack(x.si, x.p);
-                } else {
-                    ent[atomicAdd(&cur[n + x.j], 1ull)] = plan_pack(x.si, x.p);
-                }
+    const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
+    const int64_t first = (int64_t)(threadIdx.x / 64) * PLAN_ILP * 64 + lane;
+    for (int64_t base = e0; base < e1; base += (int64_t)PLAN_BLOCK * PLAN_ILP) {
+        int32_t i[PLAN_ILP], j[PLAN_ILP];
+        uint64_t pi[PLAN_ILP], pj[PLAN_ILP];
+#pragma unroll
+        for (int k = 0; k < PLAN_ILP; k++) {
+            const int64_t e = base + first + 64 * k;
+            i[k] = e < e1 ? rowid[e] : -1;
+            j[k] = e < e1 ? ci[e] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < PLAN_ILP; k++) {
+            pi[k] = i[k] >= 0 ? rowpk[i[k]] : 0ull;
+            pj[k] = i[k] >= 0 ? rowpk[j[k]] : 0ull;
+        }
+        // B side: positions from LDS (hot rows) or the row's cursor
+        bool a_side[PLAN_ILP];
+        int64_t bpos[PLAN_ILP];
+        uint64_t bval[PLAN_ILP];
+#pragma unroll
+        for (int k = 0; k < PLAN_ILP; k++) {
+            const int64_t e = base + first + 64 * k;
+            const int64_t si = (int64_t)(pi[k] >> TC_PLAN_LEN_BITS), p = e - si, lj = (int64_t)(pj[k] & lmask);
+            const bool valid = i[k] >= 0 && p > 0 && lj > 0;
+            a_side[k] = valid && lj <= p;
+            bpos[k] = -1;
+            bval[k] = plan_pack(si, p);
+            if (valid && !a_side[k]) {
+                if (j[k] < PLAN_HOT) bpos[k] = bstart + (int64_t)atomicAdd(&hot[j[k]], 1u);
+                else bpos[k] = (int64_t)atomicAdd(&cur[n + j[k]], 1ull);
             }
         }
-        const WaveRun w = wave_run(key);
-        const uint64_t take = __ballot(a_side) & w.run;
-        unsigned long long base = 0;
-        if (lane == w.head && take) base = atomicAdd(&cur[key], (unsigned long long)__popcll(take));
-        base = (unsigned long long)__shfl((long long)base, (int)w.head, 64);
-        if (a_side) ent[base + __popcll(take & w.before)] = packed;
+        // A side: one cursor atomic per row run
+#pragma unroll
+        for (int k = 0; k < PLAN_ILP; k++) {
+            const WaveRun w = wave_run(i[k]);
+            const uint64_t take = __ballot(a_side[k]) & w.run;
+            unsigned long long abase = 0;
+            if (lane == w.head && take) abase = atomicAdd(&cur[i[k]], (unsigned long long)__popcll(take));
+            abase = (unsigned long long)__shfl((long long)abase, (int)w.head, 64);
+            if (a_side[k]) ent[abase + __popcll(take & w.before)] = pj[k];
+            if (bpos[k] >= 0) ent[bpos[k]] = bval[k];
+        }
     }
 }
 
@@ -195,33 +217,20 @@ __device__ __forceinline__ int64_t plan_row_of(const int64_t *__restrict__ irp, 
     return lo;
 }
 
-__global__ void k_plan_item_work(const int64_t *__restrict__ Lrp, int64_t n,
-                                 const int64_t *__restrict__ trp, const int64_t *__restrict__ irp,
-                                 const uint64_t *__restrict__ ent, int64_t nitems,
-                                 uint64_t *__restrict__ item, int32_t *__restrict__ item_row,
-                                 int64_t *__restrict__ work)
+__global__ void k_plan_item_work(int64_t n, const int64_t *__restrict__ trp, const int64_t *__restrict__ irp,
+                                 int64_t nitems, uint64_t *__restrict__ item, int32_t *__restrict__ item_row)
 {
-    const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
     const int64_t nv = 2 * n;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nitems;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = plan_row_of(irp, nv, k);
         const int64_t e0 = trp[r] + 64 * (k - irp[r]);
         const int64_t e1 = min(trp[r + 1], e0 + 64);
-        const int64_t m = r < n ? r : r - n;
-        int64_t ids = 0;
-        for (int64_t e = e0; e < e1; e++) ids += (int64_t)(ent[e] & lmask);
-        const int64_t units = (ids + 63) >> 6;
-        int64_t w = TC_COST_ITEM + TC_COST_BATCH * ((units + TC_FLAT_INFLIGHT - 1) / TC_FLAT_INFLIGHT);
-        if (k == irp[r]) w += TC_COST_MARK * ((Lrp[m + 1] - Lrp[m] + 63) >> 6);
         item[k] = ((uint64_t)e0 << TC_PLAN_CNT_BITS) | (uint64_t)(e1 - e0);
-        item_row[k] = (int32_t)m;
-        work[k] = w;
+        item_row[k] = (int32_t)(r < n ? r : r - n);
     }
 }
 
-// Each workgroup writes its count to partial[blockIdx.x]; k_sum_partials
-// adds them (atomics on one address from every wavefront would serialise).
 // Workgroups are dispatched to the 8 XCDs in turn (workgroup b runs on XCD
 // b mod 8), and each XCD has its own L2: the waves of workgroup b take their
 // items from the counter of eighth b mod 8 first (tc_dyn_wave).  Each
@@ -265,7 +274,6 @@ void tc_plan_free(lagr_graph G)
     const size_t nv1 = (size_t)(2 * P->n + 1);
     dev_free(P->trp, 8 * nv1);
     dev_free(P->irp, 8 * nv1);
-    dev_free(P->iprefix, 8 * (size_t)(P->nitems + 1));
     dev_free(P->ent, 8 * (size_t)(P->nent > 0 ? P->nent : 1));
     dev_free(P->item, 8 * (size_t)(P->nitems > 0 ? P->nitems : 1));
     dev_free(P->item_row, 4 * (size_t)(P->nitems > 0 ? P->nitems : 1));
@@ -309,9 +317,8 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, char *msg)
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
     }
     if ((rc = scan_exclusive_i64(ctx, P->trp, P->trp, nv + 1, &P->nent, msg)) < 0) return fail(rc);
-    int64_t bstart = 0;
-    if (n > 0 && (rc = read_back(ctx, &bstart, P->trp + n, sizeof(bstart), msg)) < 0) return fail(rc);
-    if (P->nent - bstart >= ((int64_t)1 << 32))
+    // hot B rows address the B side (from trp[n]) with 32-bit offsets
+    if (P->nent >= ((int64_t)1 << 32))
         return fail(lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "L too large for the count plan"));
     P->ent = (uint64_t *)dev_alloc(8 * (size_t)(P->nent > 0 ? P->nent : 1));
     unsigned long long *cur = (unsigned long long *)ws_get(ctx, WS_TC_WORK, 8 * (size_t)(nv > 0 ? nv : 1));
@@ -321,24 +328,21 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, char *msg)
             return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan copy"));
         if (nnz > 0)
             hipLaunchKernelGGL(k_plan_fill, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx,
-                               nnz, rowpk, n, P->trp, bstart, boff, cur, P->ent);
+                               nnz, rowpk, n, P->trp, boff, cur, P->ent);
         hipLaunchKernelGGL(k_plan_items, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, ctx->stream, P->trp,
                            nv, P->irp);
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
     }
     if ((rc = fill_i64(ctx, P->irp + nv, 1, 0, msg)) < 0) return fail(rc);
     if ((rc = scan_exclusive_i64(ctx, P->irp, P->irp, nv + 1, &P->nitems, msg)) < 0) return fail(rc);
-    P->iprefix = (int64_t *)dev_alloc(8 * (size_t)(P->nitems + 1));
     P->item = (uint64_t *)dev_alloc(8 * (size_t)(P->nitems > 0 ? P->nitems : 1));
     P->item_row = (int32_t *)dev_alloc(4 * (size_t)(P->nitems > 0 ? P->nitems : 1));
-    if (!P->iprefix || !P->item || !P->item_row) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
+    if (!P->item || !P->item_row) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
     if (P->nitems > 0) {
         hipLaunchKernelGGL(k_plan_item_work, dim3(grid_for(P->nitems, 256, 16384)), dim3(256), 0, ctx->stream,
-                           Lm->rowptr, n, P->trp, P->irp, P->ent, P->nitems, P->item, P->item_row, P->iprefix);
+                           n, P->trp, P->irp, P->nitems, P->item, P->item_row);
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
     }
-    if ((rc = fill_i64(ctx, P->iprefix + P->nitems, 1, 0, msg)) < 0) return fail(rc);
-    if ((rc = scan_exclusive_i64(ctx, P->iprefix, P->iprefix, P->nitems + 1, nullptr, msg)) < 0) return fail(rc);
     return LAGR_SUCCESS;
 }
 
@@ -384,7 +388,7 @@ static int tc_on_lower(lagr_ctx ctx, const lagr_graph G, int64_t *ntri, char *ms
     if (P->nitems > 0) {
         unsigned long long *ctr = tot + 1 + blocks;
         TRY(fill_i64(ctx, (int64_t *)ctr, (int64_t)nctr, 0, msg));
-        PlanArgs a{P->nitems, L->rowptr, L->colidx, P->iprefix, P->ent, P->item, P->item_row};
+        PlanArgs a{P->nitems, L->rowptr, L->colidx, nullptr, P->ent, P->item, P->item_row};
         TIMED(ctx, "tc_split",
               hipLaunchKernelGGL(k_tc_split, dim3(blocks), dim3(TC_BLOCK), 0, ctx->stream, a, tot + 1, ctr));
         LAUNCH_CHECK();

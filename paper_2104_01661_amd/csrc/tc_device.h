@@ -431,7 +431,6 @@ struct TcPlan {
     int64_t nitems = 0;
     int64_t *trp = nullptr;      // 2n+1 entry offsets of the virtual rows
     int64_t *irp = nullptr;      // 2n+1 item offsets of the virtual rows
-    int64_t *iprefix = nullptr;  // nitems+1 exclusive work prefix of the items
     uint64_t *ent = nullptr;     // nent packed segments
     uint64_t *item = nullptr;    // nitems: (first entry << TC_PLAN_CNT_BITS) | count
     int32_t *item_row = nullptr; // nitems: row of L the item marks
@@ -441,7 +440,7 @@ struct PlanArgs {
     int64_t nitems;
     const int64_t *Lrp;
     const int32_t *Lci;
-    const int64_t *iprefix;
+    const int64_t *iprefix;   // exclusive work prefix of the items (static split; many-graph batch)
     const uint64_t *ent;
     const uint64_t *item;
     const int32_t *item_row;
