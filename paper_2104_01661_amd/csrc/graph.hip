@@ -294,7 +294,8 @@ __global__ void k_sort_short(const int32_t *__restrict__ rowL, const int64_t *__
 }
 
 // Rows of SORT_SHORT + 1 .. SORT_LONG ids (listed in rows[0 .. *count)):
-// one wave per row, a bitonic network over the row in the wave's LDS.  The row's source is P at the offset of its vertex in A
+// one wave per row, a bitonic network over the row in the wave's LDS.
+// Longer rows set *too_long and stay unsorted.  The row's source is P at the offset of its vertex in A
 // (order[r] >> oshift is the vertex with new label r).
 constexpr int SORT_LONG = 2048;
 
@@ -328,7 +329,8 @@ __global__ __launch_bounds__(256) void k_sort_long(const int32_t *__restrict__ r
                                                    const unsigned long long *__restrict__ count,
                                                    const int64_t *__restrict__ Lrp, const uint64_t *__restrict__ order,
                                                    int oshift, const int64_t *__restrict__ rpA,
-                                                   const int32_t *__restrict__ P, int32_t *__restrict__ Lci)
+                                                   const int32_t *__restrict__ P, int32_t *__restrict__ Lci,
+                                                   unsigned long long *__restrict__ too_long)
 {
     __shared__ int32_t buf[4][SORT_LONG];
     int32_t *x = buf[threadIdx.x / 64];
@@ -339,6 +341,10 @@ __global__ __launch_bounds__(256) void k_sort_long(const int32_t *__restrict__ r
     for (int64_t c = wave; c < nrows; c += nw) {
         const int32_t r = rows[c];
         const int64_t b = Lrp[r];
+        if (Lrp[r + 1] - b > SORT_LONG) {   // left to the radix sort (status[1])
+            if (lane == 0) too_long[0] = 1ull;
+            continue;
+        }
         const int len = (int)(Lrp[r + 1] - b);
         const int32_t *src = P + rpA[order[r] >> oshift];
         int N = 1;
@@ -374,6 +380,27 @@ __global__ void k_row_keys(const int32_t *__restrict__ rowL, const int64_t *__re
         const int32_t x = P[rpA[order[r] >> oshift] + (o - Lrp[r])];
         keys[o] = ((uint64_t)r << vbits) | (uint64_t)x;
     }
+}
+
+// status[0] = the longest row of L (one atomic per workgroup).
+__global__ __launch_bounds__(256) void k_row_max(const int64_t *__restrict__ rp, int64_t n,
+                                                 unsigned long long *__restrict__ status)
+{
+    __shared__ unsigned long long m_s;
+    if (threadIdx.x == 0) m_s = 0;
+    __syncthreads();
+    unsigned long long m = 0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long len = (unsigned long long)(rp[r + 1] - rp[r]);
+        m = len > m ? len : m;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(m, o, 64);
+        m = y > m ? y : m;
+    }
+    if (lane_id() == 0 && m) atomicMax(&m_s, m);
+    __syncthreads();
+    if (threadIdx.x == 0 && m_s) atomicMax(&status[0], m_s);
 }
 
 __global__ void k_keys_split(const uint64_t *__restrict__ keys, int64_t nnz, int vbits, uint64_t vmask,
@@ -636,8 +663,15 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
                            cnt);
         LAUNCH_CHECK();
     }
-    int64_t nnz = 0;
-    TRY(scan_exclusive_i64(ctx, cnt, cnt, n + 1, &nnz, msg));
+    // A is symmetric without self-loops (checked above), so L holds exactly
+    // half of its entries: no host round trip for the count (checked
+    // against the scan's total with the status read below)
+    if (nnzA % 2 != 0) return lagr_fail(msg, LAGR_INVALID_OBJECT, "odd entry count in a symmetric matrix");
+    const int64_t nnz = nnzA / 2;
+    TRY(scan_exclusive_i64(ctx, cnt, cnt, n + 1, nullptr, msg));
+    unsigned long long *status = (unsigned long long *)ws_get(ctx, WS_COUNTERS, 64);
+    if (!status) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
+    TRY(fill_i64(ctx, (int64_t *)status, 8, 0, msg));
     lagr_matrix L = new (std::nothrow) lagr_matrix_s();
     if (!L) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "matrix");
     L->type = LAGR_BOOL;
@@ -649,84 +683,74 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
         return rc;
     }
     int32_t *rowid = (int32_t *)ws_get(ctx, WS_GEN_A, sizeof(int32_t) * (nnz > 0 ? nnz : 1));
-    if (!rowid) {
+    int32_t *lrows = (int32_t *)ws_get(ctx, WS_CHUNK_A, sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    unsigned long long *nlong = (unsigned long long *)ws_get(ctx, WS_CHUNK_B, 64);
+    if (!rowid || !lrows || !nlong) {
         rc = lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
         goto fail;
     }
-    // 3. the rows are sorted from P into L
+    // 3. the rows are sorted from P into L: rows of at most SORT_SHORT ids
+    //    by rank, rows up to SORT_LONG by a bitonic network in LDS (listed
+    //    on the device), longer rows (flagged in status[1]) by a radix sort
     if (hipMemcpyAsync(L->rowptr, cnt, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, ctx->stream) !=
         hipSuccess) {
         rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "relabel copy");
         goto fail;
     }
-    {
-        int64_t *tmp = (int64_t *)ws_get(ctx, WS_FLAGS, sizeof(int64_t) * (n > 0 ? n : 1));
-        int64_t mx = 0;
-        if (!tmp) {
-            rc = lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
-            goto fail;
-        }
-        if ((rc = row_degrees(ctx, L->rowptr, n, tmp, &mx, msg)) < 0) goto fail;
-        G->L_maxrow = mx;
-    }
-    // the row of every entry of L (the plan reads it too); rows of L are
-    // short (the longest is L_maxrow), so no chunk list is needed
     if (n > 0) {
+        hipLaunchKernelGGL(k_row_max, dim3(grid_for(n, 256, 1024)), dim3(256), 0, ctx->stream, L->rowptr, n, status);
+        // the row of every entry of L (the plan reads it too)
         hipLaunchKernelGGL(k_row_ids, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, L->rowptr, n,
                            (int64_t)INT64_MAX, rowid);
-        if (hipGetLastError() != hipSuccess) {
-            rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row id launch failed");
-            goto fail;
-        }
-    }
-    if (nnz > 0 && G->L_maxrow <= SORT_LONG) {
-        hipLaunchKernelGGL(k_sort_short, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, ctx->stream, rowid,
-                           L->rowptr, okeys, dbits, A->rowptr, P, nnz, L->colidx);
+        if (nnz > 0)
+            hipLaunchKernelGGL(k_sort_short, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, ctx->stream, rowid,
+                               L->rowptr, okeys, dbits, A->rowptr, P, nnz, L->colidx);
         if (hipGetLastError() != hipSuccess) {
             rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
             goto fail;
         }
-        if (G->L_maxrow > SORT_SHORT) {
-            // the rows over SORT_SHORT, listed and counted on the device
-            int32_t *lrows = (int32_t *)ws_get(ctx, WS_CHUNK_A, sizeof(int32_t) * (size_t)n);
-            unsigned long long *nlong = (unsigned long long *)ws_get(ctx, WS_CHUNK_B, 64);
-            if (!lrows || !nlong) {
-                rc = lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
-                goto fail;
-            }
-            if ((rc = fill_i64(ctx, (int64_t *)nlong, 1, 0, msg)) < 0) goto fail;
-            hipLaunchKernelGGL(k_list_long_rows, dim3(grid_for(n, 256, 1024)), dim3(256), 0, ctx->stream, L->rowptr,
-                               n, SORT_SHORT, lrows, nlong);
-            hipLaunchKernelGGL(k_sort_long, dim3((unsigned)(ctx->num_cus * 16)), dim3(256), 0, ctx->stream, lrows,
-                               nlong, L->rowptr, okeys, dbits, A->rowptr, P, L->colidx);
-            if (hipGetLastError() != hipSuccess) {
-                rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
-                goto fail;
-            }
-        }
-    } else if (nnz > 0) {
-        uint64_t *keys = (uint64_t *)ws_get(ctx, WS_KEYS, sizeof(uint64_t) * nnz);
-        if (!keys) {
-            rc = lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
-            goto fail;
-        }
-        hipLaunchKernelGGL(k_row_keys, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, ctx->stream, rowid,
-                           L->rowptr, okeys, dbits, A->rowptr, P, nnz, vbits, keys);
-        if (hipGetLastError() != hipSuccess) {
-            rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
-            goto fail;
-        }
-        if ((rc = radix_sort_u64(ctx, keys, nnz, 2 * vbits, msg)) < 0) goto fail;
-        hipLaunchKernelGGL(k_keys_split, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, ctx->stream, keys, nnz,
-                           vbits, vmask, L->colidx, rowid);
+        if ((rc = fill_i64(ctx, (int64_t *)nlong, 1, 0, msg)) < 0) goto fail;
+        hipLaunchKernelGGL(k_list_long_rows, dim3(grid_for(n, 256, 1024)), dim3(256), 0, ctx->stream, L->rowptr, n,
+                           SORT_SHORT, lrows, nlong);
+        hipLaunchKernelGGL(k_sort_long, dim3((unsigned)(ctx->num_cus * 16)), dim3(256), 0, ctx->stream, lrows, nlong,
+                           L->rowptr, okeys, dbits, A->rowptr, P, L->colidx, status + 1);
         if (hipGetLastError() != hipSuccess) {
             rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
             goto fail;
         }
     }
     G->L = L;
-    if ((rc = tc_plan_build(ctx, G, rowid, msg)) < 0) {
+    for (int attempt = 0;; attempt++) {
+        if ((rc = tc_plan_build(ctx, G, rowid, msg)) < 0) break;
+        bool unsorted = false;
+        if ((rc = tc_plan_settle(ctx, G, status, nnz, &unsorted, msg)) < 0) break;
+        if (!unsorted || attempt > 0) break;
+        // a row longer than SORT_LONG: sort every row with a global radix
+        // sort of (row, id) keys and build the plan again
+        tc_plan_free(G);
+        uint64_t *keys = (uint64_t *)ws_get(ctx, WS_KEYS, sizeof(uint64_t) * nnz);
+        if (!keys) {
+            rc = lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
+            break;
+        }
+        hipLaunchKernelGGL(k_row_keys, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, ctx->stream, rowid,
+                           L->rowptr, okeys, dbits, A->rowptr, P, nnz, vbits, keys);
+        if (hipGetLastError() != hipSuccess) {
+            rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
+            break;
+        }
+        if ((rc = radix_sort_u64(ctx, keys, nnz, 2 * vbits, msg)) < 0) break;
+        hipLaunchKernelGGL(k_keys_split, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, ctx->stream, keys, nnz,
+                           vbits, vmask, L->colidx, rowid);
+        if (hipGetLastError() != hipSuccess) {
+            rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
+            break;
+        }
+    }
+    if (rc < 0) {
+        tc_plan_free(G);
         G->L = nullptr;
+        G->L_maxrow = -1;
         goto fail;
     }
     return lagr_ok(msg);

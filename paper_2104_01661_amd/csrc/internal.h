@@ -184,6 +184,12 @@ static inline lagr_matrix graph_in_edges(const lagr_graph G)
 
 // Build / release G->tcplan from G->L and the row of each entry of L.
 int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, char *msg);
+// One host round trip after the build: status[0] (the longest row of L)
+// and status[1] (rows left unsorted, *unsorted) come from the caller's
+// kernels; sets G->L_maxrow and the plan's entry and item counts, and
+// checks that L has nnz entries.
+int tc_plan_settle(lagr_ctx ctx, lagr_graph G, unsigned long long *status, int64_t nnz, bool *unsorted,
+                   char *msg);
 void tc_plan_free(lagr_graph G);
 
 // Rows of A longer than this are cut into chunks of this many entries for

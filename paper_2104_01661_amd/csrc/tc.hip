@@ -217,10 +217,12 @@ __device__ __forceinline__ int64_t plan_row_of(const int64_t *__restrict__ irp, 
     return lo;
 }
 
+// Item descriptors over a capacity; the item count is irp[nv], on the
+// device (the plan is built without a host round trip).
 __global__ void k_plan_item_work(int64_t n, const int64_t *__restrict__ trp, const int64_t *__restrict__ irp,
-                                 int64_t nitems, uint64_t *__restrict__ item, int32_t *__restrict__ item_row)
+                                 uint64_t *__restrict__ item, int32_t *__restrict__ item_row)
 {
-    const int64_t nv = 2 * n;
+    const int64_t nv = 2 * n, nitems = irp[nv];
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nitems;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = plan_row_of(irp, nv, k);
@@ -274,22 +276,31 @@ void tc_plan_free(lagr_graph G)
     const size_t nv1 = (size_t)(2 * P->n + 1);
     dev_free(P->trp, 8 * nv1);
     dev_free(P->irp, 8 * nv1);
-    dev_free(P->ent, 8 * (size_t)(P->nent > 0 ? P->nent : 1));
-    dev_free(P->item, 8 * (size_t)(P->nitems > 0 ? P->nitems : 1));
-    dev_free(P->item_row, 4 * (size_t)(P->nitems > 0 ? P->nitems : 1));
+    dev_free(P->ent, 8 * (size_t)(P->ent_cap > 0 ? P->ent_cap : 1));
+    dev_free(P->item, 8 * (size_t)(P->item_cap > 0 ? P->item_cap : 1));
+    dev_free(P->item_row, 4 * (size_t)(P->item_cap > 0 ? P->item_cap : 1));
     delete P;
     G->tcplan = nullptr;
 }
 
+// Built without a host round trip: the entries take at most one slot per
+// entry of L and the items at most nnz/64 + one per non-empty virtual row,
+// so both arrays are allocated at those bounds.  The entry and item counts
+// are trp[2n] and irp[2n] on the device; the caller reads them back (with
+// the rest of its status) and sets P->nent and P->nitems.
 int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, char *msg)
 {
     const lagr_matrix Lm = G->L;
     const int64_t n = Lm->nrows, nv = 2 * n;
-    if (Lm->nvals >= ((int64_t)1 << (64 - TC_PLAN_LEN_BITS)))
+    const int64_t nnz = Lm->nvals;
+    if (nnz >= ((int64_t)1 << 32))
         return lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "L too large for the count plan");
     TcPlan *P = new (std::nothrow) TcPlan();
     if (!P) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan");
     P->n = n;
+    P->nent = P->nitems = -1;
+    P->ent_cap = nnz;
+    P->item_cap = nnz / 64 + (nv < nnz ? nv : nnz) + 1;
     G->tcplan = P;
     auto fail = [&](int rc) {
         tc_plan_free(G);
@@ -297,15 +308,17 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, char *msg)
     };
     P->trp = (int64_t *)dev_alloc(8 * (size_t)(nv + 1));
     P->irp = (int64_t *)dev_alloc(8 * (size_t)(nv + 1));
-    if (!P->trp || !P->irp) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
+    P->ent = (uint64_t *)dev_alloc(8 * (size_t)(P->ent_cap > 0 ? P->ent_cap : 1));
+    P->item = (uint64_t *)dev_alloc(8 * (size_t)P->item_cap);
+    P->item_row = (int32_t *)dev_alloc(4 * (size_t)P->item_cap);
+    if (!P->trp || !P->irp || !P->ent || !P->item || !P->item_row)
+        return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
     int rc;
     if ((rc = fill_i64(ctx, P->trp, nv + 1, 0, msg)) < 0) return fail(rc);
-    const int64_t nnz = Lm->nvals;
-    if (G->L_maxrow >= ((int64_t)1 << TC_PLAN_LEN_BITS))
-        return fail(lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "rows of L too long for the count plan"));
     unsigned *boff = (unsigned *)ws_get(ctx, WS_GEN_H, sizeof(unsigned) * (size_t)PLAN_GRID * PLAN_HOT);
     uint64_t *rowpk = (uint64_t *)ws_get(ctx, WS_GEN_E, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
-    if (!boff || !rowpk) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
+    unsigned long long *cur = (unsigned long long *)ws_get(ctx, WS_TC_WORK, 8 * (size_t)(nv > 0 ? nv : 1));
+    if (!boff || !rowpk || !cur) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
     if (n > 0) {
         hipLaunchKernelGGL(k_row_pack, dim3(grid_for(n, 256, 16384)), dim3(256), 0, ctx->stream, Lm->rowptr, n,
                            rowpk);
@@ -316,13 +329,7 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, char *msg)
                            rowpk, n, (unsigned long long *)P->trp, boff);
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
     }
-    if ((rc = scan_exclusive_i64(ctx, P->trp, P->trp, nv + 1, &P->nent, msg)) < 0) return fail(rc);
-    // hot B rows address the B side (from trp[n]) with 32-bit offsets
-    if (P->nent >= ((int64_t)1 << 32))
-        return fail(lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "L too large for the count plan"));
-    P->ent = (uint64_t *)dev_alloc(8 * (size_t)(P->nent > 0 ? P->nent : 1));
-    unsigned long long *cur = (unsigned long long *)ws_get(ctx, WS_TC_WORK, 8 * (size_t)(nv > 0 ? nv : 1));
-    if (!P->ent || !cur) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
+    if ((rc = scan_exclusive_i64(ctx, P->trp, P->trp, nv + 1, nullptr, msg)) < 0) return fail(rc);
     if (n > 0) {
         if (hipMemcpyAsync(cur, P->trp, 8 * (size_t)nv, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
             return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan copy"));
@@ -334,15 +341,50 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, char *msg)
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
     }
     if ((rc = fill_i64(ctx, P->irp + nv, 1, 0, msg)) < 0) return fail(rc);
-    if ((rc = scan_exclusive_i64(ctx, P->irp, P->irp, nv + 1, &P->nitems, msg)) < 0) return fail(rc);
-    P->item = (uint64_t *)dev_alloc(8 * (size_t)(P->nitems > 0 ? P->nitems : 1));
-    P->item_row = (int32_t *)dev_alloc(4 * (size_t)(P->nitems > 0 ? P->nitems : 1));
-    if (!P->item || !P->item_row) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
-    if (P->nitems > 0) {
-        hipLaunchKernelGGL(k_plan_item_work, dim3(grid_for(P->nitems, 256, 16384)), dim3(256), 0, ctx->stream,
-                           n, P->trp, P->irp, P->nitems, P->item, P->item_row);
+    if ((rc = scan_exclusive_i64(ctx, P->irp, P->irp, nv + 1, nullptr, msg)) < 0) return fail(rc);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_plan_item_work, dim3(grid_for(P->item_cap, 256, 16384)), dim3(256), 0, ctx->stream,
+                           n, P->trp, P->irp, P->item, P->item_row);
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
     }
+    return LAGR_SUCCESS;
+}
+
+namespace {
+
+// status[2..4] = plan entries, plan items, entries of L.
+__global__ void k_tc_status(const int64_t *__restrict__ nent, const int64_t *__restrict__ nitems,
+                            const int64_t *__restrict__ nnzL, unsigned long long *__restrict__ status)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        status[2] = (unsigned long long)*nent;
+        status[3] = (unsigned long long)*nitems;
+        status[4] = (unsigned long long)*nnzL;
+    }
+}
+
+}  // namespace
+
+int tc_plan_settle(lagr_ctx ctx, lagr_graph G, unsigned long long *status, int64_t nnz, bool *unsorted, char *msg)
+{
+    TcPlan *P = G->tcplan;
+    const int64_t n = G->L->nrows;
+    hipLaunchKernelGGL(k_tc_status, dim3(1), dim3(64), 0, ctx->stream, P->trp + 2 * n, P->irp + 2 * n,
+                       G->L->rowptr + n, status);
+    LAUNCH_CHECK();
+    unsigned long long st[5] = {0, 0, 0, 0, 0};
+    TRY(read_back(ctx, st, status, sizeof(st), msg));
+    if ((int64_t)st[4] != nnz)
+        return lagr_fail(msg, LAGR_INVALID_OBJECT, "L has %lld entries, expected %lld", (long long)st[4],
+                         (long long)nnz);
+    *unsorted = st[1] != 0;
+    if (st[0] >= ((unsigned long long)1 << TC_PLAN_LEN_BITS))
+        return lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "rows of L too long for the count plan");
+    if (st[2] >= ((unsigned long long)1 << 32))
+        return lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "L too large for the count plan");
+    G->L_maxrow = (int64_t)st[0];
+    P->nent = (int64_t)st[2];
+    P->nitems = (int64_t)st[3];
     return LAGR_SUCCESS;
 }
 

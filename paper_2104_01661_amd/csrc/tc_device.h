@@ -427,8 +427,10 @@ constexpr int64_t TC_COST_MARK = 1;
 
 struct TcPlan {
     int64_t n = 0;          // rows of L
-    int64_t nent = 0;       // entries over both sides
+    int64_t nent = 0;       // entries over both sides (set once read back)
     int64_t nitems = 0;
+    int64_t ent_cap = 0;    // allocated entries (>= nent) and items (>= nitems)
+    int64_t item_cap = 0;
     int64_t *trp = nullptr;      // 2n+1 entry offsets of the virtual rows
     int64_t *irp = nullptr;      // 2n+1 item offsets of the virtual rows
     uint64_t *ent = nullptr;     // nent packed segments
