@@ -419,8 +419,8 @@ int lagr_cc(lagr_vector *component, int64_t *iters, const lagr_graph G, lagr_ctx
 typedef struct lagr_batch_s *lagr_batch;
 typedef struct {
     int32_t blocks_per_cu; /* workgroups of 4 wavefronts per compute unit, 1..16 */
-    int32_t row_charge;    /* fixed cost per work item in the balanced partition, >= 1
-                              (one unit = one round of streamed loads) */
+    int32_t row_charge;    /* work items a wavefront takes per grab from the work
+                              counters (the grain of the dynamic split), >= 1 */
     int32_t use_graph;     /* capture the launch once into a hipGraph and replay it */
 } lagr_tune;
 int lagr_batch_new(lagr_batch *B, const lagr_graph *graphs, int64_t ngraphs, lagr_ctx ctx,

@@ -5,12 +5,12 @@
 // ids, int64 row offsets into one shared id array, segment descriptors
 // re-based onto that array, work items re-based onto the packed
 // descriptors and onto global rows, and the graph of every item.  One
-// kernel (the plan's wave loop) covers every item of every graph and adds
-// each graph's count to its own counter.  The launch -- counter reset and
-// count kernel -- is captured once into a hipGraph on a stream the batch
-// owns and replayed on every call; the grid size and the fixed per-item
-// charge of the balanced partition are picked by timing a small grid of
-// candidates (lagr_batch_autotune).
+// kernel (the plan's wave loop, taking items from per-XCD work counters)
+// covers every item of every graph and adds each graph's count to its own
+// counter.  The launch -- counter reset and count kernel -- is captured once
+// into a hipGraph on a stream the batch owns and replayed on every call; the
+// grid size and the number of items taken per grab are picked by timing a
+// small grid of candidates (lagr_batch_autotune).
 #include <new>
 #include <vector>
 
@@ -27,15 +27,13 @@ struct lagr_batch_s {
     uint64_t *item = nullptr;       // K packed items
     int32_t *item_row = nullptr;    // K global rows
     int32_t *item_graph = nullptr;  // K graph ids
-    int64_t *prefix = nullptr;      // K + 1 work prefix for prefix_charge
-    int64_t prefix_charge = -1;
-    unsigned long long *counts = nullptr;   // ng
+    unsigned long long *counts = nullptr;   // ng per-graph counts, then the work counters
     int64_t *host_counts = nullptr;         // pinned, ng
     hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     lagr_tune exec_tune{};
-    lagr_tune tune{8, (int32_t)TC_COST_ITEM, 1};
+    lagr_tune tune{8, (int32_t)TC_DYN_ITEMS, 1};
     hipEvent_t ready = nullptr;
 };
 
@@ -77,35 +75,15 @@ __global__ void k_pack_items(const int32_t *__restrict__ row, int64_t n, int32_t
     }
 }
 
-// Cost of each packed item (the round-trip model of the single-graph
-// plan, with `charge` as the fixed cost per item): the marked row's cost
-// goes to the first item of the row.
-__global__ void k_batch_item_work(const uint64_t *__restrict__ item, const int32_t *__restrict__ item_row,
-                                  const uint64_t *__restrict__ ent, const int64_t *__restrict__ rp, int64_t K,
-                                  int64_t charge, int64_t *__restrict__ work)
-{
-    const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t it = item[k];
-        const int64_t e0 = (int64_t)(it >> TC_PLAN_CNT_BITS);
-        const int cnt = (int)(it & ((1u << TC_PLAN_CNT_BITS) - 1));
-        int64_t ids = 0;
-        for (int c = 0; c < cnt; c++) ids += (int64_t)(ent[e0 + c] & lmask);
-        const int64_t units = (ids + 63) >> 6;
-        int64_t w = charge + TC_COST_BATCH * ((units + TC_FLAT_INFLIGHT - 1) / TC_FLAT_INFLIGHT);
-        const int32_t m = item_row[k];
-        if (k == 0 || item_row[k - 1] != m) w += TC_COST_MARK * ((rp[m + 1] - rp[m] + 63) >> 6);
-        work[k] = w;
-    }
-}
-
-__global__ __launch_bounds__(TC_BLOCK, 8) void k_tc_batched(PlanArgs a)
+// Items taken `grain` at a time from per-XCD counters (ctr, zeroed with
+// the per-graph counts before each launch), as in the single-graph count.
+__global__ __launch_bounds__(TC_BLOCK, 8) void k_tc_batched(PlanArgs a, unsigned long long *ctr, int64_t grain)
 {
     __shared__ TcWaveLds lds[TC_WAVES];
-    const int64_t w = (int64_t)blockIdx.x * TC_WAVES + threadIdx.x / 64;
-    tc_split_wave<true>(a, lds[threadIdx.x / 64], w, (int64_t)gridDim.x * TC_WAVES);
+    tc_dyn_wave<true>(a, lds[threadIdx.x / 64], ctr, (int)(blockIdx.x % TC_DYN_PARTS), grain);
 }
+
+constexpr int64_t BATCH_CTRS = (int64_t)TC_DYN_STRIDE * TC_DYN_PARTS;   // after the ng counts
 
 PlanArgs batch_args(const lagr_batch B)
 {
@@ -113,7 +91,6 @@ PlanArgs batch_args(const lagr_batch B)
     a.nitems = B->K;
     a.Lrp = B->rp;
     a.Lci = B->ci;
-    a.iprefix = B->prefix;
     a.ent = B->ent;
     a.item = B->item;
     a.item_row = B->item_row;
@@ -130,31 +107,17 @@ int check_tune(const lagr_tune &t, char *msg)
     return LAGR_SUCCESS;
 }
 
-// work prefix for the given per-item charge
-int batch_prefix(lagr_ctx ctx, lagr_batch B, int64_t charge, char *msg)
-{
-    if (B->prefix_charge == charge) return LAGR_SUCCESS;
-    TRY(fill_i64(ctx, B->prefix + B->K, 1, 0, msg));
-    if (B->K > 0) {
-        hipLaunchKernelGGL(k_batch_item_work, dim3(grid_for(B->K, 256, 16384)), dim3(256), 0, ctx->stream, B->item,
-                           B->item_row, B->ent, B->rp, B->K, charge, B->prefix);
-        LAUNCH_CHECK();
-    }
-    TRY(scan_exclusive_i64(ctx, B->prefix, B->prefix, B->K + 1, nullptr, msg));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    B->prefix_charge = charge;
-    return LAGR_SUCCESS;
-}
-
 // counter reset + count kernel on stream s (what the hipGraph holds)
 int enqueue_count(lagr_batch B, hipStream_t s, const lagr_tune &t, char *msg)
 {
-    hipLaunchKernelGGL(k_fill_u64_batch, dim3(grid_for(B->ng, 256, 1024)), dim3(256), 0, s, B->counts,
-                       B->ng);
+    hipLaunchKernelGGL(k_fill_u64_batch, dim3(grid_for(B->ng + BATCH_CTRS, 256, 1024)), dim3(256), 0, s, B->counts,
+                       B->ng + BATCH_CTRS);
     LAUNCH_CHECK();
     if (B->K > 0) {
-        hipLaunchKernelGGL(k_tc_batched, dim3((unsigned)(B->num_cus * t.blocks_per_cu)), dim3(TC_BLOCK), 0,
-                           s, batch_args(B));
+        // a multiple of 8 workgroups, so every XCD gets the same number
+        const unsigned blocks = (unsigned)(B->num_cus * t.blocks_per_cu);
+        hipLaunchKernelGGL(k_tc_batched, dim3(blocks), dim3(TC_BLOCK), 0, s, batch_args(B), B->counts + B->ng,
+                           (int64_t)t.row_charge);
         LAUNCH_CHECK();
     }
     return LAGR_SUCCESS;
@@ -209,10 +172,9 @@ extern "C" int lagr_batch_new(lagr_batch *Bout, const lagr_graph *graphs, int64_
     B->item = (uint64_t *)dev_alloc(8 * one(B->K));
     B->item_row = (int32_t *)dev_alloc(4 * one(B->K));
     B->item_graph = (int32_t *)dev_alloc(4 * one(B->K));
-    B->prefix = (int64_t *)dev_alloc(8 * (B->K + 1));
-    B->counts = (unsigned long long *)dev_alloc(8 * ngraphs);
+    B->counts = (unsigned long long *)dev_alloc(8 * (ngraphs + BATCH_CTRS));
     int rc = LAGR_SUCCESS;
-    if (!B->rp || !B->ci || !B->ent || !B->item || !B->item_row || !B->item_graph || !B->prefix || !B->counts ||
+    if (!B->rp || !B->ci || !B->ent || !B->item || !B->item_row || !B->item_graph || !B->counts ||
         hipHostMalloc(&B->host_counts, 8 * ngraphs, hipHostMallocDefault) != hipSuccess ||
         hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&B->ready, hipEventDisableTiming) != hipSuccess) {
@@ -242,7 +204,6 @@ extern "C" int lagr_batch_new(lagr_batch *Bout, const lagr_graph *graphs, int64_
             rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "pack copy");
     }
     if (rc >= 0) rc = fill_i64(ctx, B->rp + B->R, 1, B->E, msg);
-    if (rc >= 0) rc = batch_prefix(ctx, B, B->tune.row_charge, msg);
     if (rc < 0) {
         lagr_batch_free(&B);
         return rc;
@@ -266,7 +227,6 @@ extern "C" int lagr_tc_batched(int64_t *counts, lagr_batch B, const lagr_tune *t
     if (!counts || !B || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
     const lagr_tune t = tune ? *tune : B->tune;
     TRY(check_tune(t, msg));
-    TRY(batch_prefix(ctx, B, t.row_charge, msg));
     if (t.use_graph) {
         const bool stale = !B->exec || B->exec_tune.blocks_per_cu != t.blocks_per_cu ||
                            B->exec_tune.row_charge != t.row_charge;
@@ -304,7 +264,7 @@ extern "C" int lagr_batch_autotune(lagr_tune *best, lagr_batch B, lagr_ctx ctx, 
 {
     if (!best || !B || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
     static const int bpc[] = {2, 4, 8};
-    static const int charge[] = {1, 2, 4};
+    static const int charge[] = {2, 4, 8};   // items per grab
     std::vector<int64_t> scratch(B->ng);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
@@ -357,8 +317,7 @@ extern "C" int lagr_batch_free(lagr_batch *Bp)
     dev_free(B->item, 8 * one(B->K));
     dev_free(B->item_row, 4 * one(B->K));
     dev_free(B->item_graph, 4 * one(B->K));
-    dev_free(B->prefix, 8 * (B->K + 1));
-    dev_free(B->counts, 8 * B->ng);
+    dev_free(B->counts, 8 * (B->ng + BATCH_CTRS));
     if (B->host_counts) (void)hipHostFree(B->host_counts);
     if (B->ready) (void)hipEventDestroy(B->ready);
     if (B->stream) (void)hipStreamDestroy(B->stream);

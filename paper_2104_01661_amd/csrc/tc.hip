@@ -241,7 +241,8 @@ __global__ __launch_bounds__(TC_BLOCK, 8) void k_tc_split(PlanArgs a, unsigned l
                                                           unsigned long long *__restrict__ ctr)
 {
     __shared__ TcWaveLds lds[TC_WAVES];
-    unsigned long long acc = tc_dyn_wave(a, lds[threadIdx.x / 64], ctr, (int)(blockIdx.x % TC_DYN_PARTS));
+    unsigned long long acc =
+        tc_dyn_wave<false>(a, lds[threadIdx.x / 64], ctr, (int)(blockIdx.x % TC_DYN_PARTS), TC_DYN_ITEMS);
     __shared__ unsigned long long wsum[TC_WAVES];
     if (lane_id() == 0) wsum[threadIdx.x / 64] = acc;
     __syncthreads();
@@ -421,16 +422,20 @@ static int tc_on_lower(lagr_ctx ctx, const lagr_graph G, int64_t *ntri, char *ms
 {
     const lagr_matrix L = G->L;
     const TcPlan *P = G->tcplan;
-    // eight resident waves per SIMD (the LDS and register budgets of
-    // k_tc_split allow it); the work counters follow the partials
-    const unsigned blocks = (unsigned)(ctx->num_cus * 8);
+    // up to eight resident waves per SIMD (the LDS and register budgets of
+    // k_tc_split allow it), fewer for a small plan, and a multiple of 8
+    // workgroups (one eighth of the items per XCD); the work counters follow
+    // the partials
+    const int64_t want = (P->nitems + TC_DYN_ITEMS * TC_WAVES - 1) / (TC_DYN_ITEMS * TC_WAVES);
+    const int64_t most = (int64_t)ctx->num_cus * 8;
+    const unsigned blocks = (unsigned)(((want < most ? want : most) + TC_DYN_PARTS - 1) / TC_DYN_PARTS * TC_DYN_PARTS);
     const size_t nctr = (size_t)TC_DYN_STRIDE * TC_DYN_PARTS;
     unsigned long long *tot = (unsigned long long *)ws_get(ctx, WS_TC, 8 * ((size_t)blocks + 1 + nctr));
     if (!tot) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc counter");
     if (P->nitems > 0) {
         unsigned long long *ctr = tot + 1 + blocks;
         TRY(fill_i64(ctx, (int64_t *)ctr, (int64_t)nctr, 0, msg));
-        PlanArgs a{P->nitems, L->rowptr, L->colidx, nullptr, P->ent, P->item, P->item_row};
+        PlanArgs a{P->nitems, L->rowptr, L->colidx, P->ent, P->item, P->item_row};
         TIMED(ctx, "tc_split",
               hipLaunchKernelGGL(k_tc_split, dim3(blocks), dim3(TC_BLOCK), 0, ctx->stream, a, tot + 1, ctr));
         LAUNCH_CHECK();

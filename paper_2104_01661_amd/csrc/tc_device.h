@@ -414,16 +414,11 @@ int tc_masked_dot(lagr_ctx ctx, const TcArgs &a, bool per_entry, unsigned long l
 // length.  The virtual rows are cut into items of up to 64 entries; an
 // item records its first entry and count and the row it marks.
 //
-// Items are spread over the waves by a static partition of a work prefix
-// that counts dependent memory round trips, the latency that bounds this
-// kernel: the item's own loads, one per pair of 64-id units streamed, and
-// one per 64 ids marked on the first item of a row (later items of the
-// row usually follow in the same wave and keep the marks).
+// Items are handed to waves a few at a time (tc_dyn_wave); consecutive
+// items of a row usually go to the same wave, which then keeps the row's
+// marks.
 constexpr int TC_PLAN_LEN_BITS = 24;
 constexpr int TC_PLAN_CNT_BITS = 7;
-constexpr int64_t TC_COST_ITEM = 2;
-constexpr int64_t TC_COST_BATCH = 1;   // per TC_FLAT_INFLIGHT units streamed
-constexpr int64_t TC_COST_MARK = 1;
 
 struct TcPlan {
     int64_t n = 0;          // rows of L
@@ -442,7 +437,6 @@ struct PlanArgs {
     int64_t nitems;
     const int64_t *Lrp;
     const int32_t *Lci;
-    const int64_t *iprefix;   // exclusive work prefix of the items (static split; many-graph batch)
     const uint64_t *ent;
     const uint64_t *item;
     const int32_t *item_row;
@@ -451,22 +445,31 @@ struct PlanArgs {
     unsigned long long *per_graph = nullptr;
 };
 
-// Wave w of nw takes the items whose work prefix starts in its equal share
-// of the total, marks each item's row (again only when the row changes)
-// and streams its segments.  Returns this wave's count, summed over the
-// wave; with BATCHED each graph's part is added to per_graph[g] instead
-// (the items of one graph are contiguous) and the result is 0.
+// The plan's wave loop: each wave marks each item's row (again only when the
+// row changes) and streams its segments.  Items are handed out dynamically:
+// a static split by a cost model left waves busy for about 60% of the
+// launch at 2^20 (the model misjudges some items), so each wave takes
+// TC_DYN_ITEMS (or the caller's grain) consecutive items at a time from a
+// counter.  There is one counter per XCD (ctr[TC_DYN_STRIDE * x], one
+// cache line each), covering one contiguous eighth of the items, so the
+// waves of an XCD keep working through neighbouring items (their streamed
+// rows stay in that XCD's L2); a wave whose eighth is used up moves on to
+// the next eighth in turn.  The counters must be zero at launch.  With
+// BATCHED each graph's part of the count is added to per_graph[g] (the
+// items of one graph are contiguous) and the result is 0.
+constexpr int64_t TC_DYN_ITEMS = 4;
+constexpr int TC_DYN_STRIDE = 16;   // 128 bytes between counters
+constexpr int TC_DYN_PARTS = 8;
+
 template <bool BATCHED>
-__device__ unsigned long long tc_split_wave(const PlanArgs &a, TcWaveLds &L, int64_t w, int64_t nw)
+__device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsigned long long *ctr, int part,
+                                          int64_t grain)
 {
     const unsigned lane = lane_id();
     for (int x = lane; x < TC_BM_WORDS; x += 64) L.bm[x] = 0u;
     wave_sync();
-    const int64_t T = a.iprefix[a.nitems];
-    const int64_t lo = (int64_t)((__int128)T * w / nw), hi = (int64_t)((__int128)T * (w + 1) / nw);
-    const int64_t k0 = tc_lower_bound(a.iprefix, a.nitems, lo);
-    const int64_t k1 = tc_lower_bound(a.iprefix, a.nitems, hi);
     const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
+    const int64_t N = a.nitems;
     unsigned long long acc = 0;
     int32_t marked = -1, first_id = -1, g = -1;
     int64_t alen = 0;
@@ -478,80 +481,26 @@ __device__ unsigned long long tc_split_wave(const PlanArgs &a, TcWaveLds &L, int
         if (lane == 0 && t && g >= 0) atomicAdd(&a.per_graph[g], t);
         acc = 0;
     };
-    for (int64_t k = k0; k < k1; k++) {
-        if (BATCHED) {
-            const int32_t gk = a.item_graph[k];
-            if (gk != g) {
-                flush();
-                g = gk;
-            }
-        }
-        const uint64_t it = a.item[k];
-        const int32_t m = a.item_row[k];
-        const int64_t e0 = (int64_t)(it >> TC_PLAN_CNT_BITS);
-        const int cnt = (int)(it & ((1u << TC_PLAN_CNT_BITS) - 1));
-        int64_t s = 0;
-        int len = 0;
-        if ((int)lane < cnt) {
-            const uint64_t x = a.ent[e0 + lane];
-            s = (int64_t)(x >> TC_PLAN_LEN_BITS);
-            len = (int)(x & lmask);
-        }
-        if (m != marked) {
-            if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
-            Arow = a.Lci + a.Lrp[m];
-            alen = a.Lrp[m + 1] - a.Lrp[m];
-            use_hash = tc_mark(L, Arow, alen, lane, &first_id);
-            marked = m;
-        }
-        acc += tc_stream_flat(L, use_hash, Arow, alen, a.Lci, s, len, cnt, lane);
-    }
-    if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
-    if (BATCHED) {
-        flush();
-        return 0;
-    }
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    return acc;
-}
-
-// Dynamic form of the same loop.  The static split leaves waves busy for
-// about 60% of the launch at 2^20 (the cost model misjudges some items),
-// so each wave instead takes TC_DYN_ITEMS consecutive items at a time from
-// a counter.  There is one counter per XCD (ctr[TC_DYN_STRIDE * x], one
-// cache line each), covering one contiguous eighth of the items, so the
-// waves of an XCD keep working through neighbouring items (their streamed
-// rows stay in that XCD's L2); a wave whose eighth is used up moves on to
-// the next eighth in turn.  The counters must be zero at launch.
-constexpr int64_t TC_DYN_ITEMS = 4;
-constexpr int TC_DYN_STRIDE = 16;   // 128 bytes between counters
-constexpr int TC_DYN_PARTS = 8;
-
-__device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsigned long long *ctr, int part)
-{
-    const unsigned lane = lane_id();
-    for (int x = lane; x < TC_BM_WORDS; x += 64) L.bm[x] = 0u;
-    wave_sync();
-    const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
-    const int64_t N = a.nitems;
-    unsigned long long acc = 0;
-    int32_t marked = -1, first_id = -1;
-    int64_t alen = 0;
-    const int32_t *Arow = nullptr;
-    bool use_hash = false;
     for (int tries = 0; tries < TC_DYN_PARTS;) {
         const int p = (part + tries) % TC_DYN_PARTS;
         const int64_t r0 = N * p / TC_DYN_PARTS, r1 = N * (p + 1) / TC_DYN_PARTS;
         unsigned long long c = 0;
         if (lane == 0) c = atomicAdd(&ctr[TC_DYN_STRIDE * p], 1ull);
         c = (unsigned long long)__shfl((long long)c, 0, 64);
-        const int64_t k0 = r0 + (int64_t)c * TC_DYN_ITEMS;
+        const int64_t k0 = r0 + (int64_t)c * grain;
         if (k0 >= r1) {
             tries++;
             continue;
         }
-        const int64_t k1 = k0 + TC_DYN_ITEMS < r1 ? k0 + TC_DYN_ITEMS : r1;
+        const int64_t k1 = k0 + grain < r1 ? k0 + grain : r1;
         for (int64_t k = k0; k < k1; k++) {
+            if (BATCHED) {
+                const int32_t gk = a.item_graph[k];
+                if (gk != g) {
+                    flush();
+                    g = gk;
+                }
+            }
             const uint64_t it = a.item[k];
             const int32_t m = a.item_row[k];
             const int64_t e0 = (int64_t)(it >> TC_PLAN_CNT_BITS);
@@ -574,6 +523,10 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
         }
     }
     if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
+    if (BATCHED) {
+        flush();
+        return 0;
+    }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     return acc;
 }
