@@ -235,10 +235,10 @@ def main():
     # algorithmic byte model of the min-side count (one launch of k_tc_split):
     # every pair (i, j) of L with p = position of j in row i >= 1 streams
     # the shorter of L_j (len(L_j) <= p: "A side", row i marked) and
-    # L_i[0, p) ("B side", row j marked); per launch the kernel reads the
-    # work prefix and a 12-byte descriptor per item (64 pairs at most), one
-    # 8-byte segment descriptor per pair, the streamed ids (4 B each) and
-    # every marked row once (16 B of offsets + 4 B per id).
+    # L_i[0, p) ("B side", row j marked); per launch the kernel reads a
+    # 12-byte descriptor per item (64 pairs at most), one 8-byte segment
+    # descriptor per pair, the streamed ids (4 B each) and every marked row
+    # once (16 B of offsets + 4 B per id).
     L.lagr_property_tc_lower(G, ctx)
     Lm = G.tc_lower()
     lrp, lci, _ = Lm.to_csr(ctx)
@@ -256,7 +256,7 @@ def main():
     cnt_b = torch.bincount(lci.long()[side_b], minlength=n)
     items = int(((cnt_a + 63) // 64).sum().item() + ((cnt_b + 63) // 64).sum().item())
     marked = int((16 + 4 * llen[cnt_a > 0]).sum().item() + (16 + 4 * llen[cnt_b > 0]).sum().item())
-    tc_bytes = 8 * (items + 1) + 12 * items + 8 * nent + 4 * streamed + marked
+    tc_bytes = 12 * items + 8 * nent + 4 * streamed + marked
     tc_model = {"pairs": nent, "streamed_ids": streamed, "items": items,
                 "single_side_streamed_ids": int(lj[pos >= 1].sum().item())}
     del row_of, pos, lj, valid, side_a, side_b, cnt_a, cnt_b
