@@ -148,7 +148,7 @@ extern "C" int lagr_batch_new(lagr_batch *Bout, const lagr_graph *graphs, int64_
         TRY(lagr_property_tc_lower(graphs[g], ctx, msg));
         gb[g + 1] = gb[g] + graphs[g]->L->nrows;
         eb[g + 1] = eb[g] + graphs[g]->L->nvals;
-        nb[g + 1] = nb[g] + graphs[g]->tcplan->nent;
+        nb[g + 1] = nb[g] + graphs[g]->tcplan->ent_cap;
         kb[g + 1] = kb[g] + graphs[g]->tcplan->nitems;
     }
     if (gb[ngraphs] >= ((int64_t)1 << 31))
@@ -187,9 +187,10 @@ extern "C" int lagr_batch_new(lagr_batch *Bout, const lagr_graph *graphs, int64_
         if (L->nrows > 0)
             hipLaunchKernelGGL(k_pack_rowptr, dim3(grid_for(L->nrows, 256, 4096)), dim3(256), 0, ctx->stream,
                                L->rowptr, L->nrows, eb[g], B->rp + gb[g]);
-        if (P->nent > 0)
-            hipLaunchKernelGGL(k_pack_add_u64, dim3(grid_for(P->nent, 256, 4096)), dim3(256), 0, ctx->stream,
-                               P->ent, P->nent, (uint64_t)eb[g] << TC_PLAN_LEN_BITS, B->ent + nb[g]);
+        // the whole entry array (each virtual row's region), unused slots too
+        if (P->ent_cap > 0)
+            hipLaunchKernelGGL(k_pack_add_u64, dim3(grid_for(P->ent_cap, 256, 4096)), dim3(256), 0, ctx->stream,
+                               P->ent, P->ent_cap, (uint64_t)eb[g] << TC_PLAN_LEN_BITS, B->ent + nb[g]);
         if (P->nitems > 0) {
             hipLaunchKernelGGL(k_pack_add_u64, dim3(grid_for(P->nitems, 256, 4096)), dim3(256), 0, ctx->stream,
                                P->item, P->nitems, (uint64_t)nb[g] << TC_PLAN_CNT_BITS, B->item + kb[g]);

@@ -260,13 +260,18 @@ __global__ void k_emit_padded(const int32_t *__restrict__ rowA, const int32_t *_
     }
 }
 
-// cnt[inv[u]] = cur[u]: the row lengths of L, by new label.
+// cnt[inv[u]] = cur[u], the row lengths of L by new label, and
+// cnt[n + inv[u]] = deg(u) - cur[u], the column lengths of L (A is
+// symmetric without self-loops: u's neighbours above it in the order).
 __global__ void k_lower_lengths(const unsigned long long *__restrict__ cur, const int32_t *__restrict__ inv,
-                                int64_t n, int64_t *__restrict__ cnt)
+                                const int64_t *__restrict__ rpA, int64_t n, int64_t *__restrict__ cnt)
 {
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
-         u += (int64_t)gridDim.x * blockDim.x)
-        cnt[inv[u]] = (int64_t)cur[u];
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = (int64_t)cur[u], r = inv[u];
+        cnt[r] = k;
+        cnt[n + r] = rpA[u + 1] - rpA[u] - k;
+    }
 }
 
 // Rows of at most SORT_SHORT ids: each entry's place in its row of L is the
@@ -287,84 +292,177 @@ __global__ void k_sort_short(const int32_t *__restrict__ rowL, const int64_t *__
         if (c > SORT_SHORT) continue;   // k_sort_long
         const int32_t *src = P + rpA[order[r] >> oshift];
         const int32_t x = src[o - b];
-        int64_t rank = 0;
-        for (int64_t t = 0; t < c; t++) rank += src[t] < x ? 1 : 0;
+        int rank = 0;
+#pragma unroll 8
+        for (int t = 0; t < (int)c; t++) rank += src[t] < x ? 1 : 0;
         Lci[b + rank] = x;
     }
 }
 
-// Rows of SORT_SHORT + 1 .. SORT_LONG ids (listed in rows[0 .. *count)):
-// one wave per row, a bitonic network over the row in the wave's LDS.
-// Longer rows set *too_long and stay unsorted.  The row's source is P at the offset of its vertex in A
-// (order[r] >> oshift is the vertex with new label r).
+// Rows of SORT_SHORT + 1 .. SORT_LONG ids (listed as records, below): one
+// wave per row.  The row, padded with INT32_MAX to N = 64R ids (R a power
+// of two), sits in registers as R chunks of 64 (id lane + 64k in register
+// k of lane `lane`).  Each chunk is sorted by a bitonic network across the
+// lanes (shuffles, no memory); then runs of 64, 128, ... are merged in
+// pairs through the wave's LDS: an id's place in the merged run is its
+// place in its own run plus the number of ids of the partner run below it
+// (ids of the right run count equal ids as below, so the places form a
+// permutation even among the pads), found by a binary search of the
+// partner run.  This does O(N log^2 64 + N log^2 N / 2) work instead of
+// O(len^2) compares for ranking.  Longer rows set *too_long and stay
+// unsorted.
+constexpr int SORT_MID = 512;
 constexpr int SORT_LONG = 2048;
 
-// Rows of L longer than min_len, listed in rows[0 .. *count) (count zero on
-// entry): each workgroup reserves its range with one atomic.
+// Rows of L longer than min_len, listed as records rec[2c] = start of the
+// row in L, rec[2c + 1] = (offset of its unsorted copy in P << 16) |
+// min(length, 0xffff), so that the sort reads one 16-byte record per row
+// instead of a chain of dependent loads: rows of at most mid_len ids in
+// rec1[0 .. count[0]), longer ones in rec2[0 .. count[1]) (counts zero on
+// entry), so that the launch for either class reads only its own rows.
+// Each workgroup reserves its ranges with one atomic per class.
 __global__ __launch_bounds__(256) void k_list_long_rows(const int64_t *__restrict__ Lrp, int64_t n, int64_t min_len,
-                                                        int32_t *__restrict__ rows, unsigned long long *count)
+                                                        int64_t mid_len, const uint64_t *__restrict__ order,
+                                                        int oshift, const int64_t *__restrict__ rpA,
+                                                        int64_t *__restrict__ rec1, int64_t *__restrict__ rec2,
+                                                        unsigned long long *count)
 {
-    __shared__ unsigned sc[256];
-    __shared__ unsigned long long base_s;
+    __shared__ unsigned long long sc[256];
+    __shared__ unsigned long long base_s[2];
     const int64_t share = (n + gridDim.x - 1) / gridDim.x;
     const int64_t v0 = (int64_t)blockIdx.x * share, v1 = min(n, v0 + share);
-    unsigned c = 0;
-    for (int64_t v = v0 + threadIdx.x; v < v1; v += 256) c += Lrp[v + 1] - Lrp[v] > min_len ? 1u : 0u;
+    // per-thread counts of both classes, packed 32 bits each (n < 2^31)
+    unsigned long long c = 0;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += 256) {
+        const int64_t len = Lrp[v + 1] - Lrp[v];
+        c += len > mid_len ? (1ull << 32) : len > min_len ? 1ull : 0ull;
+    }
     sc[threadIdx.x] = c;
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
-        const unsigned y = (int)threadIdx.x >= o ? sc[threadIdx.x - o] : 0u;
+        const unsigned long long y = (int)threadIdx.x >= o ? sc[threadIdx.x - o] : 0ull;
         __syncthreads();
         sc[threadIdx.x] += y;
         __syncthreads();
     }
-    if (threadIdx.x == 255) base_s = sc[255] ? atomicAdd(count, (unsigned long long)sc[255]) : 0;
+    if (threadIdx.x == 255) {
+        const unsigned long long t1 = sc[255] & 0xffffffffull, t2 = sc[255] >> 32;
+        base_s[0] = t1 ? atomicAdd(&count[0], t1) : 0;
+        base_s[1] = t2 ? atomicAdd(&count[1], t2) : 0;
+    }
     __syncthreads();
-    unsigned long long pos = base_s + sc[threadIdx.x] - c;
-    for (int64_t v = v0 + threadIdx.x; v < v1; v += 256)
-        if (Lrp[v + 1] - Lrp[v] > min_len) rows[pos++] = (int32_t)v;
+    const unsigned long long before = sc[threadIdx.x] - c;
+    unsigned long long p1 = base_s[0] + (before & 0xffffffffull), p2 = base_s[1] + (before >> 32);
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += 256) {
+        const int64_t b = Lrp[v], len = Lrp[v + 1] - b;
+        if (len > min_len) {
+            int64_t *rec = len > mid_len ? rec2 + 2 * p2++ : rec1 + 2 * p1++;
+            rec[0] = b;
+            rec[1] = (rpA[order[v] >> oshift] << 16) | (len < 0xffff ? len : 0xffff);
+        }
+    }
 }
 
-__global__ __launch_bounds__(256) void k_sort_long(const int32_t *__restrict__ rows,
+template <int R>
+__device__ __forceinline__ void sort_row_wave(const int32_t *__restrict__ src, int len, int32_t *x,
+                                              int32_t *__restrict__ out, unsigned lane)
+{
+    int32_t v[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        const int i = (int)lane + 64 * k;
+        v[k] = i < len ? src[i] : INT32_MAX;
+    }
+    // bitonic sort of each chunk across the 64 lanes, ascending
+#pragma unroll
+    for (int size = 2; size <= 64; size <<= 1)
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const bool keep_min = ((lane & (unsigned)size) == 0) == ((lane & (unsigned)stride) == 0);
+#pragma unroll
+            for (int k = 0; k < R; k++) {
+                const int32_t y = __shfl_xor(v[k], stride, 64);
+                v[k] = keep_min ? min(v[k], y) : max(v[k], y);
+            }
+        }
+    // merge rounds: id lane + 64k lies in run 64k / L (lane < 64 <= L), so
+    // the run, its partner and the side are known per register k; the R
+    // binary searches advance together, one LDS read each per step
+#pragma unroll
+    for (int L = 64; L < 64 * R; L <<= 1) {
+        if (L == 64) {
+#pragma unroll
+            for (int k = 0; k < R; k++) x[lane + 64 * k] = v[k];
+        }
+        wave_barrier_lds();
+        int base[R];
+#pragma unroll
+        for (int k = 0; k < R; k++) base[k] = 0;
+#pragma unroll
+        for (int half = L >> 1; half >= 1; half >>= 1)
+#pragma unroll
+            for (int k = 0; k < R; k++) {
+                const int run = 64 * k / L;
+                const int32_t y = x[(run ^ 1) * L + base[k] + half - 1];
+                if ((run & 1) ? y <= v[k] : y < v[k]) base[k] += half;
+            }
+        int pos[R];
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            const int run = 64 * k / L;
+            const int32_t y = x[(run ^ 1) * L + base[k]];
+            const int below = base[k] + (((run & 1) ? y <= v[k] : y < v[k]) ? 1 : 0);
+            pos[k] = (run & ~1) * L + ((int)lane + 64 * k - run * L) + below;
+        }
+        wave_barrier_lds();
+#pragma unroll
+        for (int k = 0; k < R; k++) x[pos[k]] = v[k];
+        wave_barrier_lds();
+#pragma unroll
+        for (int k = 0; k < R; k++) v[k] = x[lane + 64 * k];
+        if (2 * L == 64 * R) wave_barrier_lds();
+    }
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        const int i = (int)lane + 64 * k;
+        if (i < len) out[i] = v[k];
+    }
+}
+
+// The rows of one list (lengths up to HI), so that each launch takes only
+// the LDS its rows need (HI ids per wave) and shorter rows keep many waves
+// resident; the launch with HI = SORT_LONG flags the rows past it.
+template <int HI>
+__global__ __launch_bounds__(256) void k_sort_long(const longlong2 *__restrict__ rec,
                                                    const unsigned long long *__restrict__ count,
-                                                   const int64_t *__restrict__ Lrp, const uint64_t *__restrict__ order,
-                                                   int oshift, const int64_t *__restrict__ rpA,
                                                    const int32_t *__restrict__ P, int32_t *__restrict__ Lci,
                                                    unsigned long long *__restrict__ too_long)
 {
-    __shared__ int32_t buf[4][SORT_LONG];
+    __shared__ int32_t buf[4][HI];
     int32_t *x = buf[threadIdx.x / 64];
     const unsigned lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const int64_t nrows = (int64_t)*count;
+    longlong2 next = wave < nrows ? rec[wave] : make_longlong2(0, 0);
     for (int64_t c = wave; c < nrows; c += nw) {
-        const int32_t r = rows[c];
-        const int64_t b = Lrp[r];
-        if (Lrp[r + 1] - b > SORT_LONG) {   // left to the radix sort (status[1])
-            if (lane == 0) too_long[0] = 1ull;
+        const longlong2 cur = next;
+        if (c + nw < nrows) next = rec[c + nw];   // the next row's record, in flight meanwhile
+        const int64_t b = cur.x;
+        const int len = (int)(cur.y & 0xffff);
+        if (len > HI) {   // left to the radix sort (status[1])
+            if (HI == SORT_LONG && lane == 0) too_long[0] = 1ull;
             continue;
         }
-        const int len = (int)(Lrp[r + 1] - b);
-        const int32_t *src = P + rpA[order[r] >> oshift];
-        int N = 1;
-        while (N < len) N <<= 1;
-        for (int i = lane; i < N; i += 64) x[i] = i < len ? src[i] : INT32_MAX;
-        wave_barrier_lds();
-        for (int k = 2; k <= N; k <<= 1)
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int t = lane; t < N / 2; t += 64) {
-                    const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1)), ij = i | j;
-                    const int32_t a = x[i], c2 = x[ij];
-                    if ((a > c2) == ((i & k) == 0)) {
-                        x[i] = c2;
-                        x[ij] = a;
-                    }
-                }
-                wave_barrier_lds();
-            }
-        for (int i = lane; i < len; i += 64) Lci[b + i] = x[i];
-        wave_barrier_lds();
+        const int32_t *src = P + (cur.y >> 16);
+        if (HI <= 512) {
+            if (len <= 128) sort_row_wave<2>(src, len, x, Lci + b, lane);
+            else if (len <= 256) sort_row_wave<4>(src, len, x, Lci + b, lane);
+            else sort_row_wave<(HI >= 512 ? 8 : 4)>(src, len, x, Lci + b, lane);
+        } else {
+            if (len <= 1024) sort_row_wave<16>(src, len, x, Lci + b, lane);
+            else sort_row_wave<(HI >= 2048 ? 32 : 16)>(src, len, x, Lci + b, lane);
+        }
     }
 }
 
@@ -622,7 +720,7 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
     //    descending keeps the rows of L short for the row-by-row form)
     uint64_t *okeys = (uint64_t *)ws_get(ctx, WS_PERM, sizeof(uint64_t) * (n > 0 ? n : 1));
     int32_t *inv = (int32_t *)ws_get(ctx, WS_DEG, sizeof(int32_t) * (n > 0 ? n : 1));
-    int64_t *cnt = (int64_t *)ws_get(ctx, WS_FLAGS, sizeof(int64_t) * (n + 1));
+    int64_t *cnt = (int64_t *)ws_get(ctx, WS_FLAGS, sizeof(int64_t) * (2 * n + 1));
     const int64_t nnzA = A->nvals;
     int32_t *rowA = (int32_t *)ws_get(ctx, WS_GEN_D, sizeof(int32_t) * (nnzA > 0 ? nnzA : 1));
     if (!okeys || !inv || !cnt || !rowA) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
@@ -633,7 +731,7 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
         LAUNCH_CHECK();
     }
     TRY(radix_sort_u64(ctx, okeys, n, dbits, msg));
-    TRY(fill_i64(ctx, cnt, n + 1, 0, msg));
+    TRY(fill_i64(ctx, cnt + 2 * n, 1, 0, msg));
     if (n > 0) {
         hipLaunchKernelGGL(k_inverse_perm, dim3(grid_for(n, 256, 65536)), dim3(256), 0, ctx->stream,
                            okeys, n, dbits, inv);
@@ -659,16 +757,18 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
         LAUNCH_CHECK();
     }
     if (n > 0) {
-        hipLaunchKernelGGL(k_lower_lengths, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, cur, inv, n,
-                           cnt);
+        hipLaunchKernelGGL(k_lower_lengths, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, cur, inv,
+                           A->rowptr, n, cnt);
         LAUNCH_CHECK();
     }
     // A is symmetric without self-loops (checked above), so L holds exactly
     // half of its entries: no host round trip for the count (checked
-    // against the scan's total with the status read below)
+    // against the scan's total with the status read below).  One scan of
+    // [row lengths | column lengths | 0] gives L's row offsets (its first
+    // n+1 entries) and the regions of the count plan's 2n virtual rows.
     if (nnzA % 2 != 0) return lagr_fail(msg, LAGR_INVALID_OBJECT, "odd entry count in a symmetric matrix");
     const int64_t nnz = nnzA / 2;
-    TRY(scan_exclusive_i64(ctx, cnt, cnt, n + 1, nullptr, msg));
+    TRY(scan_exclusive_i64(ctx, cnt, cnt, 2 * n + 1, nullptr, msg));
     unsigned long long *status = (unsigned long long *)ws_get(ctx, WS_COUNTERS, 64);
     if (!status) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
     TRY(fill_i64(ctx, (int64_t *)status, 8, 0, msg));
@@ -683,14 +783,15 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
         return rc;
     }
     int32_t *rowid = (int32_t *)ws_get(ctx, WS_GEN_A, sizeof(int32_t) * (nnz > 0 ? nnz : 1));
-    int32_t *lrows = (int32_t *)ws_get(ctx, WS_CHUNK_A, sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    // two record lists of up to n rows each
+    int64_t *lrows = (int64_t *)ws_get(ctx, WS_CHUNK_A, 4 * sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     unsigned long long *nlong = (unsigned long long *)ws_get(ctx, WS_CHUNK_B, 64);
     if (!rowid || !lrows || !nlong) {
         rc = lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
         goto fail;
     }
     // 3. the rows are sorted from P into L: rows of at most SORT_SHORT ids
-    //    by rank, rows up to SORT_LONG by a bitonic network in LDS (listed
+    //    by rank, rows up to SORT_LONG by a wave sort in registers and LDS (listed
     //    on the device), longer rows (flagged in status[1]) by a radix sort
     if (hipMemcpyAsync(L->rowptr, cnt, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, ctx->stream) !=
         hipSuccess) {
@@ -709,11 +810,13 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
             rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
             goto fail;
         }
-        if ((rc = fill_i64(ctx, (int64_t *)nlong, 1, 0, msg)) < 0) goto fail;
+        if ((rc = fill_i64(ctx, (int64_t *)nlong, 2, 0, msg)) < 0) goto fail;
         hipLaunchKernelGGL(k_list_long_rows, dim3(grid_for(n, 256, 1024)), dim3(256), 0, ctx->stream, L->rowptr, n,
-                           SORT_SHORT, lrows, nlong);
-        hipLaunchKernelGGL(k_sort_long, dim3((unsigned)(ctx->num_cus * 16)), dim3(256), 0, ctx->stream, lrows, nlong,
-                           L->rowptr, okeys, dbits, A->rowptr, P, L->colidx, status + 1);
+                           SORT_SHORT, SORT_MID, okeys, dbits, A->rowptr, lrows, lrows + 2 * n, nlong);
+        hipLaunchKernelGGL(k_sort_long<SORT_MID>, dim3((unsigned)(ctx->num_cus * 16)), dim3(256), 0, ctx->stream,
+                           (const longlong2 *)lrows, nlong, P, L->colidx, status + 1);
+        hipLaunchKernelGGL(k_sort_long<SORT_LONG>, dim3((unsigned)(ctx->num_cus * 2)), dim3(256), 0, ctx->stream,
+                           (const longlong2 *)(lrows + 2 * n), nlong + 1, P, L->colidx, status + 1);
         if (hipGetLastError() != hipSuccess) {
             rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
             goto fail;
@@ -721,7 +824,7 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
     }
     G->L = L;
     for (int attempt = 0;; attempt++) {
-        if ((rc = tc_plan_build(ctx, G, rowid, msg)) < 0) break;
+        if ((rc = tc_plan_build(ctx, G, rowid, cnt, msg)) < 0) break;
         bool unsorted = false;
         if ((rc = tc_plan_settle(ctx, G, status, nnz, &unsorted, msg)) < 0) break;
         if (!unsorted || attempt > 0) break;

@@ -182,8 +182,10 @@ static inline lagr_matrix graph_in_edges(const lagr_graph G)
     return G->kind == LAGR_ADJACENCY_DIRECTED ? G->AT : G->A;
 }
 
-// Build / release G->tcplan from G->L and the row of each entry of L.
-int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, char *msg);
+// Build / release G->tcplan from G->L, the row of each entry of L and the
+// region starts of the plan's 2n virtual rows (regions: 2n+1 device int64,
+// the exclusive scan of [row lengths of L | column lengths of L | 0]).
+int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_t *regions, char *msg);
 // One host round trip after the build: status[0] (the longest row of L)
 // and status[1] (rows left unsorted, *unsorted) come from the caller's
 // kernels; sets G->L_maxrow and the plan's entry and item counts, and

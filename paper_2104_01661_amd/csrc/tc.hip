@@ -45,19 +45,26 @@ __device__ __forceinline__ uint64_t plan_pack(int64_t off, int64_t len)
     return ((uint64_t)off << TC_PLAN_LEN_BITS) | (uint64_t)len;
 }
 
+// Every virtual row has a region of the entry array whose size is known
+// before the plan is built: A-side row i at most len(L_i) entries (the
+// region of row i in L's own layout) and B-side row j at most the number
+// of rows of L holding j (the column length of L, from A's degrees), so
+// the fill needs no counting pass: each row hands out slots from a cursor
+// that starts at its region's start, and the cursor's end is the row's
+// entry count.
+//
 // B-side rows j below PLAN_HOT (the highest-degree vertices after the
-// relabel) receive most B entries; a workgroup first gathers their counts
-// in LDS, so each takes one global atomic per workgroup instead of one per
-// entry (same-address atomics serialise).  The kernels read the row of
-// every entry of L (rowid), so every thread knows its entry's row and
-// column directly; workgroup g takes the g-th contiguous share of the
-// entries, which keeps its hot counts dense.  The count kernel's atomic
-// returns the workgroup's offset inside each hot row (boff, PLAN_GRID x
-// PLAN_HOT), which the fill kernel, run on the same partition, starts from.
-// The kernels chain dependent loads (row, row start, column, column's row),
-// so they run 512-thread workgroups, four per CU (the 32 KiB LDS table
-// allows it), for more loads in flight.
-constexpr int PLAN_HOT = 8192;
+// relabel) receive most B entries, and atomics on one address serialise,
+// so their slots are taken in two steps.  k_plan_hot counts, per
+// workgroup, the B entries of each hot row in LDS and reserves them with
+// one global atomic per (workgroup, row); it needs the row length of L
+// only for hot columns (held in LDS), so it reads just the entry's row,
+// column and row start.  k_plan_fill, run on the same partition of the
+// entries (workgroup g takes the g-th contiguous share), hands out the
+// reserved slots from LDS.  The fill chains dependent loads (row, row
+// start, column, column's row), so it runs 512-thread workgroups, four per
+// CU, for more loads in flight.
+constexpr int PLAN_HOT = 4096;
 constexpr int PLAN_BLOCK = 512;
 constexpr unsigned PLAN_GRID = 1024;
 
@@ -71,69 +78,55 @@ __global__ void k_row_pack(const int64_t *__restrict__ rp, int64_t n, uint64_t *
         rowpk[r] = plan_pack(rp[r], rp[r + 1] - rp[r]);
 }
 
-// Entries per virtual row (cnt: 2n+1 entries, zero on entry).  Each wave
-// takes PLAN_ILP windows of 64 consecutive entries per iteration and runs
-// them stage by stage (their loads, then their gathers, then their
-// atomics), so a wave waits for each round trip once per PLAN_ILP windows:
-// the kernels are bound by the latency of gathers and atomics that miss
-// L2.  Every lane of a wave runs every iteration (the loop bound is
-// uniform), as wave_run's ballots and shuffles need.
-constexpr int PLAN_ILP = 2;
-
-__global__ __launch_bounds__(PLAN_BLOCK) void k_plan_count(const int32_t *__restrict__ rowid,
-                                                           const int32_t *__restrict__ ci, int64_t nnz,
-                                                           const uint64_t *__restrict__ rowpk, int64_t n,
-                                                           unsigned long long *__restrict__ cnt,
-                                                           unsigned *__restrict__ boff)
+// Per workgroup, the B entries of each hot row, reserved in the row's
+// region: boff[g * PLAN_HOT + x] = offset of workgroup g's first slot in
+// row n + x, relative to bstart = trp[n] (fewer than 2^32 entries).
+__global__ __launch_bounds__(PLAN_BLOCK) void k_plan_hot(const int32_t *__restrict__ rowid,
+                                                         const int32_t *__restrict__ ci, int64_t nnz,
+                                                         const uint64_t *__restrict__ rowpk, int64_t n,
+                                                         const int64_t *__restrict__ trp,
+                                                         unsigned long long *__restrict__ cur,
+                                                         unsigned *__restrict__ boff)
 {
     __shared__ unsigned hot[PLAN_HOT];
-    for (int x = threadIdx.x; x < PLAN_HOT; x += PLAN_BLOCK) hot[x] = 0u;
+    __shared__ unsigned hlen[PLAN_HOT];
+    const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
+    const int64_t nh = n < PLAN_HOT ? n : PLAN_HOT;
+    for (int x = threadIdx.x; x < PLAN_HOT; x += PLAN_BLOCK) {
+        hot[x] = 0u;
+        hlen[x] = x < nh ? (unsigned)(rowpk[x] & lmask) : 0u;
+    }
     __syncthreads();
     const int64_t share = (nnz + gridDim.x - 1) / gridDim.x;
     const int64_t e0 = (int64_t)blockIdx.x * share, e1 = min(nnz, e0 + share);
-    const unsigned lane = lane_id();
-    const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
-    const int64_t first = (int64_t)(threadIdx.x / 64) * PLAN_ILP * 64 + lane;
-    for (int64_t base = e0; base < e1; base += (int64_t)PLAN_BLOCK * PLAN_ILP) {
-        int32_t i[PLAN_ILP], j[PLAN_ILP];
-        uint64_t pi[PLAN_ILP], pj[PLAN_ILP];
-#pragma unroll
-        for (int k = 0; k < PLAN_ILP; k++) {
-            const int64_t e = base + first + 64 * k;
-            i[k] = e < e1 ? rowid[e] : -1;
-            j[k] = e < e1 ? ci[e] : 0;
-        }
-#pragma unroll
-        for (int k = 0; k < PLAN_ILP; k++) {
-            pi[k] = i[k] >= 0 ? rowpk[i[k]] : 0ull;
-            pj[k] = i[k] >= 0 ? rowpk[j[k]] : 0ull;
-        }
-#pragma unroll
-        for (int k = 0; k < PLAN_ILP; k++) {
-            const int64_t e = base + first + 64 * k;
-            const int64_t p = e - (int64_t)(pi[k] >> TC_PLAN_LEN_BITS), lj = (int64_t)(pj[k] & lmask);
-            const bool valid = i[k] >= 0 && p > 0 && lj > 0;
-            const bool a_side = valid && lj <= p;
-            if (valid && !a_side) {
-                if (j[k] < PLAN_HOT) atomicAdd(&hot[j[k]], 1u);
-                else atomicAdd(&cnt[n + j[k]], 1ull);
-            }
-            const WaveRun w = wave_run(i[k]);
-            const uint64_t take = __ballot(a_side) & w.run;
-            if (lane == w.head && take) atomicAdd(&cnt[i[k]], (unsigned long long)__popcll(take));
-        }
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += PLAN_BLOCK) {
+        const int32_t j = ci[e];
+        if (j >= PLAN_HOT) continue;
+        const int64_t lj = hlen[j];
+        if (lj == 0) continue;
+        const int64_t p = e - (int64_t)(rowpk[rowid[e]] >> TC_PLAN_LEN_BITS);
+        if (p > 0 && lj > p) atomicAdd(&hot[j], 1u);
     }
     __syncthreads();
+    const int64_t bstart = trp[n];
     unsigned *mine = boff + (size_t)blockIdx.x * PLAN_HOT;
-    for (int x = threadIdx.x; x < PLAN_HOT && x < n; x += PLAN_BLOCK)
-        mine[x] = hot[x] ? (unsigned)atomicAdd(&cnt[n + x], (unsigned long long)hot[x]) : 0u;
+    for (int x = threadIdx.x; x < nh; x += PLAN_BLOCK)
+        mine[x] = hot[x] ? (unsigned)((int64_t)atomicAdd(&cur[n + x], (unsigned long long)hot[x]) - bstart) : 0u;
 }
 
-// cur (a copy of the first 2n offsets) holds the write cursor of each
-// virtual row; the order of the entries within a row is immaterial.  Hot
-// B rows hand out positions from LDS as offsets from bstart = trp[n], the
-// first B-side offset (the host checks that the plan has fewer than 2^32
-// entries), starting at the workgroup's range from the count kernel.
+// Each wave takes PLAN_ILP windows of 64 consecutive entries per iteration
+// and runs them stage by stage (their loads, then their gathers, then
+// their atomics), so a wave waits for each round trip once per PLAN_ILP
+// windows: the kernel is bound by the latency of gathers and atomics that
+// miss L2.  Every lane of a wave runs every iteration (the loop bound is
+// uniform), as wave_run's ballots and shuffles need.
+constexpr int PLAN_ILP = 2;
+
+// cur (the region starts, hot rows already advanced by k_plan_hot) holds
+// the write cursor of each virtual row; the order of the entries within a
+// row is immaterial.  Hot B rows hand out positions from LDS as offsets
+// from bstart = trp[n], the first B-side slot, starting at the workgroup's
+// reservation.
 __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restrict__ rowid,
                                                           const int32_t *__restrict__ ci, int64_t nnz,
                                                           const uint64_t *__restrict__ rowpk, int64_t n,
@@ -146,7 +139,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restr
     const int64_t bstart = trp[n];
     const unsigned *mine = boff + (size_t)blockIdx.x * PLAN_HOT;
     for (int x = threadIdx.x; x < PLAN_HOT && x < n; x += PLAN_BLOCK)
-        hot[x] = (unsigned)(trp[n + x] - bstart) + mine[x];
+        hot[x] = mine[x];
     __syncthreads();
     const int64_t share = (nnz + gridDim.x - 1) / gridDim.x;
     const int64_t e0 = (int64_t)blockIdx.x * share, e1 = min(nnz, e0 + share);
@@ -198,11 +191,27 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restr
     }
 }
 
-__global__ void k_plan_items(const int64_t *__restrict__ trp, int64_t nv, int64_t *__restrict__ irp)
+// irp[r] = items of virtual row r (its entries, cur[r] - trp[r], in runs of
+// up to 64); *pairs (zero on entry) = the entries over all rows, one
+// atomic per workgroup.
+__global__ __launch_bounds__(256) void k_plan_items(const int64_t *__restrict__ trp,
+                                                    const unsigned long long *__restrict__ cur, int64_t nv,
+                                                    int64_t *__restrict__ irp, unsigned long long *pairs)
 {
+    __shared__ unsigned long long tot;
+    if (threadIdx.x == 0) tot = 0;
+    __syncthreads();
+    unsigned long long c = 0;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nv;
-         r += (int64_t)gridDim.x * blockDim.x)
-        irp[r] = (trp[r + 1] - trp[r] + 63) / 64;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = (int64_t)cur[r] - trp[r];
+        irp[r] = (k + 63) / 64;
+        c += (unsigned long long)k;
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if (lane_id() == 0 && c) atomicAdd(&tot, c);
+    __syncthreads();
+    if (threadIdx.x == 0 && tot) atomicAdd(pairs, tot);
 }
 
 // First virtual row r in [0, nv) with irp[r + 1] > k.
@@ -219,7 +228,8 @@ __device__ __forceinline__ int64_t plan_row_of(const int64_t *__restrict__ irp, 
 
 // Item descriptors over a capacity; the item count is irp[nv], on the
 // device (the plan is built without a host round trip).
-__global__ void k_plan_item_work(int64_t n, const int64_t *__restrict__ trp, const int64_t *__restrict__ irp,
+__global__ void k_plan_item_work(int64_t n, const int64_t *__restrict__ trp,
+                                 const unsigned long long *__restrict__ cur, const int64_t *__restrict__ irp,
                                  uint64_t *__restrict__ item, int32_t *__restrict__ item_row)
 {
     const int64_t nv = 2 * n, nitems = irp[nv];
@@ -227,7 +237,7 @@ __global__ void k_plan_item_work(int64_t n, const int64_t *__restrict__ trp, con
          k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = plan_row_of(irp, nv, k);
         const int64_t e0 = trp[r] + 64 * (k - irp[r]);
-        const int64_t e1 = min(trp[r + 1], e0 + 64);
+        const int64_t e1 = min((int64_t)cur[r], e0 + 64);
         item[k] = ((uint64_t)e0 << TC_PLAN_CNT_BITS) | (uint64_t)(e1 - e0);
         item_row[k] = (int32_t)(r < n ? r : r - n);
     }
@@ -274,9 +284,9 @@ void tc_plan_free(lagr_graph G)
 {
     TcPlan *P = G->tcplan;
     if (!P) return;
-    const size_t nv1 = (size_t)(2 * P->n + 1);
-    dev_free(P->trp, 8 * nv1);
-    dev_free(P->irp, 8 * nv1);
+    const size_t nv = (size_t)(2 * P->n);
+    dev_free(P->trp, 8 * (nv + 2));
+    dev_free(P->irp, 8 * (nv + 1));
     dev_free(P->ent, 8 * (size_t)(P->ent_cap > 0 ? P->ent_cap : 1));
     dev_free(P->item, 8 * (size_t)(P->item_cap > 0 ? P->item_cap : 1));
     dev_free(P->item_row, 4 * (size_t)(P->item_cap > 0 ? P->item_cap : 1));
@@ -284,30 +294,31 @@ void tc_plan_free(lagr_graph G)
     G->tcplan = nullptr;
 }
 
-// Built without a host round trip: the entries take at most one slot per
-// entry of L and the items at most nnz/64 + one per non-empty virtual row,
-// so both arrays are allocated at those bounds.  The entry and item counts
-// are trp[2n] and irp[2n] on the device; the caller reads them back (with
-// the rest of its status) and sets P->nent and P->nitems.
-int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, char *msg)
+// Built without a host round trip: the entries go to regions of known size
+// (2 nnz slots in all) and the items take at most nnz/64 + one per
+// non-empty virtual row, so every array is allocated at its bound.  The
+// pair and item counts are trp[2n+1] and irp[2n] on the device; the caller
+// reads them back (with the rest of its status) and sets P->nent and
+// P->nitems.
+int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_t *regions, char *msg)
 {
     const lagr_matrix Lm = G->L;
     const int64_t n = Lm->nrows, nv = 2 * n;
     const int64_t nnz = Lm->nvals;
-    if (nnz >= ((int64_t)1 << 32))
+    if (2 * nnz >= ((int64_t)1 << 32))
         return lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "L too large for the count plan");
     TcPlan *P = new (std::nothrow) TcPlan();
     if (!P) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan");
     P->n = n;
     P->nent = P->nitems = -1;
-    P->ent_cap = nnz;
+    P->ent_cap = 2 * nnz;
     P->item_cap = nnz / 64 + (nv < nnz ? nv : nnz) + 1;
     G->tcplan = P;
     auto fail = [&](int rc) {
         tc_plan_free(G);
         return rc;
     };
-    P->trp = (int64_t *)dev_alloc(8 * (size_t)(nv + 1));
+    P->trp = (int64_t *)dev_alloc(8 * (size_t)(nv + 2));
     P->irp = (int64_t *)dev_alloc(8 * (size_t)(nv + 1));
     P->ent = (uint64_t *)dev_alloc(8 * (size_t)(P->ent_cap > 0 ? P->ent_cap : 1));
     P->item = (uint64_t *)dev_alloc(8 * (size_t)P->item_cap);
@@ -315,37 +326,33 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, char *msg)
     if (!P->trp || !P->irp || !P->ent || !P->item || !P->item_row)
         return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
     int rc;
-    if ((rc = fill_i64(ctx, P->trp, nv + 1, 0, msg)) < 0) return fail(rc);
+    if (hipMemcpyAsync(P->trp, regions, 8 * (size_t)(nv + 1), hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
+        return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan copy"));
+    if ((rc = fill_i64(ctx, P->trp + nv + 1, 1, 0, msg)) < 0) return fail(rc);
     unsigned *boff = (unsigned *)ws_get(ctx, WS_GEN_H, sizeof(unsigned) * (size_t)PLAN_GRID * PLAN_HOT);
     uint64_t *rowpk = (uint64_t *)ws_get(ctx, WS_GEN_E, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     unsigned long long *cur = (unsigned long long *)ws_get(ctx, WS_TC_WORK, 8 * (size_t)(nv > 0 ? nv : 1));
     if (!boff || !rowpk || !cur) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
     if (n > 0) {
+        if (hipMemcpyAsync(cur, regions, 8 * (size_t)nv, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
+            return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan copy"));
         hipLaunchKernelGGL(k_row_pack, dim3(grid_for(n, 256, 16384)), dim3(256), 0, ctx->stream, Lm->rowptr, n,
                            rowpk);
-        if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
-    }
-    if (nnz > 0) {
-        hipLaunchKernelGGL(k_plan_count, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx, nnz,
-                           rowpk, n, (unsigned long long *)P->trp, boff);
-        if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
-    }
-    if ((rc = scan_exclusive_i64(ctx, P->trp, P->trp, nv + 1, nullptr, msg)) < 0) return fail(rc);
-    if (n > 0) {
-        if (hipMemcpyAsync(cur, P->trp, 8 * (size_t)nv, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
-            return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan copy"));
-        if (nnz > 0)
+        if (nnz > 0) {
+            hipLaunchKernelGGL(k_plan_hot, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx,
+                               nnz, rowpk, n, P->trp, cur, boff);
             hipLaunchKernelGGL(k_plan_fill, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx,
                                nnz, rowpk, n, P->trp, boff, cur, P->ent);
-        hipLaunchKernelGGL(k_plan_items, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, ctx->stream, P->trp,
-                           nv, P->irp);
+        }
+        hipLaunchKernelGGL(k_plan_items, dim3(grid_for(nv, 256, 4096)), dim3(256), 0, ctx->stream, P->trp, cur, nv,
+                           P->irp, (unsigned long long *)(P->trp + nv + 1));
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
     }
     if ((rc = fill_i64(ctx, P->irp + nv, 1, 0, msg)) < 0) return fail(rc);
     if ((rc = scan_exclusive_i64(ctx, P->irp, P->irp, nv + 1, nullptr, msg)) < 0) return fail(rc);
     if (n > 0) {
         hipLaunchKernelGGL(k_plan_item_work, dim3(grid_for(P->item_cap, 256, 16384)), dim3(256), 0, ctx->stream,
-                           n, P->trp, P->irp, P->item, P->item_row);
+                           n, P->trp, cur, P->irp, P->item, P->item_row);
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
     }
     return LAGR_SUCCESS;
@@ -370,7 +377,7 @@ int tc_plan_settle(lagr_ctx ctx, lagr_graph G, unsigned long long *status, int64
 {
     TcPlan *P = G->tcplan;
     const int64_t n = G->L->nrows;
-    hipLaunchKernelGGL(k_tc_status, dim3(1), dim3(64), 0, ctx->stream, P->trp + 2 * n, P->irp + 2 * n,
+    hipLaunchKernelGGL(k_tc_status, dim3(1), dim3(64), 0, ctx->stream, P->trp + 2 * n + 1, P->irp + 2 * n,
                        G->L->rowptr + n, status);
     LAUNCH_CHECK();
     unsigned long long st[5] = {0, 0, 0, 0, 0};

@@ -98,15 +98,10 @@ def lower_csr(G):
     return rp.cpu().numpy(), ci.cpu().numpy()
 
 
-@pytest.mark.parametrize("scale,ef,seed", [(10, 16, 1), (11, 8, 5), (9, 32, 6)])
-def test_tc_lower_is_the_degree_relabelled_lower_part(scale, ef, seed):
-    """L = strict lower part of A after relabelling by descending degree
-    (ties by id), rows sorted; rebuilt here with numpy from the oracle's
-    adjacency."""
-    n, s, d = rmat(scale, ef, seed)
-    G = device_graph(n, s, d)
-    lagr().lagr_property_tc_lower(G, ctx())
-    lrp, lci = lower_csr(G)
+def expected_lower(n, s, d):
+    """(rowptr, colidx) of the strict lower part of A after relabelling by
+    descending degree (ties by id), rows sorted, rebuilt with numpy from the
+    oracle's adjacency."""
     rp, ci = oracle.build_adjacency(n, s, d)
     deg = np.diff(rp)
     order = np.lexsort((np.arange(n), -deg))
@@ -116,9 +111,45 @@ def test_tc_lower_is_the_degree_relabelled_lower_part(scale, ef, seed):
     ni, nj = inv[rows], inv[ci]
     keep = nj < ni
     key = np.sort(ni[keep] * n + nj[keep])
-    want_rp = np.searchsorted(key // n, np.arange(n + 1), side="left")
+    return np.searchsorted(key // n, np.arange(n + 1), side="left"), key % n
+
+
+@pytest.mark.parametrize("scale,ef,seed", [(10, 16, 1), (11, 8, 5), (9, 32, 6)])
+def test_tc_lower_is_the_degree_relabelled_lower_part(scale, ef, seed):
+    n, s, d = rmat(scale, ef, seed)
+    G = device_graph(n, s, d)
+    lagr().lagr_property_tc_lower(G, ctx())
+    lrp, lci = lower_csr(G)
+    want_rp, want_ci = expected_lower(n, s, d)
     assert np.array_equal(lrp, want_rp)
-    assert np.array_equal(lci, key % n)
+    assert np.array_equal(lci, want_ci)
+
+
+def test_tc_lower_rows_of_every_sort_size():
+    """A dense random graph with uneven edge probabilities (p(u,v) = w_u w_v,
+    w near 1 for a core of 1,300 vertices): after the relabel, rows of L
+    run from empty to over 1,024 ids in an order unrelated to the
+    relabelled ids, so every size class of the row sort (rank sort up to 64
+    ids, wave sorts of 2 to 32 chunks of 64) has rows to put in order.  L
+    is compared with the numpy rebuild and the count with trace(A^3)/6."""
+    rng = np.random.default_rng(77)
+    n = 1400
+    w = np.where(np.arange(n) % 14 == 0, rng.uniform(0.05, 0.5, n), rng.uniform(0.9, 1.0, n))
+    iu, ju = np.triu_indices(n, 1)
+    keep = rng.random(iu.size) < w[iu] * w[ju]
+    s, d = iu[keep].astype(np.int32), ju[keep].astype(np.int32)
+    G = device_graph(n, s, d)
+    lagr().lagr_property_tc_lower(G, ctx())
+    lrp, lci = lower_csr(G)
+    want_rp, want_ci = expected_lower(n, s, d)
+    lens = np.diff(want_rp)
+    for lo, hi in ((1, 64), (65, 128), (129, 256), (257, 512), (513, 1024), (1025, 2048)):
+        assert ((lens >= lo) & (lens <= hi)).any(), (lo, hi)
+    assert np.array_equal(lrp, want_rp)
+    assert np.array_equal(lci, want_ci)
+    A = np.zeros((n, n))
+    A[s, d] = A[d, s] = 1.0
+    assert lagr().lagr_tc(G, ctx()) == int(round(np.sum((A @ A) * A) / 6))
 
 
 @pytest.mark.parametrize("entry", GOLD["graphs"], ids=lambda e: f"s{e['scale']}ef{e['edge_factor']}")
