@@ -235,10 +235,12 @@ def main():
     # algorithmic byte model of the min-side count (one launch of k_tc_split):
     # every pair (i, j) of L with p = position of j in row i >= 1 streams
     # the shorter of L_j (len(L_j) <= p: "A side", row i marked) and
-    # L_i[0, p) ("B side", row j marked); per launch the kernel reads a
-    # 12-byte descriptor per item (64 pairs at most), one 8-byte segment
-    # descriptor per pair, the streamed ids (4 B each) and every marked row
-    # once (16 B of offsets + 4 B per id).
+    # L_i[0, p) ("B side", row j marked), except that a B pair with
+    # j < 24576 and ceil(j / 32) < p reads the words of row i's bitmap up to
+    # L_j's largest id instead (a bitmap pair); per launch the kernel reads
+    # a 12-byte descriptor per item (64 pairs at most), one 8-byte
+    # descriptor per pair, the streamed ids and bitmap words (4 B each) and
+    # every marked row once (16 B of offsets + 4 B per id).
     L.lagr_property_tc_lower(G, ctx)
     Lm = G.tc_lower()
     lrp, lci, _ = Lm.to_csr(ctx)
@@ -250,16 +252,21 @@ def main():
     valid = (pos >= 1) & (lj > 0)
     side_a = valid & (lj <= pos)
     side_b = valid & (lj > pos)
-    streamed = int(lj[side_a].sum().item() + pos[side_b].sum().item())
+    jl = lci.long()
+    bitmap = side_b & (jl < 24576) & ((jl + 31) // 32 < pos)
+    last_id = lci[(lrp[1:] - 1).clamp(min=0)].long()          # largest id of each row
+    bitmap_words = int(((last_id[jl[bitmap]] >> 5) + 1).sum().item())
+    streamed = int(lj[side_a].sum().item() + pos[side_b & ~bitmap].sum().item())
     nent = int(side_a.sum().item() + side_b.sum().item())
     cnt_a = torch.bincount(row_of[side_a], minlength=n)
     cnt_b = torch.bincount(lci.long()[side_b], minlength=n)
     items = int(((cnt_a + 63) // 64).sum().item() + ((cnt_b + 63) // 64).sum().item())
     marked = int((16 + 4 * llen[cnt_a > 0]).sum().item() + (16 + 4 * llen[cnt_b > 0]).sum().item())
-    tc_bytes = 12 * items + 8 * nent + 4 * streamed + marked
-    tc_model = {"pairs": nent, "streamed_ids": streamed, "items": items,
+    tc_bytes = 12 * items + 8 * nent + 4 * (streamed + bitmap_words) + marked
+    tc_model = {"pairs": nent, "streamed_ids": streamed, "bitmap_pairs": int(bitmap.sum().item()),
+                "bitmap_words": bitmap_words, "items": items,
                 "single_side_streamed_ids": int(lj[pos >= 1].sum().item())}
-    del row_of, pos, lj, valid, side_a, side_b, cnt_a, cnt_b
+    del row_of, pos, lj, jl, valid, side_a, side_b, bitmap, last_id, cnt_a, cnt_b
 
     # per-source traversed edges for GTEPS: undirected edges in the reached set
     reached_edges = []

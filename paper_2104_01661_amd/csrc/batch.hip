@@ -20,10 +20,11 @@
 struct lagr_batch_s {
     int device = 0;
     int num_cus = 256;
-    int64_t ng = 0, R = 0, E = 0, NE = 0, K = 0;
+    int64_t ng = 0, R = 0, E = 0, NE = 0, K = 0, NB = 0;
     int64_t *rp = nullptr;          // R + 1 packed row offsets
     int32_t *ci = nullptr;          // E packed local column ids
     uint64_t *ent = nullptr;        // NE packed segment descriptors
+    uint32_t *bits = nullptr;       // NB packed bitmap words
     uint64_t *item = nullptr;       // K packed items
     int32_t *item_row = nullptr;    // K global rows
     int32_t *item_graph = nullptr;  // K graph ids
@@ -65,6 +66,18 @@ __global__ void k_pack_add_u64(const uint64_t *__restrict__ in, int64_t n, uint6
         out[i] = in[i] + add;
 }
 
+// Plan entries: segment descriptors move by add_seg, bitmap entries
+// (TC_PLAN_BITS set) by add_bits.
+__global__ void k_pack_ent(const uint64_t *__restrict__ in, int64_t n, uint64_t add_seg, uint64_t add_bits,
+                           uint64_t *__restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t x = in[i];
+        out[i] = x + ((x & TC_PLAN_BITS) ? add_bits : add_seg);
+    }
+}
+
 __global__ void k_pack_items(const int32_t *__restrict__ row, int64_t n, int32_t rbase, int32_t g,
                              int32_t *__restrict__ row_out, int32_t *__restrict__ graph_out)
 {
@@ -92,6 +105,7 @@ PlanArgs batch_args(const lagr_batch B)
     a.Lrp = B->rp;
     a.Lci = B->ci;
     a.ent = B->ent;
+    a.bits = B->bits;
     a.item = B->item;
     a.item_row = B->item_row;
     a.item_graph = B->item_graph;
@@ -142,14 +156,15 @@ extern "C" int lagr_batch_new(lagr_batch *Bout, const lagr_graph *graphs, int64_
     for (int64_t g = 0; g < ngraphs; g++)
         if (!graphs[g]) return lagr_fail(msg, LAGR_NULL_POINTER, "graph %lld is NULL", (long long)g);
     // Basic mode: compute every missing triangle-count operand
-    std::vector<int64_t> gb(ngraphs + 1), eb(ngraphs + 1), nb(ngraphs + 1), kb(ngraphs + 1);
-    gb[0] = eb[0] = nb[0] = kb[0] = 0;
+    std::vector<int64_t> gb(ngraphs + 1), eb(ngraphs + 1), nb(ngraphs + 1), kb(ngraphs + 1), bb(ngraphs + 1);
+    gb[0] = eb[0] = nb[0] = kb[0] = bb[0] = 0;
     for (int64_t g = 0; g < ngraphs; g++) {
         TRY(lagr_property_tc_lower(graphs[g], ctx, msg));
         gb[g + 1] = gb[g] + graphs[g]->L->nrows;
         eb[g + 1] = eb[g] + graphs[g]->L->nvals;
         nb[g + 1] = nb[g] + graphs[g]->tcplan->ent_cap;
         kb[g + 1] = kb[g] + graphs[g]->tcplan->nitems;
+        bb[g + 1] = bb[g] + graphs[g]->tcplan->nbits;
     }
     if (gb[ngraphs] >= ((int64_t)1 << 31))
         return lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "a batch holds fewer than 2^31 rows");
@@ -165,16 +180,18 @@ extern "C" int lagr_batch_new(lagr_batch *Bout, const lagr_graph *graphs, int64_
     B->E = eb[ngraphs];
     B->NE = nb[ngraphs];
     B->K = kb[ngraphs];
+    B->NB = bb[ngraphs];
     auto one = [](int64_t x) { return (size_t)(x > 0 ? x : 1); };
     B->rp = (int64_t *)dev_alloc(8 * (B->R + 1));
     B->ci = (int32_t *)dev_alloc(4 * one(B->E));
     B->ent = (uint64_t *)dev_alloc(8 * one(B->NE));
+    B->bits = (uint32_t *)dev_alloc(4 * one(B->NB));
     B->item = (uint64_t *)dev_alloc(8 * one(B->K));
     B->item_row = (int32_t *)dev_alloc(4 * one(B->K));
     B->item_graph = (int32_t *)dev_alloc(4 * one(B->K));
     B->counts = (unsigned long long *)dev_alloc(8 * (ngraphs + BATCH_CTRS));
     int rc = LAGR_SUCCESS;
-    if (!B->rp || !B->ci || !B->ent || !B->item || !B->item_row || !B->item_graph || !B->counts ||
+    if (!B->rp || !B->ci || !B->ent || !B->bits || !B->item || !B->item_row || !B->item_graph || !B->counts ||
         hipHostMalloc(&B->host_counts, 8 * ngraphs, hipHostMallocDefault) != hipSuccess ||
         hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&B->ready, hipEventDisableTiming) != hipSuccess) {
@@ -189,8 +206,9 @@ extern "C" int lagr_batch_new(lagr_batch *Bout, const lagr_graph *graphs, int64_
                                L->rowptr, L->nrows, eb[g], B->rp + gb[g]);
         // the whole entry array (each virtual row's region), unused slots too
         if (P->ent_cap > 0)
-            hipLaunchKernelGGL(k_pack_add_u64, dim3(grid_for(P->ent_cap, 256, 4096)), dim3(256), 0, ctx->stream,
-                               P->ent, P->ent_cap, (uint64_t)eb[g] << TC_PLAN_LEN_BITS, B->ent + nb[g]);
+            hipLaunchKernelGGL(k_pack_ent, dim3(grid_for(P->ent_cap, 256, 4096)), dim3(256), 0, ctx->stream,
+                               P->ent, P->ent_cap, (uint64_t)eb[g] << TC_PLAN_LEN_BITS, (uint64_t)bb[g],
+                               B->ent + nb[g]);
         if (P->nitems > 0) {
             hipLaunchKernelGGL(k_pack_add_u64, dim3(grid_for(P->nitems, 256, 4096)), dim3(256), 0, ctx->stream,
                                P->item, P->nitems, (uint64_t)nb[g] << TC_PLAN_CNT_BITS, B->item + kb[g]);
@@ -201,6 +219,10 @@ extern "C" int lagr_batch_new(lagr_batch *Bout, const lagr_graph *graphs, int64_
         if (hipGetLastError() != hipSuccess) rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "pack launch");
         if (rc >= 0 && L->nvals > 0 &&
             hipMemcpyAsync(B->ci + eb[g], L->colidx, 4 * L->nvals, hipMemcpyDeviceToDevice, ctx->stream) !=
+                hipSuccess)
+            rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "pack copy");
+        if (rc >= 0 && P->nbits > 0 &&
+            hipMemcpyAsync(B->bits + bb[g], P->bits, 4 * P->nbits, hipMemcpyDeviceToDevice, ctx->stream) !=
                 hipSuccess)
             rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "pack copy");
     }
@@ -315,6 +337,7 @@ extern "C" int lagr_batch_free(lagr_batch *Bp)
     dev_free(B->rp, 8 * (B->R + 1));
     dev_free(B->ci, 4 * one(B->E));
     dev_free(B->ent, 8 * one(B->NE));
+    dev_free(B->bits, 4 * one(B->NB));
     dev_free(B->item, 8 * one(B->K));
     dev_free(B->item_row, 4 * one(B->K));
     dev_free(B->item_graph, 4 * one(B->K));

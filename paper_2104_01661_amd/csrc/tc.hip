@@ -114,6 +114,102 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_hot(const int32_t *__restri
         mine[x] = hot[x] ? (unsigned)((int64_t)atomicAdd(&cur[n + x], (unsigned long long)hot[x]) - bstart) : 0u;
 }
 
+// bw[i] = the bitmap words row i needs: ceil(j / 32) for its largest id j
+// that tc_bitmap_pair accepts at its position (0 for none; zero on entry).
+// One lane per entry of L; the lanes of one row take their maximum within
+// the wave and the run head makes the row's one atomic.
+__global__ void k_bitmap_words(const int32_t *__restrict__ rowid, const int32_t *__restrict__ ci, int64_t nnz,
+                               const uint64_t *__restrict__ rowpk, unsigned long long *__restrict__ bw)
+{
+    const unsigned lane = lane_id();
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t w0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); w0 < nnz; w0 += step) {
+        const int64_t e = w0 + lane;
+        int32_t i = -1;
+        unsigned v = 0;
+        if (e < nnz) {
+            i = rowid[e];
+            const int32_t j = ci[e];
+            const int64_t p = e - (int64_t)(rowpk[i] >> TC_PLAN_LEN_BITS);
+            if (tc_bitmap_pair(j, p)) v = (unsigned)((j + 31) >> 5);
+        }
+        const WaveRun w = wave_run(i);
+        // maximum over the run: ids ascend along a row, so the last lane of
+        // the run that accepts holds it
+        const uint64_t acc = __ballot(v > 0) & w.run;
+        if (acc) {
+            const int last = 63 - __clzll((unsigned long long)acc);
+            const unsigned m = (unsigned)__shfl((int)v, last, 64);
+            if (lane == w.head) atomicMax(&bw[i], (unsigned long long)m);
+        }
+    }
+}
+
+// The rows with bitmap words (off[r + 1] > off[r]), listed in
+// rows[0 .. *count) (count zero on entry): they are contiguous runs of
+// labels, so the build below spreads them over all waves through this list.
+// Each workgroup reserves its range with one atomic.
+__global__ __launch_bounds__(256) void k_bitmap_list(const int64_t *__restrict__ off, int64_t n,
+                                                     int32_t *__restrict__ rows, unsigned long long *count)
+{
+    __shared__ unsigned sc[256];
+    __shared__ unsigned long long base_s;
+    const int64_t share = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t v0 = (int64_t)blockIdx.x * share, v1 = min(n, v0 + share);
+    unsigned c = 0;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += 256) c += off[v + 1] > off[v] ? 1u : 0u;
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const unsigned y = (int)threadIdx.x >= o ? sc[threadIdx.x - o] : 0u;
+        __syncthreads();
+        sc[threadIdx.x] += y;
+        __syncthreads();
+    }
+    if (threadIdx.x == 255) base_s = sc[255] ? atomicAdd(count, (unsigned long long)sc[255]) : 0;
+    __syncthreads();
+    unsigned long long pos = base_s + sc[threadIdx.x] - c;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += 256)
+        if (off[v + 1] > off[v]) rows[pos++] = (int32_t)v;
+}
+
+// One listed row per wave: the bits of the row's ids below 32 words (a
+// prefix of the sorted row) gathered in the wave's LDS, then written out.
+constexpr int BITMAP_BLOCK = 256;
+
+__global__ __launch_bounds__(BITMAP_BLOCK) void k_bitmap_build(const int32_t *__restrict__ rows,
+                                                               const unsigned long long *__restrict__ count,
+                                                               const int64_t *__restrict__ Lrp,
+                                                               const int32_t *__restrict__ Lci,
+                                                               const int64_t *__restrict__ off,
+                                                               uint32_t *__restrict__ bits)
+{
+    __shared__ uint32_t buf[BITMAP_BLOCK / 64][TC_BM_WORDS];
+    uint32_t *wb = buf[threadIdx.x / 64];
+    const unsigned lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const int64_t nrows = (int64_t)*count;
+    for (int64_t c = wave; c < nrows; c += nw) {
+        const int32_t r = rows[c];
+        const int64_t ob = off[r];
+        const int nwr = (int)(off[r + 1] - ob);
+        const int64_t b = Lrp[r], e = Lrp[r + 1];
+        for (int x = lane; x < nwr; x += 64) wb[x] = 0u;
+        wave_sync();
+        const int32_t lim = 32 * nwr;
+        for (int64_t t0 = b; t0 < e; t0 += 64) {
+            const int64_t t = t0 + lane;
+            const int32_t x = t < e ? Lci[t] : INT32_MAX;
+            if (x < lim) atomicOr(&wb[x >> 5], 1u << (x & 31));
+            if (__shfl(x, 63, 64) >= lim) break;   // the row ascends
+        }
+        wave_sync();
+        for (int x = lane; x < nwr; x += 64) bits[ob + x] = wb[x];
+        wave_sync();
+    }
+}
+
 // Each wave takes PLAN_ILP windows of 64 consecutive entries per iteration
 // and runs them stage by stage (their loads, then their gathers, then
 // their atomics), so a wave waits for each round trip once per PLAN_ILP
@@ -126,12 +222,14 @@ constexpr int PLAN_ILP = 2;
 // the write cursor of each virtual row; the order of the entries within a
 // row is immaterial.  Hot B rows hand out positions from LDS as offsets
 // from bstart = trp[n], the first B-side slot, starting at the workgroup's
-// reservation.
+// reservation.  A B pair that tc_bitmap_pair accepts gets the entry
+// TC_PLAN_BITS | (offset of row i's bitmap) in the same slot.
 __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restrict__ rowid,
                                                           const int32_t *__restrict__ ci, int64_t nnz,
                                                           const uint64_t *__restrict__ rowpk, int64_t n,
                                                           const int64_t *__restrict__ trp,
                                                           const unsigned *__restrict__ boff,
+                                                          const int64_t *__restrict__ bitoff,
                                                           unsigned long long *__restrict__ cur,
                                                           uint64_t *__restrict__ ent)
 {
@@ -173,6 +271,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restr
             bpos[k] = -1;
             bval[k] = plan_pack(si, p);
             if (valid && !a_side[k]) {
+                if (tc_bitmap_pair(j[k], p)) bval[k] = TC_PLAN_BITS | (uint64_t)bitoff[i[k]];
                 if (j[k] < PLAN_HOT) bpos[k] = bstart + (int64_t)atomicAdd(&hot[j[k]], 1u);
                 else bpos[k] = (int64_t)atomicAdd(&cur[n + j[k]], 1ull);
             }
@@ -290,16 +389,19 @@ void tc_plan_free(lagr_graph G)
     dev_free(P->ent, 8 * (size_t)(P->ent_cap > 0 ? P->ent_cap : 1));
     dev_free(P->item, 8 * (size_t)(P->item_cap > 0 ? P->item_cap : 1));
     dev_free(P->item_row, 4 * (size_t)(P->item_cap > 0 ? P->item_cap : 1));
+    dev_free(P->boff, 8 * (size_t)(P->n + 1));
+    dev_free(P->bits, 4 * (size_t)(P->bits_cap > 0 ? P->bits_cap : 1));
     delete P;
     G->tcplan = nullptr;
 }
 
 // Built without a host round trip: the entries go to regions of known size
-// (2 nnz slots in all) and the items take at most nnz/64 + one per
-// non-empty virtual row, so every array is allocated at its bound.  The
-// pair and item counts are trp[2n+1] and irp[2n] on the device; the caller
-// reads them back (with the rest of its status) and sets P->nent and
-// P->nitems.
+// (2 nnz slots in all), the items take at most nnz/64 + one per non-empty
+// virtual row and the bitmaps fewer words than L has entries (a row's
+// words stay below its length), so every array is allocated at its bound.
+// The pair, item and bitmap word counts are trp[2n+1], irp[2n] and boff[n]
+// on the device; the caller reads them back (with the rest of its status)
+// and sets P->nent, P->nitems and P->nbits.
 int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_t *regions, char *msg)
 {
     const lagr_matrix Lm = G->L;
@@ -313,6 +415,7 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
     P->nent = P->nitems = -1;
     P->ent_cap = 2 * nnz;
     P->item_cap = nnz / 64 + (nv < nnz ? nv : nnz) + 1;
+    P->bits_cap = nnz > 0 ? nnz : 1;
     G->tcplan = P;
     auto fail = [&](int rc) {
         tc_plan_free(G);
@@ -323,12 +426,15 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
     P->ent = (uint64_t *)dev_alloc(8 * (size_t)(P->ent_cap > 0 ? P->ent_cap : 1));
     P->item = (uint64_t *)dev_alloc(8 * (size_t)P->item_cap);
     P->item_row = (int32_t *)dev_alloc(4 * (size_t)P->item_cap);
-    if (!P->trp || !P->irp || !P->ent || !P->item || !P->item_row)
+    P->boff = (int64_t *)dev_alloc(8 * (size_t)(n + 1));
+    P->bits = (uint32_t *)dev_alloc(4 * (size_t)P->bits_cap);
+    if (!P->trp || !P->irp || !P->ent || !P->item || !P->item_row || !P->boff || !P->bits)
         return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
     int rc;
     if (hipMemcpyAsync(P->trp, regions, 8 * (size_t)(nv + 1), hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
         return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan copy"));
     if ((rc = fill_i64(ctx, P->trp + nv + 1, 1, 0, msg)) < 0) return fail(rc);
+    if ((rc = fill_i64(ctx, P->boff, n + 1, 0, msg)) < 0) return fail(rc);
     unsigned *boff = (unsigned *)ws_get(ctx, WS_GEN_H, sizeof(unsigned) * (size_t)PLAN_GRID * PLAN_HOT);
     uint64_t *rowpk = (uint64_t *)ws_get(ctx, WS_GEN_E, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     unsigned long long *cur = (unsigned long long *)ws_get(ctx, WS_TC_WORK, 8 * (size_t)(nv > 0 ? nv : 1));
@@ -339,11 +445,26 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
         hipLaunchKernelGGL(k_row_pack, dim3(grid_for(n, 256, 16384)), dim3(256), 0, ctx->stream, Lm->rowptr, n,
                            rowpk);
         if (nnz > 0) {
+            hipLaunchKernelGGL(k_bitmap_words, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, ctx->stream, rowid,
+                               Lm->colidx, nnz, rowpk, (unsigned long long *)P->boff);
             hipLaunchKernelGGL(k_plan_hot, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx,
                                nnz, rowpk, n, P->trp, cur, boff);
-            hipLaunchKernelGGL(k_plan_fill, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx,
-                               nnz, rowpk, n, P->trp, boff, cur, P->ent);
         }
+        if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
+        if ((rc = scan_exclusive_i64(ctx, P->boff, P->boff, n + 1, nullptr, msg)) < 0) return fail(rc);
+        // rows needing bitmaps, listed (n ids, then the count), then one
+        // wave each
+        int32_t *brows = (int32_t *)ws_get(ctx, WS_GEN_F, sizeof(int32_t) * (size_t)n + 64);
+        if (!brows) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
+        unsigned long long *nbrows = (unsigned long long *)(brows + n + (n & 1));
+        if ((rc = fill_i64(ctx, (int64_t *)nbrows, 1, 0, msg)) < 0) return fail(rc);
+        hipLaunchKernelGGL(k_bitmap_list, dim3(grid_for(n, 256, 1024)), dim3(256), 0, ctx->stream, P->boff, n, brows,
+                           nbrows);
+        hipLaunchKernelGGL(k_bitmap_build, dim3((unsigned)(ctx->num_cus * 8)), dim3(BITMAP_BLOCK), 0, ctx->stream,
+                           brows, nbrows, Lm->rowptr, Lm->colidx, P->boff, P->bits);
+        if (nnz > 0)
+            hipLaunchKernelGGL(k_plan_fill, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx,
+                               nnz, rowpk, n, P->trp, boff, P->boff, cur, P->ent);
         hipLaunchKernelGGL(k_plan_items, dim3(grid_for(nv, 256, 4096)), dim3(256), 0, ctx->stream, P->trp, cur, nv,
                            P->irp, (unsigned long long *)(P->trp + nv + 1));
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
@@ -360,14 +481,16 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
 
 namespace {
 
-// status[2..4] = plan entries, plan items, entries of L.
+// status[2..5] = plan entries, plan items, entries of L, bitmap words.
 __global__ void k_tc_status(const int64_t *__restrict__ nent, const int64_t *__restrict__ nitems,
-                            const int64_t *__restrict__ nnzL, unsigned long long *__restrict__ status)
+                            const int64_t *__restrict__ nnzL, const int64_t *__restrict__ nbits,
+                            unsigned long long *__restrict__ status)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         status[2] = (unsigned long long)*nent;
         status[3] = (unsigned long long)*nitems;
         status[4] = (unsigned long long)*nnzL;
+        status[5] = (unsigned long long)*nbits;
     }
 }
 
@@ -378,9 +501,9 @@ int tc_plan_settle(lagr_ctx ctx, lagr_graph G, unsigned long long *status, int64
     TcPlan *P = G->tcplan;
     const int64_t n = G->L->nrows;
     hipLaunchKernelGGL(k_tc_status, dim3(1), dim3(64), 0, ctx->stream, P->trp + 2 * n + 1, P->irp + 2 * n,
-                       G->L->rowptr + n, status);
+                       G->L->rowptr + n, P->boff + n, status);
     LAUNCH_CHECK();
-    unsigned long long st[5] = {0, 0, 0, 0, 0};
+    unsigned long long st[6] = {0, 0, 0, 0, 0, 0};
     TRY(read_back(ctx, st, status, sizeof(st), msg));
     if ((int64_t)st[4] != nnz)
         return lagr_fail(msg, LAGR_INVALID_OBJECT, "L has %lld entries, expected %lld", (long long)st[4],
@@ -393,6 +516,7 @@ int tc_plan_settle(lagr_ctx ctx, lagr_graph G, unsigned long long *status, int64
     G->L_maxrow = (int64_t)st[0];
     P->nent = (int64_t)st[2];
     P->nitems = (int64_t)st[3];
+    P->nbits = (int64_t)st[5];
     return LAGR_SUCCESS;
 }
 
@@ -442,7 +566,7 @@ static int tc_on_lower(lagr_ctx ctx, const lagr_graph G, int64_t *ntri, char *ms
     if (P->nitems > 0) {
         unsigned long long *ctr = tot + 1 + blocks;
         TRY(fill_i64(ctx, (int64_t *)ctr, (int64_t)nctr, 0, msg));
-        PlanArgs a{P->nitems, L->rowptr, L->colidx, P->ent, P->item, P->item_row};
+        PlanArgs a{P->nitems, L->rowptr, L->colidx, P->ent, P->item, P->item_row, P->bits};
         TIMED(ctx, "tc_split",
               hipLaunchKernelGGL(k_tc_split, dim3(blocks), dim3(TC_BLOCK), 0, ctx->stream, a, tot + 1, ctr));
         LAUNCH_CHECK();

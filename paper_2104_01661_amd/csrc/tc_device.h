@@ -414,11 +414,31 @@ int tc_masked_dot(lagr_ctx ctx, const TcArgs &a, bool per_entry, unsigned long l
 // length.  The virtual rows are cut into items of up to 64 entries; an
 // item records its first entry and count and the row it marks.
 //
+// Bitmap pairs.  A B-side pair whose marked row j has a low id reads
+// fewer words as bits than as ids when ceil(j/32) < p: L_i[0, p) is L_i
+// below j, which the first ceil(j/32) words of a bitmap of L_i hold, and
+// L_j's marks are a bitmap in LDS already, so the pair counts
+// popcount(word & mark word) over those words instead of probing p ids
+// (a row holding many of the highest-degree vertices pays for them once
+// per hub pair otherwise; the bitmap form of a row in SuiteSparse's
+// formats plays the same part).  Every row of L with such a pair keeps
+// the bits of its ids below 32 * bw words in `bits` at boff(i), where bw
+// covers its largest such j.  These pairs sit among row j's B entries as
+// TC_PLAN_BITS | boff(i); a wave streams an item's segments and then reads
+// the bitmaps of its flagged entries.
+//
 // Items are handed to waves a few at a time (tc_dyn_wave); consecutive
 // items of a row usually go to the same wave, which then keeps the row's
 // marks.
 constexpr int TC_PLAN_LEN_BITS = 24;
 constexpr int TC_PLAN_CNT_BITS = 7;
+constexpr uint64_t TC_PLAN_BITS = 1ull << 63;   // bitmap entry flag
+
+// The pair (id j marked at position p of row i) is a bitmap pair.
+__host__ __device__ __forceinline__ bool tc_bitmap_pair(int64_t j, int64_t p)
+{
+    return j < TC_BM_IDS && ((j + 31) >> 5) < p;
+}
 
 struct TcPlan {
     int64_t n = 0;          // rows of L
@@ -431,6 +451,10 @@ struct TcPlan {
     uint64_t *ent = nullptr;     // ent_cap packed segments; the tail of each region is unused
     uint64_t *item = nullptr;    // nitems: (first entry << TC_PLAN_CNT_BITS) | count
     int32_t *item_row = nullptr; // nitems: row of L the item marks
+    int64_t nbits = 0;           // bitmap words in use (set once read back)
+    int64_t bits_cap = 0;        // allocated bitmap words (nnz(L) bounds them)
+    int64_t *boff = nullptr;     // n+1: bitmap word offsets of the rows of L
+    uint32_t *bits = nullptr;    // bitmaps of the rows with bitmap pairs
 };
 
 struct PlanArgs {
@@ -440,6 +464,7 @@ struct PlanArgs {
     const uint64_t *ent;
     const uint64_t *item;
     const int32_t *item_row;
+    const uint32_t *bits;
     // many packed graphs: the graph of each item and its counter (else null)
     const int32_t *item_graph = nullptr;
     unsigned long long *per_graph = nullptr;
@@ -457,6 +482,41 @@ struct PlanArgs {
 // the next eighth in turn.  The counters must be zero at launch.  With
 // BATCHED each graph's part of the count is added to per_graph[g] (the
 // items of one graph are contiguous) and the result is 0.
+// The bitmap pairs of one item (lanes with `flag`, each holding the bitmap
+// offset of its streamed row in off): the marked row L_j's bits are in
+// L.bm, all in its first nw words (nw covers L_j's largest id, so nw <=
+// ceil(j/32), which every streamed row's bitmap covers).  The pairs are
+// compacted into L.seg_s (free once tc_stream_flat has returned), and the
+// (pair, word) grid is laid out with the words of a pair padded to a power
+// of two, TC_FLAT_INFLIGHT loads of 64 lanes in flight.
+__device__ __forceinline__ unsigned long long tc_bitmap_lanes(TcWaveLds &L, const uint32_t *__restrict__ bits,
+                                                              int64_t off, bool flag, int nw, unsigned lane)
+{
+    const uint64_t M = __ballot(flag);
+    const int np = __popcll(M);
+    if (flag) L.seg_s[__popcll(M & ((1ull << lane) - 1))] = off;
+    wave_sync();
+    int lg = 0;
+    while ((1 << lg) < nw) lg++;
+    const int total = np << lg;
+    unsigned long long acc = 0;
+    for (int g0 = 0; g0 < total; g0 += 64 * TC_FLAT_INFLIGHT) {
+        uint32_t x[TC_FLAT_INFLIGHT], y[TC_FLAT_INFLIGHT];
+#pragma unroll
+        for (int f = 0; f < TC_FLAT_INFLIGHT; f++) {
+            const int g = g0 + 64 * f + (int)lane;
+            const int q = g >> lg, w = g & ((1 << lg) - 1);
+            const bool v = g < total && w < nw;
+            x[f] = v ? bits[L.seg_s[q] + w] : 0u;
+            y[f] = v ? L.bm[w] : 0u;
+        }
+#pragma unroll
+        for (int f = 0; f < TC_FLAT_INFLIGHT; f++) acc += (unsigned)__popc(x[f] & y[f]);
+    }
+    wave_sync();
+    return acc;
+}
+
 constexpr int64_t TC_DYN_ITEMS = 4;
 constexpr int TC_DYN_STRIDE = 16;   // 128 bytes between counters
 constexpr int TC_DYN_PARTS = 8;
@@ -471,7 +531,7 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
     const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
     const int64_t N = a.nitems;
     unsigned long long acc = 0;
-    int32_t marked = -1, first_id = -1, g = -1;
+    int32_t marked = -1, first_id = -1, g = -1, mark_words = 0;
     int64_t alen = 0;
     const int32_t *Arow = nullptr;
     bool use_hash = false;
@@ -507,19 +567,24 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
             const int cnt = (int)(it & ((1u << TC_PLAN_CNT_BITS) - 1));
             int64_t s = 0;
             int len = 0;
+            bool bitmap = false;
             if ((int)lane < cnt) {
                 const uint64_t x = a.ent[e0 + lane];
-                s = (int64_t)(x >> TC_PLAN_LEN_BITS);
-                len = (int)(x & lmask);
+                bitmap = (x & TC_PLAN_BITS) != 0;
+                s = bitmap ? (int64_t)(x & ~TC_PLAN_BITS) : (int64_t)(x >> TC_PLAN_LEN_BITS);
+                len = bitmap ? 0 : (int)(x & lmask);
             }
             if (m != marked) {
                 if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
                 Arow = a.Lci + a.Lrp[m];
                 alen = a.Lrp[m + 1] - a.Lrp[m];
                 use_hash = tc_mark(L, Arow, alen, lane, &first_id);
+                // words of L.bm a bitmap pair reads: up to the row's largest id
+                mark_words = alen > 0 ? (Arow[alen - 1] >> 5) + 1 : 0;
                 marked = m;
             }
             acc += tc_stream_flat(L, use_hash, Arow, alen, a.Lci, s, len, cnt, lane);
+            if (__ballot(bitmap)) acc += tc_bitmap_lanes(L, a.bits, s, bitmap, mark_words, lane);
         }
     }
     if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
