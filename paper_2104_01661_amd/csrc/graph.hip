@@ -799,7 +799,7 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
         goto fail;
     }
     if (n > 0) {
-        hipLaunchKernelGGL(k_row_max, dim3(grid_for(n, 256, 1024)), dim3(256), 0, ctx->stream, L->rowptr, n, status);
+        hipLaunchKernelGGL(k_row_max, dim3(grid_for(n, 256, 256)), dim3(256), 0, ctx->stream, L->rowptr, n, status);
         // the row of every entry of L (the plan reads it too)
         hipLaunchKernelGGL(k_row_ids, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, L->rowptr, n,
                            (int64_t)INT64_MAX, rowid);

@@ -62,6 +62,54 @@ __global__ void k_scan_tiles(const int64_t *__restrict__ in, int64_t *__restrict
     if (threadIdx.x == 0 && tile_sums) tile_sums[blockIdx.x] = total;
 }
 
+// Two-pass form for up to SCAN_DIRECT tiles: k_tile_sums, then each block
+// adds the sums of the tiles before it itself (at most SCAN_DIRECT values,
+// from L2) and scans its tile, instead of scanning the sums in a third
+// launch and adding them back in a fourth.
+constexpr int64_t SCAN_DIRECT = 4096;
+
+__global__ void k_tile_sums(const int64_t *__restrict__ in, int64_t n, int64_t *__restrict__ tile_sums)
+{
+    __shared__ int64_t lds[SCAN_BLOCK / 64 + 1];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        const int64_t idx = base + i;
+        s += idx < n ? in[idx] : 0;
+    }
+    int64_t total;
+    block_exclusive_scan(s, lds, total);
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_tiles_after(const int64_t *__restrict__ in, int64_t *__restrict__ out, int64_t n,
+                                   const int64_t *__restrict__ tile_sums)
+{
+    __shared__ int64_t lds[SCAN_BLOCK / 64 + 1];
+    int64_t before = 0;
+    for (int64_t t = threadIdx.x; t < (int64_t)blockIdx.x; t += SCAN_BLOCK) before += tile_sums[t];
+    int64_t prefix;
+    block_exclusive_scan(before, lds, prefix);
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int64_t v[SCAN_ITEMS];
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        const int64_t idx = base + i;
+        v[i] = idx < n ? in[idx] : 0;
+        s += v[i];
+    }
+    int64_t total;
+    int64_t run = block_exclusive_scan(s, lds, total) + prefix;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        const int64_t idx = base + i;
+        if (idx < n) out[idx] = run;
+        run += v[i];
+    }
+}
+
 __global__ void k_scan_add(int64_t *__restrict__ out, int64_t n, const int64_t *__restrict__ tile_offs)
 {
     const int64_t add = tile_offs[blockIdx.x];
@@ -93,6 +141,13 @@ static int scan_level(lagr_ctx ctx, const int64_t *in, int64_t *out, int64_t n, 
     if (level >= 4) return lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "scan: input too large");
     int64_t *sums = (int64_t *)ws_get(ctx, (WsSlot)(WS_SCAN_L0 + level), sizeof(int64_t) * tiles);
     if (!sums) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "scan workspace");
+    if (tiles <= SCAN_DIRECT) {
+        hipLaunchKernelGGL(k_tile_sums, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, ctx->stream, in, n, sums);
+        hipLaunchKernelGGL(k_scan_tiles_after, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, ctx->stream, in, out, n,
+                           sums);
+        LAUNCH_CHECK();
+        return LAGR_SUCCESS;
+    }
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, ctx->stream, in,
                        out, n, sums);
     LAUNCH_CHECK();

@@ -291,26 +291,13 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restr
 }
 
 // irp[r] = items of virtual row r (its entries, cur[r] - trp[r], in runs of
-// up to 64); *pairs (zero on entry) = the entries over all rows, one
-// atomic per workgroup.
-__global__ __launch_bounds__(256) void k_plan_items(const int64_t *__restrict__ trp,
-                                                    const unsigned long long *__restrict__ cur, int64_t nv,
-                                                    int64_t *__restrict__ irp, unsigned long long *pairs)
+// up to 64).
+__global__ void k_plan_items(const int64_t *__restrict__ trp, const unsigned long long *__restrict__ cur, int64_t nv,
+                             int64_t *__restrict__ irp)
 {
-    __shared__ unsigned long long tot;
-    if (threadIdx.x == 0) tot = 0;
-    __syncthreads();
-    unsigned long long c = 0;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nv;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = (int64_t)cur[r] - trp[r];
-        irp[r] = (k + 63) / 64;
-        c += (unsigned long long)k;
-    }
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-    if (lane_id() == 0 && c) atomicAdd(&tot, c);
-    __syncthreads();
-    if (threadIdx.x == 0 && tot) atomicAdd(pairs, tot);
+         r += (int64_t)gridDim.x * blockDim.x)
+        irp[r] = ((int64_t)cur[r] - trp[r] + 63) / 64;
 }
 
 // First virtual row r in [0, nv) with irp[r + 1] > k.
@@ -384,7 +371,7 @@ void tc_plan_free(lagr_graph G)
     TcPlan *P = G->tcplan;
     if (!P) return;
     const size_t nv = (size_t)(2 * P->n);
-    dev_free(P->trp, 8 * (nv + 2));
+    dev_free(P->trp, 8 * (nv + 1));
     dev_free(P->irp, 8 * (nv + 1));
     dev_free(P->ent, 8 * (size_t)(P->ent_cap > 0 ? P->ent_cap : 1));
     dev_free(P->item, 8 * (size_t)(P->item_cap > 0 ? P->item_cap : 1));
@@ -399,9 +386,9 @@ void tc_plan_free(lagr_graph G)
 // (2 nnz slots in all), the items take at most nnz/64 + one per non-empty
 // virtual row and the bitmaps fewer words than L has entries (a row's
 // words stay below its length), so every array is allocated at its bound.
-// The pair, item and bitmap word counts are trp[2n+1], irp[2n] and boff[n]
-// on the device; the caller reads them back (with the rest of its status)
-// and sets P->nent, P->nitems and P->nbits.
+// The item and bitmap word counts are irp[2n] and boff[n] on the device;
+// the caller reads them back (with the rest of its status) and sets
+// P->nitems and P->nbits.
 int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_t *regions, char *msg)
 {
     const lagr_matrix Lm = G->L;
@@ -412,7 +399,7 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
     TcPlan *P = new (std::nothrow) TcPlan();
     if (!P) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan");
     P->n = n;
-    P->nent = P->nitems = -1;
+    P->nitems = -1;
     P->ent_cap = 2 * nnz;
     P->item_cap = nnz / 64 + (nv < nnz ? nv : nnz) + 1;
     P->bits_cap = nnz > 0 ? nnz : 1;
@@ -421,7 +408,7 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
         tc_plan_free(G);
         return rc;
     };
-    P->trp = (int64_t *)dev_alloc(8 * (size_t)(nv + 2));
+    P->trp = (int64_t *)dev_alloc(8 * (size_t)(nv + 1));
     P->irp = (int64_t *)dev_alloc(8 * (size_t)(nv + 1));
     P->ent = (uint64_t *)dev_alloc(8 * (size_t)(P->ent_cap > 0 ? P->ent_cap : 1));
     P->item = (uint64_t *)dev_alloc(8 * (size_t)P->item_cap);
@@ -433,7 +420,6 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
     int rc;
     if (hipMemcpyAsync(P->trp, regions, 8 * (size_t)(nv + 1), hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
         return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan copy"));
-    if ((rc = fill_i64(ctx, P->trp + nv + 1, 1, 0, msg)) < 0) return fail(rc);
     if ((rc = fill_i64(ctx, P->boff, n + 1, 0, msg)) < 0) return fail(rc);
     unsigned *boff = (unsigned *)ws_get(ctx, WS_GEN_H, sizeof(unsigned) * (size_t)PLAN_GRID * PLAN_HOT);
     uint64_t *rowpk = (uint64_t *)ws_get(ctx, WS_GEN_E, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
@@ -465,8 +451,8 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
         if (nnz > 0)
             hipLaunchKernelGGL(k_plan_fill, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx,
                                nnz, rowpk, n, P->trp, boff, P->boff, cur, P->ent);
-        hipLaunchKernelGGL(k_plan_items, dim3(grid_for(nv, 256, 4096)), dim3(256), 0, ctx->stream, P->trp, cur, nv,
-                           P->irp, (unsigned long long *)(P->trp + nv + 1));
+        hipLaunchKernelGGL(k_plan_items, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, ctx->stream, P->trp, cur, nv,
+                           P->irp);
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
     }
     if ((rc = fill_i64(ctx, P->irp + nv, 1, 0, msg)) < 0) return fail(rc);
@@ -481,13 +467,11 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
 
 namespace {
 
-// status[2..5] = plan entries, plan items, entries of L, bitmap words.
-__global__ void k_tc_status(const int64_t *__restrict__ nent, const int64_t *__restrict__ nitems,
-                            const int64_t *__restrict__ nnzL, const int64_t *__restrict__ nbits,
-                            unsigned long long *__restrict__ status)
+// status[3..5] = plan items, entries of L, bitmap words.
+__global__ void k_tc_status(const int64_t *__restrict__ nitems, const int64_t *__restrict__ nnzL,
+                            const int64_t *__restrict__ nbits, unsigned long long *__restrict__ status)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        status[2] = (unsigned long long)*nent;
         status[3] = (unsigned long long)*nitems;
         status[4] = (unsigned long long)*nnzL;
         status[5] = (unsigned long long)*nbits;
@@ -500,8 +484,8 @@ int tc_plan_settle(lagr_ctx ctx, lagr_graph G, unsigned long long *status, int64
 {
     TcPlan *P = G->tcplan;
     const int64_t n = G->L->nrows;
-    hipLaunchKernelGGL(k_tc_status, dim3(1), dim3(64), 0, ctx->stream, P->trp + 2 * n + 1, P->irp + 2 * n,
-                       G->L->rowptr + n, P->boff + n, status);
+    hipLaunchKernelGGL(k_tc_status, dim3(1), dim3(64), 0, ctx->stream, P->irp + 2 * n, G->L->rowptr + n,
+                       P->boff + n, status);
     LAUNCH_CHECK();
     unsigned long long st[6] = {0, 0, 0, 0, 0, 0};
     TRY(read_back(ctx, st, status, sizeof(st), msg));
@@ -511,10 +495,7 @@ int tc_plan_settle(lagr_ctx ctx, lagr_graph G, unsigned long long *status, int64
     *unsorted = st[1] != 0;
     if (st[0] >= ((unsigned long long)1 << TC_PLAN_LEN_BITS))
         return lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "rows of L too long for the count plan");
-    if (st[2] >= ((unsigned long long)1 << 32))
-        return lagr_fail(msg, LAGR_NOT_IMPLEMENTED, "L too large for the count plan");
     G->L_maxrow = (int64_t)st[0];
-    P->nent = (int64_t)st[2];
     P->nitems = (int64_t)st[3];
     P->nbits = (int64_t)st[5];
     return LAGR_SUCCESS;

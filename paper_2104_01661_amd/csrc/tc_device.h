@@ -442,11 +442,10 @@ __host__ __device__ __forceinline__ bool tc_bitmap_pair(int64_t j, int64_t p)
 
 struct TcPlan {
     int64_t n = 0;          // rows of L
-    int64_t nent = 0;       // pairs over both sides (set once read back)
     int64_t nitems = 0;
     int64_t ent_cap = 0;    // entry slots, 2 nnz(L): every virtual row has its own region
     int64_t item_cap = 0;   // allocated items (>= nitems)
-    int64_t *trp = nullptr;      // 2n+2: region starts of the virtual rows, then the pair count
+    int64_t *trp = nullptr;      // 2n+1: region starts of the virtual rows
     int64_t *irp = nullptr;      // 2n+1 item offsets of the virtual rows
     uint64_t *ent = nullptr;     // ent_cap packed segments; the tail of each region is unused
     uint64_t *item = nullptr;    // nitems: (first entry << TC_PLAN_CNT_BITS) | count
