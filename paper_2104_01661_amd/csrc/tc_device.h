@@ -486,8 +486,9 @@ struct PlanArgs {
 // L.bm, all in its first nw words (nw covers L_j's largest id, so nw <=
 // ceil(j/32), which every streamed row's bitmap covers).  The pairs are
 // compacted into L.seg_s (free once tc_stream_flat has returned), and the
-// (pair, word) grid is laid out with the words of a pair padded to a power
-// of two, TC_FLAT_INFLIGHT loads of 64 lanes in flight.
+// (pair, word) grid g = q * nw + w is walked 64 elements per load,
+// TC_FLAT_INFLIGHT loads in flight; q = g / nw by a multiply with
+// ceil(2^32 / nw), exact while g * nw < 2^32 (g < 64 * 768 here).
 __device__ __forceinline__ unsigned long long tc_bitmap_lanes(TcWaveLds &L, const uint32_t *__restrict__ bits,
                                                               int64_t off, bool flag, int nw, unsigned lane)
 {
@@ -495,17 +496,16 @@ __device__ __forceinline__ unsigned long long tc_bitmap_lanes(TcWaveLds &L, cons
     const int np = __popcll(M);
     if (flag) L.seg_s[__popcll(M & ((1ull << lane) - 1))] = off;
     wave_sync();
-    int lg = 0;
-    while ((1 << lg) < nw) lg++;
-    const int total = np << lg;
+    const unsigned long long magic = (0x100000000ull + (unsigned)nw - 1) / (unsigned)nw;   // 2^32 for nw = 1
+    const int total = np * nw;
     unsigned long long acc = 0;
     for (int g0 = 0; g0 < total; g0 += 64 * TC_FLAT_INFLIGHT) {
         uint32_t x[TC_FLAT_INFLIGHT], y[TC_FLAT_INFLIGHT];
 #pragma unroll
         for (int f = 0; f < TC_FLAT_INFLIGHT; f++) {
             const int g = g0 + 64 * f + (int)lane;
-            const int q = g >> lg, w = g & ((1 << lg) - 1);
-            const bool v = g < total && w < nw;
+            const int q = (int)(((unsigned long long)(unsigned)g * magic) >> 32), w = g - q * nw;
+            const bool v = g < total;
             x[f] = v ? bits[L.seg_s[q] + w] : 0u;
             y[f] = v ? L.bm[w] : 0u;
         }
