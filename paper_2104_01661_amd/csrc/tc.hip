@@ -114,10 +114,14 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_hot(const int32_t *__restri
         mine[x] = hot[x] ? (unsigned)((int64_t)atomicAdd(&cur[n + x], (unsigned long long)hot[x]) - bstart) : 0u;
 }
 
-// bw[i] = the bitmap words row i needs: ceil(j / 32) for its largest id j
-// that tc_bitmap_pair accepts at its position (0 for none; zero on entry).
-// One lane per entry of L; the lanes of one row take their maximum within
-// the wave and the run head makes the row's one atomic.
+// bw[i] = the bitmap words row i needs (0 for none; zero on entry):
+// ceil(j / 32) for its largest id j that tc_bitmap_pair accepts at its
+// position (row i streamed by a B pair), and all of the row,
+// tc_full_words(last id, length), when that is worth reading instead of
+// the row's ids (row i streamed whole by an A pair).  One lane per entry
+// of L; the lanes of one row take their maximum within the wave (the
+// words grow with the id along the row, so the last lane that asks for
+// any holds it) and the run head makes the row's one atomic.
 __global__ void k_bitmap_words(const int32_t *__restrict__ rowid, const int32_t *__restrict__ ci, int64_t nnz,
                                const uint64_t *__restrict__ rowpk, unsigned long long *__restrict__ bw)
 {
@@ -130,8 +134,11 @@ __global__ void k_bitmap_words(const int32_t *__restrict__ rowid, const int32_t 
         if (e < nnz) {
             i = rowid[e];
             const int32_t j = ci[e];
-            const int64_t p = e - (int64_t)(rowpk[i] >> TC_PLAN_LEN_BITS);
+            const uint64_t pk = rowpk[i];
+            const int64_t p = e - (int64_t)(pk >> TC_PLAN_LEN_BITS);
             if (tc_bitmap_pair(j, p)) v = (unsigned)((j + 31) >> 5);
+            const int64_t len = (int64_t)(pk & ((1ull << TC_PLAN_LEN_BITS) - 1));
+            if (p == len - 1 && i <= TC_BM_IDS) v = max(v, tc_full_words(j, len));   // the row's last (largest) id
         }
         const WaveRun w = wave_run(i);
         // maximum over the run: ids ascend along a row, so the last lane of
@@ -210,6 +217,23 @@ __global__ __launch_bounds__(BITMAP_BLOCK) void k_bitmap_build(const int32_t *__
     }
 }
 
+// For the rows j < nd (the lowest ids, whose columns hold most entries of
+// L): lowpk[j] = {rowpk[j], TC_PLAN_BITS | (words << TC_PLAN_WORDS_SHIFT)
+// | offset of row j's bitmap when an A pair should read row j as bits
+// (tc_full_words > 0), else 0}.  The fill gathers this 16-byte entry (the
+// table, 0.4 MB at nd = 24,577, stays in L2) instead of rowpk for those
+// columns.
+__global__ void k_low_pack(const int64_t *__restrict__ Lrp, const int32_t *__restrict__ Lci,
+                           const int64_t *__restrict__ boff, int64_t nd, ulonglong2 *__restrict__ lowpk)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nd; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = Lrp[j], len = Lrp[j + 1] - b;
+        const unsigned w = len > 0 ? tc_full_words(Lci[b + len - 1], len) : 0u;
+        lowpk[j] = make_ulonglong2(plan_pack(b, len),
+                                   w ? TC_PLAN_BITS | ((uint64_t)w << TC_PLAN_WORDS_SHIFT) | (uint64_t)boff[j] : 0ull);
+    }
+}
+
 // Each wave takes PLAN_ILP windows of 64 consecutive entries per iteration
 // and runs them stage by stage (their loads, then their gathers, then
 // their atomics), so a wave waits for each round trip once per PLAN_ILP
@@ -223,13 +247,15 @@ constexpr int PLAN_ILP = 2;
 // row is immaterial.  Hot B rows hand out positions from LDS as offsets
 // from bstart = trp[n], the first B-side slot, starting at the workgroup's
 // reservation.  A B pair that tc_bitmap_pair accepts gets the entry
-// TC_PLAN_BITS | (offset of row i's bitmap) in the same slot.
+// TC_PLAN_BITS | (offset of row i's bitmap) in the same slot, and an A
+// pair whose row j reads better as bits gets lowpk[j].y.
 __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restrict__ rowid,
                                                           const int32_t *__restrict__ ci, int64_t nnz,
                                                           const uint64_t *__restrict__ rowpk, int64_t n,
                                                           const int64_t *__restrict__ trp,
                                                           const unsigned *__restrict__ boff,
                                                           const int64_t *__restrict__ bitoff,
+                                                          const ulonglong2 *__restrict__ lowpk, int64_t nd,
                                                           unsigned long long *__restrict__ cur,
                                                           uint64_t *__restrict__ ent)
 {
@@ -246,7 +272,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restr
     const int64_t first = (int64_t)(threadIdx.x / 64) * PLAN_ILP * 64 + lane;
     for (int64_t base = e0; base < e1; base += (int64_t)PLAN_BLOCK * PLAN_ILP) {
         int32_t i[PLAN_ILP], j[PLAN_ILP];
-        uint64_t pi[PLAN_ILP], pj[PLAN_ILP];
+        uint64_t pi[PLAN_ILP], pj[PLAN_ILP], fb[PLAN_ILP];
 #pragma unroll
         for (int k = 0; k < PLAN_ILP; k++) {
             const int64_t e = base + first + 64 * k;
@@ -256,7 +282,15 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restr
 #pragma unroll
         for (int k = 0; k < PLAN_ILP; k++) {
             pi[k] = i[k] >= 0 ? rowpk[i[k]] : 0ull;
-            pj[k] = i[k] >= 0 ? rowpk[j[k]] : 0ull;
+            pj[k] = 0ull;
+            fb[k] = 0ull;
+            if (i[k] >= 0 && j[k] < nd) {
+                const ulonglong2 lp = lowpk[j[k]];
+                pj[k] = lp.x;
+                fb[k] = lp.y;
+            } else if (i[k] >= 0) {
+                pj[k] = rowpk[j[k]];
+            }
         }
         // B side: positions from LDS (hot rows) or the row's cursor
         bool a_side[PLAN_ILP];
@@ -284,7 +318,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restr
             unsigned long long abase = 0;
             if (lane == w.head && take) abase = atomicAdd(&cur[i[k]], (unsigned long long)__popcll(take));
             abase = (unsigned long long)__shfl((long long)abase, (int)w.head, 64);
-            if (a_side[k]) ent[abase + __popcll(take & w.before)] = pj[k];
+            if (a_side[k]) ent[abase + __popcll(take & w.before)] = fb[k] ? fb[k] : pj[k];
             if (bpos[k] >= 0) ent[bpos[k]] = bval[k];
         }
     }
@@ -448,9 +482,14 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
                            nbrows);
         hipLaunchKernelGGL(k_bitmap_build, dim3((unsigned)(ctx->num_cus * 8)), dim3(BITMAP_BLOCK), 0, ctx->stream,
                            brows, nbrows, Lm->rowptr, Lm->colidx, P->boff, P->bits);
+        const int64_t nd = n < TC_BM_IDS + 1 ? n : TC_BM_IDS + 1;   // rows whose ids all lie below TC_BM_IDS
+        ulonglong2 *lowpk = (ulonglong2 *)ws_get(ctx, WS_GEN_G, sizeof(ulonglong2) * (size_t)nd);
+        if (!lowpk) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
+        hipLaunchKernelGGL(k_low_pack, dim3(grid_for(nd, 256, 1024)), dim3(256), 0, ctx->stream, Lm->rowptr,
+                           Lm->colidx, P->boff, nd, lowpk);
         if (nnz > 0)
             hipLaunchKernelGGL(k_plan_fill, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx,
-                               nnz, rowpk, n, P->trp, boff, P->boff, cur, P->ent);
+                               nnz, rowpk, n, P->trp, boff, P->boff, lowpk, nd, cur, P->ent);
         hipLaunchKernelGGL(k_plan_items, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, ctx->stream, P->trp, cur, nv,
                            P->irp);
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));

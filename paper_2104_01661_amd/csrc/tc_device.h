@@ -433,11 +433,21 @@ int tc_masked_dot(lagr_ctx ctx, const TcArgs &a, bool per_entry, unsigned long l
 constexpr int TC_PLAN_LEN_BITS = 24;
 constexpr int TC_PLAN_CNT_BITS = 7;
 constexpr uint64_t TC_PLAN_BITS = 1ull << 63;   // bitmap entry flag
+constexpr int TC_PLAN_WORDS_SHIFT = 40;          // an A pair's bitmap words (below: the offset)
 
 // The pair (id j marked at position p of row i) is a bitmap pair.
 __host__ __device__ __forceinline__ bool tc_bitmap_pair(int64_t j, int64_t p)
 {
     return j < TC_BM_IDS && ((j + 31) >> 5) < p;
+}
+
+// Words of a whole row with largest id `last` and `len` ids, when an A pair
+// streaming it does better reading them than the ids (and all lie below
+// TC_BM_IDS, within the LDS marks); 0 otherwise.
+__host__ __device__ __forceinline__ unsigned tc_full_words(int64_t last, int64_t len)
+{
+    const int64_t w = (last >> 5) + 1;
+    return last < TC_BM_IDS && w < len ? (unsigned)w : 0u;
 }
 
 struct TcPlan {
@@ -482,35 +492,80 @@ struct PlanArgs {
 // BATCHED each graph's part of the count is added to per_graph[g] (the
 // items of one graph are contiguous) and the result is 0.
 // The bitmap pairs of one item (lanes with `flag`, each holding the bitmap
-// offset of its streamed row in off): the marked row L_j's bits are in
-// L.bm, all in its first nw words (nw covers L_j's largest id, so nw <=
-// ceil(j/32), which every streamed row's bitmap covers).  The pairs are
-// compacted into L.seg_s (free once tc_stream_flat has returned), and the
-// (pair, word) grid g = q * nw + w is walked 64 elements per load,
-// TC_FLAT_INFLIGHT loads in flight; q = g / nw by a multiply with
-// ceil(2^32 / nw), exact while g * nw < 2^32 (g < 64 * 768 here).
+// offset of its streamed row in off and, for an A pair, the words to read
+// in nwl).  A B item's pairs all read mark_words words: the marked row
+// L_j's bits are in L.bm, all in its first mark_words words (they cover
+// L_j's largest id, so mark_words <= ceil(j/32), which every streamed
+// row's bitmap covers).  An A pair reads the whole of its streamed row L_j
+// as bits (nwl words, all ids below TC_BM_IDS) against the marks of L_i.
+// The pairs are compacted into L.seg_s / L.seg_x (free once
+// tc_stream_flat has returned) and their (pair, word) grid is walked 64
+// elements per load, TC_FLAT_INFLIGHT loads in flight: with one width, the
+// pair of element g is g / nw by a multiply with ceil(2^32 / nw) (exact
+// while g * nw < 2^32, g < 64 * 768 here); with per-pair widths, each lane
+// walks the pairs' word offsets forward as tc_stream_flat walks segments.
 __device__ __forceinline__ unsigned long long tc_bitmap_lanes(TcWaveLds &L, const uint32_t *__restrict__ bits,
-                                                              int64_t off, bool flag, int nw, unsigned lane)
+                                                              int64_t off, int nwl, bool flag, int mark_words,
+                                                              unsigned lane)
 {
     const uint64_t M = __ballot(flag);
     const int np = __popcll(M);
-    if (flag) L.seg_s[__popcll(M & ((1ull << lane) - 1))] = off;
-    wave_sync();
-    const unsigned long long magic = (0x100000000ull + (unsigned)nw - 1) / (unsigned)nw;   // 2^32 for nw = 1
-    const int total = np * nw;
+    const int r = __popcll(M & ((1ull << lane) - 1));
+    const bool varied = __ballot(flag && nwl > 0) != 0;   // an A item
     unsigned long long acc = 0;
-    for (int g0 = 0; g0 < total; g0 += 64 * TC_FLAT_INFLIGHT) {
-        uint32_t x[TC_FLAT_INFLIGHT], y[TC_FLAT_INFLIGHT];
+    if (!varied) {
+        const int nw = mark_words;
+        if (flag) L.seg_s[r] = off;
+        wave_sync();
+        const unsigned long long magic = (0x100000000ull + (unsigned)nw - 1) / (unsigned)nw;   // 2^32 for nw = 1
+        const int total = np * nw;
+        for (int g0 = 0; g0 < total; g0 += 64 * TC_FLAT_INFLIGHT) {
+            uint32_t x[TC_FLAT_INFLIGHT], y[TC_FLAT_INFLIGHT];
 #pragma unroll
-        for (int f = 0; f < TC_FLAT_INFLIGHT; f++) {
-            const int g = g0 + 64 * f + (int)lane;
-            const int q = (int)(((unsigned long long)(unsigned)g * magic) >> 32), w = g - q * nw;
-            const bool v = g < total;
-            x[f] = v ? bits[L.seg_s[q] + w] : 0u;
-            y[f] = v ? L.bm[w] : 0u;
+            for (int f = 0; f < TC_FLAT_INFLIGHT; f++) {
+                const int g = g0 + 64 * f + (int)lane;
+                const int q = (int)(((unsigned long long)(unsigned)g * magic) >> 32), w = g - q * nw;
+                const bool v = g < total;
+                x[f] = v ? bits[L.seg_s[q] + w] : 0u;
+                y[f] = v ? L.bm[w] : 0u;
+            }
+#pragma unroll
+            for (int f = 0; f < TC_FLAT_INFLIGHT; f++) acc += (unsigned)__popc(x[f] & y[f]);
         }
+    } else {
+        // exclusive word offsets of the flagged lanes, in lane order
+        const int mine = flag ? nwl : 0;
+        int incl = mine;
 #pragma unroll
-        for (int f = 0; f < TC_FLAT_INFLIGHT; f++) acc += (unsigned)__popc(x[f] & y[f]);
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d, 64);
+            if ((int)lane >= d) incl += y;
+        }
+        const int total = __shfl(incl, 63, 64);
+        if (flag) {
+            L.seg_s[r] = off;
+            L.seg_x[r] = incl - mine;
+        }
+        if (lane == 0) L.seg_x[np] = total;
+        wave_sync();
+        int t = 0;
+        for (int g0 = 0; g0 < total; g0 += 64 * TC_FLAT_INFLIGHT) {
+            uint32_t x[TC_FLAT_INFLIGHT], y[TC_FLAT_INFLIGHT];
+#pragma unroll
+            for (int f = 0; f < TC_FLAT_INFLIGHT; f++) {
+                const int g = g0 + 64 * f + (int)lane;
+                x[f] = 0u;
+                y[f] = 0u;
+                if (g < total) {
+                    while (L.seg_x[t + 1] <= g) t++;
+                    const int w = g - L.seg_x[t];
+                    x[f] = bits[L.seg_s[t] + w];
+                    y[f] = L.bm[w];
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < TC_FLAT_INFLIGHT; f++) acc += (unsigned)__popc(x[f] & y[f]);
+        }
     }
     wave_sync();
     return acc;
@@ -570,8 +625,8 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
             if ((int)lane < cnt) {
                 const uint64_t x = a.ent[e0 + lane];
                 bitmap = (x & TC_PLAN_BITS) != 0;
-                s = bitmap ? (int64_t)(x & ~TC_PLAN_BITS) : (int64_t)(x >> TC_PLAN_LEN_BITS);
-                len = bitmap ? 0 : (int)(x & lmask);
+                s = bitmap ? (int64_t)(x & ((1ull << TC_PLAN_WORDS_SHIFT) - 1)) : (int64_t)(x >> TC_PLAN_LEN_BITS);
+                len = (int)(bitmap ? (x & ~TC_PLAN_BITS) >> TC_PLAN_WORDS_SHIFT : x & lmask);
             }
             if (m != marked) {
                 if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
@@ -582,8 +637,9 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
                 mark_words = alen > 0 ? (Arow[alen - 1] >> 5) + 1 : 0;
                 marked = m;
             }
-            acc += tc_stream_flat(L, use_hash, Arow, alen, a.Lci, s, len, cnt, lane);
-            if (__ballot(bitmap)) acc += tc_bitmap_lanes(L, a.bits, s, bitmap, mark_words, lane);
+            // a bitmap lane streams no ids (its len field holds an A pair's words)
+            acc += tc_stream_flat(L, use_hash, Arow, alen, a.Lci, s, bitmap ? 0 : len, cnt, lane);
+            if (__ballot(bitmap)) acc += tc_bitmap_lanes(L, a.bits, s, len, bitmap, mark_words, lane);
         }
     }
     if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
