@@ -239,7 +239,10 @@ def main():
     # j < 24576 and ceil(j / 32) < p reads the words of row i's bitmap up to
     # L_j's largest id instead, and an A pair whose L_j has all its ids
     # below 24576 and fewer words (largest id / 32 + 1) than ids reads
-    # those words of row j's bitmap (bitmap pairs); per launch the kernel reads
+    # those words of row j's bitmap (bitmap pairs); a pair with a hub column
+    # (j < 4096) goes to the B side only when p is below both len(L_j) and
+    # L_j's words, and otherwise reads the shorter of L_j's ids and words
+    # from row i; per launch the kernel reads
     # a 12-byte descriptor per item (64 pairs at most), one 8-byte
     # descriptor per pair, the streamed ids and bitmap words (4 B each) and
     # every marked row once (16 B of offsets + 4 B per id).
@@ -256,9 +259,12 @@ def main():
     side_b = valid & (lj > pos)
     jl = lci.long()
     last_id = lci[(lrp[1:] - 1).clamp(min=0)].long()          # largest id of each row
-    bitmap_b = side_b & (jl < 24576) & ((jl + 31) // 32 < pos)
     words_j = (last_id[jl] >> 5) + 1
-    bitmap_a = side_a & (jl <= 24576) & (last_id[jl] < 24576) & (words_j < lj)
+    hub = valid & (jl < 4096)
+    side_b = (side_b & ~hub) | (hub & (pos < lj) & (pos < words_j))
+    side_a = valid & ~side_b
+    bitmap_b = side_b & ~hub & (jl < 24576) & ((jl + 31) // 32 < pos)
+    bitmap_a = side_a & (((jl <= 24576) & (last_id[jl] < 24576) & (words_j < lj)) | (hub & (words_j < lj)))
     bitmap = bitmap_a | bitmap_b
     bitmap_words = int(words_j[bitmap].sum().item())
     streamed = int(lj[side_a & ~bitmap_a].sum().item() + pos[side_b & ~bitmap_b].sum().item())
@@ -271,7 +277,7 @@ def main():
     tc_model = {"pairs": nent, "streamed_ids": streamed, "bitmap_pairs": int(bitmap.sum().item()),
                 "bitmap_words": bitmap_words, "items": items,
                 "single_side_streamed_ids": int(lj[pos >= 1].sum().item())}
-    del row_of, pos, lj, jl, valid, side_a, side_b, bitmap, bitmap_a, bitmap_b, words_j, last_id, cnt_a, cnt_b
+    del row_of, pos, lj, jl, valid, hub, side_a, side_b, bitmap, bitmap_a, bitmap_b, words_j, last_id, cnt_a, cnt_b
 
     # per-source traversed edges for GTEPS: undirected edges in the reached set
     reached_edges = []

@@ -78,23 +78,45 @@ __global__ void k_row_pack(const int64_t *__restrict__ rp, int64_t n, uint64_t *
         rowpk[r] = plan_pack(rp[r], rp[r + 1] - rp[r]);
 }
 
+// hubw[x] (x < nh) = the words of hub row x's bitmap up to its largest id
+// (0 for an empty row): what a hub pair reading L_x as bits costs.
+__global__ void k_hub_words(const int64_t *__restrict__ Lrp, const int32_t *__restrict__ Lci, int64_t nh,
+                            unsigned *__restrict__ hubw)
+{
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < nh; x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = Lrp[x], e = Lrp[x + 1];
+        hubw[x] = e > b ? (unsigned)((Lci[e - 1] >> 5) + 1) : 0u;
+    }
+}
+
+// A hub pair (column j < PLAN_HOT) goes to B row j only when p is below
+// both len(L_j) and L_j's bitmap words; otherwise row i reads L_j's ids or
+// bitmap, whichever is shorter.
+__host__ __device__ __forceinline__ bool plan_hub_b(int64_t p, int64_t lj, int64_t words)
+{
+    return p < lj && p < words;
+}
+
 // Per workgroup, the B entries of each hot row, reserved in the row's
 // region: boff[g * PLAN_HOT + x] = offset of workgroup g's first slot in
 // row n + x, relative to bstart = trp[n] (fewer than 2^32 entries).
 __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_hot(const int32_t *__restrict__ rowid,
                                                          const int32_t *__restrict__ ci, int64_t nnz,
-                                                         const uint64_t *__restrict__ rowpk, int64_t n,
+                                                         const uint64_t *__restrict__ rowpk,
+                                                         const unsigned *__restrict__ hubw, int64_t n,
                                                          const int64_t *__restrict__ trp,
                                                          unsigned long long *__restrict__ cur,
                                                          unsigned *__restrict__ boff)
 {
     __shared__ unsigned hot[PLAN_HOT];
     __shared__ unsigned hlen[PLAN_HOT];
+    __shared__ unsigned hw[PLAN_HOT];
     const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
     const int64_t nh = n < PLAN_HOT ? n : PLAN_HOT;
     for (int x = threadIdx.x; x < PLAN_HOT; x += PLAN_BLOCK) {
         hot[x] = 0u;
         hlen[x] = x < nh ? (unsigned)(rowpk[x] & lmask) : 0u;
+        hw[x] = x < nh ? hubw[x] : 0u;
     }
     __syncthreads();
     const int64_t share = (nnz + gridDim.x - 1) / gridDim.x;
@@ -105,7 +127,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_hot(const int32_t *__restri
         const int64_t lj = hlen[j];
         if (lj == 0) continue;
         const int64_t p = e - (int64_t)(rowpk[rowid[e]] >> TC_PLAN_LEN_BITS);
-        if (p > 0 && lj > p) atomicAdd(&hot[j], 1u);
+        if (p > 0 && plan_hub_b(p, lj, hw[j])) atomicAdd(&hot[j], 1u);
     }
     __syncthreads();
     const int64_t bstart = trp[n];
@@ -136,9 +158,10 @@ __global__ void k_bitmap_words(const int32_t *__restrict__ rowid, const int32_t 
             const int32_t j = ci[e];
             const uint64_t pk = rowpk[i];
             const int64_t p = e - (int64_t)(pk >> TC_PLAN_LEN_BITS);
-            if (tc_bitmap_pair(j, p)) v = (unsigned)((j + 31) >> 5);
+            if (j >= PLAN_HOT && tc_bitmap_pair(j, p)) v = (unsigned)((j + 31) >> 5);   // hub pairs: plan_hub_b
             const int64_t len = (int64_t)(pk & ((1ull << TC_PLAN_LEN_BITS) - 1));
-            if (p == len - 1 && i <= TC_BM_IDS) v = max(v, tc_full_words(j, len));   // the row's last (largest) id
+            if (p == len - 1 && i <= TC_BM_IDS)   // the row's last (largest) id
+                v = max(v, i < PLAN_HOT ? (unsigned)((j >> 5) + 1) : tc_full_words(j, len));
         }
         const WaveRun w = wave_run(i);
         // maximum over the run: ids ascend along a row, so the last lane of
@@ -228,7 +251,8 @@ __global__ void k_low_pack(const int64_t *__restrict__ Lrp, const int32_t *__res
 {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nd; j += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = Lrp[j], len = Lrp[j + 1] - b;
-        const unsigned w = len > 0 ? tc_full_words(Lci[b + len - 1], len) : 0u;
+        const int64_t last = len > 0 ? Lci[b + len - 1] : 0;
+        const unsigned w = len == 0 ? 0u : j < PLAN_HOT ? (unsigned)((last >> 5) + 1) : tc_full_words(last, len);
         lowpk[j] = make_ulonglong2(plan_pack(b, len),
                                    w ? TC_PLAN_BITS | ((uint64_t)w << TC_PLAN_WORDS_SHIFT) | (uint64_t)boff[j] : 0ull);
     }
@@ -292,22 +316,30 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restr
                 pj[k] = rowpk[j[k]];
             }
         }
-        // B side: positions from LDS (hot rows) or the row's cursor
+        // row i's region (A pairs, hub pairs that read L_j) or B row j:
+        // positions from LDS (hub rows) or the row's cursor
         bool a_side[PLAN_ILP];
         int64_t bpos[PLAN_ILP];
-        uint64_t bval[PLAN_ILP];
+        uint64_t aval[PLAN_ILP], bval[PLAN_ILP];
 #pragma unroll
         for (int k = 0; k < PLAN_ILP; k++) {
             const int64_t e = base + first + 64 * k;
             const int64_t si = (int64_t)(pi[k] >> TC_PLAN_LEN_BITS), p = e - si, lj = (int64_t)(pj[k] & lmask);
             const bool valid = i[k] >= 0 && p > 0 && lj > 0;
-            a_side[k] = valid && lj <= p;
             bpos[k] = -1;
             bval[k] = plan_pack(si, p);
-            if (valid && !a_side[k]) {
-                if (tc_bitmap_pair(j[k], p)) bval[k] = TC_PLAN_BITS | (uint64_t)bitoff[i[k]];
-                if (j[k] < PLAN_HOT) bpos[k] = bstart + (int64_t)atomicAdd(&hot[j[k]], 1u);
-                else bpos[k] = (int64_t)atomicAdd(&cur[n + j[k]], 1ull);
+            if (j[k] < PLAN_HOT) {
+                const int64_t words = (int64_t)((fb[k] & ~TC_PLAN_BITS) >> TC_PLAN_WORDS_SHIFT);
+                a_side[k] = valid && !plan_hub_b(p, lj, words);
+                aval[k] = lj <= words ? pj[k] : fb[k];
+                if (valid && !a_side[k]) bpos[k] = bstart + (int64_t)atomicAdd(&hot[j[k]], 1u);
+            } else {
+                a_side[k] = valid && lj <= p;
+                aval[k] = fb[k] ? fb[k] : pj[k];
+                if (valid && !a_side[k]) {
+                    if (tc_bitmap_pair(j[k], p)) bval[k] = TC_PLAN_BITS | (uint64_t)bitoff[i[k]];
+                    bpos[k] = (int64_t)atomicAdd(&cur[n + j[k]], 1ull);
+                }
             }
         }
         // A side: one cursor atomic per row run
@@ -318,7 +350,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restr
             unsigned long long abase = 0;
             if (lane == w.head && take) abase = atomicAdd(&cur[i[k]], (unsigned long long)__popcll(take));
             abase = (unsigned long long)__shfl((long long)abase, (int)w.head, 64);
-            if (a_side[k]) ent[abase + __popcll(take & w.before)] = fb[k] ? fb[k] : pj[k];
+            if (a_side[k]) ent[abase + __popcll(take & w.before)] = aval[k];
             if (bpos[k] >= 0) ent[bpos[k]] = bval[k];
         }
     }
@@ -436,7 +468,9 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
     P->nitems = -1;
     P->ent_cap = 2 * nnz;
     P->item_cap = nnz / 64 + (nv < nnz ? nv : nnz) + 1;
-    P->bits_cap = nnz > 0 ? nnz : 1;
+    // rows' words stay below their lengths, except hub rows' (at most
+    // PLAN_HOT / 32 words each)
+    P->bits_cap = nnz + (int64_t)PLAN_HOT * (PLAN_HOT / 32);
     G->tcplan = P;
     auto fail = [&](int rc) {
         tc_plan_free(G);
@@ -455,7 +489,9 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
     if (hipMemcpyAsync(P->trp, regions, 8 * (size_t)(nv + 1), hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
         return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan copy"));
     if ((rc = fill_i64(ctx, P->boff, n + 1, 0, msg)) < 0) return fail(rc);
-    unsigned *boff = (unsigned *)ws_get(ctx, WS_GEN_H, sizeof(unsigned) * (size_t)PLAN_GRID * PLAN_HOT);
+    // per-workgroup hub reservations, then the hub rows' bitmap words
+    unsigned *boff = (unsigned *)ws_get(ctx, WS_GEN_H, sizeof(unsigned) * ((size_t)PLAN_GRID + 1) * PLAN_HOT);
+    unsigned *hubw = boff + (size_t)PLAN_GRID * PLAN_HOT;
     uint64_t *rowpk = (uint64_t *)ws_get(ctx, WS_GEN_E, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     unsigned long long *cur = (unsigned long long *)ws_get(ctx, WS_TC_WORK, 8 * (size_t)(nv > 0 ? nv : 1));
     if (!boff || !rowpk || !cur) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
@@ -467,8 +503,11 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
         if (nnz > 0) {
             hipLaunchKernelGGL(k_bitmap_words, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, ctx->stream, rowid,
                                Lm->colidx, nnz, rowpk, (unsigned long long *)P->boff);
+            const int64_t nh = n < PLAN_HOT ? n : PLAN_HOT;
+            hipLaunchKernelGGL(k_hub_words, dim3(grid_for(nh, 256, 64)), dim3(256), 0, ctx->stream, Lm->rowptr,
+                               Lm->colidx, nh, hubw);
             hipLaunchKernelGGL(k_plan_hot, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx,
-                               nnz, rowpk, n, P->trp, cur, boff);
+                               nnz, rowpk, hubw, n, P->trp, cur, boff);
         }
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
         if ((rc = scan_exclusive_i64(ctx, P->boff, P->boff, n + 1, nullptr, msg)) < 0) return fail(rc);
