@@ -89,7 +89,21 @@ __global__ void k_hub_words(const int64_t *__restrict__ Lrp, const int32_t *__re
     }
 }
 
-// A hub pair (column j < PLAN_HOT) goes to B row j only when p is below
+// The hub columns: j < plan_hubs(n), a 1/256 share of the vertices (the
+// highest-degree ones after the relabel) and at most PLAN_HOT, in graphs
+// of 2^18 vertices or more.  Keeping hub pairs in row i trades count time
+// for a smaller transpose; that pays where the hub columns' B rows are
+// large (at 2^20: 44 us less in all), not in small graphs (a batch of
+// 2,000 graphs of 2^8 to 2^16 vertices, whose preparation is not in its
+// count, counted 25% slower with hubs).
+static inline int64_t plan_hubs(int64_t n)
+{
+    if (n < ((int64_t)1 << 18)) return 0;
+    const int64_t h = n >> 8;
+    return h < PLAN_HOT ? h : PLAN_HOT;
+}
+
+// A hub pair (column j < plan_hubs(n)) goes to B row j only when p is below
 // both len(L_j) and L_j's bitmap words; otherwise row i reads L_j's ids or
 // bitmap, whichever is shorter.
 __host__ __device__ __forceinline__ bool plan_hub_b(int64_t p, int64_t lj, int64_t words)
@@ -103,7 +117,7 @@ __host__ __device__ __forceinline__ bool plan_hub_b(int64_t p, int64_t lj, int64
 __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_hot(const int32_t *__restrict__ rowid,
                                                          const int32_t *__restrict__ ci, int64_t nnz,
                                                          const uint64_t *__restrict__ rowpk,
-                                                         const unsigned *__restrict__ hubw, int64_t n,
+                                                         const unsigned *__restrict__ hubw, int64_t nhub, int64_t n,
                                                          const int64_t *__restrict__ trp,
                                                          unsigned long long *__restrict__ cur,
                                                          unsigned *__restrict__ boff)
@@ -116,7 +130,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_hot(const int32_t *__restri
     for (int x = threadIdx.x; x < PLAN_HOT; x += PLAN_BLOCK) {
         hot[x] = 0u;
         hlen[x] = x < nh ? (unsigned)(rowpk[x] & lmask) : 0u;
-        hw[x] = x < nh ? hubw[x] : 0u;
+        hw[x] = x < nhub ? hubw[x] : 0u;
     }
     __syncthreads();
     const int64_t share = (nnz + gridDim.x - 1) / gridDim.x;
@@ -127,7 +141,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_hot(const int32_t *__restri
         const int64_t lj = hlen[j];
         if (lj == 0) continue;
         const int64_t p = e - (int64_t)(rowpk[rowid[e]] >> TC_PLAN_LEN_BITS);
-        if (p > 0 && plan_hub_b(p, lj, hw[j])) atomicAdd(&hot[j], 1u);
+        if (p > 0 && (j < nhub ? plan_hub_b(p, lj, hw[j]) : lj > p)) atomicAdd(&hot[j], 1u);
     }
     __syncthreads();
     const int64_t bstart = trp[n];
@@ -145,7 +159,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_hot(const int32_t *__restri
 // words grow with the id along the row, so the last lane that asks for
 // any holds it) and the run head makes the row's one atomic.
 __global__ void k_bitmap_words(const int32_t *__restrict__ rowid, const int32_t *__restrict__ ci, int64_t nnz,
-                               const uint64_t *__restrict__ rowpk, unsigned long long *__restrict__ bw)
+                               const uint64_t *__restrict__ rowpk, int64_t nhub, unsigned long long *__restrict__ bw)
 {
     const unsigned lane = lane_id();
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
@@ -158,10 +172,10 @@ __global__ void k_bitmap_words(const int32_t *__restrict__ rowid, const int32_t 
             const int32_t j = ci[e];
             const uint64_t pk = rowpk[i];
             const int64_t p = e - (int64_t)(pk >> TC_PLAN_LEN_BITS);
-            if (j >= PLAN_HOT && tc_bitmap_pair(j, p)) v = (unsigned)((j + 31) >> 5);   // hub pairs: plan_hub_b
+            if (j >= nhub && tc_bitmap_pair(j, p)) v = (unsigned)((j + 31) >> 5);   // hub pairs: plan_hub_b
             const int64_t len = (int64_t)(pk & ((1ull << TC_PLAN_LEN_BITS) - 1));
             if (p == len - 1 && i <= TC_BM_IDS)   // the row's last (largest) id
-                v = max(v, i < PLAN_HOT ? (unsigned)((j >> 5) + 1) : tc_full_words(j, len));
+                v = max(v, i < nhub ? (unsigned)((j >> 5) + 1) : tc_full_words(j, len));
         }
         const WaveRun w = wave_run(i);
         // maximum over the run: ids ascend along a row, so the last lane of
@@ -247,12 +261,12 @@ __global__ __launch_bounds__(BITMAP_BLOCK) void k_bitmap_build(const int32_t *__
 // table, 0.4 MB at nd = 24,577, stays in L2) instead of rowpk for those
 // columns.
 __global__ void k_low_pack(const int64_t *__restrict__ Lrp, const int32_t *__restrict__ Lci,
-                           const int64_t *__restrict__ boff, int64_t nd, ulonglong2 *__restrict__ lowpk)
+                           const int64_t *__restrict__ boff, int64_t nd, int64_t nhub, ulonglong2 *__restrict__ lowpk)
 {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nd; j += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = Lrp[j], len = Lrp[j + 1] - b;
         const int64_t last = len > 0 ? Lci[b + len - 1] : 0;
-        const unsigned w = len == 0 ? 0u : j < PLAN_HOT ? (unsigned)((last >> 5) + 1) : tc_full_words(last, len);
+        const unsigned w = len == 0 ? 0u : j < nhub ? (unsigned)((last >> 5) + 1) : tc_full_words(last, len);
         lowpk[j] = make_ulonglong2(plan_pack(b, len),
                                    w ? TC_PLAN_BITS | ((uint64_t)w << TC_PLAN_WORDS_SHIFT) | (uint64_t)boff[j] : 0ull);
     }
@@ -280,6 +294,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restr
                                                           const unsigned *__restrict__ boff,
                                                           const int64_t *__restrict__ bitoff,
                                                           const ulonglong2 *__restrict__ lowpk, int64_t nd,
+                                                          int64_t nhub,
                                                           unsigned long long *__restrict__ cur,
                                                           uint64_t *__restrict__ ent)
 {
@@ -328,7 +343,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restr
             const bool valid = i[k] >= 0 && p > 0 && lj > 0;
             bpos[k] = -1;
             bval[k] = plan_pack(si, p);
-            if (j[k] < PLAN_HOT) {
+            if (j[k] < nhub) {
                 const int64_t words = (int64_t)((fb[k] & ~TC_PLAN_BITS) >> TC_PLAN_WORDS_SHIFT);
                 a_side[k] = valid && !plan_hub_b(p, lj, words);
                 aval[k] = lj <= words ? pj[k] : fb[k];
@@ -338,7 +353,8 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restr
                 aval[k] = fb[k] ? fb[k] : pj[k];
                 if (valid && !a_side[k]) {
                     if (tc_bitmap_pair(j[k], p)) bval[k] = TC_PLAN_BITS | (uint64_t)bitoff[i[k]];
-                    bpos[k] = (int64_t)atomicAdd(&cur[n + j[k]], 1ull);
+                    if (j[k] < PLAN_HOT) bpos[k] = bstart + (int64_t)atomicAdd(&hot[j[k]], 1u);
+                    else bpos[k] = (int64_t)atomicAdd(&cur[n + j[k]], 1ull);
                 }
             }
         }
@@ -492,6 +508,7 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
     // per-workgroup hub reservations, then the hub rows' bitmap words
     unsigned *boff = (unsigned *)ws_get(ctx, WS_GEN_H, sizeof(unsigned) * ((size_t)PLAN_GRID + 1) * PLAN_HOT);
     unsigned *hubw = boff + (size_t)PLAN_GRID * PLAN_HOT;
+    const int64_t nhub = plan_hubs(n);
     uint64_t *rowpk = (uint64_t *)ws_get(ctx, WS_GEN_E, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     unsigned long long *cur = (unsigned long long *)ws_get(ctx, WS_TC_WORK, 8 * (size_t)(nv > 0 ? nv : 1));
     if (!boff || !rowpk || !cur) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
@@ -502,12 +519,12 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
                            rowpk);
         if (nnz > 0) {
             hipLaunchKernelGGL(k_bitmap_words, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, ctx->stream, rowid,
-                               Lm->colidx, nnz, rowpk, (unsigned long long *)P->boff);
-            const int64_t nh = n < PLAN_HOT ? n : PLAN_HOT;
-            hipLaunchKernelGGL(k_hub_words, dim3(grid_for(nh, 256, 64)), dim3(256), 0, ctx->stream, Lm->rowptr,
-                               Lm->colidx, nh, hubw);
+                               Lm->colidx, nnz, rowpk, nhub, (unsigned long long *)P->boff);
+            if (nhub > 0)
+                hipLaunchKernelGGL(k_hub_words, dim3(grid_for(nhub, 256, 64)), dim3(256), 0, ctx->stream,
+                                   Lm->rowptr, Lm->colidx, nhub, hubw);
             hipLaunchKernelGGL(k_plan_hot, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx,
-                               nnz, rowpk, hubw, n, P->trp, cur, boff);
+                               nnz, rowpk, hubw, nhub, n, P->trp, cur, boff);
         }
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
         if ((rc = scan_exclusive_i64(ctx, P->boff, P->boff, n + 1, nullptr, msg)) < 0) return fail(rc);
@@ -525,10 +542,10 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
         ulonglong2 *lowpk = (ulonglong2 *)ws_get(ctx, WS_GEN_G, sizeof(ulonglong2) * (size_t)nd);
         if (!lowpk) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
         hipLaunchKernelGGL(k_low_pack, dim3(grid_for(nd, 256, 1024)), dim3(256), 0, ctx->stream, Lm->rowptr,
-                           Lm->colidx, P->boff, nd, lowpk);
+                           Lm->colidx, P->boff, nd, nhub, lowpk);
         if (nnz > 0)
             hipLaunchKernelGGL(k_plan_fill, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx,
-                               nnz, rowpk, n, P->trp, boff, P->boff, lowpk, nd, cur, P->ent);
+                               nnz, rowpk, n, P->trp, boff, P->boff, lowpk, nd, nhub, cur, P->ent);
         hipLaunchKernelGGL(k_plan_items, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, ctx->stream, P->trp, cur, nv,
                            P->irp);
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));

@@ -184,6 +184,25 @@ def test_tc_large_config():
     assert lagr().lagr_tc(G, ctx()) == e["triangles"]
 
 
+@pytest.mark.parametrize("scale,ef,seed", [(18, 8, 41), (18, 16, 42)])
+def test_tc_with_hub_columns_matches_the_oracle(scale, ef, seed):
+    """Graphs of 2^18 vertices: the count plan keeps pairs with one of the
+    1,024 hub columns in row i (ids or bitmap of L_j) or transposes them,
+    by cost; the count is checked against the oracle's, and again through
+    a batch of this graph and a small one (the packed plan re-bases the
+    bitmap entries)."""
+    L = lagr()
+    n, s, d = rmat(scale, ef, seed)
+    G = device_graph(n, s, d)
+    want = oracle.triangle_count(*oracle.build_adjacency(n, s, d))
+    assert L.lagr_tc(G, ctx()) == want
+    n2, s2, d2 = rmat(9, 8, seed)
+    G2 = device_graph(n2, s2, d2)
+    B = L.Batch(ctx(), [G2, G])
+    got = B.tc(ctx(), L.Tune(8, 4, 0))
+    assert got[1] == want and got[0] == oracle.triangle_count(*oracle.build_adjacency(n2, s2, d2))
+
+
 # ----------------------------------------------------------------- BFS
 
 def bfs_host(G, s, flags=0):
