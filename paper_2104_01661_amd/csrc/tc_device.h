@@ -491,38 +491,47 @@ struct PlanArgs {
 // the next eighth in turn.  The counters must be zero at launch.  With
 // BATCHED each graph's part of the count is added to per_graph[g] (the
 // items of one graph are contiguous) and the result is 0.
-// The bitmap pairs of one item (lanes with `flag`, each holding the bitmap
-// offset of its streamed row in off and, for an A pair, the words to read
-// in nwl).  A B item's pairs all read mark_words words: the marked row
-// L_j's bits are in L.bm, all in its first mark_words words (they cover
-// L_j's largest id, so mark_words <= ceil(j/32), which every streamed
-// row's bitmap covers).  An A pair reads the whole of its streamed row L_j
-// as bits (nwl words, all ids below TC_BM_IDS) against the marks of L_i.
-// The pairs are compacted into L.seg_s / L.seg_x (free once
-// tc_stream_flat has returned) and their (pair, word) grid is walked 64
-// elements per load, TC_FLAT_INFLIGHT loads in flight: with one width, the
-// pair of element g is g / nw by a multiply with ceil(2^32 / nw) (exact
-// while g * nw < 2^32, g < 64 * 768 here); with per-pair widths, each lane
-// walks the pairs' word offsets forward as tc_stream_flat walks segments.
+constexpr int TC_BITS_INFLIGHT = 6;   // bitmap word loads in flight per lane
+
+// The bitmap pairs of one item.  tc_stream_flat left each lane's entry in
+// L.seg_s[lane] (lane < cnt); a bitmap entry is the plan's raw word (sign
+// bit set: TC_PLAN_BITS), holding the bitmap offset of its streamed row
+// and, for an A pair, the words to read (so no per-lane state has to live
+// in registers across the streaming loop).  A B item's pairs all read the
+// marked row's words: L_j's bits are in L.bm, all in its first mark_words
+// words (they cover L_j's largest id, so mark_words <= ceil(j/32), which
+// every streamed row's bitmap covers).  An A pair reads the whole of its
+// streamed row L_j as bits (nwl words, all ids below TC_BM_IDS) against
+// the marks of L_i.  The pairs are compacted into L.seg_s / L.seg_x and
+// their (pair, word) grid is walked 64 elements per load,
+// TC_BITS_INFLIGHT loads in flight: with one width, the pair of element g
+// is g / nw by a multiply with ceil(2^32 / nw) (exact while g * nw < 2^32,
+// g < 64 * 768 here); with per-pair widths, each lane walks the pairs'
+// word offsets forward as tc_stream_flat walks segments.
 __device__ __forceinline__ unsigned long long tc_bitmap_lanes(TcWaveLds &L, const uint32_t *__restrict__ bits,
-                                                              int64_t off, int nwl, bool flag, int mark_words,
+                                                              const int32_t *__restrict__ Arow, int64_t alen, int cnt,
                                                               unsigned lane)
 {
+    const uint64_t x = (int)lane < cnt ? (uint64_t)L.seg_s[lane] : 0ull;
+    const bool flag = (x & TC_PLAN_BITS) != 0;
+    const int64_t off = (int64_t)(x & ((1ull << TC_PLAN_WORDS_SHIFT) - 1));
+    const int nwl = (int)((x & ~TC_PLAN_BITS) >> TC_PLAN_WORDS_SHIFT);
+    wave_sync();
     const uint64_t M = __ballot(flag);
     const int np = __popcll(M);
     const int r = __popcll(M & ((1ull << lane) - 1));
     const bool varied = __ballot(flag && nwl > 0) != 0;   // an A item
     unsigned long long acc = 0;
     if (!varied) {
-        const int nw = mark_words;
+        const int nw = alen > 0 ? (Arow[alen - 1] >> 5) + 1 : 0;   // up to the marked row's largest id
         if (flag) L.seg_s[r] = off;
         wave_sync();
         const unsigned long long magic = (0x100000000ull + (unsigned)nw - 1) / (unsigned)nw;   // 2^32 for nw = 1
         const int total = np * nw;
-        for (int g0 = 0; g0 < total; g0 += 64 * TC_FLAT_INFLIGHT) {
-            uint32_t x[TC_FLAT_INFLIGHT], y[TC_FLAT_INFLIGHT];
+        for (int g0 = 0; g0 < total; g0 += 64 * TC_BITS_INFLIGHT) {
+            uint32_t x[TC_BITS_INFLIGHT], y[TC_BITS_INFLIGHT];
 #pragma unroll
-            for (int f = 0; f < TC_FLAT_INFLIGHT; f++) {
+            for (int f = 0; f < TC_BITS_INFLIGHT; f++) {
                 const int g = g0 + 64 * f + (int)lane;
                 const int q = (int)(((unsigned long long)(unsigned)g * magic) >> 32), w = g - q * nw;
                 const bool v = g < total;
@@ -530,7 +539,7 @@ __device__ __forceinline__ unsigned long long tc_bitmap_lanes(TcWaveLds &L, cons
                 y[f] = v ? L.bm[w] : 0u;
             }
 #pragma unroll
-            for (int f = 0; f < TC_FLAT_INFLIGHT; f++) acc += (unsigned)__popc(x[f] & y[f]);
+            for (int f = 0; f < TC_BITS_INFLIGHT; f++) acc += (unsigned)__popc(x[f] & y[f]);
         }
     } else {
         // exclusive word offsets of the flagged lanes, in lane order
@@ -549,10 +558,10 @@ __device__ __forceinline__ unsigned long long tc_bitmap_lanes(TcWaveLds &L, cons
         if (lane == 0) L.seg_x[np] = total;
         wave_sync();
         int t = 0;
-        for (int g0 = 0; g0 < total; g0 += 64 * TC_FLAT_INFLIGHT) {
-            uint32_t x[TC_FLAT_INFLIGHT], y[TC_FLAT_INFLIGHT];
+        for (int g0 = 0; g0 < total; g0 += 64 * TC_BITS_INFLIGHT) {
+            uint32_t x[TC_BITS_INFLIGHT], y[TC_BITS_INFLIGHT];
 #pragma unroll
-            for (int f = 0; f < TC_FLAT_INFLIGHT; f++) {
+            for (int f = 0; f < TC_BITS_INFLIGHT; f++) {
                 const int g = g0 + 64 * f + (int)lane;
                 x[f] = 0u;
                 y[f] = 0u;
@@ -564,7 +573,7 @@ __device__ __forceinline__ unsigned long long tc_bitmap_lanes(TcWaveLds &L, cons
                 }
             }
 #pragma unroll
-            for (int f = 0; f < TC_FLAT_INFLIGHT; f++) acc += (unsigned)__popc(x[f] & y[f]);
+            for (int f = 0; f < TC_BITS_INFLIGHT; f++) acc += (unsigned)__popc(x[f] & y[f]);
         }
     }
     wave_sync();
@@ -585,7 +594,7 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
     const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
     const int64_t N = a.nitems;
     unsigned long long acc = 0;
-    int32_t marked = -1, first_id = -1, g = -1, mark_words = 0;
+    int32_t marked = -1, first_id = -1, g = -1;
     int64_t alen = 0;
     const int32_t *Arow = nullptr;
     bool use_hash = false;
@@ -621,25 +630,23 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
             const int cnt = (int)(it & ((1u << TC_PLAN_CNT_BITS) - 1));
             int64_t s = 0;
             int len = 0;
-            bool bitmap = false;
             if ((int)lane < cnt) {
                 const uint64_t x = a.ent[e0 + lane];
-                bitmap = (x & TC_PLAN_BITS) != 0;
-                s = bitmap ? (int64_t)(x & ((1ull << TC_PLAN_WORDS_SHIFT) - 1)) : (int64_t)(x >> TC_PLAN_LEN_BITS);
-                len = (int)(bitmap ? (x & ~TC_PLAN_BITS) >> TC_PLAN_WORDS_SHIFT : x & lmask);
+                // a bitmap entry streams no ids: it rides in s, raw, to tc_bitmap_lanes
+                const bool bitmap = (x & TC_PLAN_BITS) != 0;
+                s = bitmap ? (int64_t)x : (int64_t)(x >> TC_PLAN_LEN_BITS);
+                len = bitmap ? 0 : (int)(x & lmask);
             }
+            const bool any_bitmap = __ballot(s < 0) != 0;
             if (m != marked) {
                 if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
                 Arow = a.Lci + a.Lrp[m];
                 alen = a.Lrp[m + 1] - a.Lrp[m];
                 use_hash = tc_mark(L, Arow, alen, lane, &first_id);
-                // words of L.bm a bitmap pair reads: up to the row's largest id
-                mark_words = alen > 0 ? (Arow[alen - 1] >> 5) + 1 : 0;
                 marked = m;
             }
-            // a bitmap lane streams no ids (its len field holds an A pair's words)
-            acc += tc_stream_flat(L, use_hash, Arow, alen, a.Lci, s, bitmap ? 0 : len, cnt, lane);
-            if (__ballot(bitmap)) acc += tc_bitmap_lanes(L, a.bits, s, len, bitmap, mark_words, lane);
+            acc += tc_stream_flat(L, use_hash, Arow, alen, a.Lci, s, len, cnt, lane);
+            if (any_bitmap) acc += tc_bitmap_lanes(L, a.bits, Arow, alen, cnt, lane);
         }
     }
     if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
