@@ -199,13 +199,12 @@ __global__ void k_inverse_perm(const uint64_t *__restrict__ keys, int64_t n, int
         inv[keys[p] >> dbits] = (int32_t)p;
 }
 
-// rowA[e] = the row of entry e of a matrix with row offsets rp (A, and L
-// for the plan).  A wave takes 64 consecutive rows and writes them one
-// after the other, its lanes over the row's entries (coalesced stores; a
-// lane per row would scatter every store).  Rows of more than long_row
-// entries are left to k_row_ids_chunks, so that no wave writes a hub row
-// alone.
-__global__ void k_row_ids(const int64_t *__restrict__ rp, int64_t n, int64_t long_row, int32_t *__restrict__ rowA)
+// rowA[e] = the row of entry e of L (the sorts and the plan read it).  A
+// wave takes 64 consecutive rows and writes them one after the other, its
+// lanes over the row's entries (coalesced stores; a lane per row would
+// scatter every store).  The rows of L are short (at most a few thousand
+// ids after the degree order), so no wave is left with a hub row.
+__global__ void k_row_ids(const int64_t *__restrict__ rp, int64_t n, int32_t *__restrict__ rowA)
 {
     const unsigned lane = lane_id();
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
@@ -215,48 +214,91 @@ __global__ void k_row_ids(const int64_t *__restrict__ rp, int64_t n, int64_t lon
         const int rows = (int)min((int64_t)64, n - r0);
         for (int k = 0; k < rows; k++) {
             const int64_t b = __shfl(mb, k, 64), e = __shfl(me, k, 64);
-            if (e - b > long_row) continue;
             for (int64_t p = b + lane; p < e; p += 64) rowA[p] = (int32_t)(r0 + k);
         }
     }
 }
 
-__global__ void k_row_ids_chunks(RowChunks ch, int32_t *__restrict__ rowA)
+// wrow[w] = the row holding entry 64w of A (the first entry of window w).
+// A wave takes 64 consecutive rows and writes, row after row, the windows
+// that start in each, its lanes over them (a hub row starts many; a lane
+// per row would write a hub's windows alone).
+__global__ void k_window_rows(const int64_t *__restrict__ rp, int64_t n, int32_t *__restrict__ wrow)
 {
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const unsigned lane = lane_id();
-    for (int64_t c = wave; c < ch.n; c += nw)
-        for (int64_t p = ch.beg[c] + lane; p < ch.end[c]; p += 64) rowA[p] = ch.row[c];
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); r0 < n; r0 += step) {
+        const int64_t r = r0 + lane;
+        const int64_t mb = r < n ? (rp[r] + 63) >> 6 : 0, me = r < n ? (rp[r + 1] + 63) >> 6 : 0;
+        uint64_t todo = __ballot(me > mb);
+        while (todo) {
+            const int k = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            const int64_t wb = (int64_t)__shfl((long long)mb, k, 64), we = (int64_t)__shfl((long long)me, k, 64);
+            for (int64_t w = wb + lane; w < we; w += 64) wrow[w] = (int32_t)(r0 + k);
+        }
+    }
 }
 
 // The strictly lower part of the relabelled A, written in A's own layout:
 // the ids inv[v] < inv[u] of row u go, unsorted, to P[rpA[u] ..), and
 // cur[u] (zero on entry) ends as their number, the length of row inv[u] of
 // L.  Emitting into the space of the source row needs no counting pass
-// first.  One lane per entry of A; the loop steps whole wavefronts
-// (wave_run needs every lane), and the lanes of one row make one atomic.
-__global__ void k_emit_padded(const int32_t *__restrict__ rowA, const int32_t *__restrict__ ci,
-                              const int64_t *__restrict__ rpA, const int32_t *__restrict__ inv, int64_t nnz,
-                              unsigned long long *__restrict__ cur, int32_t *__restrict__ P)
+// first.  Waves take windows of 64 consecutive entries of A in turn (grid
+// stride: the waves at work at once cover neighbouring windows), one lane
+// per entry, and need no stored row id per entry: a lane finds its row
+// from the window's first row (wrow) by a binary search, over shuffles, of
+// the next 64 row ends held one per lane (again 64 rows on while a lane's
+// entry lies past them, as after a run of empty rows).  The lanes of one
+// row make one atomic.  (Contiguous runs of windows per wave, each found
+// by a search of the row offsets, took 343 us at 2^20 against 253 us.)
+__global__ void k_emit_windows(const int32_t *__restrict__ wrow, const int32_t *__restrict__ ci,
+                               const int64_t *__restrict__ rpA, int64_t n, const int32_t *__restrict__ inv,
+                               int64_t nnz, unsigned long long *__restrict__ cur, int32_t *__restrict__ P)
 {
     const unsigned lane = lane_id();
-    const int64_t step = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t w0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); w0 < nnz; w0 += step) {
-        const int64_t e = w0 + lane;
-        int32_t u = -1, iv = 0;
+    const int64_t nwin = (nnz + 63) >> 6;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t w = wave; w < nwin; w += nwaves) {
+        const int64_t e = (w << 6) + lane;
+        int32_t u = -1;
+        int64_t ub = 0;
+        bool need = e < nnz;
+        int64_t rc = wrow[w];
+        while (__ballot(need)) {
+            const int64_t ri = rc + 1 + lane;
+            const int64_t end = ri <= n ? rpA[ri] : INT64_MAX;   // end of row rc + lane
+            const int64_t start0 = rpA[rc];
+            // rows of this chunk ending at or before e
+            int cntr = 0;
+#pragma unroll
+            for (int sft = 32; sft >= 1; sft >>= 1) {
+                const int64_t y = (int64_t)__shfl((long long)end, cntr + sft - 1, 64);
+                if (y <= e) cntr += sft;
+            }
+            const int64_t last = (int64_t)__shfl((long long)end, 63, 64);
+            if (cntr == 63 && last <= e) cntr = 64;
+            const int64_t prev = (int64_t)__shfl((long long)end, cntr > 0 ? cntr - 1 : 0, 64);
+            if (need && cntr < 64) {
+                u = (int32_t)(rc + cntr);
+                ub = cntr > 0 ? prev : start0;
+                need = false;
+            }
+            rc += 64;
+        }
+        int32_t iv = 0;
         bool take = false;
-        if (e < nnz) {
-            u = rowA[e];
+        if (u >= 0) {
             iv = inv[ci[e]];
             take = iv < inv[u];
         }
-        const WaveRun w = wave_run(u);
-        const uint64_t t = __ballot(take) & w.run;
+        const WaveRun wr = wave_run(u);
+        const uint64_t t = __ballot(take) & wr.run;
         unsigned long long base = 0;
-        if (lane == w.head && t) base = atomicAdd(&cur[u], (unsigned long long)__popcll(t));
-        base = (unsigned long long)__shfl((long long)base, (int)w.head, 64);
-        if (take) P[rpA[u] + (int64_t)base + __popcll(t & w.before)] = iv;
+        if (lane == wr.head && t) base = atomicAdd(&cur[u], (unsigned long long)__popcll(t));
+        base = (unsigned long long)__shfl((long long)base, (int)wr.head, 64);
+        if (take) P[ub + (int64_t)base + __popcll(t & wr.before)] = iv;
     }
 }
 
@@ -722,8 +764,9 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
     int32_t *inv = (int32_t *)ws_get(ctx, WS_DEG, sizeof(int32_t) * (n > 0 ? n : 1));
     int64_t *cnt = (int64_t *)ws_get(ctx, WS_FLAGS, sizeof(int64_t) * (2 * n + 1));
     const int64_t nnzA = A->nvals;
-    int32_t *rowA = (int32_t *)ws_get(ctx, WS_GEN_D, sizeof(int32_t) * (nnzA > 0 ? nnzA : 1));
-    if (!okeys || !inv || !cnt || !rowA) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
+    const int64_t nwin = (nnzA + 63) >> 6;
+    int32_t *wrow = (int32_t *)ws_get(ctx, WS_GEN_D, sizeof(int32_t) * (nwin > 0 ? nwin : 1));
+    if (!okeys || !inv || !cnt || !wrow) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
     const int dbits = (bits_for((uint64_t)G->max_degree) + 7) / 8 * 8;
     if (n > 0) {
         hipLaunchKernelGGL(k_order_keys, dim3(grid_for(n, 256, 65536)), dim3(256), 0, ctx->stream,
@@ -736,24 +779,19 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
         hipLaunchKernelGGL(k_inverse_perm, dim3(grid_for(n, 256, 65536)), dim3(256), 0, ctx->stream,
                            okeys, n, dbits, inv);
         LAUNCH_CHECK();
-        // 2. the row of every entry of A; the relabelled strictly lower part
-        //    lands unsorted in A's layout, counting its row lengths
-        RowChunks ch;
-        TRY(graph_chunks(G, ctx, &ch, msg));
-        hipLaunchKernelGGL(k_row_ids, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, A->rowptr, n,
-                           GRAPH_LONG_ROW, rowA);
-        if (ch.n > 0)
-            hipLaunchKernelGGL(k_row_ids_chunks, dim3(grid_for(ch.n * 64, 256, 8192)), dim3(256), 0,
-                               ctx->stream, ch, rowA);
-        LAUNCH_CHECK();
     }
     int32_t *P = (int32_t *)ws_get(ctx, WS_GEN_C, sizeof(int32_t) * (nnzA > 0 ? nnzA : 1));
     unsigned long long *cur = (unsigned long long *)ws_get(ctx, WS_GEN_B, sizeof(int64_t) * (n > 0 ? n : 1));
     if (!P || !cur) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
     TRY(fill_i64(ctx, (int64_t *)cur, n, 0, msg));
     if (nnzA > 0) {
-        hipLaunchKernelGGL(k_emit_padded, dim3(grid_for(nnzA, 256, 8192)), dim3(256), 0, ctx->stream, rowA,
-                           A->colidx, A->rowptr, inv, nnzA, cur, P);
+        // 2. the first row of every 64-entry window of A; the relabelled
+        //    strictly lower part lands unsorted in A's layout, counting its
+        //    row lengths
+        hipLaunchKernelGGL(k_window_rows, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, A->rowptr, n,
+                           wrow);
+        hipLaunchKernelGGL(k_emit_windows, dim3(grid_for(nnzA, 256, 8192)), dim3(256), 0, ctx->stream, wrow,
+                           A->colidx, A->rowptr, n, inv, nnzA, cur, P);
         LAUNCH_CHECK();
     }
     if (n > 0) {
@@ -802,7 +840,7 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
         hipLaunchKernelGGL(k_row_max, dim3(grid_for(n, 256, 256)), dim3(256), 0, ctx->stream, L->rowptr, n, status);
         // the row of every entry of L (the plan reads it too)
         hipLaunchKernelGGL(k_row_ids, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, L->rowptr, n,
-                           (int64_t)INT64_MAX, rowid);
+                           rowid);
         if (nnz > 0)
             hipLaunchKernelGGL(k_sort_short, dim3(grid_for(nnz, 256, 65536)), dim3(256), 0, ctx->stream, rowid,
                                L->rowptr, okeys, dbits, A->rowptr, P, nnz, L->colidx);
