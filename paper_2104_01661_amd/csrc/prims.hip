@@ -457,7 +457,7 @@ int row_degrees(lagr_ctx ctx, const int64_t *rowptr, int64_t n, int64_t *deg, in
     if (!m) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "counters");
     HIP_TRY(hipMemsetAsync(m, 0, sizeof(unsigned long long), ctx->stream));
     if (n > 0) {
-        hipLaunchKernelGGL(k_degrees, dim3(grid_for(n, 256, 1024)), dim3(256), 0, ctx->stream,
+        hipLaunchKernelGGL(k_degrees, dim3(grid_for(n, 256, 256)), dim3(256), 0, ctx->stream,
                            rowptr, n, deg, m);
         LAUNCH_CHECK();
     }

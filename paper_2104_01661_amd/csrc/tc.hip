@@ -111,16 +111,28 @@ __host__ __device__ __forceinline__ bool plan_hub_b(int64_t p, int64_t lj, int64
     return p < lj && p < words;
 }
 
-// Per workgroup, the B entries of each hot row, reserved in the row's
-// region: boff[g * PLAN_HOT + x] = offset of workgroup g's first slot in
-// row n + x, relative to bstart = trp[n] (fewer than 2^32 entries).
+// One pass over the entries of L, on the fill's partition (workgroup g
+// takes the g-th contiguous share):
+//  * per workgroup, the B entries of each hot row, reserved in the row's
+//    region: boff[g * PLAN_HOT + x] = offset of workgroup g's first slot in
+//    row n + x, relative to bstart = trp[n] (fewer than 2^32 entries);
+//  * bw[i] = the bitmap words row i needs (0 for none; zero on entry):
+//    ceil(j / 32) for its largest id j that tc_bitmap_pair accepts at its
+//    position (row i streamed by a B pair), and all of the row: for a hub
+//    row every word up to its largest id, else tc_full_words(last id,
+//    length) when that is worth reading instead of the row's ids (row i
+//    streamed whole by an A pair).  The lanes of one row take their maximum
+//    within the wave (the words grow with the id along the row, so the
+//    last lane that asks for any holds it) and the run head makes the
+//    row's one atomic.
+// Waves step whole (wave_run needs every lane).
 __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_hot(const int32_t *__restrict__ rowid,
                                                          const int32_t *__restrict__ ci, int64_t nnz,
                                                          const uint64_t *__restrict__ rowpk,
                                                          const unsigned *__restrict__ hubw, int64_t nhub, int64_t n,
                                                          const int64_t *__restrict__ trp,
                                                          unsigned long long *__restrict__ cur,
-                                                         unsigned *__restrict__ boff)
+                                                         unsigned *__restrict__ boff, unsigned long long *__restrict__ bw)
 {
     __shared__ unsigned hot[PLAN_HOT];
     __shared__ unsigned hlen[PLAN_HOT];
@@ -133,53 +145,27 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_hot(const int32_t *__restri
         hw[x] = x < nhub ? hubw[x] : 0u;
     }
     __syncthreads();
+    const unsigned lane = lane_id();
     const int64_t share = (nnz + gridDim.x - 1) / gridDim.x;
     const int64_t e0 = (int64_t)blockIdx.x * share, e1 = min(nnz, e0 + share);
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += PLAN_BLOCK) {
-        const int32_t j = ci[e];
-        if (j >= PLAN_HOT) continue;
-        const int64_t lj = hlen[j];
-        if (lj == 0) continue;
-        const int64_t p = e - (int64_t)(rowpk[rowid[e]] >> TC_PLAN_LEN_BITS);
-        if (p > 0 && (j < nhub ? plan_hub_b(p, lj, hw[j]) : lj > p)) atomicAdd(&hot[j], 1u);
-    }
-    __syncthreads();
-    const int64_t bstart = trp[n];
-    unsigned *mine = boff + (size_t)blockIdx.x * PLAN_HOT;
-    for (int x = threadIdx.x; x < nh; x += PLAN_BLOCK)
-        mine[x] = hot[x] ? (unsigned)((int64_t)atomicAdd(&cur[n + x], (unsigned long long)hot[x]) - bstart) : 0u;
-}
-
-// bw[i] = the bitmap words row i needs (0 for none; zero on entry):
-// ceil(j / 32) for its largest id j that tc_bitmap_pair accepts at its
-// position (row i streamed by a B pair), and all of the row,
-// tc_full_words(last id, length), when that is worth reading instead of
-// the row's ids (row i streamed whole by an A pair).  One lane per entry
-// of L; the lanes of one row take their maximum within the wave (the
-// words grow with the id along the row, so the last lane that asks for
-// any holds it) and the run head makes the row's one atomic.
-__global__ void k_bitmap_words(const int32_t *__restrict__ rowid, const int32_t *__restrict__ ci, int64_t nnz,
-                               const uint64_t *__restrict__ rowpk, int64_t nhub, unsigned long long *__restrict__ bw)
-{
-    const unsigned lane = lane_id();
-    const int64_t step = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t w0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); w0 < nnz; w0 += step) {
-        const int64_t e = w0 + lane;
+    for (int64_t base = e0 + (threadIdx.x & ~63u); base < e1; base += PLAN_BLOCK) {
+        const int64_t e = base + lane;
         int32_t i = -1;
         unsigned v = 0;
-        if (e < nnz) {
+        if (e < e1) {
             i = rowid[e];
             const int32_t j = ci[e];
             const uint64_t pk = rowpk[i];
-            const int64_t p = e - (int64_t)(pk >> TC_PLAN_LEN_BITS);
+            const int64_t p = e - (int64_t)(pk >> TC_PLAN_LEN_BITS), len = (int64_t)(pk & lmask);
+            if (j < PLAN_HOT) {
+                const int64_t lj = hlen[j];
+                if (lj > 0 && p > 0 && (j < nhub ? plan_hub_b(p, lj, hw[j]) : lj > p)) atomicAdd(&hot[j], 1u);
+            }
             if (j >= nhub && tc_bitmap_pair(j, p)) v = (unsigned)((j + 31) >> 5);   // hub pairs: plan_hub_b
-            const int64_t len = (int64_t)(pk & ((1ull << TC_PLAN_LEN_BITS) - 1));
             if (p == len - 1 && i <= TC_BM_IDS)   // the row's last (largest) id
                 v = max(v, i < nhub ? (unsigned)((j >> 5) + 1) : tc_full_words(j, len));
         }
         const WaveRun w = wave_run(i);
-        // maximum over the run: ids ascend along a row, so the last lane of
-        // the run that accepts holds it
         const uint64_t acc = __ballot(v > 0) & w.run;
         if (acc) {
             const int last = 63 - __clzll((unsigned long long)acc);
@@ -187,6 +173,11 @@ __global__ void k_bitmap_words(const int32_t *__restrict__ rowid, const int32_t 
             if (lane == w.head) atomicMax(&bw[i], (unsigned long long)m);
         }
     }
+    __syncthreads();
+    const int64_t bstart = trp[n];
+    unsigned *mine = boff + (size_t)blockIdx.x * PLAN_HOT;
+    for (int x = threadIdx.x; x < nh; x += PLAN_BLOCK)
+        mine[x] = hot[x] ? (unsigned)((int64_t)atomicAdd(&cur[n + x], (unsigned long long)hot[x]) - bstart) : 0u;
 }
 
 // The rows with bitmap words (off[r + 1] > off[r]), listed in
@@ -518,13 +509,11 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
         hipLaunchKernelGGL(k_row_pack, dim3(grid_for(n, 256, 16384)), dim3(256), 0, ctx->stream, Lm->rowptr, n,
                            rowpk);
         if (nnz > 0) {
-            hipLaunchKernelGGL(k_bitmap_words, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, ctx->stream, rowid,
-                               Lm->colidx, nnz, rowpk, nhub, (unsigned long long *)P->boff);
             if (nhub > 0)
                 hipLaunchKernelGGL(k_hub_words, dim3(grid_for(nhub, 256, 64)), dim3(256), 0, ctx->stream,
                                    Lm->rowptr, Lm->colidx, nhub, hubw);
             hipLaunchKernelGGL(k_plan_hot, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx,
-                               nnz, rowpk, hubw, nhub, n, P->trp, cur, boff);
+                               nnz, rowpk, hubw, nhub, n, P->trp, cur, boff, (unsigned long long *)P->boff);
         }
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
         if ((rc = scan_exclusive_i64(ctx, P->boff, P->boff, n + 1, nullptr, msg)) < 0) return fail(rc);
