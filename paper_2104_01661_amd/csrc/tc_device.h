@@ -586,7 +586,7 @@ __device__ __forceinline__ unsigned long long tc_bitmap_lanes(TcWaveLds &L, cons
     return acc;
 }
 
-constexpr int64_t TC_DYN_ITEMS = 4;
+constexpr int64_t TC_DYN_ITEMS = 8;
 constexpr int TC_DYN_STRIDE = 16;   // 128 bytes between counters
 constexpr int TC_DYN_PARTS = 8;
 
