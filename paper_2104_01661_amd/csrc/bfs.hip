@@ -383,10 +383,13 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
     if (hipGetLastError() != hipSuccess) BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs init launch"));
     hipGraphExec_t exec = nullptr;
     BFS_TRY(bfs_graph(ctx, d, n, W, &exec, msg));
-    // replay two levels at a time; look at the done flag after 6 levels and
-    // then after every 2 (each look is a host round trip)
+    // replay two levels at a time; look at the done flag after 8 levels and
+    // then after every 4 (each look is a host round trip; a level past the
+    // end costs only kernels that return at once).  An R-MAT graph of 2^20
+    // vertices is 5 to 6 levels deep, which the search finishes in 7 to 8
+    // steps: one look.
     int64_t levels = 0;
-    for (int64_t replays = 3;; replays = 1) {
+    for (int64_t replays = 4;; replays = 2) {
         for (int64_t r = 0; r < replays; r++)
             if (hipGraphLaunch(exec, ctx->stream) != hipSuccess)
                 BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs graph launch"));
