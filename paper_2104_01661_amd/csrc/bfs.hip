@@ -57,6 +57,19 @@ struct BfsDev {
 
 namespace {
 
+// The per-search reset in one launch: levels to -1, parents to -1, the
+// three bitmaps (visited, two frontiers) to 0.
+__global__ void k_bfs_reset(int32_t *__restrict__ level, int64_t *__restrict__ parent, int64_t n,
+                            uint32_t *__restrict__ bms, int64_t nw)
+{
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+        level[i] = -1;
+        parent[i] = -1;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += step) bms[i] = 0u;
+}
+
 __global__ void k_bfs_init(BfsDev *d, int64_t src)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -376,9 +389,8 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
     memcpy(ctx->pinned, &h, sizeof(h));
     if (hipMemcpyAsync(d, ctx->pinned, sizeof(h), hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
         BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs state copy"));
-    BFS_TRY(fill_u32(ctx, (uint32_t *)lev32, n, 0xFFFFFFFFu, msg));
-    BFS_TRY(fill_i64(ctx, parent, n, -1, msg));
-    BFS_TRY(fill_u32(ctx, bms, 3 * W, 0u, msg));
+    hipLaunchKernelGGL(k_bfs_reset, dim3(grid_for(n, 256, 4096)), dim3(256), 0, ctx->stream, lev32, parent, n, bms,
+                       3 * W);
     hipLaunchKernelGGL(k_bfs_init, dim3(1), dim3(64), 0, ctx->stream, d, source);
     if (hipGetLastError() != hipSuccess) BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs init launch"));
     hipGraphExec_t exec = nullptr;
