@@ -130,10 +130,8 @@ __device__ __forceinline__ void push_range(const BfsDev &d, int32_t u, int64_t b
 // its level.  The parent is the smallest frontier neighbour (atomicMin on
 // the unsigned parent, whose "absent" value -1 is the largest), or, with
 // LAGR_BFS_ANY_PARENT, the CAS winner.
-__global__ __launch_bounds__(256) void k_bfs_push(BfsDev *dp, int par)
+__device__ __forceinline__ void bfs_push(const BfsDev &d, int par)
 {
-    const BfsDev &d = *dp;
-    if (d.done || d.pull) return;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const unsigned lane = lane_id();
@@ -143,17 +141,15 @@ __global__ __launch_bounds__(256) void k_bfs_push(BfsDev *dp, int par)
     for (int64_t f = wave; f < d.nq; f += nw) {
         const int32_t u = frontier[f];
         const int64_t b = d.rp[u], e = d.rp[u + 1];
-        if (e - b > GRAPH_LONG_ROW) continue;   // k_bfs_push_chunks
+        if (e - b > GRAPH_LONG_ROW) continue;   // bfs_push_chunks
         push_range(d, u, b, e, lane, lev, next_bm);
     }
 }
 
 // The frontier's hub vertices: every chunk of a long row whose vertex is in
 // the frontier bitmap is pushed by a whole wave.
-__global__ __launch_bounds__(256) void k_bfs_push_chunks(BfsDev *dp, int par)
+__device__ __forceinline__ void bfs_push_chunks(const BfsDev &d, int par)
 {
-    const BfsDev &d = *dp;
-    if (d.done || d.pull) return;
     const unsigned lane = lane_id();
     const int32_t lev = d.lev;
     uint32_t *next_bm = d.bm[par ^ 1];
@@ -169,10 +165,8 @@ __global__ __launch_bounds__(256) void k_bfs_push_chunks(BfsDev *dp, int par)
 // trips per batch rather than two per neighbour.
 constexpr int PULL_BATCH = 8;
 
-__global__ __launch_bounds__(256) void k_bfs_pull(BfsDev *dp, int par)
+__device__ __forceinline__ void bfs_pull(const BfsDev &d, int par)
 {
-    const BfsDev &d = *dp;
-    if (d.done || !d.pull) return;
     const int64_t n = d.n;
     const int32_t lev = d.lev;
     const uint32_t *cur_bm = d.bm[par];
@@ -205,6 +199,23 @@ __global__ __launch_bounds__(256) void k_bfs_pull(BfsDev *dp, int par)
         const int64_t w0 = (v - lane) >> 5;
         if (lane == 0 && (uint32_t)m) next_bm[w0] = (uint32_t)m;
         if (lane == 32 && (uint32_t)(m >> 32)) next_bm[w0 + 1] = (uint32_t)(m >> 32);
+    }
+}
+
+// The level's expansion in one launch: pull, or push over the frontier
+// list and then over the hub chunks marked in the frontier bitmap.  One
+// kernel node per level instead of three: a node whose work the direction
+// skips still costs its dispatch (a few microseconds at thousands of
+// workgroups).
+__global__ __launch_bounds__(256) void k_bfs_expand(BfsDev *dp, int par)
+{
+    const BfsDev &d = *dp;
+    if (d.done) return;
+    if (d.pull) {
+        bfs_pull(d, par);
+    } else {
+        bfs_push(d, par);
+        bfs_push_chunks(d, par);
     }
 }
 
@@ -261,9 +272,7 @@ __global__ void k_level_to_i64(const int32_t *__restrict__ in, int64_t *__restri
 int enqueue_level(BfsDev *d, int par, int64_t n, int64_t W, int num_cus, hipStream_t s, char *msg)
 {
     hipLaunchKernelGGL(k_bfs_decide, dim3(1), dim3(64), 0, s, d);
-    hipLaunchKernelGGL(k_bfs_push, dim3((unsigned)(num_cus * 8)), dim3(256), 0, s, d, par);
-    hipLaunchKernelGGL(k_bfs_push_chunks, dim3((unsigned)(num_cus * 2)), dim3(256), 0, s, d, par);
-    hipLaunchKernelGGL(k_bfs_pull, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, d, par);
+    hipLaunchKernelGGL(k_bfs_expand, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, d, par);
     hipLaunchKernelGGL(k_bfs_compact, dim3(grid_for(W, 256, 1 << 30)), dim3(256), 0, s, d, par);
     LAUNCH_CHECK();
     return LAGR_SUCCESS;
