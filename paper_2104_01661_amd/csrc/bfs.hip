@@ -12,8 +12,8 @@
 // A compaction pass then lists the next frontier, counts it and its degree
 // sum and adds it to the visited set.  The level loop runs on the device:
 // a one-thread kernel folds the counters into the level state and picks
-// the direction, and every kernel of a level returns at once when the
-// search is done or the other direction was picked.  Two levels (the two
+// the next level's direction, and every kernel of a level returns at once
+// when the search is done.  Two levels (the two
 // buffer parities) are captured once into a hipGraph per context and
 // replayed; the host looks at the done flag only every few levels.
 #include "internal.h"
@@ -57,39 +57,17 @@ struct BfsDev {
 
 namespace {
 
-// The per-search reset in one launch: levels to -1, parents to -1, the
-// three bitmaps (visited, two frontiers) to 0.
-__global__ void k_bfs_reset(int32_t *__restrict__ level, int64_t *__restrict__ parent, int64_t n,
-                            uint32_t *__restrict__ bms, int64_t nw)
-{
-    const int64_t step = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
-        level[i] = -1;
-        parent[i] = -1;
-    }
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += step) bms[i] = 0u;
-}
-
-__global__ void k_bfs_init(BfsDev *d, int64_t src)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        d->level[src] = 0;
-        d->parent[src] = (unsigned long long)src;
-        d->list[0][0] = (int32_t)src;
-        d->visited[src >> 5] |= 1u << (src & 31);
-        d->bm[0][src >> 5] |= 1u << (src & 31);
-        d->enext = (unsigned long long)(d->rp[src + 1] - d->rp[src]);
-    }
-}
 
 // Start of a level: fold the last compaction's counters into the state,
 // stop when the frontier is empty, and pick the direction (Beamer, Asanovic
 // and Patterson, SC 2012, the heuristic the paper cites): pull when the
 // frontier's edges exceed the unexplored edges / BFS_ALPHA, back to push
-// when the frontier has fewer than n / BFS_BETA vertices.
-__global__ void k_bfs_decide(BfsDev *d)
+// when the frontier has fewer than n / BFS_BETA vertices.  One thread runs
+// it: in the start kernel for the first level, then in a one-thread kernel
+// after each compaction.  (Folding it into the compaction's last workgroup
+// by a ticket counter measured no faster than the separate node.)
+__device__ void bfs_decide(BfsDev *d)
 {
-    if (threadIdx.x != 0 || d->done) return;
     const int64_t nq = (int64_t)d->nnext, mf = (int64_t)d->enext;
     d->nq = nq;
     d->mf = mf;
@@ -105,6 +83,29 @@ __global__ void k_bfs_decide(BfsDev *d)
     }
     d->nnext = 0;
     d->enext = 0;
+}
+
+// The per-search start in one launch: levels and parents to -1 and the
+// three bitmaps (visited, two frontiers) to 0, except the source's entries;
+// then the first level's decision, with the source as the frontier.
+__global__ void k_bfs_start(BfsDev *d, int32_t *__restrict__ level, int64_t *__restrict__ parent, int64_t n,
+                            uint32_t *__restrict__ bms, int64_t W, int64_t src)
+{
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = t0; i < n; i += step) {
+        level[i] = i == src ? 0 : -1;
+        parent[i] = i == src ? src : -1;
+    }
+    const int64_t sw = src >> 5;
+    const uint32_t sbit = 1u << (src & 31);
+    for (int64_t i = t0; i < 3 * W; i += step) bms[i] = (i == sw || i == W + sw) ? sbit : 0u;
+    if (t0 == 0) {
+        d->list[0][0] = (int32_t)src;
+        d->nnext = 1;
+        d->enext = (unsigned long long)(d->rp[src + 1] - d->rp[src]);
+        bfs_decide(d);
+    }
 }
 
 // Push the neighbours rp-range [b, e) of frontier vertex u, one per lane.
@@ -219,6 +220,11 @@ __global__ __launch_bounds__(256) void k_bfs_expand(BfsDev *dp, int par)
     }
 }
 
+__global__ void k_bfs_decide(BfsDev *d)
+{
+    if (threadIdx.x == 0 && !d->done) bfs_decide(d);
+}
+
 // End of a level: the next frontier from its bitmap, a thread per 32-bit
 // word.  Each workgroup scans its words' popcounts, reserves its range of
 // the list with one atomic (atomics on one address from every wavefront
@@ -269,11 +275,11 @@ __global__ void k_level_to_i64(const int32_t *__restrict__ in, int64_t *__restri
 }
 
 // One level on stream s with buffer parity par.
-int enqueue_level(BfsDev *d, int par, int64_t n, int64_t W, int num_cus, hipStream_t s, char *msg)
+int enqueue_level(BfsDev *d, int par, int64_t n, int64_t W, hipStream_t s, char *msg)
 {
-    hipLaunchKernelGGL(k_bfs_decide, dim3(1), dim3(64), 0, s, d);
     hipLaunchKernelGGL(k_bfs_expand, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, d, par);
     hipLaunchKernelGGL(k_bfs_compact, dim3(grid_for(W, 256, 1 << 30)), dim3(256), 0, s, d, par);
+    hipLaunchKernelGGL(k_bfs_decide, dim3(1), dim3(64), 0, s, d);
     LAUNCH_CHECK();
     return LAGR_SUCCESS;
 }
@@ -291,8 +297,8 @@ static int bfs_graph(lagr_ctx ctx, BfsDev *d, int64_t n, int64_t W, hipGraphExec
     ctx->bfs_exec = nullptr;
     if (!ctx->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_level(d, 0, n, W, ctx->num_cus, ctx->capture_stream, msg);
-    if (rc >= 0) rc = enqueue_level(d, 1, n, W, ctx->num_cus, ctx->capture_stream, msg);
+    int rc = enqueue_level(d, 0, n, W, ctx->capture_stream, msg);
+    if (rc >= 0) rc = enqueue_level(d, 1, n, W, ctx->capture_stream, msg);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(ctx->capture_stream, &g);
     if (rc < 0 || e != hipSuccess) {
@@ -393,15 +399,13 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
     h.push_only = (flags & LAGR_BFS_PUSH_ONLY) ? 1 : 0;
     h.lev = 0;
     h.mu = A->nvals;
-    h.nnext = 1;   // the source (k_bfs_init sets enext to its degree)
     static_assert(sizeof(BfsDev) <= 4096, "BfsDev must fit the pinned staging buffer");
     memcpy(ctx->pinned, &h, sizeof(h));
     if (hipMemcpyAsync(d, ctx->pinned, sizeof(h), hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
         BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs state copy"));
-    hipLaunchKernelGGL(k_bfs_reset, dim3(grid_for(n, 256, 4096)), dim3(256), 0, ctx->stream, lev32, parent, n, bms,
-                       3 * W);
-    hipLaunchKernelGGL(k_bfs_init, dim3(1), dim3(64), 0, ctx->stream, d, source);
-    if (hipGetLastError() != hipSuccess) BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs init launch"));
+    hipLaunchKernelGGL(k_bfs_start, dim3(grid_for(n, 256, 4096)), dim3(256), 0, ctx->stream, d, lev32, parent, n,
+                       bms, W, source);
+    if (hipGetLastError() != hipSuccess) BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs start launch"));
     hipGraphExec_t exec = nullptr;
     BFS_TRY(bfs_graph(ctx, d, n, W, &exec, msg));
     // replay two levels at a time; look at the done flag after 8 levels and
