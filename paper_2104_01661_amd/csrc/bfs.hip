@@ -51,6 +51,7 @@ struct BfsDev {
     // level state: lev, direction, termination, frontier size / degree sum,
     // unexplored degree sum, and the compaction counters of the last level
     int32_t lev, pull, done, pad_;
+    int32_t *done_host;       // pinned host word set when the search ends
     int64_t nq, mf, mu;
     unsigned long long nnext, enext;
 };
@@ -75,6 +76,8 @@ __device__ void bfs_decide(BfsDev *d)
     d->lev += 1;
     if (nq == 0 || d->lev == INT32_MAX) {
         d->done = 1;
+        __hip_atomic_store(d->done_host, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __threadfence_system();
         return;
     }
     if (!d->push_only) {
@@ -85,11 +88,12 @@ __device__ void bfs_decide(BfsDev *d)
     d->enext = 0;
 }
 
-// The per-search start in one launch: levels and parents to -1 and the
-// three bitmaps (visited, two frontiers) to 0, except the source's entries;
-// then the first level's decision, with the source as the frontier.
-__global__ void k_bfs_start(BfsDev *d, int32_t *__restrict__ level, int64_t *__restrict__ parent, int64_t n,
-                            uint32_t *__restrict__ bms, int64_t W, int64_t src)
+// The per-search start in one launch: the level state from the kernel
+// argument h into d, levels and parents to -1 and the three bitmaps
+// (visited, two frontiers) to 0, except the source's entries; then the
+// first level's decision, with the source as the frontier.
+__global__ void k_bfs_start(BfsDev h, BfsDev *d, int32_t *__restrict__ level, int64_t *__restrict__ parent,
+                            int64_t n, uint32_t *__restrict__ bms, int64_t W, int64_t src)
 {
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -101,6 +105,7 @@ __global__ void k_bfs_start(BfsDev *d, int32_t *__restrict__ level, int64_t *__r
     const uint32_t sbit = 1u << (src & 31);
     for (int64_t i = t0; i < 3 * W; i += step) bms[i] = (i == sw || i == W + sw) ? sbit : 0u;
     if (t0 == 0) {
+        *d = h;
         d->list[0][0] = (int32_t)src;
         d->nnext = 1;
         d->enext = (unsigned long long)(d->rp[src + 1] - d->rp[src]);
@@ -378,8 +383,7 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
         }                        \
     } while (0)
 
-    // the struct goes through the context's pinned staging buffer; the copy
-    // is ordered before everything below on the stream
+    // the level state goes to the device as the start kernel's argument
     BfsDev h{};
     h.rp = A->rowptr;
     h.ci = A->colidx;
@@ -399,12 +403,15 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
     h.push_only = (flags & LAGR_BFS_PUSH_ONLY) ? 1 : 0;
     h.lev = 0;
     h.mu = A->nvals;
-    static_assert(sizeof(BfsDev) <= 4096, "BfsDev must fit the pinned staging buffer");
-    memcpy(ctx->pinned, &h, sizeof(h));
-    if (hipMemcpyAsync(d, ctx->pinned, sizeof(h), hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
-        BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs state copy"));
-    hipLaunchKernelGGL(k_bfs_start, dim3(grid_for(n, 256, 4096)), dim3(256), 0, ctx->stream, d, lev32, parent, n,
-                       bms, W, source);
+    // the decision kernel stores 1 to this pinned word when the search
+    // ends; the host clears it first (nothing else writes it: the last
+    // search on this context drained before it returned)
+    volatile int32_t *done_flag = (volatile int32_t *)((char *)ctx->pinned + LAGR_PINNED_STAGE);
+    h.done_host = (int32_t *)((char *)ctx->pinned_dev + LAGR_PINNED_STAGE);
+    *done_flag = 0;
+    static_assert(sizeof(BfsDev) <= 1024, "BfsDev is passed as a kernel argument");
+    hipLaunchKernelGGL(k_bfs_start, dim3(grid_for(n, 256, 4096)), dim3(256), 0, ctx->stream, h, d, lev32, parent,
+                       n, bms, W, source);
     if (hipGetLastError() != hipSuccess) BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs start launch"));
     hipGraphExec_t exec = nullptr;
     BFS_TRY(bfs_graph(ctx, d, n, W, &exec, msg));
@@ -419,9 +426,9 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
             if (hipGraphLaunch(exec, ctx->stream) != hipSuccess)
                 BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs graph launch"));
         levels += 2 * replays;
-        int32_t done = 0;
-        BFS_TRY(read_back(ctx, &done, &d->done, sizeof(done), msg));
-        if (done) break;
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess)
+            BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs level loop: %s", hipGetErrorString(hipGetLastError())));
+        if (*done_flag) break;
         if (levels > n + 2) BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs did not terminate"));
     }
     if (level_out) {

@@ -84,9 +84,14 @@ extern "C" int lagr_ctx_new(lagr_ctx *ctx, int device, void *stream, char *msg)
     if (!c) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "context");
     c->device = device;
     c->stream = (hipStream_t)stream;
-    if (hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(&c->pinned, LAGR_PINNED_BYTES, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "pinned staging buffer");
+    }
+    if (hipHostGetDevicePointer(&c->pinned_dev, c->pinned, 0) != hipSuccess || !c->pinned_dev) {
+        (void)hipHostFree(c->pinned);
+        delete c;
+        return lagr_fail(msg, LAGR_DEVICE_ERROR, "pinned staging buffer: no device address");
     }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cus = prop.multiProcessorCount;

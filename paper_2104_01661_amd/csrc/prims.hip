@@ -166,15 +166,11 @@ int scan_exclusive_i64(lagr_ctx ctx, const int64_t *in, int64_t *out, int64_t n,
         return LAGR_SUCCESS;
     }
     int64_t last_in = 0;
-    if (total) {
-        // the last input is needed after an in-place scan overwrote it
-        HIP_TRY(hipMemcpyAsync(&((int64_t *)ctx->pinned)[1], in + n - 1, sizeof(int64_t),
-                               hipMemcpyDeviceToHost, ctx->stream));
-    }
+    // the last input is needed after an in-place scan overwrote it
+    if (total) TRY(stage_to_host(ctx, 8, in + n - 1, sizeof(int64_t), msg));
     TRY(scan_level(ctx, in, out, n, 0, msg));
     if (total) {
-        HIP_TRY(hipMemcpyAsync(&((int64_t *)ctx->pinned)[2], out + n - 1, sizeof(int64_t),
-                               hipMemcpyDeviceToHost, ctx->stream));
+        TRY(stage_to_host(ctx, 16, out + n - 1, sizeof(int64_t), msg));
         HIP_TRY(hipStreamSynchronize(ctx->stream));
         last_in = ((int64_t *)ctx->pinned)[1];
         *total = last_in + ((int64_t *)ctx->pinned)[2];
@@ -332,10 +328,37 @@ int fill_u8(lagr_ctx ctx, uint8_t *p, int64_t n, uint8_t value, char *msg)
     return LAGR_SUCCESS;
 }
 
+namespace {
+// A few words device -> pinned host memory, stored at system scope and
+// fenced so that the host sees them once the stream has drained.
+__global__ void k_to_host(const uint32_t *__restrict__ src, uint32_t *dst, int64_t words)
+{
+    for (int64_t w = threadIdx.x; w < words; w += blockDim.x)
+        __hip_atomic_store(dst + w, src[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __threadfence_system();
+}
+}  // namespace
+
+int stage_to_host(lagr_ctx ctx, size_t offset, const void *dev, size_t bytes, char *msg)
+{
+    if (offset > LAGR_PINNED_STAGE || bytes > LAGR_PINNED_STAGE - offset)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "stage_to_host: %zu bytes at %zu exceed the staging buffer",
+                         bytes, offset);
+    if (bytes == 0) return LAGR_SUCCESS;
+    if (((uintptr_t)dev & 3u) == 0 && (bytes & 3u) == 0 && (offset & 3u) == 0) {
+        hipLaunchKernelGGL(k_to_host, dim3(1), dim3(64), 0, ctx->stream, (const uint32_t *)dev,
+                           (uint32_t *)((char *)ctx->pinned_dev + offset), (int64_t)(bytes / 4));
+        HIP_TRY(hipGetLastError());
+    } else {
+        HIP_TRY(hipMemcpyAsync((char *)ctx->pinned + offset, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    return LAGR_SUCCESS;
+}
+
 int read_back(lagr_ctx ctx, void *host, const void *dev, size_t bytes, char *msg)
 {
-    if (bytes > 4096) return lagr_fail(msg, LAGR_INVALID_VALUE, "read_back: too large");
-    HIP_TRY(hipMemcpyAsync(ctx->pinned, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    if (bytes > LAGR_PINNED_STAGE) return lagr_fail(msg, LAGR_INVALID_VALUE, "read_back: too large");
+    TRY(stage_to_host(ctx, 0, dev, bytes, msg));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     memcpy(host, ctx->pinned, bytes);
     return LAGR_SUCCESS;
