@@ -880,8 +880,7 @@ int msbfs_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, uin
         TRY(stats_of(list_of(b ^ 1), (int64_t)h[0], next, d));
         b ^= 1;
     }
-    TRY(stage_to_host(ctx, 0, dstats, 8 * 3 * 64, msg));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    TRY(stage_to_host(ctx, 0, dstats, 8 * 3 * 64, true, msg));
     memcpy(stats, ctx->pinned, 8 * 3 * 64);
     return LAGR_SUCCESS;
 }

@@ -426,8 +426,7 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
             if (hipGraphLaunch(exec, ctx->stream) != hipSuccess)
                 BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs graph launch"));
         levels += 2 * replays;
-        if (hipStreamSynchronize(ctx->stream) != hipSuccess)
-            BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs level loop: %s", hipGetErrorString(hipGetLastError())));
+        BFS_TRY(host_wait(ctx, msg));
         if (*done_flag) break;
         if (levels > n + 2) BFS_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bfs did not terminate"));
     }

@@ -93,6 +93,7 @@ extern "C" int lagr_ctx_new(lagr_ctx *ctx, int device, void *stream, char *msg)
         delete c;
         return lagr_fail(msg, LAGR_DEVICE_ERROR, "pinned staging buffer: no device address");
     }
+    memset(c->pinned, 0, LAGR_PINNED_BYTES);   // the flags start clear
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cus = prop.multiProcessorCount;
     *ctx = c;

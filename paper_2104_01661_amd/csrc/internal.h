@@ -108,6 +108,7 @@ struct lagr_ctx_s {
     size_t ws_bytes[WS_NSLOTS] = {};
     void *pinned = nullptr;          // pinned host staging for scalars: LAGR_PINNED_BYTES
     void *pinned_dev = nullptr;      // the same buffer's device address
+    uint32_t host_seq = 0;           // last sequence number of a host wait
     int num_cus = 256;
     std::vector<void *> lvpool;      // per-level lane masks + vertex lists (BC)
     size_t lv_bytes = 0;
@@ -233,15 +234,23 @@ int fill_u32(lagr_ctx ctx, uint32_t *p, int64_t n, uint32_t value, char *msg);
 int fill_u8(lagr_ctx ctx, uint8_t *p, int64_t n, uint8_t value, char *msg);
 // The pinned buffer: LAGR_PINNED_STAGE bytes of staging for read_back and
 // stage_to_host, then LAGR_PINNED_FLAGS bytes of flags that kernels store
-// to directly (the BFS level loop's done flag at offset LAGR_PINNED_STAGE).
+// to directly: the BFS level loop's done flag at LAGR_PINNED_STAGE and the
+// sequence word of host waits at LAGR_PINNED_SEQ.
 constexpr size_t LAGR_PINNED_STAGE = 4096;
+constexpr size_t LAGR_PINNED_SEQ = LAGR_PINNED_STAGE + 64;
 constexpr size_t LAGR_PINNED_FLAGS = 256;
 constexpr size_t LAGR_PINNED_BYTES = LAGR_PINNED_STAGE + LAGR_PINNED_FLAGS;
 // Enqueue a copy of `bytes` device bytes to the pinned buffer at `offset`
 // (a one-workgroup kernel storing to the buffer's device address when both
 // are 4-byte multiples, which costs less than the runtime's copy; else
-// hipMemcpyAsync).  The host reads the buffer after a stream sync.
-int stage_to_host(lagr_ctx ctx, size_t offset, const void *dev, size_t bytes, char *msg);
+// hipMemcpyAsync).  With wait, return once the copy and all earlier work
+// on the stream are done (the kernel stores a sequence number after the
+// words and the host polls it); without, the host reads the buffer only
+// after a later wait.
+int stage_to_host(lagr_ctx ctx, size_t offset, const void *dev, size_t bytes, bool wait, char *msg);
+// Return once all work enqueued on the context's stream is done (the same
+// polled sequence number, with no words).
+int host_wait(lagr_ctx ctx, char *msg);
 // Copy a few bytes device -> host through the context's pinned buffer and
 // wait for the stream.
 int read_back(lagr_ctx ctx, void *host, const void *dev, size_t bytes, char *msg);

@@ -2,6 +2,9 @@
 // offsets from sorted keys, row degrees.
 #include "internal.h"
 
+#include <atomic>
+#include <chrono>
+
 namespace {
 
 constexpr int SCAN_BLOCK = 256;
@@ -167,11 +170,10 @@ int scan_exclusive_i64(lagr_ctx ctx, const int64_t *in, int64_t *out, int64_t n,
     }
     int64_t last_in = 0;
     // the last input is needed after an in-place scan overwrote it
-    if (total) TRY(stage_to_host(ctx, 8, in + n - 1, sizeof(int64_t), msg));
+    if (total) TRY(stage_to_host(ctx, 8, in + n - 1, sizeof(int64_t), false, msg));
     TRY(scan_level(ctx, in, out, n, 0, msg));
     if (total) {
-        TRY(stage_to_host(ctx, 16, out + n - 1, sizeof(int64_t), msg));
-        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        TRY(stage_to_host(ctx, 16, out + n - 1, sizeof(int64_t), true, msg));
         last_in = ((int64_t *)ctx->pinned)[1];
         *total = last_in + ((int64_t *)ctx->pinned)[2];
     }
@@ -330,36 +332,77 @@ int fill_u8(lagr_ctx ctx, uint8_t *p, int64_t n, uint8_t value, char *msg)
 
 namespace {
 // A few words device -> pinned host memory, stored at system scope and
-// fenced so that the host sees them once the stream has drained.
-__global__ void k_to_host(const uint32_t *__restrict__ src, uint32_t *dst, int64_t words)
+// fenced; with a flag, thread 0 then stores seq to it with release order,
+// so a host that sees seq there also sees the words.
+__global__ void k_to_host(const uint32_t *__restrict__ src, uint32_t *dst, int64_t words, uint32_t *flag,
+                          uint32_t seq)
 {
     for (int64_t w = threadIdx.x; w < words; w += blockDim.x)
         __hip_atomic_store(dst + w, src[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __threadfence_system();
+    if (flag) {
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// Wait for the flag store of sequence number seq.  The host polls the
+// pinned word (a blocking stream sync sleeps until an interrupt, tens of
+// microseconds after a short wait), asks the runtime every 64 polls whether
+// the stream failed or drained, and after 2 ms of polling blocks instead.
+int wait_host_flag(lagr_ctx ctx, uint32_t seq, char *msg)
+{
+    volatile uint32_t *f = (volatile uint32_t *)((char *)ctx->pinned + LAGR_PINNED_SEQ);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned it = 1;; it++) {
+        if (*f == seq) {
+            std::atomic_thread_fence(std::memory_order_acquire);
+            return LAGR_SUCCESS;
+        }
+        if ((it & 63u) == 0) {
+            const hipError_t e = hipStreamQuery(ctx->stream);
+            if (e == hipSuccess) break;
+            if (e != hipErrorNotReady)
+                return lagr_fail(msg, LAGR_DEVICE_ERROR, "stream: %s", hipGetErrorString(e));
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) break;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (*f != seq) return lagr_fail(msg, LAGR_DEVICE_ERROR, "host flag %u not set after the stream drained", seq);
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return LAGR_SUCCESS;
 }
 }  // namespace
 
-int stage_to_host(lagr_ctx ctx, size_t offset, const void *dev, size_t bytes, char *msg)
+int stage_to_host(lagr_ctx ctx, size_t offset, const void *dev, size_t bytes, bool wait, char *msg)
 {
     if (offset > LAGR_PINNED_STAGE || bytes > LAGR_PINNED_STAGE - offset)
         return lagr_fail(msg, LAGR_INVALID_VALUE, "stage_to_host: %zu bytes at %zu exceed the staging buffer",
                          bytes, offset);
-    if (bytes == 0) return LAGR_SUCCESS;
-    if (((uintptr_t)dev & 3u) == 0 && (bytes & 3u) == 0 && (offset & 3u) == 0) {
-        hipLaunchKernelGGL(k_to_host, dim3(1), dim3(64), 0, ctx->stream, (const uint32_t *)dev,
-                           (uint32_t *)((char *)ctx->pinned_dev + offset), (int64_t)(bytes / 4));
-        HIP_TRY(hipGetLastError());
-    } else {
+    const bool words = ((uintptr_t)dev & 3u) == 0 && (bytes & 3u) == 0 && (offset & 3u) == 0;
+    if (!words) {
         HIP_TRY(hipMemcpyAsync((char *)ctx->pinned + offset, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
+        if (wait) HIP_TRY(hipStreamSynchronize(ctx->stream));
+        return LAGR_SUCCESS;
     }
-    return LAGR_SUCCESS;
+    if (bytes == 0 && !wait) return LAGR_SUCCESS;
+    const uint32_t seq = ++ctx->host_seq;
+    hipLaunchKernelGGL(k_to_host, dim3(1), dim3(64), 0, ctx->stream, (const uint32_t *)dev,
+                       (uint32_t *)((char *)ctx->pinned_dev + offset), (int64_t)(bytes / 4),
+                       wait ? (uint32_t *)((char *)ctx->pinned_dev + LAGR_PINNED_SEQ) : nullptr, seq);
+    HIP_TRY(hipGetLastError());
+    return wait ? wait_host_flag(ctx, seq, msg) : LAGR_SUCCESS;
+}
+
+int host_wait(lagr_ctx ctx, char *msg)
+{
+    return stage_to_host(ctx, 0, ctx->pinned_dev, 0, true, msg);
 }
 
 int read_back(lagr_ctx ctx, void *host, const void *dev, size_t bytes, char *msg)
 {
     if (bytes > LAGR_PINNED_STAGE) return lagr_fail(msg, LAGR_INVALID_VALUE, "read_back: too large");
-    TRY(stage_to_host(ctx, 0, dev, bytes, msg));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    TRY(stage_to_host(ctx, 0, dev, bytes, true, msg));
     memcpy(host, ctx->pinned, bytes);
     return LAGR_SUCCESS;
 }
