@@ -211,10 +211,15 @@ __global__ void k_row_ids(const int64_t *__restrict__ rp, int64_t n, int32_t *__
     for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); r0 < n; r0 += step) {
         const int64_t r = r0 + lane;
         const int64_t mb = r < n ? rp[r] : 0, me = r < n ? rp[r + 1] : 0;
+        // four 16-lane groups, each writing one row at a time: most rows
+        // of L are shorter than 16 entries
         const int rows = (int)min((int64_t)64, n - r0);
-        for (int k = 0; k < rows; k++) {
-            const int64_t b = __shfl(mb, k, 64), e = __shfl(me, k, 64);
-            for (int64_t p = b + lane; p < e; p += 64) rowA[p] = (int32_t)(r0 + k);
+        const unsigned g = lane >> 4, sub = lane & 15u;
+        for (int k0 = 0; k0 < rows; k0 += 4) {
+            const int k = k0 + (int)g;
+            const int64_t b = __shfl(mb, k & 63, 64), e = __shfl(me, k & 63, 64);
+            if (k < rows)
+                for (int64_t p = b + sub; p < e; p += 16) rowA[p] = (int32_t)(r0 + k);
         }
     }
 }
