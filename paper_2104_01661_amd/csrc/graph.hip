@@ -257,6 +257,8 @@ __global__ void k_window_rows(const int64_t *__restrict__ rp, int64_t n, int32_t
 // entry lies past them, as after a run of empty rows).  The lanes of one
 // row make one atomic.  (Contiguous runs of windows per wave, each found
 // by a search of the row offsets, took 343 us at 2^20 against 253 us.)
+constexpr int EMIT_ILP = 2;   // windows per wavefront in flight
+
 __global__ void k_emit_windows(const int32_t *__restrict__ wrow, const int32_t *__restrict__ ci,
                                const int64_t *__restrict__ rpA, int64_t n, const int32_t *__restrict__ inv,
                                int64_t nnz, unsigned long long *__restrict__ cur, int32_t *__restrict__ P)
@@ -265,45 +267,80 @@ __global__ void k_emit_windows(const int32_t *__restrict__ wrow, const int32_t *
     const int64_t nwin = (nnz + 63) >> 6;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t w = wave; w < nwin; w += nwaves) {
-        const int64_t e = (w << 6) + lane;
-        int32_t u = -1;
-        int64_t ub = 0;
-        bool need = e < nnz;
-        int64_t rc = wrow[w];
-        while (__ballot(need)) {
-            const int64_t ri = rc + 1 + lane;
-            const int64_t end = ri <= n ? rpA[ri] : INT64_MAX;   // end of row rc + lane
-            const int64_t start0 = rpA[rc];
-            // rows of this chunk ending at or before e
-            int cntr = 0;
+    // rows of the 64 after rc whose end is at or before e; sets u / ub of
+    // a lane whose row is among them
+    auto search = [&](int64_t rc, int64_t end, int64_t start0, int64_t e, bool &need, int32_t &u, int64_t &ub) {
+        int cntr = 0;
 #pragma unroll
-            for (int sft = 32; sft >= 1; sft >>= 1) {
-                const int64_t y = (int64_t)__shfl((long long)end, cntr + sft - 1, 64);
-                if (y <= e) cntr += sft;
-            }
-            const int64_t last = (int64_t)__shfl((long long)end, 63, 64);
-            if (cntr == 63 && last <= e) cntr = 64;
-            const int64_t prev = (int64_t)__shfl((long long)end, cntr > 0 ? cntr - 1 : 0, 64);
-            if (need && cntr < 64) {
-                u = (int32_t)(rc + cntr);
-                ub = cntr > 0 ? prev : start0;
-                need = false;
-            }
-            rc += 64;
+        for (int sft = 32; sft >= 1; sft >>= 1) {
+            const int64_t y = (int64_t)__shfl((long long)end, cntr + sft - 1, 64);
+            if (y <= e) cntr += sft;
         }
-        int32_t iv = 0;
-        bool take = false;
-        if (u >= 0) {
-            iv = inv[ci[e]];
-            take = iv < inv[u];
+        const int64_t last = (int64_t)__shfl((long long)end, 63, 64);
+        if (cntr == 63 && last <= e) cntr = 64;
+        const int64_t prev = (int64_t)__shfl((long long)end, cntr > 0 ? cntr - 1 : 0, 64);
+        if (need && cntr < 64) {
+            u = (int32_t)(rc + cntr);
+            ub = cntr > 0 ? prev : start0;
+            need = false;
         }
-        const WaveRun wr = wave_run(u);
-        const uint64_t t = __ballot(take) & wr.run;
-        unsigned long long base = 0;
-        if (lane == wr.head && t) base = atomicAdd(&cur[u], (unsigned long long)__popcll(t));
-        base = (unsigned long long)__shfl((long long)base, (int)wr.head, 64);
-        if (take) P[ub + (int64_t)base + __popcll(t & wr.before)] = iv;
+    };
+    for (int64_t w0 = wave; w0 < nwin; w0 += EMIT_ILP * nwaves) {
+        int64_t e[EMIT_ILP], rc[EMIT_ILP], ub[EMIT_ILP], end[EMIT_ILP], start0[EMIT_ILP];
+        int32_t u[EMIT_ILP];
+        bool need[EMIT_ILP];
+        // the windows' first search rounds: their loads are independent
+#pragma unroll
+        for (int k = 0; k < EMIT_ILP; k++) {
+            const int64_t w = w0 + k * nwaves;
+            e[k] = (w << 6) + lane;
+            u[k] = -1;
+            ub[k] = 0;
+            need[k] = w < nwin && e[k] < nnz;
+            rc[k] = w < nwin ? wrow[w] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < EMIT_ILP; k++) {
+            const int64_t ri = rc[k] + 1 + lane;
+            end[k] = ri <= n ? rpA[ri] : INT64_MAX;   // end of row rc + lane
+            start0[k] = rc[k] < n ? rpA[rc[k]] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < EMIT_ILP; k++) {
+            search(rc[k], end[k], start0[k], e[k], need[k], u[k], ub[k]);
+            rc[k] += 64;
+            // a window that spans more than 64 rows searches on
+            while (__ballot(need[k])) {
+                const int64_t ri = rc[k] + 1 + lane;
+                const int64_t en = ri <= n ? rpA[ri] : INT64_MAX;
+                search(rc[k], en, rpA[rc[k]], e[k], need[k], u[k], ub[k]);
+                rc[k] += 64;
+            }
+        }
+        int32_t cj[EMIT_ILP], iv[EMIT_ILP];
+        bool take[EMIT_ILP];
+#pragma unroll
+        for (int k = 0; k < EMIT_ILP; k++) cj[k] = u[k] >= 0 ? ci[e[k]] : 0;
+#pragma unroll
+        for (int k = 0; k < EMIT_ILP; k++) {
+            iv[k] = u[k] >= 0 ? inv[cj[k]] : 0;
+            take[k] = u[k] >= 0 && iv[k] < inv[u[k]];
+        }
+        WaveRun wr[EMIT_ILP];
+        uint64_t t[EMIT_ILP];
+        unsigned long long base[EMIT_ILP];
+#pragma unroll
+        for (int k = 0; k < EMIT_ILP; k++) {
+            wr[k] = wave_run(u[k]);
+            t[k] = __ballot(take[k]) & wr[k].run;
+            base[k] = 0;
+            if (lane == wr[k].head && t[k]) base[k] = atomicAdd(&cur[u[k]], (unsigned long long)__popcll(t[k]));
+        }
+#pragma unroll
+        for (int k = 0; k < EMIT_ILP; k++) {
+            base[k] = (unsigned long long)__shfl((long long)base[k], (int)wr[k].head, 64);
+            if (take[k]) P[ub[k] + (int64_t)base[k] + __popcll(t[k] & wr[k].before)] = iv[k];
+        }
     }
 }
 
