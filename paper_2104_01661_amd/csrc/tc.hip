@@ -134,15 +134,18 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_hot(const int32_t *__restri
                                                          unsigned long long *__restrict__ cur,
                                                          unsigned *__restrict__ boff, unsigned long long *__restrict__ bw)
 {
+    // hot row x: its counter, and its length and hub bitmap words as two
+    // 16-bit halves (0xFFFF: read the global value).  32 KiB of LDS keep
+    // four workgroups on a CU, so the whole grid is resident at once.
     __shared__ unsigned hot[PLAN_HOT];
-    __shared__ unsigned hlen[PLAN_HOT];
-    __shared__ unsigned hw[PLAN_HOT];
+    __shared__ unsigned hmeta[PLAN_HOT];
     const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
     const int64_t nh = n < PLAN_HOT ? n : PLAN_HOT;
     for (int x = threadIdx.x; x < PLAN_HOT; x += PLAN_BLOCK) {
         hot[x] = 0u;
-        hlen[x] = x < nh ? (unsigned)(rowpk[x] & lmask) : 0u;
-        hw[x] = x < nhub ? hubw[x] : 0u;
+        const uint64_t len = x < nh ? (rowpk[x] & lmask) : 0u;
+        const unsigned words = x < nhub ? hubw[x] : 0u;
+        hmeta[x] = (unsigned)min(len, (uint64_t)0xFFFF) | min(words, 0xFFFFu) << 16;
     }
     __syncthreads();
     const unsigned lane = lane_id();
@@ -158,8 +161,13 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_hot(const int32_t *__restri
             const uint64_t pk = rowpk[i];
             const int64_t p = e - (int64_t)(pk >> TC_PLAN_LEN_BITS), len = (int64_t)(pk & lmask);
             if (j < PLAN_HOT) {
-                const int64_t lj = hlen[j];
-                if (lj > 0 && p > 0 && (j < nhub ? plan_hub_b(p, lj, hw[j]) : lj > p)) atomicAdd(&hot[j], 1u);
+                const unsigned m = hmeta[j];
+                const int64_t lj = (m & 0xFFFFu) != 0xFFFFu ? (int64_t)(m & 0xFFFFu) : (int64_t)(rowpk[j] & lmask);
+                if (lj > 0 && p > 0) {
+                    bool b_side = lj > p;
+                    if (j < nhub) b_side = plan_hub_b(p, lj, (m >> 16) != 0xFFFFu ? (int64_t)(m >> 16) : hubw[j]);
+                    if (b_side) atomicAdd(&hot[j], 1u);
+                }
             }
             if (j >= nhub && tc_bitmap_pair(j, p)) v = (unsigned)((j + 31) >> 5);   // hub pairs: plan_hub_b
             if (p == len - 1 && i <= TC_BM_IDS)   // the row's last (largest) id
