@@ -208,7 +208,9 @@ __device__ __forceinline__ void bfs_pull(const BfsDev &d, int par)
     }
 }
 
-// The level's expansion in one launch: pull, or push over the frontier
+// The level's expansion in one launch (2048 workgroups at most: all of
+// them resident at once, and a level past the end dispatches half as many
+// as a grid of one thread per vertex): pull, or push over the frontier
 // list and then over the hub chunks marked in the frontier bitmap.  One
 // kernel node per level instead of three: a node whose work the direction
 // skips still costs its dispatch (a few microseconds at thousands of
@@ -282,7 +284,7 @@ __global__ void k_level_to_i64(const int32_t *__restrict__ in, int64_t *__restri
 // One level on stream s with buffer parity par.
 int enqueue_level(BfsDev *d, int par, int64_t n, int64_t W, hipStream_t s, char *msg)
 {
-    hipLaunchKernelGGL(k_bfs_expand, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, d, par);
+    hipLaunchKernelGGL(k_bfs_expand, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, d, par);
     hipLaunchKernelGGL(k_bfs_compact, dim3(grid_for(W, 256, 1 << 30)), dim3(256), 0, s, d, par);
     hipLaunchKernelGGL(k_bfs_decide, dim3(1), dim3(64), 0, s, d);
     LAUNCH_CHECK();
