@@ -22,6 +22,7 @@ namespace {
 
 constexpr int BFS_ALPHA = 14;
 constexpr int BFS_BETA = 24;
+constexpr unsigned BFS_EXPAND_MAX = 2048;   // expansion workgroups at most
 
 __device__ __forceinline__ bool bit_test(const uint32_t *bm, int64_t v)
 {
@@ -52,6 +53,10 @@ struct BfsDev {
     // unexplored degree sum, and the compaction counters of the last level
     int32_t lev, pull, done, pad_;
     int32_t *done_host;       // pinned host word set when the search ends
+    // a pull level's new frontier per expansion workgroup: size in blk[g],
+    // degree sum in blk[BFS_EXPAND_MAX + g], for the eg workgroups
+    unsigned long long *blk;
+    int64_t eg;
     int64_t nq, mf, mu;
     unsigned long long nnext, enext;
 };
@@ -179,6 +184,13 @@ __device__ __forceinline__ void bfs_pull(const BfsDev &d, int par)
     uint32_t *next_bm = d.bm[par ^ 1];
     int64_t *parent = (int64_t *)d.parent;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    __shared__ unsigned long long s_cnt, s_deg;
+    if (threadIdx.x == 0) {
+        s_cnt = 0;
+        s_deg = 0;
+    }
+    __syncthreads();
+    unsigned long long cnt = 0, deg = 0;
     // every lane runs the same trip count, so the ballot sees the whole wave
     for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x; v0 < n; v0 += stride) {
         const int64_t v = v0 + threadIdx.x;
@@ -197,14 +209,35 @@ __device__ __forceinline__ void bfs_pull(const BfsDev &d, int par)
         if (par_v >= 0) {
             parent[v] = par_v;
             d.level[v] = lev;
+            cnt += 1;
+            deg += (unsigned long long)(d.rp[v + 1] - d.rp[v]);
         }
         // the wave's 64 vertices are 64-aligned: they own two bitmap words,
-        // which no other wave writes in this kernel
+        // which no other wave writes or reads in this kernel.  Every word of
+        // the next bitmap is written (so it needs no clearing), and the new
+        // vertices join the visited set here.
         const uint64_t m = __ballot(par_v >= 0);
         const unsigned lane = lane_id();
         const int64_t w0 = (v - lane) >> 5;
-        if (lane == 0 && (uint32_t)m) next_bm[w0] = (uint32_t)m;
-        if (lane == 32 && (uint32_t)(m >> 32)) next_bm[w0 + 1] = (uint32_t)(m >> 32);
+        if ((lane == 0 || lane == 32) && w0 + (lane >> 5) < d.W) {
+            const int64_t w = w0 + (lane >> 5);
+            const uint32_t x = (uint32_t)(m >> lane);
+            next_bm[w] = x;
+            if (x) d.visited[w] |= x;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        cnt += __shfl_xor(cnt, o, 64);
+        deg += __shfl_xor(deg, o, 64);
+    }
+    if (lane_id() == 0 && cnt) {
+        atomicAdd(&s_cnt, cnt);
+        atomicAdd(&s_deg, deg);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        d.blk[blockIdx.x] = s_cnt;
+        d.blk[BFS_EXPAND_MAX + blockIdx.x] = s_deg;
     }
 }
 
@@ -243,7 +276,40 @@ __global__ __launch_bounds__(256) void k_bfs_compact(BfsDev *dp, int par)
     const BfsDev &d = *dp;
     if (d.done) return;
     __shared__ unsigned scan[256];
-    __shared__ unsigned long long base_s, deg_s;
+    __shared__ unsigned long long base_s, deg_s, nq_s;
+    if (d.pull) {
+        // After a pull level: its workgroups counted the new frontier.  When
+        // the next level pulls again (the test of bfs_decide), it needs
+        // neither the list nor a cleared bitmap: skip the pass.
+        unsigned long long c = 0, g = 0;
+        for (int64_t b = threadIdx.x; b < d.eg; b += blockDim.x) {
+            c += d.blk[b];
+            g += d.blk[BFS_EXPAND_MAX + b];
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            c += __shfl_xor(c, o, 64);
+            g += __shfl_xor(g, o, 64);
+        }
+        if (threadIdx.x == 0) {
+            nq_s = 0;
+            deg_s = 0;
+        }
+        __syncthreads();
+        if (lane_id() == 0 && c) {
+            atomicAdd(&nq_s, c);
+            atomicAdd(&deg_s, g);
+        }
+        __syncthreads();
+        const int64_t nq = (int64_t)nq_s;
+        if (nq > 0 && nq >= d.n / BFS_BETA) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                dp->nnext = nq_s;
+                dp->enext = deg_s;
+            }
+            return;
+        }
+        __syncthreads();
+    }
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t *next_bm = d.bm[par ^ 1];
     int32_t *next_list = d.list[par ^ 1];
@@ -284,7 +350,7 @@ __global__ void k_level_to_i64(const int32_t *__restrict__ in, int64_t *__restri
 // One level on stream s with buffer parity par.
 int enqueue_level(BfsDev *d, int par, int64_t n, int64_t W, hipStream_t s, char *msg)
 {
-    hipLaunchKernelGGL(k_bfs_expand, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, d, par);
+    hipLaunchKernelGGL(k_bfs_expand, dim3(grid_for(n, 256, BFS_EXPAND_MAX)), dim3(256), 0, s, d, par);
     hipLaunchKernelGGL(k_bfs_compact, dim3(grid_for(W, 256, 1 << 30)), dim3(256), 0, s, d, par);
     hipLaunchKernelGGL(k_bfs_decide, dim3(1), dim3(64), 0, s, d);
     LAUNCH_CHECK();
@@ -359,7 +425,9 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
     const int64_t W = (n + 31) / 32;
     int32_t *lev32 = (int32_t *)ws_get(ctx, WS_BFS_A, sizeof(int32_t) * n);
     int32_t *lists = (int32_t *)ws_get(ctx, WS_BFS_B, sizeof(int32_t) * 2 * n);
-    uint32_t *bms = (uint32_t *)ws_get(ctx, WS_BFS_C, sizeof(uint32_t) * 3 * W);
+    // three bitmaps, then the pull levels' per-workgroup counters
+    const size_t bm_bytes = (sizeof(uint32_t) * 3 * W + 255) & ~(size_t)255;
+    uint32_t *bms = (uint32_t *)ws_get(ctx, WS_BFS_C, bm_bytes + sizeof(unsigned long long) * 2 * BFS_EXPAND_MAX);
     BfsDev *d = (BfsDev *)ws_get(ctx, WS_BFS_D, sizeof(BfsDev));
     int64_t *parent_scratch = nullptr;
     if (!parent_out) parent_scratch = (int64_t *)ws_get(ctx, WS_BFS_E, sizeof(int64_t) * n);
@@ -401,6 +469,8 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
     h.list[0] = lists;
     h.list[1] = lists + n;
     h.ch = ch;
+    h.blk = (unsigned long long *)((char *)bms + bm_bytes);
+    h.eg = grid_for(n, 256, BFS_EXPAND_MAX);
     h.any_parent = (flags & LAGR_BFS_ANY_PARENT) ? 1 : 0;
     h.push_only = (flags & LAGR_BFS_PUSH_ONLY) ? 1 : 0;
     h.lev = 0;
