@@ -235,7 +235,11 @@ __global__ void k_window_rows(const int64_t *__restrict__ rp, int64_t n, int32_t
     for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); r0 < n; r0 += step) {
         const int64_t r = r0 + lane;
         const int64_t mb = r < n ? (rp[r] + 63) >> 6 : 0, me = r < n ? (rp[r + 1] + 63) >> 6 : 0;
-        uint64_t todo = __ballot(me > mb);
+        // a row that starts at most 4 windows writes them itself (nearly
+        // every row); the wave writes the longer ones together
+        if (me - mb <= 4)
+            for (int64_t w = mb; w < me; w++) wrow[w] = (int32_t)r;
+        uint64_t todo = __ballot(me - mb > 4);
         while (todo) {
             const int k = __ffsll((unsigned long long)todo) - 1;
             todo &= todo - 1;
