@@ -244,11 +244,9 @@ __device__ __forceinline__ unsigned long long relax_group(const SsspDev &d, cons
 }
 
 // Light phase: groups of frontier vertices per wavefront (rows of at most
-// GRAPH_LONG_ROW entries; longer rows in k_sssp_light_chunks).
-__global__ __launch_bounds__(256) void k_sssp_light(SsspDev *dp, int par)
+// GRAPH_LONG_ROW entries; longer rows in sssp_light_chunks).
+__device__ __forceinline__ void sssp_light(const SsspDev &d, int par)
 {
-    const SsspDev &d = *dp;
-    if (d.done || d.phase != SSSP_LIGHT) return;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const unsigned lane = lane_id();
@@ -267,15 +265,24 @@ __global__ __launch_bounds__(256) void k_sssp_light(SsspDev *dp, int par)
         (void)relax_group<false>(d, d.list[par], f0, g, nq, lane, d.bm[par ^ 1]);
 }
 
-__global__ __launch_bounds__(256) void k_sssp_light_chunks(SsspDev *dp, int par)
+__device__ __forceinline__ void sssp_light_chunks(const SsspDev &d, int par)
 {
-    const SsspDev &d = *dp;
-    if (d.done || d.phase != SSSP_LIGHT) return;
     const unsigned lane = lane_id();
     uint32_t *next_bm = d.bm[par ^ 1];
     for_marked_chunks(d.ch, d.bm[par], [&](int32_t u, int64_t b, int64_t e) {
         (void)relax_range<false>(d, as_f64(d.dist[u]), b, e, lane, next_bm);
     });
+}
+
+// One light step in one launch: the frontier's short rows, then the chunks
+// of its long rows (a kernel node with nothing to do still costs its
+// dispatch).
+__global__ __launch_bounds__(256) void k_sssp_light(SsspDev *dp, int par)
+{
+    const SsspDev &d = *dp;
+    if (d.done || d.phase != SSSP_LIGHT) return;
+    sssp_light(d, par);
+    sssp_light_chunks(d, par);
 }
 
 // A 32-vertex word per thread: the workgroup scans the words' popcounts,
@@ -339,8 +346,9 @@ __global__ __launch_bounds__(256) void k_sssp_settled(SsspDev *dp)
     block_min_to(far, &dp->nmin);
 }
 
-// Heavy phase: groups of settled vertices per wavefront (short rows; long
-// rows in k_sssp_heavy_chunks); improved distances fold into nmin.
+// Heavy phase in one launch: groups of settled vertices per wavefront
+// (short rows), then the chunks of the long rows; improved distances fold
+// into nmin.
 __global__ __launch_bounds__(256) void k_sssp_heavy(SsspDev *dp)
 {
     const SsspDev &d = *dp;
@@ -365,15 +373,6 @@ __global__ __launch_bounds__(256) void k_sssp_heavy(SsspDev *dp)
             far = x < far ? x : far;
         }
     }
-    block_min_to(far, &dp->nmin);
-}
-
-__global__ __launch_bounds__(256) void k_sssp_heavy_chunks(SsspDev *dp)
-{
-    const SsspDev &d = *dp;
-    if (d.done || !d.heavy_now) return;
-    const unsigned lane = lane_id();
-    unsigned long long far = SSSP_INF;
     for_marked_chunks(d.ch, d.sbm, [&](int32_t u, int64_t b, int64_t e) {
         const unsigned long long x = relax_range<true>(d, as_f64(d.dist[u]), b, e, lane, nullptr);
         far = x < far ? x : far;
@@ -440,11 +439,9 @@ int enqueue_step(SsspDev *d, int par, int64_t W, int num_cus, hipStream_t s, cha
     const unsigned wgrid = grid_for(W, 256, 1 << 30);
     hipLaunchKernelGGL(k_sssp_decide, dim3(1), dim3(64), 0, s, d);
     hipLaunchKernelGGL(k_sssp_light, dim3((unsigned)(num_cus * 8)), dim3(256), 0, s, d, par);
-    hipLaunchKernelGGL(k_sssp_light_chunks, dim3((unsigned)(num_cus * 2)), dim3(256), 0, s, d, par);
     hipLaunchKernelGGL(k_sssp_compact, dim3(wgrid), dim3(256), 0, s, d, par);
     hipLaunchKernelGGL(k_sssp_settled, dim3(wgrid), dim3(256), 0, s, d);
     hipLaunchKernelGGL(k_sssp_heavy, dim3((unsigned)(num_cus * 8)), dim3(256), 0, s, d);
-    hipLaunchKernelGGL(k_sssp_heavy_chunks, dim3((unsigned)(num_cus * 2)), dim3(256), 0, s, d);
     hipLaunchKernelGGL(k_sssp_next, dim3(1), dim3(64), 0, s, d);
     hipLaunchKernelGGL(k_sssp_bucket, dim3(wgrid), dim3(256), 0, s, d, par);
     LAUNCH_CHECK();
