@@ -310,10 +310,9 @@ __device__ __forceinline__ void block_list_words(uint32_t x, int64_t w, int32_t 
 
 // End of a light step: the next frontier from bm[par ^ 1] (its bits stay
 // for the next step's chunk kernel); the consumed bm[par] is cleared.
-__global__ __launch_bounds__(256) void k_sssp_compact(SsspDev *dp, int par)
+__device__ __forceinline__ void sssp_compact(SsspDev *dp, int par)
 {
     const SsspDev &d = *dp;
-    if (d.done || d.phase != SSSP_LIGHT) return;
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t x = w < d.W ? d.bm[par ^ 1][w] : 0u;
     if (w < d.W) d.bm[par][w] = 0u;
@@ -324,10 +323,9 @@ __global__ __launch_bounds__(256) void k_sssp_compact(SsspDev *dp, int par)
 // final once the light phase is over), as a bitmap and a list; and the
 // smallest t at or above hi (the next bucket, unless the heavy phase
 // lowers it).
-__global__ __launch_bounds__(256) void k_sssp_settled(SsspDev *dp)
+__device__ __forceinline__ void sssp_settled(SsspDev *dp)
 {
     const SsspDev &d = *dp;
-    if (d.done || !d.heavy_now) return;
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned long long lo = as_bits(d.lo), hi = as_bits(d.hi);
     uint32_t x = 0u;
@@ -344,6 +342,17 @@ __global__ __launch_bounds__(256) void k_sssp_settled(SsspDev *dp)
     }
     block_list_words(x, w, d.slist, &dp->nsettled);
     block_min_to(far, &dp->nmin);
+}
+
+// The bitmap pass of a step, one launch for both kinds (a step is either a
+// light one or the heavy one, never both): the next frontier after a light
+// step, or the settled set before the heavy phase.
+__global__ __launch_bounds__(256) void k_sssp_words(SsspDev *dp, int par)
+{
+    const SsspDev &d = *dp;
+    if (d.done) return;
+    if (d.phase == SSSP_LIGHT) sssp_compact(dp, par);
+    else if (d.heavy_now) sssp_settled(dp);
 }
 
 // Heavy phase in one launch: groups of settled vertices per wavefront
@@ -380,34 +389,34 @@ __global__ __launch_bounds__(256) void k_sssp_heavy(SsspDev *dp)
     block_min_to(far, &dp->nmin);
 }
 
-// After the heavy phase: the bucket of the smallest unsettled distance, or
-// the end of the search when no reached vertex is left unsettled.
-__global__ void k_sssp_next(SsspDev *d)
-{
-    if (threadIdx.x != 0 || d->done || !d->heavy_now) return;
-    if (d->nmin == SSSP_INF) {
-        d->done = 1;
-        return;
-    }
-    const double m = as_f64(d->nmin), delta = d->delta;
-    double b = floor(m / delta);
-    if (b * delta > m) b -= 1.0;
-    if ((b + 1.0) * delta <= m) b += 1.0;
-    d->bucket = (int64_t)b;
-    d->lo = b * delta;
-    d->hi = (b + 1.0) * delta;
-    d->phase = SSSP_LIGHT;
-    d->nnext = 0;
-}
-
-// First frontier of the new bucket: every vertex with lo <= t < hi, as
-// list[par ^ 1] and bitmap bm[par ^ 1] (every word is written).
+// After the heavy phase: the bucket of the smallest unsettled distance (or
+// the end of the search when no reached vertex is left unsettled) and its
+// vertices as the next frontier.  Every workgroup derives the bucket from
+// the final nmin itself; workgroup 0 records it.  (nnext is zero here: the
+// decision that started the heavy phase cleared it.)
 __global__ __launch_bounds__(256) void k_sssp_bucket(SsspDev *dp, int par)
 {
     const SsspDev &d = *dp;
     if (d.done || !d.heavy_now) return;
+    const unsigned long long nmin = d.nmin;
+    const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+    if (nmin == SSSP_INF) {
+        if (first) dp->done = 1;
+        return;
+    }
+    const double m = as_f64(nmin), delta = d.delta;
+    double bk = floor(m / delta);
+    if (bk * delta > m) bk -= 1.0;
+    if ((bk + 1.0) * delta <= m) bk += 1.0;
+    const double lod = bk * delta, hid = (bk + 1.0) * delta;
+    if (first) {
+        dp->bucket = (int64_t)bk;
+        dp->lo = lod;
+        dp->hi = hid;
+        dp->phase = SSSP_LIGHT;
+    }
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const unsigned long long lo = as_bits(d.lo), hi = as_bits(d.hi);
+    const unsigned long long lo = as_bits(lod), hi = as_bits(hid);
     uint32_t x = 0u;
     if (w < d.W) {
         const int64_t v0 = w * 32;
@@ -439,10 +448,8 @@ int enqueue_step(SsspDev *d, int par, int64_t W, int num_cus, hipStream_t s, cha
     const unsigned wgrid = grid_for(W, 256, 1 << 30);
     hipLaunchKernelGGL(k_sssp_decide, dim3(1), dim3(64), 0, s, d);
     hipLaunchKernelGGL(k_sssp_light, dim3((unsigned)(num_cus * 8)), dim3(256), 0, s, d, par);
-    hipLaunchKernelGGL(k_sssp_compact, dim3(wgrid), dim3(256), 0, s, d, par);
-    hipLaunchKernelGGL(k_sssp_settled, dim3(wgrid), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_sssp_words, dim3(wgrid), dim3(256), 0, s, d, par);
     hipLaunchKernelGGL(k_sssp_heavy, dim3((unsigned)(num_cus * 8)), dim3(256), 0, s, d);
-    hipLaunchKernelGGL(k_sssp_next, dim3(1), dim3(64), 0, s, d);
     hipLaunchKernelGGL(k_sssp_bucket, dim3(wgrid), dim3(256), 0, s, d, par);
     LAUNCH_CHECK();
     return LAGR_SUCCESS;
