@@ -49,12 +49,9 @@ __global__ void k_pr_init(const int64_t *__restrict__ rp, int64_t n, double damp
 
 // Rows of at most PR_THREAD_ROW in-edges: r(j) = teleport + sum in
 // ascending order.  Longer rows are left to the chunk kernels.
-__global__ __launch_bounds__(PR_BLOCK) void k_pr_rows(const int64_t *__restrict__ rpT,
-                                                      const int32_t *__restrict__ ciT, int64_t n, double teleport,
-                                                      const double *__restrict__ w, double *__restrict__ r,
-                                                      const PrDev *st)
+__device__ __forceinline__ void pr_rows(const int64_t *__restrict__ rpT, const int32_t *__restrict__ ciT, int64_t n,
+                                        double teleport, const double *__restrict__ w, double *__restrict__ r)
 {
-    if (st->done) return;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
          j += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = rpT[j], e = rpT[j + 1];
@@ -74,11 +71,9 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_rows(const int64_t *__restrict_
 
 // A chunk of a long row per wavefront: lane l adds entries l, l + 64, ...
 // in order, then a fixed butterfly adds the lanes.
-__global__ __launch_bounds__(PR_BLOCK) void k_pr_chunks(const int32_t *__restrict__ ciT, RowChunks ch,
-                                                        const double *__restrict__ w, double *__restrict__ part,
-                                                        const PrDev *st)
+__device__ __forceinline__ void pr_chunks(const int32_t *__restrict__ ciT, const RowChunks &ch,
+                                          const double *__restrict__ w, double *__restrict__ part)
 {
-    if (st->done) return;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const unsigned lane = lane_id();
@@ -96,6 +91,20 @@ __global__ __launch_bounds__(PR_BLOCK) void k_pr_chunks(const int32_t *__restric
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
         if (lane == 0) part[c] = s;
     }
+}
+
+// One gather pass per iteration: the chunks of the long rows (a wave
+// each), then the short rows (a lane each), in one launch, so the short
+// rows fill the machine while the chunk work drains.  Each row's and each
+// chunk's summation order is fixed, whatever the grid.
+__global__ __launch_bounds__(PR_BLOCK) void k_pr_gather(const int64_t *__restrict__ rpT,
+                                                        const int32_t *__restrict__ ciT, int64_t n, double teleport,
+                                                        const double *__restrict__ w, double *__restrict__ r,
+                                                        RowChunks ch, double *__restrict__ part, const PrDev *st)
+{
+    if (st->done) return;
+    pr_chunks(ciT, ch, w, part);
+    pr_rows(rpT, ciT, n, teleport, w, r);
 }
 
 // r(j) of a long row: its chunks' sums in chunk order (a row's chunks are
@@ -224,6 +233,7 @@ extern "C" int lagr_pagerank(lagr_vector *rank_out, int64_t *iters_out, const la
     const unsigned rgrid = grid_for(n, PR_BLOCK, 8192);
     const unsigned cgrid = grid_for(ch.n * 64, PR_BLOCK, 4096);
     const unsigned bgrid = grid_for(ch.n, PR_BLOCK, 1024);
+    const unsigned ggrid = rgrid > cgrid ? rgrid : cgrid;
     // r and t trade places every iteration; after k iterations the rank is
     // in r when k is even (counting from the buffer r starts in)
     double *cur = r, *prev = t;
@@ -232,11 +242,9 @@ extern "C" int lagr_pagerank(lagr_vector *rank_out, int64_t *iters_out, const la
     while (launched < itermax) {
         for (int g = 0; g < PR_GROUP && launched < itermax; g++, launched++) {
             std::swap(cur, prev);   // prev: the prior rank t; cur receives the new r
-            hipLaunchKernelGGL(k_pr_rows, dim3(rgrid), dim3(PR_BLOCK), 0, ctx->stream, AT->rowptr, AT->colidx, n,
-                               teleport, w, cur, st);
+            hipLaunchKernelGGL(k_pr_gather, dim3(ggrid), dim3(PR_BLOCK), 0, ctx->stream, AT->rowptr, AT->colidx,
+                               n, teleport, w, cur, ch, part, st);
             if (ch.n > 0) {
-                hipLaunchKernelGGL(k_pr_chunks, dim3(cgrid), dim3(PR_BLOCK), 0, ctx->stream, AT->colidx, ch, w,
-                                   part, st);
                 hipLaunchKernelGGL(k_pr_combine, dim3(bgrid), dim3(PR_BLOCK), 0, ctx->stream, AT->rowptr, ch,
                                    teleport, part, cur, st);
             }
