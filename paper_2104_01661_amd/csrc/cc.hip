@@ -34,9 +34,8 @@ __global__ void k_cc_init(int64_t n, int32_t *__restrict__ f, int32_t *__restric
 // mngf(u) = min(mngf(u), min over neighbours v of gf(v)) for rows of at most
 // CC_THREAD_ROW entries (one lane each, loads batched); longer rows are left
 // to k_cc_mngf_chunks.
-__global__ __launch_bounds__(CC_BLOCK) void k_cc_mngf(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                      int64_t n, const int32_t *__restrict__ gf,
-                                                      int32_t *__restrict__ mngf)
+__device__ __forceinline__ void cc_mngf_rows(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci, int64_t n,
+                                             const int32_t *__restrict__ gf, int32_t *__restrict__ mngf)
 {
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
          u += (int64_t)gridDim.x * blockDim.x) {
@@ -56,9 +55,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_cc_mngf(const int64_t *__restrict_
 }
 
 // A chunk of a long row per wavefront: the wave's minimum, one atomic.
-__global__ __launch_bounds__(CC_BLOCK) void k_cc_mngf_chunks(const int32_t *__restrict__ ci, RowChunks ch,
-                                                             const int32_t *__restrict__ gf,
-                                                             int32_t *__restrict__ mngf)
+__device__ __forceinline__ void cc_mngf_chunks(const int32_t *__restrict__ ci, const RowChunks &ch,
+                                               const int32_t *__restrict__ gf, int32_t *__restrict__ mngf)
 {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
@@ -69,6 +67,16 @@ __global__ __launch_bounds__(CC_BLOCK) void k_cc_mngf_chunks(const int32_t *__re
         for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
         if (lane == 0 && m < INT32_MAX) atomicMin(&mngf[ch.row[c]], m);
     }
+}
+
+// One launch per side: the long rows' chunks (a wave each), then the short
+// rows (a lane each); they touch disjoint entries of mngf.
+__global__ __launch_bounds__(CC_BLOCK) void k_cc_mngf(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                      int64_t n, const int32_t *__restrict__ gf,
+                                                      int32_t *__restrict__ mngf, RowChunks ch)
+{
+    cc_mngf_chunks(ci, ch, gf, mngf);
+    cc_mngf_rows(rp, ci, n, gf, mngf);
 }
 
 // Steps 1 to 3: f(x(u)) = min(f(x(u)), mngf(u)); f(u) = min(f(u), mngf(u), gf(u)).
@@ -180,11 +188,9 @@ extern "C" int lagr_cc(lagr_vector *component, int64_t *iters_out, const lagr_gr
         iters++;
         for (int k = 0; k < 2; k++) {
             if (!sides[k]) continue;
-            hipLaunchKernelGGL(k_cc_mngf, dim3(vgrid), dim3(CC_BLOCK), 0, ctx->stream, sides[k]->rowptr,
-                               sides[k]->colidx, n, gf, mngf);
-            if (chs[k].n > 0)
-                hipLaunchKernelGGL(k_cc_mngf_chunks, dim3(grid_for(chs[k].n * 64, CC_BLOCK, 4096)), dim3(CC_BLOCK),
-                                   0, ctx->stream, sides[k]->colidx, chs[k], gf, mngf);
+            const unsigned cgrid = chs[k].n > 0 ? grid_for(chs[k].n * 64, CC_BLOCK, 4096) : 0u;
+            hipLaunchKernelGGL(k_cc_mngf, dim3(vgrid > cgrid ? vgrid : cgrid), dim3(CC_BLOCK), 0, ctx->stream,
+                               sides[k]->rowptr, sides[k]->colidx, n, gf, mngf, chs[k]);
         }
         hipLaunchKernelGGL(k_cc_hook, dim3(vgrid), dim3(CC_BLOCK), 0, ctx->stream, n, x, mngf, gf, f);
         CC_TRY(fill_i64(ctx, (int64_t *)changed, 1, 0, msg));
