@@ -128,7 +128,7 @@ __device__ __forceinline__ double gather_hits(uint64_t hits, int32_t u, uint64_t
 
 // Pull: one wave per active vertex (rows of at most BC_LONG neighbours);
 // writes next[v] (zero on entry) and sigma of the lanes it reaches.
-__global__ __launch_bounds__(256) void k_bc_pull(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+__device__ __forceinline__ void bc_pull_rows(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                                  const int32_t *__restrict__ act, int64_t na,
                                                  const uint64_t *__restrict__ cur, uint64_t *__restrict__ next,
                                                  const uint64_t *__restrict__ unvis, double *__restrict__ sigma)
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_bc_pull(const int64_t *__restrict__ rp,
     for (int64_t q = wave; q < na; q += nw) {
         const int64_t v = act[q];
         const int64_t b = rp[v], e = rp[v + 1];
-        if (e - b > BC_LONG) continue;   // k_bc_forward_chunks
+        if (e - b > BC_LONG) continue;   // bc_forward_chunks
         const uint64_t uv = unvis[v];
         double acc = 0.0;
         for (int64_t p0 = b; p0 < e; p0 += 64) {
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(256) void k_bc_compact(const int64_t *__restrict__ 
 
 // Backward targets: one wave per vertex of level i-1's list (rows of at
 // most BC_LONG neighbours).
-__global__ __launch_bounds__(256) void k_bc_backward(const int64_t *__restrict__ rp,
+__device__ __forceinline__ void bc_backward_rows(const int64_t *__restrict__ rp,
                                                      const int32_t *__restrict__ ci,
                                                      const int32_t *__restrict__ tlist, int64_t nt,
                                                      const uint64_t *__restrict__ at_i,   // depth i
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(256) void k_bc_backward(const int64_t *__restrict__
     for (int64_t q = wave; q < nt; q += nw) {
         const int64_t v = tlist[q];
         const int64_t b = rp[v], e = rp[v + 1];
-        if (e - b > BC_LONG) continue;   // k_bc_backward_chunks
+        if (e - b > BC_LONG) continue;   // bc_backward_chunks
         const uint64_t dm = at_im1[v];
         double acc = 0.0;
         if (has_deeper) {
@@ -358,7 +358,7 @@ __device__ __forceinline__ double gather_lanes(const int32_t *__restrict__ ci, i
     return acc;
 }
 
-__global__ __launch_bounds__(256) void k_bc_forward_chunks(const int32_t *__restrict__ ci, RowChunks ch,
+__device__ __forceinline__ void bc_forward_chunks(const int32_t *__restrict__ ci, const RowChunks &ch,
                                                            const uint64_t *__restrict__ cur,
                                                            const uint64_t *__restrict__ unvis,
                                                            const double *__restrict__ sigma,
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(256) void k_bc_forward_combine(const int64_t *__res
     }
 }
 
-__global__ __launch_bounds__(256) void k_bc_backward_chunks(const int32_t *__restrict__ ci, RowChunks ch,
+__device__ __forceinline__ void bc_backward_chunks(const int32_t *__restrict__ ci, const RowChunks &ch,
                                                             const uint64_t *__restrict__ at_i,
                                                             const uint64_t *__restrict__ at_im1,
                                                             const double *__restrict__ W,
@@ -411,6 +411,35 @@ __global__ __launch_bounds__(256) void k_bc_backward_chunks(const int32_t *__res
         if (dm == 0) continue;
         partial[c * 64 + lane] = gather_lanes(ci, ch.beg[c], ch.end[c], at_i, dm, W, lane);
     }
+}
+
+// A pull level in one launch: the hub rows' chunks (a wave each, into
+// partial), then the short rows.  The chunks read sigma of frontier
+// vertices; the short rows write sigma of unvisited ones: for each source
+// lane the two sets are disjoint.
+__global__ __launch_bounds__(256) void k_bc_pull(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                 const int32_t *__restrict__ act, int64_t na,
+                                                 const uint64_t *__restrict__ cur, uint64_t *__restrict__ next,
+                                                 const uint64_t *__restrict__ unvis, double *sigma, RowChunks ch,
+                                                 double *__restrict__ partial)
+{
+    bc_forward_chunks(ci, ch, cur, unvis, sigma, partial);
+    bc_pull_rows(rp, ci, act, na, cur, next, unvis, sigma);
+}
+
+// A backward level in one launch: the hub rows' chunks (with has_chunks),
+// then the short rows.  Both read W of depth-i vertices; the short rows
+// write W of depth-(i-1) ones: for each source lane the sets are disjoint.
+__global__ __launch_bounds__(256) void k_bc_backward(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                     const int32_t *__restrict__ tlist, int64_t nt,
+                                                     const uint64_t *__restrict__ at_i,
+                                                     const uint64_t *__restrict__ at_im1, int has_deeper,
+                                                     int gshift, const double *__restrict__ sigma, double *W,
+                                                     double *__restrict__ centrality, RowChunks ch, int has_chunks,
+                                                     double *__restrict__ partial)
+{
+    if (has_chunks) bc_backward_chunks(ci, ch, at_i, at_im1, W, partial);
+    bc_backward_rows(rp, ci, tlist, nt, at_i, at_im1, has_deeper, gshift, sigma, W, centrality);
 }
 
 __global__ __launch_bounds__(256) void k_bc_backward_combine(const int64_t *__restrict__ rp, RowChunks ch,
@@ -735,15 +764,12 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
                     BC_LAUNCHED();
                 }
             } else if (na > 0) {
+                const unsigned pg = chT.n > 0 && cblocksT > wgrid(na) ? cblocksT : wgrid(na);
                 TIMED(ctx, "bc_forward",
-                      hipLaunchKernelGGL(k_bc_pull, dim3(wgrid(na)), dim3(256), 0, ctx->stream, AT->rowptr,
-                                         AT->colidx, act_cur, na, levels(depth), next, unvis, sigma));
+                      hipLaunchKernelGGL(k_bc_pull, dim3(pg), dim3(256), 0, ctx->stream, AT->rowptr, AT->colidx,
+                                         act_cur, na, levels(depth), next, unvis, sigma, chT, partial));
                 BC_LAUNCHED();
                 if (chT.n > 0) {
-                    TIMED(ctx, "bc_forward_chunks",
-                          hipLaunchKernelGGL(k_bc_forward_chunks, dim3(cblocksT), dim3(256), 0, ctx->stream,
-                                             AT->colidx, chT, levels(depth), unvis, sigma, partial));
-                    BC_LAUNCHED();
                     hipLaunchKernelGGL(k_bc_forward_combine, dim3(cblocksT), dim3(256), 0, ctx->stream,
                                        AT->rowptr, chT, partial, next, unvis, sigma);
                     BC_LAUNCHED();
@@ -759,19 +785,14 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
             const int has_deeper = i <= depth ? 1 : 0;
             const uint64_t *at_i = has_deeper ? levels(i) : levels(i - 1);
             const int64_t nt = nlev[i - 1];
+            const int has_chunks = ch.n > 0 && has_deeper ? 1 : 0;
+            const unsigned bg = has_chunks && cblocks > wgrid(nt) ? cblocks : wgrid(nt);
             TIMED(ctx, "bc_backward",
-                  hipLaunchKernelGGL(k_bc_backward, dim3(wgrid(nt)), dim3(256), 0, ctx->stream, A->rowptr,
-                                     A->colidx, lists(i - 1), nt, at_i, levels(i - 1), has_deeper, gshift,
-                                     sigma, Wv, cent));
+                  hipLaunchKernelGGL(k_bc_backward, dim3(bg), dim3(256), 0, ctx->stream, A->rowptr, A->colidx,
+                                     lists(i - 1), nt, at_i, levels(i - 1), has_deeper, gshift, sigma, Wv, cent,
+                                     ch, has_chunks, partial));
             BC_LAUNCHED();
             if (ch.n > 0) {
-                if (has_deeper) {
-                    TIMED(ctx, "bc_backward_chunks",
-                          hipLaunchKernelGGL(k_bc_backward_chunks, dim3(cblocks), dim3(256), 0,
-                                             ctx->stream, A->colidx, ch, at_i, levels(i - 1), Wv,
-                                             partial));
-                    BC_LAUNCHED();
-                }
                 hipLaunchKernelGGL(k_bc_backward_combine, dim3(cblocks), dim3(256), 0, ctx->stream,
                                    A->rowptr, ch, levels(i - 1), has_deeper, gshift, partial, sigma,
                                    Wv, cent);
