@@ -186,7 +186,7 @@ __device__ __forceinline__ void bc_push_range(const int32_t *__restrict__ ci, in
 }
 
 // Push: one wave per frontier vertex (rows of at most BC_LONG neighbours).
-__global__ __launch_bounds__(256) void k_bc_push(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+__device__ __forceinline__ void bc_push_rows(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                                  const int32_t *__restrict__ front, int64_t nf,
                                                  const uint64_t *__restrict__ cur, uint64_t *__restrict__ next,
                                                  const uint64_t *__restrict__ unvis, double *__restrict__ sigma)
@@ -197,13 +197,13 @@ __global__ __launch_bounds__(256) void k_bc_push(const int64_t *__restrict__ rp,
     for (int64_t q = wave; q < nf; q += nw) {
         const int64_t u = front[q];
         const int64_t b = rp[u], e = rp[u + 1];
-        if (e - b > BC_LONG) continue;   // k_bc_push_chunks
+        if (e - b > BC_LONG) continue;   // bc_push_chunks
         bc_push_range(ci, b, e, cur[u], sigma[u * 64 + lane], unvis, sigma, next, lane);
     }
 }
 
 // Push for the frontier's hub vertices, one wave per chunk.
-__global__ __launch_bounds__(256) void k_bc_push_chunks(const int32_t *__restrict__ ci, RowChunks ch,
+__device__ __forceinline__ void bc_push_chunks(const int32_t *__restrict__ ci, const RowChunks &ch,
                                                         const uint64_t *__restrict__ cur,
                                                         uint64_t *__restrict__ next,
                                                         const uint64_t *__restrict__ unvis,
@@ -411,6 +411,18 @@ __device__ __forceinline__ void bc_backward_chunks(const int32_t *__restrict__ c
         if (dm == 0) continue;
         partial[c * 64 + lane] = gather_lanes(ci, ch.beg[c], ch.end[c], at_i, dm, W, lane);
     }
+}
+
+// A push level in one launch: the frontier's hub chunks, then its short
+// rows.  Both read sigma of frontier vertices and add into sigma of
+// unvisited ones (atomically): for each source lane the sets are disjoint.
+__global__ __launch_bounds__(256) void k_bc_push(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                 const int32_t *__restrict__ front, int64_t nf,
+                                                 const uint64_t *__restrict__ cur, uint64_t *next,
+                                                 const uint64_t *__restrict__ unvis, double *sigma, RowChunks ch)
+{
+    bc_push_chunks(ci, ch, cur, next, unvis, sigma);
+    bc_push_rows(rp, ci, front, nf, cur, next, unvis, sigma);
 }
 
 // A pull level in one launch: the hub rows' chunks (a wave each, into
@@ -753,16 +765,11 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
             BC_TRY(fill_i64(ctx, (int64_t *)next, n, 0, msg));
             const bool push = ef * BC_PUSH_RATIO < ea;
             if (push) {
+                const unsigned qg = ch.n > 0 && cblocks > wgrid(nf) ? cblocks : wgrid(nf);
                 TIMED(ctx, "bc_forward",
-                      hipLaunchKernelGGL(k_bc_push, dim3(wgrid(nf)), dim3(256), 0, ctx->stream, A->rowptr,
-                                         A->colidx, lists(depth), nf, levels(depth), next, unvis, sigma));
+                      hipLaunchKernelGGL(k_bc_push, dim3(qg), dim3(256), 0, ctx->stream, A->rowptr, A->colidx,
+                                         lists(depth), nf, levels(depth), next, unvis, sigma, ch));
                 BC_LAUNCHED();
-                if (ch.n > 0) {
-                    TIMED(ctx, "bc_forward_chunks",
-                          hipLaunchKernelGGL(k_bc_push_chunks, dim3(cblocks), dim3(256), 0, ctx->stream,
-                                             A->colidx, ch, levels(depth), next, unvis, sigma));
-                    BC_LAUNCHED();
-                }
             } else if (na > 0) {
                 const unsigned pg = chT.n > 0 && cblocksT > wgrid(na) ? cblocksT : wgrid(na);
                 TIMED(ctx, "bc_forward",
