@@ -37,7 +37,7 @@ def test_generator_and_oracle_regression(entry):
         assert abs(bc.sum() - entry["bc_sum"]) <= 1e-9 * entry["bc_sum"]
 
 
-def test_small_tc_sizes_match_survey_probe_magnitude():
+def test_small_graph_has_the_expected_magnitude():
     """The 2^10-vertex graph has about 21k stored entries and 7.7e4 triangles."""
     e = load()["graphs"][0]
     assert e["scale"] == 10 and 0.95 * 21150 <= e["nnz"] <= 1.05 * 21150
