@@ -370,7 +370,7 @@ int lagr_bfs(lagr_vector *level, lagr_vector *parent, const lagr_graph G, int64_
 int lagr_bc(lagr_vector *centrality, const lagr_graph G, const int64_t *sources, int32_t ns,
             lagr_ctx ctx, char *msg);
 
-/* Single-source shortest paths by delta-stepping (Section IV-E, Algorithm
+/* Single-source shortest paths by delta-stepping (Section IV-D, Algorithm
  * 5) over the min.plus semiring.  G->A must be LAGR_FP64: A(u, v) is the
  * weight of the edge u -> v (rows are out-edges; any graph kind), and every
  * weight must be positive and finite (Algorithm 5's split into light edges,

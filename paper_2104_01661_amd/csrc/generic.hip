@@ -141,6 +141,15 @@ struct Csr {
     lagr_type type = LAGR_BOOL;
 };
 
+// Value of a valued mask entry as a truth value (Section III, "Masks": an
+// entry that is present and nonzero).  For FP64 both +0.0 and -0.0 are zero,
+// so the sign bit is ignored; any other bit pattern (NaN included) is true.
+__device__ __forceinline__ bool mask_value_true(const Csr &M, int64_t p)
+{
+    const uint64_t b = M.val[p];
+    return M.type == LAGR_FP64 ? (b << 1) != 0 : b != 0;
+}
+
 __global__ void k_iota32(int32_t *__restrict__ p, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -202,7 +211,7 @@ __global__ void k_dot(const Csr M, const Csr A, const Csr BT, int valued_mask, S
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < M.nvals;
          q += (int64_t)gridDim.x * blockDim.x) {
         has[q] = 0;
-        if (valued_mask && M.val && M.val[q] == 0) continue;   // explicit zero (int64 or +0.0)
+        if (valued_mask && M.val && !mask_value_true(M, q)) continue;   // explicit zero
         const int64_t i = row_of(M.rp, M.nrows, q);
         const int64_t j = M.ci[q];
         int64_t a = A.rp[i], ae = A.rp[i + 1], b = BT.rp[j], be = BT.rp[j + 1];
@@ -232,7 +241,7 @@ __global__ void k_counts_to_has(const int64_t *__restrict__ cnt, int64_t n, cons
 {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x) {
-        const bool masked_out = valued_mask && M.val && M.val[q] == 0;
+        const bool masked_out = valued_mask && M.val && !mask_value_true(M, q);
         has[q] = (!masked_out && cnt[q] > 0) ? 1 : 0;
         out[q] = (uint64_t)cnt[q];
     }
@@ -316,7 +325,7 @@ __device__ __forceinline__ bool mask_at(const Csr &M, bool has_mask, bool struct
             else hi = mid;
         }
         on = lo < end && M.ci[lo] == j;
-        if (on && !structural && M.val) on = M.val[lo] != 0;
+        if (on && !structural && M.val) on = mask_value_true(M, lo);
     }
     return comp ? !on : on;
 }
@@ -525,7 +534,7 @@ __device__ int64_t write_row(const WriteArgs &w, int64_t i, int32_t *ci, uint64_
         if (w.has_mask) {
             while (m < me && w.M.ci[m] < j) m++;
             on = m < me && w.M.ci[m] == j;
-            if (on && !w.structural && w.M.val) on = w.M.val[m] != 0;
+            if (on && !w.structural && w.M.val) on = mask_value_true(w.M, m);
         }
         if (w.comp) on = !on;
         uint64_t cv = inC ? load_val(w.C.val, c, w.vk) : 0;

@@ -1,4 +1,4 @@
-// Single-source shortest paths by delta-stepping (Section IV-E, Algorithm 5)
+// Single-source shortest paths by delta-stepping (Section IV-D, Algorithm 5)
 // over the min.plus semiring.  Algorithm 5 splits A into light edges
 // (0 < w <= delta) and heavy edges (w > delta) and settles the buckets
 // [i delta, (i+1) delta) of tentative distances in increasing order:

@@ -41,3 +41,17 @@ def test_small_graph_has_the_expected_magnitude():
     """The 2^10-vertex graph has about 21k stored entries and 7.7e4 triangles."""
     e = load()["graphs"][0]
     assert e["scale"] == 10 and 0.95 * 21150 <= e["nnz"] <= 1.05 * 21150
+
+
+def test_many_graph_golden_spot_check():
+    """A few of the stored 2,000-graph counts (written by make_golden.py
+    --many from the oracle) recomputed: the generator and oracle still agree."""
+    with open(os.path.join(os.path.dirname(GOLD), "many_graph_counts.json")) as f:
+        rows = json.load(f)["graphs"]
+    assert len(rows) == graphgen.MANY["count"]
+    small = [r for r in rows if r[1] <= 10][:6]
+    for g, scale, ef, nnz, tri in small:
+        assert graphgen.many_graph_params(g)[:2] == (scale, ef)
+        n, s, d = graphgen.rmat_edges(*graphgen.many_graph_params(g))
+        rp, ci = oracle.build_adjacency(n, s, d)
+        assert (int(ci.size), oracle.triangle_count(rp, ci)) == (nnz, tri)

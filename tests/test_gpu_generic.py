@@ -319,3 +319,39 @@ def test_algorithm3_with_generic_calls():
     for j, v in vec_from_dev(cent).e.items():
         got[j] = v
     assert np.allclose(got, oracle.brandes(rp, ci, srcs), rtol=1e-12, atol=1e-9)
+
+
+def test_fp64_valued_mask_treats_both_zeros_as_false():
+    """A valued FP64 mask entry is true when present and nonzero (Section
+    III, "Masks"): +0.0 and -0.0 both mask the position out, NaN and other
+    values keep it.  Checked for mxm (dot and saxpy forms), vxm and assign."""
+    L = lagr()
+    rng = np.random.default_rng(19)
+    m, k, n = 4, 5, 6
+    A = rand_mat(rng, m, k, 0.7, "bool")
+    B = rand_mat(rng, k, n, 0.7, "int64")
+    vals = [0.0, -0.0, 1.5, -2.0, float("nan")]
+    M = S.Mat(m, n, {(i, j): vals[(i * n + j) % len(vals)] for i in range(m) for j in range(n)
+                     if (i + j) % 3 != 2}, "fp64")
+    for comp, replace in itertools.product((False, True), (False, True)):
+        C0 = rand_mat(rng, m, n, 0.4, "int64")
+        want = S.mxm(C0, M, None, "plus.pair", A, B, comp=comp, replace=replace, deterministic=True)
+        Cd = to_dev(C0)
+        L.lagr_mxm(Cd, to_dev(M), 0, L.PLUS_PAIR, to_dev(A), to_dev(B),
+                   desc_bits(comp, False, replace, False, False), ctx())
+        same(from_dev(Cd).e, want.e)
+    u = rand_vec(rng, k, 0.8, "bool")
+    mk = S.Vec(n, {j: vals[j % len(vals)] for j in range(n)}, "fp64")
+    for comp in (False, True):
+        w0 = rand_vec(rng, n, 0.4, "int64")
+        want = S.vxm(w0, mk, None, "plus.pair", u, B, comp=comp, deterministic=True)
+        wd = vec_to_dev(w0, "sparse")
+        L.lagr_vxm(wd, vec_to_dev(mk, "sparse"), 0, L.PLUS_PAIR, vec_to_dev(u, "sparse"), to_dev(B),
+                   desc_bits(comp, False, False, False, False), ctx())
+        same(vec_from_dev(wd).e, want.e)
+        w1 = rand_vec(rng, n, 0.5, "int64")
+        want = S.assign_scalar(w1, mk, None, 3, comp=comp)
+        wd = vec_to_dev(w1, "bitmap")
+        L.lagr_assign_scalar(wd, vec_to_dev(mk, "bitmap"), 0, 3, desc_bits(comp, False, False, False, False),
+                             ctx())
+        same(vec_from_dev(wd).e, want.e)
