@@ -342,6 +342,19 @@ int lagr_tc(int64_t *ntriangles, lagr_graph G, lagr_ctx ctx, char *msg);
 /* Advanced mode (Section II, "User modes"): LAGR_PROPERTY_MISSING when
  * lagr_property_tc_lower has not been computed; never computes it. */
 int lagr_tc_adv(int64_t *ntriangles, const lagr_graph G, lagr_ctx ctx, char *msg);
+/* Allocation-free variant of lagr_tc_adv, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc.  It calls no allocator and does not synchronise:
+ * the count is written to ntriangles_dev, a DEVICE int64 owned by the
+ * caller, valid once ctx's stream has reached that point.  The workgroup
+ * partials and work counters live in a fixed per-device scratch array of
+ * the library (4,096 partials + 129 words, 33.8 KB, held until the process
+ * ends); a grid that would need more partials is rejected with
+ * LAGR_INVALID_VALUE before any launch.  Every call on one GPU shares that
+ * scratch: calls that overlap on one GPU (two streams, two threads) race
+ * and must be serialised by the caller.  LAGR_PROPERTY_MISSING when
+ * lagr_property_tc_lower has not been computed. */
+int lagr_tc_adv_noalloc(int64_t *ntriangles_dev, const lagr_graph G, lagr_ctx ctx, char *msg);
 
 /* Breadth-first search (Section IV-A, Algorithms 1-2).  Outputs (either
  * may be NULL): level, an INT64 FULL vector (source 0, -1 unreached) and

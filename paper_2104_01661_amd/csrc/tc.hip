@@ -2,6 +2,8 @@
 // counting (Section IV-E, Algorithm 6) as C<s(L)> = L plus.pair L^T and
 // t = sum(C), computed without forming C (the fusion Section VI-B asks
 // for).  The row kernel is described in tc_device.h.
+#include <mutex>
+
 #include "internal.h"
 #include "tc_device.h"
 
@@ -659,6 +661,80 @@ extern "C" int lagr_tc_adv(int64_t *ntriangles, const lagr_graph G, lagr_ctx ctx
     if (!ntriangles || !G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
     if (!G->L || !G->tcplan) return lagr_fail(msg, LAGR_PROPERTY_MISSING, "tc_lower property not computed");
     TRY(tc_on_lower(ctx, G, ntriangles, msg));
+    return lagr_ok(msg);
+}
+
+// ---------------------------------------------- allocation-free count
+
+// Scratch of the allocation-free count: one partial per workgroup, the
+// total, and the per-XCD work counters, in a fixed device array (each GPU
+// the library runs on holds its own copy until the process ends).  Host
+// code never passes the array's name to a kernel: its device address comes
+// from hipGetSymbolAddress, taken once per device.
+constexpr int TC_NOALLOC_MAX_BLOCKS = 4096;
+constexpr size_t TC_NOALLOC_WORDS =
+    (size_t)TC_NOALLOC_MAX_BLOCKS + 1 + (size_t)TC_DYN_STRIDE * TC_DYN_PARTS;
+static __device__ __align__(256) unsigned long long scratch[TC_NOALLOC_WORDS];
+
+constexpr int TC_NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static unsigned long long *g_scratch_dev[TC_NOALLOC_MAX_DEVICES];
+
+// The device address of `scratch` on ctx's device (looked up on the first
+// call there, with that device current).
+static int scratch_address(lagr_ctx ctx, unsigned long long **out, char *msg)
+{
+    const int dev = ctx->device;
+    if (dev < 0 || dev >= TC_NOALLOC_MAX_DEVICES)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "device %d has no scratch slot", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        int cur = -1;
+        HIP_TRY(hipGetDevice(&cur));
+        if (cur != dev) HIP_TRY(hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return lagr_fail(msg, LAGR_DEVICE_ERROR, "scratch address: %s", hipGetErrorString(e));
+        g_scratch_dev[dev] = (unsigned long long *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return LAGR_SUCCESS;
+}
+
+extern "C" int lagr_tc_adv_noalloc(int64_t *ntriangles_dev, const lagr_graph G, lagr_ctx ctx, char *msg)
+{
+    if (!ntriangles_dev || !G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    if (ctx->device < 0) return lagr_fail(msg, LAGR_DEVICE_ERROR, "validation-only context");
+    if (!G->L || !G->tcplan) return lagr_fail(msg, LAGR_PROPERTY_MISSING, "tc_lower property not computed");
+    const lagr_matrix L = G->L;
+    const TcPlan *P = G->tcplan;
+    // the grid of lagr_tc_adv, which must fit the scratch
+    const int64_t want = (P->nitems + TC_DYN_ITEMS * TC_WAVES - 1) / (TC_DYN_ITEMS * TC_WAVES);
+    const int64_t most = (int64_t)ctx->num_cus * 8;
+    const int64_t blocks = ((want < most ? want : most) + TC_DYN_PARTS - 1) / TC_DYN_PARTS * TC_DYN_PARTS;
+    if (blocks > TC_NOALLOC_MAX_BLOCKS)
+        return lagr_fail(msg, LAGR_INVALID_VALUE,
+                         "the count needs %lld workgroup partials; the fixed scratch holds %d",
+                         (long long)blocks, TC_NOALLOC_MAX_BLOCKS);
+    unsigned long long *sp = nullptr;
+    TRY(scratch_address(ctx, &sp, msg));
+    if (P->nitems > 0) {
+        unsigned long long *part = sp;
+        unsigned long long *ctr = sp + TC_NOALLOC_MAX_BLOCKS + 1;
+        // the counters keep the previous call's values: clear them (a fill
+        // kernel, so the call may also be captured into a graph)
+        TRY(fill_i64(ctx, (int64_t *)ctr, (int64_t)TC_DYN_STRIDE * TC_DYN_PARTS, 0, msg));
+        PlanArgs a{P->nitems, L->rowptr, L->colidx, P->ent, P->item, P->item_row, P->bits};
+        hipLaunchKernelGGL(k_tc_split, dim3((unsigned)blocks), dim3(TC_BLOCK), 0, ctx->stream, a, part, ctr);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, ctx->stream, part, blocks,
+                           (unsigned long long *)ntriangles_dev);
+        LAUNCH_CHECK();
+    } else {
+        TRY(fill_i64(ctx, ntriangles_dev, 1, 0, msg));
+    }
     return lagr_ok(msg);
 }
 

@@ -107,6 +107,7 @@ _PROTOS = {
     "lagr_graph_free": [_PP],
     "lagr_tc": [_P, _P, _P, _C],
     "lagr_tc_adv": [_P, _P, _P, _C],
+    "lagr_tc_adv_noalloc": [_P, _P, _P, _C],
     "lagr_bfs": [_PP, _PP, _P, _I64, _U32, _P, _C],
     "lagr_bc": [_PP, _P, _P, _I32, _P, _C],
     "lagr_sssp": [_PP, _P, _I64, ctypes.c_double, _P, _C],
@@ -152,6 +153,8 @@ def call_nomsg(name, *args):
 # ------------------------------------------------------------ allocator
 
 _alloc_refs = None
+# device allocations made by the library through the registered allocator
+alloc_calls = 0
 
 
 def use_torch_allocator(enable: bool = True):
@@ -164,6 +167,8 @@ def use_torch_allocator(enable: bool = True):
         return
 
     def _alloc(nbytes, user):
+        global alloc_calls
+        alloc_calls += 1
         try:
             return torch.cuda.caching_allocator_alloc(int(nbytes))
         except Exception:
@@ -435,6 +440,14 @@ def lagr_tc_adv(G: Graph, ctx: Context) -> int:
     t = ctypes.c_int64()
     call("lagr_tc_adv", ctypes.byref(t), G.h, ctx.h)
     return t.value
+
+
+def lagr_tc_adv_noalloc(G: Graph, out, ctx: Context):
+    """Allocation-free count into `out`, a one-element int64 device tensor;
+    queued on ctx's stream, no synchronisation."""
+    assert out.dtype == torch.int64 and out.is_cuda and out.numel() >= 1
+    call("lagr_tc_adv_noalloc", _ptr(out), G.h, ctx.h)
+    return out
 
 
 def lagr_property_tc_lower(G: Graph, ctx: Context):
