@@ -167,6 +167,8 @@ int lagr_ctx_new(lagr_ctx *ctx, int device, void *stream, char *msg);
  * arguments exactly as usual, but no device work can run on it (calls that
  * pass their checks fail with LAGR_DEVICE_ERROR or LAGR_OUT_OF_MEMORY).  It
  * needs no GPU, so host-side tests of the argument checks can use it. */
+/* Switch the context's stream; work queued on the old stream finishes
+ * first (the call waits for it). */
 int lagr_ctx_set_stream(lagr_ctx ctx, void *stream, char *msg);
 int lagr_ctx_free(lagr_ctx *ctx);
 /* Wait for all work queued on the context's stream. */
@@ -367,7 +369,12 @@ int lagr_tc_adv_noalloc(int64_t *ntriangles_dev, const lagr_graph G, lagr_ctx ct
  * LAGR_BFS_ANY_PARENT allows any valid one.  On a directed graph the search
  * follows out-edges (A(u, v) is u -> v) and the parent of v is an
  * in-neighbour; pull steps read AT, which is computed and cached on first
- * use unless LAGR_BFS_PUSH_ONLY is given. */
+ * use unless LAGR_BFS_PUSH_ONLY is given.  The call returns once the
+ * search has ended (it watches a word the device stores when a level finds
+ * the frontier empty), possibly before the last few queued level kernels,
+ * which only pass the finished state on, have run: the outputs are valid
+ * after lagr_wait or a sync of the context's stream, like every device
+ * output. */
 #define LAGR_BFS_PUSH_ONLY 1u
 #define LAGR_BFS_ANY_PARENT 2u
 int lagr_bfs(lagr_vector *level, lagr_vector *parent, const lagr_graph G, int64_t source,

@@ -103,6 +103,9 @@ extern "C" int lagr_ctx_new(lagr_ctx *ctx, int device, void *stream, char *msg)
 extern "C" int lagr_ctx_set_stream(lagr_ctx ctx, void *stream, char *msg)
 {
     if (!ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "ctx is NULL");
+    // work a call left queued (a search's last levels) finishes on the old
+    // stream before the context's next work starts on the new one
+    if (ctx->device >= 0 && ctx->stream != (hipStream_t)stream) HIP_TRY(hipStreamSynchronize(ctx->stream));
     ctx->stream = (hipStream_t)stream;
     return lagr_ok(msg);
 }
@@ -113,6 +116,8 @@ extern "C" int lagr_ctx_free(lagr_ctx *ctx)
     lagr_ctx c = *ctx;
     if (c->device >= 0) (void)hipStreamSynchronize(c->stream);
     if (c->bfs_exec) (void)hipGraphExecDestroy(c->bfs_exec);
+    if (c->bfs_exec_more) (void)hipGraphExecDestroy(c->bfs_exec_more);
+    if (c->bfs_graph) (void)hipGraphDestroy(c->bfs_graph);
     if (c->sssp_exec) (void)hipGraphExecDestroy(c->sssp_exec);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     timers_clear(c);

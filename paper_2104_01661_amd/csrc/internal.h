@@ -112,11 +112,16 @@ struct lagr_ctx_s {
     int num_cus = 256;
     std::vector<void *> lvpool;      // per-level lane masks + vertex lists (BC)
     size_t lv_bytes = 0;
-    // BFS: captured two-level graph (valid for bfs_key vertices and the
-    // state struct at bfs_state) and the stream it is captured on
+    // BFS: graphs of the search's start and first levels, and of further
+    // levels, valid for bfs_key vertices and the state struct at
+    // bfs_state, and the stream they are captured on
     hipGraphExec_t bfs_exec = nullptr;
+    hipGraphExec_t bfs_exec_more = nullptr;
+    hipGraph_t bfs_graph = nullptr;            // the first graph (its start node is updated per search)
+    hipGraphNode_t bfs_start_node = nullptr;
     int64_t bfs_key = -1;
     void *bfs_state = nullptr;
+    void *bfs_ctr = nullptr;
     // SSSP: captured two-step graph, keyed the same way
     hipGraphExec_t sssp_exec = nullptr;
     int64_t sssp_key = -1;
@@ -236,7 +241,10 @@ int fill_u8(lagr_ctx ctx, uint8_t *p, int64_t n, uint8_t value, char *msg);
 // stage_to_host, then LAGR_PINNED_FLAGS bytes of flags that kernels store
 // to directly: the BFS level loop's done flag at LAGR_PINNED_STAGE and the
 // sequence word of host waits at LAGR_PINNED_SEQ.
+// The BFS level loop also stores the index of the level that has started
+// at LAGR_PINNED_LEVEL.
 constexpr size_t LAGR_PINNED_STAGE = 4096;
+constexpr size_t LAGR_PINNED_LEVEL = LAGR_PINNED_STAGE + 8;
 constexpr size_t LAGR_PINNED_SEQ = LAGR_PINNED_STAGE + 64;
 constexpr size_t LAGR_PINNED_FLAGS = 256;
 constexpr size_t LAGR_PINNED_BYTES = LAGR_PINNED_STAGE + LAGR_PINNED_FLAGS;
