@@ -38,6 +38,8 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--small-reps", type=int, default=200,
+                   help="timed calls of the 2^10-vertex triangle-count latency leg")
     p.add_argument("--no-bc", action="store_true")
     p.add_argument("--no-sssp", action="store_true")
     p.add_argument("--no-prcc", action="store_true")
@@ -53,8 +55,14 @@ def parse():
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="first run a plain elementwise copy of this many MiB (calibrates HBM "
                         "traffic counters: bytes read and written are known)")
-    p.add_argument("--cpu-stride", type=int, default=4,
-                   help="oracle CPU sample: every stride-th row of the triangle count")
+    p.add_argument("--cpu-stride", type=int, default=32,
+                   help="oracle at T = 1: every stride-th row of the triangle count")
+    p.add_argument("--cpu-bfs-sample", type=int, default=8,
+                   help="oracle at T = 1: BFS sources timed")
+    p.add_argument("--cpu-bc-sample", type=int, default=16,
+                   help="oracle at T = 1: betweenness sources timed")
+    p.add_argument("--cpu-full", action="store_true",
+                   help="oracle at T = 1 on the whole workloads (minutes)")
     return p.parse_args()
 
 
@@ -67,6 +75,8 @@ def kernel_source_sha(files):
 
 
 TC_KERNEL_FILES = ["paper_2104_01661_amd/csrc/tc.hip", "paper_2104_01661_amd/csrc/tc_device.h"]
+BFS_KERNEL_FILES = ["paper_2104_01661_amd/csrc/bfs.hip"]
+BC_KERNEL_FILES = ["paper_2104_01661_amd/csrc/bc.hip"]
 
 
 def load_counters(name, files):
@@ -194,6 +204,130 @@ def serve_leg(args, L, ctx, dev, graphgen, np, torch):
             "p99_speedup_vs_plain": round(plain["p99_ms"] / served["p99_ms"], 2)}
 
 
+def cpu_host():
+    """CPU model, logical CPUs the process may use, and the OpenMP default."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, usable, os.cpu_count()
+
+
+def cpu_leg(args, n, src, dst, sources, nnzL, reached_edges, np):
+    """The oracle timed on the host's cores: its timing build (the same C
+    source, -O3 -march=native, OpenMP over independent units: rows of the
+    triangle count, BFS sources, ranges of betweenness sources summed in a
+    fixed order) at T = all threads the process gets and at T = 1, median of
+    3.  At T = all it runs the whole workloads: the 2^20 triangle count, the
+    64 BFS sources (levels and smallest parents), the 4 x 64 betweenness
+    sources at 2^18.  At T = 1 it runs a bounded sample of each (the full
+    set with --cpu-full).  Every result is checked against the checker
+    build of the oracle (-O2, single-threaded per call)."""
+    import concurrent.futures as cf
+    import graphgen
+    import oracle
+
+    def med3(fn, reps=3):
+        ts, r = [], None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), r
+
+    model, usable, logical = cpu_host()
+    T = oracle.Timing(True)
+    t_all = T.threads()
+    rp, ci = oracle.build_adjacency(n, src, dst)
+    srcs = np.asarray(sources, dtype=np.int64)
+    bcfg = graphgen.BC
+    bn, bs, bd = graphgen.rmat_edges(bcfg["scale"], bcfg["edge_factor"], bcfg["seed"])
+    brp, bci = oracle.build_adjacency(bn, bs, bd)
+    bsrc = graphgen.sources(bn, bs, bd, bcfg["batches"] * bcfg["batch_size"], bcfg["seed"])
+    with open(os.path.join(ROOT, "tests", "golden", "oracle_values.json")) as f:
+        gold_tc = json.load(f)["large"]["triangles"]
+
+    res = {"kind": "oracle", "cpu_model": model, "logical_cpus": logical, "usable_cpus": usable,
+           "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS"),
+           "build": "gcc -O3 -march=native -fopenmp (oracle timing build); checks: gcc -O2 checker"}
+    # ---- T = all threads
+    log(f"cpu baseline: T = {t_all}")
+    tc_s, tc = med3(lambda: T.triangle_count(rp, ci))
+    assert tc == gold_tc, f"timing-build count {tc} differs from the stored oracle count {gold_tc}"
+    bfs_s, (lv, pa) = med3(lambda: T.bfs_sources(rp, ci, srcs))
+    nparts = 4 * t_all
+    bc_s, bc = med3(lambda: T.brandes(brp, bci, bsrc, nparts))
+    # checks against the checker build, its calls spread over a thread pool
+    chk = oracle.Timing(False)
+    pool = min(16, usable or 1)
+
+    def chk_bfs(k):
+        lo, po = oracle.bfs(rp, ci, int(srcs[k]))
+        return (np.array_equal(lo, lv[k]) and
+                np.array_equal(oracle.bfs_min_parent(rp, ci, int(srcs[k]), lo), pa[k]))
+
+    bsz = bcfg["batch_size"]
+    with cf.ThreadPoolExecutor(pool) as ex:
+        assert all(ex.map(chk_bfs, range(srcs.size))), "timing-build BFS differs from the checker"
+        parts = list(ex.map(lambda b: oracle.brandes(brp, bci, bsrc[b * bsz:(b + 1) * bsz]),
+                            range(bcfg["batches"])))
+    want = parts[0].copy()
+    for p_ in parts[1:]:
+        want += p_
+    zero = want == 0
+    assert (bc[zero] == 0).all() and np.max(np.abs(bc[~zero] - want[~zero]) / np.abs(want[~zero])) <= 1e-12, \
+        "timing-build betweenness differs from the checker"
+    del lv, pa, chk
+    m_bfs = float(np.sum(reached_edges))
+    res["t_all"] = {"threads": t_all,
+                    "tc_s": round(tc_s, 3), "tc_edges_per_s": round(nnzL / tc_s, 1),
+                    "bfs64_s": round(bfs_s, 3), "bfs_teps_aggregate": round(m_bfs / bfs_s, 1),
+                    "bc_4x64_s": round(bc_s, 3), "bc_s_per_batch": round(bc_s / bcfg["batches"], 4),
+                    "bc_source_ranges": nparts}
+    # ---- T = 1
+    T.set_threads(1)
+    full = args.cpu_full
+    stride = 1 if full else args.cpu_stride
+    up = np.zeros(n, dtype=np.int64)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    np.add.at(up, rows[ci > rows], 1)
+    tc_edges = int(up[::stride].sum())
+    del rows, up
+    nb = srcs.size if full else args.cpu_bfs_sample
+    nbc = bsrc.size if full else args.cpu_bc_sample
+    log(f"cpu baseline: T = 1 ({'full' if full else 'sampled'})")
+    reps = 3
+    tc1_s, tc1 = med3(lambda: T.triangle_count(rp, ci, stride), reps)
+    if full:
+        assert tc1 == gold_tc
+    bfs1_s, _ = med3(lambda: T.bfs_sources(rp, ci, srcs[:nb]), reps)
+    bc1_s, _ = med3(lambda: T.brandes(brp, bci, bsrc[:nbc], 1), reps)
+    T.set_threads(t_all)
+    res["t_1"] = {"threads": 1,
+                  "tc_sample": "all rows" if full else f"rows u = 0, {stride}, {2 * stride}, ... ({tc_edges} "
+                                                       f"of {nnzL} undirected edges)",
+                  "tc_s": round(tc1_s, 3), "tc_edges_per_s": round(tc_edges / tc1_s, 1),
+                  "bfs_sources": nb, "bfs_s": round(bfs1_s, 3),
+                  "bfs_teps_aggregate": round(float(np.sum(reached_edges[:nb])) / bfs1_s, 1),
+                  "bc_sources": nbc, "bc_s": round(bc1_s, 3),
+                  "bc_s_per_batch": round(bc1_s * bcfg["batch_size"] / nbc, 4)}
+    res["value"] = res["t_all"]["tc_edges_per_s"]
+    res["unit"] = "edges/s"
+    res["cores"] = t_all
+    res["sample"] = (f"whole 2^20 triangle count ({nnzL} undirected edges) at T = {t_all}, median of 3; "
+                     f"T = 1 figures on {'the whole workloads' if full else 'bounded samples'} in t_1")
+    return res
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -277,14 +411,21 @@ def main():
     tc_model = {"pairs": nent, "streamed_ids": streamed, "bitmap_pairs": int(bitmap.sum().item()),
                 "bitmap_words": bitmap_words, "items": items,
                 "single_side_streamed_ids": int(lj[pos >= 1].sum().item())}
+    # the two reference byte models of the masked product: compulsory (L
+    # streamed once) and the no-reuse gather (every pair (i, j) of L reads
+    # row j's offsets and ids)
+    tc_compulsory = 8 * (n + 1) + 4 * nnzL
+    tc_gather = tc_compulsory + 16 * nnzL + 4 * int(llen[lci.long()].sum().item())
     del row_of, pos, lj, jl, valid, hub, side_a, side_b, bitmap, bitmap_a, bitmap_b, words_j, last_id, cnt_a, cnt_b
 
     # per-source traversed edges for GTEPS: undirected edges in the reached set
-    reached_edges = []
+    reached_edges, reached_vertices, depths = [], [], []
     for s in sources:
         lv, _ = L.lagr_bfs(G, s, ctx, want_parent=False)
         lvl = lv.values_full(ctx).cpu().numpy()
         reached_edges.append(int(deg[lvl >= 0].sum()) // 2)
+        reached_vertices.append(int((lvl >= 0).sum()))
+        depths.append(int(lvl.max()))
     n_small_component = sum(1 for m in reached_edges if m < nnzA // 4)
 
     # -------------------------------------------------------------- step
@@ -351,11 +492,57 @@ def main():
     if counters:
         traffic = int((counters["fetch_kib"] * counters["fetch_scale"]
                        + counters["write_kib"] * counters["write_scale"]) * 1024)
+    def gbs(nbytes, ms):
+        return round(nbytes / (ms * 1e-3) / 1e9, 1)
+
     roofline = {"bound": "hbm", "kernel": "k_tc_split (fused masked plus.pair + reduce, min-side)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_kind": "fabric bytes (L2-miss FETCH_SIZE + WRITE_SIZE, Infinity Cache hits included)",
                 "algorithmic_bytes": tc_bytes, "kernel_ms": round(tc_kernel_ms, 4),
-                "model": tc_model}
+                "model": tc_model,
+                "byte_models": {
+                    "plan (the value above: what this kernel's plan must read)":
+                        {"bytes": tc_bytes, "gbs": gbs(tc_bytes, tc_kernel_ms),
+                         "frac": round(gbs(tc_bytes, tc_kernel_ms) / HBM_PEAK_GBS, 4)},
+                    "compulsory 8(n+1) + 4 nnz(L)":
+                        {"bytes": tc_compulsory, "gbs": gbs(tc_compulsory, tc_kernel_ms),
+                         "frac": round(gbs(tc_compulsory, tc_kernel_ms) / HBM_PEAK_GBS, 4)},
+                    "no-reuse gather: + sum over (i,j) in L of 16 + 4 len(L_j)":
+                        {"bytes": tc_gather, "gbs": gbs(tc_gather, tc_kernel_ms),
+                         "frac": round(gbs(tc_gather, tc_kernel_ms) / HBM_PEAK_GBS, 4)},
+                    "counter traffic":
+                        None if traffic is None else
+                        {"bytes": traffic, "gbs": gbs(traffic, tc_kernel_ms),
+                         "frac": round(gbs(traffic, tc_kernel_ms) / HBM_PEAK_GBS, 4)}}}
+
+    # BFS: the push-only byte model per source (every edge of the reached
+    # set's rows read once as a 4-byte id, the row offsets, 16 bytes of level,
+    # parent and frontier per reached vertex, one frontier bitmap per level)
+    bfs_model = [4 * 2 * m + 8 * (n + 1) + 16 * r + (n // 8) * (dd + 1)
+                 for m, r, dd in zip(reached_edges, reached_vertices, depths)]
+    bfs_gbs = [b / (t * 1e-3) / 1e9 for b, t in zip(bfs_model, bfs_med_per_src)]
+    bfs_counters = load_counters("bfs_search", BFS_KERNEL_FILES)
+    bfs_traffic = None
+    if bfs_counters:
+        bfs_traffic = int((bfs_counters["fetch_kib"] * bfs_counters["fetch_scale"]
+                           + bfs_counters["write_kib"] * bfs_counters["write_scale"]) * 1024)
+    bfs_med_ms = float(np.median(bfs_med_per_src))
+    roofline_bfs = {"bound": "hbm", "kernel": "BFS search (start kernel + one level kernel per level), per source",
+                    "achieved": round(float(np.median(bfs_gbs)), 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(float(np.median(bfs_gbs)) / HBM_PEAK_GBS, 4),
+                    "traffic": bfs_traffic,
+                    "traffic_kind": "fabric bytes per search (sum over its kernels)",
+                    "algorithmic_bytes": int(np.median(bfs_model)), "search_ms": round(bfs_med_ms, 4),
+                    "model": "push-only: 4 B per entry of the reached rows + 8(n+1) + 16 B per reached vertex "
+                             "+ n/8 per level (median source)"}
+    tc_total = float(np.median(tc_ms))
+    bfs_total = float(np.sum(bfs_med_per_src))
+    step_share = {"tc_whole_ms": round(tc_total, 4), "tc_count_kernel_ms": round(tc_kernel_ms, 4),
+                  "bfs_64_sources_ms": round(bfs_total, 4),
+                  "tc_share": round(tc_total / (tc_total + bfs_total), 4),
+                  "count_kernel_share": round(tc_kernel_ms / (tc_total + bfs_total), 4),
+                  "bfs_share": round(bfs_total / (tc_total + bfs_total), 4)}
 
     out = {
         "metric": "TC edges/s, BFS GTEPS (R-MAT s20)",
@@ -380,7 +567,44 @@ def main():
                 "ms_median": round(float(np.median(bfs_med_per_src)), 4),
                 "sources_outside_giant_component": n_small_component},
         "roofline": roofline,
+        "roofline_bfs": roofline_bfs,
+        "step_share": step_share,
     }
+
+    # ------------------------------------- triangle-count latency (2^10)
+    log("triangle-count latency leg (2^10)")
+    c1 = graphgen.TC_SMALL
+    n1, s1, d1 = graphgen.rmat_edges(c1["scale"], c1["edge_factor"], c1["seed"])
+    G1 = L.Graph(ctx, L.Matrix.build(ctx, n1, n1, torch.from_numpy(s1).to(dev), torch.from_numpy(d1).to(dev),
+                                     L.BUILD_SYMMETRIZE | L.BUILD_DROP_LOOPS))
+    G1.check(ctx)
+    with open(os.path.join(ROOT, "tests", "golden", "oracle_values.json")) as f:
+        t1_gold = [g for g in json.load(f)["graphs"]
+                   if (g["scale"], g["edge_factor"], g["seed"]) == (c1["scale"], c1["edge_factor"], c1["seed"])]
+    whole, prepared, counts = [], [], set()
+    for rep in range(5 + args.small_reps):
+        G1.delete_properties(ctx)
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        counts.add(L.lagr_tc(G1, ctx))
+        a1 = time.perf_counter()
+        counts.add(L.lagr_tc_adv(G1, ctx))
+        a2 = time.perf_counter()
+        if rep >= 5:
+            whole.append(a1 - a0)
+            prepared.append(a2 - a1)
+    assert len(counts) == 1 and (not t1_gold or counts == {t1_gold[0]["triangles"]}), counts
+    nnzL1 = G1.tc_lower().info()[3]
+    out["tc_small"] = {"workload": c1["name"], "vertices": n1, "undirected_edges": nnzL1,
+                       "triangles": counts.pop(), "reps": len(whole),
+                       "latency_us_whole_median": round(float(np.median(whole)) * 1e6, 1),
+                       "latency_us_whole_min": round(float(np.min(whole)) * 1e6, 1),
+                       "latency_us_prepared_median": round(float(np.median(prepared)) * 1e6, 1),
+                       "latency_us_prepared_min": round(float(np.min(prepared)) * 1e6, 1),
+                       "edges_per_s_whole": round(nnzL1 / float(np.median(whole)), 1),
+                       "edges_per_s_prepared": round(nnzL1 / float(np.median(prepared)), 1),
+                       "timing": "host wall clock around each call (each returns the count on the host)"}
+    del G1
 
     # ------------------------------------------------ betweenness (2^18)
     log("betweenness leg")
@@ -403,9 +627,32 @@ def main():
             torch.cuda.synchronize()
             bc_runs.append(e0.elapsed_time(e1))
             del c
-        out["bc"] = {"workload": bcfg["name"], "s_per_batch":
-                     round(float(np.median(bc_runs)) * 1e-3 / bcfg["batches"], 6),
+        s_batch = float(np.median(bc_runs)) * 1e-3 / bcfg["batches"]
+        out["bc"] = {"workload": bcfg["name"], "s_per_batch": round(s_batch, 6),
                      "batches": bcfg["batches"], "batch_size": bcfg["batch_size"], "dtype": "f64"}
+        # byte model per batch: 12 B per (source, entry of its component)
+        # in each of the two sweeps, 48 B per (source, vertex of its
+        # component) of path-count, dependency and depth state
+        lab, _ = L.lagr_cc(BG, ctx)
+        lab = lab.values_full(ctx).cpu().numpy()
+        brp = BG.matrix().to_csr(ctx)[0].cpu().numpy()
+        bdeg = np.diff(brp)
+        comp_v = np.bincount(lab, minlength=bn)
+        comp_e = np.bincount(lab, weights=bdeg, minlength=bn)
+        bc_bytes = float(sum(24 * comp_e[lab[x]] + 48 * comp_v[lab[x]] for x in bsrc)) / bcfg["batches"]
+        bc_counters = load_counters("bc_batch", BC_KERNEL_FILES)
+        bc_traffic = None
+        if bc_counters:
+            bc_traffic = int((bc_counters["fetch_kib"] * bc_counters["fetch_scale"]
+                              + bc_counters["write_kib"] * bc_counters["write_scale"]) * 1024)
+        ach = bc_bytes / s_batch / 1e9
+        out["roofline_bc"] = {"bound": "hbm", "kernel": "BC batch of 64 sources (forward and backward sweeps)",
+                              "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": bc_traffic,
+                              "traffic_kind": "fabric bytes per batch (sum over its kernels)",
+                              "algorithmic_bytes": int(bc_bytes), "batch_ms": round(s_batch * 1e3, 4),
+                              "model": "24 B per (source, entry of its component) + 48 B per (source, vertex "
+                                       "of its component)"}
 
     # ------------------------------------- delta-stepping SSSP (2^20)
     log("sssp leg")
@@ -525,23 +772,7 @@ def main():
     # ------------------------------------------------ CPU oracle baseline
     log("CPU oracle baseline")
     if not args.no_cpu_baseline:
-        import oracle
-        orp, oci = oracle.build_adjacency(n, src, dst)
-        stride = max(1, args.cpu_stride)
-        rows = np.arange(0, n, stride)
-        # edges the sample processes: (u, v) with v > u for the sampled rows u
-        up = np.zeros(n, dtype=np.int64)
-        idx = np.repeat(np.arange(n), np.diff(orp))
-        np.add.at(up, idx[oci > idx], 1)
-        edges = int(up[rows].sum())
-        c0 = time.perf_counter()
-        oracle.triangle_count_rows(orp, oci, 0, n, stride)
-        c1 = time.perf_counter()
-        out["cpu_baseline"] = {"value": round(edges / (c1 - c0), 1), "unit": "edges/s",
-                               "cores": 1, "kind": "oracle",
-                               "sample": f"triangle count of rows u = 0, {stride}, {2 * stride}, ... "
-                                         f"({edges} of {nnzL} undirected edges) of the same graph, "
-                                         f"single-threaded C, {c1 - c0:.1f} s"}
+        out["cpu_baseline"] = cpu_leg(args, n, src, dst, sources, nnzL, reached_edges, np)
     print(json.dumps(out))
 
 

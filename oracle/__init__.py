@@ -26,15 +26,19 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
+_SO_MT = os.path.join(_HERE, "liboracle_mt.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 
 
 def build(force: bool = False) -> str:
-    """Compile the C oracle (plain -O2, single-threaded)."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        tmp = _SO + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", _SRC, "-o", tmp])
-        os.replace(tmp, _SO)
+    """Compile the C oracle: the checker (plain -O2, single-threaded) and,
+    from the same source, the timing build of the CPU baseline (-O3
+    -march=native, OpenMP over independent units in the timing drivers)."""
+    for so, flags in ((_SO, ["-O2"]), (_SO_MT, ["-O3", "-march=native", "-fopenmp"])):
+        if force or not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(_SRC):
+            tmp = so + ".tmp"
+            subprocess.check_call(["gcc", *flags, "-fPIC", "-shared", _SRC, "-o", tmp])
+            os.replace(tmp, so)
     return _SO
 
 
@@ -43,12 +47,26 @@ _P = ctypes.c_void_p
 _I = ctypes.c_int64
 
 
+def _declare(lib):
+    lib.orc_threads.restype = ctypes.c_int
+    lib.orc_threads.argtypes = []
+    lib.orc_set_threads.restype = None
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
+    lib.orc_tc_par.restype = _I
+    lib.orc_tc_par.argtypes = [_I, _P, _P, _I]
+    lib.orc_bfs_sources.restype = ctypes.c_int
+    lib.orc_bfs_sources.argtypes = [_I, _P, _P, _I, _P, _P, _P]
+    lib.orc_brandes_parts.restype = ctypes.c_int
+    lib.orc_brandes_parts.argtypes = [_I, _P, _P, _I, _P, _I, _P, _P]
+
+
 def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_SO):
             build()
         lib = ctypes.CDLL(_SO)
+        _declare(lib)
         lib.orc_build.restype = _I
         lib.orc_build.argtypes = [_I, _I, _P, _P, _P, _P]
         lib.orc_tc.restype = _I
@@ -261,3 +279,59 @@ def dijkstra(rowptr, colidx, weights, source: int):
     if _load().orc_dijkstra(rowptr.size - 1, pr, pc, pw, int(source), out.ctypes.data) != 0:
         raise MemoryError("oracle: dijkstra failed")
     return out
+
+
+# ------------------------------------------------------------ timing build
+
+class Timing:
+    """The timing build of the oracle (the same C source, -O3 -march=native,
+    OpenMP over independent units) or, with threaded=False, the checker
+    library itself.  Used by the benchmark's CPU-baseline leg only."""
+
+    def __init__(self, threaded: bool = True):
+        if threaded:
+            if not os.path.exists(_SO_MT) or os.path.getmtime(_SO_MT) < os.path.getmtime(_SRC):
+                build()
+            self.lib = ctypes.CDLL(_SO_MT)
+            _declare(self.lib)
+        else:
+            self.lib = _load()
+
+    def threads(self) -> int:
+        return int(self.lib.orc_threads())
+
+    def set_threads(self, t: int):
+        self.lib.orc_set_threads(int(t))
+
+    def triangle_count(self, rowptr, colidx, stride: int = 1) -> int:
+        """Triangles whose smallest vertex is one of 0, stride, 2 stride, ..."""
+        rowptr, pr = _c(rowptr, np.int64)
+        colidx, pc = _c(colidx, np.int32)
+        return int(self.lib.orc_tc_par(rowptr.size - 1, pr, pc, int(stride)))
+
+    def bfs_sources(self, rowptr, colidx, sources):
+        """(levels int32[ns, n], smallest parents int64[ns, n])."""
+        rowptr, pr = _c(rowptr, np.int64)
+        colidx, pc = _c(colidx, np.int32)
+        srcs, ps = _c(sources, np.int64)
+        n = rowptr.size - 1
+        lv = np.empty((srcs.size, n), dtype=np.int32)
+        pa = np.empty((srcs.size, n), dtype=np.int64)
+        if self.lib.orc_bfs_sources(n, pr, pc, srcs.size, ps, lv.ctypes.data, pa.ctypes.data) != 0:
+            raise MemoryError("oracle: bfs failed")
+        return lv, pa
+
+    def brandes(self, rowptr, colidx, sources, nparts: int):
+        rowptr, pr = _c(rowptr, np.int64)
+        colidx, pc = _c(colidx, np.int32)
+        srcs, ps = _c(sources, np.int64)
+        n = rowptr.size - 1
+        part = np.empty((max(1, nparts), n), dtype=np.float64)
+        out = np.empty(n, dtype=np.float64)
+        rc = self.lib.orc_brandes_parts(n, pr, pc, srcs.size, ps, int(nparts), part.ctypes.data,
+                                        out.ctypes.data)
+        if rc == -2:
+            raise OverflowError("oracle: a shortest-path count reached 2^53")
+        if rc != 0:
+            raise MemoryError("oracle: brandes failed")
+        return out

@@ -531,3 +531,84 @@ int orc_dijkstra(int64_t n, const int64_t *rp, const int32_t *ci, const double *
     free(done);
     return 0;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Timing drivers.  They call the functions above, unchanged, over
+ * independent units of work: rows of the triangle count, BFS sources,
+ * contiguous ranges of betweenness sources.  Built with OpenMP (the timing
+ * build of this same file) the units run on several threads; built without
+ * it (the checker) they run one after another with the same results.  The
+ * betweenness ranges are fixed by nparts, not by the thread count, and are
+ * added in range order, so the sum does not depend on the threads.        */
+/* ---------------------------------------------------------------------- */
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
+/* Triangles with rows spread over the threads in dynamic chunks. */
+int64_t orc_tc_par(int64_t n, const int64_t *rp, const int32_t *ci, int64_t stride)
+{
+    int64_t t = 0;
+    if (stride < 1) stride = 1;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : t)
+    for (int64_t u = 0; u < n; u += stride) t += orc_tc_rows(n, rp, ci, u, u + 1, 1);
+    return t;
+}
+
+/* Queue BFS and the smallest parents from each of ns sources: levels and
+ * parents are ns x n, source k in row k. */
+int orc_bfs_sources(int64_t n, const int64_t *rp, const int32_t *ci, int64_t ns, const int64_t *sources,
+                    int32_t *levels, int64_t *parents)
+{
+    int rc = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : rc)
+    for (int64_t k = 0; k < ns; k++) {
+        int32_t *lv = levels + k * n;
+        int64_t *pa = parents + k * n;
+        int r = orc_bfs(n, rp, ci, sources[k], lv, pa);
+        if (r == 0) orc_bfs_min_parent(n, rp, ci, sources[k], lv, pa);
+        if (r < rc) rc = r;
+    }
+    return rc;
+}
+
+/* Betweenness over ns sources cut into nparts contiguous ranges: each range
+ * summed by orc_brandes into part[k * n ...], then the ranges added in
+ * order into centrality.  part holds nparts x n doubles. */
+int orc_brandes_parts(int64_t n, const int64_t *rp, const int32_t *ci, int64_t ns, const int64_t *sources,
+                      int64_t nparts, double *part, double *centrality)
+{
+    int rc = 0;
+    if (nparts < 1) nparts = 1;
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : rc)
+    for (int64_t k = 0; k < nparts; k++) {
+        const int64_t lo = ns * k / nparts, hi = ns * (k + 1) / nparts;
+        int r = orc_brandes(n, rp, ci, hi - lo, sources + lo, part + k * n);
+        if (r < rc) rc = r;
+    }
+    for (int64_t v = 0; v < n; v++) {
+        double c = part[v];
+        for (int64_t k = 1; k < nparts; k++) c += part[k * n + v];
+        centrality[v] = c;
+    }
+    return rc;
+}
