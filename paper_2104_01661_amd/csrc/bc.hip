@@ -12,7 +12,9 @@
 //
 // Forward level d (F<!s(P), r> = F plus.first A, then P += F), in the
 // direction that touches fewer edges (the choice the paper describes for
-// BC, after Beamer):
+// BC, after Beamer), taken on the device from the counts the previous
+// level's compaction left, so the host queues a chunk of levels at once and
+// reads the frontier sizes once per chunk instead of once per level:
 //   pull: a wave per active vertex v gathers, in ascending neighbour order,
 //         sigma(u, k) of the neighbours u at depth d in lane k;
 //   push: a wave per frontier vertex u adds sigma(u, k) to every neighbour
@@ -42,6 +44,27 @@ constexpr int64_t BC_CHUNK = GRAPH_LONG_ROW;
 // push a forward level when the frontier's edges are fewer than the active
 // vertices' edges / BC_PUSH_RATIO
 constexpr int64_t BC_PUSH_RATIO = 10;
+// forward levels: the fixed grid, the levels queued before the host first
+// reads the frontier sizes, then per further read, and the ring of level
+// counters (larger than a chunk plus one)
+constexpr unsigned BC_FORWARD_GRID = 8192;
+constexpr size_t BC_FIRST_LEVELS = 8;
+constexpr size_t BC_MORE_LEVELS = 4;
+constexpr size_t BC_RING = 16;
+
+// A forward level's direction from its counts c = {frontier size, its
+// out-degree sum, active size, its in-degree sum}, which the compaction of
+// the previous level left on the device: 0 the frontier is empty (the sweep
+// is over), 1 push (the frontier's edges are fewer than the active
+// vertices' edges / BC_PUSH_RATIO), 2 pull, 3 nothing (no active vertex).
+__device__ __forceinline__ int bc_direction(const unsigned long long *__restrict__ c)
+{
+    const unsigned long long nf = c[0], ef = c[1], na = c[2], ea = c[3];
+    if (nf == 0) return 0;
+    if (ef * (unsigned long long)BC_PUSH_RATIO < ea) return 1;
+    return na > 0 ? 2 : 3;
+}
+
 
 __global__ __launch_bounds__(256) void k_bc_init(int64_t n, uint64_t lanes,
                                                  uint64_t *__restrict__ unvis,
@@ -226,12 +249,16 @@ __device__ __forceinline__ void bc_push_chunks(const int32_t *__restrict__ ci, c
 // out-degree sum (rp), active size, its in-degree sum.  Workgroup g owns the g-th contiguous share of the vertices: it
 // counts, reserves its ranges with one atomic per counter and writes its
 // vertices in ascending order.
+// With cin (the counts of the level that wrote next), a level whose
+// frontier was empty compacts nothing.
 __global__ __launch_bounds__(256) void k_bc_compact(const int64_t *__restrict__ rp,
                                                     const int64_t *__restrict__ rpT, int64_t n,
                                                     const uint64_t *__restrict__ next, uint64_t *__restrict__ unvis,
                                                     int32_t *__restrict__ flist, int32_t *__restrict__ alist,
-                                                    unsigned long long *__restrict__ cnt)
+                                                    unsigned long long *__restrict__ cnt,
+                                                    const unsigned long long *__restrict__ cin)
 {
+    if (cin && cin[0] == 0) return;
     __shared__ unsigned sf[256], sa[256];
     __shared__ unsigned long long base_f, base_a, sum_ef, sum_ea;
     const int64_t share = (n + gridDim.x - 1) / gridDim.x;
@@ -378,8 +405,10 @@ __global__ __launch_bounds__(256) void k_bc_forward_combine(const int64_t *__res
                                                             const double *__restrict__ partial,
                                                             uint64_t *__restrict__ next,
                                                             const uint64_t *__restrict__ unvis,
-                                                            double *__restrict__ sigma)
+                                                            double *__restrict__ sigma,
+                                                            const unsigned long long *__restrict__ c)
 {
+    if (bc_direction(c) != 2) return;   // only after a pull
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const unsigned lane = lane_id();
@@ -413,30 +442,26 @@ __device__ __forceinline__ void bc_backward_chunks(const int32_t *__restrict__ c
     }
 }
 
-// A push level in one launch: the frontier's hub chunks, then its short
-// rows.  Both read sigma of frontier vertices and add into sigma of
-// unvisited ones (atomically): for each source lane the sets are disjoint.
-__global__ __launch_bounds__(256) void k_bc_push(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                 const int32_t *__restrict__ front, int64_t nf,
-                                                 const uint64_t *__restrict__ cur, uint64_t *next,
-                                                 const uint64_t *__restrict__ unvis, double *sigma, RowChunks ch)
+// A forward level in one launch, its direction taken on the device: push
+// over the frontier list (rows of A, hub chunks first), or pull over the
+// active list (rows of AT, the hub rows' chunks into partial first).
+__global__ __launch_bounds__(256) void k_bc_forward(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                    const int64_t *__restrict__ rpT, const int32_t *__restrict__ ciT,
+                                                    const int32_t *__restrict__ front,
+                                                    const int32_t *__restrict__ act,
+                                                    const uint64_t *__restrict__ cur, uint64_t *next,
+                                                    const uint64_t *__restrict__ unvis, double *sigma, RowChunks ch,
+                                                    RowChunks chT, double *__restrict__ partial,
+                                                    const unsigned long long *__restrict__ c)
 {
-    bc_push_chunks(ci, ch, cur, next, unvis, sigma);
-    bc_push_rows(rp, ci, front, nf, cur, next, unvis, sigma);
-}
-
-// A pull level in one launch: the hub rows' chunks (a wave each, into
-// partial), then the short rows.  The chunks read sigma of frontier
-// vertices; the short rows write sigma of unvisited ones: for each source
-// lane the two sets are disjoint.
-__global__ __launch_bounds__(256) void k_bc_pull(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                 const int32_t *__restrict__ act, int64_t na,
-                                                 const uint64_t *__restrict__ cur, uint64_t *__restrict__ next,
-                                                 const uint64_t *__restrict__ unvis, double *sigma, RowChunks ch,
-                                                 double *__restrict__ partial)
-{
-    bc_forward_chunks(ci, ch, cur, unvis, sigma, partial);
-    bc_pull_rows(rp, ci, act, na, cur, next, unvis, sigma);
+    const int dir = bc_direction(c);
+    if (dir == 1) {
+        bc_push_chunks(ci, ch, cur, next, unvis, sigma);
+        bc_push_rows(rp, ci, front, (int64_t)c[0], cur, next, unvis, sigma);
+    } else if (dir == 2) {
+        bc_forward_chunks(ciT, chT, cur, unvis, sigma, partial);
+        bc_pull_rows(rpT, ciT, act, (int64_t)c[2], cur, next, unvis, sigma);
+    }
 }
 
 // A backward level in one launch: the hub rows' chunks (with has_chunks),
@@ -492,57 +517,6 @@ __global__ __launch_bounds__(256) void k_bc_backward_combine(const int64_t *__re
 // machinery of the betweenness batches but no path counts: a vertex
 // reaches lane k at depth d + 1 when a neighbour is at depth d in lane k.
 
-// Pull over the active list (rows of at most BC_LONG neighbours): OR of the
-// neighbours' depth-d masks within the vertex's unreached lanes, stopping
-// once every unreached lane is found.
-__global__ __launch_bounds__(256) void k_ms_pull(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                 const int32_t *__restrict__ act, int64_t na,
-                                                 const uint64_t *__restrict__ cur, uint64_t *__restrict__ next,
-                                                 const uint64_t *__restrict__ unvis)
-{
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
-    const unsigned lane = lane_id();
-    for (int64_t q = wave; q < na; q += nw) {
-        const int64_t v = act[q];
-        const int64_t b = rp[v], e = rp[v + 1];
-        if (e - b > BC_LONG) continue;   // k_ms_pull_chunks
-        const uint64_t uv = unvis[v];
-        uint64_t acc = 0;
-        for (int64_t p0 = b; p0 < e && acc != uv; p0 += 64) {
-            const int64_t p = p0 + lane;
-            uint64_t m = p < e ? (cur[ci[p]] & uv) : 0;
-            for (int o = 32; o > 0; o >>= 1) m |= shfl64(m, (int)(lane ^ o));
-            acc |= m;
-        }
-        if (lane == 0 && acc) next[v] = acc;
-    }
-}
-
-// Pull for hub vertices with unreached lanes, one wave per chunk (OR-ed in).
-__global__ __launch_bounds__(256) void k_ms_pull_chunks(const int32_t *__restrict__ ci, RowChunks ch,
-                                                        const uint64_t *__restrict__ cur,
-                                                        uint64_t *__restrict__ next,
-                                                        const uint64_t *__restrict__ unvis)
-{
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
-    const unsigned lane = lane_id();
-    for (int64_t c = wave; c < ch.n; c += nw) {
-        const int64_t v = ch.row[c];
-        const uint64_t uv = unvis[v];
-        if (uv == 0) continue;
-        uint64_t acc = 0;
-        for (int64_t p0 = ch.beg[c]; p0 < ch.end[c] && acc != uv; p0 += 64) {
-            const int64_t p = p0 + lane;
-            uint64_t m = p < ch.end[c] ? (cur[ci[p]] & uv) : 0;
-            for (int o = 32; o > 0; o >>= 1) m |= shfl64(m, (int)(lane ^ o));
-            acc |= m;
-        }
-        if (lane == 0 && acc) atomicOr((unsigned long long *)&next[v], (unsigned long long)acc);
-    }
-}
-
 // Push from the frontier over the neighbour range [b, e) of u (lanes fm).
 __device__ __forceinline__ void ms_push_range(const int32_t *__restrict__ ci, int64_t b, int64_t e, uint64_t fm,
                                               const uint64_t *__restrict__ unvis, uint64_t *__restrict__ next,
@@ -555,33 +529,62 @@ __device__ __forceinline__ void ms_push_range(const int32_t *__restrict__ ci, in
     }
 }
 
-__global__ __launch_bounds__(256) void k_ms_push(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                 const int32_t *__restrict__ front, int64_t nf,
-                                                 const uint64_t *__restrict__ cur, uint64_t *__restrict__ next,
-                                                 const uint64_t *__restrict__ unvis)
+// A multi-source level in one launch, its direction taken on the device
+// from its counts c (bc_direction): push over the frontier list (hub
+// chunks, then short rows) or pull over the active list (short rows, then
+// the hub rows' chunks).
+__global__ __launch_bounds__(256) void k_ms_forward(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                    const int32_t *__restrict__ front,
+                                                    const int32_t *__restrict__ act,
+                                                    const uint64_t *__restrict__ cur, uint64_t *__restrict__ next,
+                                                    const uint64_t *__restrict__ unvis, RowChunks ch,
+                                                    const unsigned long long *__restrict__ c)
 {
+    const int dir = bc_direction(c);
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
     const unsigned lane = lane_id();
-    for (int64_t q = wave; q < nf; q += nw) {
-        const int64_t u = front[q];
-        const int64_t b = rp[u], e = rp[u + 1];
-        if (e - b > BC_LONG) continue;   // k_ms_push_chunks
-        ms_push_range(ci, b, e, cur[u], unvis, next, lane);
-    }
-}
-
-__global__ __launch_bounds__(256) void k_ms_push_chunks(const int32_t *__restrict__ ci, RowChunks ch,
-                                                        const uint64_t *__restrict__ cur,
-                                                        uint64_t *__restrict__ next,
-                                                        const uint64_t *__restrict__ unvis)
-{
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
-    const unsigned lane = lane_id();
-    for (int64_t c = wave; c < ch.n; c += nw) {
-        const uint64_t fm = cur[ch.row[c]];
-        if (fm) ms_push_range(ci, ch.beg[c], ch.end[c], fm, unvis, next, lane);
+    if (dir == 1) {
+        for (int64_t k = wave; k < ch.n; k += nw) {
+            const uint64_t fm = cur[ch.row[k]];
+            if (fm) ms_push_range(ci, ch.beg[k], ch.end[k], fm, unvis, next, lane);
+        }
+        const int64_t nf = (int64_t)c[0];
+        for (int64_t q = wave; q < nf; q += nw) {
+            const int64_t u = front[q];
+            const int64_t b = rp[u], e = rp[u + 1];
+            if (e - b > BC_LONG) continue;   // its chunks above
+            ms_push_range(ci, b, e, cur[u], unvis, next, lane);
+        }
+    } else if (dir == 2) {
+        const int64_t na = (int64_t)c[2];
+        for (int64_t q = wave; q < na; q += nw) {
+            const int64_t v = act[q];
+            const int64_t b = rp[v], e = rp[v + 1];
+            if (e - b > BC_LONG) continue;   // its chunks below
+            const uint64_t uv = unvis[v];
+            uint64_t acc = 0;
+            for (int64_t p0 = b; p0 < e && acc != uv; p0 += 64) {
+                const int64_t p = p0 + lane;
+                uint64_t m = p < e ? (cur[ci[p]] & uv) : 0;
+                for (int o = 32; o > 0; o >>= 1) m |= shfl64(m, (int)(lane ^ o));
+                acc |= m;
+            }
+            if (lane == 0 && acc) next[v] = acc;
+        }
+        for (int64_t k = wave; k < ch.n; k += nw) {
+            const int64_t v = ch.row[k];
+            const uint64_t uv = unvis[v];
+            if (uv == 0) continue;
+            uint64_t acc = 0;
+            for (int64_t p0 = ch.beg[k]; p0 < ch.end[k] && acc != uv; p0 += 64) {
+                const int64_t p = p0 + lane;
+                uint64_t m = p < ch.end[k] ? (cur[ci[p]] & uv) : 0;
+                for (int o = 32; o > 0; o >>= 1) m |= shfl64(m, (int)(lane ^ o));
+                acc |= m;
+            }
+            if (lane == 0 && acc) atomicOr((unsigned long long *)&next[v], (unsigned long long)acc);
+        }
     }
 }
 
@@ -589,10 +592,13 @@ __global__ __launch_bounds__(256) void k_ms_push_chunks(const int32_t *__restric
 // their masks): stats[k] += count, stats[64 + k] += count * d, stats[128 +
 // k] = max depth; with lev, lev[v * 64 + k] = d.  64 list entries per
 // wave step; one set of atomics per workgroup.
-__global__ __launch_bounds__(256) void k_ms_stats(const int32_t *__restrict__ front, int64_t nf,
+__global__ __launch_bounds__(256) void k_ms_stats(const int32_t *__restrict__ front,
+                                                  const unsigned long long *__restrict__ c,
                                                   const uint64_t *__restrict__ mask, int64_t d,
                                                   uint16_t *__restrict__ lev, unsigned long long *__restrict__ stats)
 {
+    const int64_t nf = (int64_t)c[0];   // the level's size, from its counts
+    if (nf == 0) return;
     __shared__ unsigned long long cnt[64];
     if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -660,7 +666,7 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
     double *Wv = (double *)ws_get(ctx, WS_BC_W, sizeof(double) * 64 * n1);
     uint64_t *unvis = (uint64_t *)ws_get(ctx, WS_BC_UNVIS, sizeof(uint64_t) * n1);
     int32_t *acts = (int32_t *)ws_get(ctx, WS_BC_ACT, sizeof(int32_t) * 2 * n1);
-    unsigned long long *cnt = (unsigned long long *)ws_get(ctx, WS_BC_CNT, 64);
+    unsigned long long *cnt = (unsigned long long *)ws_get(ctx, WS_BC_CNT, sizeof(unsigned long long) * 4 * BC_RING);
     int64_t *dsrc = (int64_t *)ws_get(ctx, WS_BFS_D, sizeof(int64_t) * 64 + 64);
     if (!sigma || !Wv || !unvis || !acts || !cnt || !dsrc) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc workspace");
     int rc = LAGR_SUCCESS;
@@ -719,22 +725,26 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
         cblocksT = grid_for(chT.n * 64, 256, 16384);
     }
     const unsigned compact_blocks = (unsigned)(n > 0 ? (ctx->num_cus < n ? ctx->num_cus : n) : 1);
-    int32_t *act_cur = acts, *act_next = acts + n1;
-    // compaction after a level: returns frontier size / degree sum, active
-    // size / degree sum
-    unsigned long long h[4];
-    auto compact = [&](const uint64_t *next, int32_t *flist) -> int {
-        TRY(fill_i64(ctx, (int64_t *)cnt, 4, 0, msg));
+    // the active list of level d is acts + (d & 1) n1; the counts of level d
+    // (frontier size and out-degree sum, active size and in-degree sum) are
+    // slot d % BC_RING of the counter ring, written by the compaction of
+    // level d - 1 and read on the device by level d's kernels
+    auto act_of = [&](size_t d) { return acts + (d & 1) * n1; };
+    auto slot = [&](size_t d) { return cnt + 4 * (d % BC_RING); };
+    auto compact = [&](const uint64_t *next, size_t d_next, const unsigned long long *cin) -> int {
         if (n > 0) {
-            hipLaunchKernelGGL(k_bc_compact, dim3(compact_blocks), dim3(256), 0, ctx->stream, A->rowptr, AT->rowptr, n, next,
-                               unvis, flist, act_next, cnt);
+            hipLaunchKernelGGL(k_bc_compact, dim3(compact_blocks), dim3(256), 0, ctx->stream, A->rowptr, AT->rowptr,
+                               n, next, unvis, lists(d_next), act_of(d_next), slot(d_next), cin);
             LAUNCH_CHECK();
         }
-        TRY(read_back(ctx, h, cnt, sizeof(h), msg));
-        std::swap(act_cur, act_next);
         return LAGR_SUCCESS;
     };
     auto wgrid = [](int64_t items) { return grid_for(items * 64, 256, 16384); };
+    // forward levels run with a fixed grid (their loops stride over the
+    // lists), so the host queues them without knowing the counts
+    unsigned fgrid = BC_FORWARD_GRID;
+    if (cblocks > fgrid) fgrid = cblocks;
+    if (cblocksT > fgrid) fgrid = cblocksT;
     std::vector<int64_t> nlev;
     for (int b = 0; b < nbatches; b++) {
         const int64_t *src = lane_src + 64 * b;
@@ -749,44 +759,57 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
             BC_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bc sources copy"));
         // push adds into sigma, so every unreached (vertex, lane) starts at 0
         BC_TRY(fill_i64(ctx, (int64_t *)sigma, n * 64, 0, msg));
+        BC_TRY(fill_i64(ctx, (int64_t *)cnt, 4 * BC_RING, 0, msg));
         hipLaunchKernelGGL(k_bc_init, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, n,
                            lanes, unvis, m0);
         BC_LAUNCHED();
         hipLaunchKernelGGL(k_bc_sources, dim3(1), dim3(64), 0, ctx->stream, dsrc, unvis, m0, sigma);
         BC_LAUNCHED();
-        BC_TRY(compact(m0, lists(0)));
-        nlev.assign(1, (int64_t)h[0]);
-        // forward sweep: depth d -> d + 1 until no lane advances
+        BC_TRY(compact(m0, 0, nullptr));
+        // forward sweep: depth d -> d + 1 until no lane advances, queued a
+        // chunk of levels at a time (BC_FIRST_LEVELS, then BC_MORE_LEVELS);
+        // after each chunk one read of its levels' frontier sizes
+        nlev.clear();
+        size_t d0 = 0;
         size_t depth = 0;
-        while (true) {
-            const int64_t nf = (int64_t)h[0], ef = (int64_t)h[1], na = (int64_t)h[2], ea = (int64_t)h[3];
-            uint64_t *next = level_buf(depth + 1);
-            if (!next) BC_TRY(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc level buffers"));
-            BC_TRY(fill_i64(ctx, (int64_t *)next, n, 0, msg));
-            const bool push = ef * BC_PUSH_RATIO < ea;
-            if (push) {
-                const unsigned qg = ch.n > 0 && cblocks > wgrid(nf) ? cblocks : wgrid(nf);
+        bool done = false;
+        for (size_t chunk = BC_FIRST_LEVELS; !done; chunk = BC_MORE_LEVELS) {
+            if (d0 + chunk > (size_t)n + 2) BC_TRY(lagr_fail(msg, LAGR_DEVICE_ERROR, "bc forward sweep did not end"));
+            // the slots the chunk's compactions add to start from zero
+            for (size_t d = d0 + 1; d <= d0 + chunk; d++)
+                if (d >= BC_RING) BC_TRY(fill_i64(ctx, (int64_t *)slot(d), 4, 0, msg));
+            for (size_t d = d0; d < d0 + chunk; d++) {
+                uint64_t *next = level_buf(d + 1);
+                if (!next) BC_TRY(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "bc level buffers"));
+                BC_TRY(fill_i64(ctx, (int64_t *)next, n, 0, msg));
                 TIMED(ctx, "bc_forward",
-                      hipLaunchKernelGGL(k_bc_push, dim3(qg), dim3(256), 0, ctx->stream, A->rowptr, A->colidx,
-                                         lists(depth), nf, levels(depth), next, unvis, sigma, ch));
-                BC_LAUNCHED();
-            } else if (na > 0) {
-                const unsigned pg = chT.n > 0 && cblocksT > wgrid(na) ? cblocksT : wgrid(na);
-                TIMED(ctx, "bc_forward",
-                      hipLaunchKernelGGL(k_bc_pull, dim3(pg), dim3(256), 0, ctx->stream, AT->rowptr, AT->colidx,
-                                         act_cur, na, levels(depth), next, unvis, sigma, chT, partial));
+                      hipLaunchKernelGGL(k_bc_forward, dim3(fgrid), dim3(256), 0, ctx->stream, A->rowptr, A->colidx,
+                                         AT->rowptr, AT->colidx, lists(d), act_of(d), levels(d), next, unvis, sigma,
+                                         ch, chT, partial, slot(d)));
                 BC_LAUNCHED();
                 if (chT.n > 0) {
                     hipLaunchKernelGGL(k_bc_forward_combine, dim3(cblocksT), dim3(256), 0, ctx->stream,
-                                       AT->rowptr, chT, partial, next, unvis, sigma);
+                                       AT->rowptr, chT, partial, next, unvis, sigma, slot(d));
                     BC_LAUNCHED();
                 }
+                BC_TRY(compact(next, d + 1, slot(d)));
             }
-            BC_TRY(compact(next, lists(depth + 1)));
-            if (h[0] == 0) break;
-            depth++;
-            nlev.push_back((int64_t)h[0]);
+            // the frontier sizes of levels d0 .. d0 + chunk: one read of the ring
+            unsigned long long ring[4 * BC_RING];
+            BC_TRY(stage_to_host(ctx, 0, cnt, sizeof(ring), true, msg));
+            memcpy(ring, ctx->pinned, sizeof(ring));
+            for (size_t d = d0; d <= d0 + chunk; d++) {
+                if (d < nlev.size()) continue;   // level d0 was read with the previous chunk
+                const unsigned long long nf = ring[4 * (d % BC_RING)];
+                if (nf == 0) {
+                    done = true;
+                    break;
+                }
+                nlev.push_back((int64_t)nf);
+            }
+            d0 += chunk;
         }
+        depth = nlev.size() - 1;   // the deepest non-empty level
         // backward sweep: targets at depth i-1 gather from depth i
         for (size_t i = depth + 1; i >= 2; i--) {
             const int has_deeper = i <= depth ? 1 : 0;
@@ -818,6 +841,97 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
 // the number of reached vertices (the source included), the sum of their
 // levels and the largest level into stats[3][64] (host); with lev
 // (n x 64 uint16), every reached (vertex, lane)'s level, 0xFFFF elsewhere.
+//
+// The levels' directions and their end are decided on the device (each
+// level's kernels read the counts the previous compaction left), so the
+// host queues the start and the first MS_FIRST_LEVELS levels at once --
+// replayed from a hipGraph captured once per context and buffer set -- and
+// reads the frontier sizes once; deeper searches continue MS_MORE_LEVELS
+// levels per read.
+constexpr size_t MS_FIRST_LEVELS = 8;
+constexpr size_t MS_MORE_LEVELS = 4;
+
+namespace {
+// k_bc_init with the lane mask from src[64] (the sources' copy carries it,
+// so a captured start serves any set of lanes)
+__global__ __launch_bounds__(256) void k_ms_init(int64_t n, const int64_t *__restrict__ src,
+                                                 uint64_t *__restrict__ unvis, uint64_t *__restrict__ mask0)
+{
+    const uint64_t lanes = (uint64_t)src[64];
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        unvis[v] = lanes;
+        mask0[v] = 0;
+    }
+}
+
+template <class T>
+__global__ void k_set(T *__restrict__ p, int64_t n, T v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+struct MsBufs {
+    const int64_t *rp;
+    const int32_t *ci;
+    int64_t n;
+    uint64_t lanes;
+    uint64_t *unvis;
+    int32_t *acts;
+    unsigned long long *cnt;
+    int64_t *dsrc;
+    unsigned long long *dstats;
+    uint64_t *mask[2];
+    int32_t *list[2];
+    uint16_t *lev;
+    RowChunks ch;
+    unsigned compact_blocks;
+};
+
+// Queue levels d0 .. d0 + count - 1 (and, with start, the search's start)
+// on stream s.
+int ms_enqueue(const MsBufs &B, hipStream_t s, bool start, size_t d0, size_t count, char *msg)
+{
+    const int64_t n = B.n;
+    const size_t n1 = (size_t)(n > 0 ? n : 1);
+    auto slot = [&](size_t d) { return B.cnt + 4 * (d % BC_RING); };
+    auto act_of = [&](size_t d) { return B.acts + (d & 1) * n1; };
+    if (start) {
+        hipLaunchKernelGGL(k_set<int64_t>, dim3(1), dim3(64), 0, s, (int64_t *)B.cnt, (int64_t)(4 * BC_RING), (int64_t)0);
+        if (B.lev)
+            hipLaunchKernelGGL(k_set<uint32_t>, dim3(grid_for(n * 32, 256, 16384)), dim3(256), 0, s,
+                               (uint32_t *)B.lev, n * 32, 0xFFFFFFFFu);
+        hipLaunchKernelGGL(k_ms_init, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, B.dsrc, B.unvis, B.mask[0]);
+        hipLaunchKernelGGL(k_ms_sources, dim3(1), dim3(64), 0, s, B.dsrc, B.unvis, B.mask[0], B.dstats);
+        if (n > 0)
+            hipLaunchKernelGGL(k_bc_compact, dim3(B.compact_blocks), dim3(256), 0, s, B.rp, B.rp, n, B.mask[0],
+                               B.unvis, B.list[0], act_of(0), slot(0), (const unsigned long long *)nullptr);
+        hipLaunchKernelGGL(k_ms_stats, dim3(256), dim3(256), 0, s, B.list[0], slot(0), B.mask[0], (int64_t)0, B.lev,
+                           B.dstats);
+        LAUNCH_CHECK();
+    } else {
+        // the slots these levels' compactions add to start from zero
+        for (size_t d = d0 + 1; d <= d0 + count; d++)
+            hipLaunchKernelGGL(k_set<int64_t>, dim3(1), dim3(64), 0, s, (int64_t *)slot(d), (int64_t)4, (int64_t)0);
+    }
+    for (size_t d = d0; d < d0 + count; d++) {
+        const int b = (int)(d & 1);
+        uint64_t *cur = B.mask[b], *next = B.mask[b ^ 1];
+        hipLaunchKernelGGL(k_set<int64_t>, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, (int64_t *)next, n,
+                           (int64_t)0);
+        hipLaunchKernelGGL(k_ms_forward, dim3(BC_FORWARD_GRID), dim3(256), 0, s, B.rp, B.ci, B.list[b], act_of(d),
+                           cur, next, B.unvis, B.ch, slot(d));
+        if (n > 0)
+            hipLaunchKernelGGL(k_bc_compact, dim3(B.compact_blocks), dim3(256), 0, s, B.rp, B.rp, n, next, B.unvis,
+                               B.list[b ^ 1], act_of(d + 1), slot(d + 1), slot(d));
+        hipLaunchKernelGGL(k_ms_stats, dim3(256), dim3(256), 0, s, B.list[b ^ 1], slot(d + 1), next,
+                           (int64_t)(d + 1), B.lev, B.dstats);
+        LAUNCH_CHECK();
+    }
+    return LAGR_SUCCESS;
+}
+}  // namespace
+
 int msbfs_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, uint16_t *lev, int64_t *stats,
                   char *msg)
 {
@@ -826,7 +940,7 @@ int msbfs_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, uin
     const size_t n1 = (size_t)(n > 0 ? n : 1);
     uint64_t *unvis = (uint64_t *)ws_get(ctx, WS_BC_UNVIS, sizeof(uint64_t) * n1);
     int32_t *acts = (int32_t *)ws_get(ctx, WS_BC_ACT, sizeof(int32_t) * 2 * n1);
-    unsigned long long *cnt = (unsigned long long *)ws_get(ctx, WS_BC_CNT, 64);
+    unsigned long long *cnt = (unsigned long long *)ws_get(ctx, WS_BC_CNT, sizeof(unsigned long long) * 4 * BC_RING);
     int64_t *dsrc = (int64_t *)ws_get(ctx, WS_BFS_D, sizeof(int64_t) * 64 + 64);
     unsigned long long *dstats = (unsigned long long *)ws_get(ctx, WS_BFS_E, sizeof(int64_t) * 3 * 64);
     if (!unvis || !acts || !cnt || !dsrc || !dstats) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "msbfs workspace");
@@ -845,68 +959,73 @@ int msbfs_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, uin
         if (!p) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "msbfs level buffers");
         ctx->lvpool.push_back(p);
     }
-    auto mask_of = [&](int b) { return (uint64_t *)ctx->lvpool[b]; };
-    auto list_of = [&](int b) { return (int32_t *)((char *)ctx->lvpool[b] + mask_bytes); };
-    uint64_t lanes = 0;
+    MsBufs B;
+    B.rp = A->rowptr;
+    B.ci = A->colidx;
+    B.n = n;
+    B.lanes = 0;
     for (int k = 0; k < 64; k++)
-        if (lane_src[k] >= 0) lanes |= 1ull << k;
-    RowChunks ch;
-    TRY(graph_chunks(G, ctx, &ch, msg));
-    const unsigned cblocks = ch.n > 0 ? grid_for(ch.n * 64, 256, 16384) : 1;
-    const unsigned compact_blocks = (unsigned)(n > 0 ? (ctx->num_cus < n ? ctx->num_cus : n) : 1);
-    int32_t *act_cur = acts, *act_next = acts + n1;
-    unsigned long long h[4];
-    auto compact = [&](const uint64_t *next, int32_t *flist) -> int {
-        TRY(fill_i64(ctx, (int64_t *)cnt, 4, 0, msg));
-        if (n > 0) {
-            hipLaunchKernelGGL(k_bc_compact, dim3(compact_blocks), dim3(256), 0, ctx->stream, A->rowptr, A->rowptr, n, next,
-                               unvis, flist, act_next, cnt);
-            LAUNCH_CHECK();
+        if (lane_src[k] >= 0) B.lanes |= 1ull << k;
+    B.unvis = unvis;
+    B.acts = acts;
+    B.cnt = cnt;
+    B.dsrc = dsrc;
+    B.dstats = dstats;
+    for (int b = 0; b < 2; b++) {
+        B.mask[b] = (uint64_t *)ctx->lvpool[b];
+        B.list[b] = (int32_t *)((char *)ctx->lvpool[b] + mask_bytes);
+    }
+    B.lev = lev;
+    TRY(graph_chunks(G, ctx, &B.ch, msg));
+    B.compact_blocks = (unsigned)(n > 0 ? (ctx->num_cus < n ? ctx->num_cus : n) : 1);
+    // the sources and the lane mask; the copy is from pinned staging
+    int64_t *stage = (int64_t *)((char *)ctx->pinned + 2048);
+    HIP_TRY(hipStreamSynchronize(ctx->stream));   // the staging area is free
+    memcpy(stage, lane_src, sizeof(int64_t) * 64);
+    stage[64] = (int64_t)B.lanes;
+    HIP_TRY(hipMemcpyAsync(dsrc, stage, sizeof(int64_t) * 65, hipMemcpyHostToDevice, ctx->stream));
+    // the start and the first levels: the context's captured graph for this
+    // buffer set (every argument of its nodes), captured on first use
+    const std::vector<uintptr_t> key = {(uintptr_t)B.rp, (uintptr_t)B.ci, (uintptr_t)n,
+                                        (uintptr_t)unvis, (uintptr_t)acts, (uintptr_t)cnt, (uintptr_t)dsrc,
+                                        (uintptr_t)dstats, (uintptr_t)B.mask[0], (uintptr_t)B.mask[1],
+                                        (uintptr_t)lev, (uintptr_t)B.ch.n, (uintptr_t)B.ch.row,
+                                        (uintptr_t)B.compact_blocks};
+    if (!ctx->ms_exec || ctx->ms_key != key) {
+        if (ctx->ms_exec) (void)hipGraphExecDestroy(ctx->ms_exec);
+        ctx->ms_exec = nullptr;
+        ctx->ms_key.clear();
+        if (!ctx->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+        const int rc = ms_enqueue(B, ctx->capture_stream, true, 0, MS_FIRST_LEVELS, msg);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(ctx->capture_stream, &g);
+        if (rc < 0 || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc < 0 ? rc : lagr_fail(msg, LAGR_DEVICE_ERROR, "msbfs capture: %s", hipGetErrorString(e));
         }
-        TRY(read_back(ctx, h, cnt, sizeof(h), msg));
-        std::swap(act_cur, act_next);
-        return LAGR_SUCCESS;
-    };
-    auto wgrid = [](int64_t items) { return grid_for(items * 64, 256, 16384); };
-    auto stats_of = [&](const int32_t *flist, int64_t nf, const uint64_t *mask, int64_t d) -> int {
-        if (nf > 0) {
-            hipLaunchKernelGGL(k_ms_stats, dim3(grid_for(nf, 256, 256)), dim3(256), 0, ctx->stream, flist, nf, mask,
-                               d, lev, dstats);
-            LAUNCH_CHECK();
+        const hipError_t ei = hipGraphInstantiate(&ctx->ms_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            ctx->ms_exec = nullptr;
+            return lagr_fail(msg, LAGR_DEVICE_ERROR, "msbfs graph: %s", hipGetErrorString(ei));
         }
-        return LAGR_SUCCESS;
-    };
-    HIP_TRY(hipMemcpyAsync(dsrc, lane_src, sizeof(int64_t) * 64, hipMemcpyHostToDevice, ctx->stream));
-    if (lev) TRY(fill_u32(ctx, (uint32_t *)lev, n * 32, 0xFFFFFFFFu, msg));
-    uint64_t *m0 = mask_of(0);
-    hipLaunchKernelGGL(k_bc_init, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, n, lanes, unvis, m0);
-    hipLaunchKernelGGL(k_ms_sources, dim3(1), dim3(64), 0, ctx->stream, dsrc, unvis, m0, dstats);
-    LAUNCH_CHECK();
-    TRY(compact(m0, list_of(0)));
-    TRY(stats_of(list_of(0), (int64_t)h[0], m0, 0));
-    int b = 0;
-    for (int64_t d = 1; d < 65535; d++) {
-        const int64_t nf = (int64_t)h[0], ef = (int64_t)h[1], na = (int64_t)h[2], ea = (int64_t)h[3];
-        uint64_t *cur = mask_of(b), *next = mask_of(b ^ 1);
-        TRY(fill_i64(ctx, (int64_t *)next, n, 0, msg));
-        if (ef * BC_PUSH_RATIO < ea) {
-            hipLaunchKernelGGL(k_ms_push, dim3(wgrid(nf)), dim3(256), 0, ctx->stream, A->rowptr, A->colidx,
-                               list_of(b), nf, cur, next, unvis);
-            if (ch.n > 0)
-                hipLaunchKernelGGL(k_ms_push_chunks, dim3(cblocks), dim3(256), 0, ctx->stream, A->colidx, ch, cur,
-                                   next, unvis);
-        } else if (na > 0) {
-            hipLaunchKernelGGL(k_ms_pull, dim3(wgrid(na)), dim3(256), 0, ctx->stream, A->rowptr, A->colidx,
-                               act_cur, na, cur, next, unvis);
-            if (ch.n > 0)
-                hipLaunchKernelGGL(k_ms_pull_chunks, dim3(cblocks), dim3(256), 0, ctx->stream, A->colidx, ch, cur,
-                                   next, unvis);
-        }
-        LAUNCH_CHECK();
-        TRY(compact(next, list_of(b ^ 1)));
-        if (h[0] == 0) break;
-        TRY(stats_of(list_of(b ^ 1), (int64_t)h[0], next, d));
-        b ^= 1;
+        ctx->ms_key = key;
+    }
+    HIP_TRY(hipGraphLaunch(ctx->ms_exec, ctx->stream));
+    // read the frontier sizes (one read of the counter ring per chunk)
+    size_t d0 = 0;
+    for (size_t chunk = MS_FIRST_LEVELS;; chunk = MS_MORE_LEVELS) {
+        unsigned long long ring[4 * BC_RING];
+        TRY(stage_to_host(ctx, 0, cnt, sizeof(ring), true, msg));
+        memcpy(ring, ctx->pinned, sizeof(ring));
+        bool done = false;
+        for (size_t d = d0 + 1; d <= d0 + chunk; d++)
+            if (ring[4 * (d % BC_RING)] == 0) done = true;
+        if (done) break;
+        d0 += chunk;
+        if (d0 + MS_MORE_LEVELS >= 65535) return lagr_fail(msg, LAGR_DEVICE_ERROR, "msbfs did not end");
+        TRY(ms_enqueue(B, ctx->stream, false, d0, MS_MORE_LEVELS, msg));
     }
     TRY(stage_to_host(ctx, 0, dstats, 8 * 3 * 64, true, msg));
     memcpy(stats, ctx->pinned, 8 * 3 * 64);

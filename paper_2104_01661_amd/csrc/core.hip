@@ -119,6 +119,7 @@ extern "C" int lagr_ctx_free(lagr_ctx *ctx)
     if (c->bfs_exec_more) (void)hipGraphExecDestroy(c->bfs_exec_more);
     if (c->bfs_graph) (void)hipGraphDestroy(c->bfs_graph);
     if (c->sssp_exec) (void)hipGraphExecDestroy(c->sssp_exec);
+    if (c->ms_exec) (void)hipGraphExecDestroy(c->ms_exec);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     timers_clear(c);
     for (int s = 0; s < WS_NSLOTS; s++) dev_free(c->ws[s], c->ws_bytes[s]);

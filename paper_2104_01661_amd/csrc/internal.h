@@ -122,6 +122,10 @@ struct lagr_ctx_s {
     int64_t bfs_key = -1;
     void *bfs_state = nullptr;
     void *bfs_ctr = nullptr;
+    // multi-source BFS: captured start and first levels, keyed by every
+    // argument of their nodes
+    hipGraphExec_t ms_exec = nullptr;
+    std::vector<uintptr_t> ms_key;
     // SSSP: captured two-step graph, keyed the same way
     hipGraphExec_t sssp_exec = nullptr;
     int64_t sssp_key = -1;
