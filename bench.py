@@ -428,6 +428,15 @@ def main():
         depths.append(int(lvl.max()))
     n_small_component = sum(1 for m in reached_edges if m < nnzA // 4)
 
+    # ------------------------------------------------------------ tuning
+    # untimed set-up: the graph's count-plan hub columns and BFS direction
+    # thresholds, each picked by timing its candidates on this graph
+    log("autotuning the count plan's hub columns and the BFS thresholds")
+    t0 = time.perf_counter()
+    tuned_hubs = L.lagr_tc_autotune(G, ctx)
+    tuned_ab = L.lagr_bfs_autotune(G, sources, ctx)
+    tune_s = time.perf_counter() - t0
+
     # -------------------------------------------------------------- step
     log("timed steps (TC + 64 BFS) on the s20 graph")
     ev_tc = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -559,7 +568,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["name"], "vertices": n, "entries_A": nnzA,
                    "undirected_edges": nnzL, "triangles": tc_counts[0],
-                   "bfs_sources": len(sources)},
+                   "bfs_sources": len(sources),
+                   "tuned": {"tc_hub_columns": tuned_hubs, "bfs_alpha": tuned_ab[0], "bfs_beta": tuned_ab[1],
+                             "seconds": round(tune_s, 3)}},
         "tc": {"ms_median": round(tc_med, 4), "edges_per_s_prepared":
                round(nnzL / (float(np.median(prep)) * 1e-3), 1),
                "ms_prepared_median": round(float(np.median(prep)), 4)},
@@ -570,6 +581,27 @@ def main():
         "roofline_bfs": roofline_bfs,
         "step_share": step_share,
     }
+
+    # ------------------------------ the 64 sources as one batched search
+    log("batched multi-source BFS leg")
+    L.lagr_bfs_batch(G, sources, ctx, want_levels=False)
+    bb_ms = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, bb_reached, _, _ = L.lagr_bfs_batch(G, sources, ctx, want_levels=False)
+        e1.record()
+        torch.cuda.synchronize()
+        bb_ms.append(e0.elapsed_time(e1))
+    assert list(bb_reached) == reached_vertices, "batched and single-source searches reach different sets"
+    bb = float(np.median(bb_ms))
+    out["bfs_batched"] = {"sources": len(sources), "ms_all_sources": round(bb, 4),
+                          "gteps_aggregate": round(float(np.sum(reached_edges)) / (bb * 1e-3) / 1e9, 4),
+                          "speedup_vs_per_source_calls": round(float(np.sum(bfs_med_per_src)) / bb, 3),
+                          "output": "levels of every (source, vertex) (no parents); one multi-source search "
+                                    "with a 64-bit lane mask per vertex, start and first 8 levels replayed from "
+                                    "a captured hipGraph"}
 
     # ------------------------------------- triangle-count latency (2^10)
     log("triangle-count latency leg (2^10)")

@@ -324,6 +324,18 @@ int lagr_property_at(lagr_graph G, lagr_ctx ctx, char *msg);
  * operand (Section V, DeleteProperties).  The results of lagr_graph_check
  * (ndiag, symmetry) describe A, which a graph never changes, and are kept. */
 int lagr_graph_delete_properties(lagr_graph G, lagr_ctx ctx, char *msg);
+/* Tuning settings kept in G (lagr_graph_delete_properties keeps them):
+ * tc_hubs, the count plan's hub columns (-1: the default, n/256 capped at
+ * 4,096 from 2^18 vertices on, else none; changing it drops the cached
+ * triangle-count operand, after
+ * waiting for ctx's stream), and the BFS direction thresholds alpha and
+ * beta (> 0; -1 keeps the current value).  Other values fail with
+ * LAGR_INVALID_VALUE.  lagr_graph_get_tuning reads the three back (NULL
+ * pointers are skipped).  lagr_tc_autotune and lagr_bfs_autotune set them
+ * by timing. */
+int lagr_graph_set_tuning(lagr_graph G, int64_t tc_hubs, int32_t bfs_alpha, int32_t bfs_beta, lagr_ctx ctx,
+                          char *msg);
+int lagr_graph_get_tuning(int64_t *tc_hubs, int32_t *bfs_alpha, int32_t *bfs_beta, const lagr_graph G, char *msg);
 /* Borrowed read access to G->A and to the cached triangle-count operand
  * (NULL if not computed).  The handles stay owned by G: do not free them. */
 int lagr_graph_matrix(lagr_matrix *A, const lagr_graph G, char *msg);
@@ -358,6 +370,14 @@ int lagr_tc_adv(int64_t *ntriangles, const lagr_graph G, lagr_ctx ctx, char *msg
  * lagr_property_tc_lower has not been computed. */
 int lagr_tc_adv_noalloc(int64_t *ntriangles_dev, const lagr_graph G, lagr_ctx ctx, char *msg);
 
+/* The count plan's hub columns of G, picked by timing: each candidate
+ * (none, or n/1024 .. n/128 of the highest-degree vertices, at most 4,096)
+ * rebuilds the triangle-count preparation and times lagr_tc (median of 3);
+ * the fastest is kept in G (it survives lagr_graph_delete_properties) and
+ * the operand is left built.  hubs (may be NULL): the chosen count.  Every
+ * candidate must give the same count (else LAGR_DEVICE_ERROR). */
+int lagr_tc_autotune(int64_t *hubs, lagr_graph G, lagr_ctx ctx, char *msg);
+
 /* Breadth-first search (Section IV-A, Algorithms 1-2).  Outputs (either
  * may be NULL): level, an INT64 FULL vector (source 0, -1 unreached) and
  * parent, an INT64 FULL vector (parent(src) = src, -1 unreached).  Each
@@ -379,6 +399,31 @@ int lagr_tc_adv_noalloc(int64_t *ntriangles_dev, const lagr_graph G, lagr_ctx ct
 #define LAGR_BFS_ANY_PARENT 2u
 int lagr_bfs(lagr_vector *level, lagr_vector *parent, const lagr_graph G, int64_t source,
              uint32_t flags, lagr_ctx ctx, char *msg);
+
+/* BFS direction thresholds of G, picked by timing lagr_bfs from the HOST
+ * int64 sources[ns] (total over the sources) for alpha in {6, 10, 14, 20,
+ * 32} x beta in {12, 24, 48}: a level pulls when its frontier's edges
+ * exceed the unexplored edges / alpha and pushes again below n / beta
+ * frontier vertices.  The pair is kept in G for later searches (levels and
+ * default parents do not depend on it); alpha, beta (may be NULL) return
+ * it. */
+int lagr_bfs_autotune(int32_t *alpha, int32_t *beta, lagr_graph G, const int64_t *sources, int32_t ns,
+                      lagr_ctx ctx, char *msg);
+
+/* Breadth-first search from many sources at once: Algorithm 1 with a
+ * matrix frontier, Q<!s(P), r> = Q any.secondi A for a block of up to 64
+ * sources (one wavefront lane each, 64-bit lane masks per vertex), push or
+ * pull per level as lagr_bfs chooses.  The start and the first 8 levels of
+ * each block replay one captured hipGraph; the level directions and the end
+ * are decided on the device.  sources: HOST int64[ns] (repeats allowed).
+ * Outputs (each may be NULL): levels, a caller-owned DEVICE int32 array of
+ * ns x n (row k: the level of every vertex from sources[k], -1 unreached);
+ * reached, level_sum, depth: caller-owned HOST int64 arrays of ns (vertices
+ * reached with the source, the sum of their levels, the largest level).
+ * Undirected graphs only (LAGR_INVALID_VALUE otherwise); LAGR_INVALID_INDEX
+ * for a source outside [0, n).  Synchronises. */
+int lagr_bfs_batch(int32_t *levels, int64_t *reached, int64_t *level_sum, int64_t *depth, const lagr_graph G,
+                   const int64_t *sources, int32_t ns, lagr_ctx ctx, char *msg);
 
 /* Batched betweenness centrality (Section IV-B, Algorithm 3): unnormalised
  * sum over the given sources of the dependency of every vertex, where a

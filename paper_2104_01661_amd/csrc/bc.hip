@@ -1032,6 +1032,66 @@ int msbfs_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, uin
     return LAGR_SUCCESS;
 }
 
+namespace {
+// levels[k * n + v] = level of v from lane k's source (-1 unreached), for
+// lanes k < nl, from the lane-major 16-bit levels lev[v * 64 + k]
+__global__ __launch_bounds__(256) void k_lanes_to_rows(const uint16_t *__restrict__ lev, int64_t n, int nl,
+                                                       int32_t *__restrict__ levels)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    // a wave reads 64 vertices' 64 lanes (8 KB) and writes 64 consecutive
+    // vertices of each row
+    for (int64_t v0 = wave * 64; v0 < n; v0 += nw * 64) {
+        for (int k = 0; k < nl; k++) {
+            const int64_t v = v0 + lane;
+            if (v < n) {
+                const uint16_t x = lev[v * 64 + k];
+                levels[(int64_t)k * n + v] = x == 0xFFFF ? -1 : (int32_t)x;
+            }
+        }
+    }
+}
+}  // namespace
+
+extern "C" int lagr_bfs_batch(int32_t *levels, int64_t *reached, int64_t *level_sum, int64_t *depth,
+                              const lagr_graph G, const int64_t *sources, int32_t ns, lagr_ctx ctx, char *msg)
+{
+    if (!G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    if (ns < 0 || (ns > 0 && !sources)) return lagr_fail(msg, LAGR_INVALID_VALUE, "bad sources");
+    if (G->kind != LAGR_ADJACENCY_UNDIRECTED)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "the batched search needs an undirected graph");
+    const int64_t n = G->A->nrows;
+    for (int32_t k = 0; k < ns; k++)
+        if (sources[k] < 0 || sources[k] >= n)
+            return lagr_fail(msg, LAGR_INVALID_INDEX, "source %lld out of range", (long long)sources[k]);
+    uint16_t *lev = nullptr;
+    if (levels) {
+        lev = (uint16_t *)ws_get(ctx, WS_GEN_A, sizeof(uint16_t) * 64 * (size_t)(n > 0 ? n : 1));
+        if (!lev) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "level lanes");
+    }
+    for (int32_t b0 = 0; b0 < ns; b0 += 64) {
+        const int nl = ns - b0 < 64 ? ns - b0 : 64;
+        int64_t src[64];
+        for (int k = 0; k < 64; k++) src[k] = k < nl ? sources[b0 + k] : -1;
+        int64_t st[3 * 64];
+        TRY(msbfs_compute(ctx, G, src, lev, st, msg));
+        for (int k = 0; k < nl; k++) {
+            if (reached) reached[b0 + k] = st[k];
+            if (level_sum) level_sum[b0 + k] = st[64 + k];
+            if (depth) depth[b0 + k] = st[128 + k];
+        }
+        if (levels && n > 0) {
+            hipLaunchKernelGGL(k_lanes_to_rows, dim3(grid_for(n, 256, 4096)), dim3(256), 0, ctx->stream, lev, n, nl,
+                               levels + (int64_t)b0 * n);
+            LAUNCH_CHECK();
+        }
+    }
+    if (levels) HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return lagr_ok(msg);
+}
+
 extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const int64_t *sources,
                        int32_t ns, lagr_ctx ctx, char *msg)
 {

@@ -26,14 +26,14 @@
 // levels are nodes of a hipGraph built once per context; the host watches
 // pinned words that the kernels store and queues further levels only when
 // the first ones did not finish the search.
+#include <algorithm>
 #include <atomic>
+#include <chrono>
 
 #include "internal.h"
 
 namespace {
 
-constexpr int BFS_ALPHA = 14;
-constexpr int BFS_BETA = 24;
 constexpr unsigned BFS_GRID = 2048;        // workgroups of a level kernel
 constexpr int BFS_SPREAD = 16;             // vertex, degree and hub counters
 constexpr int BFS_NCTR = 3 * BFS_SPREAD;
@@ -81,6 +81,7 @@ struct BfsDev {
     unsigned long long *ctr;  // BFS_NCTR counters, BFS_CTR_STRIDE words apart
     RowChunks ch;
     int32_t any_parent, push_only;
+    int32_t alpha, beta;      // direction thresholds
     int64_t src;
     int32_t *done_host;       // pinned host word set when the search ends
     int32_t *level_host;      // pinned host word: the last level started
@@ -91,13 +92,14 @@ namespace {
 
 // Level k's state from level k-1's and the counters (Beamer, Asanovic and
 // Patterson, SC 2012, the heuristic the paper cites): pull when the
-// frontier's edges exceed the unexplored edges / BFS_ALPHA, back to push
-// when the frontier has fewer than n / BFS_BETA vertices.  Every workgroup
+// frontier's edges exceed the unexplored edges / alpha, back to push when
+// the frontier has fewer than n / beta vertices (14 and 24 by default, the
+// graph's tuned values after lagr_bfs_autotune).  Every workgroup
 // of level k evaluates it from the same inputs.  Wave 0 of the workgroup
 // calls it with the previous state and the counters (both loaded at once);
 // the result goes to *ns.
 __device__ void bfs_level_state(const BfsLevel *__restrict__ psp, const unsigned long long *__restrict__ ctr,
-                                int64_t n, int push_only, BfsLevel *ns)
+                                int64_t n, int push_only, int alpha, int beta, BfsLevel *ns)
 {
     const unsigned lane = lane_id();
     // lanes 0..15: vertex counts; 16..31: degree sums; 32..47: hub counts
@@ -128,8 +130,8 @@ __device__ void bfs_level_state(const BfsLevel *__restrict__ psp, const unsigned
     ns->done = (ns->nq == 0 || k >= INT32_MAX - 1) ? 1 : 0;
     int pull = ps.pull;
     if (!push_only) {
-        if (!pull && ns->mf > ns->mu / BFS_ALPHA) pull = 1;
-        else if (pull && ns->nq < n / BFS_BETA) pull = 0;
+        if (!pull && ns->mf > ns->mu / alpha) pull = 1;
+        else if (pull && ns->nq < n / beta) pull = 0;
     }
     ns->pull = pull;
 }
@@ -308,7 +310,7 @@ __global__ __launch_bounds__(256, 8) void k_bfs_level(const BfsDev *__restrict__
 {
     __shared__ BfsLevel S;
     __shared__ unsigned long long s_cnt, s_deg, s_hub;
-    if (threadIdx.x < 64) bfs_level_state(st + (par ^ 1), ctr, dp->n, dp->push_only, &S);
+    if (threadIdx.x < 64) bfs_level_state(st + (par ^ 1), ctr, dp->n, dp->push_only, dp->alpha, dp->beta, &S);
     LevelArgs a;
     a.rp = dp->rp;
     a.rpT = dp->rpT;
@@ -600,6 +602,8 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
     h.ch = ch;
     h.any_parent = (flags & LAGR_BFS_ANY_PARENT) ? 1 : 0;
     h.push_only = (flags & LAGR_BFS_PUSH_ONLY) ? 1 : 0;
+    h.alpha = G->bfs_alpha;
+    h.beta = G->bfs_beta;
     h.src = source;
     // the state "before level 0", which level 0 (parity 0) reads from st[1]
     h.st[1].lev = -1;
@@ -666,5 +670,56 @@ extern "C" int lagr_bfs(lagr_vector *level_out, lagr_vector *parent_out, const l
         pv = nullptr;
     }
 #undef BFS_TRY
+    return lagr_ok(msg);
+}
+
+// The BFS direction thresholds for this graph: every (alpha, beta) of a
+// small grid around Beamer's (14, 24) times lagr_bfs from the given
+// sources (host clock, the sum over the sources of the median of 3
+// searches each); the fastest pair is kept in G for later searches.
+extern "C" int lagr_bfs_autotune(int32_t *alpha, int32_t *beta, lagr_graph G, const int64_t *sources, int32_t ns,
+                                 lagr_ctx ctx, char *msg)
+{
+    if (!G || !ctx || (ns > 0 && !sources)) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    if (ns <= 0) return lagr_fail(msg, LAGR_INVALID_VALUE, "no sources to time");
+    if (ctx->device < 0) return lagr_fail(msg, LAGR_DEVICE_ERROR, "validation-only context");
+    const int32_t as[] = {6, 10, 14, 20, 32};
+    const int32_t bs[] = {12, 24, 48};
+    int32_t ba = G->bfs_alpha, bb = G->bfs_beta;
+    double best = -1.0;
+    for (const int32_t a : as)
+        for (const int32_t b : bs) {
+            G->bfs_alpha = a;
+            G->bfs_beta = b;
+            std::vector<double> per;
+            for (int32_t k = 0; k < ns; k++) {
+                double ts[3];
+                for (int r = 0; r < 3; r++) {
+                    // no outputs: the search runs in the context's workspace
+                    const auto t0 = std::chrono::steady_clock::now();
+                    int rc = lagr_bfs(nullptr, nullptr, G, sources[k], 0, ctx, msg);
+                    if (rc >= 0) rc = host_wait(ctx, msg);
+                    ts[r] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                    if (rc < 0) {
+                        G->bfs_alpha = ba;
+                        G->bfs_beta = bb;
+                        return rc;
+                    }
+                }
+                std::sort(ts, ts + 3);
+                per.push_back(ts[1]);
+            }
+            double tot = 0.0;
+            for (const double t : per) tot += t;
+            if (best < 0 || tot < best) {
+                best = tot;
+                ba = a;
+                bb = b;
+            }
+        }
+    G->bfs_alpha = ba;
+    G->bfs_beta = bb;
+    if (alpha) *alpha = ba;
+    if (beta) *beta = bb;
     return lagr_ok(msg);
 }

@@ -1056,6 +1056,35 @@ extern "C" int lagr_graph_delete_properties(lagr_graph G, lagr_ctx ctx, char *ms
     return lagr_ok(msg);
 }
 
+extern "C" int lagr_graph_set_tuning(lagr_graph G, int64_t tc_hubs, int32_t bfs_alpha, int32_t bfs_beta,
+                                     lagr_ctx ctx, char *msg)
+{
+    if (!G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    if (tc_hubs < -1 || bfs_alpha == 0 || bfs_beta == 0 || bfs_alpha < -1 || bfs_beta < -1)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "tuning values out of range");
+    if (tc_hubs != G->tc_hubs) {
+        // the count operand was planned for the old hub count: drop it
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        lagr_matrix_free(&G->L);
+        tc_plan_free(G);
+        G->L_maxrow = -1;
+        G->tc_hubs = tc_hubs;
+    }
+    if (bfs_alpha > 0) G->bfs_alpha = bfs_alpha;
+    if (bfs_beta > 0) G->bfs_beta = bfs_beta;
+    return lagr_ok(msg);
+}
+
+extern "C" int lagr_graph_get_tuning(int64_t *tc_hubs, int32_t *bfs_alpha, int32_t *bfs_beta, const lagr_graph G,
+                                     char *msg)
+{
+    if (!G) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    if (tc_hubs) *tc_hubs = G->tc_hubs;
+    if (bfs_alpha) *bfs_alpha = G->bfs_alpha;
+    if (bfs_beta) *bfs_beta = G->bfs_beta;
+    return lagr_ok(msg);
+}
+
 extern "C" int lagr_graph_ndiag(int64_t *ndiag, const lagr_graph G, char *msg)
 {
     if (!ndiag || !G) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");

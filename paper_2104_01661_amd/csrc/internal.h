@@ -184,6 +184,11 @@ struct lagr_graph_s {
     // undirected graph uses A itself) and the chunks of its long rows
     lagr_matrix AT = nullptr;
     ChunkCache chunks_t;
+    // tuning settings (kept by lagr_graph_delete_properties): the count
+    // plan's hub columns (-1: the default share of the vertices) and the
+    // BFS direction thresholds
+    int64_t tc_hubs = -1;
+    int32_t bfs_alpha = 14, bfs_beta = 24;
 };
 
 // The pull side of G: AT for a directed graph (nullptr if not computed),

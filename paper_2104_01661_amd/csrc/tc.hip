@@ -2,6 +2,8 @@
 // counting (Section IV-E, Algorithm 6) as C<s(L)> = L plus.pair L^T and
 // t = sum(C), computed without forming C (the fusion Section VI-B asks
 // for).  The row kernel is described in tc_device.h.
+#include <algorithm>
+#include <chrono>
 #include <mutex>
 
 #include "internal.h"
@@ -509,7 +511,8 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
     // per-workgroup hub reservations, then the hub rows' bitmap words
     unsigned *boff = (unsigned *)ws_get(ctx, WS_GEN_H, sizeof(unsigned) * ((size_t)PLAN_GRID + 1) * PLAN_HOT);
     unsigned *hubw = boff + (size_t)PLAN_GRID * PLAN_HOT;
-    const int64_t nhub = plan_hubs(n);
+    int64_t nhub = plan_hubs(n);
+    if (G->tc_hubs >= 0) nhub = G->tc_hubs < PLAN_HOT ? (G->tc_hubs < n ? G->tc_hubs : n) : PLAN_HOT;
     uint64_t *rowpk = (uint64_t *)ws_get(ctx, WS_GEN_E, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     unsigned long long *cur = (unsigned long long *)ws_get(ctx, WS_TC_WORK, 8 * (size_t)(nv > 0 ? nv : 1));
     if (!boff || !rowpk || !cur) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
@@ -661,6 +664,51 @@ extern "C" int lagr_tc_adv(int64_t *ntriangles, const lagr_graph G, lagr_ctx ctx
     if (!ntriangles || !G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
     if (!G->L || !G->tcplan) return lagr_fail(msg, LAGR_PROPERTY_MISSING, "tc_lower property not computed");
     TRY(tc_on_lower(ctx, G, ntriangles, msg));
+    return lagr_ok(msg);
+}
+
+// ------------------------------------------------------------ autotuning
+
+// The count plan's hub columns for this graph: each candidate share of the
+// vertices (none, then n / 1024 .. n / 128, at most PLAN_HOT) rebuilds the
+// preparation and times the whole count (host clock around lagr_tc, median
+// of 3); the fastest is kept in G and its plan left built.
+extern "C" int lagr_tc_autotune(int64_t *hubs, lagr_graph G, lagr_ctx ctx, char *msg)
+{
+    if (!G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    if (ctx->device < 0) return lagr_fail(msg, LAGR_DEVICE_ERROR, "validation-only context");
+    const int64_t n = G->A->nrows;
+    std::vector<int64_t> cand = {0};
+    for (int sh = 10; sh >= 7; sh--) {
+        int64_t h = n >> sh;
+        if (h > PLAN_HOT) h = PLAN_HOT;
+        if (h > cand.back()) cand.push_back(h);
+    }
+    int64_t best = -1;
+    double best_t = 0.0;
+    int64_t t_ref = -1;
+    for (const int64_t h : cand) {
+        G->tc_hubs = h;
+        double ts[3];
+        for (int r = 0; r < 3; r++) {
+            TRY(lagr_graph_delete_properties(G, ctx, msg));
+            const auto t0 = std::chrono::steady_clock::now();
+            int64_t t = 0;
+            TRY(lagr_tc(&t, G, ctx, msg));
+            ts[r] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (t_ref < 0) t_ref = t;
+            if (t != t_ref) return lagr_fail(msg, LAGR_DEVICE_ERROR, "tuning candidates counted differently");
+        }
+        std::sort(ts, ts + 3);
+        if (best < 0 || ts[1] < best_t) {
+            best = h;
+            best_t = ts[1];
+        }
+    }
+    G->tc_hubs = best;
+    TRY(lagr_graph_delete_properties(G, ctx, msg));
+    TRY(lagr_property_tc_lower(G, ctx, msg));
+    if (hubs) *hubs = best;
     return lagr_ok(msg);
 }
 

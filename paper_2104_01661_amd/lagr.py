@@ -110,6 +110,11 @@ _PROTOS = {
     "lagr_tc_adv_noalloc": [_P, _P, _P, _C],
     "lagr_bfs": [_PP, _PP, _P, _I64, _U32, _P, _C],
     "lagr_bc": [_PP, _P, _P, _I32, _P, _C],
+    "lagr_bfs_batch": [_P, _P, _P, _P, _P, _P, _I32, _P, _C],
+    "lagr_bfs_autotune": [_P, _P, _P, _P, _I32, _P, _C],
+    "lagr_tc_autotune": [_P, _P, _P, _C],
+    "lagr_graph_set_tuning": [_P, _I64, _I32, _I32, _P, _C],
+    "lagr_graph_get_tuning": [_P, _P, _P, _P, _C],
     "lagr_sssp": [_PP, _P, _I64, ctypes.c_double, _P, _C],
     "lagr_pagerank": [_PP, _P, _P, ctypes.c_double, ctypes.c_double, _I64, _P, _C],
     "lagr_cc": [_PP, _P, _P, _P, _C],
@@ -388,6 +393,14 @@ class Graph:
     def delete_properties(self, ctx):
         call("lagr_graph_delete_properties", self.h, ctx.h)
 
+    def set_tuning(self, ctx, tc_hubs=-1, bfs_alpha=-1, bfs_beta=-1):
+        call("lagr_graph_set_tuning", self.h, tc_hubs, bfs_alpha, bfs_beta, ctx.h)
+
+    def tuning(self):
+        h, a, b = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        call("lagr_graph_get_tuning", ctypes.byref(h), ctypes.byref(a), ctypes.byref(b), self.h)
+        return h.value, a.value, b.value
+
     def _borrowed(self, fn):
         h = ctypes.c_void_p()
         call(fn, ctypes.byref(h), self.h)
@@ -480,6 +493,38 @@ def lagr_cc(G: Graph, ctx: Context):
     out, it = ctypes.c_void_p(), ctypes.c_int64()
     call("lagr_cc", ctypes.byref(out), ctypes.byref(it), G.h, ctx.h)
     return Vector(out), it.value
+
+
+def lagr_bfs_batch(G: Graph, sources, ctx: Context, want_levels=True):
+    """Multi-source BFS: (levels int32 device tensor [ns, n] or None,
+    reached, level_sum, depth as int64 numpy arrays)."""
+    import numpy as np
+    src = np.ascontiguousarray(np.asarray(sources, dtype=np.int64))
+    ns = src.size
+    n = G.matrix().info()[1]
+    lev = torch.empty((ns, n), dtype=torch.int32, device="cuda") if want_levels and ns else None
+    reached = np.zeros(ns, dtype=np.int64)
+    lsum = np.zeros(ns, dtype=np.int64)
+    depth = np.zeros(ns, dtype=np.int64)
+    call("lagr_bfs_batch", _ptr(lev), reached.ctypes.data_as(ctypes.c_void_p),
+         lsum.ctypes.data_as(ctypes.c_void_p), depth.ctypes.data_as(ctypes.c_void_p), G.h,
+         src.ctypes.data_as(ctypes.c_void_p), ns, ctx.h)
+    return lev, reached, lsum, depth
+
+
+def lagr_bfs_autotune(G: Graph, sources, ctx: Context):
+    import numpy as np
+    src = np.ascontiguousarray(np.asarray(sources, dtype=np.int64))
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    call("lagr_bfs_autotune", ctypes.byref(a), ctypes.byref(b), G.h, src.ctypes.data_as(ctypes.c_void_p),
+         src.size, ctx.h)
+    return a.value, b.value
+
+
+def lagr_tc_autotune(G: Graph, ctx: Context) -> int:
+    h = ctypes.c_int64()
+    call("lagr_tc_autotune", ctypes.byref(h), G.h, ctx.h)
+    return h.value
 
 
 def lagr_bc(G: Graph, sources, ctx: Context) -> Vector:

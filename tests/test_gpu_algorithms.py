@@ -6,6 +6,7 @@ import os
 
 import numpy as np
 import pytest
+import torch
 
 import graphgen
 import oracle
@@ -312,3 +313,76 @@ def test_bc_large_config_one_batch():
     rp, ci = oracle.build_adjacency(n, s, d)
     srcs = graphgen.sources(n, s, d, 256, 3)[:64]
     assert_bc_close(bc_host(G, srcs), oracle.brandes(rp, ci, srcs))
+
+
+def test_bfs_batch_ragged_duplicate_and_isolated_sources():
+    """lagr_bfs_batch over 70 sources (a full block of 64 and a ragged one),
+    with a repeated source and an isolated one, against the queue BFS; a
+    directed graph and a bad source are rejected."""
+    L = lagr()
+    c = ctx()
+    n, s, d = rmat(12, 8, 102)
+    G = device_graph(n, s, d)
+    rp, ci = oracle.build_adjacency(n, s, d)
+    deg = np.diff(rp)
+    iso = int(np.nonzero(deg == 0)[0][0])
+    srcs = [int(x) for x in graphgen.sources(n, s, d, 68, 7)] + [iso]
+    srcs.insert(5, srcs[3])
+    lev, reached, lsum, depth = L.lagr_bfs_batch(G, srcs, c)
+    assert lev.shape == (70, n)
+    for k, src in enumerate(srcs):
+        ref, _ = oracle.bfs(rp, ci, src)
+        assert np.array_equal(lev[k].cpu().numpy(), ref), src
+        r = ref >= 0
+        assert (reached[k], lsum[k], depth[k]) == (int(r.sum()), int(ref[r].sum()), int(ref.max()))
+    _, reached_only, _, _ = L.lagr_bfs_batch(G, srcs[:3], c, want_levels=False)
+    assert list(reached_only) == list(reached[:3])
+    with pytest.raises(L.LagrError) as e:
+        L.lagr_bfs_batch(G, [n], c)
+    assert e.value.code == L.INVALID_INDEX
+    A = L.Matrix.build(c, 4, 4, torch.tensor([0, 1], dtype=torch.int32).cuda(),
+                       torch.tensor([1, 2], dtype=torch.int32).cuda(), 0)
+    D = L.Graph(c, A, L.ADJACENCY_DIRECTED)
+    with pytest.raises(L.LagrError) as e:
+        L.lagr_bfs_batch(D, [0], c)
+    assert e.value.code == L.INVALID_VALUE
+
+
+def test_tc_and_bfs_autotune_keep_results():
+    """The tuners time their candidates on the device and keep the fastest
+    in the graph: the hub count is one of the candidates, the thresholds
+    one of the grid's pairs, and counts, levels and parents after tuning
+    (and after dropping the cached properties) equal the oracle's."""
+    L = lagr()
+    c = ctx()
+    n, s, d = rmat(14, 16, 103)
+    G = device_graph(n, s, d)
+    rp, ci = oracle.build_adjacency(n, s, d)
+    want = oracle.triangle_count(rp, ci)
+    hubs = L.lagr_tc_autotune(G, c)
+    assert hubs in {0} | {min(n >> k, 4096) for k in range(7, 11)}
+    assert L.lagr_tc(G, c) == want
+    G.delete_properties(c)
+    assert L.lagr_tc(G, c) == want
+    srcs = [int(x) for x in graphgen.sources(n, s, d, 4, 103)]
+    a, b = L.lagr_bfs_autotune(G, srcs, c)
+    assert a in (6, 10, 14, 20, 32) and b in (12, 24, 48)
+    for src in srcs:
+        lv_o, _ = oracle.bfs(rp, ci, src)
+        lv, pa = bfs_host(G, src)
+        assert np.array_equal(lv, lv_o.astype(np.int64))
+        assert np.array_equal(pa, oracle.bfs_min_parent(rp, ci, src, lv_o))
+    with pytest.raises(L.LagrError) as e:
+        L.lagr_bfs_autotune(G, [], c)
+    assert e.value.code == L.INVALID_VALUE
+    assert G.tuning() == (hubs, a, b)
+    # set by hand: a new hub count drops the operand, which is rebuilt
+    G.set_tuning(c, 0, 32, -1)
+    assert G.tuning() == (0, 32, b) and G.tc_lower() is None
+    assert L.lagr_tc(G, c) == want
+    lv, _ = bfs_host(G, srcs[0])
+    assert np.array_equal(lv, oracle.bfs(rp, ci, srcs[0])[0].astype(np.int64))
+    for bad in ((-2, -1, -1), (-1, 0, -1), (-1, -1, -5)):
+        with pytest.raises(L.LagrError) as e:
+            G.set_tuning(c, *bad)
+        assert e.value.code == L.INVALID_VALUE

@@ -218,3 +218,23 @@ def test_min_plus_mxm_one_hot_rows_under_a_mask_at_2_14(comp):
         keep = ~inm if comp else inm
         assert np.array_equal(gci[grp[r]:grp[r + 1]], cols[keep]), r
         assert np.array_equal(gva[grp[r]:grp[r + 1]], vals[keep]), r
+
+
+def test_batched_bfs_levels_of_all_64_sources_of_the_2_20_graph():
+    """lagr_bfs_batch: the 64 bench sources in one multi-source search,
+    every (source, vertex) level against the queue BFS."""
+    L = lagr()
+    c = ctx()
+    cfg = graphgen.LARGE
+    n, s, d = graphgen.rmat_edges(cfg["scale"], cfg["edge_factor"], cfg["seed"])
+    G = device_graph(n, s, d)
+    rp, ci = oracle.build_adjacency(n, s, d)
+    srcs = [int(x) for x in graphgen.sources(n, s, d, cfg["bfs_sources"], cfg["seed"])]
+    lev, reached, lsum, depth = L.lagr_bfs_batch(G, srcs, c)
+    with cf.ThreadPoolExecutor(POOL) as ex:
+        refs = list(ex.map(lambda x: oracle.bfs(rp, ci, x)[0], srcs))
+    for k, (src, ref) in enumerate(zip(srcs, refs)):
+        got = lev[k].cpu().numpy()
+        assert np.array_equal(got, ref), f"levels differ, source {src}"
+        r = ref >= 0
+        assert (reached[k], lsum[k], depth[k]) == (int(r.sum()), int(ref[r].sum()), int(ref.max()))
