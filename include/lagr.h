@@ -133,7 +133,7 @@ typedef enum {
 #define LAGR_DESC_TRAN0 8u         /* use the transpose of the first input */
 #define LAGR_DESC_TRAN1 16u        /* use the transpose of the second input*/
 #define LAGR_DESC_DETERMINISTIC 32u/* any monoid returns the smallest k    */
-#define LAGR_DESC_ASSIGN_PARENT 64u/* vxm only: also p<s(w)> = w (fused)   */
+#define LAGR_DESC_ASSIGN_PARENT 64u/* vxm only: also m<s(w)> = w (fused)   */
 #define LAGR_DESC_S (LAGR_DESC_STRUCT)
 #define LAGR_DESC_RSC (LAGR_DESC_REPLACE | LAGR_DESC_STRUCT | LAGR_DESC_COMP)
 
@@ -257,13 +257,22 @@ int lagr_mxm(lagr_matrix C, const lagr_matrix M, lagr_binop accum, lagr_semiring
 
 /* w'<m'> accum= u' (+).(x) A'  (Table I, vxm; with LAGR_DESC_TRAN1 it is
  * the pull form w<m> accum= A (+).(x) u of mxv).  u length m, A' m x n,
- * w and m length n.  With LAGR_DESC_ASSIGN_PARENT, `parent` (a vector of
- * length n, INT64) additionally receives parent<s(w)> = w after the
- * product -- the fused vxm + assign step of BFS (Section VI-B); pass NULL
- * otherwise. */
+ * w and m length n.
+ * LAGR_DESC_ASSIGN_PARENT (an extension: the fused vxm + assign of BFS,
+ * Section VI-B) makes the mask the parent vector p of Algorithms 1-2: m
+ * must be INT64 and receives m<s(w)> = w after the product (m is then an
+ * inout argument and may change storage format).
+ * Execution: the BFS-shaped calls -- any.secondi, accum NOOP, a mask with
+ * LAGR_DESC_RSC (push over A, or pull over the stored AT with TRAN1),
+ * with or without ASSIGN_PARENT -- run on dedicated kernels that enqueue
+ * on ctx's stream and return without waiting: w becomes a bitmap vector
+ * whose entry count stays on the device (lagr_vector_nvals reads that one
+ * word), and its arrays are double-buffered by ctx, so a loop such as
+ * q<!s(p), r> = q any.secondi A allocates nothing after its first steps.
+ * Push and pull give the same w (the smallest admissible k).  Every other
+ * shape is computed on the general path, which waits for the stream. */
 int lagr_vxm(lagr_vector w, const lagr_vector m, lagr_binop accum, lagr_semiring semiring,
-             const lagr_vector u, const lagr_matrix A, uint32_t desc, lagr_vector parent,
-             lagr_ctx ctx, char *msg);
+             const lagr_vector u, const lagr_matrix A, uint32_t desc, lagr_ctx ctx, char *msg);
 
 /* Fused product and reduction: *s = plus-reduce of (C<M> = A' (+).(x) B'),
  * without forming C (Section VI-B, the mxm + reduce fusion proposed for

@@ -124,6 +124,8 @@ extern "C" int lagr_ctx_free(lagr_ctx *ctx)
     timers_clear(c);
     for (int s = 0; s < WS_NSLOTS; s++) dev_free(c->ws[s], c->ws_bytes[s]);
     for (void *p : c->lvpool) dev_free(p, c->lv_bytes);
+    dev_free(c->vspare_present, c->vspare_pb);
+    dev_free(c->vspare_values, c->vspare_vb);
     if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
     *ctx = nullptr;
@@ -367,6 +369,7 @@ void vector_release_arrays(lagr_vector v)
     v->values = nullptr;
     v->idx_bytes = v->present_bytes = v->values_bytes = 0;
     v->nvals = 0;
+    v->count_dev = nullptr;
 }
 
 extern "C" int lagr_vector_new(lagr_vector *v, lagr_type type, int64_t n, lagr_ctx ctx, char *msg)

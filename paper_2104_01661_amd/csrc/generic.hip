@@ -22,7 +22,6 @@
 #include "internal.h"
 #include "tc_device.h"
 
-int bitmap_count(lagr_ctx ctx, const uint8_t *present, int64_t n, int64_t *count, char *msg);
 int vector_tuples(lagr_ctx ctx, const lagr_vector v, int32_t *idx, void *vals, int64_t *nvals,
                   char *msg);
 
@@ -1085,8 +1084,7 @@ extern "C" int lagr_mxm(lagr_matrix C, const lagr_matrix M, lagr_binop accum, la
 }
 
 extern "C" int lagr_vxm(lagr_vector w, const lagr_vector m, lagr_binop accum, lagr_semiring semiring,
-                        const lagr_vector u, const lagr_matrix A, uint32_t desc, lagr_vector parent,
-                        lagr_ctx ctx, char *msg)
+                        const lagr_vector u, const lagr_matrix A, uint32_t desc, lagr_ctx ctx, char *msg)
 {
     if (!w || !u || !A || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
     TRY(check_desc(desc, msg));
@@ -1102,9 +1100,14 @@ extern "C" int lagr_vxm(lagr_vector w, const lagr_vector m, lagr_binop accum, la
     if (w->type != tt) return lagr_fail(msg, LAGR_DOMAIN_MISMATCH, "w's type differs from the result type");
     TRY(check_accum(accum, w->type, msg));
     if (desc & LAGR_DESC_ASSIGN_PARENT) {
-        if (!parent) return lagr_fail(msg, LAGR_NULL_POINTER, "ASSIGN_PARENT needs a parent vector");
-        if (parent->n != w->n || parent->type != LAGR_INT64)
-            return lagr_fail(msg, LAGR_DOMAIN_MISMATCH, "parent must be INT64 of w's length");
+        // the mask is the parent vector p, and receives p<s(w)> = w
+        if (!m) return lagr_fail(msg, LAGR_NULL_POINTER, "ASSIGN_PARENT needs the parent vector as the mask");
+        if (m->type != LAGR_INT64) return lagr_fail(msg, LAGR_DOMAIN_MISMATCH, "the parent vector must be INT64");
+    }
+    {
+        const int fast = vxm_any_secondi_fast(w, m, accum, semiring, u, A, desc, ctx, msg);
+        if (fast < 0) return fast;
+        if (fast) return lagr_ok(msg);
     }
     {
         Pool pool;
@@ -1121,8 +1124,7 @@ extern "C" int lagr_vxm(lagr_vector w, const lagr_vector m, lagr_binop accum, la
         HIP_TRY(hipStreamSynchronize(ctx->stream));
         TRY(install_vector(ctx, w, r, msg));
     }
-    if (desc & LAGR_DESC_ASSIGN_PARENT)
-        TRY(lagr_assign_vector(parent, w, LAGR_NOOP, w, LAGR_DESC_STRUCT, ctx, msg));
+    if (desc & LAGR_DESC_ASSIGN_PARENT) TRY(lagr_assign_vector(m, w, LAGR_NOOP, w, LAGR_DESC_STRUCT, ctx, msg));
     return lagr_ok(msg);
 }
 

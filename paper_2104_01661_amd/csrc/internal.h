@@ -91,6 +91,10 @@ enum WsSlot {
     WS_SSSP,          // SSSP device state
     WS_CHUNK_A,       // long-row chunk lists
     WS_CHUNK_B,
+    WS_VXM_CAND,      // any.secondi push: per-output smallest index (kept all-ones)
+    WS_VXM_UMAP,      // any.secondi: presence maps of sparse operands
+    WS_VXM_MMAP,
+    WS_VXM_LONG,      // any.secondi push: queued long rows
     WS_NSLOTS
 };
 
@@ -131,6 +135,15 @@ struct lagr_ctx_s {
     int64_t sssp_key = -1;
     void *sssp_state = nullptr;
     hipStream_t capture_stream = nullptr;
+    // any.secondi vxm: the WS_VXM_CAND buffer whose header (zero) and
+    // first vxm_cand_n candidates (all ones) are in their between-call
+    // state, and a spare pair of bitmap-vector arrays that the next result
+    // on this stream takes (double buffering)
+    void *vxm_cand = nullptr;
+    int64_t vxm_cand_n = 0;
+    uint8_t *vspare_present = nullptr;
+    void *vspare_values = nullptr;
+    size_t vspare_pb = 0, vspare_vb = 0;
 };
 
 // Returns a device buffer of at least `bytes` for the slot (contents are
@@ -155,6 +168,10 @@ struct lagr_vector_s {
     uint8_t *present = nullptr;     // BITMAP
     void *values = nullptr;
     size_t idx_bytes = 0, present_bytes = 0, values_bytes = 0;      // 0 = borrowed
+    // BITMAP only: a device word holding the entry count (in the tail of
+    // the present array), kept by the operations that write it; nullptr:
+    // count the presence bytes
+    unsigned long long *count_dev = nullptr;
 };
 
 struct TcPlan;
@@ -220,6 +237,13 @@ static inline size_t type_size(lagr_type t) { return t == LAGR_BOOL ? 0 : 8; }
 // Release a matrix's / vector's owned arrays and reset them to empty.
 void matrix_release_arrays(lagr_matrix A);
 void vector_release_arrays(lagr_vector v);
+// Entries of a presence-byte map (synchronises).
+int bitmap_count(lagr_ctx ctx, const uint8_t *present, int64_t n, int64_t *count, char *msg);
+// vxm with any.secondi under a complemented structural mask with replace
+// (push, or pull with TRAN1), optionally assigning the parents into the
+// mask: 1 when served, 0 when the call has another shape, < 0 on error.
+int vxm_any_secondi_fast(lagr_vector w, lagr_vector m, lagr_binop accum, lagr_semiring semiring,
+                         const lagr_vector u, const lagr_matrix A, uint32_t desc, lagr_ctx ctx, char *msg);
 // Allocate owned arrays for a CSR of the given size (rowptr always).
 int matrix_alloc(lagr_matrix A, int64_t nvals, char *msg);
 

@@ -119,8 +119,15 @@ int vector_tuples(lagr_ctx ctx, const lagr_vector v, int32_t *idx, void *vals, i
 extern "C" int lagr_vector_nvals(int64_t *nvals, const lagr_vector v, lagr_ctx ctx, char *msg)
 {
     if (!nvals || !v || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
-    if (v->fmt == LAGR_VEC_BITMAP) TRY(bitmap_count(ctx, v->present, v->n, nvals, msg));
-    else *nvals = v->nvals;
+    if (v->fmt == LAGR_VEC_BITMAP && v->count_dev) {
+        unsigned long long c = 0;
+        TRY(read_back(ctx, &c, v->count_dev, sizeof(c), msg));
+        *nvals = (int64_t)c;
+    } else if (v->fmt == LAGR_VEC_BITMAP) {
+        TRY(bitmap_count(ctx, v->present, v->n, nvals, msg));
+    } else {
+        *nvals = v->nvals;
+    }
     return lagr_ok(msg);
 }
 

@@ -85,7 +85,7 @@ _PROTOS = {
     "lagr_vector_extract_dense": [_P, _P, _P, _P, _P, _C],
     "lagr_vector_free": [_PP],
     "lagr_mxm": [_P, _P, _INT, _INT, _P, _P, _U32, _P, _C],
-    "lagr_vxm": [_P, _P, _INT, _INT, _P, _P, _U32, _P, _P, _C],
+    "lagr_vxm": [_P, _P, _INT, _INT, _P, _P, _U32, _P, _C],
     "lagr_mxm_reduce": [_P, _P, _INT, _P, _P, _U32, _P, _C],
     "lagr_reduce_scalar": [_P, _INT, _INT, _P, _P, _C],
     "lagr_vector_reduce_scalar": [_P, _INT, _INT, _P, _P, _C],
@@ -541,9 +541,8 @@ def lagr_mxm(C: Matrix, M, accum, semiring, A: Matrix, B: Matrix, desc, ctx: Con
     return call("lagr_mxm", C.h, None if M is None else M.h, accum, semiring, A.h, B.h, desc, ctx.h)
 
 
-def lagr_vxm(w: Vector, m, accum, semiring, u: Vector, A: Matrix, desc, ctx: Context, parent=None):
-    return call("lagr_vxm", w.h, None if m is None else m.h, accum, semiring, u.h, A.h, desc,
-                None if parent is None else parent.h, ctx.h)
+def lagr_vxm(w: Vector, m, accum, semiring, u: Vector, A: Matrix, desc, ctx: Context):
+    return call("lagr_vxm", w.h, None if m is None else m.h, accum, semiring, u.h, A.h, desc, ctx.h)
 
 
 def lagr_mxm_reduce(M: Matrix, semiring, A: Matrix, B: Matrix, desc, ctx: Context, fp64=False):

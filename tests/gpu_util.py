@@ -89,3 +89,32 @@ def assert_bc_close(got, want, rtol=1e-12):
     nz = ~zero
     err = np.abs(got[nz] - want[nz]) / np.abs(want[nz])
     assert err.size == 0 or err.max() <= rtol, f"max rel err {err.max():.3e}"
+
+
+def bfs_graphblas(c, A, AT, n, src, mode="auto", alpha=14, beta=24):
+    """Algorithms 1-2 written with lagr_vxm: q<!s(p), r> = q any.secondi A
+    (push), or the same product over AT under TRAN1 (pull), each with the
+    parents assigned into p in the same call.  mode "push" is Algorithm 1;
+    "auto" switches direction by Beamer's test on the two entry counts.
+    Returns the parent array (-1 unreached) and the number of levels."""
+    L = lagr()
+    idx = torch.tensor([src], dtype=torch.int32, device="cuda")
+    val = torch.tensor([src], dtype=torch.int64, device="cuda")
+    q = L.Vector.wrap_sparse(c, n, idx, val, typ=L.INT64)
+    p = L.Vector.wrap_sparse(c, n, idx.clone(), val.clone(), typ=L.INT64)
+    pull, nq, nvisited, levels = False, 1, 1, 0
+    while nq > 0:
+        if mode == "auto":
+            if not pull and nq > (n - nvisited) / alpha:
+                pull = True
+            elif pull and nq < n / beta:
+                pull = False
+        if pull:
+            L.lagr_vxm(q, p, 0, L.ANY_SECONDI, q, AT, L.DESC_RSC | L.DESC_TRAN1 | L.DESC_ASSIGN_PARENT, c)
+        else:
+            L.lagr_vxm(q, p, 0, L.ANY_SECONDI, q, A, L.DESC_RSC | L.DESC_ASSIGN_PARENT, c)
+        nq = q.nvals(c)
+        nvisited += nq
+        levels += 1
+    pres, vals = p.to_dense(c, fill=-1)
+    return vals.cpu().numpy(), levels - 1

@@ -114,11 +114,14 @@ def test_vxm_reduce_assign_checks(api, ctx):
     w = vec(api, ctx, INT64, 6)
     w5 = vec(api, ctx, INT64, 5)
     u32 = ctypes.c_uint32
-    assert api("lagr_vxm", w5, None, NOOP, ANY_SECONDI, u, A, u32(0), None, ctx) == DIMENSION_MISMATCH
-    assert api("lagr_vxm", w, None, NOOP, ANY_SECONDI, u, A, u32(8), None, ctx) == INVALID_VALUE
-    assert api("lagr_vxm", w, None, NOOP, ANY_SECONDI, u, A, u32(64), None, ctx) == NULL_POINTER
+    assert api("lagr_vxm", w5, None, NOOP, ANY_SECONDI, u, A, u32(0), ctx) == DIMENSION_MISMATCH
+    assert api("lagr_vxm", w, None, NOOP, ANY_SECONDI, u, A, u32(8), ctx) == INVALID_VALUE
+    assert api("lagr_vxm", w, None, NOOP, ANY_SECONDI, u, A, u32(64), ctx) == NULL_POINTER
     wf = vec(api, ctx, FP64, 6)
-    assert api("lagr_vxm", wf, None, NOOP, ANY_SECONDI, u, A, u32(0), None, ctx) == DOMAIN_MISMATCH
+    assert api("lagr_vxm", wf, None, NOOP, ANY_SECONDI, u, A, u32(0), ctx) == DOMAIN_MISMATCH
+    # ASSIGN_PARENT writes the parents into the mask, which must be INT64
+    mf = vec(api, ctx, FP64, 6)
+    assert api("lagr_vxm", w, mf, NOOP, ANY_SECONDI, u, A, u32(64 | 7), ctx) == DOMAIN_MISMATCH
     s = ctypes.c_int64()
     assert api("lagr_reduce_scalar", ctypes.byref(s), NOOP, TIMES, A, ctx) == INVALID_VALUE
     assert api("lagr_reduce_rows", w5, None, NOOP, PLUS, A, u32(0), ctx) == DIMENSION_MISMATCH

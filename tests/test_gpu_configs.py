@@ -3,6 +3,8 @@
 * R-MAT 2^20, ef 16 (seed 2): direction-optimising BFS from all 64 bench
   sources, levels and default (smallest) parents bit for bit against the
   FIFO-queue BFS and the min-parent oracle (Section IV-A, Algorithms 1-2).
+  The same search written with lagr_vxm (push only, and push / pull by the
+  direction test) from 8 of the sources: parents bit for bit.
 * R-MAT 2^18, ef 16 (seed 3): betweenness over the 4 batches of 64 sources,
   summed, against Brandes' FP64 oracle at 1e-12 relative with exact zeros
   (Section IV-B, Algorithm 3).
@@ -28,7 +30,7 @@ import torch
 
 import graphgen
 import oracle
-from gpu_util import assert_bc_close, ctx, device_graph, lagr
+from gpu_util import assert_bc_close, bfs_graphblas, ctx, device_graph, lagr
 
 pytestmark = pytest.mark.gpu
 
@@ -63,6 +65,24 @@ def test_bfs_all_64_sources_of_the_2_20_graph():
             futs[k] = None
             assert np.array_equal(lv, lv_o.astype(np.int64)), f"levels differ, source {src}"
             assert np.array_equal(pa, mp), f"parents differ, source {src}"
+
+
+def test_bfs_written_with_vxm_on_the_2_20_graph():
+    L = lagr()
+    c = ctx()
+    cfg = graphgen.LARGE
+    n, s, d = graphgen.rmat_edges(cfg["scale"], cfg["edge_factor"], cfg["seed"])
+    G = device_graph(n, s, d)
+    rp, ci = oracle.build_adjacency(n, s, d)
+    srcs = [int(x) for x in graphgen.sources(n, s, d, cfg["bfs_sources"], cfg["seed"])][:8]
+    A = G.matrix()
+    for src in srcs:
+        lv, _ = oracle.bfs(rp, ci, src)
+        mp = oracle.bfs_min_parent(rp, ci, src, lv)
+        for mode in ("push", "auto"):
+            pa, depth = bfs_graphblas(c, A, A, n, src, mode)
+            assert np.array_equal(pa, mp), f"parents differ, source {src}, {mode}"
+            assert depth == int(lv.max())
 
 
 def test_bc_4_batches_of_64_sources_of_the_2_18_graph():

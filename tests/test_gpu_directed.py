@@ -139,7 +139,7 @@ def test_push_and_pull_levels_agree_on_a_directed_graph():
         p = L.Vector.wrap_sparse(c, n, idx.clone(), val.clone(), typ=L.INT64)
         levels = []
         for _ in range(n):
-            L.lagr_vxm(q, p, 0, L.ANY_SECONDI, q, M, desc | L.DESC_ASSIGN_PARENT, c, parent=p)
+            L.lagr_vxm(q, p, 0, L.ANY_SECONDI, q, M, desc | L.DESC_ASSIGN_PARENT, c)
             qi, _ = q.to_tuples(c)
             if qi.numel() == 0:
                 break

@@ -143,7 +143,8 @@ def test_mxm_all_descriptor_combinations(sr):
 
 
 @pytest.mark.parametrize("fmt_u,fmt_w,fmt_m", [("sparse", "sparse", "sparse"), ("bitmap", "bitmap", "bitmap"),
-                                               ("sparse", "full", "bitmap"), ("bitmap", "sparse", "full")])
+                                               ("sparse", "full", "bitmap"), ("bitmap", "sparse", "full"),
+                                               ("full", "bitmap", "sparse")])
 def test_vxm_formats_and_descriptors(fmt_u, fmt_w, fmt_m):
     L = lagr()
     rng = np.random.default_rng(7)
@@ -162,6 +163,83 @@ def test_vxm_formats_and_descriptors(fmt_u, fmt_w, fmt_m):
             L.lagr_vxm(wd, vec_to_dev(mk, fmt_m), accum, sr, vec_to_dev(u, fmt_u), to_dev(A),
                        desc_bits(comp, struct, replace, False, t1), ctx())
             same(vec_from_dev(wd).e, want.e)
+
+
+@pytest.mark.parametrize("fmt_u", ["sparse", "bitmap", "full"])
+@pytest.mark.parametrize("fmt_m", ["sparse", "bitmap", "full"])
+def test_vxm_any_secondi_with_parent_assignment(fmt_u, fmt_m):
+    """The BFS-shaped call w<!s(p), r> = u any.secondi A' with the parents
+    assigned into the mask (p<s(w)> = w), push and pull, on every operand
+    format and on sizes past one 256-wide block: w and p against the
+    semantics oracle's vxm then assign, and both entry counts (kept on the
+    device) against theirs."""
+    L = lagr()
+    c = ctx()
+    rng = np.random.default_rng(31)
+    for t1, n, dens in itertools.product((False, True), (9, 700), (0.1, 0.6)):
+        u = rand_vec(rng, n, 1.0 if fmt_u == "full" else dens, "int64")
+        A = rand_mat(rng, n, n, 4.0 / n, "bool")
+        p0 = rand_vec(rng, n, 1.0 if fmt_m == "full" else 0.3, "int64")
+        want_w = S.vxm(S.Vec(n, {}, "int64"), p0, None, "any.secondi", u, A, comp=True, struct=True,
+                       replace=True, tran1=t1, deterministic=True)
+        want_p = S.assign_vector(p0, want_w, None, want_w, struct=True)
+        w = L.Vector.new(c, L.INT64, n)
+        pd = vec_to_dev(p0, fmt_m)
+        L.lagr_vxm(w, pd, 0, L.ANY_SECONDI, vec_to_dev(u, fmt_u), to_dev(A),
+                   L.DESC_RSC | L.DESC_ASSIGN_PARENT | (L.DESC_TRAN1 if t1 else 0), c)
+        same(vec_from_dev(w).e, want_w.e)
+        same(vec_from_dev(pd).e, want_p.e)
+        assert w.nvals(c) == len(want_w.e) and pd.nvals(c) == len(want_p.e)
+
+
+def test_vxm_bfs_loop_allocates_nothing_after_its_first_steps():
+    """Algorithm 1's loop on the BFS-shaped fast path: results double-buffer
+    through the context, so from the third step on no device memory is
+    allocated, and the entry counts are read from the device words."""
+    L = lagr()
+    c = ctx()
+    n, s, d = graphgen.rmat_edges(12, 8, 5)
+    G = device_graph(n, s, d)
+    A = G.matrix()
+    rp, ci = oracle.build_adjacency(n, s, d)
+    src = int(graphgen.sources(n, s, d, 1, 5)[0])
+    lv, _ = oracle.bfs(rp, ci, src)
+    idx = torch.tensor([src], dtype=torch.int32, device="cuda")
+    val = torch.tensor([src], dtype=torch.int64, device="cuda")
+    q = L.Vector.wrap_sparse(c, n, idx, val, typ=L.INT64)
+    p = L.Vector.wrap_sparse(c, n, idx.clone(), val.clone(), typ=L.INT64)
+    counts, before = [], None
+    for step in range(int(lv.max()) + 1):
+        if step == 2:
+            before = L.alloc_calls
+        L.lagr_vxm(q, p, 0, L.ANY_SECONDI, q, A, L.DESC_RSC | L.DESC_ASSIGN_PARENT, c)
+        counts.append(q.nvals(c))
+    assert L.alloc_calls == before
+    assert counts == [int((lv == k).sum()) for k in range(1, int(lv.max()) + 2)]
+    assert p.nvals(c) == int((lv >= 0).sum())
+
+
+def test_vxm_push_splits_long_rows():
+    """Rows longer than the push kernel's batch limit (2,048 entries) are
+    walked in chunks by the whole grid: a star with 7,000 leaves plus a
+    path, searched with Algorithm 1 from a leaf and from the path's end,
+    push and pull, against the queue BFS's smallest parents."""
+    from gpu_util import bfs_graphblas
+    c = ctx()
+    leaves = 7000
+    n = leaves + 1 + 50
+    edges = [(0, i) for i in range(1, leaves + 1)] + [(leaves + k, leaves + k + 1) for k in range(50)]
+    src = np.array([e[0] for e in edges], dtype=np.int32)
+    dst = np.array([e[1] for e in edges], dtype=np.int32)
+    G = device_graph(n, src, dst)
+    rp, ci = oracle.build_adjacency(n, src, dst)
+    A = G.matrix()
+    for s0 in (3, n - 1):
+        lv, _ = oracle.bfs(rp, ci, s0)
+        mp = oracle.bfs_min_parent(rp, ci, s0, lv)
+        for mode in ("push", "auto"):
+            pa, depth = bfs_graphblas(c, A, A, n, s0, mode)
+            assert np.array_equal(pa, mp) and depth == int(lv.max())
 
 
 def test_ewise_assign_reduce():
@@ -271,7 +349,7 @@ def test_algorithm1_with_vxm_assign_parent():
     q = vec_to_dev(S.Vec(n, {src: src}, "int64"), "sparse")
     level = {src: 0}
     for lev in range(1, n):
-        L.lagr_vxm(q, p, 0, L.ANY_SECONDI, q, Ad, L.DESC_RSC | L.DESC_ASSIGN_PARENT, ctx(), parent=p)
+        L.lagr_vxm(q, p, 0, L.ANY_SECONDI, q, Ad, L.DESC_RSC | L.DESC_ASSIGN_PARENT, ctx())
         got = vec_from_dev(q).e
         if not got:
             break
