@@ -34,7 +34,16 @@
  *    relies on for fusion, Section VI-B): device work is queued on the
  *    context's stream.  Results held in device objects are valid once
  *    lagr_wait(ctx) returns or the stream is synchronised; a call whose
- *    output is a host scalar synchronises before it returns.
+ *    output is a host scalar synchronises before it returns.  Temporary
+ *    buffers and replaced arrays are freed when the context next waits for
+ *    its stream, never by a wait of their own.  Apart from host scalars, a
+ *    call waits only to read back a size that it must know on the host to
+ *    allocate: the entry count of a CSR result, or of a vector operand
+ *    that it turns into a list.  The BFS-shaped vxm calls never wait.
+ *  - A transpose descriptor (TRAN0 / TRAN1) uses the matrix's transpose,
+ *    built by the first call that needs it and kept with the matrix until
+ *    its arrays change; a wrapped matrix whose borrowed arrays the caller
+ *    changes must be wrapped again.
  *  - One context per host thread.  Objects may be read by several calls at
  *    once but not written by two at once.
  *
@@ -87,17 +96,23 @@ enum {
     } while (0)
 
 /* ---------------------------------------------------------------- enums */
+/* LAGR_INT32 arrays that cross the boundary (wraps, extracts, host
+ * scalars) hold int32 values.  Inside, every value takes an 8-byte slot, so
+ * a wrap of INT32 values copies them (widened) into library-owned storage
+ * -- the row offsets and ids stay borrowed -- and arithmetic whose result
+ * type is INT32 wraps modulo 2^32, as in the GraphBLAS INT32 domain. */
 typedef enum {
     LAGR_BOOL = 0,   /* pattern only; every present entry has the value 1 */
     LAGR_INT64 = 1,
-    LAGR_FP64 = 2
+    LAGR_FP64 = 2,
+    LAGR_INT32 = 3
 } lagr_type;
 
 /* The semirings of Table II that the path uses.  Result domains:
  *   PLUS_PAIR   plus monoid, pair(x,y) = 1         -> INT64 (a count)
  *   ANY_SECONDI any monoid,  secondi(a_ik,b_kj) = k -> INT64 (an index)
  *   PLUS_FIRST  plus monoid, first(x,y) = x         -> the type of A'
- *               (LAGR_BOOL A' gives INT64)
+ *               (LAGR_BOOL A' gives INT64, LAGR_INT32 gives INT32)
  *   MIN_PLUS    min monoid (identity +inf), x + y   -> FP64
  * The additive identity is never stored: an output entry exists iff at
  * least one k has both A'(i,k) and B'(k,j).  The `any` monoid returns one
@@ -190,7 +205,8 @@ int lagr_matrix_new(lagr_matrix *A, lagr_type type, int64_t nrows, int64_t ncols
                     lagr_ctx ctx, char *msg);
 /* Wrap caller device arrays as a CSR matrix (borrowed; see above).
  * rowptr: int64[nrows+1], rowptr[0] = 0, rowptr[nrows] = nvals;
- * colidx: int32[nvals]; values: int64 or double [nvals], NULL for BOOL.
+ * colidx: int32[nvals]; values: int64, double or int32 [nvals] by type,
+ * NULL for BOOL.
  * Sortedness is the caller's promise; lagr_graph_check verifies it. */
 int lagr_matrix_wrap_csr(lagr_matrix *A, lagr_type type, int64_t nrows, int64_t ncols,
                          int64_t nvals, const int64_t *rowptr, const int32_t *colidx,
@@ -218,7 +234,7 @@ int lagr_matrix_free(lagr_matrix *A);
 /* ------------------------------------------------------------- vectors */
 int lagr_vector_new(lagr_vector *v, lagr_type type, int64_t n, lagr_ctx ctx, char *msg);
 /* Borrowed wraps.  idx int32[nvals] sorted ascending; present uint8[n]
- * (0 / 1); values int64 or double arrays (NULL for BOOL). */
+ * (0 / 1); values int64, double or int32 arrays by type (NULL for BOOL). */
 int lagr_vector_wrap_sparse(lagr_vector *v, lagr_type type, int64_t n, int64_t nvals,
                             const int32_t *idx, const void *values, lagr_ctx ctx, char *msg);
 int lagr_vector_wrap_bitmap(lagr_vector *v, lagr_type type, int64_t n, const uint8_t *present,
@@ -249,9 +265,12 @@ int lagr_vector_free(lagr_vector *v);
  * accum: LAGR_NOOP or a binop on C's type.  C's type must equal the
  * semiring's result type.  C may be the same object as A, B or M; the
  * result is computed into new storage before C is replaced.
- * The masked dot form (mask present, not complemented, LAGR_DESC_TRAN1) is
- * computed entry by entry on the mask's pattern; plus.pair there uses a
- * wavefront hash intersection (Algorithm 6's C<s(L)> = L plus.pair L^T). */
+ * With a mask that is not complemented the product is computed in dot
+ * form, entry by entry on the mask's pattern, from rows of A' and rows of
+ * B'^T -- under LAGR_DESC_TRAN1 those are B's own rows, so Algorithm 6's
+ * C<s(L)> = L plus.pair L^T reads L twice and transposes nothing;
+ * plus.pair there runs the triangle-count intersection kernels.  Other
+ * shapes run in saxpy form over rows of B'. */
 int lagr_mxm(lagr_matrix C, const lagr_matrix M, lagr_binop accum, lagr_semiring semiring,
              const lagr_matrix A, const lagr_matrix B, uint32_t desc, lagr_ctx ctx, char *msg);
 
@@ -283,7 +302,7 @@ int lagr_mxm_reduce(void *s, const lagr_matrix M, lagr_semiring semiring, const 
 
 /* s accum= reduce of every entry of A with `monoid` (LAGR_PLUS or
  * LAGR_MIN) (Table I, reduce to scalar).  s is a host scalar of A's type
- * (INT64 for BOOL).  No entry: s is left unchanged and LAGR_NO_VALUE is
+ * (int64 for BOOL, int32 for INT32).  No entry: s is left unchanged and LAGR_NO_VALUE is
  * returned.  Entries are combined in row-major order.  Synchronises. */
 int lagr_reduce_scalar(void *s, lagr_binop accum, lagr_binop monoid, const lagr_matrix A,
                        lagr_ctx ctx, char *msg);
@@ -294,7 +313,8 @@ int lagr_vector_reduce_scalar(void *s, lagr_binop accum, lagr_binop monoid, cons
 int lagr_reduce_rows(lagr_vector w, const lagr_vector m, lagr_binop accum, lagr_binop monoid,
                      const lagr_matrix A, uint32_t desc, lagr_ctx ctx, char *msg);
 
-/* w<m>(:) accum= u  and  w<m>(:) accum= s  (Table I, assign; all indices). */
+/* w<m>(:) accum= u  and  w<m>(:) accum= s  (Table I, assign; all indices;
+ * s points to one host value of w's type). */
 int lagr_assign_vector(lagr_vector w, const lagr_vector m, lagr_binop accum, const lagr_vector u,
                        uint32_t desc, lagr_ctx ctx, char *msg);
 int lagr_assign_scalar(lagr_vector w, const lagr_vector m, lagr_binop accum, const void *s,
@@ -358,10 +378,21 @@ int lagr_graph_free(lagr_graph *G);
 /* ---------------------------------------------------------- algorithms */
 
 /* Triangle count (Section IV-E, Algorithm 6), Basic mode: computes any
- * missing property (requires an undirected graph with no self-loops).  The
- * count is the fused masked plus.pair product on the degree-ordered
- * strictly lower part, reduced without forming C.  Synchronises. */
-int lagr_tc(int64_t *ntriangles, lagr_graph G, lagr_ctx ctx, char *msg);
+ * missing property (requires an undirected graph with no self-loops) and
+ * returns the plus-reduction of C<s(L)> = L plus.pair L^T over the
+ * degree-ordered strictly lower part L.  `method` picks how:
+ *   LAGR_TC_DEFAULT  the count plan of lagr_tc_adv (each pair of L's rows
+ *                    intersected once on its cheaper side, C never formed);
+ *   LAGR_TC_DOT      the fused masked dot of lagr_mxm_reduce over L (the
+ *                    mxm + reduce fusion of Section VI-B, no plan);
+ *   LAGR_TC_MXM      Algorithm 6 as written: C formed by lagr_mxm, then
+ *                    lagr_reduce_scalar (the unfused form).
+ * All give the same count; another method is LAGR_INVALID_VALUE.
+ * Synchronises. */
+#define LAGR_TC_DEFAULT 0
+#define LAGR_TC_DOT 1
+#define LAGR_TC_MXM 2
+int lagr_tc(int64_t *ntriangles, lagr_graph G, int method, lagr_ctx ctx, char *msg);
 /* Advanced mode (Section II, "User modes"): LAGR_PROPERTY_MISSING when
  * lagr_property_tc_lower has not been computed; never computes it. */
 int lagr_tc_adv(int64_t *ntriangles, const lagr_graph G, lagr_ctx ctx, char *msg);

@@ -7,7 +7,10 @@ accumulators", "Masks"), for tiny inputs, in pure Python loops.
 Objects are dictionaries of present entries: a matrix is
 ``Mat(nrows, ncols, {(i, j): value}, kind)`` and a vector is
 ``Vec(n, {i: value}, kind)``; kind is "bool" (pattern only, every value
-1), "int64" or "fp64".
+1), "int32", "int64" or "fp64".  The paper leaves the domains to the
+GraphBLAS C API, where an int32 result is taken modulo 2^32: each stage
+here (a product's entries, a write's stored values, a reduction) takes its
+int32 results modulo 2^32 into [-2^31, 2^31).
 
 The `any` monoid may return any one of the candidates (Section IV-A), so a
 result entry produced by it is an ``AnyOf`` holding every admissible value
@@ -69,6 +72,17 @@ class Vec:
 
 def _val(x, kind):
     return 1 if kind == "bool" else x
+
+
+def _cast(x, kind):
+    """A value stored in a container of `kind`: int32 keeps the residue
+    modulo 2^32 in [-2^31, 2^31) (from fp64, the truncated integer first);
+    every other kind keeps the value as it is."""
+    if kind != "int32":
+        return x
+    if isinstance(x, AnyOf):
+        return AnyOf({_cast(v, kind) for v in x.c})
+    return ((int(x) + 2 ** 31) % 2 ** 32) - 2 ** 31
 
 
 # Semirings of Table II restricted to the four on the path.  Each is
@@ -141,15 +155,17 @@ def _truthy(v):
     return v != 0
 
 
-def _write(Cold: dict, T: dict, mask, accum, replace):
-    """Mask / accumulate / replace step shared by every operation."""
+def _write(Cold: dict, T: dict, mask, accum, replace, kind=None):
+    """Mask / accumulate / replace step shared by every operation; T's
+    values are first stored in the output's kind."""
+    T = {key: _cast(t, kind) for key, t in T.items()}
     if accum is None:
         Z = dict(T)
     else:
         op = _BINOPS[accum]
         Z = dict(Cold)
         for key, t in T.items():
-            Z[key] = _lift(op, Cold[key], t) if key in Cold else t
+            Z[key] = _cast(_lift(op, Cold[key], t), kind) if key in Cold else t
     out = {}
     for key in set(Cold) | set(Z):
         if mask(key):
@@ -190,7 +206,9 @@ def mxm(C: Mat, M, accum, semiring, A: Mat, B: Mat, *, comp=False, struct=False,
         raise ValueError("mask dimension mismatch")
     mask = _mask_fn(M, comp, struct)
     T = product(semiring, A2, B2, deterministic)
-    return Mat(C.nrows, C.ncols, _write(C.e, T, mask, accum, replace), C.kind)
+    tk = _out_kind(semiring, A2.kind)
+    T = {key: _cast(t, tk) for key, t in T.items()}
+    return Mat(C.nrows, C.ncols, _write(C.e, T, mask, accum, replace, C.kind), C.kind)
 
 
 def _row(v: Vec) -> Mat:
@@ -221,7 +239,7 @@ def ewise_add(C: Mat, M, accum, op, A: Mat, B: Mat, *, comp=False, struct=False,
         else:
             T[key] = _val(B.e[key], B.kind)
     mask = _mask_fn(M, comp, struct)
-    return Mat(C.nrows, C.ncols, _write(C.e, T, mask, accum, replace), C.kind)
+    return Mat(C.nrows, C.ncols, _write(C.e, T, mask, accum, replace, C.kind), C.kind)
 
 
 def ewise_mult(C: Mat, M, accum, op, A: Mat, B: Mat, *, comp=False, struct=False,
@@ -231,21 +249,21 @@ def ewise_mult(C: Mat, M, accum, op, A: Mat, B: Mat, *, comp=False, struct=False
     T = {key: _lift(f, _val(A.e[key], A.kind), _val(B.e[key], B.kind))
          for key in set(A.e) & set(B.e)}
     mask = _mask_fn(M, comp, struct)
-    return Mat(C.nrows, C.ncols, _write(C.e, T, mask, accum, replace), C.kind)
+    return Mat(C.nrows, C.ncols, _write(C.e, T, mask, accum, replace, C.kind), C.kind)
 
 
 def assign_vector(w: Vec, m, accum, u: Vec, *, comp=False, struct=False, replace=False) -> Vec:
     """w<m>(:) accum= u."""
     mask = _mask_fn(m, comp, struct)
     T = {i: _val(x, u.kind) for i, x in u.e.items()}
-    return Vec(w.n, _write(w.e, T, mask, accum, replace), w.kind)
+    return Vec(w.n, _write(w.e, T, mask, accum, replace, w.kind), w.kind)
 
 
 def assign_scalar(w: Vec, m, accum, s, *, comp=False, struct=False, replace=False) -> Vec:
     """w<m>(:) accum= s  (every position receives s)."""
     mask = _mask_fn(m, comp, struct)
     T = {i: s for i in range(w.n)}
-    return Vec(w.n, _write(w.e, T, mask, accum, replace), w.kind)
+    return Vec(w.n, _write(w.e, T, mask, accum, replace, w.kind), w.kind)
 
 
 def reduce_scalar(A, monoid):
@@ -259,7 +277,7 @@ def reduce_scalar(A, monoid):
     s = vals[0]
     for v in vals[1:]:
         s = s + v if monoid == "plus" else (v if v < s else s)
-    return s
+    return _cast(s, kind)
 
 
 def reduce_rows(w: Vec, m, accum, monoid, A: Mat, *, tran0=False, comp=False,
@@ -273,9 +291,9 @@ def reduce_rows(w: Vec, m, accum, monoid, A: Mat, *, tran0=False, comp=False,
             s = vals[0]
             for v in vals[1:]:
                 s = s + v if monoid == "plus" else (v if v < s else s)
-            T[i] = s
+            T[i] = _cast(s, A2.kind)
     mask = _mask_fn(m, comp, struct)
-    return Vec(w.n, _write(w.e, T, mask, accum, replace), w.kind)
+    return Vec(w.n, _write(w.e, T, mask, accum, replace, w.kind), w.kind)
 
 
 def strictly_lower(A: Mat) -> Mat:

@@ -105,7 +105,10 @@ extern "C" int lagr_ctx_set_stream(lagr_ctx ctx, void *stream, char *msg)
     if (!ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "ctx is NULL");
     // work a call left queued (a search's last levels) finishes on the old
     // stream before the context's next work starts on the new one
-    if (ctx->device >= 0 && ctx->stream != (hipStream_t)stream) HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (ctx->device >= 0 && ctx->stream != (hipStream_t)stream) {
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        flush_deferred(ctx);
+    }
     ctx->stream = (hipStream_t)stream;
     return lagr_ok(msg);
 }
@@ -123,6 +126,7 @@ extern "C" int lagr_ctx_free(lagr_ctx *ctx)
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     timers_clear(c);
     for (int s = 0; s < WS_NSLOTS; s++) dev_free(c->ws[s], c->ws_bytes[s]);
+    flush_deferred(c);
     for (void *p : c->lvpool) dev_free(p, c->lv_bytes);
     dev_free(c->vspare_present, c->vspare_pb);
     dev_free(c->vspare_values, c->vspare_vb);
@@ -136,6 +140,7 @@ extern "C" int lagr_wait(lagr_ctx ctx, char *msg)
 {
     if (!ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "ctx is NULL");
     HIP_TRY(hipStreamSynchronize(ctx->stream));
+    flush_deferred(ctx);
     return lagr_ok(msg);
 }
 
@@ -201,6 +206,7 @@ void *ws_get(lagr_ctx ctx, WsSlot slot, size_t bytes)
     if (ctx->ws[slot]) {
         // queued work may still read the old buffer
         (void)hipStreamSynchronize(ctx->stream);
+        flush_deferred(ctx);
         dev_free(ctx->ws[slot], ctx->ws_bytes[slot]);
         ctx->ws[slot] = nullptr;
         ctx->ws_bytes[slot] = 0;
@@ -216,8 +222,56 @@ void *ws_get(lagr_ctx ctx, WsSlot slot, size_t bytes)
 
 // ------------------------------------------------------------- matrices
 
+void defer_free(lagr_ctx ctx, void *p, size_t bytes)
+{
+    if (!p) return;
+    ctx->deferred.emplace_back(p, bytes);
+    ctx->deferred_bytes += bytes;
+    if (ctx->deferred_bytes > ((size_t)2 << 30)) {
+        (void)hipStreamSynchronize(ctx->stream);
+        flush_deferred(ctx);
+    }
+}
+
+void flush_deferred(lagr_ctx ctx)
+{
+    for (auto &b : ctx->deferred) dev_free(b.first, b.second);
+    ctx->deferred.clear();
+    ctx->deferred_bytes = 0;
+}
+
+void matrix_release_arrays_later(lagr_ctx ctx, lagr_matrix A)
+{
+    if (A->tcache) {
+        matrix_release_arrays_later(ctx, A->tcache);
+        delete A->tcache;
+        A->tcache = nullptr;
+    }
+    if (A->rowptr_bytes) defer_free(ctx, A->rowptr, A->rowptr_bytes);
+    if (A->colidx_bytes) defer_free(ctx, A->colidx, A->colidx_bytes);
+    if (A->values_bytes) defer_free(ctx, A->values, A->values_bytes);
+    A->rowptr = nullptr;
+    A->colidx = nullptr;
+    A->values = nullptr;
+    A->rowptr_bytes = A->colidx_bytes = A->values_bytes = 0;
+}
+
+void vector_release_arrays_later(lagr_ctx ctx, lagr_vector v)
+{
+    if (v->idx_bytes) defer_free(ctx, v->idx, v->idx_bytes);
+    if (v->present_bytes) defer_free(ctx, v->present, v->present_bytes);
+    if (v->values_bytes) defer_free(ctx, v->values, v->values_bytes);
+    v->idx = nullptr;
+    v->present = nullptr;
+    v->values = nullptr;
+    v->idx_bytes = v->present_bytes = v->values_bytes = 0;
+    v->nvals = 0;
+    v->count_dev = nullptr;
+}
+
 void matrix_release_arrays(lagr_matrix A)
 {
+    if (A->tcache) lagr_matrix_free(&A->tcache);
     if (A->rowptr_bytes) dev_free(A->rowptr, A->rowptr_bytes);
     if (A->colidx_bytes) dev_free(A->colidx, A->colidx_bytes);
     if (A->values_bytes) dev_free(A->values, A->values_bytes);
@@ -254,8 +308,53 @@ int matrix_alloc(lagr_matrix A, int64_t nvals, char *msg)
 
 static int check_type(lagr_type t, char *msg)
 {
-    if (t != LAGR_BOOL && t != LAGR_INT64 && t != LAGR_FP64)
+    if (t != LAGR_BOOL && t != LAGR_INT64 && t != LAGR_FP64 && t != LAGR_INT32)
         return lagr_fail(msg, LAGR_INVALID_VALUE, "unknown type %d", (int)t);
+    return LAGR_SUCCESS;
+}
+
+namespace {
+__global__ void k_widen_i32(const int32_t *__restrict__ s, int64_t *__restrict__ d, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = s[i];
+}
+__global__ void k_narrow_i64(const int64_t *__restrict__ s, int32_t *__restrict__ d, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = (int32_t)s[i];
+}
+
+// A library-owned widened copy of n int32 values (nullptr on failure).
+int64_t *widened_copy(lagr_ctx ctx, const void *values, int64_t n, size_t *bytes, char *msg)
+{
+    *bytes = 8 * (size_t)(n > 0 ? n : 1);
+    int64_t *w = (int64_t *)dev_alloc(*bytes);
+    if (!w) {
+        lagr_fail(msg, LAGR_OUT_OF_MEMORY, "INT32 values");
+        return nullptr;
+    }
+    if (widen_i32(ctx, (const int32_t *)values, w, n, msg) < 0) {
+        dev_free(w, *bytes);
+        return nullptr;
+    }
+    return w;
+}
+}  // namespace
+
+int widen_i32(lagr_ctx ctx, const int32_t *src, int64_t *dst, int64_t n, char *msg)
+{
+    if (n <= 0) return LAGR_SUCCESS;
+    hipLaunchKernelGGL(k_widen_i32, dim3(grid_for(n, 256, 16384)), dim3(256), 0, ctx->stream, src, dst, n);
+    LAUNCH_CHECK();
+    return LAGR_SUCCESS;
+}
+
+int narrow_i64(lagr_ctx ctx, const int64_t *src, int32_t *dst, int64_t n, char *msg)
+{
+    if (n <= 0) return LAGR_SUCCESS;
+    hipLaunchKernelGGL(k_narrow_i64, dim3(grid_for(n, 256, 16384)), dim3(256), 0, ctx->stream, src, dst, n);
+    LAUNCH_CHECK();
     return LAGR_SUCCESS;
 }
 
@@ -310,6 +409,13 @@ extern "C" int lagr_matrix_wrap_csr(lagr_matrix *A, lagr_type type, int64_t nrow
     M->rowptr = const_cast<int64_t *>(rowptr);
     M->colidx = const_cast<int32_t *>(colidx);
     M->values = type == LAGR_BOOL ? nullptr : const_cast<void *>(values);
+    if (type == LAGR_INT32) {
+        M->values = widened_copy(ctx, values, nvals, &M->values_bytes, msg);
+        if (!M->values) {
+            delete M;
+            return LAGR_OUT_OF_MEMORY;
+        }
+    }
     *A = M;
     return lagr_ok(msg);
 }
@@ -342,7 +448,9 @@ extern "C" int lagr_matrix_extract_csr(const lagr_matrix A, int64_t *rowptr, int
     if (colidx && A->nvals)
         HIP_TRY(hipMemcpyAsync(colidx, A->colidx, sizeof(int32_t) * A->nvals,
                                hipMemcpyDeviceToDevice, ctx->stream));
-    if (values && A->nvals && A->type != LAGR_BOOL)
+    if (values && A->nvals && A->type == LAGR_INT32)
+        TRY(narrow_i64(ctx, (const int64_t *)A->values, (int32_t *)values, A->nvals, msg));
+    else if (values && A->nvals && A->type != LAGR_BOOL)
         HIP_TRY(hipMemcpyAsync(values, A->values, 8 * A->nvals, hipMemcpyDeviceToDevice,
                                ctx->stream));
     return lagr_ok(msg);
@@ -408,6 +516,10 @@ extern "C" int lagr_vector_wrap_sparse(lagr_vector *v, lagr_type type, int64_t n
     x->nvals = nvals;
     x->idx = const_cast<int32_t *>(idx);
     x->values = type == LAGR_BOOL ? nullptr : const_cast<void *>(values);
+    if (type == LAGR_INT32 && !(x->values = widened_copy(ctx, values, nvals, &x->values_bytes, msg))) {
+        delete x;
+        return LAGR_OUT_OF_MEMORY;
+    }
     *v = x;
     return lagr_ok(msg);
 }
@@ -431,6 +543,10 @@ extern "C" int lagr_vector_wrap_bitmap(lagr_vector *v, lagr_type type, int64_t n
     x->nvals = -1;
     x->present = const_cast<uint8_t *>(present);
     x->values = type == LAGR_BOOL ? nullptr : const_cast<void *>(values);
+    if (type == LAGR_INT32 && !(x->values = widened_copy(ctx, values, n, &x->values_bytes, msg))) {
+        delete x;
+        return LAGR_OUT_OF_MEMORY;
+    }
     *v = x;
     return lagr_ok(msg);
 }
@@ -451,6 +567,10 @@ extern "C" int lagr_vector_wrap_full(lagr_vector *v, lagr_type type, int64_t n, 
     x->fmt = LAGR_VEC_FULL;
     x->nvals = n;
     x->values = const_cast<void *>(values);
+    if (type == LAGR_INT32 && !(x->values = widened_copy(ctx, values, n, &x->values_bytes, msg))) {
+        delete x;
+        return LAGR_OUT_OF_MEMORY;
+    }
     *v = x;
     return lagr_ok(msg);
 }

@@ -14,7 +14,8 @@
 // whose entry count is kept in a device word: no call here waits for the
 // stream or allocates in steady state.  The result's arrays come from a
 // spare pair kept by the context, and w's previous arrays become the spare
-// (double buffering: w may be u or m, as in q = q any.secondi A).
+// (double buffering: w may be u or m, as in q = q any.secondi A); arrays
+// that leave are freed once the queued kernels are done (defer_free).
 //
 // Push: each wavefront takes 64 frontier vertices k (list entries of a
 // SPARSE u, or 64 consecutive indices of a bitmap or full u) and spreads
@@ -308,7 +309,7 @@ int parent_to_bitmap(lagr_ctx ctx, lagr_vector p, char *msg)
     }
     hipLaunchKernelGGL(k_set_word, dim3(1), dim3(1), 0, ctx->stream, cw, (unsigned long long)count);
     LAUNCH_CHECK();
-    vector_release_arrays(p);
+    vector_release_arrays_later(ctx, p);
     p->fmt = LAGR_VEC_BITMAP;
     p->present = pres;
     p->present_bytes = pb;
@@ -443,8 +444,8 @@ int vxm_any_secondi_fast(lagr_vector w, lagr_vector m, lagr_binop accum, lagr_se
     // w's old arrays become the spare (kernels queued above still read
     // them; the next user of the spare is later on the same stream)
     if (w->fmt == LAGR_VEC_BITMAP && w->present_bytes == pb && w->values_bytes == vb) {
-        dev_free(ctx->vspare_present, ctx->vspare_pb);
-        dev_free(ctx->vspare_values, ctx->vspare_vb);
+        defer_free(ctx, ctx->vspare_present, ctx->vspare_pb);
+        defer_free(ctx, ctx->vspare_values, ctx->vspare_vb);
         ctx->vspare_present = w->present;
         ctx->vspare_values = w->values;
         ctx->vspare_pb = pb;
@@ -453,7 +454,7 @@ int vxm_any_secondi_fast(lagr_vector w, lagr_vector m, lagr_binop accum, lagr_se
         w->values = nullptr;
         w->present_bytes = w->values_bytes = 0;
     }
-    vector_release_arrays(w);
+    vector_release_arrays_later(ctx, w);
     w->fmt = LAGR_VEC_BITMAP;
     w->present = wp;
     w->present_bytes = pb;

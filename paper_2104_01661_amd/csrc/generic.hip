@@ -17,6 +17,7 @@
 //     ascending k.  `any` keeps the first, i.e. the smallest k.
 // Transposed inputs are transposed explicitly.  All temporaries are
 // allocated per call and the call waits for the stream before it returns.
+#include <mutex>
 #include <new>
 
 #include "internal.h"
@@ -29,8 +30,11 @@ namespace {
 
 // ------------------------------------------------------------ value algebra
 
-// Values travel as 64-bit words holding an int64 or a double.
-enum VKind { VK_I64 = 0, VK_F64 = 1 };
+// Values travel as 64-bit words holding an int64, a double or a
+// sign-extended int32 (whose arithmetic wraps modulo 2^32).
+enum VKind { VK_I64 = 0, VK_F64 = 1, VK_I32 = 2 };
+
+__device__ __forceinline__ uint64_t wrap32(int64_t x) { return (uint64_t)(int64_t)(int32_t)(uint32_t)x; }
 
 __host__ __device__ __forceinline__ double bits_f(uint64_t b)
 {
@@ -57,7 +61,8 @@ __device__ __forceinline__ uint64_t convert(uint64_t x, int from, int to)
 {
     if (from == to) return x;
     if (to == VK_F64) return f_bits((double)(int64_t)x);
-    return (uint64_t)(int64_t)bits_f(x);
+    const uint64_t i = from == VK_F64 ? (uint64_t)(int64_t)bits_f(x) : x;
+    return to == VK_I32 ? wrap32((int64_t)i) : i;
 }
 
 __device__ __forceinline__ uint64_t binop(int op, int vk, uint64_t c, uint64_t t)
@@ -76,15 +81,17 @@ __device__ __forceinline__ uint64_t binop(int op, int vk, uint64_t c, uint64_t t
         }
     }
     const int64_t x = (int64_t)c, y = (int64_t)t;
+    uint64_t r;
     switch (op) {
-    case LAGR_PLUS: return (uint64_t)(x + y);
-    case LAGR_MIN: return (uint64_t)(y < x ? y : x);
+    case LAGR_PLUS: r = (uint64_t)x + (uint64_t)y; break;
+    case LAGR_MIN: r = (uint64_t)(y < x ? y : x); break;
     case LAGR_FIRST:
-    case LAGR_ANY: return c;
-    case LAGR_SECOND: return t;
-    case LAGR_TIMES: return (uint64_t)(x * y);
-    default: return t;
+    case LAGR_ANY: r = c; break;
+    case LAGR_SECOND: r = t; break;
+    case LAGR_TIMES: r = (uint64_t)x * (uint64_t)y; break;
+    default: r = t; break;
     }
+    return vk == VK_I32 ? wrap32((int64_t)r) : r;
 }
 
 struct Sem {
@@ -122,7 +129,8 @@ __device__ __forceinline__ uint64_t sem_add(const Sem &s, uint64_t r, uint64_t t
     switch (s.semiring) {
     case LAGR_PLUS_PAIR: return r + t;
     case LAGR_ANY_SECONDI: return r;
-    case LAGR_PLUS_FIRST: return s.okind == VK_F64 ? f_bits(bits_f(r) + bits_f(t)) : r + t;
+    case LAGR_PLUS_FIRST:
+        return s.okind == VK_F64 ? f_bits(bits_f(r) + bits_f(t)) : s.okind == VK_I32 ? wrap32((int64_t)(r + t)) : r + t;
     default: {
         const double x = bits_f(r), y = bits_f(t);
         return f_bits(y < x ? y : x);
@@ -604,15 +612,18 @@ __global__ void k_scatter_dense(const Csr V, uint8_t *__restrict__ present, uint
 
 namespace {
 
-// Per-call device allocations, released when the owner goes out of scope
-// (after the stream has been synchronised by the caller).
+// Per-call device allocations.  When the owner goes out of scope they are
+// handed to the context's deferred frees, so the call need not wait for
+// the kernels that read them.
 struct Pool {
     struct Blk {
         void *p;
         size_t n;
     };
+    lagr_ctx ctx;
     Blk blks[48];
     int nb = 0;
+    explicit Pool(lagr_ctx c) : ctx(c) {}
     void *get(size_t bytes)
     {
         if (bytes == 0) bytes = 8;
@@ -632,11 +643,11 @@ struct Pool {
     }
     ~Pool()
     {
-        for (int i = 0; i < nb; i++) dev_free(blks[i].p, blks[i].n);
+        for (int i = 0; i < nb; i++) defer_free(ctx, blks[i].p, blks[i].n);
     }
 };
 
-int vkind_of(lagr_type t) { return t == LAGR_FP64 ? VK_F64 : VK_I64; }
+int vkind_of(lagr_type t) { return t == LAGR_FP64 ? VK_F64 : t == LAGR_INT32 ? VK_I32 : VK_I64; }
 
 Csr view(const lagr_matrix A)
 {
@@ -755,14 +766,14 @@ lagr_type sem_type(lagr_semiring s, lagr_type atype)
     switch (s) {
     case LAGR_PLUS_PAIR:
     case LAGR_ANY_SECONDI: return LAGR_INT64;
-    case LAGR_PLUS_FIRST: return atype == LAGR_FP64 ? LAGR_FP64 : LAGR_INT64;
+    case LAGR_PLUS_FIRST: return atype == LAGR_BOOL ? LAGR_INT64 : atype;
     default: return LAGR_FP64;
     }
 }
 
 // T = A' (+).(x) B' on the positions a (complemented) mask may keep
-int product(lagr_ctx ctx, const Csr &A2, const Csr &B2, const Csr *M, bool structural, bool comp,
-            lagr_semiring semiring, Pool &pool, Csr *T, char *msg)
+int product(lagr_ctx ctx, const Csr &A2, const Csr &B2, const Csr *B2T, const Csr *M, bool structural,
+            bool comp, lagr_semiring semiring, Pool &pool, Csr *T, char *msg)
 {
     const lagr_type ttype = sem_type(semiring, A2.type);
     Sem s;
@@ -773,9 +784,10 @@ int product(lagr_ctx ctx, const Csr &A2, const Csr &B2, const Csr *M, bool struc
     s.akind = semiring == LAGR_MIN_PLUS ? VK_F64 : s.astore;
     s.bkind = semiring == LAGR_MIN_PLUS ? VK_F64 : s.bstore;
     if (M && !comp) {
-        // dot form: needs the rows of B'^T
+        // dot form: needs the rows of B'^T (given, or transposed here)
         Csr BT;
-        TRY(transpose(ctx, B2, pool, &BT, msg));
+        if (B2T) BT = *B2T;
+        else TRY(transpose(ctx, B2, pool, &BT, msg));
         uint64_t *vals = (uint64_t *)pool.get(8 * (M->nvals > 0 ? M->nvals : 1));
         uint8_t *has = (uint8_t *)pool.get(M->nvals > 0 ? M->nvals : 1);
         if (!vals || !has) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "dot form");
@@ -922,9 +934,10 @@ int write_step(lagr_ctx ctx, const Csr &C, const Csr &T, const Csr *M, uint32_t 
     return LAGR_SUCCESS;
 }
 
-void install_matrix(lagr_matrix C, const NewCsr &r)
+void install_matrix(lagr_ctx ctx, lagr_matrix C, const NewCsr &r)
 {
-    matrix_release_arrays(C);
+    // queued kernels may still read C's old arrays (C may be an input)
+    matrix_release_arrays_later(ctx, C);
     C->rowptr = r.rp;
     C->colidx = r.ci;
     C->values = r.val;
@@ -937,14 +950,15 @@ void install_matrix(lagr_matrix C, const NewCsr &r)
 // store a 1-row result into vector w, keeping its storage class
 int install_vector(lagr_ctx ctx, lagr_vector w, const NewCsr &r, char *msg)
 {
+    // queued kernels may still read w's old arrays (w may be an input)
     if (w->fmt == LAGR_VEC_SPARSE) {
-        vector_release_arrays(w);
+        vector_release_arrays_later(ctx, w);
         w->idx = r.ci;
         w->idx_bytes = r.cb;
         w->values = r.val;
         w->values_bytes = r.vb;
         w->nvals = r.nnz;
-        dev_free(r.rp, r.rb);
+        defer_free(ctx, r.rp, r.rb);
         return LAGR_SUCCESS;
     }
     const int64_t n = w->n;
@@ -967,11 +981,10 @@ int install_vector(lagr_ctx ctx, lagr_vector w, const NewCsr &r, char *msg)
         hipLaunchKernelGGL(k_scatter_dense, G1(r.nnz), V, pres, vals);
         LAUNCH_CHECK();
     }
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    dev_free(r.rp, r.rb);
-    dev_free(r.ci, r.cb);
-    dev_free(r.val, r.vb);
-    vector_release_arrays(w);
+    defer_free(ctx, r.rp, r.rb);
+    defer_free(ctx, r.ci, r.cb);
+    defer_free(ctx, r.val, r.vb);
+    vector_release_arrays_later(ctx, w);
     w->values = vals;
     w->values_bytes = vals ? 8 * (size_t)(n > 0 ? n : 1) : 0;
     if (w->fmt == LAGR_VEC_FULL && r.nnz == n && w->type != LAGR_BOOL) {
@@ -1017,7 +1030,7 @@ int check_semiring(lagr_semiring s, char *msg)
 int matrix_transpose(lagr_ctx ctx, const lagr_matrix A, lagr_matrix *out, char *msg)
 {
     *out = nullptr;
-    Pool pool;
+    Pool pool(ctx);
     Csr T;
     TRY(transpose(ctx, view(A), pool, &T, msg));
     lagr_matrix M = new (std::nothrow) lagr_matrix_s();
@@ -1035,13 +1048,21 @@ int matrix_transpose(lagr_ctx ctx, const lagr_matrix A, lagr_matrix *out, char *
     pool.release((void *)T.rp);
     pool.release((void *)T.ci);
     if (T.val) pool.release((void *)T.val);
-    // the pool frees the sort keys when it goes: finish using them first
-    const hipError_t e = hipStreamSynchronize(ctx->stream);
-    if (e != hipSuccess) {
-        lagr_matrix_free(&M);
-        return lagr_fail(msg, LAGR_DEVICE_ERROR, "transpose: %s", hipGetErrorString(e));
-    }
+    // (the pool's sort keys are freed once the queued kernels are done)
     *out = M;
+    return LAGR_SUCCESS;
+}
+
+// Rows of A^T: A's cached transpose, built by the first call that needs it.
+// A matrix is not written while a call reads it, so the cache stays valid
+// until its arrays are replaced; the lock covers two threads asking for
+// the same matrix's transpose at once.
+int cached_transpose(lagr_ctx ctx, const lagr_matrix A, Csr *out, char *msg)
+{
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!A->tcache) TRY(matrix_transpose(ctx, A, &A->tcache, msg));
+    *out = view(A->tcache);
     return LAGR_SUCCESS;
 }
 
@@ -1067,19 +1088,26 @@ extern "C" int lagr_mxm(lagr_matrix C, const lagr_matrix M, lagr_binop accum, la
         return lagr_fail(msg, LAGR_DOMAIN_MISMATCH, "C's type %d differs from the semiring result type %d",
                          (int)C->type, (int)tt);
     TRY(check_accum(accum, C->type, msg));
-    Pool pool;
-    Csr Av = view(A), Bv = view(B), A2 = Av, B2 = Bv;
-    if (t0) TRY(transpose(ctx, Av, pool, &A2, msg));
-    if (t1) TRY(transpose(ctx, Bv, pool, &B2, msg));
+    Pool pool(ctx);
+    Csr A2 = view(A), B2 = view(B), B2T;
+    // the dot form (a mask, not complemented) reads rows of B'^T, which is
+    // B itself under TRAN1; the saxpy form reads rows of B'
+    const bool dot = M && !(desc & LAGR_DESC_COMP);
+    if (t0) TRY(cached_transpose(ctx, A, &A2, msg));
+    if (dot) {
+        if (t1) B2T = view(B);
+        else TRY(cached_transpose(ctx, B, &B2T, msg));
+    } else if (t1) {
+        TRY(cached_transpose(ctx, B, &B2, msg));
+    }
     Csr Mv;
     if (M) Mv = view(M);
     Csr T;
-    TRY(product(ctx, A2, B2, M ? &Mv : nullptr, desc & LAGR_DESC_STRUCT, desc & LAGR_DESC_COMP, semiring,
-                pool, &T, msg));
+    TRY(product(ctx, A2, B2, dot ? &B2T : nullptr, M ? &Mv : nullptr, desc & LAGR_DESC_STRUCT,
+                desc & LAGR_DESC_COMP, semiring, pool, &T, msg));
     NewCsr r;
     TRY(write_step(ctx, view(C), T, M ? &Mv : nullptr, desc, accum, pool, &r, msg));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    install_matrix(C, r);
+    install_matrix(ctx, C, r);
     return lagr_ok(msg);
 }
 
@@ -1110,18 +1138,25 @@ extern "C" int lagr_vxm(lagr_vector w, const lagr_vector m, lagr_binop accum, la
         if (fast) return lagr_ok(msg);
     }
     {
-        Pool pool;
-        Csr U, W, Mv, A2 = view(A);
+        Pool pool(ctx);
+        Csr U, W, Mv, A2 = view(A), A2T;
         TRY(vec_view(ctx, u, pool, &U, msg));
         TRY(vec_view(ctx, w, pool, &W, msg));
         if (m) TRY(vec_view(ctx, m, pool, &Mv, msg));
-        if (t1) TRY(transpose(ctx, view(A), pool, &A2, msg));
+        // as in lagr_mxm: the dot form reads rows of A'^T (A itself under
+        // TRAN1), the saxpy form rows of A'
+        const bool dot = m && !(desc & LAGR_DESC_COMP);
+        if (dot) {
+            if (t1) A2T = view(A);
+            else TRY(cached_transpose(ctx, A, &A2T, msg));
+        } else if (t1) {
+            TRY(cached_transpose(ctx, A, &A2, msg));
+        }
         Csr T;
-        TRY(product(ctx, U, A2, m ? &Mv : nullptr, desc & LAGR_DESC_STRUCT, desc & LAGR_DESC_COMP,
-                    semiring, pool, &T, msg));
+        TRY(product(ctx, U, A2, dot ? &A2T : nullptr, m ? &Mv : nullptr, desc & LAGR_DESC_STRUCT,
+                    desc & LAGR_DESC_COMP, semiring, pool, &T, msg));
         NewCsr r;
         TRY(write_step(ctx, W, T, m ? &Mv : nullptr, desc, accum, pool, &r, msg));
-        HIP_TRY(hipStreamSynchronize(ctx->stream));
         TRY(install_vector(ctx, w, r, msg));
     }
     if (desc & LAGR_DESC_ASSIGN_PARENT) TRY(lagr_assign_vector(m, w, LAGR_NOOP, w, LAGR_DESC_STRUCT, ctx, msg));
@@ -1178,7 +1213,7 @@ extern "C" int lagr_mxm_reduce(void *s, const lagr_matrix M, lagr_semiring semir
 static int reduce_values(lagr_ctx ctx, const uint64_t *vals, int64_t nv, lagr_type from, lagr_type to,
                          lagr_binop monoid, uint64_t *out, char *msg)
 {
-    Pool pool;
+    Pool pool(ctx);
     const int64_t tiles = (nv + RED_TILE - 1) / RED_TILE;
     uint64_t *part = (uint64_t *)pool.get(8 * (tiles + 1));
     if (!part) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "reduce");
@@ -1205,15 +1240,27 @@ static int scalar_result(void *s, lagr_binop accum, lagr_type t, uint64_t r)
         case LAGR_DIV: *x = *x / y; break;
         default: break;   // FIRST / ANY keep s
         }
+    } else if (t == LAGR_INT32) {
+        // modulo 2^32, through unsigned arithmetic
+        const uint32_t y = (uint32_t)r;
+        int32_t *x = (int32_t *)s;
+        switch (accum) {
+        case LAGR_NOOP:
+        case LAGR_SECOND: *x = (int32_t)y; break;
+        case LAGR_PLUS: *x = (int32_t)((uint32_t)*x + y); break;
+        case LAGR_MIN: *x = (int32_t)y < *x ? (int32_t)y : *x; break;
+        case LAGR_TIMES: *x = (int32_t)((uint32_t)*x * y); break;
+        default: break;
+        }
     } else {
         const int64_t y = (int64_t)r;
         int64_t *x = (int64_t *)s;
         switch (accum) {
         case LAGR_NOOP:
         case LAGR_SECOND: *x = y; break;
-        case LAGR_PLUS: *x = *x + y; break;
+        case LAGR_PLUS: *x = (int64_t)((uint64_t)*x + (uint64_t)y); break;
         case LAGR_MIN: *x = y < *x ? y : *x; break;
-        case LAGR_TIMES: *x = *x * y; break;
+        case LAGR_TIMES: *x = (int64_t)((uint64_t)*x * (uint64_t)y); break;
         default: break;
         }
     }
@@ -1226,7 +1273,7 @@ extern "C" int lagr_reduce_scalar(void *s, lagr_binop accum, lagr_binop monoid, 
     if (!s || !A || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
     if (monoid != LAGR_PLUS && monoid != LAGR_MIN)
         return lagr_fail(msg, LAGR_INVALID_VALUE, "the reduce monoid is PLUS or MIN");
-    const lagr_type t = A->type == LAGR_FP64 ? LAGR_FP64 : LAGR_INT64;
+    const lagr_type t = A->type == LAGR_BOOL ? LAGR_INT64 : A->type;
     TRY(check_accum(accum, t, msg));
     if (A->nvals == 0) {
         if (msg) snprintf(msg, LAGR_MSG_LEN, "no entries");
@@ -1244,9 +1291,9 @@ extern "C" int lagr_vector_reduce_scalar(void *s, lagr_binop accum, lagr_binop m
     if (!s || !u || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
     if (monoid != LAGR_PLUS && monoid != LAGR_MIN)
         return lagr_fail(msg, LAGR_INVALID_VALUE, "the reduce monoid is PLUS or MIN");
-    const lagr_type t = u->type == LAGR_FP64 ? LAGR_FP64 : LAGR_INT64;
+    const lagr_type t = u->type == LAGR_BOOL ? LAGR_INT64 : u->type;
     TRY(check_accum(accum, t, msg));
-    Pool pool;
+    Pool pool(ctx);
     Csr U;
     TRY(vec_view(ctx, u, pool, &U, msg));
     if (U.nvals == 0) {
@@ -1271,12 +1318,12 @@ extern "C" int lagr_reduce_rows(lagr_vector w, const lagr_vector m, lagr_binop a
     const int64_t rows = t0 ? A->ncols : A->nrows;
     if (w->n != rows) return lagr_fail(msg, LAGR_DIMENSION_MISMATCH, "w length differs from A' rows");
     if (m && m->n != w->n) return lagr_fail(msg, LAGR_DIMENSION_MISMATCH, "mask length differs from w");
-    const lagr_type t = A->type == LAGR_FP64 ? LAGR_FP64 : LAGR_INT64;
+    const lagr_type t = A->type == LAGR_BOOL ? LAGR_INT64 : A->type;
     if (w->type != t) return lagr_fail(msg, LAGR_DOMAIN_MISMATCH, "w's type differs from A's value type");
     TRY(check_accum(accum, w->type, msg));
-    Pool pool;
+    Pool pool(ctx);
     Csr A2 = view(A);
-    if (t0) TRY(transpose(ctx, view(A), pool, &A2, msg));
+    if (t0) TRY(cached_transpose(ctx, A, &A2, msg));
     int64_t *has = (int64_t *)pool.get(8 * (rows + 1));
     uint64_t *val = (uint64_t *)pool.get(8 * (rows > 0 ? rows : 1));
     int64_t *rp = (int64_t *)pool.get(16);
@@ -1313,7 +1360,6 @@ extern "C" int lagr_reduce_rows(lagr_vector w, const lagr_vector m, lagr_binop a
     if (m) TRY(vec_view(ctx, m, pool, &Mv, msg));
     NewCsr r;
     TRY(write_step(ctx, W, T, m ? &Mv : nullptr, desc, accum, pool, &r, msg));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
     TRY(install_vector(ctx, w, r, msg));
     return lagr_ok(msg);
 }
@@ -1328,14 +1374,13 @@ extern "C" int lagr_assign_vector(lagr_vector w, const lagr_vector m, lagr_binop
     if (w->type == LAGR_BOOL && u->type != LAGR_BOOL)
         return lagr_fail(msg, LAGR_DOMAIN_MISMATCH, "a BOOL vector cannot take values");
     TRY(check_accum(accum, w->type, msg));
-    Pool pool;
+    Pool pool(ctx);
     Csr U, W, Mv;
     TRY(vec_view(ctx, u, pool, &U, msg));
     TRY(vec_view(ctx, w, pool, &W, msg));
     if (m) TRY(vec_view(ctx, m, pool, &Mv, msg));
     NewCsr r;
     TRY(write_step(ctx, W, U, m ? &Mv : nullptr, desc, accum, pool, &r, msg));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
     TRY(install_vector(ctx, w, r, msg));
     return lagr_ok(msg);
 }
@@ -1348,14 +1393,20 @@ extern "C" int lagr_assign_scalar(lagr_vector w, const lagr_vector m, lagr_binop
     if (m && m->n != w->n) return lagr_fail(msg, LAGR_DIMENSION_MISMATCH, "mask length differs from w");
     if (w->type == LAGR_BOOL) return lagr_fail(msg, LAGR_DOMAIN_MISMATCH, "a BOOL vector cannot take values");
     TRY(check_accum(accum, w->type, msg));
-    Pool pool;
+    Pool pool(ctx);
     const int64_t n = w->n;
     int32_t *ci = (int32_t *)pool.get(4 * (n > 0 ? n : 1));
     uint64_t *va = (uint64_t *)pool.get(8 * (n > 0 ? n : 1));
     int64_t *rp = (int64_t *)pool.get(16);
     if (!ci || !va || !rp) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "assign");
     uint64_t sv;
-    memcpy(&sv, s, 8);
+    if (w->type == LAGR_INT32) {
+        int32_t s32;
+        memcpy(&s32, s, 4);
+        sv = (uint64_t)(int64_t)s32;
+    } else {
+        memcpy(&sv, s, 8);
+    }
     if (n > 0) {
         hipLaunchKernelGGL(k_iota32, G1(n), ci, n);
         LAUNCH_CHECK();
@@ -1377,7 +1428,6 @@ extern "C" int lagr_assign_scalar(lagr_vector w, const lagr_vector m, lagr_binop
     if (m) TRY(vec_view(ctx, m, pool, &Mv, msg));
     NewCsr r;
     TRY(write_step(ctx, W, T, m ? &Mv : nullptr, desc, accum, pool, &r, msg));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
     TRY(install_vector(ctx, w, r, msg));
     return lagr_ok(msg);
 }
@@ -1399,10 +1449,10 @@ static int ewise(bool uni, lagr_matrix C, const lagr_matrix M, lagr_binop accum,
     if (op == LAGR_DIV && C->type != LAGR_FP64)
         return lagr_fail(msg, LAGR_DOMAIN_MISMATCH, "DIV is defined on FP64 only");
     TRY(check_accum(accum, C->type, msg));
-    Pool pool;
+    Pool pool(ctx);
     Csr A2 = view(A), B2 = view(B);
-    if (t0) TRY(transpose(ctx, view(A), pool, &A2, msg));
-    if (t1) TRY(transpose(ctx, view(B), pool, &B2, msg));
+    if (t0) TRY(cached_transpose(ctx, A, &A2, msg));
+    if (t1) TRY(cached_transpose(ctx, B, &B2, msg));
     const int vk = vkind_of(C->type);
     int64_t *off = (int64_t *)pool.get(8 * (ar + 1));
     if (!off) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "ewise");
@@ -1444,8 +1494,7 @@ static int ewise(bool uni, lagr_matrix C, const lagr_matrix M, lagr_binop accum,
     if (M) Mv = view(M);
     NewCsr r;
     TRY(write_step(ctx, view(C), T, M ? &Mv : nullptr, desc, accum, pool, &r, msg));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    install_matrix(C, r);
+    install_matrix(ctx, C, r);
     return lagr_ok(msg);
 }
 

@@ -11,6 +11,7 @@
 #include "../../include/lagr.h"
 
 #include <string>
+#include <utility>
 #include <vector>
 
 // ------------------------------------------------------------------ errors
@@ -144,7 +145,18 @@ struct lagr_ctx_s {
     uint8_t *vspare_present = nullptr;
     void *vspare_values = nullptr;
     size_t vspare_pb = 0, vspare_vb = 0;
+    // device buffers that queued work may still read, freed at this
+    // context's next wait for its stream (defer_free)
+    std::vector<std::pair<void *, size_t>> deferred;
+    size_t deferred_bytes = 0;
 };
+
+// Free p once the work queued so far on ctx's stream is done: at the
+// context's next wait (lagr_wait, a read-back, a host wait), or at once
+// after a stream sync when more than 2 GiB are pending.
+void defer_free(lagr_ctx ctx, void *p, size_t bytes);
+// Free everything deferred (the caller has waited for the stream).
+void flush_deferred(lagr_ctx ctx);
 
 // Returns a device buffer of at least `bytes` for the slot (contents are
 // undefined).  nullptr on allocation failure.
@@ -157,6 +169,9 @@ struct lagr_matrix_s {
     int32_t *colidx = nullptr;
     void *values = nullptr;
     size_t rowptr_bytes = 0, colidx_bytes = 0, values_bytes = 0;  // 0 = borrowed
+    // the transpose, built on the first call that asks for it with a
+    // transpose descriptor and dropped with the arrays
+    lagr_matrix_s *tcache = nullptr;
 };
 
 struct lagr_vector_s {
@@ -233,10 +248,18 @@ constexpr int64_t GRAPH_LONG_ROW = 512;
 
 
 static inline size_t type_size(lagr_type t) { return t == LAGR_BOOL ? 0 : 8; }
+// Bytes of one value in arrays that cross the boundary.
+static inline size_t api_value_size(lagr_type t) { return t == LAGR_BOOL ? 0 : t == LAGR_INT32 ? 4 : 8; }
+// int32 <-> the 8-byte slots the library keeps values in (n values).
+int widen_i32(lagr_ctx ctx, const int32_t *src, int64_t *dst, int64_t n, char *msg);
+int narrow_i64(lagr_ctx ctx, const int64_t *src, int32_t *dst, int64_t n, char *msg);
 
 // Release a matrix's / vector's owned arrays and reset them to empty.
 void matrix_release_arrays(lagr_matrix A);
 void vector_release_arrays(lagr_vector v);
+// The same, with the frees deferred until ctx's queued work is done.
+void matrix_release_arrays_later(lagr_ctx ctx, lagr_matrix A);
+void vector_release_arrays_later(lagr_ctx ctx, lagr_vector v);
 // Entries of a presence-byte map (synchronises).
 int bitmap_count(lagr_ctx ctx, const uint8_t *present, int64_t n, int64_t *count, char *msg);
 // vxm with any.secondi under a complemented structural mask with replace

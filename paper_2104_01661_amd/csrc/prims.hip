@@ -357,6 +357,7 @@ int wait_host_flag(lagr_ctx ctx, uint32_t seq, char *msg)
     for (unsigned it = 1;; it++) {
         if (*f == seq) {
             std::atomic_thread_fence(std::memory_order_acquire);
+            flush_deferred(ctx);        // the stream has run up to the flag
             return LAGR_SUCCESS;
         }
         if ((it & 63u) == 0) {
@@ -370,6 +371,7 @@ int wait_host_flag(lagr_ctx ctx, uint32_t seq, char *msg)
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     if (*f != seq) return lagr_fail(msg, LAGR_DEVICE_ERROR, "host flag %u not set after the stream drained", seq);
     std::atomic_thread_fence(std::memory_order_acquire);
+    flush_deferred(ctx);
     return LAGR_SUCCESS;
 }
 }  // namespace
@@ -382,7 +384,10 @@ int stage_to_host(lagr_ctx ctx, size_t offset, const void *dev, size_t bytes, bo
     const bool words = ((uintptr_t)dev & 3u) == 0 && (bytes & 3u) == 0 && (offset & 3u) == 0;
     if (!words) {
         HIP_TRY(hipMemcpyAsync((char *)ctx->pinned + offset, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
-        if (wait) HIP_TRY(hipStreamSynchronize(ctx->stream));
+        if (wait) {
+            HIP_TRY(hipStreamSynchronize(ctx->stream));
+            flush_deferred(ctx);
+        }
         return LAGR_SUCCESS;
     }
     if (bytes == 0 && !wait) return LAGR_SUCCESS;

@@ -694,7 +694,7 @@ extern "C" int lagr_tc_autotune(int64_t *hubs, lagr_graph G, lagr_ctx ctx, char 
             TRY(lagr_graph_delete_properties(G, ctx, msg));
             const auto t0 = std::chrono::steady_clock::now();
             int64_t t = 0;
-            TRY(lagr_tc(&t, G, ctx, msg));
+            TRY(lagr_tc(&t, G, LAGR_TC_DEFAULT, ctx, msg));
             ts[r] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
             if (t_ref < 0) t_ref = t;
             if (t != t_ref) return lagr_fail(msg, LAGR_DEVICE_ERROR, "tuning candidates counted differently");
@@ -786,9 +786,32 @@ extern "C" int lagr_tc_adv_noalloc(int64_t *ntriangles_dev, const lagr_graph G, 
     return lagr_ok(msg);
 }
 
-extern "C" int lagr_tc(int64_t *ntriangles, lagr_graph G, lagr_ctx ctx, char *msg)
+// The three methods count the same C<s(L)> = L plus.pair L^T, reduced
+// (Algorithm 6): the count plan (the default), the fused masked dot of
+// lagr_mxm_reduce over L, or Algorithm 6 as written -- C formed by
+// lagr_mxm, then reduced by lagr_reduce_scalar.
+extern "C" int lagr_tc(int64_t *ntriangles, lagr_graph G, int method, lagr_ctx ctx, char *msg)
 {
     if (!ntriangles || !G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    if (method < LAGR_TC_DEFAULT || method > LAGR_TC_MXM)
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "unknown triangle-count method %d", method);
     TRY(lagr_property_tc_lower(G, ctx, msg));
-    return lagr_tc_adv(ntriangles, G, ctx, msg);
+    if (method == LAGR_TC_DEFAULT) return lagr_tc_adv(ntriangles, G, ctx, msg);
+    const lagr_matrix Lm = G->L;
+    const uint32_t desc = LAGR_DESC_STRUCT | LAGR_DESC_TRAN1;
+    if (method == LAGR_TC_DOT) {
+        int64_t t = 0;
+        TRY(lagr_mxm_reduce(&t, Lm, LAGR_PLUS_PAIR, Lm, Lm, desc, ctx, msg));
+        *ntriangles = t;
+        return lagr_ok(msg);
+    }
+    lagr_matrix C = nullptr;
+    TRY(lagr_matrix_new(&C, LAGR_INT64, Lm->nrows, Lm->ncols, ctx, msg));
+    int rc = lagr_mxm(C, Lm, LAGR_NOOP, LAGR_PLUS_PAIR, Lm, Lm, desc, ctx, msg);
+    int64_t t = 0;
+    if (rc >= 0) rc = lagr_reduce_scalar(&t, LAGR_NOOP, LAGR_PLUS, C, ctx, msg);
+    lagr_matrix_free(&C);
+    if (rc < 0) return rc;
+    *ntriangles = t;          // no entry (LAGR_NO_VALUE): no triangle
+    return lagr_ok(msg);
 }

@@ -136,6 +136,15 @@ extern "C" int lagr_vector_extract_tuples(const lagr_vector v, int32_t *idx, voi
 {
     if (!v || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
     int64_t nv = 0;
+    if (v->type == LAGR_INT32 && values) {
+        // the values go through 8-byte slots, then narrow
+        TRY(lagr_vector_nvals(&nv, v, ctx, msg));
+        int64_t *tmp = (int64_t *)ws_get(ctx, WS_GEN_G, 8 * (size_t)(nv > 0 ? nv : 1));
+        if (!tmp) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "extract");
+        TRY(vector_tuples(ctx, v, idx, tmp, &nv, msg));
+        TRY(narrow_i64(ctx, tmp, (int32_t *)values, nv, msg));
+        return lagr_ok(msg);
+    }
     TRY(vector_tuples(ctx, v, idx, values, &nv, msg));
     return lagr_ok(msg);
 }
@@ -146,9 +155,21 @@ extern "C" int lagr_vector_extract_dense(const lagr_vector v, uint8_t *present, 
     if (!v || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
     const int64_t n = v->n;
     uint64_t f = 0;
-    if (fill && v->type != LAGR_BOOL) memcpy(&f, fill, 8);
+    if (fill && v->type == LAGR_INT32) {
+        int32_t f32;
+        memcpy(&f32, fill, 4);
+        f = (uint64_t)(int64_t)f32;
+    } else if (fill && v->type != LAGR_BOOL) {
+        memcpy(&f, fill, 8);
+    }
     if (v->type == LAGR_BOOL) values = nullptr;
     if (n == 0) return lagr_ok(msg);
+    void *out32 = nullptr;      // INT32: the caller's array, filled by narrowing
+    if (v->type == LAGR_INT32 && values) {
+        out32 = values;
+        values = ws_get(ctx, WS_GEN_G, 8 * (size_t)n);
+        if (!values) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "extract");
+    }
     if (v->fmt == LAGR_VEC_SPARSE) {
         hipLaunchKernelGGL(k_dense_from_bitmap, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
                            ctx->stream, (const uint8_t *)nullptr, (const uint64_t *)nullptr, n, f,
@@ -167,5 +188,6 @@ extern "C" int lagr_vector_extract_dense(const lagr_vector v, uint8_t *present, 
                            (const uint64_t *)v->values, n, f, present, (uint64_t *)values);
         LAUNCH_CHECK();
     }
+    if (out32) TRY(narrow_i64(ctx, (const int64_t *)values, (int32_t *)out32, n, msg));
     return lagr_ok(msg);
 }

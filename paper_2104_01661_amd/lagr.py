@@ -29,7 +29,7 @@ DIMENSION_MISMATCH, INVALID_OBJECT, OUT_OF_MEMORY, PROPERTY_MISSING = -5, -6, -7
 NOT_IMPLEMENTED, DEVICE_ERROR, BUDGET_EXCEEDED = -9, -10, -11
 
 # types
-BOOL, INT64, FP64 = 0, 1, 2
+BOOL, INT64, FP64, INT32 = 0, 1, 2, 3
 # semirings
 PLUS_PAIR, ANY_SECONDI, PLUS_FIRST, MIN_PLUS = 0, 1, 2, 3
 # binops
@@ -105,7 +105,7 @@ _PROTOS = {
     "lagr_graph_delete_properties": [_P, _P, _C],
     "lagr_graph_ndiag": [_P, _P, _C],
     "lagr_graph_free": [_PP],
-    "lagr_tc": [_P, _P, _P, _C],
+    "lagr_tc": [_P, _P, _INT, _P, _C],
     "lagr_tc_adv": [_P, _P, _P, _C],
     "lagr_tc_adv_noalloc": [_P, _P, _P, _C],
     "lagr_bfs": [_PP, _PP, _P, _I64, _U32, _P, _C],
@@ -224,7 +224,22 @@ class Context:
             pass
 
 
-_TORCH = {BOOL: None, INT64: torch.int64, FP64: torch.float64}
+_TORCH = {BOOL: None, INT64: torch.int64, FP64: torch.float64, INT32: torch.int32}
+
+
+def _scalar(typ, value=None):
+    """A host scalar of the library type typ (int64 for BOOL)."""
+    if typ == FP64:
+        return ctypes.c_double(value or 0.0)
+    if typ == INT32:
+        return ctypes.c_int32(value or 0)
+    return ctypes.c_int64(value or 0)
+
+
+def _typ_of(values):
+    if values is None:
+        return BOOL
+    return {torch.float64: FP64, torch.int32: INT32}.get(values.dtype, INT64)
 
 
 class Matrix:
@@ -243,7 +258,7 @@ class Matrix:
     @classmethod
     def wrap_csr(cls, ctx, nrows, ncols, rowptr, colidx, values=None, typ=None):
         if typ is None:
-            typ = BOOL if values is None else (FP64 if values.dtype == torch.float64 else INT64)
+            typ = _typ_of(values)
         rowptr = rowptr.to(torch.int64).contiguous()
         colidx = colidx.to(torch.int32).contiguous()
         if values is not None:
@@ -303,7 +318,7 @@ class Vector:
     @classmethod
     def wrap_sparse(cls, ctx, n, idx, values=None, typ=None):
         if typ is None:
-            typ = BOOL if values is None else (FP64 if values.dtype == torch.float64 else INT64)
+            typ = _typ_of(values)
         idx = idx.to(torch.int32).contiguous()
         if values is not None:
             values = values.to(_TORCH[typ]).contiguous()
@@ -315,7 +330,7 @@ class Vector:
     @classmethod
     def wrap_bitmap(cls, ctx, present, values=None, typ=None):
         if typ is None:
-            typ = BOOL if values is None else (FP64 if values.dtype == torch.float64 else INT64)
+            typ = _typ_of(values)
         present = present.to(torch.uint8).contiguous()
         if values is not None:
             values = values.to(_TORCH[typ]).contiguous()
@@ -326,7 +341,7 @@ class Vector:
 
     @classmethod
     def wrap_full(cls, ctx, values):
-        typ = FP64 if values.dtype == torch.float64 else INT64
+        typ = _typ_of(values)
         values = values.to(_TORCH[typ]).contiguous()
         h = ctypes.c_void_p()
         call("lagr_vector_wrap_full", ctypes.byref(h), typ, values.numel(), _ptr(values), ctx.h)
@@ -349,7 +364,7 @@ class Vector:
         pres = torch.empty(n, dtype=torch.uint8, device=dev)
         vt = _TORCH[typ] or torch.int64
         vals = torch.empty(n, dtype=vt, device=dev)
-        f = ctypes.c_int64(fill) if vt == torch.int64 else ctypes.c_double(fill)
+        f = _scalar(typ, fill)
         call("lagr_vector_extract_dense", self.h, _ptr(pres), None if typ == BOOL else _ptr(vals),
              ctypes.byref(f), ctx.h)
         ctx.wait()
@@ -443,9 +458,12 @@ class Graph:
 
 # ------------------------------------------------------------ algorithms
 
-def lagr_tc(G: Graph, ctx: Context) -> int:
+TC_DEFAULT, TC_DOT, TC_MXM = 0, 1, 2
+
+
+def lagr_tc(G: Graph, ctx: Context, method: int = TC_DEFAULT) -> int:
     t = ctypes.c_int64()
-    call("lagr_tc", ctypes.byref(t), G.h, ctx.h)
+    call("lagr_tc", ctypes.byref(t), G.h, method, ctx.h)
     return t.value
 
 
@@ -552,13 +570,13 @@ def lagr_mxm_reduce(M: Matrix, semiring, A: Matrix, B: Matrix, desc, ctx: Contex
 
 
 def lagr_reduce_scalar(A: Matrix, monoid, ctx: Context, accum=NOOP, init=None, fp64=False):
-    s = ctypes.c_double(init or 0.0) if fp64 else ctypes.c_int64(init or 0)
+    s = _scalar(A.info()[0], init)
     rc = call("lagr_reduce_scalar", ctypes.byref(s), accum, monoid, A.h, ctx.h)
     return None if rc == NO_VALUE and init is None else s.value
 
 
 def lagr_vector_reduce_scalar(u: Vector, monoid, ctx: Context, accum=NOOP, init=None, fp64=False):
-    s = ctypes.c_double(init or 0.0) if fp64 else ctypes.c_int64(init or 0)
+    s = _scalar(u.info()[0], init)
     rc = call("lagr_vector_reduce_scalar", ctypes.byref(s), accum, monoid, u.h, ctx.h)
     return None if rc == NO_VALUE and init is None else s.value
 
@@ -572,7 +590,7 @@ def lagr_assign_vector(w: Vector, m, accum, u: Vector, desc, ctx: Context):
 
 
 def lagr_assign_scalar(w: Vector, m, accum, s, desc, ctx: Context, fp64=False):
-    x = ctypes.c_double(s) if fp64 else ctypes.c_int64(s)
+    x = _scalar(w.info()[0], s)
     return call("lagr_assign_scalar", w.h, None if m is None else m.h, accum, ctypes.byref(x), desc,
                 ctx.h)
 

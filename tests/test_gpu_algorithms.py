@@ -185,6 +185,28 @@ def test_tc_large_config():
     assert lagr().lagr_tc(G, ctx()) == e["triangles"]
 
 
+@pytest.mark.parametrize("scale,ef,seed", [(10, 16, 1), (14, 16, 103)])
+def test_tc_methods_agree_with_the_oracle(scale, ef, seed):
+    """lagr_tc's three methods -- the count plan, the fused masked dot of
+    lagr_mxm_reduce, and Algorithm 6 as written (C formed by lagr_mxm, then
+    reduced) -- all equal the oracle's count; K_12 gives C(12, 3); an
+    unknown method is rejected."""
+    L = lagr()
+    c = ctx()
+    n, s, d = rmat(scale, ef, seed)
+    G = device_graph(n, s, d)
+    want = oracle.triangle_count(*oracle.build_adjacency(n, s, d))
+    for method in (L.TC_DEFAULT, L.TC_DOT, L.TC_MXM, L.TC_DOT, L.TC_DEFAULT):
+        assert L.lagr_tc(G, c, method) == want, method
+    G, _ = graph_from_edges(*Gs.complete(12))
+    assert [L.lagr_tc(G, c, m) for m in (0, 1, 2)] == [220] * 3
+    G, _ = graph_from_edges(*Gs.path(9))
+    assert [L.lagr_tc(G, c, m) for m in (0, 1, 2)] == [0] * 3
+    with pytest.raises(L.LagrError) as e:
+        L.lagr_tc(G, c, 3)
+    assert e.value.code == L.INVALID_VALUE
+
+
 @pytest.mark.parametrize("scale,ef,seed", [(18, 8, 41), (18, 16, 42)])
 def test_tc_with_hub_columns_matches_the_oracle(scale, ef, seed):
     """Graphs of 2^18 vertices: the count plan keeps pairs with one of the

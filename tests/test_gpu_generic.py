@@ -15,8 +15,9 @@ from gpu_util import ctx, device_graph, lagr
 
 pytestmark = pytest.mark.gpu
 
-KIND = {"bool": 0, "int64": 1, "fp64": 2}
-NAME = {0: "bool", 1: "int64", 2: "fp64"}
+KIND = {"bool": 0, "int64": 1, "fp64": 2, "int32": 3}
+NAME = {0: "bool", 1: "int64", 2: "fp64", 3: "int32"}
+TDTYPE = {"int64": torch.int64, "fp64": torch.float64, "int32": torch.int32}
 SEMIRINGS = {0: "plus.pair", 1: "any.secondi", 2: "plus.first", 3: "min.plus"}
 BINOPS = {0: None, 1: "plus", 2: "min", 3: "first", 4: "second", 5: "times", 6: "div", 7: "any"}
 
@@ -30,6 +31,9 @@ def rand_mat(rng, m, n, density, kind):
                     e[(i, j)] = 1
                 elif kind == "int64":
                     e[(i, j)] = int(rng.integers(-2, 6))
+                elif kind == "int32":
+                    # large magnitudes, so that sums and products wrap
+                    e[(i, j)] = int(rng.integers(-2 ** 31, 2 ** 31))
                 else:
                     e[(i, j)] = float(rng.integers(-2, 6))
     return S.Mat(m, n, e, kind)
@@ -49,10 +53,8 @@ def to_dev(M: S.Mat):
     rp = np.cumsum(rp)
     ci = np.array([j for _, j in keys], dtype=np.int32)
     vals = None
-    if M.kind == "int64":
-        vals = torch.tensor([M.e[k] for k in keys], dtype=torch.int64, device="cuda")
-    elif M.kind == "fp64":
-        vals = torch.tensor([M.e[k] for k in keys], dtype=torch.float64, device="cuda")
+    if M.kind != "bool":
+        vals = torch.tensor([M.e[k] for k in keys], dtype=TDTYPE[M.kind], device="cuda")
     return L.Matrix.wrap_csr(ctx(), M.nrows, M.ncols, torch.from_numpy(rp).cuda(),
                              torch.from_numpy(ci).cuda(), vals, typ=KIND[M.kind])
 
@@ -73,7 +75,7 @@ def vec_to_dev(v: S.Vec, fmt):
     L = lagr()
     c = ctx()
     idx = sorted(v.e)
-    dt = {"int64": torch.int64, "fp64": torch.float64}.get(v.kind)
+    dt = TDTYPE.get(v.kind)
     if fmt == "sparse":
         vals = None if v.kind == "bool" else torch.tensor([v.e[i] for i in idx], dtype=dt, device="cuda")
         return L.Vector.wrap_sparse(c, v.n, torch.tensor(idx, dtype=torch.int32, device="cuda"), vals,
@@ -240,6 +242,52 @@ def test_vxm_push_splits_long_rows():
         for mode in ("push", "auto"):
             pa, depth = bfs_graphblas(c, A, A, n, s0, mode)
             assert np.array_equal(pa, mp) and depth == int(lv.max())
+
+
+def test_int32_domain_against_the_semantics_oracle():
+    """LAGR_INT32 end to end: wraps widen the caller's int32 values,
+    extracts narrow them, and results whose type is INT32 (plus.first over
+    an INT32 A, eWise, accumulators, reductions, assign) are taken modulo
+    2^32, equal to the semantics oracle's int32 domain; the values are
+    drawn over the whole int32 range so that nearly every sum wraps."""
+    L = lagr()
+    c = ctx()
+    rng = np.random.default_rng(41)
+    for trial in range(6):
+        A = rand_mat(rng, 5, 6, 0.6, "int32")
+        B = rand_mat(rng, 6, 7, 0.6, "bool")
+        C0 = rand_mat(rng, 5, 7, 0.4, "int32")
+        M = rand_mat(rng, 5, 7, 0.6, "int64")
+        for accum, comp in ((0, False), (1, False), (2, True), (5, False)):
+            want = S.mxm(C0, M, BINOPS[accum], "plus.first", A, B, comp=comp, deterministic=True)
+            Cd = to_dev(C0)
+            L.lagr_mxm(Cd, to_dev(M), accum, L.PLUS_FIRST, to_dev(A), to_dev(B),
+                       desc_bits(comp, False, False, False, False), c)
+            same(from_dev(Cd).e, want.e)
+        X = rand_mat(rng, 5, 7, 0.5, "int32")
+        for op, f in ((1, S.ewise_add), (5, S.ewise_mult), (2, S.ewise_add)):
+            want = f(C0, None, BINOPS[1], BINOPS[op], C0, X)
+            Cd = to_dev(C0)
+            fn = L.lagr_ewise_add if f is S.ewise_add else L.lagr_ewise_mult
+            fn(Cd, None, 1, op, to_dev(C0), to_dev(X), 0, c)
+            same(from_dev(Cd).e, want.e)
+        assert L.lagr_reduce_scalar(to_dev(X), L.PLUS, c) == S.reduce_scalar(X, "plus")
+        assert L.lagr_reduce_scalar(to_dev(X), L.MIN, c) == S.reduce_scalar(X, "min")
+        w0 = rand_vec(rng, 5, 0.5, "int32")
+        for fmt in ("sparse", "bitmap"):
+            wd = vec_to_dev(w0, fmt)
+            L.lagr_reduce_rows(wd, None, 1, L.PLUS, to_dev(X), 0, c)
+            same(vec_from_dev(wd).e, S.reduce_rows(w0, None, "plus", "plus", X).e)
+            wd = vec_to_dev(w0, fmt)
+            L.lagr_assign_scalar(wd, None, 1, 2 ** 31 - 1, 0, c)
+            same(vec_from_dev(wd).e, S.assign_scalar(w0, None, "plus", 2 ** 31 - 1).e)
+        u = rand_vec(rng, 5, 1.0, "int32")
+        ud = vec_to_dev(u, "full")
+        pres, vals = ud.to_dense(c, fill=-3)
+        assert vals.dtype == torch.int32 and vals.cpu().tolist() == [u.e[i] for i in range(5)]
+        w = L.Vector.new(c, L.INT32, 6)
+        L.lagr_vxm(w, None, 0, L.PLUS_FIRST, ud, to_dev(A), 0, c)
+        same(vec_from_dev(w).e, S.vxm(S.Vec(6, {}, "int32"), None, None, "plus.first", u, A).e)
 
 
 def test_ewise_assign_reduce():

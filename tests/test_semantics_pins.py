@@ -262,3 +262,31 @@ def test_algorithm5_fixpoint_through_semantics_matches_dijkstra():
     for j, x in t.e.items():
         got[j] = x
     assert np.array_equal(got, oracle.dijkstra(rp, ci, w, 0))
+
+
+def test_int32_domain_wraps_like_numpy_int32():
+    """The int32 domain (GraphBLAS C API, which the paper defers to):
+    results are taken modulo 2^32.  Worked by hand, and against numpy's
+    int32 arithmetic, which wraps the same way."""
+    big = 2 ** 31 - 1
+    A = S.Mat(1, 2, {(0, 0): big, (0, 1): 1}, "int32")
+    ones = S.Mat(2, 1, {(0, 0): 1, (1, 0): 1}, "bool")
+    C = S.mxm(S.Mat(1, 1, {}, "int32"), None, None, "plus.first", A, ones)
+    assert C.e == {(0, 0): -2 ** 31}
+    # the product is stored as int32 before the accumulator: min(5, -2^31)
+    C = S.mxm(S.Mat(1, 1, {(0, 0): 5}, "int32"), None, "min", "plus.first", A, ones)
+    assert C.e == {(0, 0): -2 ** 31}
+    # an int64 output of the same product does not wrap
+    A64 = S.Mat(1, 2, {(0, 0): big, (0, 1): 1}, "int64")
+    assert S.mxm(S.Mat(1, 1, {}, "int64"), None, None, "plus.first", A64, ones).e == {(0, 0): 2 ** 31}
+    X = S.Mat(1, 2, {(0, 0): 65536, (0, 1): 3}, "int32")
+    Y = S.Mat(1, 2, {(0, 0): 65536, (0, 1): -7}, "int32")
+    assert S.ewise_mult(S.Mat(1, 2, {}, "int32"), None, None, "times", X, Y).e == {(0, 0): 0, (0, 1): -21}
+    rng = np.random.default_rng(5)
+    vals = rng.integers(-2 ** 31, 2 ** 31, 40)
+    M = S.Mat(5, 8, {(k // 8, k % 8): int(v) for k, v in enumerate(vals)}, "int32")
+    assert S.reduce_scalar(M, "plus") == int(np.sum(vals.astype(np.int32), dtype=np.int32))
+    w = S.reduce_rows(S.Vec(5, {}, "int32"), None, None, "plus", M)
+    assert w.e == {i: int(np.sum(vals[8 * i:8 * i + 8].astype(np.int32), dtype=np.int32)) for i in range(5)}
+    s = S.assign_scalar(S.Vec(3, {1: big}, "int32"), None, "plus", 1)
+    assert s.e == {0: 1, 1: -2 ** 31, 2: 1}
