@@ -551,9 +551,16 @@ int lagr_batch_free(lagr_batch *B);
  * same kind on the same graph: up to max_bfs_batch BFS queries run as one
  * multi-source BFS (one wavefront lane each), up to max_bc_batch BC
  * queries of up to 8 sources run as one 64-lane Algorithm 3 batch, and all
- * visible counts of one graph share one count.  A batch is admitted only
- * when its working-set estimate fits budget_bytes beside the running
- * batches; one larger than the whole budget completes with status
+ * visible counts of one graph share one count.  While max_bc_workers
+ * workers run BC batches, a free worker takes the oldest visible query of
+ * another kind instead, so short queries do not wait behind long ones.
+ * Memory: the server accounts, per worker, the larger of the device memory
+ * its context and buffers hold from earlier batches (measured after each
+ * batch) and its running batch's working-set estimate, plus the kept
+ * result vectors.  A batch is admitted only when that total, with its own
+ * estimate, fits budget_bytes; when nothing runs and it still does not
+ * fit, the workers free their held workspaces first.  A batch whose
+ * estimate alone exceeds the budget completes with status
  * LAGR_BUDGET_EXCEEDED.  Every result is the same whatever the batch. */
 typedef struct lagr_server_s *lagr_server;
 enum { LAGR_QUERY_TC = 0, LAGR_QUERY_BFS = 1, LAGR_QUERY_BC = 2 };
@@ -563,6 +570,8 @@ typedef struct {
     int32_t max_bc_batch;   /* 1..8 */
     int32_t keep_vectors;   /* keep each BFS level / BC vector for lagr_server_result_vector */
     int64_t budget_bytes;   /* device working-set budget over concurrent batches */
+    int32_t max_bc_workers; /* workers that may run BC batches at once (0: workers - 2, at least 1) */
+    int32_t pad_;
 } lagr_server_config;
 typedef struct {
     int32_t kind;           /* LAGR_QUERY_* */
@@ -589,8 +598,13 @@ typedef struct {
     int64_t completed;
     int64_t batches[3], queries[3];   /* per LAGR_QUERY_* */
     int64_t rejected;
-    int64_t peak_bytes;     /* largest admitted working-set estimate in flight */
+    int64_t peak_bytes;     /* largest accounted use when a batch was admitted: kept vectors +
+                               per worker the larger of its held workspace and its running
+                               batch's estimate (at most budget_bytes, unless a batch had to
+                               run alone beside kept vectors) */
     int64_t pending;
+    int64_t device_peak_bytes;   /* largest device use hipMemGetInfo showed after a batch */
+    int64_t held_bytes;          /* accounted use now */
 } lagr_server_counts;
 /* Builds every graph's cached triangle-count operand and long-row chunk
  * list on ctx's stream (so workers never write a graph), then starts the

@@ -658,6 +658,7 @@ __global__ void k_ms_sources(const int64_t *__restrict__ src, uint64_t *__restri
 int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nbatches, int gshift,
                double *cent, char *msg)
 {
+    ctx->last_bc_levels = 0;
     const lagr_matrix A = G->A;
     const int64_t n = A->nrows;
     const size_t n1 = (size_t)(n > 0 ? n : 1);
@@ -810,6 +811,7 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
             d0 += chunk;
         }
         depth = nlev.size() - 1;   // the deepest non-empty level
+        if ((int64_t)nlev.size() > ctx->last_bc_levels) ctx->last_bc_levels = (int64_t)nlev.size();
         // backward sweep: targets at depth i-1 gather from depth i
         for (size_t i = depth + 1; i >= 2; i--) {
             const int has_deeper = i <= depth ? 1 : 0;

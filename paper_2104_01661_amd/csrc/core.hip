@@ -233,6 +233,50 @@ void defer_free(lagr_ctx ctx, void *p, size_t bytes)
     }
 }
 
+size_t ctx_retained_bytes(const lagr_ctx ctx)
+{
+    size_t b = ctx->lv_bytes * ctx->lvpool.size() + ctx->vspare_pb + ctx->vspare_vb + ctx->deferred_bytes;
+    for (int s = 0; s < WS_NSLOTS; s++) b += ctx->ws_bytes[s];
+    return b;
+}
+
+void ctx_trim(lagr_ctx ctx)
+{
+    (void)hipStreamSynchronize(ctx->stream);
+    flush_deferred(ctx);
+    // captured graphs point into the workspace: drop them with it
+    if (ctx->bfs_exec) (void)hipGraphExecDestroy(ctx->bfs_exec);
+    if (ctx->bfs_exec_more) (void)hipGraphExecDestroy(ctx->bfs_exec_more);
+    if (ctx->bfs_graph) (void)hipGraphDestroy(ctx->bfs_graph);
+    if (ctx->sssp_exec) (void)hipGraphExecDestroy(ctx->sssp_exec);
+    if (ctx->ms_exec) (void)hipGraphExecDestroy(ctx->ms_exec);
+    ctx->bfs_exec = ctx->bfs_exec_more = nullptr;
+    ctx->bfs_graph = nullptr;
+    ctx->bfs_start_node = nullptr;
+    ctx->bfs_key = -1;
+    ctx->bfs_state = nullptr;
+    ctx->bfs_ctr = nullptr;
+    ctx->sssp_exec = nullptr;
+    ctx->sssp_key = -1;
+    ctx->sssp_state = nullptr;
+    ctx->ms_exec = nullptr;
+    ctx->ms_key.clear();
+    for (int s = 0; s < WS_NSLOTS; s++) {
+        dev_free(ctx->ws[s], ctx->ws_bytes[s]);
+        ctx->ws[s] = nullptr;
+        ctx->ws_bytes[s] = 0;
+    }
+    for (void *p : ctx->lvpool) dev_free(p, ctx->lv_bytes);
+    ctx->lvpool.clear();
+    dev_free(ctx->vspare_present, ctx->vspare_pb);
+    dev_free(ctx->vspare_values, ctx->vspare_vb);
+    ctx->vspare_present = nullptr;
+    ctx->vspare_values = nullptr;
+    ctx->vspare_pb = ctx->vspare_vb = 0;
+    ctx->vxm_cand = nullptr;
+    ctx->vxm_cand_n = 0;
+}
+
 void flush_deferred(lagr_ctx ctx)
 {
     for (auto &b : ctx->deferred) dev_free(b.first, b.second);

@@ -136,6 +136,7 @@ struct lagr_ctx_s {
     int64_t sssp_key = -1;
     void *sssp_state = nullptr;
     hipStream_t capture_stream = nullptr;
+    int64_t last_bc_levels = 0;       // levels of the deepest batch of the last bc_compute
     // any.secondi vxm: the WS_VXM_CAND buffer whose header (zero) and
     // first vxm_cand_n candidates (all ones) are in their between-call
     // state, and a spare pair of bitmap-vector arrays that the next result
@@ -157,6 +158,12 @@ struct lagr_ctx_s {
 void defer_free(lagr_ctx ctx, void *p, size_t bytes);
 // Free everything deferred (the caller has waited for the stream).
 void flush_deferred(lagr_ctx ctx);
+// Device bytes a context holds between calls (workspace, level pool,
+// spare vector arrays, deferred frees).
+size_t ctx_retained_bytes(const lagr_ctx ctx);
+// Wait for the stream and free all of it (and the captured graphs that
+// point into it); later calls allocate again.
+void ctx_trim(lagr_ctx ctx);
 
 // Returns a device buffer of at least `bytes` for the slot (contents are
 // undefined).  nullptr on allocation failure.

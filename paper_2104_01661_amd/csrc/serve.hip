@@ -136,6 +136,12 @@ struct Grow {
         bytes = p ? want : 0;
         return p;
     }
+    void release()
+    {
+        if (p) dev_free(p, bytes);
+        p = nullptr;
+        bytes = 0;
+    }
     ~Grow()
     {
         if (p) dev_free(p, bytes);
@@ -155,10 +161,19 @@ struct lagr_server_s {
     std::vector<lagr_result> done;
     size_t polled = 0;
     std::unordered_map<int64_t, Kept> kept;
+    int64_t kept_bytes = 0;
     int64_t next_ticket = 0;
     int64_t completed = 0;
-    int64_t in_use = 0, peak = 0;
-    int running = 0;
+    // device memory: per worker, what its context and buffers hold between
+    // batches (measured after each batch) and the estimate of its running
+    // batch (0 when idle); in_use = kept vectors + the sum over workers of
+    // the larger of the two
+    std::vector<int64_t> held, fp_run;
+    std::vector<int64_t> bc_levels;   // per graph: the most BC levels a batch needed
+    int64_t in_use = 0, peak = 0, dev_peak = 0;
+    int running = 0, running_bc = 0;
+    int bc_cap = 1;           // workers that may run betweenness batches at once
+    bool trim_all = false;    // idle workers free their workspaces
     bool stop = false;
     int64_t batches[3] = {0, 0, 0}, queries[3] = {0, 0, 0}, rejected = 0;
     std::vector<std::thread> workers;
@@ -171,29 +186,56 @@ struct lagr_server_s {
 
 namespace {
 
-// Device working set of one batch, in bytes: for a multi-source BFS the
-// unreached masks and two active lists (16n) and two level buffers of lane
-// masks and vertex lists (24n), plus, when results are kept, the 64 x
+// Device working set of one batch, in bytes (an estimate; the admission
+// also counts what each worker measurably holds): for a multi-source BFS
+// the unreached masks and two active lists (16n) and two level buffers of
+// lane masks and vertex lists (24n), plus, when results are kept, the 64 x
 // 16-bit level lanes and one int64 vector per query; for BC the 64-lane
-// sigma and W arrays (2 x 512n), the level buffers (12n per level, counted
-// as 8 levels), the unreached masks and lists, the 8 group sums and the
-// kept vectors; for a count the work partials.
+// sigma and W arrays (2 x 512n), one level buffer of 12n per level (8
+// levels until a batch on the graph has shown its depth), the unreached
+// masks and lists, the 8 group sums, the 64 partial sums of every hub-row
+// chunk, and the kept vectors; for a count the work partials.
 int64_t footprint(const lagr_server_s *S, int kind, int graph, int nq)
 {
-    const int64_t n = S->graphs[graph]->A->nrows;
+    const lagr_graph G = S->graphs[graph];
+    const int64_t n = G->A->nrows;
     const bool keep = S->cfg.keep_vectors != 0;
     if (kind == LAGR_QUERY_TC) return 16 * (n + 1);
     if (kind == LAGR_QUERY_BFS) return 40 * n + (keep ? (128 + 8 * (int64_t)nq) * n : 0);
-    return (1024 + 12 * 8 + 16 + 64) * n + (keep ? 8 * (int64_t)nq * n : 0);
+    const int64_t levels = std::max<int64_t>(8, S->bc_levels[graph]);
+    const int64_t chunks = G->chunks.n > 0 ? G->chunks.n : 0;
+    return (1024 + 12 * levels + 16 + 64) * n + 512 * chunks + (keep ? 8 * (int64_t)nq * n : 0);
 }
 
 struct Worker {
     lagr_server_s *S;
+    int index = 0;
     int device;
     hipStream_t stream = nullptr;
     lagr_ctx ctx = nullptr;
     Grow lev, cent, digest;
+    int64_t retained() const
+    {
+        return (int64_t)(ctx_retained_bytes(ctx) + lev.bytes + cent.bytes + digest.bytes);
+    }
+    void trim()
+    {
+        ctx_trim(ctx);
+        lev.release();
+        cent.release();
+        digest.release();
+    }
 };
+
+// Memory the server would hold with worker w running a batch of estimate
+// fp (under S->mu).
+int64_t projected(const lagr_server_s *S, int w, int64_t fp)
+{
+    int64_t t = S->kept_bytes;
+    for (size_t o = 0; o < S->held.size(); o++)
+        t += (int)o == w ? std::max(S->held[o], fp) : std::max(S->held[o], S->fp_run[o]);
+    return t;
+}
 
 // run one batch; fills res (same order as batch)
 int run_batch(Worker &W, const std::vector<Slot> &batch, std::vector<lagr_result> &res, char *msg)
@@ -269,7 +311,10 @@ int run_batch(Worker &W, const std::vector<Slot> &batch, std::vector<lagr_result
     HIP_TRY(hipStreamSynchronize(W.ctx->stream));
     if (!kept.empty()) {
         std::lock_guard<std::mutex> lk(S->mu);
-        for (auto &kv : kept) S->kept[kv.first] = kv.second;
+        for (auto &kv : kept) {
+            S->kept[kv.first] = kv.second;
+            S->kept_bytes += (int64_t)kv.second.bytes;
+        }
     }
     return LAGR_SUCCESS;
 }
@@ -287,23 +332,55 @@ void worker_main(Worker *W)
             std::unique_lock<std::mutex> lk(S->mu);
             for (;;) {
                 if (S->stop) return;
+                if (S->trim_all && S->fp_run[W->index] == 0 && S->held[W->index] > 0) {
+                    lk.unlock();
+                    W->trim();
+                    lk.lock();
+                    S->held[W->index] = W->retained();
+                    S->in_use = projected(S, -1, 0);
+                    S->cv_work.notify_all();
+                    continue;
+                }
+                if (S->trim_all && S->running == 0) {
+                    bool all = true;
+                    for (int64_t h : S->held) all = all && h == 0;
+                    if (all) S->trim_all = false;
+                }
                 if (S->pending.empty()) {
                     S->cv_work.wait(lk);
                     continue;
                 }
                 const double t = S->now();
-                const Slot &head = S->pending.front();
-                if (head.q.arrival > t) {
-                    S->cv_work.wait_for(lk, std::chrono::duration<double>(head.q.arrival - t));
+                const Slot &front = S->pending.front();
+                if (front.q.arrival > t) {
+                    S->cv_work.wait_for(lk, std::chrono::duration<double>(front.q.arrival - t));
                     continue;
                 }
-                // the oldest visible query and its visible companions
+                // the oldest visible query and its visible companions; while
+                // max_bc_workers workers run betweenness batches, the oldest
+                // visible query of another kind instead (BFS and counts take
+                // a few milliseconds, a betweenness batch on a large graph
+                // tens of them)
+                size_t hi = 0;
+                if (front.q.kind == LAGR_QUERY_BC && S->running_bc >= S->bc_cap) {
+                    hi = S->pending.size();
+                    for (size_t i = 1; i < S->pending.size() && S->pending[i].q.arrival <= t; i++)
+                        if (S->pending[i].q.kind != LAGR_QUERY_BC) {
+                            hi = i;
+                            break;
+                        }
+                    if (hi == S->pending.size()) {
+                        S->cv_work.wait(lk);      // a running batch ends first
+                        continue;
+                    }
+                }
+                const Slot &head = S->pending[hi];
                 const int kind = head.q.kind, graph = head.q.graph;
                 const size_t cap = kind == LAGR_QUERY_BFS ? (size_t)S->cfg.max_bfs_batch
                                  : kind == LAGR_QUERY_BC ? (size_t)S->cfg.max_bc_batch
                                                          : (size_t)1 << 30;
                 std::vector<size_t> take;
-                for (size_t i = 0; i < S->pending.size() && take.size() < cap; i++) {
+                for (size_t i = hi; i < S->pending.size() && take.size() < cap; i++) {
                     const Slot &s = S->pending[i];
                     if (s.q.arrival > t) break;
                     if (s.q.kind == kind && s.q.graph == graph) take.push_back(i);
@@ -327,18 +404,43 @@ void worker_main(Worker *W)
                     S->cv_done.notify_all();
                     continue;
                 }
-                if (S->in_use + fp > S->cfg.budget_bytes && S->running > 0) {
-                    S->cv_work.wait(lk);   // admitted again when memory frees up
-                    continue;
+                // memory: the estimate beside what every worker holds
+                if (projected(S, W->index, fp) > S->cfg.budget_bytes) {
+                    if (S->running > 0) {
+                        S->cv_work.wait(lk);   // admitted again when memory frees up
+                        continue;
+                    }
+                    // nothing runs: the workspaces held from earlier batches
+                    // are freed -- this worker's now, the idle workers' when
+                    // they wake -- and the batch is looked at again; with
+                    // only kept result vectors beside it, it runs
+                    if (S->held[W->index] > 0) {
+                        lk.unlock();
+                        W->trim();
+                        lk.lock();
+                        S->held[W->index] = W->retained();
+                        continue;
+                    }
+                    bool others = false;
+                    for (size_t o = 0; o < S->held.size(); o++) others = others || S->held[o] > 0;
+                    if (others) {
+                        S->trim_all = true;
+                        S->cv_work.notify_all();
+                        S->cv_work.wait(lk);
+                        continue;
+                    }
                 }
                 for (size_t j = take.size(); j-- > 0;) {
                     batch.push_back(S->pending[take[j]]);
                     S->pending.erase(S->pending.begin() + (long)take[j]);
                 }
                 std::reverse(batch.begin(), batch.end());
-                S->in_use += fp;
+                S->fp_run[W->index] = fp;
+                S->in_use = projected(S, -1, 0);
                 S->peak = std::max(S->peak, S->in_use);
+                S->trim_all = false;
                 S->running++;
+                if (kind == LAGR_QUERY_BC) S->running_bc++;
                 S->batches[kind]++;
                 S->queries[kind] += (int64_t)batch.size();
                 break;
@@ -357,6 +459,10 @@ void worker_main(Worker *W)
         }
         const int rc = run_batch(*W, batch, res, msg);
         const double done = S->now();
+        // measured: what this worker now holds, and the device's use
+        const int64_t held = W->retained();
+        size_t dfree = 0, dtotal = 0;
+        const bool have_info = hipMemGetInfo(&dfree, &dtotal) == hipSuccess;
         {
             std::lock_guard<std::mutex> lk(S->mu);
             for (auto &r : res) {
@@ -365,8 +471,14 @@ void worker_main(Worker *W)
                 S->done.push_back(r);
             }
             S->completed += (int64_t)res.size();
-            S->in_use -= fp;
+            S->fp_run[W->index] = 0;
+            S->held[W->index] = held;
+            S->in_use = projected(S, -1, 0);
+            if (batch[0].q.kind == LAGR_QUERY_BC && rc >= 0)
+                S->bc_levels[batch[0].q.graph] = std::max(S->bc_levels[batch[0].q.graph], W->ctx->last_bc_levels);
+            if (have_info) S->dev_peak = std::max(S->dev_peak, (int64_t)(dtotal - dfree));
             S->running--;
+            if (batch[0].q.kind == LAGR_QUERY_BC) S->running_bc--;
         }
         S->cv_done.notify_all();
         S->cv_work.notify_all();
@@ -384,7 +496,8 @@ extern "C" int lagr_server_new(lagr_server *Sp, const lagr_graph *graphs, int32_
     *Sp = nullptr;
     if (ngraphs < 1) return lagr_fail(msg, LAGR_INVALID_VALUE, "the server needs at least one graph");
     if (cfg->workers < 1 || cfg->workers > 16 || cfg->max_bfs_batch < 1 || cfg->max_bfs_batch > 64 ||
-        cfg->max_bc_batch < 1 || cfg->max_bc_batch > 8 || cfg->budget_bytes <= 0)
+        cfg->max_bc_batch < 1 || cfg->max_bc_batch > 8 || cfg->budget_bytes <= 0 || cfg->max_bc_workers < 0 ||
+        cfg->max_bc_workers > cfg->workers)
         return lagr_fail(msg, LAGR_INVALID_VALUE, "server configuration out of range");
     for (int32_t g = 0; g < ngraphs; g++) {
         if (!graphs[g]) return lagr_fail(msg, LAGR_NULL_POINTER, "graph %d is NULL", g);
@@ -403,12 +516,17 @@ extern "C" int lagr_server_new(lagr_server *Sp, const lagr_graph *graphs, int32_
     S->graphs.assign(graphs, graphs + ngraphs);
     S->device = ctx->device;
     S->cfg = *cfg;
+    S->held.assign((size_t)cfg->workers, 0);
+    S->bc_levels.assign((size_t)ngraphs, 0);
+    S->fp_run.assign((size_t)cfg->workers, 0);
+    S->bc_cap = cfg->max_bc_workers > 0 ? cfg->max_bc_workers : std::max(1, cfg->workers - 2);
     S->t0 = std::chrono::steady_clock::now();
     std::vector<Worker *> ws;
     for (int w = 0; w < cfg->workers; w++) {
         Worker *W = new (std::nothrow) Worker();
         if (!W) break;
         W->S = S;
+        W->index = w;
         W->device = ctx->device;
         if (hipStreamCreateWithFlags(&W->stream, hipStreamNonBlocking) != hipSuccess ||
             lagr_ctx_new(&W->ctx, ctx->device, W->stream, msg) < 0) {
@@ -510,6 +628,7 @@ extern "C" int lagr_server_result_vector(lagr_server S, int64_t ticket, lagr_vec
             return lagr_fail(msg, LAGR_INVALID_INDEX, "no kept vector for ticket %lld", (long long)ticket);
         kv = it->second;
         S->kept.erase(it);
+        S->kept_bytes -= (int64_t)kv.bytes;
     }
     lagr_vector x = new (std::nothrow) lagr_vector_s();
     void *p = x ? dev_alloc(kv.bytes) : nullptr;
@@ -548,6 +667,8 @@ extern "C" int lagr_server_stats(const lagr_server S, lagr_server_counts *st, ch
     st->rejected = S->rejected;
     st->peak_bytes = S->peak;
     st->pending = (int64_t)S->pending.size();
+    st->device_peak_bytes = S->dev_peak;
+    st->held_bytes = S->in_use;
     return lagr_ok(msg);
 }
 

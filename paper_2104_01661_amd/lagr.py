@@ -680,7 +680,8 @@ BUDGET_EXCEEDED = -11
 class ServerConfig(ctypes.Structure):
     _fields_ = [("workers", ctypes.c_int32), ("max_bfs_batch", ctypes.c_int32),
                 ("max_bc_batch", ctypes.c_int32), ("keep_vectors", ctypes.c_int32),
-                ("budget_bytes", ctypes.c_int64)]
+                ("budget_bytes", ctypes.c_int64), ("max_bc_workers", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 class Query(ctypes.Structure):
@@ -705,12 +706,14 @@ class Result(ctypes.Structure):
 class ServerCounts(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("batches", ctypes.c_int64 * 3),
                 ("queries", ctypes.c_int64 * 3), ("rejected", ctypes.c_int64),
-                ("peak_bytes", ctypes.c_int64), ("pending", ctypes.c_int64)]
+                ("peak_bytes", ctypes.c_int64), ("pending", ctypes.c_int64),
+                ("device_peak_bytes", ctypes.c_int64), ("held_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {"completed": self.completed, "batches": list(self.batches),
                 "queries": list(self.queries), "rejected": self.rejected,
-                "peak_bytes": self.peak_bytes, "pending": self.pending}
+                "peak_bytes": self.peak_bytes, "pending": self.pending,
+                "device_peak_bytes": self.device_peak_bytes, "held_bytes": self.held_bytes}
 
 
 for _name, _args in {
@@ -743,11 +746,11 @@ class Server:
     outlive it; the binding keeps references to them."""
 
     def __init__(self, ctx: Context, graphs, workers=2, max_bfs_batch=64, max_bc_batch=8,
-                 keep_vectors=False, budget_bytes=64 << 30):
+                 keep_vectors=False, budget_bytes=64 << 30, max_bc_workers=0):
         self._graphs = list(graphs)
         arr = (ctypes.c_void_p * len(graphs))(*[g.h.value for g in graphs])
         cfg = ServerConfig(workers, max_bfs_batch, max_bc_batch, int(bool(keep_vectors)),
-                           int(budget_bytes))
+                           int(budget_bytes), int(max_bc_workers), 0)
         self.h = ctypes.c_void_p()
         call("lagr_server_new", ctypes.byref(self.h), arr, len(graphs), ctypes.byref(cfg), ctx.h)
 

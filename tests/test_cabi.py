@@ -168,7 +168,8 @@ def test_message_cleared_on_success(api, ctx):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("workers", ctypes.c_int32), ("max_bfs_batch", ctypes.c_int32),
                 ("max_bc_batch", ctypes.c_int32), ("keep_vectors", ctypes.c_int32),
-                ("budget_bytes", ctypes.c_int64)]
+                ("budget_bytes", ctypes.c_int64), ("max_bc_workers", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 def test_server_checks(api, ctx):
@@ -179,7 +180,8 @@ def test_server_checks(api, ctx):
     assert api("lagr_server_new", ctypes.byref(S), none, 0, ctypes.byref(good), ctx) == INVALID_VALUE
     for bad in (ServerConfig(0, 64, 8, 0, 1 << 30), ServerConfig(17, 64, 8, 0, 1 << 30),
                 ServerConfig(2, 65, 8, 0, 1 << 30), ServerConfig(2, 64, 9, 0, 1 << 30),
-                ServerConfig(2, 64, 8, 0, 0)):
+                ServerConfig(2, 64, 8, 0, 0), ServerConfig(2, 64, 8, 0, 1 << 30, 3),
+                ServerConfig(2, 64, 8, 0, 1 << 30, -1)):
         assert api("lagr_server_new", ctypes.byref(S), none, 1, ctypes.byref(bad), ctx) == INVALID_VALUE
     A = wrap(api, ctx, BOOL, 5, 5)
     G = ctypes.c_void_p()

@@ -158,6 +158,8 @@ def test_server_arrival_gating_and_budget():
                 assert r.reached == want["reached"] and r.depth == want["depth"]
     st = S.stats()
     assert st["rejected"] == 1 and 0 < st["peak_bytes"] <= budget
+    # the device's measured use and the accounted use after the stream
+    assert st["device_peak_bytes"] > 0 and 0 <= st["held_bytes"]
     S.free()
 
 
