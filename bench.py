@@ -724,7 +724,27 @@ def main():
             del c
         s_batch = float(np.median(bc_runs)) * 1e-3 / bcfg["batches"]
         out["bc"] = {"workload": bcfg["name"], "s_per_batch": round(s_batch, 6),
-                     "batches": bcfg["batches"], "batch_size": bcfg["batch_size"], "dtype": "f64"}
+                     "batches": bcfg["batches"], "batch_size": bcfg["batch_size"], "dtype": "f64",
+                     "backward": "pull on every level (fixed addition order)"}
+        # the backward sweep with push levels where level i has fewer edges
+        # (FP64 atomics: equal to rounding, not bit for bit)
+        ref = L.lagr_bc(BG, bsrc, ctx).values_full(ctx)
+        pp_runs = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            c = L.lagr_bc(BG, bsrc, ctx, L.BC_BACKWARD_PUSH_PULL)
+            e1.record()
+            torch.cuda.synchronize()
+            pp_runs.append(e0.elapsed_time(e1))
+        got = c.values_full(ctx)
+        nz = ref != 0
+        rel = float(((got[nz] - ref[nz]).abs() / ref[nz].abs()).max().item()) if bool(nz.any()) else 0.0
+        assert rel <= 1e-12 and bool((got[~nz] == 0).all()), "push/pull backward differs from pull"
+        out["bc"]["push_pull_backward"] = {"s_per_batch": round(float(np.median(pp_runs)) * 1e-3 / bcfg["batches"], 6),
+                                           "max_rel_diff_vs_pull": rel}
+        del c, got, ref
         # byte model per batch: 12 B per (source, entry of its component)
         # in each of the two sweeps, 48 B per (source, vertex of its
         # component) of path-count, dependency and depth state

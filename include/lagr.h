@@ -474,6 +474,19 @@ int lagr_bfs_batch(int32_t *levels, int64_t *reached, int64_t *level_sum, int64_
  * computed and cached on first use. */
 int lagr_bc(lagr_vector *centrality, const lagr_graph G, const int64_t *sources, int32_t ns,
             lagr_ctx ctx, char *msg);
+/* lagr_bc with a choice for the backward sweep (Section IV-B gives both
+ * forms of its step: pull W = W A^T, push W = W B).  flags 0: pull on every
+ * level, which adds each vertex's terms in a fixed order, so the result is
+ * the same bits on every run (what lagr_bc does).
+ * LAGR_BC_BACKWARD_PUSH_PULL: push where level i has fewer edges than
+ * level i-1 / 4, else pull; LAGR_BC_BACKWARD_PUSH_ONLY: push on every
+ * level.  Push adds with FP64 atomics in no fixed order: the scores then
+ * agree with the pull's to rounding (relative differences of a few ulps
+ * per level), not bit for bit.  Other flags: LAGR_INVALID_VALUE. */
+#define LAGR_BC_BACKWARD_PUSH_PULL 1u
+#define LAGR_BC_BACKWARD_PUSH_ONLY 2u
+int lagr_bc_dir(lagr_vector *centrality, const lagr_graph G, const int64_t *sources, int32_t ns,
+                uint32_t flags, lagr_ctx ctx, char *msg);
 
 /* Single-source shortest paths by delta-stepping (Section IV-D, Algorithm
  * 5) over the min.plus semiring.  G->A must be LAGR_FP64: A(u, v) is the

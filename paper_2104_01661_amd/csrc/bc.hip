@@ -44,6 +44,10 @@ constexpr int64_t BC_CHUNK = GRAPH_LONG_ROW;
 // push a forward level when the frontier's edges are fewer than the active
 // vertices' edges / BC_PUSH_RATIO
 constexpr int64_t BC_PUSH_RATIO = 10;
+// A backward level pushes (BC_BACKWARD_AUTO) when its edges are fewer than
+// the next shallower level's / BC_BACK_PUSH_RATIO (its atomics cost more
+// per edge than the gather's loads).
+constexpr int64_t BC_BACK_PUSH_RATIO = 4;
 // forward levels: the fixed grid, the levels queued before the host first
 // reads the frontier sizes, then per further read, and the ring of level
 // counters (larger than a chunk plus one)
@@ -510,6 +514,106 @@ __global__ __launch_bounds__(256) void k_bc_backward_combine(const int64_t *__re
     }
 }
 
+// ---------------------------------------------- backward sweep, push form
+//
+// The push form of a backward level (W = W B, Section IV-B): every vertex
+// w at depth i scatters its W(w) into the accumulators of its in-neighbours
+// v at depth i-1, lane by lane, with FP64 atomics -- so the order of the
+// additions, and the last bits of the result, vary from run to run (the
+// pull form above adds in a fixed order).  The accumulators are the W
+// slots of the depth-(i-1) lanes, cleared first; a finishing pass then
+// turns each into delta = sigma * sum and W = (1 + delta) / sigma, as the
+// pull form does in one pass.
+
+// W[v][lanes at depth i-1] = 0 for the vertices of level i-1.
+__global__ __launch_bounds__(256) void k_bc_back_clear(const int32_t *__restrict__ tlist, int64_t nt,
+                                                       const uint64_t *__restrict__ at_im1, double *__restrict__ W)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t q = wave; q < nt; q += nw) {
+        const int64_t v = tlist[q];
+        if ((at_im1[v] >> lane) & 1ull) W[v * 64 + lane] = 0.0;
+    }
+}
+
+// Scatter of the in-neighbour range [b, e) of w (lanes fm, this lane's
+// value wl): 64 neighbours loaded at once, then every one with a lane
+// at depth i-1 taken in turn by the whole wave.
+__device__ __forceinline__ void back_push_range(const int32_t *__restrict__ ciT, int64_t b, int64_t e, uint64_t fm,
+                                                double wl, const uint64_t *__restrict__ at_im1, double *W,
+                                                unsigned lane)
+{
+    for (int64_t p0 = b; p0 < e; p0 += 64) {
+        const int64_t p = p0 + lane;
+        int32_t v = 0;
+        uint64_t hm = 0;
+        if (p < e) {
+            v = ciT[p];
+            hm = at_im1[v] & fm;
+        }
+        uint64_t hits = __ballot(hm != 0);
+        while (hits) {
+            const int t = __ffsll((unsigned long long)hits) - 1;
+            hits &= hits - 1;
+            const int32_t vv = __shfl(v, t, 64);
+            const uint64_t mm = shfl64(hm, t);
+            if ((mm >> lane) & 1ull)
+                __hip_atomic_fetch_add(W + (int64_t)vv * 64 + lane, wl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// One wave per vertex of level i (rows of at most BC_LONG in-neighbours),
+// then one wave per chunk of the longer rows.
+__global__ __launch_bounds__(256) void k_bc_back_push(const int64_t *__restrict__ rpT, const int32_t *__restrict__ ciT,
+                                                      const int32_t *__restrict__ slist, int64_t ns,
+                                                      const uint64_t *__restrict__ at_i,
+                                                      const uint64_t *__restrict__ at_im1, double *W, RowChunks chT)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t q = wave; q < ns; q += nw) {
+        const int64_t w = slist[q];
+        const int64_t b = rpT[w], e = rpT[w + 1];
+        if (e - b > BC_LONG) continue;   // its chunks below
+        const uint64_t fm = at_i[w];
+        const double wl = (fm >> lane) & 1ull ? W[w * 64 + lane] : 0.0;
+        back_push_range(ciT, b, e, fm, wl, at_im1, W, lane);
+    }
+    for (int64_t c = wave; c < chT.n; c += nw) {
+        const int64_t w = chT.row[c];
+        const uint64_t fm = at_i[w];
+        if (fm == 0) continue;
+        const double wl = (fm >> lane) & 1ull ? W[w * 64 + lane] : 0.0;
+        back_push_range(ciT, chT.beg[c], chT.end[c], fm, wl, at_im1, W, lane);
+    }
+}
+
+// delta and W of the vertices of level i-1 from their accumulated sums.
+__global__ __launch_bounds__(256) void k_bc_back_finish(const int32_t *__restrict__ tlist, int64_t nt,
+                                                        const uint64_t *__restrict__ at_im1, int gshift,
+                                                        const double *__restrict__ sigma, double *__restrict__ W,
+                                                        double *__restrict__ centrality)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / 64;
+    const unsigned lane = lane_id();
+    for (int64_t q = wave; q < nt; q += nw) {
+        const int64_t v = tlist[q];
+        const uint64_t dm = at_im1[v];
+        double delta = 0.0;
+        if ((dm >> lane) & 1ull) {
+            const double s = sigma[v * 64 + lane];
+            delta = s * W[v * 64 + lane];
+            W[v * 64 + lane] = (1.0 + delta) / s;
+        }
+        group_add(delta, gshift, lane, centrality, v);
+    }
+}
+
 
 // ------------------------------------------------ multi-source BFS lanes
 //
@@ -656,7 +760,7 @@ __global__ void k_ms_sources(const int64_t *__restrict__ src, uint64_t *__restri
 // 8 lanes (cent is n x 8) -- the serving path, where each group is one
 // query.  cent is zeroed here.
 int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nbatches, int gshift,
-               double *cent, char *msg)
+               double *cent, char *msg, int backward)
 {
     ctx->last_bc_levels = 0;
     const lagr_matrix A = G->A;
@@ -746,7 +850,7 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
     unsigned fgrid = BC_FORWARD_GRID;
     if (cblocks > fgrid) fgrid = cblocks;
     if (cblocksT > fgrid) fgrid = cblocksT;
-    std::vector<int64_t> nlev;
+    std::vector<int64_t> nlev, elev;
     for (int b = 0; b < nbatches; b++) {
         const int64_t *src = lane_src + 64 * b;
         uint64_t lanes = 0;
@@ -771,6 +875,7 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
         // chunk of levels at a time (BC_FIRST_LEVELS, then BC_MORE_LEVELS);
         // after each chunk one read of its levels' frontier sizes
         nlev.clear();
+        elev.clear();
         size_t d0 = 0;
         size_t depth = 0;
         bool done = false;
@@ -807,14 +912,35 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
                     break;
                 }
                 nlev.push_back((int64_t)nf);
+                elev.push_back((int64_t)ring[4 * (d % BC_RING) + 1]);
             }
             d0 += chunk;
         }
         depth = nlev.size() - 1;   // the deepest non-empty level
         if ((int64_t)nlev.size() > ctx->last_bc_levels) ctx->last_bc_levels = (int64_t)nlev.size();
-        // backward sweep: targets at depth i-1 gather from depth i
+        // backward sweep: targets at depth i-1 gather from depth i (pull),
+        // or depth i scatters to them (push: by request, on every level or
+        // where level i has fewer edges than level i-1 / BC_BACK_PUSH_RATIO)
         for (size_t i = depth + 1; i >= 2; i--) {
             const int has_deeper = i <= depth ? 1 : 0;
+            const bool push = has_deeper && (backward == BC_BACKWARD_PUSH ||
+                                             (backward == BC_BACKWARD_AUTO &&
+                                              elev[i] * BC_BACK_PUSH_RATIO < elev[i - 1]));
+            if (push) {
+                const int64_t nt = nlev[i - 1], nsrc = nlev[i];
+                hipLaunchKernelGGL(k_bc_back_clear, dim3(wgrid(nt)), dim3(256), 0, ctx->stream, lists(i - 1), nt,
+                                   levels(i - 1), Wv);
+                BC_LAUNCHED();
+                const unsigned pg = chT.n > 0 && cblocksT > wgrid(nsrc) ? cblocksT : wgrid(nsrc);
+                TIMED(ctx, "bc_backward_push",
+                      hipLaunchKernelGGL(k_bc_back_push, dim3(pg), dim3(256), 0, ctx->stream, AT->rowptr, AT->colidx,
+                                         lists(i), nsrc, levels(i), levels(i - 1), Wv, chT));
+                BC_LAUNCHED();
+                hipLaunchKernelGGL(k_bc_back_finish, dim3(wgrid(nt)), dim3(256), 0, ctx->stream, lists(i - 1), nt,
+                                   levels(i - 1), gshift, sigma, Wv, cent);
+                BC_LAUNCHED();
+                continue;
+            }
             const uint64_t *at_i = has_deeper ? levels(i) : levels(i - 1);
             const int64_t nt = nlev[i - 1];
             const int has_chunks = ch.n > 0 && has_deeper ? 1 : 0;
@@ -1097,7 +1223,18 @@ extern "C" int lagr_bfs_batch(int32_t *levels, int64_t *reached, int64_t *level_
 extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const int64_t *sources,
                        int32_t ns, lagr_ctx ctx, char *msg)
 {
+    return lagr_bc_dir(centrality_out, G, sources, ns, 0, ctx, msg);
+}
+
+extern "C" int lagr_bc_dir(lagr_vector *centrality_out, const lagr_graph G, const int64_t *sources,
+                           int32_t ns, uint32_t flags, lagr_ctx ctx, char *msg)
+{
     if (!centrality_out || !G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
+    if (flags & ~(uint32_t)(LAGR_BC_BACKWARD_PUSH_PULL | LAGR_BC_BACKWARD_PUSH_ONLY))
+        return lagr_fail(msg, LAGR_INVALID_VALUE, "unknown flags 0x%x", flags);
+    const int backward = (flags & LAGR_BC_BACKWARD_PUSH_ONLY)   ? BC_BACKWARD_PUSH
+                         : (flags & LAGR_BC_BACKWARD_PUSH_PULL) ? BC_BACKWARD_AUTO
+                                                                : BC_BACKWARD_PULL;
     *centrality_out = nullptr;
     if (ns < 0 || (ns > 0 && !sources)) return lagr_fail(msg, LAGR_INVALID_VALUE, "bad sources");
     const int64_t n = G->A->nrows;
@@ -1122,7 +1259,7 @@ extern "C" int lagr_bc(lagr_vector *centrality_out, const lagr_graph G, const in
         delete cv;
         return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "centrality");
     }
-    const int rc = bc_compute(ctx, G, lane_src.data(), nbatches, 6, (double *)cv->values, msg);
+    const int rc = bc_compute(ctx, G, lane_src.data(), nbatches, 6, (double *)cv->values, msg, backward);
     if (rc < 0) {
         lagr_vector_free(&cv);
         return rc;

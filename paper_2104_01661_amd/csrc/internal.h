@@ -352,9 +352,12 @@ int matrix_transpose(lagr_ctx ctx, const lagr_matrix A, lagr_matrix *out, char *
 int graph_ensure_at(lagr_graph G, lagr_ctx ctx, char *msg);
 // Betweenness of 64-lane batches (lane_src: HOST, 64 per batch, -1 idle)
 // into cent: gshift 6 sums all lanes (n values), gshift 3 sums groups of 8
-// lanes (n x 8 values).
+// lanes (n x 8 values).  backward: BC_BACKWARD_PULL (fixed order: the
+// same bits every run), BC_BACKWARD_AUTO (push or pull per level) or
+// BC_BACKWARD_PUSH (push on every level).
+enum { BC_BACKWARD_PULL = 0, BC_BACKWARD_AUTO = 1, BC_BACKWARD_PUSH = 2 };
 int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nbatches, int gshift,
-               double *cent, char *msg);
+               double *cent, char *msg, int backward = BC_BACKWARD_PULL);
 // Multi-source BFS of up to 64 lanes (lane_src: HOST, 64, -1 idle): per
 // lane reached count, level sum and depth into stats[3][64] (host); with
 // lev (n x 64 uint16), the level of every reached (vertex, lane), 0xFFFF

@@ -110,6 +110,7 @@ _PROTOS = {
     "lagr_tc_adv_noalloc": [_P, _P, _P, _C],
     "lagr_bfs": [_PP, _PP, _P, _I64, _U32, _P, _C],
     "lagr_bc": [_PP, _P, _P, _I32, _P, _C],
+    "lagr_bc_dir": [_PP, _P, _P, _I32, _U32, _P, _C],
     "lagr_bfs_batch": [_P, _P, _P, _P, _P, _P, _I32, _P, _C],
     "lagr_bfs_autotune": [_P, _P, _P, _P, _I32, _P, _C],
     "lagr_tc_autotune": [_P, _P, _P, _C],
@@ -545,11 +546,17 @@ def lagr_tc_autotune(G: Graph, ctx: Context) -> int:
     return h.value
 
 
-def lagr_bc(G: Graph, sources, ctx: Context) -> Vector:
+BC_BACKWARD_PUSH_PULL, BC_BACKWARD_PUSH_ONLY = 1, 2
+
+
+def lagr_bc(G: Graph, sources, ctx: Context, flags: int = 0) -> Vector:
     import numpy as np
     s = np.ascontiguousarray(np.asarray(sources, dtype=np.int64))
     out = ctypes.c_void_p()
-    call("lagr_bc", ctypes.byref(out), G.h, ctypes.c_void_p(s.ctypes.data), s.size, ctx.h)
+    if flags:
+        call("lagr_bc_dir", ctypes.byref(out), G.h, ctypes.c_void_p(s.ctypes.data), s.size, flags, ctx.h)
+    else:
+        call("lagr_bc", ctypes.byref(out), G.h, ctypes.c_void_p(s.ctypes.data), s.size, ctx.h)
     return Vector(out)
 
 

@@ -323,6 +323,32 @@ def test_bc_rmat_against_brandes(scale, ef, seed, ns):
     assert_bc_close(bc_host(G, srcs), oracle.brandes(rp, ci, srcs))
 
 
+@pytest.mark.parametrize("scale,ef,seed,ns", [(10, 16, 1, 100), (12, 8, 102, 64), (14, 16, 103, 64)])
+def test_bc_backward_push_against_brandes(scale, ef, seed, ns):
+    """The backward sweep's push form (W = W B with FP64 atomics), on every
+    level and chosen per level, against Brandes at 1e-12 with exact zeros;
+    an unknown flag is rejected."""
+    L = lagr()
+    c = ctx()
+    n, s, d = rmat(scale, ef, seed)
+    G = device_graph(n, s, d)
+    rp, ci = oracle.build_adjacency(n, s, d)
+    srcs = graphgen.sources(n, s, d, ns, seed)
+    want = oracle.brandes(rp, ci, srcs)
+    for flags in (L.BC_BACKWARD_PUSH_ONLY, L.BC_BACKWARD_PUSH_PULL):
+        assert_bc_close(L.lagr_bc(G, srcs, c, flags).values_full(c).cpu().numpy(), want)
+    with pytest.raises(L.LagrError) as e:
+        L.lagr_bc(G, srcs, c, 4)
+    assert e.value.code == L.INVALID_VALUE
+    # closed forms through the push: a path and a star
+    G, (rp, ci) = graph_from_edges(*Gs.path(30))
+    got = L.lagr_bc(G, list(range(30)), c, L.BC_BACKWARD_PUSH_ONLY).values_full(c).cpu().numpy()
+    assert_bc_close(got, oracle.brandes(rp, ci, np.arange(30)))
+    G, (rp, ci) = graph_from_edges(*Gs.star(3000))
+    got = L.lagr_bc(G, list(range(64)), c, L.BC_BACKWARD_PUSH_ONLY).values_full(c).cpu().numpy()
+    assert_bc_close(got, oracle.brandes(rp, ci, np.arange(64)))
+
+
 def test_bc_duplicate_and_isolated_sources():
     G, (rp, ci) = graph_from_edges(8, [(0, 1), (1, 2), (2, 3), (3, 0), (2, 4)])
     srcs = [2, 2, 7, 0]

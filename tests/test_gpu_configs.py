@@ -107,6 +107,9 @@ def test_bc_4_batches_of_64_sources_of_the_2_18_graph():
     for b in range(cfg["batches"]):
         gb = L.lagr_bc(G, srcs[b * bs:(b + 1) * bs], c).values_full(c).cpu().numpy()
         assert_bc_close(gb, parts[b])
+    # the backward sweep with push levels (chosen per level, and on every level)
+    for flags in (L.BC_BACKWARD_PUSH_PULL, L.BC_BACKWARD_PUSH_ONLY):
+        assert_bc_close(L.lagr_bc(G, srcs, c, flags).values_full(c).cpu().numpy(), want)
 
 
 def test_many_graph_batch_counts_equal_the_stored_oracle_counts():

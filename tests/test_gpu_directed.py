@@ -118,7 +118,11 @@ def test_directed_bc_matches_directed_brandes(scale, ef, seed, ns):
     rp, ci = oracle.build_directed(n, s, d)
     srcs = graphgen.sources(n, s, d, ns, seed)
     got = L.lagr_bc(G, srcs, ctx()).values_full(ctx()).cpu().numpy()
-    assert_bc_close(got, oracle.brandes_directed(rp, ci, srcs))
+    want = oracle.brandes_directed(rp, ci, srcs)
+    assert_bc_close(got, want)
+    # the backward push scatters over in-edges (rows of AT)
+    for flags in (L.BC_BACKWARD_PUSH_ONLY, L.BC_BACKWARD_PUSH_PULL):
+        assert_bc_close(L.lagr_bc(G, srcs, ctx(), flags).values_full(ctx()).cpu().numpy(), want)
 
 
 def test_push_and_pull_levels_agree_on_a_directed_graph():
