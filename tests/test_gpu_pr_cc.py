@@ -4,11 +4,19 @@ the device, through the C ABI, against the oracle.
 PageRank tolerance: an iteration adds, for every vertex, k non-negative
 terms; the device adds a row of at most 32 in-edges in the listing's
 ascending order (the same bits) and longer rows in another fixed order,
-which changes the sum by at most (k - 1) * 2^-53 relative.  With damping
-<= 1 the errors of successive iterations at most add up, so after T
-iterations |gpu - oracle| <= T * kmax * 2^-53 * |oracle| (a factor of 4 is
-kept for the teleport add and the divisions).  The iteration count must
-match exactly.  Components are integer labels: bit-exact."""
+which changes the sum by at most (k - 1) * 2^-53 relative.  With no row
+longer than 32 every iteration gives the oracle's bits from the oracle's
+inputs, so the ranks are equal.  Otherwise let kmax (> 32) be the most
+in-edges of a vertex.  An iteration's new rank is the exact teleport term
+plus damping a times a weighted sum of the old ranks with non-negative
+weights, so a relative error E in every old rank gives at most a * E in
+the new one, plus the two roundings of at most kmax - 1 additions each:
+after T iterations the relative error is at most 4 * kmax * 2^-53 * (1 +
+a + ... + a^(T-1)) (the factor 4 also covers the teleport add and the
+divisions).  The observed largest error is checked
+to lie under that bound and is shown beside it when it does not.  The
+iteration count must match exactly.  Components are integer labels:
+bit-exact."""
 import math
 
 import numpy as np
@@ -44,11 +52,19 @@ def pagerank(G, damping=0.85, tol=1e-4, itermax=100):
     return v.values_full(ctx()).cpu().numpy(), k
 
 
+def rank_bound(iters, rp, ci, damping=0.85):
+    indeg = np.bincount(ci, minlength=rp.size - 1) if ci.size else np.zeros(1, dtype=np.int64)
+    long_rows = indeg[indeg > 32]
+    if long_rows.size == 0:
+        return 0.0
+    return 4.0 * float(long_rows.max()) * 2.0 ** -53 * sum(damping ** t for t in range(max(iters, 1)))
+
+
 def assert_rank_close(got, want, iters, rp, ci):
-    kmax = int(np.bincount(ci, minlength=rp.size - 1).max()) if ci.size else 1
-    rtol = 4.0 * max(iters, 1) * max(kmax, 1) * 2.0 ** -53
+    rtol = rank_bound(iters, rp, ci)
     err = np.abs(got - want) / np.abs(want)
-    assert err.max() <= rtol, f"max rel err {err.max():.3e} > {rtol:.3e}"
+    assert err.max() <= rtol, f"max rel err {err.max():.3e} > bound {rtol:.3e}"
+    return float(err.max()), rtol
 
 
 @pytest.mark.parametrize("scale,ef,seed,directed", [(10, 16, 301, False), (12, 8, 302, False),
@@ -59,7 +75,8 @@ def test_pagerank_matches_the_oracle(scale, ef, seed, directed):
         got, k = pagerank(G, 0.85, tol, itermax)
         want, ko = oracle.pagerank(rp, ci, 0.85, tol, itermax)
         assert k == ko, (tol, k, ko)
-        assert_rank_close(got, want, k, rp, ci)
+        err, bound = assert_rank_close(got, want, k, rp, ci)
+        print(f"\npagerank s{scale}: {k} iterations, largest relative error {err:.3e}, bound {bound:.3e}")
     # a second run gives the same bits
     again, _ = pagerank(G, 0.85, 1e-9, 200)
     assert np.array_equal(again, pagerank(G, 0.85, 1e-9, 200)[0])
@@ -103,7 +120,8 @@ def test_pagerank_full_size_rmat_s20():
     got, k = pagerank(G, 0.85, 1e-4, 20)
     want, ko = oracle.pagerank(rp, ci, 0.85, 1e-4, 20)
     assert k == ko
-    assert_rank_close(got, want, k, rp, ci)
+    err, bound = assert_rank_close(got, want, k, rp, ci)
+    print(f"\npagerank 2^20: {k} iterations, largest relative error {err:.3e}, bound {bound:.3e}")
 
 
 @pytest.mark.parametrize("scale,ef,seed,directed", [(10, 2, 311, False), (14, 2, 312, False),
