@@ -606,6 +606,135 @@ __global__ void k_scatter_dense(const Csr V, uint8_t *__restrict__ present, uint
     }
 }
 
+// ------------------------------- plus.first under a complemented mask
+//
+// C<!s(M), r> = A plus.first B' with A of at most 64 rows (Algorithm 3's
+// forward step F<!s(P), r> = F plus.first A, one source per row): the rows
+// of A become the lanes of a wavefront.  A's entries are scattered into a
+// dense k x 64 table with a lane mask per k, M's into a lane mask per
+// output column; one wavefront per output column j then walks row j of
+// B'^T (ascending k) and each lane adds the terms of its row -- the
+// ascending-k order of the general path, so the same bits.  The result's
+// lane masks are turned into C's rows by per-lane counts over 64-column
+// tiles, one scan, and a write pass.
+
+__device__ __forceinline__ uint64_t lane_shfl64(uint64_t x, int src)
+{
+    const unsigned lo = __shfl((unsigned)(x & 0xffffffffu), src, 64);
+    const unsigned hi = __shfl((unsigned)(x >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// blockIdx.y = row l: table[k][l] = value (when table), mask[k] |= 1 << l
+__global__ void k_lane_scatter(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                               const uint64_t *__restrict__ val, int vk, uint64_t *__restrict__ table,
+                               unsigned long long *__restrict__ mask)
+{
+    const int l = blockIdx.y;
+    const int64_t b = rp[l], e = rp[l + 1];
+    for (int64_t p = b + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < e; p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = ci[p];
+        if (table) table[k * 64 + l] = load_val(val, p, vk);
+        atomicOr(mask + k, 1ull << l);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lane_pull(const int64_t *__restrict__ brp, const int32_t *__restrict__ bci,
+                                                   int64_t nj, uint64_t rows, const uint64_t *__restrict__ table,
+                                                   const unsigned long long *__restrict__ fmask,
+                                                   const unsigned long long *__restrict__ mmask, int fk, int ok,
+                                                   unsigned long long *__restrict__ omask, uint64_t *__restrict__ oval)
+{
+    const unsigned lane = threadIdx.x & 63u;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t j = wave; j < nj; j += nw) {
+        const uint64_t adm = ~(uint64_t)mmask[j] & rows;
+        uint64_t acc = ok == VK_F64 ? f_bits(0.0) : 0ull;
+        bool have = false;
+        if (adm) {
+            const int64_t b = brp[j], e = brp[j + 1];
+            for (int64_t p0 = b; p0 < e; p0 += 64) {
+                const int64_t p = p0 + lane;
+                int32_t k = 0;
+                uint64_t hm = 0;
+                if (p < e) {
+                    k = bci[p];
+                    hm = (uint64_t)fmask[k] & adm;
+                }
+                uint64_t hits = __ballot(hm != 0);
+                while (hits) {
+                    const int t = __ffsll((unsigned long long)hits) - 1;
+                    hits &= hits - 1;
+                    const int32_t kk = __shfl(k, t, 64);
+                    const uint64_t mm = lane_shfl64(hm, t);
+                    if ((mm >> lane) & 1ull) {
+                        const uint64_t x = convert(table[(int64_t)kk * 64 + lane], fk, ok);
+                        acc = have ? (ok == VK_F64 ? f_bits(bits_f(acc) + bits_f(x)) : acc + x) : x;
+                        have = true;
+                    }
+                }
+            }
+        }
+        const uint64_t hv = __ballot(have);
+        if (lane == 0) omask[j] = hv;
+        if (have) oval[j * 64 + lane] = ok == VK_I32 ? wrap32((int64_t)acc) : acc;
+    }
+}
+
+// cnt[l * ntiles + t] = outputs of row l in columns [64 t, 64 t + 64)
+__global__ __launch_bounds__(256) void k_lane_count(const unsigned long long *__restrict__ omask, int64_t nj,
+                                                    int ns, int64_t *__restrict__ cnt)
+{
+    const unsigned lane = threadIdx.x & 63u;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t ntiles = (nj + 63) / 64;
+    for (int64_t t = wave; t < ntiles; t += nw) {
+        const int64_t j = t * 64 + lane;
+        const uint64_t om = j < nj ? (uint64_t)omask[j] : 0ull;
+        int mine = 0;
+        for (int l = 0; l < ns; l++) {
+            const int c = __popcll(__ballot((om >> l) & 1ull));
+            if ((int)lane == l) mine = c;
+        }
+        if ((int)lane < ns) cnt[(int64_t)lane * ntiles + t] = mine;
+    }
+}
+
+__global__ void k_lane_rowptr(const int64_t *__restrict__ pos, int64_t ntiles, int ns, int64_t total,
+                              int64_t *__restrict__ rp)
+{
+    const int l = threadIdx.x;
+    if (l < ns) rp[l] = ntiles > 0 ? pos[(int64_t)l * ntiles] : 0;
+    if (l == ns) rp[ns] = total;
+}
+
+__global__ __launch_bounds__(256) void k_lane_write(const unsigned long long *__restrict__ omask,
+                                                    const uint64_t *__restrict__ oval, int64_t nj, int ns,
+                                                    const int64_t *__restrict__ pos, int32_t *__restrict__ ci,
+                                                    uint64_t *__restrict__ val)
+{
+    const unsigned lane = threadIdx.x & 63u;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t ntiles = (nj + 63) / 64;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (int64_t t = wave; t < ntiles; t += nw) {
+        const int64_t j = t * 64 + lane;
+        const uint64_t om = j < nj ? (uint64_t)omask[j] : 0ull;
+        for (int l = 0; l < ns; l++) {
+            const bool on = (om >> l) & 1ull;
+            const uint64_t b = __ballot(on);
+            if (on) {
+                const int64_t q = pos[(int64_t)l * ntiles + t] + __popcll(b & below);
+                ci[q] = (int32_t)j;
+                val[q] = oval[j * 64 + l];
+            }
+        }
+    }
+}
+
 }  // namespace
 
 // =============================================================== host side
@@ -1066,6 +1195,85 @@ int cached_transpose(lagr_ctx ctx, const lagr_matrix A, Csr *out, char *msg)
     return LAGR_SUCCESS;
 }
 
+// C<!s(M), r> = A plus.first B' on lanes (A has at most 64 rows, no
+// accumulator; C is replaced, or empty).  Returns 1 when computed, 0 when
+// the call has another shape, < 0 on error.
+static int mxm_plus_first_lanes(lagr_ctx ctx, lagr_matrix C, const lagr_matrix M, lagr_binop accum,
+                                lagr_semiring semiring, const lagr_matrix A, const lagr_matrix B, uint32_t desc,
+                                char *msg)
+{
+    const uint32_t sc = LAGR_DESC_STRUCT | LAGR_DESC_COMP;
+    if (semiring != LAGR_PLUS_FIRST || !M || (desc & sc) != sc || (desc & LAGR_DESC_TRAN0) || accum != LAGR_NOOP)
+        return 0;
+    if (A->nrows > 64 || A->nrows < 1 || ctx->device < 0) return 0;
+    if (!(desc & LAGR_DESC_REPLACE) && C->nvals != 0) return 0;
+    const int ns = (int)A->nrows;
+    const int64_t nk = A->ncols, nj = C->ncols;
+    const bool t1 = desc & LAGR_DESC_TRAN1;
+    // rows of B'^T: B itself under TRAN1, else B's cached transpose
+    Csr BT;
+    if (t1) BT = view(B);
+    else TRY(cached_transpose(ctx, B, &BT, msg));
+    Pool pool(ctx);
+    const size_t k1 = (size_t)(nk > 0 ? nk : 1), j1 = (size_t)(nj > 0 ? nj : 1);
+    uint64_t *table = (uint64_t *)pool.get(8 * 64 * k1);
+    unsigned long long *fmask = (unsigned long long *)pool.get(8 * k1);
+    unsigned long long *mmask = (unsigned long long *)pool.get(8 * j1);
+    unsigned long long *omask = (unsigned long long *)pool.get(8 * j1);
+    uint64_t *oval = (uint64_t *)pool.get(8 * 64 * j1);
+    const int64_t ntiles = (nj + 63) / 64;
+    int64_t *pos = (int64_t *)pool.get(8 * ((size_t)ns * (size_t)ntiles + 1));
+    if (!table || !fmask || !mmask || !omask || !oval || !pos) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "lanes");
+    TRY(fill_i64(ctx, (int64_t *)fmask, nk, 0, msg));
+    TRY(fill_i64(ctx, (int64_t *)mmask, nj, 0, msg));
+    const int fk = vkind_of(A->type), ok = vkind_of(C->type);
+    const unsigned sx = grid_for(nk > nj ? nk : nj, 256, 1024);
+    if (A->nvals > 0) {
+        hipLaunchKernelGGL(k_lane_scatter, dim3(sx, (unsigned)ns), dim3(256), 0, ctx->stream, A->rowptr, A->colidx,
+                           (const uint64_t *)A->values, fk, table, fmask);
+        LAUNCH_CHECK();
+    }
+    if (M->nvals > 0) {
+        hipLaunchKernelGGL(k_lane_scatter, dim3(sx, (unsigned)ns), dim3(256), 0, ctx->stream, M->rowptr, M->colidx,
+                           (const uint64_t *)nullptr, fk, (uint64_t *)nullptr, mmask);
+        LAUNCH_CHECK();
+    }
+    const uint64_t rows = ns == 64 ? ~0ull : ((1ull << ns) - 1);
+    if (nj > 0) {
+        hipLaunchKernelGGL(k_lane_pull, dim3(grid_for(nj * 64, 256, 16384)), dim3(256), 0, ctx->stream, BT.rp, BT.ci,
+                           nj, rows, table, fmask, mmask, fk, ok, omask, oval);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_lane_count, dim3(grid_for(ntiles * 64, 256, 16384)), dim3(256), 0, ctx->stream, omask,
+                           nj, ns, pos);
+        LAUNCH_CHECK();
+    }
+    int64_t nnz = 0;
+    TRY(scan_exclusive_i64(ctx, pos, pos, (int64_t)ns * ntiles, &nnz, msg));
+    NewCsr r;
+    r.nnz = nnz;
+    r.rb = 8 * (size_t)(ns + 1);
+    r.cb = 4 * (size_t)(nnz > 0 ? nnz : 1);
+    r.vb = 8 * (size_t)(nnz > 0 ? nnz : 1);
+    r.rp = (int64_t *)dev_alloc(r.rb);
+    r.ci = (int32_t *)dev_alloc(r.cb);
+    r.val = (uint64_t *)dev_alloc(r.vb);
+    if (!r.rp || !r.ci || !r.val) {
+        dev_free(r.rp, r.rb);
+        dev_free(r.ci, r.cb);
+        dev_free(r.val, r.vb);
+        return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "result arrays");
+    }
+    hipLaunchKernelGGL(k_lane_rowptr, dim3(1), dim3(128), 0, ctx->stream, pos, ntiles, ns, nnz, r.rp);
+    LAUNCH_CHECK();
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_lane_write, dim3(grid_for(ntiles * 64, 256, 16384)), dim3(256), 0, ctx->stream, omask,
+                           oval, nj, ns, pos, r.ci, r.val);
+        LAUNCH_CHECK();
+    }
+    install_matrix(ctx, C, r);
+    return 1;
+}
+
 // =================================================================== API
 
 extern "C" int lagr_mxm(lagr_matrix C, const lagr_matrix M, lagr_binop accum, lagr_semiring semiring,
@@ -1088,6 +1296,12 @@ extern "C" int lagr_mxm(lagr_matrix C, const lagr_matrix M, lagr_binop accum, la
         return lagr_fail(msg, LAGR_DOMAIN_MISMATCH, "C's type %d differs from the semiring result type %d",
                          (int)C->type, (int)tt);
     TRY(check_accum(accum, C->type, msg));
+    {
+        // Algorithm 3's forward step on its own kernels
+        const int fast = mxm_plus_first_lanes(ctx, C, M, accum, semiring, A, B, desc, msg);
+        if (fast < 0) return fast;
+        if (fast) return lagr_ok(msg);
+    }
     Pool pool(ctx);
     Csr A2 = view(A), B2 = view(B), B2T;
     // the dot form (a mask, not complemented) reads rows of B'^T, which is

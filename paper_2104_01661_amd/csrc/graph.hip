@@ -400,7 +400,7 @@ __global__ void k_sort_short(const int32_t *__restrict__ rowL, const int64_t *__
 // O(len^2) compares for ranking.  Longer rows set *too_long and stay
 // unsorted.
 constexpr int SORT_MID = 512;
-constexpr int SORT_LONG = 2048;
+constexpr int SORT_LONG = (int)TC_SORT_LONG;
 
 // Rows of L longer than min_len, listed as records rec[2c] = start of the
 // row in L, rec[2c + 1] = (offset of its unsorted copy in P << 16) |
@@ -778,21 +778,28 @@ extern "C" int lagr_property_row_degree(lagr_graph G, lagr_ctx ctx, char *msg)
     const int64_t n = G->A->nrows;
     int64_t *deg = (int64_t *)dev_alloc(sizeof(int64_t) * (n > 0 ? n : 1));
     if (!deg) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "row degree");
-    int64_t mx = 0;
-    int rc = row_degrees(ctx, G->A->rowptr, n, deg, &mx, msg);
+    int64_t mx = 0, nbig = 0;
+    int rc = row_degrees(ctx, G->A->rowptr, n, deg, &mx, msg, TC_SORT_LONG, &nbig);
     if (rc < 0) {
         dev_free(deg, sizeof(int64_t) * (n > 0 ? n : 1));
         return rc;
     }
     G->row_degree = deg;
     G->max_degree = mx;
+    G->deg_over_sort = nbig;
     return lagr_ok(msg);
 }
 
 extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
 {
+    TRY(tc_lower_build(G, ctx, false, msg));
+    return lagr_ok(msg);
+}
+
+int tc_lower_build(lagr_graph G, lagr_ctx ctx, bool defer, char *msg)
+{
     if (!G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
-    if (G->L) return lagr_ok(msg);
+    if (G->L) return LAGR_SUCCESS;
     if (G->kind != LAGR_ADJACENCY_UNDIRECTED)
         return lagr_fail(msg, LAGR_INVALID_VALUE, "triangle counting needs an undirected graph");
     if (G->ndiag < 0 || G->symmetric < 0) TRY(lagr_graph_check(G, ctx, msg));
@@ -814,6 +821,14 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
     int32_t *wrow = (int32_t *)ws_get(ctx, WS_GEN_D, sizeof(int32_t) * (nwin > 0 ? nwin : 1));
     if (!okeys || !inv || !cnt || !wrow) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
     const int dbits = (bits_for((uint64_t)G->max_degree) + 7) / 8 * 8;
+    // the first row of every 64-entry window of A (step 2 below; it reads
+    // A only, so it goes first and runs while the order's small kernels
+    // are queued)
+    if (nnzA > 0) {
+        hipLaunchKernelGGL(k_window_rows, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, A->rowptr, n,
+                           wrow);
+        LAUNCH_CHECK();
+    }
     if (n > 0) {
         hipLaunchKernelGGL(k_order_keys, dim3(grid_for(n, 256, 65536)), dim3(256), 0, ctx->stream,
                            G->row_degree, n, G->max_degree, dbits, okeys);
@@ -831,11 +846,9 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
     if (!P || !cur) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
     TRY(fill_i64(ctx, (int64_t *)cur, n, 0, msg));
     if (nnzA > 0) {
-        // 2. the first row of every 64-entry window of A; the relabelled
-        //    strictly lower part lands unsorted in A's layout, counting its
-        //    row lengths
-        hipLaunchKernelGGL(k_window_rows, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, A->rowptr, n,
-                           wrow);
+        // 2. with the first row of every 64-entry window of A (above), the
+        //    relabelled strictly lower part lands unsorted in A's layout,
+        //    counting its row lengths
         hipLaunchKernelGGL(k_emit_windows, dim3(grid_for(nnzA, 256, 8192)), dim3(256), 0, ctx->stream, wrow,
                            A->colidx, A->rowptr, n, inv, nnzA, cur, P);
         LAUNCH_CHECK();
@@ -907,6 +920,24 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
         }
     }
     G->L = L;
+    // A row of L holds neighbours of its vertex ranked before it, so at most
+    // its degree.  Let C be the number of vertices with more than SORT_LONG
+    // neighbours: a vertex with at most SORT_LONG neighbours has a row of at
+    // most SORT_LONG ids, and one with more is ranked among the first C
+    // (the order is by descending degree), so its row holds at most C - 1
+    // ids.  With C <= SORT_LONG + 1 every row is therefore sorted in LDS,
+    // and with the largest degree below the plan's length field every row
+    // fits it: the plan's status can then wait for the count.
+    if (defer && G->deg_over_sort >= 0 && G->deg_over_sort <= SORT_LONG + 1 && tc_plan_fits(G->max_degree)) {
+        if ((rc = tc_plan_build(ctx, G, rowid, cnt, msg)) >= 0 && (rc = tc_plan_status(ctx, G, status, msg)) >= 0) {
+            G->tc_status_pending = true;
+            return LAGR_SUCCESS;
+        }
+        tc_plan_free(G);
+        G->L = nullptr;
+        G->L_maxrow = -1;
+        goto fail;
+    }
     for (int attempt = 0;; attempt++) {
         if ((rc = tc_plan_build(ctx, G, rowid, cnt, msg)) < 0) break;
         bool unsorted = false;
@@ -940,7 +971,7 @@ extern "C" int lagr_property_tc_lower(lagr_graph G, lagr_ctx ctx, char *msg)
         G->L_maxrow = -1;
         goto fail;
     }
-    return lagr_ok(msg);
+    return LAGR_SUCCESS;
 fail:
     matrix_release_arrays(L);
     delete L;
@@ -1046,9 +1077,11 @@ extern "C" int lagr_graph_delete_properties(lagr_graph G, lagr_ctx ctx, char *ms
     if (G->row_degree) dev_free(G->row_degree, sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     G->row_degree = nullptr;
     G->max_degree = -1;
+    G->deg_over_sort = -1;
     lagr_matrix_free(&G->L);
     tc_plan_free(G);
     G->L_maxrow = -1;
+    G->tc_status_pending = false;
     lagr_matrix_free(&G->AT);
     free_chunks(G->chunks_t);
     // ndiag and the symmetry flag describe A, which a graph never changes:
@@ -1068,6 +1101,7 @@ extern "C" int lagr_graph_set_tuning(lagr_graph G, int64_t tc_hubs, int32_t bfs_
         lagr_matrix_free(&G->L);
         tc_plan_free(G);
         G->L_maxrow = -1;
+        G->tc_status_pending = false;
         G->tc_hubs = tc_hubs;
     }
     if (bfs_alpha > 0) G->bfs_alpha = bfs_alpha;

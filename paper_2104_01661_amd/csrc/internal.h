@@ -211,10 +211,14 @@ struct lagr_graph_s {
     lagr_kind kind = LAGR_ADJACENCY_UNDIRECTED;
     int64_t *row_degree = nullptr;  // cached property, int64[n]
     int64_t max_degree = -1;
+    int64_t deg_over_sort = -1;     // vertices with more neighbours than the LDS row sort takes (with row_degree)
     int64_t ndiag = -1;             // -1 unknown
     int symmetric = -1;             // -1 unknown, 0 no, 1 yes
     lagr_matrix L = nullptr;        // degree-ordered strictly lower part
     int64_t L_maxrow = -1;
+    // the plan's status (its counts, L's longest row) is still on the device,
+    // in the context's counters, to be read with the first count
+    bool tc_status_pending = false;
     // chunks of A's rows longer than GRAPH_LONG_ROW (owned arrays)
     ChunkCache chunks;
     // min-side triangle-count plan over L (built with L, owned)
@@ -247,6 +251,19 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
 // checks that L has nnz entries.
 int tc_plan_settle(lagr_ctx ctx, lagr_graph G, unsigned long long *status, int64_t nnz, bool *unsorted,
                    char *msg);
+// The same checks on a status already read back (st[0..5]).
+int tc_plan_settle_host(lagr_graph G, const unsigned long long *st, int64_t nnz, bool *unsorted, char *msg);
+// Launch the kernel that copies the plan's counts into status[3..5].
+int tc_plan_status(lagr_ctx ctx, lagr_graph G, unsigned long long *status, char *msg);
+// The triangle-count operand, for lagr_tc: with defer, and when the degrees
+// prove every row of L short enough for the row sort, the plan's status is
+// left on the device (G->tc_status_pending) for the count to read with its
+// result.
+int tc_lower_build(lagr_graph G, lagr_ctx ctx, bool defer, char *msg);
+// Rows of L up to this many ids are sorted in LDS.
+constexpr int64_t TC_SORT_LONG = 2048;
+// Whether rows of max_row ids fit the count plan's length field.
+bool tc_plan_fits(int64_t max_row);
 void tc_plan_free(lagr_graph G);
 
 // Rows of A longer than this are cut into chunks of this many entries for
@@ -364,9 +381,10 @@ int bc_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, int nb
 // elsewhere.
 int msbfs_compute(lagr_ctx ctx, const lagr_graph G, const int64_t *lane_src, uint16_t *lev, int64_t *stats,
                   char *msg);
-// Row degrees (rowptr differences) into deg[n] and their maximum (host).
+// Row degrees (rowptr differences) into deg[n], their maximum and the number
+// above `big` (host).
 int row_degrees(lagr_ctx ctx, const int64_t *rowptr, int64_t n, int64_t *deg,
-                int64_t *maxdeg, char *msg);
+                int64_t *maxdeg, char *msg, int64_t big = INT64_MAX, int64_t *nbig = nullptr);
 
 static inline int bits_for(uint64_t x)
 {

@@ -431,27 +431,36 @@ __global__ void k_rowptr_from_keys(const uint64_t *__restrict__ keys, int64_t nn
     }
 }
 
-__global__ void k_degrees(const int64_t *__restrict__ rowptr, int64_t n, int64_t *__restrict__ deg,
-                          unsigned long long *__restrict__ maxdeg)
+// deg[v], the largest degree into m[0] and the number of degrees above
+// big into m[1] (both zero on entry)
+__global__ void k_degrees(const int64_t *__restrict__ rowptr, int64_t n, int64_t *__restrict__ deg, int64_t big,
+                          unsigned long long *__restrict__ m)
 {
     int64_t local = 0;
+    unsigned long long nbig = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t d = rowptr[v + 1] - rowptr[v];
         deg[v] = d;
         local = d > local ? d : local;
+        nbig += d > big ? 1 : 0;
     }
     for (int o = 32; o > 0; o >>= 1) {
         int64_t y = __shfl_xor(local, o, 64);
         local = y > local ? y : local;
+        nbig += __shfl_xor(nbig, o, 64);
     }
     // one atomic per workgroup (atomics on one address serialise)
-    __shared__ unsigned long long wmax;
-    if (threadIdx.x == 0) wmax = 0;
+    __shared__ unsigned long long wmax, wbig;
+    if (threadIdx.x == 0) wmax = wbig = 0;
     __syncthreads();
-    if (lane_id() == 0) atomicMax(&wmax, (unsigned long long)local);
+    if (lane_id() == 0) {
+        atomicMax(&wmax, (unsigned long long)local);
+        if (nbig) atomicAdd(&wbig, nbig);
+    }
     __syncthreads();
-    if (threadIdx.x == 0 && wmax) atomicMax(maxdeg, wmax);
+    if (threadIdx.x == 0 && wmax) atomicMax(m, wmax);
+    if (threadIdx.x == 0 && wbig) atomicAdd(m + 1, wbig);
 }
 }  // namespace
 
@@ -522,18 +531,19 @@ int row_chunks(lagr_ctx ctx, const int64_t *rowptr, int64_t nrows, int64_t min_l
 }
 
 int row_degrees(lagr_ctx ctx, const int64_t *rowptr, int64_t n, int64_t *deg, int64_t *maxdeg,
-                char *msg)
+                char *msg, int64_t big, int64_t *nbig)
 {
     unsigned long long *m = (unsigned long long *)ws_get(ctx, WS_COUNTERS, 64);
     if (!m) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "counters");
-    HIP_TRY(hipMemsetAsync(m, 0, sizeof(unsigned long long), ctx->stream));
+    TRY(fill_i64(ctx, (int64_t *)m, 2, 0, msg));
     if (n > 0) {
         hipLaunchKernelGGL(k_degrees, dim3(grid_for(n, 256, 256)), dim3(256), 0, ctx->stream,
-                           rowptr, n, deg, m);
+                           rowptr, n, deg, big, m);
         LAUNCH_CHECK();
     }
-    unsigned long long h = 0;
-    TRY(read_back(ctx, &h, m, sizeof(h), msg));
-    if (maxdeg) *maxdeg = (int64_t)h;
+    unsigned long long h[2] = {0, 0};
+    TRY(read_back(ctx, h, m, sizeof(h), msg));
+    if (maxdeg) *maxdeg = (int64_t)h[0];
+    if (nbig) *nbig = (int64_t)h[1];
     return LAGR_SUCCESS;
 }

@@ -463,6 +463,7 @@ void tc_plan_free(lagr_graph G)
     dev_free(P->item_row, 4 * (size_t)(P->item_cap > 0 ? P->item_cap : 1));
     dev_free(P->boff, 8 * (size_t)(P->n + 1));
     dev_free(P->bits, 4 * (size_t)(P->bits_cap > 0 ? P->bits_cap : 1));
+    dev_free(P->status, 64);
     delete P;
     G->tcplan = nullptr;
 }
@@ -502,7 +503,8 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
     P->item_row = (int32_t *)dev_alloc(4 * (size_t)P->item_cap);
     P->boff = (int64_t *)dev_alloc(8 * (size_t)(n + 1));
     P->bits = (uint32_t *)dev_alloc(4 * (size_t)P->bits_cap);
-    if (!P->trp || !P->irp || !P->ent || !P->item || !P->item_row || !P->boff || !P->bits)
+    P->status = (unsigned long long *)dev_alloc(64);
+    if (!P->trp || !P->irp || !P->ent || !P->item || !P->item_row || !P->boff || !P->bits || !P->status)
         return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
     int rc;
     if (hipMemcpyAsync(P->trp, regions, 8 * (size_t)(nv + 1), hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
@@ -564,28 +566,48 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
 
 namespace {
 
-// status[3..5] = plan items, entries of L, bitmap words.
+// The plan's status: out[0..1] = in[0..1] (L's longest row, the unsorted
+// flag, from the preparation's kernels), out[3..5] = plan items, entries of
+// L, bitmap words.
 __global__ void k_tc_status(const int64_t *__restrict__ nitems, const int64_t *__restrict__ nnzL,
-                            const int64_t *__restrict__ nbits, unsigned long long *__restrict__ status)
+                            const int64_t *__restrict__ nbits, const unsigned long long *__restrict__ in,
+                            unsigned long long *__restrict__ out)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        status[3] = (unsigned long long)*nitems;
-        status[4] = (unsigned long long)*nnzL;
-        status[5] = (unsigned long long)*nbits;
+        out[0] = in[0];
+        out[1] = in[1];
+        out[2] = 0;
+        out[3] = (unsigned long long)*nitems;
+        out[4] = (unsigned long long)*nnzL;
+        out[5] = (unsigned long long)*nbits;
     }
 }
 
 }  // namespace
 
-int tc_plan_settle(lagr_ctx ctx, lagr_graph G, unsigned long long *status, int64_t nnz, bool *unsorted, char *msg)
+int tc_plan_status(lagr_ctx ctx, lagr_graph G, unsigned long long *status, char *msg)
 {
     TcPlan *P = G->tcplan;
     const int64_t n = G->L->nrows;
     hipLaunchKernelGGL(k_tc_status, dim3(1), dim3(64), 0, ctx->stream, P->irp + 2 * n, G->L->rowptr + n,
-                       P->boff + n, status);
+                       P->boff + n, status, P->status);
     LAUNCH_CHECK();
+    return LAGR_SUCCESS;
+}
+
+bool tc_plan_fits(int64_t max_row) { return max_row < ((int64_t)1 << TC_PLAN_LEN_BITS); }
+
+int tc_plan_settle(lagr_ctx ctx, lagr_graph G, unsigned long long *status, int64_t nnz, bool *unsorted, char *msg)
+{
+    TRY(tc_plan_status(ctx, G, status, msg));
     unsigned long long st[6] = {0, 0, 0, 0, 0, 0};
-    TRY(read_back(ctx, st, status, sizeof(st), msg));
+    TRY(read_back(ctx, st, G->tcplan->status, sizeof(st), msg));
+    return tc_plan_settle_host(G, st, nnz, unsorted, msg);
+}
+
+int tc_plan_settle_host(lagr_graph G, const unsigned long long *st, int64_t nnz, bool *unsorted, char *msg)
+{
+    TcPlan *P = G->tcplan;
     if ((int64_t)st[4] != nnz)
         return lagr_fail(msg, LAGR_INVALID_OBJECT, "L has %lld entries, expected %lld", (long long)st[4],
                          (long long)nnz);
@@ -627,24 +649,30 @@ int tc_masked_dot(lagr_ctx ctx, const TcArgs &a, bool per_entry, unsigned long l
 
 // ------------------------------------------------------------------- TC
 
+// With the plan's status still on the device (G->tc_status_pending), the
+// count reads the item count there, its grid is sized from the item
+// capacity, and the status comes back with the count in one read.
 static int tc_on_lower(lagr_ctx ctx, const lagr_graph G, int64_t *ntri, char *msg)
 {
     const lagr_matrix L = G->L;
-    const TcPlan *P = G->tcplan;
+    TcPlan *P = G->tcplan;
+    const bool pending = G->tc_status_pending;
+    const int64_t items = pending ? P->item_cap : P->nitems;
     // up to eight resident waves per SIMD (the LDS and register budgets of
     // k_tc_split allow it), fewer for a small plan, and a multiple of 8
     // workgroups (one eighth of the items per XCD); the work counters follow
     // the partials
-    const int64_t want = (P->nitems + TC_DYN_ITEMS * TC_WAVES - 1) / (TC_DYN_ITEMS * TC_WAVES);
+    const int64_t want = (items + TC_DYN_ITEMS * TC_WAVES - 1) / (TC_DYN_ITEMS * TC_WAVES);
     const int64_t most = (int64_t)ctx->num_cus * 8;
     const unsigned blocks = (unsigned)(((want < most ? want : most) + TC_DYN_PARTS - 1) / TC_DYN_PARTS * TC_DYN_PARTS);
     const size_t nctr = (size_t)TC_DYN_STRIDE * TC_DYN_PARTS;
     unsigned long long *tot = (unsigned long long *)ws_get(ctx, WS_TC, 8 * ((size_t)blocks + 1 + nctr));
     if (!tot) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc counter");
-    if (P->nitems > 0) {
+    if (items > 0) {
         unsigned long long *ctr = tot + 1 + blocks;
         TRY(fill_i64(ctx, (int64_t *)ctr, (int64_t)nctr, 0, msg));
-        PlanArgs a{P->nitems, L->rowptr, L->colidx, P->ent, P->item, P->item_row, P->bits};
+        PlanArgs a{P->nitems, pending ? P->irp + 2 * L->nrows : nullptr, L->rowptr, L->colidx, P->ent, P->item,
+                   P->item_row, P->bits};
         TIMED(ctx, "tc_split",
               hipLaunchKernelGGL(k_tc_split, dim3(blocks), dim3(TC_BLOCK), 0, ctx->stream, a, tot + 1, ctr));
         LAUNCH_CHECK();
@@ -654,7 +682,20 @@ static int tc_on_lower(lagr_ctx ctx, const lagr_graph G, int64_t *ntri, char *ms
         TRY(fill_i64(ctx, (int64_t *)tot, 1, 0, msg));
     }
     unsigned long long h = 0;
-    TRY(read_back(ctx, &h, tot, sizeof(h), msg));
+    if (!pending) {
+        TRY(read_back(ctx, &h, tot, sizeof(h), msg));
+    } else {
+        // the count and the plan's status in one wait
+        unsigned long long st[6];
+        TRY(stage_to_host(ctx, 0, tot, sizeof(h), false, msg));
+        TRY(stage_to_host(ctx, 8, P->status, sizeof(st), true, msg));
+        memcpy(&h, ctx->pinned, sizeof(h));
+        memcpy(st, (char *)ctx->pinned + 8, sizeof(st));
+        bool unsorted = false;
+        TRY(tc_plan_settle_host(G, st, L->nvals, &unsorted, msg));
+        if (unsorted) return lagr_fail(msg, LAGR_DEVICE_ERROR, "a row of L was left unsorted");
+        G->tc_status_pending = false;
+    }
     *ntri = (int64_t)h;
     return LAGR_SUCCESS;
 }
@@ -755,7 +796,8 @@ extern "C" int lagr_tc_adv_noalloc(int64_t *ntriangles_dev, const lagr_graph G, 
 {
     if (!ntriangles_dev || !G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
     if (ctx->device < 0) return lagr_fail(msg, LAGR_DEVICE_ERROR, "validation-only context");
-    if (!G->L || !G->tcplan) return lagr_fail(msg, LAGR_PROPERTY_MISSING, "tc_lower property not computed");
+    if (!G->L || !G->tcplan || G->tc_status_pending)
+        return lagr_fail(msg, LAGR_PROPERTY_MISSING, "tc_lower property not computed");
     const lagr_matrix L = G->L;
     const TcPlan *P = G->tcplan;
     // the grid of lagr_tc_adv, which must fit the scratch
@@ -774,7 +816,7 @@ extern "C" int lagr_tc_adv_noalloc(int64_t *ntriangles_dev, const lagr_graph G, 
         // the counters keep the previous call's values: clear them (a fill
         // kernel, so the call may also be captured into a graph)
         TRY(fill_i64(ctx, (int64_t *)ctr, (int64_t)TC_DYN_STRIDE * TC_DYN_PARTS, 0, msg));
-        PlanArgs a{P->nitems, L->rowptr, L->colidx, P->ent, P->item, P->item_row, P->bits};
+        PlanArgs a{P->nitems, nullptr, L->rowptr, L->colidx, P->ent, P->item, P->item_row, P->bits};
         hipLaunchKernelGGL(k_tc_split, dim3((unsigned)blocks), dim3(TC_BLOCK), 0, ctx->stream, a, part, ctr);
         LAUNCH_CHECK();
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, ctx->stream, part, blocks,
@@ -795,8 +837,21 @@ extern "C" int lagr_tc(int64_t *ntriangles, lagr_graph G, int method, lagr_ctx c
     if (!ntriangles || !G || !ctx) return lagr_fail(msg, LAGR_NULL_POINTER, "NULL argument");
     if (method < LAGR_TC_DEFAULT || method > LAGR_TC_MXM)
         return lagr_fail(msg, LAGR_INVALID_VALUE, "unknown triangle-count method %d", method);
+    if (method == LAGR_TC_DEFAULT) {
+        // the plan's status read once, with the count
+        TRY(tc_lower_build(G, ctx, true, msg));
+        const int rc = lagr_tc_adv(ntriangles, G, ctx, msg);
+        if (rc < 0 && G->tc_status_pending) {
+            // a failed count leaves no half-known operand behind
+            (void)hipStreamSynchronize(ctx->stream);
+            tc_plan_free(G);
+            lagr_matrix_free(&G->L);
+            G->L_maxrow = -1;
+            G->tc_status_pending = false;
+        }
+        return rc;
+    }
     TRY(lagr_property_tc_lower(G, ctx, msg));
-    if (method == LAGR_TC_DEFAULT) return lagr_tc_adv(ntriangles, G, ctx, msg);
     const lagr_matrix Lm = G->L;
     const uint32_t desc = LAGR_DESC_STRUCT | LAGR_DESC_TRAN1;
     if (method == LAGR_TC_DOT) {

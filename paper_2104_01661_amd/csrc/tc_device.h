@@ -469,11 +469,13 @@ struct TcPlan {
     int64_t nbits = 0;           // bitmap words in use (set once read back)
     int64_t bits_cap = 0;        // allocated bitmap words (nnz(L) bounds them)
     int64_t *boff = nullptr;     // n+1: bitmap word offsets of the rows of L
+    unsigned long long *status = nullptr;   // 8 words: L's longest row, unsorted flag, -, items, nnz(L), words
     uint32_t *bits = nullptr;    // bitmaps of the rows with bitmap pairs
 };
 
 struct PlanArgs {
     int64_t nitems;
+    const int64_t *nitems_dev = nullptr;   // when not null, the item count is read here
     const int64_t *Lrp;
     const int32_t *Lci;
     const uint64_t *ent;
@@ -598,7 +600,7 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
     for (int x = lane; x < TC_BM_WORDS; x += 64) L.bm[x] = 0u;
     wave_sync();
     const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
-    const int64_t N = a.nitems;
+    const int64_t N = a.nitems_dev ? *a.nitems_dev : a.nitems;
     unsigned long long acc = 0;
     int32_t marked = -1, first_id = -1, g = -1;
     int64_t alen = 0;

@@ -290,6 +290,33 @@ def test_int32_domain_against_the_semantics_oracle():
         same(vec_from_dev(w).e, S.vxm(S.Vec(6, {}, "int32"), None, None, "plus.first", u, A).e)
 
 
+@pytest.mark.parametrize("kind", ["fp64", "int64", "bool", "int32"])
+def test_plus_first_under_a_complemented_mask_on_lanes(kind):
+    """C<!s(M), r> = F plus.first B' with F of at most 64 rows (Algorithm
+    3's forward step, one source per row) runs on the lane kernels: against
+    the semantics oracle for 1, 5 and 64 rows, both transposes of B, with
+    replace and into an empty C; a non-empty C without replace keeps the
+    general path and is checked too."""
+    L = lagr()
+    c = ctx()
+    rng = np.random.default_rng(53)
+    for ns, n, t1 in itertools.product((1, 5, 64), (300, 700), (False, True)):
+        F = rand_mat(rng, ns, n, 0.08, kind)
+        B = rand_mat(rng, n, n, 6.0 / n, "bool")
+        M = rand_mat(rng, ns, n, 0.3, "int64")
+        ck = "int64" if kind == "bool" else kind
+        for replace, C0 in ((True, rand_mat(rng, ns, n, 0.1, ck)), (False, S.Mat(ns, n, {}, ck)),
+                            (False, rand_mat(rng, ns, n, 0.1, ck))):
+            want = S.mxm(C0, M, None, "plus.first", F, B, comp=True, struct=True, replace=replace, tran1=t1)
+            Cd = to_dev(C0)
+            L.lagr_mxm(Cd, to_dev(M), 0, L.PLUS_FIRST, to_dev(F), to_dev(B),
+                       desc_bits(True, True, replace, False, t1), c)
+            got = from_dev(Cd).e
+            assert set(got) == set(want.e)
+            for key, v in want.e.items():
+                assert got[key] == v, key           # ascending-k sums on both sides
+
+
 def test_ewise_assign_reduce():
     L = lagr()
     rng = np.random.default_rng(11)
