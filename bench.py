@@ -41,6 +41,9 @@ def parse():
     p.add_argument("--small-reps", type=int, default=200,
                    help="timed calls of the 2^10-vertex triangle-count latency leg")
     p.add_argument("--no-bc", action="store_true")
+    p.add_argument("--tuned", type=str, default="",
+                   help="HUBS,ALPHA,BETA: set the graph's tuning instead of timing the candidates "
+                        "(for profiled runs, which would trace every candidate)")
     p.add_argument("--no-sssp", action="store_true")
     p.add_argument("--no-prcc", action="store_true")
     p.add_argument("--no-batch", action="store_true")
@@ -447,10 +450,16 @@ def main():
     # ------------------------------------------------------------ tuning
     # untimed set-up: the graph's count-plan hub columns and BFS direction
     # thresholds, each picked by timing its candidates on this graph
-    log("autotuning the count plan's hub columns and the BFS thresholds")
     t0 = time.perf_counter()
-    tuned_hubs = L.lagr_tc_autotune(G, ctx)
-    tuned_ab = L.lagr_bfs_autotune(G, sources, ctx)
+    if args.tuned:
+        hubs_s, a_s, b_s = args.tuned.split(",")
+        G.set_tuning(ctx, int(hubs_s), int(a_s), int(b_s))
+        tuned_hubs, tuned_ab = int(hubs_s), (int(a_s), int(b_s))
+        log(f"tuning given: {args.tuned}")
+    else:
+        log("autotuning the count plan's hub columns and the BFS thresholds")
+        tuned_hubs = L.lagr_tc_autotune(G, ctx)
+        tuned_ab = L.lagr_bfs_autotune(G, sources, ctx)
     tune_s = time.perf_counter() - t0
 
     # -------------------------------------------------------------- step
@@ -586,7 +595,7 @@ def main():
                    "undirected_edges": nnzL, "triangles": tc_counts[0],
                    "bfs_sources": len(sources),
                    "tuned": {"tc_hub_columns": tuned_hubs, "bfs_alpha": tuned_ab[0], "bfs_beta": tuned_ab[1],
-                             "seconds": round(tune_s, 3)}},
+                             "seconds": round(tune_s, 3), "by": "given" if args.tuned else "timing"}},
         "tc": {"ms_median": round(tc_med, 4), "edges_per_s_prepared":
                round(nnzL / (float(np.median(prep)) * 1e-3), 1),
                "ms_prepared_median": round(float(np.median(prep)), 4)},
