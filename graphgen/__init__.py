@@ -28,6 +28,7 @@ TAG_SOURCES = 0x737263          # "src"
 TAG_PARAMS = 0x70726d           # "prm"
 TAG_QUERIES = 0x717279          # "qry"
 TAG_WEIGHTS = 0x777467          # "wtg"
+TAG_SPREAD = 0x737072           # "spr"
 
 
 def build(force: bool = False) -> str:
@@ -85,6 +86,22 @@ def rmat_edges(scale: int, edge_factor: int, seed: int,
     dst = np.empty(m, dtype=np.int32)
     _load().gg_rmat_edges(scale, m, seed, a, b, c, src.ctypes.data, dst.ctypes.data)
     return n, src, dst
+
+
+def spread_edges(n: int, scale: int, edge_factor: int, extra: int, seed: int, step: int = 1000003):
+    """Raw draws on n >= 2^scale vertices: R-MAT draws of the given scale
+    placed by v -> v * step mod n (one-to-one: step is a prime that must not
+    divide n), then `extra` uniform draws over all n vertices.  A sparse
+    graph whose non-isolated vertices spread over a wide id range."""
+    if n < (1 << scale) or n % step == 0:
+        raise ValueError("n must be at least 2^scale and not a multiple of step")
+    _, s, d = rmat_edges(scale, edge_factor, seed)
+    s = (s.astype(np.int64) * step) % n
+    d = (d.astype(np.int64) * step) % n
+    u = uniforms(seed, TAG_SPREAD, 2 * extra)
+    us = np.minimum((u[:extra] * n).astype(np.int64), n - 1)
+    ud = np.minimum((u[extra:] * n).astype(np.int64), n - 1)
+    return n, np.concatenate([s, us]).astype(np.int32), np.concatenate([d, ud]).astype(np.int32)
 
 
 def touched_vertices(n: int, src: np.ndarray, dst: np.ndarray) -> np.ndarray:

@@ -226,6 +226,23 @@ def test_tc_with_hub_columns_matches_the_oracle(scale, ef, seed):
     assert got[1] == want and got[0] == oracle.triangle_count(*oracle.build_adjacency(n2, s2, d2))
 
 
+@pytest.mark.parametrize("n,scale,extra", [((1 << 21) + 4321, 15, 3000000), (5 * (1 << 20) + 77, 15, 4000000),
+                                           (13 * (1 << 20) + 5, 14, 4000000)])
+def test_tc_cold_columns_over_wide_id_ranges(n, scale, extra):
+    """Sparse graphs of 2 to 13 million vertices (R-MAT draws spread over
+    the ids plus uniform draws, so most vertices are isolated and the rest
+    have labels far apart): the count plan's regions, cursors and item
+    table span millions of virtual rows, most of them empty; the counts
+    equal the oracle's, and the DOT method's."""
+    L = lagr()
+    n, s, d = graphgen.spread_edges(n, scale, 16, extra, 7)
+    G = device_graph(n, s, d)
+    want = oracle.triangle_count(*oracle.build_adjacency(n, s, d))
+    assert want > 0
+    assert L.lagr_tc(G, ctx()) == want
+    assert L.lagr_tc(G, ctx(), L.TC_DOT) == want
+
+
 # ----------------------------------------------------------------- BFS
 
 def bfs_host(G, s, flags=0):
