@@ -192,11 +192,17 @@ __global__ void k_order_keys(const int64_t *__restrict__ deg, int64_t n, int64_t
         keys[v] = ((uint64_t)v << dbits) | (uint64_t)(maxdeg - deg[v]);
 }
 
-__global__ void k_inverse_perm(const uint64_t *__restrict__ keys, int64_t n, int dbits, int32_t *__restrict__ inv)
+// inv[v] = the new label of vertex v; also clears the emit's row counters
+// (cur, n of them) and the last slot of the lengths to be scanned (cnt_end).
+__global__ void k_inverse_perm(const uint64_t *__restrict__ keys, int64_t n, int dbits, int32_t *__restrict__ inv,
+                               unsigned long long *__restrict__ cur, int64_t *__restrict__ cnt_end)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *cnt_end = 0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x)
+         p += (int64_t)gridDim.x * blockDim.x) {
         inv[keys[p] >> dbits] = (int32_t)p;
+        cur[p] = 0ull;
+    }
 }
 
 // rowA[e] = the row of entry e of L (the sorts and the plan read it).  A
@@ -352,8 +358,10 @@ __global__ void k_emit_windows(const int32_t *__restrict__ wrow, const int32_t *
 // cnt[n + inv[u]] = deg(u) - cur[u], the column lengths of L (A is
 // symmetric without self-loops: u's neighbours above it in the order).
 __global__ void k_lower_lengths(const unsigned long long *__restrict__ cur, const int32_t *__restrict__ inv,
-                                const int64_t *__restrict__ rpA, int64_t n, int64_t *__restrict__ cnt)
+                                const int64_t *__restrict__ rpA, int64_t n, int64_t *__restrict__ cnt,
+                                unsigned long long *__restrict__ status)
 {
+    if (blockIdx.x == 0 && threadIdx.x < 8) status[threadIdx.x] = 0ull;   // the preparation's status words
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
          u += (int64_t)gridDim.x * blockDim.x) {
         const int64_t k = (int64_t)cur[u], r = inv[u];
@@ -568,17 +576,26 @@ __global__ void k_row_keys(const int32_t *__restrict__ rowL, const int64_t *__re
     }
 }
 
-// status[0] = the longest row of L (one atomic per workgroup).
+// L's row offsets, rp_out[0..n] = rp[0..n] (the first n+1 scanned lengths),
+// and status[0] = the longest row of L (one atomic per workgroup); also
+// clears the two long-row list counts (nlong).
 __global__ __launch_bounds__(256) void k_row_max(const int64_t *__restrict__ rp, int64_t n,
-                                                 unsigned long long *__restrict__ status)
+                                                 int64_t *__restrict__ rp_out,
+                                                 unsigned long long *__restrict__ status,
+                                                 unsigned long long *__restrict__ nlong)
 {
     __shared__ unsigned long long m_s;
     if (threadIdx.x == 0) m_s = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 2) nlong[threadIdx.x] = 0ull;
     __syncthreads();
     unsigned long long m = 0;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-        const unsigned long long len = (unsigned long long)(rp[r + 1] - rp[r]);
-        m = len > m ? len : m;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= n; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = rp[r];
+        rp_out[r] = b;
+        if (r < n) {
+            const unsigned long long len = (unsigned long long)(rp[r + 1] - b);
+            m = len > m ? len : m;
+        }
     }
     for (int o = 32; o > 0; o >>= 1) {
         const unsigned long long y = __shfl_xor(m, o, 64);
@@ -835,16 +852,14 @@ int tc_lower_build(lagr_graph G, lagr_ctx ctx, bool defer, char *msg)
         LAUNCH_CHECK();
     }
     TRY(radix_sort_u64(ctx, okeys, n, dbits, msg));
-    TRY(fill_i64(ctx, cnt + 2 * n, 1, 0, msg));
-    if (n > 0) {
-        hipLaunchKernelGGL(k_inverse_perm, dim3(grid_for(n, 256, 65536)), dim3(256), 0, ctx->stream,
-                           okeys, n, dbits, inv);
-        LAUNCH_CHECK();
-    }
     int32_t *P = (int32_t *)ws_get(ctx, WS_GEN_C, sizeof(int32_t) * (nnzA > 0 ? nnzA : 1));
     unsigned long long *cur = (unsigned long long *)ws_get(ctx, WS_GEN_B, sizeof(int64_t) * (n > 0 ? n : 1));
-    if (!P || !cur) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
-    TRY(fill_i64(ctx, (int64_t *)cur, n, 0, msg));
+    unsigned long long *status = (unsigned long long *)ws_get(ctx, WS_COUNTERS, 64);
+    if (!P || !cur || !status) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
+    // (with n = 0 the kernel still clears cnt[2n], the scan's only entry)
+    hipLaunchKernelGGL(k_inverse_perm, dim3(grid_for(n, 256, 65536)), dim3(256), 0, ctx->stream, okeys, n, dbits,
+                       inv, cur, cnt + 2 * n);
+    LAUNCH_CHECK();
     if (nnzA > 0) {
         // 2. with the first row of every 64-entry window of A (above), the
         //    relabelled strictly lower part lands unsorted in A's layout,
@@ -853,11 +868,9 @@ int tc_lower_build(lagr_graph G, lagr_ctx ctx, bool defer, char *msg)
                            A->colidx, A->rowptr, n, inv, nnzA, cur, P);
         LAUNCH_CHECK();
     }
-    if (n > 0) {
-        hipLaunchKernelGGL(k_lower_lengths, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, cur, inv,
-                           A->rowptr, n, cnt);
-        LAUNCH_CHECK();
-    }
+    hipLaunchKernelGGL(k_lower_lengths, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, cur, inv,
+                       A->rowptr, n, cnt, status);
+    LAUNCH_CHECK();
     // A is symmetric without self-loops (checked above), so L holds exactly
     // half of its entries: no host round trip for the count (checked
     // against the scan's total with the status read below).  One scan of
@@ -866,9 +879,6 @@ int tc_lower_build(lagr_graph G, lagr_ctx ctx, bool defer, char *msg)
     if (nnzA % 2 != 0) return lagr_fail(msg, LAGR_INVALID_OBJECT, "odd entry count in a symmetric matrix");
     const int64_t nnz = nnzA / 2;
     TRY(scan_exclusive_i64(ctx, cnt, cnt, 2 * n + 1, nullptr, msg));
-    unsigned long long *status = (unsigned long long *)ws_get(ctx, WS_COUNTERS, 64);
-    if (!status) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
-    TRY(fill_i64(ctx, (int64_t *)status, 8, 0, msg));
     lagr_matrix L = new (std::nothrow) lagr_matrix_s();
     if (!L) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "matrix");
     L->type = LAGR_BOOL;
@@ -890,13 +900,13 @@ int tc_lower_build(lagr_graph G, lagr_ctx ctx, bool defer, char *msg)
     // 3. the rows are sorted from P into L: rows of at most SORT_SHORT ids
     //    by rank, rows up to SORT_LONG by a wave sort in registers and LDS (listed
     //    on the device), longer rows (flagged in status[1]) by a radix sort
-    if (hipMemcpyAsync(L->rowptr, cnt, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, ctx->stream) !=
-        hipSuccess) {
-        rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "relabel copy");
+    hipLaunchKernelGGL(k_row_max, dim3(grid_for(n + 1, 256, 256)), dim3(256), 0, ctx->stream, cnt, n, L->rowptr,
+                       status, nlong);
+    if (hipGetLastError() != hipSuccess) {
+        rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row offsets launch failed");
         goto fail;
     }
     if (n > 0) {
-        hipLaunchKernelGGL(k_row_max, dim3(grid_for(n, 256, 256)), dim3(256), 0, ctx->stream, L->rowptr, n, status);
         // the row of every entry of L (the plan reads it too)
         hipLaunchKernelGGL(k_row_ids, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, L->rowptr, n,
                            rowid);
@@ -907,7 +917,6 @@ int tc_lower_build(lagr_graph G, lagr_ctx ctx, bool defer, char *msg)
             rc = lagr_fail(msg, LAGR_DEVICE_ERROR, "row sort launch failed");
             goto fail;
         }
-        if ((rc = fill_i64(ctx, (int64_t *)nlong, 2, 0, msg)) < 0) goto fail;
         hipLaunchKernelGGL(k_list_long_rows, dim3(grid_for(n, 256, 1024)), dim3(256), 0, ctx->stream, L->rowptr, n,
                            SORT_SHORT, SORT_MID, okeys, dbits, A->rowptr, lrows, lrows + 2 * n, nlong);
         hipLaunchKernelGGL(k_sort_long<SORT_MID>, dim3((unsigned)(ctx->num_cus * 16)), dim3(256), 0, ctx->stream,

@@ -72,24 +72,35 @@ constexpr int PLAN_HOT = 4096;
 constexpr int PLAN_BLOCK = 512;
 constexpr unsigned PLAN_GRID = 1024;
 
-// rowpk[r] = plan_pack(start of row r, length of row r): one gather gives
-// both (the plan kernels gather it for the row and for the column of every
-// entry, at random columns).
-__global__ void k_row_pack(const int64_t *__restrict__ rp, int64_t n, uint64_t *__restrict__ rowpk)
+// The plan's set-up, in one pass over the virtual rows r <= 2n:
+//  * rowpk[r] = plan_pack(start of row r, length of row r) for r < n: one
+//    gather gives both (the plan kernels gather it for the row and for the
+//    column of every entry, at random columns);
+//  * trp = the regions (2n + 1 starts), and cur, the rows' write cursors,
+//    = their first 2n;
+//  * bw (n + 1 bitmap word counts, raised by k_plan_hot) = 0, and the
+//    bitmap row list's count *nbrows = 0;
+//  * hubw[x] (x < nh) = the words of hub row x's bitmap up to its largest
+//    id (0 for an empty row): what a hub pair reading L_x as bits costs.
+__global__ void k_row_pack(const int64_t *__restrict__ rp, const int32_t *__restrict__ Lci, int64_t n,
+                           uint64_t *__restrict__ rowpk, const int64_t *__restrict__ regions,
+                           int64_t *__restrict__ trp, unsigned long long *__restrict__ cur,
+                           int64_t *__restrict__ bw, unsigned long long *__restrict__ nbrows, int64_t nh,
+                           unsigned *__restrict__ hubw)
 {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
-         r += (int64_t)gridDim.x * blockDim.x)
-        rowpk[r] = plan_pack(rp[r], rp[r + 1] - rp[r]);
-}
-
-// hubw[x] (x < nh) = the words of hub row x's bitmap up to its largest id
-// (0 for an empty row): what a hub pair reading L_x as bits costs.
-__global__ void k_hub_words(const int64_t *__restrict__ Lrp, const int32_t *__restrict__ Lci, int64_t nh,
-                            unsigned *__restrict__ hubw)
-{
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < nh; x += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = Lrp[x], e = Lrp[x + 1];
-        hubw[x] = e > b ? (unsigned)((Lci[e - 1] >> 5) + 1) : 0u;
+    const int64_t nv = 2 * n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nbrows = 0ull;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= nv;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = regions[r];
+        trp[r] = g;
+        if (r < nv) cur[r] = (unsigned long long)g;
+        if (r <= n) bw[r] = 0;
+        if (r < n) {
+            const int64_t b = rp[r], e = rp[r + 1];
+            rowpk[r] = plan_pack(b, e - b);
+            if (r < nh) hubw[r] = e > b ? (unsigned)((Lci[e - 1] >> 5) + 1) : 0u;
+        }
     }
 }
 
@@ -195,10 +206,18 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_hot(const int32_t *__restri
 // The rows with bitmap words (off[r + 1] > off[r]), listed in
 // rows[0 .. *count) (count zero on entry): they are contiguous runs of
 // labels, so the build below spreads them over all waves through this list.
-// Each workgroup reserves its range with one atomic.
+// Each workgroup reserves its range with one atomic.  The same launch
+// writes lowpk (see low_pack below) for the rows j < nd.
+__device__ void low_pack(const int64_t *__restrict__ Lrp, const int32_t *__restrict__ Lci,
+                         const int64_t *__restrict__ boff, int64_t nd, int64_t nhub, ulonglong2 *__restrict__ lowpk);
+
 __global__ __launch_bounds__(256) void k_bitmap_list(const int64_t *__restrict__ off, int64_t n,
-                                                     int32_t *__restrict__ rows, unsigned long long *count)
+                                                     int32_t *__restrict__ rows, unsigned long long *count,
+                                                     const int64_t *__restrict__ Lrp,
+                                                     const int32_t *__restrict__ Lci, int64_t nd, int64_t nhub,
+                                                     ulonglong2 *__restrict__ lowpk)
 {
+    low_pack(Lrp, Lci, off, nd, nhub, lowpk);
     __shared__ unsigned sc[256];
     __shared__ unsigned long long base_s;
     const int64_t share = (n + gridDim.x - 1) / gridDim.x;
@@ -263,8 +282,9 @@ __global__ __launch_bounds__(BITMAP_BLOCK) void k_bitmap_build(const int32_t *__
 // (tc_full_words > 0), else 0}.  The fill gathers this 16-byte entry (the
 // table, 0.4 MB at nd = 24,577, stays in L2) instead of rowpk for those
 // columns.
-__global__ void k_low_pack(const int64_t *__restrict__ Lrp, const int32_t *__restrict__ Lci,
-                           const int64_t *__restrict__ boff, int64_t nd, int64_t nhub, ulonglong2 *__restrict__ lowpk)
+// (grid-stride over the launch of k_bitmap_list)
+__device__ void low_pack(const int64_t *__restrict__ Lrp, const int32_t *__restrict__ Lci,
+                         const int64_t *__restrict__ boff, int64_t nd, int64_t nhub, ulonglong2 *__restrict__ lowpk)
 {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nd; j += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = Lrp[j], len = Lrp[j + 1] - b;
@@ -376,10 +396,11 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restr
 }
 
 // irp[r] = items of virtual row r (its entries, cur[r] - trp[r], in runs of
-// up to 64).
+// up to 64), r < nv, and irp[nv] = 0.
 __global__ void k_plan_items(const int64_t *__restrict__ trp, const unsigned long long *__restrict__ cur, int64_t nv,
                              int64_t *__restrict__ irp)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) irp[nv] = 0;   // the scan's last slot
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nv;
          r += (int64_t)gridDim.x * blockDim.x)
         irp[r] = ((int64_t)cur[r] - trp[r] + 63) / 64;
@@ -507,9 +528,6 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
     if (!P->trp || !P->irp || !P->ent || !P->item || !P->item_row || !P->boff || !P->bits || !P->status)
         return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
     int rc;
-    if (hipMemcpyAsync(P->trp, regions, 8 * (size_t)(nv + 1), hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
-        return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan copy"));
-    if ((rc = fill_i64(ctx, P->boff, n + 1, 0, msg)) < 0) return fail(rc);
     // per-workgroup hub reservations, then the hub rows' bitmap words
     unsigned *boff = (unsigned *)ws_get(ctx, WS_GEN_H, sizeof(unsigned) * ((size_t)PLAN_GRID + 1) * PLAN_HOT);
     unsigned *hubw = boff + (size_t)PLAN_GRID * PLAN_HOT;
@@ -518,43 +536,37 @@ int tc_plan_build(lagr_ctx ctx, lagr_graph G, const int32_t *rowid, const int64_
     uint64_t *rowpk = (uint64_t *)ws_get(ctx, WS_GEN_E, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     unsigned long long *cur = (unsigned long long *)ws_get(ctx, WS_TC_WORK, 8 * (size_t)(nv > 0 ? nv : 1));
     if (!boff || !rowpk || !cur) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
+    // rows needing bitmaps are listed below (n ids, then the count)
+    int32_t *brows = (int32_t *)ws_get(ctx, WS_GEN_F, sizeof(int32_t) * (size_t)n + 64);
+    if (!brows) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
+    unsigned long long *nbrows = (unsigned long long *)(brows + n + (n & 1));
+    // regions and cursors, the bitmap words' clear, rowpk and the hub rows'
+    // words (with n = 0: trp[0] and the clears)
+    hipLaunchKernelGGL(k_row_pack, dim3(grid_for(nv + 1, 256, 16384)), dim3(256), 0, ctx->stream, Lm->rowptr,
+                       Lm->colidx, n, rowpk, regions, P->trp, cur, P->boff, nbrows, nnz > 0 ? nhub : 0, hubw);
     if (n > 0) {
-        if (hipMemcpyAsync(cur, regions, 8 * (size_t)nv, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
-            return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan copy"));
-        hipLaunchKernelGGL(k_row_pack, dim3(grid_for(n, 256, 16384)), dim3(256), 0, ctx->stream, Lm->rowptr, n,
-                           rowpk);
         if (nnz > 0) {
-            if (nhub > 0)
-                hipLaunchKernelGGL(k_hub_words, dim3(grid_for(nhub, 256, 64)), dim3(256), 0, ctx->stream,
-                                   Lm->rowptr, Lm->colidx, nhub, hubw);
             hipLaunchKernelGGL(k_plan_hot, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx,
                                nnz, rowpk, hubw, nhub, n, P->trp, cur, boff, (unsigned long long *)P->boff);
         }
         if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
         if ((rc = scan_exclusive_i64(ctx, P->boff, P->boff, n + 1, nullptr, msg)) < 0) return fail(rc);
-        // rows needing bitmaps, listed (n ids, then the count), then one
-        // wave each
-        int32_t *brows = (int32_t *)ws_get(ctx, WS_GEN_F, sizeof(int32_t) * (size_t)n + 64);
-        if (!brows) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
-        unsigned long long *nbrows = (unsigned long long *)(brows + n + (n & 1));
-        if ((rc = fill_i64(ctx, (int64_t *)nbrows, 1, 0, msg)) < 0) return fail(rc);
-        hipLaunchKernelGGL(k_bitmap_list, dim3(grid_for(n, 256, 1024)), dim3(256), 0, ctx->stream, P->boff, n, brows,
-                           nbrows);
-        hipLaunchKernelGGL(k_bitmap_build, dim3((unsigned)(ctx->num_cus * 8)), dim3(BITMAP_BLOCK), 0, ctx->stream,
-                           brows, nbrows, Lm->rowptr, Lm->colidx, P->boff, P->bits);
+        // the rows needing bitmaps, listed, then one wave each; the list's
+        // launch also packs the lowest rows (lowpk)
         const int64_t nd = n < TC_BM_IDS + 1 ? n : TC_BM_IDS + 1;   // rows whose ids all lie below TC_BM_IDS
         ulonglong2 *lowpk = (ulonglong2 *)ws_get(ctx, WS_GEN_G, sizeof(ulonglong2) * (size_t)nd);
         if (!lowpk) return fail(lagr_fail(msg, LAGR_OUT_OF_MEMORY, "count plan"));
-        hipLaunchKernelGGL(k_low_pack, dim3(grid_for(nd, 256, 1024)), dim3(256), 0, ctx->stream, Lm->rowptr,
-                           Lm->colidx, P->boff, nd, nhub, lowpk);
+        hipLaunchKernelGGL(k_bitmap_list, dim3(grid_for(n, 256, 1024)), dim3(256), 0, ctx->stream, P->boff, n, brows,
+                           nbrows, Lm->rowptr, Lm->colidx, nd, nhub, lowpk);
+        hipLaunchKernelGGL(k_bitmap_build, dim3((unsigned)(ctx->num_cus * 8)), dim3(BITMAP_BLOCK), 0, ctx->stream,
+                           brows, nbrows, Lm->rowptr, Lm->colidx, P->boff, P->bits);
         if (nnz > 0)
             hipLaunchKernelGGL(k_plan_fill, dim3(PLAN_GRID), dim3(PLAN_BLOCK), 0, ctx->stream, rowid, Lm->colidx,
                                nnz, rowpk, n, P->trp, boff, P->boff, lowpk, nd, nhub, cur, P->ent);
-        hipLaunchKernelGGL(k_plan_items, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, ctx->stream, P->trp, cur, nv,
-                           P->irp);
-        if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
     }
-    if ((rc = fill_i64(ctx, P->irp + nv, 1, 0, msg)) < 0) return fail(rc);
+    hipLaunchKernelGGL(k_plan_items, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, ctx->stream, P->trp, cur, nv,
+                       P->irp);
+    if (hipGetLastError() != hipSuccess) return fail(lagr_fail(msg, LAGR_DEVICE_ERROR, "plan launch"));
     if ((rc = scan_exclusive_i64(ctx, P->irp, P->irp, nv + 1, nullptr, msg)) < 0) return fail(rc);
     if (n > 0) {
         hipLaunchKernelGGL(k_plan_item_work, dim3(grid_for(P->item_cap, 256, 16384)), dim3(256), 0, ctx->stream,
