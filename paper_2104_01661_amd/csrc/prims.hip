@@ -41,26 +41,66 @@ __device__ int64_t block_exclusive_scan(int64_t x, int64_t *lds_waves, int64_t &
     return excl;
 }
 
-__global__ void k_scan_tiles(const int64_t *__restrict__ in, int64_t *__restrict__ out,
-                             int64_t n, int64_t *__restrict__ tile_sums)
+// A tile is SCAN_ITEMS rows of SCAN_BLOCK consecutive elements: thread t
+// holds element t of each row (v[i] = element i * SCAN_BLOCK + t of the
+// tile), so every load and store of a wave covers 64 consecutive elements.
+// striped_scan sets excl[i] to the sum of the tile's elements before
+// element (i, t) and returns the tile's total: each row is scanned across
+// the block (within waves by shuffles, then over the wave totals in LDS),
+// and row i starts after the totals of rows 0 .. i-1.
+__device__ __forceinline__ int64_t striped_scan(const int64_t (&v)[SCAN_ITEMS], int64_t (&excl)[SCAN_ITEMS],
+                                                int64_t (*wt)[SCAN_ITEMS])
 {
-    __shared__ int64_t lds[SCAN_BLOCK / 64 + 1];
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-    int64_t v[SCAN_ITEMS];
-    int64_t s = 0;
+    const unsigned lane = lane_id();
+    const unsigned wave = threadIdx.x / 64;
+    int64_t incl[SCAN_ITEMS];
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) incl[i] = v[i];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1)
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; i++) {
+            const int64_t y = __shfl_up(incl[i], d, 64);
+            if ((int)lane >= d) incl[i] += y;
+        }
+    if (lane == 63)
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; i++) wt[wave][i] = incl[i];
+    __syncthreads();
+    int64_t row_start = 0;
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; i++) {
-        int64_t idx = base + i;
-        v[i] = idx < n ? in[idx] : 0;
-        s += v[i];
+        int64_t before = 0, row = 0;
+#pragma unroll
+        for (int w = 0; w < SCAN_BLOCK / 64; w++) {
+            const int64_t x = wt[w][i];
+            before += (unsigned)w < wave ? x : 0;
+            row += x;
+        }
+        excl[i] = row_start + before + incl[i] - v[i];
+        row_start += row;
     }
-    int64_t total;
-    int64_t run = block_exclusive_scan(s, lds, total);
+    __syncthreads();   // wt is free again
+    return row_start;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tiles(const int64_t *__restrict__ in,
+                                                           int64_t *__restrict__ out, int64_t n,
+                                                           int64_t *__restrict__ tile_sums)
+{
+    __shared__ int64_t wt[SCAN_BLOCK / 64][SCAN_ITEMS];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x;
+    int64_t v[SCAN_ITEMS], excl[SCAN_ITEMS];
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; i++) {
-        int64_t idx = base + i;
-        if (idx < n) out[idx] = run;
-        run += v[i];
+        const int64_t idx = base + (int64_t)i * SCAN_BLOCK;
+        v[i] = idx < n ? in[idx] : 0;
+    }
+    const int64_t total = striped_scan(v, excl, wt);
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        const int64_t idx = base + (int64_t)i * SCAN_BLOCK;
+        if (idx < n) out[idx] = excl[i];
     }
     if (threadIdx.x == 0 && tile_sums) tile_sums[blockIdx.x] = total;
 }
@@ -71,14 +111,15 @@ __global__ void k_scan_tiles(const int64_t *__restrict__ in, int64_t *__restrict
 // launch and adding them back in a fourth.
 constexpr int64_t SCAN_DIRECT = 4096;
 
-__global__ void k_tile_sums(const int64_t *__restrict__ in, int64_t n, int64_t *__restrict__ tile_sums)
+__global__ __launch_bounds__(SCAN_BLOCK) void k_tile_sums(const int64_t *__restrict__ in, int64_t n,
+                                                          int64_t *__restrict__ tile_sums)
 {
     __shared__ int64_t lds[SCAN_BLOCK / 64 + 1];
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x;
     int64_t s = 0;
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; i++) {
-        const int64_t idx = base + i;
+        const int64_t idx = base + (int64_t)i * SCAN_BLOCK;
         s += idx < n ? in[idx] : 0;
     }
     int64_t total;
@@ -86,30 +127,28 @@ __global__ void k_tile_sums(const int64_t *__restrict__ in, int64_t n, int64_t *
     if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
 }
 
-__global__ void k_scan_tiles_after(const int64_t *__restrict__ in, int64_t *__restrict__ out, int64_t n,
-                                   const int64_t *__restrict__ tile_sums)
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tiles_after(const int64_t *__restrict__ in,
+                                                                 int64_t *__restrict__ out, int64_t n,
+                                                                 const int64_t *__restrict__ tile_sums)
 {
     __shared__ int64_t lds[SCAN_BLOCK / 64 + 1];
+    __shared__ int64_t wt[SCAN_BLOCK / 64][SCAN_ITEMS];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x;
+    int64_t v[SCAN_ITEMS], excl[SCAN_ITEMS];
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; i++) {
+        const int64_t idx = base + (int64_t)i * SCAN_BLOCK;
+        v[i] = idx < n ? in[idx] : 0;
+    }
     int64_t before = 0;
     for (int64_t t = threadIdx.x; t < (int64_t)blockIdx.x; t += SCAN_BLOCK) before += tile_sums[t];
     int64_t prefix;
     block_exclusive_scan(before, lds, prefix);
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-    int64_t v[SCAN_ITEMS];
-    int64_t s = 0;
+    striped_scan(v, excl, wt);
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; i++) {
-        const int64_t idx = base + i;
-        v[i] = idx < n ? in[idx] : 0;
-        s += v[i];
-    }
-    int64_t total;
-    int64_t run = block_exclusive_scan(s, lds, total) + prefix;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; i++) {
-        const int64_t idx = base + i;
-        if (idx < n) out[idx] = run;
-        run += v[i];
+        const int64_t idx = base + (int64_t)i * SCAN_BLOCK;
+        if (idx < n) out[idx] = prefix + excl[i];
     }
 }
 
