@@ -265,8 +265,12 @@ __global__ void k_window_rows(const int64_t *__restrict__ rp, int64_t n, int32_t
 // from the window's first row (wrow) by a binary search, over shuffles, of
 // the next 64 row ends held one per lane (again 64 rows on while a lane's
 // entry lies past them, as after a run of empty rows).  The lanes of one
-// row make one atomic.  (Contiguous runs of windows per wave, each found
-// by a search of the row offsets, took 343 us at 2^20 against 253 us.)
+// row make one atomic.  An entry's id and its label depend on the window
+// alone, and the labels of the 64 candidate rows are read with their ends,
+// so a window waits for three round trips (first row and ids; row ends,
+// row labels and id labels; the atomic) instead of five.  (Contiguous runs
+// of windows per wave, each found by a search of the row offsets, took
+// 343 us at 2^20 against 253 us.)
 constexpr int EMIT_ILP = 2;   // windows per wavefront in flight
 
 __global__ void k_emit_windows(const int32_t *__restrict__ wrow, const int32_t *__restrict__ ci,
@@ -277,9 +281,11 @@ __global__ void k_emit_windows(const int32_t *__restrict__ wrow, const int32_t *
     const int64_t nwin = (nnz + 63) >> 6;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    // rows of the 64 after rc whose end is at or before e; sets u / ub of
-    // a lane whose row is among them
-    auto search = [&](int64_t rc, int64_t end, int64_t start0, int64_t e, bool &need, int32_t &u, int64_t &ub) {
+    // rows of the 64 after rc whose end is at or before e; sets u, ub and
+    // the row's label ivu (from lab, the label of row rc + lane) of a lane
+    // whose row is among them
+    auto search = [&](int64_t rc, int64_t end, int64_t start0, int32_t lab, int64_t e, bool &need, int32_t &u,
+                      int64_t &ub, int32_t &ivu) {
         int cntr = 0;
 #pragma unroll
         for (int sft = 32; sft >= 1; sft >>= 1) {
@@ -289,53 +295,57 @@ __global__ void k_emit_windows(const int32_t *__restrict__ wrow, const int32_t *
         const int64_t last = (int64_t)__shfl((long long)end, 63, 64);
         if (cntr == 63 && last <= e) cntr = 64;
         const int64_t prev = (int64_t)__shfl((long long)end, cntr > 0 ? cntr - 1 : 0, 64);
+        const int32_t lr = __shfl(lab, cntr & 63, 64);
         if (need && cntr < 64) {
             u = (int32_t)(rc + cntr);
             ub = cntr > 0 ? prev : start0;
+            ivu = lr;
             need = false;
         }
     };
     for (int64_t w0 = wave; w0 < nwin; w0 += EMIT_ILP * nwaves) {
         int64_t e[EMIT_ILP], rc[EMIT_ILP], ub[EMIT_ILP], end[EMIT_ILP], start0[EMIT_ILP];
-        int32_t u[EMIT_ILP];
+        int32_t u[EMIT_ILP], cj[EMIT_ILP], iv[EMIT_ILP], ivu[EMIT_ILP], lab[EMIT_ILP];
         bool need[EMIT_ILP];
-        // the windows' first search rounds: their loads are independent
+        // the windows' first rows and the entries' ids: both known from the
+        // window alone
 #pragma unroll
         for (int k = 0; k < EMIT_ILP; k++) {
             const int64_t w = w0 + k * nwaves;
             e[k] = (w << 6) + lane;
             u[k] = -1;
             ub[k] = 0;
+            ivu[k] = 0;
             need[k] = w < nwin && e[k] < nnz;
             rc[k] = w < nwin ? wrow[w] : 0;
+            cj[k] = need[k] ? ci[e[k]] : 0;
         }
+        // then the next 64 row ends and their rows' labels, and the ids'
+        // labels, together
 #pragma unroll
         for (int k = 0; k < EMIT_ILP; k++) {
             const int64_t ri = rc[k] + 1 + lane;
             end[k] = ri <= n ? rpA[ri] : INT64_MAX;   // end of row rc + lane
             start0[k] = rc[k] < n ? rpA[rc[k]] : 0;
+            lab[k] = rc[k] + lane < n ? inv[rc[k] + lane] : 0;
+            iv[k] = need[k] ? inv[cj[k]] : 0;
         }
 #pragma unroll
         for (int k = 0; k < EMIT_ILP; k++) {
-            search(rc[k], end[k], start0[k], e[k], need[k], u[k], ub[k]);
+            search(rc[k], end[k], start0[k], lab[k], e[k], need[k], u[k], ub[k], ivu[k]);
             rc[k] += 64;
             // a window that spans more than 64 rows searches on
             while (__ballot(need[k])) {
                 const int64_t ri = rc[k] + 1 + lane;
                 const int64_t en = ri <= n ? rpA[ri] : INT64_MAX;
-                search(rc[k], en, rpA[rc[k]], e[k], need[k], u[k], ub[k]);
+                const int32_t lb = rc[k] + lane < n ? inv[rc[k] + lane] : 0;
+                search(rc[k], en, rpA[rc[k]], lb, e[k], need[k], u[k], ub[k], ivu[k]);
                 rc[k] += 64;
             }
         }
-        int32_t cj[EMIT_ILP], iv[EMIT_ILP];
         bool take[EMIT_ILP];
 #pragma unroll
-        for (int k = 0; k < EMIT_ILP; k++) cj[k] = u[k] >= 0 ? ci[e[k]] : 0;
-#pragma unroll
-        for (int k = 0; k < EMIT_ILP; k++) {
-            iv[k] = u[k] >= 0 ? inv[cj[k]] : 0;
-            take[k] = u[k] >= 0 && iv[k] < inv[u[k]];
-        }
+        for (int k = 0; k < EMIT_ILP; k++) take[k] = u[k] >= 0 && iv[k] < ivu[k];
         WaveRun wr[EMIT_ILP];
         uint64_t t[EMIT_ILP];
         unsigned long long base[EMIT_ILP];
@@ -822,9 +832,21 @@ int tc_lower_build(lagr_graph G, lagr_ctx ctx, bool defer, char *msg)
     if (G->ndiag < 0 || G->symmetric < 0) TRY(lagr_graph_check(G, ctx, msg));
     if (G->ndiag != 0)
         return lagr_fail(msg, LAGR_INVALID_VALUE, "graph has %lld self-loops", (long long)G->ndiag);
-    TRY(lagr_property_row_degree(G, ctx, msg));
     lagr_matrix A = G->A;
     const int64_t n = A->nrows;
+    const int64_t nnzA = A->nvals;
+    const int64_t nwin = (nnzA + 63) >> 6;
+    int32_t *wrow = (int32_t *)ws_get(ctx, WS_GEN_D, sizeof(int32_t) * (nwin > 0 ? nwin : 1));
+    if (!wrow) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
+    // the first row of every 64-entry window of A (step 2 below): it reads
+    // A only, so it is queued before the degrees, whose largest value the
+    // host reads back (the radix sort's digit count depends on it)
+    if (nnzA > 0) {
+        hipLaunchKernelGGL(k_window_rows, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, A->rowptr, n,
+                           wrow);
+        LAUNCH_CHECK();
+    }
+    TRY(lagr_property_row_degree(G, ctx, msg));
     const int vbits = bits_for((uint64_t)(n > 0 ? n - 1 : 0));
     const uint64_t vmask = vbits ? ((1ull << vbits) - 1) : 0ull;
 
@@ -833,19 +855,8 @@ int tc_lower_build(lagr_graph G, lagr_ctx ctx, bool defer, char *msg)
     uint64_t *okeys = (uint64_t *)ws_get(ctx, WS_PERM, sizeof(uint64_t) * (n > 0 ? n : 1));
     int32_t *inv = (int32_t *)ws_get(ctx, WS_DEG, sizeof(int32_t) * (n > 0 ? n : 1));
     int64_t *cnt = (int64_t *)ws_get(ctx, WS_FLAGS, sizeof(int64_t) * (2 * n + 1));
-    const int64_t nnzA = A->nvals;
-    const int64_t nwin = (nnzA + 63) >> 6;
-    int32_t *wrow = (int32_t *)ws_get(ctx, WS_GEN_D, sizeof(int32_t) * (nwin > 0 ? nwin : 1));
-    if (!okeys || !inv || !cnt || !wrow) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
+    if (!okeys || !inv || !cnt) return lagr_fail(msg, LAGR_OUT_OF_MEMORY, "tc workspace");
     const int dbits = (bits_for((uint64_t)G->max_degree) + 7) / 8 * 8;
-    // the first row of every 64-entry window of A (step 2 below; it reads
-    // A only, so it goes first and runs while the order's small kernels
-    // are queued)
-    if (nnzA > 0) {
-        hipLaunchKernelGGL(k_window_rows, dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, A->rowptr, n,
-                           wrow);
-        LAUNCH_CHECK();
-    }
     if (n > 0) {
         hipLaunchKernelGGL(k_order_keys, dim3(grid_for(n, 256, 65536)), dim3(256), 0, ctx->stream,
                            G->row_degree, n, G->max_degree, dbits, okeys);
