@@ -167,7 +167,8 @@ __device__ __forceinline__ void tc_unmark_kept(TcWaveLds &L, int32_t first_id, i
 // 64u .. 64u+63 of the concatenation, so short segments share units, and
 // INFLIGHT units are loaded before any is probed.  Each lane finds
 // the segment of its id by walking the wave's LDS copy of the segment
-// offsets forward (its ids only increase).
+// offsets forward (its ids only increase), holding its current segment and
+// the next offset in registers so that LDS is read only on a crossing.
 // Unit loads in flight per wave: 7 for the single-graph count, 5 for the
 // many-graph kernel, whose per-graph bookkeeping leaves fewer registers
 // (each the faster of 5, 6 and 7 as measured at 2^20 and on a batch of
@@ -195,7 +196,10 @@ __device__ __forceinline__ unsigned long long tc_stream_flat(TcWaveLds &L, bool 
     if (lane == 0) L.seg_x[cnt] = total;
     wave_sync();
     unsigned long long acc = 0;
-    int t = 0;
+    // the lane's current segment t (start cs in Bci, offset cx) and the next
+    // one's offset nx, kept in registers: LDS is read only on a crossing
+    int t = 0, cx = 0, nx = L.seg_x[1];
+    int64_t cs = L.seg_s[0];
     for (int g0 = 0; g0 < total; g0 += 64 * INFLIGHT) {
         int32_t k[INFLIGHT];
         bool v[INFLIGHT];
@@ -205,8 +209,15 @@ __device__ __forceinline__ unsigned long long tc_stream_flat(TcWaveLds &L, bool 
             v[f] = g < total;
             k[f] = 0;
             if (v[f]) {
-                while (L.seg_x[t + 1] <= g) t++;
-                k[f] = Bci[L.seg_s[t] + (g - L.seg_x[t])];
+                if (nx <= g) {
+                    do {
+                        t++;
+                        cx = nx;
+                        nx = L.seg_x[t + 1];
+                    } while (nx <= g);
+                    cs = L.seg_s[t];
+                }
+                k[f] = Bci[cs + (g - cx)];
             }
         }
 #pragma unroll
