@@ -439,12 +439,13 @@ __global__ void k_plan_item_work(int64_t n, const int64_t *__restrict__ trp,
 // b mod 8), and each XCD has its own L2: the waves of workgroup b take their
 // items from the counter of eighth b mod 8 first (tc_dyn_wave).  Each
 // workgroup writes its count to partial[blockIdx.x].
+template <bool OFF32>
 __global__ __launch_bounds__(TC_BLOCK, 8) void k_tc_split(PlanArgs a, unsigned long long *__restrict__ partial,
                                                           unsigned long long *__restrict__ ctr)
 {
     __shared__ TcWaveLds lds[TC_WAVES];
     unsigned long long acc =
-        tc_dyn_wave<false>(a, lds[threadIdx.x / 64], ctr, (int)(blockIdx.x % TC_DYN_PARTS), TC_DYN_ITEMS);
+        tc_dyn_wave<false, OFF32>(a, lds[threadIdx.x / 64], ctr, (int)(blockIdx.x % TC_DYN_PARTS), TC_DYN_ITEMS);
     __shared__ unsigned long long wsum[TC_WAVES];
     if (lane_id() == 0) wsum[threadIdx.x / 64] = acc;
     __syncthreads();
@@ -661,6 +662,12 @@ int tc_masked_dot(lagr_ctx ctx, const TcArgs &a, bool per_entry, unsigned long l
 
 // ------------------------------------------------------------------- TC
 
+// The count's ids sit below 2^30 entries of L: 32-bit byte offsets reach them.
+static inline bool tc_off32(const lagr_matrix L)
+{
+    return L->nvals < ((int64_t)1 << 30);
+}
+
 // With the plan's status still on the device (G->tc_status_pending), the
 // count reads the item count there, its grid is sized from the item
 // capacity, and the status comes back with the count in one read.
@@ -685,8 +692,12 @@ static int tc_on_lower(lagr_ctx ctx, const lagr_graph G, int64_t *ntri, char *ms
         TRY(fill_i64(ctx, (int64_t *)ctr, (int64_t)nctr, 0, msg));
         PlanArgs a{P->nitems, pending ? P->irp + 2 * L->nrows : nullptr, L->rowptr, L->colidx, P->ent, P->item,
                    P->item_row, P->bits};
-        TIMED(ctx, "tc_split",
-              hipLaunchKernelGGL(k_tc_split, dim3(blocks), dim3(TC_BLOCK), 0, ctx->stream, a, tot + 1, ctr));
+        if (tc_off32(L))
+            TIMED(ctx, "tc_split",
+                  hipLaunchKernelGGL(k_tc_split<true>, dim3(blocks), dim3(TC_BLOCK), 0, ctx->stream, a, tot + 1, ctr));
+        else
+            TIMED(ctx, "tc_split",
+                  hipLaunchKernelGGL(k_tc_split<false>, dim3(blocks), dim3(TC_BLOCK), 0, ctx->stream, a, tot + 1, ctr));
         LAUNCH_CHECK();
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, ctx->stream, tot + 1, (int64_t)blocks, tot);
         LAUNCH_CHECK();
@@ -829,7 +840,10 @@ extern "C" int lagr_tc_adv_noalloc(int64_t *ntriangles_dev, const lagr_graph G, 
         // kernel, so the call may also be captured into a graph)
         TRY(fill_i64(ctx, (int64_t *)ctr, (int64_t)TC_DYN_STRIDE * TC_DYN_PARTS, 0, msg));
         PlanArgs a{P->nitems, nullptr, L->rowptr, L->colidx, P->ent, P->item, P->item_row, P->bits};
-        hipLaunchKernelGGL(k_tc_split, dim3((unsigned)blocks), dim3(TC_BLOCK), 0, ctx->stream, a, part, ctr);
+        if (tc_off32(L))
+            hipLaunchKernelGGL(k_tc_split<true>, dim3((unsigned)blocks), dim3(TC_BLOCK), 0, ctx->stream, a, part, ctr);
+        else
+            hipLaunchKernelGGL(k_tc_split<false>, dim3((unsigned)blocks), dim3(TC_BLOCK), 0, ctx->stream, a, part, ctr);
         LAUNCH_CHECK();
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, ctx->stream, part, blocks,
                            (unsigned long long *)ntriangles_dev);

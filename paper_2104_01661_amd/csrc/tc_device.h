@@ -176,7 +176,9 @@ __device__ __forceinline__ void tc_unmark_kept(TcWaveLds &L, int32_t first_id, i
 constexpr int TC_FLAT_INFLIGHT = 7;
 constexpr int TC_FLAT_INFLIGHT_BATCHED = 5;
 
-template <int INFLIGHT = TC_FLAT_INFLIGHT>
+// With OFF32 every streamed id lies below 2^30 entries of Bci, so an id is
+// loaded at a 32-bit byte offset from Bci (no 64-bit address arithmetic).
+template <int INFLIGHT = TC_FLAT_INFLIGHT, bool OFF32 = false>
 __device__ __forceinline__ unsigned long long tc_stream_flat(TcWaveLds &L, bool use_hash,
                                                              const int32_t *__restrict__ Arow, int64_t alen,
                                                              const int32_t *__restrict__ Bci, int64_t s,
@@ -199,7 +201,8 @@ __device__ __forceinline__ unsigned long long tc_stream_flat(TcWaveLds &L, bool 
     // the lane's current segment t (start cs in Bci, offset cx) and the next
     // one's offset nx, kept in registers: LDS is read only on a crossing
     int t = 0, cx = 0, nx = L.seg_x[1];
-    int64_t cs = L.seg_s[0];
+    int64_t cs = OFF32 ? 0 : L.seg_s[0];
+    uint32_t cs32 = OFF32 ? (uint32_t)L.seg_s[0] : 0u;
     for (int g0 = 0; g0 < total; g0 += 64 * INFLIGHT) {
         int32_t k[INFLIGHT];
         bool v[INFLIGHT];
@@ -215,9 +218,11 @@ __device__ __forceinline__ unsigned long long tc_stream_flat(TcWaveLds &L, bool 
                         cx = nx;
                         nx = L.seg_x[t + 1];
                     } while (nx <= g);
-                    cs = L.seg_s[t];
+                    if (OFF32) cs32 = (uint32_t)L.seg_s[t];
+                    else cs = L.seg_s[t];
                 }
-                k[f] = Bci[cs + (g - cx)];
+                if (OFF32) k[f] = *(const int32_t *)((const char *)Bci + ((cs32 + (uint32_t)(g - cx)) << 2));
+                else k[f] = Bci[cs + (g - cx)];
             }
         }
 #pragma unroll
@@ -603,7 +608,7 @@ constexpr int64_t TC_DYN_ITEMS = 8;
 constexpr int TC_DYN_STRIDE = 16;   // 128 bytes between counters
 constexpr int TC_DYN_PARTS = 8;
 
-template <bool BATCHED>
+template <bool BATCHED, bool OFF32 = false>
 __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsigned long long *ctr, int part,
                                           int64_t grain)
 {
@@ -664,7 +669,7 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
                 use_hash = tc_mark(L, Arow, alen, lane, &first_id);
                 marked = m;
             }
-            acc += tc_stream_flat<BATCHED ? TC_FLAT_INFLIGHT_BATCHED : TC_FLAT_INFLIGHT>(L, use_hash, Arow, alen,
+            acc += tc_stream_flat<BATCHED ? TC_FLAT_INFLIGHT_BATCHED : TC_FLAT_INFLIGHT, OFF32>(L, use_hash, Arow, alen,
                                                                                      a.Lci, s, len, cnt, lane);
             if (any_bitmap) acc += tc_bitmap_lanes(L, a.bits, Arow, alen, cnt, lane);
         }
