@@ -80,11 +80,10 @@ __device__ __forceinline__ uint32_t tc_hash(int32_t x)
     return ((uint32_t)x * 0x9E3779B1u) >> (32 - TC_HS_LOG);
 }
 
-// Is k in A_i?
-__device__ __forceinline__ unsigned tc_member(const TcWaveLds &L, bool use_hash, const int32_t *Arow,
-                                              int64_t alen, int32_t k)
+// Is k in A_i, for k >= TC_BM_IDS (past the LDS bitmap)?
+__device__ __forceinline__ unsigned tc_member_large(const TcWaveLds &L, bool use_hash, const int32_t *Arow,
+                                                    int64_t alen, int32_t k)
 {
-    if (k < TC_BM_IDS) return (L.bm[k >> 5] >> (k & 31)) & 1u;
     if (use_hash) {
         uint32_t h = tc_hash(k);
         while (true) {
@@ -101,6 +100,15 @@ __device__ __forceinline__ unsigned tc_member(const TcWaveLds &L, bool use_hash,
         else hi = mid;
     }
     return (lo < alen && Arow[lo] == k) ? 1u : 0u;
+}
+
+// Is k in A_i?
+__device__ __forceinline__ unsigned tc_member(const TcWaveLds &L, bool use_hash, const int32_t *Arow,
+                                              int64_t alen, int32_t k)
+{
+    // (the bit-field extract reads only the low 5 bits of its offset: k & 31)
+    if (k < TC_BM_IDS) return __builtin_amdgcn_ubfe(L.bm[k >> 5], (unsigned)k, 1u);
+    return tc_member_large(L, use_hash, Arow, alen, k);
 }
 
 // Mark the ids of Arow in the wave's LDS sets; returns whether the hash
@@ -225,9 +233,19 @@ __device__ __forceinline__ unsigned long long tc_stream_flat(TcWaveLds &L, bool 
                 else k[f] = Bci[cs + (g - cx)];
             }
         }
+        // the bitmap probes of all units together (no branch: an id past
+        // the bitmap, or a lane past the end, reads word 0 and masks it
+        // out), then the ids past the bitmap, in the units that hold any
+        uint32_t wd[INFLIGHT];
+#pragma unroll
+        for (int f = 0; f < INFLIGHT; f++) wd[f] = L.bm[(k[f] < TC_BM_IDS ? k[f] : 0) >> 5];
 #pragma unroll
         for (int f = 0; f < INFLIGHT; f++)
-            acc += v[f] ? tc_member(L, use_hash, Arow, alen, k[f]) : 0u;
+            acc += (v[f] && k[f] < TC_BM_IDS) ? __builtin_amdgcn_ubfe(wd[f], (unsigned)k[f], 1u) : 0u;
+#pragma unroll
+        for (int f = 0; f < INFLIGHT; f++)
+            if (__ballot(v[f] && k[f] >= TC_BM_IDS))
+                acc += (v[f] && k[f] >= TC_BM_IDS) ? tc_member_large(L, use_hash, Arow, alen, k[f]) : 0u;
     }
     wave_sync();
     return acc;
