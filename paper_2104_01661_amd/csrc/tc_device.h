@@ -93,13 +93,13 @@ __device__ __forceinline__ unsigned tc_member_large(const TcWaveLds &L, bool use
             h = (h + 1) & (TC_HS_SLOTS - 1);
         }
     }
-    int64_t lo = 0, hi = alen;
+    int lo = 0, hi = (int)alen;   // (a row holds fewer than 2^31 ids)
     while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
+        const int mid = (int)(((unsigned)lo + (unsigned)hi) >> 1);
         if (Arow[mid] < k) lo = mid + 1;
         else hi = mid;
     }
-    return (lo < alen && Arow[lo] == k) ? 1u : 0u;
+    return (lo < (int)alen && Arow[lo] == k) ? 1u : 0u;
 }
 
 // Is k in A_i?
@@ -118,20 +118,22 @@ __device__ __forceinline__ unsigned tc_member(const TcWaveLds &L, bool use_hash,
 __device__ __forceinline__ bool tc_mark(TcWaveLds &L, const int32_t *__restrict__ Arow, int64_t alen,
                                         unsigned lane, int32_t *first_id = nullptr)
 {
-    int64_t nlarge = 0;
-    if (first_id) *first_id = (int64_t)lane < alen ? Arow[lane] : -1;
+    // (a row of L holds fewer than 2^31 ids: 32-bit positions)
+    const int n = (int)alen;
+    int nlarge = 0;
+    if (first_id) *first_id = (int)lane < n ? Arow[lane] : -1;
 #pragma unroll 4
-    for (int64_t t0 = 0; t0 < alen; t0 += 64) {
-        const int64_t t = t0 + lane;
-        const int32_t x = t < alen ? Arow[t] : 0;
-        if (t < alen && x < TC_BM_IDS) atomicOr(&L.bm[x >> 5], 1u << (x & 31));
-        nlarge += __popcll(__ballot(t < alen && x >= TC_BM_IDS));
+    for (int t0 = 0; t0 < n; t0 += 64) {
+        const int t = t0 + (int)lane;
+        const int32_t x = t < n ? Arow[t] : 0;
+        if (t < n && x < TC_BM_IDS) atomicOr(&L.bm[x >> 5], 1u << (x & 31));
+        nlarge += __popcll(__ballot(t < n && x >= TC_BM_IDS));
     }
     const bool use_hash = nlarge > 0 && nlarge <= TC_HS_MAX;
     if (use_hash) {
         for (int s = lane; s < TC_HS_SLOTS; s += 64) L.hs[s] = -1;
         wave_sync();
-        for (int64_t t = lane; t < alen; t += 64) {
+        for (int t = lane; t < n; t += 64) {
             const int32_t x = Arow[t];
             if (x >= TC_BM_IDS) {
                 uint32_t h = tc_hash(x);
