@@ -450,7 +450,9 @@ struct WaveRun {
 __device__ __forceinline__ WaveRun wave_run(int32_t key)
 {
     const unsigned lane = lane_id();
-    const int32_t prev = __shfl_up(key, 1, 64);
+    // the previous lane's key by a DPP wave shift (wave_shr:1; lane 0 has
+    // none and is a head anyway)
+    const int32_t prev = __builtin_amdgcn_update_dpp(0, key, 0x138, 0xf, 0xf, false);
     const uint64_t H = __ballot(lane == 0 || prev != key);
     const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
     WaveRun w;

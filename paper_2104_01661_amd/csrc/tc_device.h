@@ -297,13 +297,8 @@ __device__ unsigned long long tc_row(const TcArgs &a, int64_t i, TcWaveLds &L,
         }
         // units of 64 ids: exclusive and inclusive unit offsets per segment
         const int nch = (len + 63) >> 6;
-        int incl = nch;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int y = __shfl_up(incl, d, 64);
-            if ((int)lane >= d) incl += y;
-        }
-        const int U = __shfl(incl, 63, 64);
+        const int incl = wave_incl_sum(nch);
+        const int U = __builtin_amdgcn_readlane(incl, 63);
         const int excl = incl - nch;
         unsigned segcnt = 0;
         int t = 0;       // segment of the current unit (wave-uniform)
@@ -600,13 +595,8 @@ __device__ __forceinline__ unsigned long long tc_bitmap_lanes(TcWaveLds &L, cons
     } else {
         // exclusive word offsets of the flagged lanes, in lane order
         const int mine = flag ? nwl : 0;
-        int incl = mine;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int y = __shfl_up(incl, d, 64);
-            if ((int)lane >= d) incl += y;
-        }
-        const int total = __shfl(incl, 63, 64);
+        const int incl = wave_incl_sum(mine);
+        const int total = __builtin_amdgcn_readlane(incl, 63);
         if (flag) {
             L.seg_s[r] = off;
             L.seg_x[r] = incl - mine;
