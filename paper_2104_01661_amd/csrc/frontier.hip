@@ -116,12 +116,8 @@ __global__ __launch_bounds__(256) void k_vxm_push(const VxmArgs a)
             }
         }
         // inclusive prefix of len over the wave
-        int32_t inc = len;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int32_t y = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += y;
-        }
-        const int32_t total = __shfl(inc, 63, 64);
+        const int32_t inc = wave_incl_sum(len);
+        const int32_t total = __builtin_amdgcn_readlane(inc, 63);
         if (total == 0) continue;
         s_off[wib][lane + 1] = inc;
         if (lane == 0) s_off[wib][0] = 0;

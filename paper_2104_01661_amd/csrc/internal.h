@@ -442,6 +442,23 @@ __device__ __forceinline__ void for_marked_chunks(const RowChunks &ch, const uin
 // from many lanes on one address are serialised).  run: the lanes of the
 // run; before: those of them below this lane.  Every lane of the wave must
 // call it.
+// Inclusive sum over the 64 lanes by DPP moves (no LDS round trip):
+// Hillis-Steele steps of 1, 2, 4 and 8 lanes within each 16-lane row
+// (row_shr; a lane with no source lane adds 0), then the end of row 0 into
+// rows 1 and 3 and the end of row 1 (now rows 0-1) into rows 2 and 3
+// (row_bcast:15 / :31 with row masks 0xa / 0xc).  Every lane must be active.
+__device__ __forceinline__ int wave_incl_sum(int x)
+{
+    int t = x;
+    t += __builtin_amdgcn_update_dpp(0, t, 0x111, 0xf, 0xf, false);   // row_shr:1
+    t += __builtin_amdgcn_update_dpp(0, t, 0x112, 0xf, 0xf, false);   // row_shr:2
+    t += __builtin_amdgcn_update_dpp(0, t, 0x114, 0xf, 0xf, false);   // row_shr:4
+    t += __builtin_amdgcn_update_dpp(0, t, 0x118, 0xf, 0xf, false);   // row_shr:8
+    t += __builtin_amdgcn_update_dpp(0, t, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    t += __builtin_amdgcn_update_dpp(0, t, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return t;
+}
+
 struct WaveRun {
     unsigned head;
     uint64_t run, before;

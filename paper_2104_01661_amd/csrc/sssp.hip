@@ -214,12 +214,8 @@ __device__ __forceinline__ unsigned long long relax_group(const SsspDev &d, cons
             du = as_f64(d.dist[u]);
         }
     }
-    int incl = len;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(incl, o, 64);
-        if ((int)lane >= o) incl += y;
-    }
-    const int total = __shfl(incl, 63, 64);
+    const int incl = wave_incl_sum(len);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
     const int64_t start = b - (incl - len);   // row start minus the row's offset in the sequence
     unsigned long long far = SSSP_INF;
     for (int t0 = 0; t0 < total; t0 += 64 * RELAX_BATCH) {
