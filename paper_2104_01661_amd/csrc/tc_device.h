@@ -205,7 +205,10 @@ __device__ __forceinline__ unsigned long long tc_stream_flat(TcWaveLds &L, bool 
     unsigned long long acc = 0;
     // the lane's current segment t (start cs in Bci, offset cx) and the next
     // one's offset nx, kept in registers: LDS is read only on a crossing
-    int t = 0, cx = 0, nx = L.seg_x[1];
+    // (px points at seg_x[t + 1]: a crossing step is one pointer increment
+    // and one LDS read; t and cx are recovered after the walk)
+    const int32_t *px = &L.seg_x[1];
+    int cx = 0, nx = *px;
     int64_t cs = OFF32 ? 0 : L.seg_s[0];
     uint32_t cs32 = OFF32 ? (uint32_t)L.seg_s[0] : 0u;
     for (int g0 = 0; g0 < total; g0 += 64 * INFLIGHT) {
@@ -219,10 +222,11 @@ __device__ __forceinline__ unsigned long long tc_stream_flat(TcWaveLds &L, bool 
             if (v[f]) {
                 if (nx <= g) {
                     do {
-                        t++;
-                        cx = nx;
-                        nx = L.seg_x[t + 1];
+                        ++px;
+                        nx = *px;
                     } while (nx <= g);
+                    const int t = (int)(px - &L.seg_x[1]);
+                    cx = px[-1];
                     if (OFF32) cs32 = (uint32_t)L.seg_s[t];
                     else cs = L.seg_s[t];
                 }
