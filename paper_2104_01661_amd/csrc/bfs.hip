@@ -105,14 +105,9 @@ __device__ void bfs_level_state(const BfsLevel *__restrict__ psp, const unsigned
     // lanes 0..15: vertex counts; 16..31: degree sums; 32..47: hub counts
     const unsigned long long v = lane < BFS_NCTR ? ctr[(size_t)lane * BFS_CTR_STRIDE] : 0ull;
     const BfsLevel ps = *psp;
-    unsigned long long cnt = lane < BFS_SPREAD ? v : 0ull;
-    unsigned long long deg = (lane >= BFS_SPREAD && lane < 2 * BFS_SPREAD) ? v : 0ull;
-    unsigned long long hub = (lane >= 2 * BFS_SPREAD && lane < BFS_NCTR) ? v : 0ull;
-    for (int o = 32; o > 0; o >>= 1) {
-        cnt += __shfl_xor(cnt, o, 64);
-        deg += __shfl_xor(deg, o, 64);
-        hub += __shfl_xor(hub, o, 64);
-    }
+    const unsigned long long cnt = wave_sum64(lane < BFS_SPREAD ? v : 0ull);
+    const unsigned long long deg = wave_sum64((lane >= BFS_SPREAD && lane < 2 * BFS_SPREAD) ? v : 0ull);
+    const unsigned long long hub = wave_sum64((lane >= 2 * BFS_SPREAD && lane < BFS_NCTR) ? v : 0ull);
     if (lane != 0) return;
     if (ps.done) {
         ns->done = 2;   // finished before this level
@@ -380,11 +375,9 @@ __global__ __launch_bounds__(256, 8) void k_bfs_level(const BfsDev *__restrict__
     }
     // the level's vertex count, degree sum and hub count: one atomic per
     // workgroup on one of BFS_SPREAD counters
-    for (int o = 32; o > 0; o >>= 1) {
-        cnt += __shfl_xor(cnt, o, 64);
-        deg += __shfl_xor(deg, o, 64);
-        hub += __shfl_xor(hub, o, 64);
-    }
+    cnt = wave_sum64(cnt);
+    deg = wave_sum64(deg);
+    hub = wave_sum64(hub);
     if (lane == 0 && (cnt | deg | hub)) {
         atomicAdd(&s_cnt, cnt);
         atomicAdd(&s_deg, deg);

@@ -459,6 +459,31 @@ __device__ __forceinline__ int wave_incl_sum(int x)
     return t;
 }
 
+// A 64-bit value moved by one DPP control (both halves; 0 where the
+// source lane is missing or the row is masked off).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)x, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(x >> 32), CTRL, ROW_MASK, 0xf, false);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+// The sum of x over the 64 lanes (every lane active), by the steps of
+// wave_incl_sum on 64-bit values; the total is read from lane 63.
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long x)
+{
+    x += dpp_u64<0x111, 0xf>(x);   // row_shr:1
+    x += dpp_u64<0x112, 0xf>(x);   // row_shr:2
+    x += dpp_u64<0x114, 0xf>(x);   // row_shr:4
+    x += dpp_u64<0x118, 0xf>(x);   // row_shr:8
+    x += dpp_u64<0x142, 0xa>(x);   // row_bcast:15
+    x += dpp_u64<0x143, 0xc>(x);   // row_bcast:31
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 struct WaveRun {
     unsigned head;
     uint64_t run, before;
