@@ -263,7 +263,7 @@ __global__ __launch_bounds__(256) void k_bc_compact(const int64_t *__restrict__ 
                                                     const unsigned long long *__restrict__ cin)
 {
     if (cin && cin[0] == 0) return;
-    __shared__ unsigned sf[256], sa[256];
+    __shared__ unsigned wf[4], wa[4];
     __shared__ unsigned long long base_f, base_a, sum_ef, sum_ea;
     const int64_t share = (n + gridDim.x - 1) / gridDim.x;
     const int64_t v0 = (int64_t)blockIdx.x * share, v1 = min(n, v0 + share);
@@ -286,36 +286,26 @@ __global__ __launch_bounds__(256) void k_bc_compact(const int64_t *__restrict__ 
             ea += (unsigned long long)din;
         }
     }
-    sf[threadIdx.x] = cf;
-    sa[threadIdx.x] = ca;
     if (threadIdx.x == 0) sum_ef = sum_ea = 0;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        const unsigned yf = (int)threadIdx.x >= o ? sf[threadIdx.x - o] : 0u;
-        const unsigned ya = (int)threadIdx.x >= o ? sa[threadIdx.x - o] : 0u;
-        __syncthreads();
-        sf[threadIdx.x] += yf;
-        sa[threadIdx.x] += ya;
-        __syncthreads();
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        ef += __shfl_xor(ef, o, 64);
-        ea += __shfl_xor(ea, o, 64);
-    }
+    unsigned tf, ta;
+    const unsigned xf = block_excl_scan256(cf, wf, tf);
+    const unsigned xa = block_excl_scan256(ca, wa, ta);
+    ef = wave_sum64(ef);
+    ea = wave_sum64(ea);
     if (lane_id() == 0) {
         if (ef) atomicAdd(&sum_ef, ef);
         if (ea) atomicAdd(&sum_ea, ea);
     }
-    if (threadIdx.x == 255) {
-        base_f = sf[255] ? atomicAdd(&cnt[0], (unsigned long long)sf[255]) : 0;
-        base_a = sa[255] ? atomicAdd(&cnt[2], (unsigned long long)sa[255]) : 0;
+    if (threadIdx.x == 0) {
+        base_f = tf ? atomicAdd(&cnt[0], (unsigned long long)tf) : 0;
+        base_a = ta ? atomicAdd(&cnt[2], (unsigned long long)ta) : 0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         if (sum_ef) atomicAdd(&cnt[1], sum_ef);
         if (sum_ea) atomicAdd(&cnt[3], sum_ea);
     }
-    unsigned long long pf = base_f + sf[threadIdx.x] - cf, pa = base_a + sa[threadIdx.x] - ca;
+    unsigned long long pf = base_f + xf, pa = base_a + xa;
     for (int64_t v = v0 + threadIdx.x; v < v1; v += 256) {
         const uint64_t nm = next[v], uv = unvis[v];
         if (nm) flist[pf++] = (int32_t)v;

@@ -459,6 +459,27 @@ __device__ __forceinline__ int wave_incl_sum(int x)
     return t;
 }
 
+// Exclusive prefix of x over a block of 256 threads (in thread order) and
+// the block total: DPP sums within the waves, then the four wave totals
+// through LDS (wtot, 4 entries).  Every thread of the block must call it;
+// wtot may be reused after the next __syncthreads.
+__device__ __forceinline__ unsigned block_excl_scan256(unsigned x, unsigned *wtot, unsigned &total)
+{
+    const unsigned lane = lane_id(), w = threadIdx.x >> 6;
+    const unsigned incl = (unsigned)wave_incl_sum((int)x);
+    if (lane == 63) wtot[w] = incl;
+    __syncthreads();
+    unsigned before = 0, all = 0;
+#pragma unroll
+    for (unsigned k = 0; k < 4; k++) {
+        const unsigned t = wtot[k];
+        before += k < w ? t : 0u;
+        all += t;
+    }
+    total = all;
+    return before + incl - x;
+}
+
 // A 64-bit value moved by one DPP control (both halves; 0 where the
 // source lane is missing or the row is masked off).
 template <int CTRL, int ROW_MASK>

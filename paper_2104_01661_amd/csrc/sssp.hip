@@ -287,20 +287,14 @@ __global__ __launch_bounds__(256) void k_sssp_light(SsspDev *dp, int par)
 __device__ __forceinline__ void block_list_words(uint32_t x, int64_t w, int32_t *__restrict__ out_list,
                                                  unsigned long long *counter)
 {
-    __shared__ unsigned scan[256];
+    __shared__ unsigned wtot[4];
     __shared__ unsigned long long base_s;
     const unsigned c = (unsigned)__popc(x);
-    scan[threadIdx.x] = c;
+    unsigned total;
+    const unsigned before = block_excl_scan256(c, wtot, total);
+    if (threadIdx.x == 0) base_s = total ? atomicAdd(counter, (unsigned long long)total) : 0;
     __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        const unsigned y = (int)threadIdx.x >= o ? scan[threadIdx.x - o] : 0u;
-        __syncthreads();
-        scan[threadIdx.x] += y;
-        __syncthreads();
-    }
-    if (threadIdx.x == 255) base_s = scan[255] ? atomicAdd(counter, (unsigned long long)scan[255]) : 0;
-    __syncthreads();
-    unsigned long long pos = base_s + scan[threadIdx.x] - c;
+    unsigned long long pos = base_s + before;
     for (uint32_t y = x; y; y &= y - 1) out_list[pos++] = (int32_t)(w * 32 + __ffs(y) - 1);
 }
 
