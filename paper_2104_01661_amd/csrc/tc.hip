@@ -662,10 +662,13 @@ int tc_masked_dot(lagr_ctx ctx, const TcArgs &a, bool per_entry, unsigned long l
 
 // ------------------------------------------------------------------- TC
 
-// The count's ids sit below 2^30 entries of L: 32-bit byte offsets reach them.
+// The count's ids sit below 2^30 entries of L, and its bitmap words below
+// 2^30 words (the bitmaps hold fewer words than L has entries, plus at most
+// PLAN_HOT / 32 words for each of PLAN_HOT hub rows): 32-bit byte offsets
+// reach them.
 static inline bool tc_off32(const lagr_matrix L)
 {
-    return L->nvals < ((int64_t)1 << 30);
+    return L->nvals < ((int64_t)1 << 30) - ((int64_t)1 << 20);
 }
 
 // With the plan's status still on the device (G->tc_status_pending), the

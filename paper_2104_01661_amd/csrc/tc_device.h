@@ -546,6 +546,9 @@ constexpr int TC_BITS_INFLIGHT = 6;   // bitmap word loads in flight per lane
 // is g / nw by a multiply with ceil(2^32 / nw) (exact while g * nw < 2^32,
 // g < 64 * 768 here); with per-pair widths, each lane walks the pairs'
 // word offsets forward as tc_stream_flat walks segments.
+// With OFF32 every bitmap word lies below 2^30 words of bits (32-bit byte
+// offsets from bits, as in tc_stream_flat).
+template <bool OFF32 = false>
 __device__ __forceinline__ unsigned long long tc_bitmap_lanes(TcWaveLds &L, const uint32_t *__restrict__ bits,
                                                               const int32_t *__restrict__ Arow, int64_t alen, int cnt,
                                                               unsigned lane)
@@ -573,7 +576,11 @@ __device__ __forceinline__ unsigned long long tc_bitmap_lanes(TcWaveLds &L, cons
                 const int g = g0 + 64 * f + (int)lane;
                 const int q = (int)(((unsigned long long)(unsigned)g * magic) >> 32), w = g - q * nw;
                 const bool v = g < total;
-                x[f] = v ? bits[L.seg_s[q] + w] : 0u;
+                if (OFF32)
+                    x[f] = v ? *(const uint32_t *)((const char *)bits + (((uint32_t)L.seg_s[q] + (uint32_t)w) << 2))
+                             : 0u;
+                else
+                    x[f] = v ? bits[L.seg_s[q] + w] : 0u;
                 y[f] = v ? L.bm[w] : 0u;
             }
 #pragma unroll
@@ -601,7 +608,8 @@ __device__ __forceinline__ unsigned long long tc_bitmap_lanes(TcWaveLds &L, cons
                 if (g < total) {
                     while (L.seg_x[t + 1] <= g) t++;
                     const int w = g - L.seg_x[t];
-                    x[f] = bits[L.seg_s[t] + w];
+                    if (OFF32) x[f] = *(const uint32_t *)((const char *)bits + (((uint32_t)L.seg_s[t] + (uint32_t)w) << 2));
+                    else x[f] = bits[L.seg_s[t] + w];
                     y[f] = L.bm[w];
                 }
             }
@@ -680,7 +688,7 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
             }
             acc += tc_stream_flat<BATCHED ? TC_FLAT_INFLIGHT_BATCHED : TC_FLAT_INFLIGHT, OFF32>(L, use_hash, Arow, alen,
                                                                                      a.Lci, s, len, cnt, lane);
-            if (any_bitmap) acc += tc_bitmap_lanes(L, a.bits, Arow, alen, cnt, lane);
+            if (any_bitmap) acc += tc_bitmap_lanes<OFF32>(L, a.bits, Arow, alen, cnt, lane);
         }
     }
     if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
