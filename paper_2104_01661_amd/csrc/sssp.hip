@@ -148,16 +148,20 @@ __device__ __forceinline__ unsigned long long relax_batch(const SsspDev &d, cons
         nb[k] = as_bits(du[k] + w[k]);
         cur[k] = ok[k] ? d.dist[v[k]] : 0ull;
     }
-    unsigned long long old[RELAX_BATCH];
+    // The atomic's old value is not waited for: a lane whose value is below
+    // the one it read has lowered t(v) or lost to a lower value stored in
+    // this step, whose own lane marks v too (a lower value is inside the
+    // bucket whenever this one is) and reports a value no larger; so the
+    // marks and the smallest value are those of the winners alone.
 #pragma unroll
     for (int k = 0; k < RELAX_BATCH; k++) {
         ok[k] = ok[k] && nb[k] < cur[k];
-        old[k] = ok[k] ? atomicMin(&d.dist[v[k]], nb[k]) : 0ull;
+        if (ok[k]) atomicMin(&d.dist[v[k]], nb[k]);
     }
     unsigned long long far = SSSP_INF;
 #pragma unroll
     for (int k = 0; k < RELAX_BATCH; k++) {
-        if (!ok[k] || nb[k] >= old[k]) continue;
+        if (!ok[k]) continue;
         if (!HEAVY && as_f64(nb[k]) < d.hi) atomicOr(&next_bm[v[k] >> 5], 1u << (v[k] & 31));
         else far = nb[k] < far ? nb[k] : far;
     }
