@@ -198,8 +198,16 @@ __device__ __forceinline__ int group_size(int64_t nq, int64_t nw)
 // Relax the edges of the g vertices list[f0 .. f0 + g) (rows of at most
 // GRAPH_LONG_ROW entries) with the whole wave: an inclusive scan of the row
 // lengths over the lanes lays the g rows end to end, and lane l takes edge
-// t0 + l of that sequence, whose owner is the first lane with scan > t
-// (six shuffle steps).  Every lane of the wave must call it.
+// t0 + l of that sequence.  The rows' ends, starts and distances go to the
+// wave's LDS, and each lane walks them forward to the owner of its edge
+// (its edges only increase: about one step per row boundary crossed),
+// keeping the owner's start and distance in registers.  Every lane of the
+// wave must call it (256-thread workgroups).
+struct RelaxRows {
+    int end[64];
+    int64_t start[64];
+    double du[64];
+};
 template <bool HEAVY>
 __device__ __forceinline__ unsigned long long relax_group(const SsspDev &d, const int32_t *__restrict__ list,
                                                           int64_t f0, int g, int64_t nq, unsigned lane,
@@ -221,6 +229,21 @@ __device__ __forceinline__ unsigned long long relax_group(const SsspDev &d, cons
     const int incl = wave_incl_sum(len);
     const int total = __builtin_amdgcn_readlane(incl, 63);
     const int64_t start = b - (incl - len);   // row start minus the row's offset in the sequence
+    __shared__ RelaxRows rows[4];
+    RelaxRows &R = rows[threadIdx.x >> 6];
+    // (the wave's LDS operations run in order; the fences keep the compiler
+    // from moving them across: the previous call's reads, then these writes)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    R.end[lane] = incl;
+    R.start[lane] = start;
+    R.du[lane] = du;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int r = 0, rend = R.end[0];
+    int64_t sr = R.start[0];
+    double dr = R.du[0];
     unsigned long long far = SSSP_INF;
     for (int t0 = 0; t0 < total; t0 += 64 * RELAX_BATCH) {
         int64_t p[RELAX_BATCH];
@@ -228,14 +251,20 @@ __device__ __forceinline__ unsigned long long relax_group(const SsspDev &d, cons
 #pragma unroll
         for (int k = 0; k < RELAX_BATCH; k++) {
             const int t = t0 + 64 * k + (int)lane;
-            int lo = 0;
-            for (int step = 32; step > 0; step >>= 1) {
-                const int probe = __shfl(incl, lo + step - 1, 64);
-                if (probe <= t) lo += step;
+            p[k] = -1;
+            dk[k] = 0.0;
+            if (t < total) {
+                if (rend <= t) {
+                    do {
+                        ++r;
+                        rend = R.end[r];
+                    } while (rend <= t);
+                    sr = R.start[r];
+                    dr = R.du[r];
+                }
+                p[k] = sr + t;
+                dk[k] = dr;
             }
-            const int64_t sk = __shfl(start, lo, 64);
-            dk[k] = __shfl(du, lo, 64);
-            p[k] = t < total ? sk + t : -1;
         }
         const unsigned long long x = relax_batch<HEAVY>(d, dk, p, next_bm);
         far = x < far ? x : far;
