@@ -81,11 +81,18 @@ __device__ __forceinline__ void push_entry(const VxmArgs &a, int64_t p, uint32_t
 // Each wavefront takes 64 frontier vertices (list entries, or 64
 // consecutive indices of a bitmap / full u), one per lane, and spreads the
 // entries of their rows over its lanes: an in-wave prefix sum of the row
-// lengths, then entry t of the batch belongs to the lane whose range holds
-// t (binary search over the 64 offsets in LDS).  A long row is queued.
+// lengths lays the rows end to end in LDS (offsets, row starts, indices),
+// and lane l takes entries t = l, l + 64, ... of the batch, walking the
+// offsets forward to the row that holds t (its entries only increase: one
+// step per row boundary crossed).  VXM_DEPTH entries per lane go through
+// each stage together (their ids, then their mask bytes, then their
+// atomics).  A long row is queued.
+constexpr int VXM_DEPTH = 4;
+
 __global__ __launch_bounds__(256) void k_vxm_push(const VxmArgs a)
 {
     __shared__ int32_t s_off[4][65];
+    __shared__ int64_t s_b[4][64], s_k[4][64];
     const int lane = threadIdx.x & 63, wib = threadIdx.x >> 6;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -121,27 +128,47 @@ __global__ __launch_bounds__(256) void k_vxm_push(const VxmArgs a)
         if (total == 0) continue;
         s_off[wib][lane + 1] = inc;
         if (lane == 0) s_off[wib][0] = 0;
-        __builtin_amdgcn_wave_barrier();
+        s_b[wib][lane] = b - (inc - len);   // row start minus the row's offset in the batch
+        s_k[wib][lane] = k;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        // the loop is uniform over the wave: every lane takes part in the
-        // shuffles (a shuffle from a lane that has left a loop reads a
-        // stale register), and only lanes with t < total touch memory
-        for (int32_t t0 = 0; t0 < total; t0 += 64) {
-            const int32_t t = t0 + lane;
-            // the lane l with s_off[l] <= t < s_off[l + 1]
-            int lo = 0;
-            if (t < total) {
-                int hi = 63;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_off[wib][mid] <= t) lo = mid;
-                    else hi = mid - 1;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // the lane's row r (offsets s_off[r] <= t < rend = s_off[r + 1]),
+        // its start minus offset rb and index rk, in registers
+        int r = 0, rend = s_off[wib][1];
+        int64_t rb = s_b[wib][0], rk = s_k[wib][0];
+        for (int32_t t0 = 0; t0 < total; t0 += 64 * VXM_DEPTH) {
+            int64_t pp[VXM_DEPTH];
+            uint32_t kk[VXM_DEPTH];
+#pragma unroll
+            for (int dd = 0; dd < VXM_DEPTH; dd++) {
+                const int32_t t = t0 + 64 * dd + lane;
+                pp[dd] = -1;
+                kk[dd] = 0;
+                if (t < total) {
+                    if (rend <= t) {
+                        do {
+                            ++r;
+                            rend = s_off[wib][r + 1];
+                        } while (rend <= t);
+                        rb = s_b[wib][r];
+                        rk = s_k[wib][r];
+                    }
+                    pp[dd] = rb + t;
+                    kk[dd] = (uint32_t)rk;
                 }
             }
-            const int64_t kb = __shfl(b, lo, 64);
-            const int64_t kk = __shfl(k, lo, 64);
-            if (t < total) push_entry(a, kb + (t - s_off[wib][lo]), (uint32_t)kk);
+            int32_t jj[VXM_DEPTH];
+#pragma unroll
+            for (int dd = 0; dd < VXM_DEPTH; dd++) jj[dd] = pp[dd] >= 0 ? a.ci[pp[dd]] : -1;
+            uint8_t mp[VXM_DEPTH];
+#pragma unroll
+            for (int dd = 0; dd < VXM_DEPTH; dd++) mp[dd] = jj[dd] >= 0 ? a.mpres[jj[dd]] : (uint8_t)1;
+#pragma unroll
+            for (int dd = 0; dd < VXM_DEPTH; dd++)
+                if (!mp[dd]) __hip_atomic_fetch_min(a.cand + jj[dd], kk[dd], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
 }
