@@ -89,11 +89,13 @@ __global__ void k_pack_items(const int32_t *__restrict__ row, int64_t n, int32_t
 }
 
 // Items taken `grain` at a time from per-XCD counters (ctr, zeroed with
-// the per-graph counts before each launch), as in the single-graph count.
+// the per-graph counts before each launch), as in the single-graph count;
+// OFF32 when the packed ids and bitmap words each number below 2^30.
+template <bool OFF32>
 __global__ __launch_bounds__(TC_BLOCK, 8) void k_tc_batched(PlanArgs a, unsigned long long *ctr, int64_t grain)
 {
     __shared__ TcWaveLds lds[TC_WAVES];
-    tc_dyn_wave<true>(a, lds[threadIdx.x / 64], ctr, (int)(blockIdx.x % TC_DYN_PARTS), grain);
+    tc_dyn_wave<true, OFF32>(a, lds[threadIdx.x / 64], ctr, (int)(blockIdx.x % TC_DYN_PARTS), grain);
 }
 
 constexpr int64_t BATCH_CTRS = (int64_t)TC_DYN_STRIDE * TC_DYN_PARTS;   // after the ng counts
@@ -130,8 +132,13 @@ int enqueue_count(lagr_batch B, hipStream_t s, const lagr_tune &t, char *msg)
     if (B->K > 0) {
         // a multiple of 8 workgroups, so every XCD gets the same number
         const unsigned blocks = (unsigned)(B->num_cus * t.blocks_per_cu);
-        hipLaunchKernelGGL(k_tc_batched, dim3(blocks), dim3(TC_BLOCK), 0, s, batch_args(B), B->counts + B->ng,
-                           (int64_t)t.row_charge);
+        const int64_t lim = (int64_t)1 << 30;
+        if (B->E < lim && B->NB < lim)
+            hipLaunchKernelGGL(k_tc_batched<true>, dim3(blocks), dim3(TC_BLOCK), 0, s, batch_args(B), B->counts + B->ng,
+                               (int64_t)t.row_charge);
+        else
+            hipLaunchKernelGGL(k_tc_batched<false>, dim3(blocks), dim3(TC_BLOCK), 0, s, batch_args(B),
+                               B->counts + B->ng, (int64_t)t.row_charge);
         LAUNCH_CHECK();
     }
     return LAGR_SUCCESS;
