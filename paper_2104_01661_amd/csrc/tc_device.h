@@ -657,16 +657,26 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
             continue;
         }
         const int64_t k1 = k0 + grain < r1 ? k0 + grain : r1;
-        for (int64_t k = k0; k < k1; k++) {
+        // the grabbed items' descriptors, up to 64 at a time, one per lane
+        // (one load each), then read back item by item with readlane: an
+        // item does not wait for its own descriptor load
+        for (int64_t kc = k0; kc < k1; kc += 64) {
+        const int kn = (int)(k1 - kc < 64 ? k1 - kc : 64);
+        const bool hasl = (int)lane < kn;
+        const uint64_t itv = hasl ? a.item[kc + lane] : 0ull;
+        const int32_t mv = hasl ? a.item_row[kc + lane] : 0;
+        const int32_t gv = (BATCHED && hasl) ? a.item_graph[kc + lane] : 0;
+        for (int q = 0; q < kn; q++) {
             if (BATCHED) {
-                const int32_t gk = a.item_graph[k];
+                const int32_t gk = __builtin_amdgcn_readlane(gv, q);
                 if (gk != g) {
                     flush();
                     g = gk;
                 }
             }
-            const uint64_t it = a.item[k];
-            const int32_t m = a.item_row[k];
+            const uint64_t it = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(itv >> 32), q) << 32) |
+                                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)itv, q);
+            const int32_t m = __builtin_amdgcn_readlane(mv, q);
             const int64_t e0 = (int64_t)(it >> TC_PLAN_CNT_BITS);
             const int cnt = (int)(it & ((1u << TC_PLAN_CNT_BITS) - 1));
             int64_t s = 0;
@@ -689,6 +699,7 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
             acc += tc_stream_flat<BATCHED ? TC_FLAT_INFLIGHT_BATCHED : TC_FLAT_INFLIGHT, OFF32>(L, use_hash, Arow, alen,
                                                                                      a.Lci, s, len, cnt, lane);
             if (any_bitmap) acc += tc_bitmap_lanes<OFF32>(L, a.bits, Arow, alen, cnt, lane);
+        }
         }
     }
     if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
