@@ -666,6 +666,17 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
         const uint64_t itv = hasl ? a.item[kc + lane] : 0ull;
         const int32_t mv = hasl ? a.item_row[kc + lane] : 0;
         const int32_t gv = (BATCHED && hasl) ? a.item_graph[kc + lane] : 0;
+        auto item_at = [&](int q) {
+            return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(itv >> 32), q) << 32) |
+                   (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)itv, q);
+        };
+        // each lane's entry of the next item is loaded while this one streams
+        uint64_t xn = 0;
+        {
+            const uint64_t it0 = item_at(0);
+            if ((int)lane < (int)(it0 & ((1u << TC_PLAN_CNT_BITS) - 1)))
+                xn = a.ent[(int64_t)(it0 >> TC_PLAN_CNT_BITS) + lane];
+        }
         for (int q = 0; q < kn; q++) {
             if (BATCHED) {
                 const int32_t gk = __builtin_amdgcn_readlane(gv, q);
@@ -674,15 +685,20 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
                     g = gk;
                 }
             }
-            const uint64_t it = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(itv >> 32), q) << 32) |
-                                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)itv, q);
+            const uint64_t it = item_at(q);
             const int32_t m = __builtin_amdgcn_readlane(mv, q);
-            const int64_t e0 = (int64_t)(it >> TC_PLAN_CNT_BITS);
             const int cnt = (int)(it & ((1u << TC_PLAN_CNT_BITS) - 1));
+            const uint64_t xq = xn;
+            xn = 0;
+            if (q + 1 < kn) {
+                const uint64_t itn = item_at(q + 1);
+                if ((int)lane < (int)(itn & ((1u << TC_PLAN_CNT_BITS) - 1)))
+                    xn = a.ent[(int64_t)(itn >> TC_PLAN_CNT_BITS) + lane];
+            }
             int64_t s = 0;
             int len = 0;
             if ((int)lane < cnt) {
-                const uint64_t x = a.ent[e0 + lane];
+                const uint64_t x = xq;
                 // a bitmap entry streams no ids: it rides in s, raw, to tc_bitmap_lanes
                 const bool bitmap = (x & TC_PLAN_BITS) != 0;
                 s = bitmap ? (int64_t)x : (int64_t)(x >> TC_PLAN_LEN_BITS);
