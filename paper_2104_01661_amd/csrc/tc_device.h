@@ -55,9 +55,9 @@ __device__ __forceinline__ int64_t tc_graph_of(const TcArgs &a, int64_t r)
 }
 
 struct TcWaveLds {
-    uint32_t bm[TC_BM_WORDS];
-    int32_t hs[TC_HS_SLOTS];
     int64_t seg_s[64];      // flattened streaming: segment starts
+    uint32_t bm[TC_BM_WORDS + 1];   // word TC_BM_WORDS stays zero
+    int32_t hs[TC_HS_SLOTS];
     int32_t seg_x[65];      // and exclusive id offsets (seg_x[cnt] = total)
 };
 
@@ -202,7 +202,7 @@ __device__ __forceinline__ unsigned long long tc_stream_flat(TcWaveLds &L, bool 
     }
     if (lane == 0) L.seg_x[cnt] = total;
     wave_sync();
-    unsigned long long acc = 0;
+    unsigned acc = 0;   // (a lane probes one id in 64 of an int total)
     // the lane's current segment t (start cs in Bci, offset cx) and the next
     // one's offset nx, kept in registers: LDS is read only on a crossing
     // (px points at seg_x[t + 1]: a crossing step is one pointer increment
@@ -218,7 +218,7 @@ __device__ __forceinline__ unsigned long long tc_stream_flat(TcWaveLds &L, bool 
         for (int f = 0; f < INFLIGHT; f++) {
             const int g = g0 + 64 * f + (int)lane;
             v[f] = g < total;
-            k[f] = 0;
+            k[f] = -1;
             if (v[f]) {
                 if (nx <= g) {
                     do {
@@ -235,21 +235,28 @@ __device__ __forceinline__ unsigned long long tc_stream_flat(TcWaveLds &L, bool 
             }
         }
         // the bitmap probes of all units together (no branch: an id past
-        // the bitmap, or a lane past the end, reads word 0 and masks it
-        // out), then the ids past the bitmap, in the units that hold any
+        // the bitmap, or a lane past the end with id -1, reads the zero
+        // word after the bitmap), then the ids past the bitmap, in the
+        // units that hold any
         uint32_t wd[INFLIGHT];
+        bool large = false;
 #pragma unroll
-        for (int f = 0; f < INFLIGHT; f++) wd[f] = L.bm[(k[f] < TC_BM_IDS ? k[f] : 0) >> 5];
+        for (int f = 0; f < INFLIGHT; f++) {
+            const unsigned w = (unsigned)k[f] >> 5;
+            wd[f] = L.bm[w < (unsigned)TC_BM_WORDS ? w : (unsigned)TC_BM_WORDS];
+            large = large || k[f] >= TC_BM_IDS;
+        }
 #pragma unroll
-        for (int f = 0; f < INFLIGHT; f++)
-            acc += (v[f] && k[f] < TC_BM_IDS) ? __builtin_amdgcn_ubfe(wd[f], (unsigned)k[f], 1u) : 0u;
+        for (int f = 0; f < INFLIGHT; f++) acc += __builtin_amdgcn_ubfe(wd[f], (unsigned)k[f], 1u);
+        if (__ballot(large)) {
 #pragma unroll
-        for (int f = 0; f < INFLIGHT; f++)
-            if (__ballot(v[f] && k[f] >= TC_BM_IDS))
-                acc += (v[f] && k[f] >= TC_BM_IDS) ? tc_member_large(L, use_hash, Arow, alen, k[f]) : 0u;
+            for (int f = 0; f < INFLIGHT; f++)
+                if (__ballot(k[f] >= TC_BM_IDS))
+                    acc += k[f] >= TC_BM_IDS ? tc_member_large(L, use_hash, Arow, alen, k[f]) : 0u;
+        }
     }
     wave_sync();
-    return acc;
+    return (unsigned long long)acc;
 }
 
 // Row i by the whole wave.  Returns the row's total; with PER_ENTRY also
@@ -361,7 +368,7 @@ __device__ unsigned long long tc_rows_balanced(const TcArgs &a, TcWaveLds &L,
                                                unsigned long long *__restrict__ per_graph = nullptr)
 {
     const unsigned lane = lane_id();
-    for (int x = lane; x < TC_BM_WORDS; x += 64) L.bm[x] = 0u;
+    for (int x = lane; x <= TC_BM_WORDS; x += 64) L.bm[x] = 0u;
     wave_sync();
     const int64_t T = prefix[a.nrows];
     const int64_t lo = (int64_t)((__int128)T * w / nw), hi = (int64_t)((__int128)T * (w + 1) / nw);
@@ -630,7 +637,7 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
                                           int64_t grain)
 {
     const unsigned lane = lane_id();
-    for (int x = lane; x < TC_BM_WORDS; x += 64) L.bm[x] = 0u;
+    for (int x = lane; x <= TC_BM_WORDS; x += 64) L.bm[x] = 0u;
     wave_sync();
     const uint64_t lmask = (1ull << TC_PLAN_LEN_BITS) - 1;
     const int64_t N = a.nitems_dev ? *a.nitems_dev : a.nitems;
