@@ -54,8 +54,18 @@ __device__ __forceinline__ int64_t tc_graph_of(const TcArgs &a, int64_t r)
     return lo;
 }
 
+// A streamed segment of the flattened loop: the next segment's offset and
+// the segment's start in Bci minus its own offset (32-bit form).
+struct TcPair {
+    uint32_t x, b;
+};
+
 struct TcWaveLds {
-    int64_t seg_s[64];      // flattened streaming: segment starts
+    union {
+        int64_t seg_s[64];  // flattened streaming: segment starts
+        TcPair seg_p[64];   // or, with 32-bit offsets, per streamed segment
+                            // (next offset, start - offset)
+    };
     uint32_t bm[TC_BM_WORDS + 1];   // word TC_BM_WORDS stays zero
     int32_t hs[TC_HS_SLOTS];
     int32_t seg_x[65];      // and exclusive id offsets (seg_x[cnt] = total)
@@ -187,7 +197,11 @@ constexpr int TC_FLAT_INFLIGHT = 7;
 constexpr int TC_FLAT_INFLIGHT_BATCHED = 5;
 
 // With OFF32 every streamed id lies below 2^30 entries of Bci, so an id is
-// loaded at a 32-bit byte offset from Bci (no 64-bit address arithmetic).
+// loaded at a 32-bit byte offset from Bci (no 64-bit address arithmetic),
+// and the segments of nonzero length (in lane order) go to L.seg_p as
+// pairs: a crossing step reads the next offset and the start together.
+// The other lanes below cnt keep s in L.seg_s after them, from slot
+// nonzero-lengths-count on (a bitmap entry rides there to tc_bitmap_lanes).
 template <int INFLIGHT = TC_FLAT_INFLIGHT, bool OFF32 = false>
 __device__ __forceinline__ unsigned long long tc_stream_flat(TcWaveLds &L, bool use_hash,
                                                              const int32_t *__restrict__ Arow, int64_t alen,
@@ -196,21 +210,39 @@ __device__ __forceinline__ unsigned long long tc_stream_flat(TcWaveLds &L, bool 
 {
     const int incl = wave_incl_sum(len);
     const int total = __builtin_amdgcn_readlane(incl, 63);
-    if ((int)lane < cnt) {
-        L.seg_s[lane] = s;
-        L.seg_x[lane] = incl - len;
+    if (OFF32) {
+        const uint64_t mk = __ballot(len > 0);
+        const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
+        if (len > 0) L.seg_p[below] = TcPair{(uint32_t)incl, (uint32_t)s - (uint32_t)(incl - len)};
+        else if ((int)lane < cnt) L.seg_s[__popcll(mk) + (int)lane - below] = s;
+    } else {
+        if ((int)lane < cnt) {
+            L.seg_s[lane] = s;
+            L.seg_x[lane] = incl - len;
+        }
+        if (lane == 0) L.seg_x[cnt] = total;
     }
-    if (lane == 0) L.seg_x[cnt] = total;
     wave_sync();
     unsigned acc = 0;   // (a lane probes one id in 64 of an int total)
-    // the lane's current segment t (start cs in Bci, offset cx) and the next
-    // one's offset nx, kept in registers: LDS is read only on a crossing
-    // (px points at seg_x[t + 1]: a crossing step is one pointer increment
-    // and one LDS read; t and cx are recovered after the walk)
+    // the lane's current segment t (start s_t in Bci, offset x_t) and the
+    // next one's offset nx, kept in registers: LDS is read only on a
+    // crossing (px points at seg_x[t + 1], pp at seg_p[t]: a crossing step
+    // is one pointer increment and one LDS read).
+    // Id g of the concatenation is Bci[s_t - x_t + g]: cb holds s_t - x_t.
     const int32_t *px = &L.seg_x[1];
-    int cx = 0, nx = *px;
-    int64_t cs = OFF32 ? 0 : L.seg_s[0];
-    uint32_t cs32 = OFF32 ? (uint32_t)L.seg_s[0] : 0u;
+    const TcPair *pp = &L.seg_p[0];
+    int nx;
+    int64_t cb = 0;
+    uint32_t cb32 = 0u;
+    if (OFF32) {
+        const TcPair p0 = *pp;
+        nx = (int)p0.x;
+        cb32 = p0.b;
+    } else {
+        nx = *px;
+        cb = L.seg_s[0];
+    }
     for (int g0 = 0; g0 < total; g0 += 64 * INFLIGHT) {
         int32_t k[INFLIGHT];
         bool v[INFLIGHT];
@@ -221,17 +253,25 @@ __device__ __forceinline__ unsigned long long tc_stream_flat(TcWaveLds &L, bool 
             k[f] = -1;
             if (v[f]) {
                 if (nx <= g) {
-                    do {
-                        ++px;
-                        nx = *px;
-                    } while (nx <= g);
-                    const int t = (int)(px - &L.seg_x[1]);
-                    cx = px[-1];
-                    if (OFF32) cs32 = (uint32_t)L.seg_s[t];
-                    else cs = L.seg_s[t];
+                    if (OFF32) {
+                        TcPair pr;
+                        do {
+                            ++pp;
+                            pr = *pp;
+                        } while ((int)pr.x <= g);
+                        nx = (int)pr.x;
+                        cb32 = pr.b;
+                    } else {
+                        do {
+                            ++px;
+                            nx = *px;
+                        } while (nx <= g);
+                        const int t = (int)(px - &L.seg_x[1]);
+                        cb = L.seg_s[t] - px[-1];
+                    }
                 }
-                if (OFF32) k[f] = *(const int32_t *)((const char *)Bci + ((cs32 + (uint32_t)(g - cx)) << 2));
-                else k[f] = Bci[cs + (g - cx)];
+                if (OFF32) k[f] = *(const int32_t *)((const char *)Bci + ((cb32 + (uint32_t)g) << 2));
+                else k[f] = Bci[cb + g];
             }
         }
         // the bitmap probes of all units together (no branch: an id past
@@ -538,8 +578,9 @@ struct PlanArgs {
 // items of one graph are contiguous) and the result is 0.
 constexpr int TC_BITS_INFLIGHT = 6;   // bitmap word loads in flight per lane
 
-// The bitmap pairs of one item.  tc_stream_flat left each lane's entry in
-// L.seg_s[lane] (lane < cnt); a bitmap entry is the plan's raw word (sign
+// The bitmap pairs of one item.  tc_stream_flat left the entries in
+// L.seg_s[first .. cnt) (first: 0, or with OFF32 the number of segments
+// of nonzero length, whose pairs fill the slots below); a bitmap entry is the plan's raw word (sign
 // bit set: TC_PLAN_BITS), holding the bitmap offset of its streamed row
 // and, for an A pair, the words to read (so no per-lane state has to live
 // in registers across the streaming loop).  A B item's pairs all read the
@@ -557,10 +598,10 @@ constexpr int TC_BITS_INFLIGHT = 6;   // bitmap word loads in flight per lane
 // offsets from bits, as in tc_stream_flat).
 template <bool OFF32 = false>
 __device__ __forceinline__ unsigned long long tc_bitmap_lanes(TcWaveLds &L, const uint32_t *__restrict__ bits,
-                                                              const int32_t *__restrict__ Arow, int64_t alen, int cnt,
-                                                              unsigned lane)
+                                                              const int32_t *__restrict__ Arow, int64_t alen, int first,
+                                                              int cnt, unsigned lane)
 {
-    const uint64_t x = (int)lane < cnt ? (uint64_t)L.seg_s[lane] : 0ull;
+    const uint64_t x = first <= (int)lane && (int)lane < cnt ? (uint64_t)L.seg_s[lane] : 0ull;
     const bool flag = (x & TC_PLAN_BITS) != 0;
     const int64_t off = (int64_t)(x & ((1ull << TC_PLAN_WORDS_SHIFT) - 1));
     const int nwl = (int)((x & ~TC_PLAN_BITS) >> TC_PLAN_WORDS_SHIFT);
@@ -712,6 +753,7 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
                 len = bitmap ? 0 : (int)(x & lmask);
             }
             const bool any_bitmap = __ballot(s < 0) != 0;
+            const int nstream = OFF32 ? __popcll(__ballot(len > 0)) : 0;
             if (m != marked) {
                 if (marked >= 0) tc_unmark_kept(L, first_id, alen, lane);
                 Arow = a.Lci + a.Lrp[m];
@@ -721,7 +763,8 @@ __device__ unsigned long long tc_dyn_wave(const PlanArgs &a, TcWaveLds &L, unsig
             }
             acc += tc_stream_flat<BATCHED ? TC_FLAT_INFLIGHT_BATCHED : TC_FLAT_INFLIGHT, OFF32>(L, use_hash, Arow, alen,
                                                                                      a.Lci, s, len, cnt, lane);
-            if (any_bitmap) acc += tc_bitmap_lanes<OFF32>(L, a.bits, Arow, alen, cnt, lane);
+            if (any_bitmap)
+                acc += tc_bitmap_lanes<OFF32>(L, a.bits, Arow, alen, nstream, cnt, lane);
         }
         }
     }
