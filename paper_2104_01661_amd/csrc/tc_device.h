@@ -615,54 +615,123 @@ __device__ __forceinline__ unsigned long long tc_bitmap_lanes(TcWaveLds &L, cons
         const int nw = alen > 0 ? (Arow[alen - 1] >> 5) + 1 : 0;   // up to the marked row's largest id
         if (flag) L.seg_s[r] = off;
         wave_sync();
-        const unsigned long long magic = (0x100000000ull + (unsigned)nw - 1) / (unsigned)nw;   // 2^32 for nw = 1
         const int total = np * nw;
-        for (int g0 = 0; g0 < total; g0 += 64 * TC_BITS_INFLIGHT) {
-            uint32_t x[TC_BITS_INFLIGHT], y[TC_BITS_INFLIGHT];
+        if (OFF32 && total > 0) {
+            // element g = q nw + w: each lane steps its (pair q, word w)
+            // forward by 64 elements per unit, so g < total is q < np; an
+            // idle lane probes the zero word after the bitmap
+            const int dq = 64 / nw, dw = 64 - dq * nw;
+            int q = (int)lane / nw, w = (int)lane - q * nw;
+            unsigned acc32 = 0;   // (at most 768 words of 32 bits per lane)
+            for (int g0 = 0; g0 < total; g0 += 64 * TC_BITS_INFLIGHT) {
+                int qf[TC_BITS_INFLIGHT], wf[TC_BITS_INFLIGHT];
+                uint32_t base[TC_BITS_INFLIGHT], x[TC_BITS_INFLIGHT], y[TC_BITS_INFLIGHT];
 #pragma unroll
-            for (int f = 0; f < TC_BITS_INFLIGHT; f++) {
-                const int g = g0 + 64 * f + (int)lane;
-                const int q = (int)(((unsigned long long)(unsigned)g * magic) >> 32), w = g - q * nw;
-                const bool v = g < total;
-                if (OFF32)
-                    x[f] = v ? *(const uint32_t *)((const char *)bits + (((uint32_t)L.seg_s[q] + (uint32_t)w) << 2))
-                             : 0u;
-                else
-                    x[f] = v ? bits[L.seg_s[q] + w] : 0u;
-                y[f] = v ? L.bm[w] : 0u;
+                for (int f = 0; f < TC_BITS_INFLIGHT; f++) {
+                    qf[f] = q;
+                    wf[f] = w;
+                    w += dw;
+                    q += dq;
+                    if (w >= nw) {
+                        w -= nw;
+                        q++;
+                    }
+                }
+#pragma unroll
+                for (int f = 0; f < TC_BITS_INFLIGHT; f++) base[f] = (uint32_t)L.seg_s[qf[f] < np ? qf[f] : 0];
+#pragma unroll
+                for (int f = 0; f < TC_BITS_INFLIGHT; f++) {
+                    const bool v = qf[f] < np;
+                    x[f] = v ? *(const uint32_t *)((const char *)bits + ((base[f] + (uint32_t)wf[f]) << 2)) : 0u;
+                    y[f] = L.bm[v ? wf[f] : TC_BM_WORDS];
+                }
+#pragma unroll
+                for (int f = 0; f < TC_BITS_INFLIGHT; f++) acc32 += (unsigned)__popc(x[f] & y[f]);
             }
+            acc = acc32;
+        } else if (!OFF32) {
+            const unsigned long long magic = (0x100000000ull + (unsigned)nw - 1) / (unsigned)nw;   // 2^32 for nw = 1
+            for (int g0 = 0; g0 < total; g0 += 64 * TC_BITS_INFLIGHT) {
+                uint32_t x[TC_BITS_INFLIGHT], y[TC_BITS_INFLIGHT];
 #pragma unroll
-            for (int f = 0; f < TC_BITS_INFLIGHT; f++) acc += (unsigned)__popc(x[f] & y[f]);
+                for (int f = 0; f < TC_BITS_INFLIGHT; f++) {
+                    const int g = g0 + 64 * f + (int)lane;
+                    const int q = (int)(((unsigned long long)(unsigned)g * magic) >> 32), w = g - q * nw;
+                    const bool v = g < total;
+                    x[f] = v ? bits[L.seg_s[q] + w] : 0u;
+                    y[f] = v ? L.bm[w] : 0u;
+                }
+#pragma unroll
+                for (int f = 0; f < TC_BITS_INFLIGHT; f++) acc += (unsigned)__popc(x[f] & y[f]);
+            }
         }
     } else {
         // exclusive word offsets of the flagged lanes, in lane order
         const int mine = flag ? nwl : 0;
         const int incl = wave_incl_sum(mine);
         const int total = __builtin_amdgcn_readlane(incl, 63);
-        if (flag) {
-            L.seg_s[r] = off;
-            L.seg_x[r] = incl - mine;
-        }
-        if (lane == 0) L.seg_x[np] = total;
-        wave_sync();
-        int t = 0;
-        for (int g0 = 0; g0 < total; g0 += 64 * TC_BITS_INFLIGHT) {
-            uint32_t x[TC_BITS_INFLIGHT], y[TC_BITS_INFLIGHT];
+        if (OFF32) {
+            // pairs (next offset, bits offset - offset) walked from registers
+            // as tc_stream_flat walks its segments; cx: the current pair's
+            // own offset
+            if (flag) L.seg_p[r] = TcPair{(uint32_t)incl, (uint32_t)off - (uint32_t)(incl - mine)};
+            wave_sync();
+            const TcPair *pp = &L.seg_p[0];
+            const TcPair p0 = *pp;
+            int nx = (int)p0.x, cx = 0;
+            uint32_t cb = p0.b;
+            unsigned acc32 = 0;
+            for (int g0 = 0; g0 < total; g0 += 64 * TC_BITS_INFLIGHT) {
+                uint32_t x[TC_BITS_INFLIGHT], y[TC_BITS_INFLIGHT];
 #pragma unroll
-            for (int f = 0; f < TC_BITS_INFLIGHT; f++) {
-                const int g = g0 + 64 * f + (int)lane;
-                x[f] = 0u;
-                y[f] = 0u;
-                if (g < total) {
-                    while (L.seg_x[t + 1] <= g) t++;
-                    const int w = g - L.seg_x[t];
-                    if (OFF32) x[f] = *(const uint32_t *)((const char *)bits + (((uint32_t)L.seg_s[t] + (uint32_t)w) << 2));
-                    else x[f] = bits[L.seg_s[t] + w];
-                    y[f] = L.bm[w];
+                for (int f = 0; f < TC_BITS_INFLIGHT; f++) {
+                    const int g = g0 + 64 * f + (int)lane;
+                    x[f] = 0u;
+                    y[f] = 0u;
+                    if (g < total) {
+                        if (nx <= g) {
+                            TcPair pr;
+                            do {
+                                cx = nx;
+                                ++pp;
+                                pr = *pp;
+                                nx = (int)pr.x;
+                            } while (nx <= g);
+                            cb = pr.b;
+                        }
+                        x[f] = *(const uint32_t *)((const char *)bits + ((cb + (uint32_t)g) << 2));
+                        y[f] = L.bm[g - cx];
+                    }
                 }
-            }
 #pragma unroll
-            for (int f = 0; f < TC_BITS_INFLIGHT; f++) acc += (unsigned)__popc(x[f] & y[f]);
+                for (int f = 0; f < TC_BITS_INFLIGHT; f++) acc32 += (unsigned)__popc(x[f] & y[f]);
+            }
+            acc = acc32;
+        } else {
+            if (flag) {
+                L.seg_s[r] = off;
+                L.seg_x[r] = incl - mine;
+            }
+            if (lane == 0) L.seg_x[np] = total;
+            wave_sync();
+            int t = 0;
+            for (int g0 = 0; g0 < total; g0 += 64 * TC_BITS_INFLIGHT) {
+                uint32_t x[TC_BITS_INFLIGHT], y[TC_BITS_INFLIGHT];
+#pragma unroll
+                for (int f = 0; f < TC_BITS_INFLIGHT; f++) {
+                    const int g = g0 + 64 * f + (int)lane;
+                    x[f] = 0u;
+                    y[f] = 0u;
+                    if (g < total) {
+                        while (L.seg_x[t + 1] <= g) t++;
+                        const int w = g - L.seg_x[t];
+                        x[f] = bits[L.seg_s[t] + w];
+                        y[f] = L.bm[w];
+                    }
+                }
+#pragma unroll
+                for (int f = 0; f < TC_BITS_INFLIGHT; f++) acc += (unsigned)__popc(x[f] & y[f]);
+            }
         }
     }
     wave_sync();
