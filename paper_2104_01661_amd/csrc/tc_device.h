@@ -68,7 +68,8 @@ struct TcWaveLds {
     };
     uint32_t bm[TC_BM_WORDS + 1];   // word TC_BM_WORDS stays zero
     int32_t hs[TC_HS_SLOTS];
-    int32_t seg_x[65];      // and exclusive id offsets (seg_x[cnt] = total)
+    int32_t seg_x[65];      // exclusive id offsets of the segments in seg_s
+                            // (seg_x[cnt] = total)
 };
 
 __device__ __forceinline__ void wave_sync()
@@ -579,21 +580,23 @@ struct PlanArgs {
 constexpr int TC_BITS_INFLIGHT = 6;   // bitmap word loads in flight per lane
 
 // The bitmap pairs of one item.  tc_stream_flat left the entries in
-// L.seg_s[first .. cnt) (first: 0, or with OFF32 the number of segments
-// of nonzero length, whose pairs fill the slots below); a bitmap entry is the plan's raw word (sign
-// bit set: TC_PLAN_BITS), holding the bitmap offset of its streamed row
-// and, for an A pair, the words to read (so no per-lane state has to live
-// in registers across the streaming loop).  A B item's pairs all read the
-// marked row's words: L_j's bits are in L.bm, all in its first mark_words
-// words (they cover L_j's largest id, so mark_words <= ceil(j/32), which
-// every streamed row's bitmap covers).  An A pair reads the whole of its
-// streamed row L_j as bits (nwl words, all ids below TC_BM_IDS) against
-// the marks of L_i.  The pairs are compacted into L.seg_s / L.seg_x and
-// their (pair, word) grid is walked 64 elements per load,
-// TC_BITS_INFLIGHT loads in flight: with one width, the pair of element g
-// is g / nw by a multiply with ceil(2^32 / nw) (exact while g * nw < 2^32,
-// g < 64 * 768 here); with per-pair widths, each lane walks the pairs'
-// word offsets forward as tc_stream_flat walks segments.
+// L.seg_s[first .. cnt) (first: 0, or with OFF32 the number of segments of
+// nonzero length, whose pairs fill the slots below); a bitmap entry is the
+// plan's raw word (sign bit set: TC_PLAN_BITS), holding the bitmap offset
+// of its streamed row and, for an A pair, the words to read (so no
+// per-lane state has to live in registers across the streaming loop).  A
+// B item's pairs all read the marked row's words: L_j's bits are in L.bm,
+// all in its first mark_words words (they cover L_j's largest id, so
+// mark_words <= ceil(j/32), which every streamed row's bitmap covers).  An
+// A pair reads the whole of its streamed row L_j as bits (nwl words, all
+// ids below TC_BM_IDS) against the marks of L_i.  The pairs are compacted
+// into the segment slots of L and their (pair, word) grid is walked 64
+// elements per load, TC_BITS_INFLIGHT loads in flight.  With one width nw,
+// each lane steps its (pair, word) position forward by 64 elements per
+// load (with 64-bit offsets the pair of element g is g / nw, by a multiply
+// with ceil(2^32 / nw), exact while g * nw < 2^32: g < 64 * 768 here);
+// with per-pair widths, each lane walks the pairs' word offsets forward as
+// tc_stream_flat walks segments.
 // With OFF32 every bitmap word lies below 2^30 words of bits (32-bit byte
 // offsets from bits, as in tc_stream_flat).
 template <bool OFF32 = false>
