@@ -243,6 +243,35 @@ def test_tc_cold_columns_over_wide_id_ranges(n, scale, extra):
     assert L.lagr_tc(G, ctx(), L.TC_DOT) == want
 
 
+@pytest.mark.parametrize("scale,ef,seed", [(12, 4, 11), (13, 8, 12)])
+def test_tc_planted_cliques_of_many_widths(scale, ef, seed):
+    """Cliques of 5 to 700 vertices planted at random ids of a sparse R-MAT
+    graph: after the degree relabel their rows of L are dense prefixes of
+    many lengths, so the count plan holds bitmap pairs of many word widths
+    (one-width items and items of several widths, whose elements straddle
+    pairs at every offset) beside streamed segments in the same items.  The
+    count equals the oracle's, the DOT method's and the many-graph batch's."""
+    L = lagr()
+    n, s, d = rmat(scale, ef, seed)
+    rng = np.random.default_rng(seed)
+    ss, dd = [np.asarray(s, dtype=np.int64)], [np.asarray(d, dtype=np.int64)]
+    for c in (5, 33, 63, 64, 65, 97, 130, 257, 700):
+        v = rng.choice(n, size=c, replace=False)
+        iu, ju = np.triu_indices(c, 1)
+        ss.append(v[iu])
+        dd.append(v[ju])
+    s2, d2 = np.concatenate(ss), np.concatenate(dd)
+    G = device_graph(n, s2, d2)
+    want = oracle.triangle_count(*oracle.build_adjacency(n, s2, d2))
+    assert want > math.comb(700, 3)
+    assert L.lagr_tc(G, ctx()) == want
+    assert L.lagr_tc(G, ctx(), L.TC_DOT) == want
+    n3, s3, d3 = rmat(8, 8, seed)
+    B = L.Batch(ctx(), [device_graph(n3, s3, d3), G])
+    got = B.tc(ctx(), L.Tune(8, 4, 0))
+    assert got[1] == want and got[0] == oracle.triangle_count(*oracle.build_adjacency(n3, s3, d3))
+
+
 # ----------------------------------------------------------------- BFS
 
 def bfs_host(G, s, flags=0):
