@@ -385,10 +385,10 @@ def main():
     arp, aci, _ = Am.to_csr(ctx)
     deg = torch.diff(arp).cpu().numpy()
 
-    # algorithmic byte model of the min-side count (one launch of k_tc_split):
+    # algorithmic byte model of the planned count (one launch of k_tc_split):
     # every pair (i, j) of L with p = position of j in row i >= 1 streams
-    # the shorter of L_j (len(L_j) <= p: "A side", row i marked) and
-    # L_i[0, p) ("B side", row j marked), except that a B pair with
+    # L_j ("A side", row i marked) unless L_j is more than twice as long as
+    # L_i[0, p) ("B side", row j marked, streaming L_i[0, p)), except that a B pair with
     # j < 24576 and ceil(j / 32) < p reads the words of row i's bitmap up to
     # L_j's largest id instead, and an A pair whose L_j has all its ids
     # below 24576 and fewer words (largest id / 32 + 1) than ids reads
@@ -408,8 +408,7 @@ def main():
     pos = torch.arange(nnzL, device=dev) - lrp[row_of]
     lj = llen[lci.long()]
     valid = (pos >= 1) & (lj > 0)
-    side_a = valid & (lj <= pos)
-    side_b = valid & (lj > pos)
+    side_b = valid & (lj > 2 * pos)
     jl = lci.long()
     last_id = lci[(lrp[1:] - 1).clamp(min=0)].long()          # largest id of each row
     words_j = (last_id[jl] >> 5) + 1

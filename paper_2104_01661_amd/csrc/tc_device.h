@@ -489,10 +489,12 @@ int tc_masked_dot(lagr_ctx ctx, const TcArgs &a, bool per_entry, unsigned long l
 // In the triangle-count form every pair (i, j) of L (j < i) contributes
 // |L_i and L_j|, and both sets only hold ids below j: L_j entirely, L_i in
 // its first p entries, where p is the position of j in row i.  The plan
-// streams the shorter of the two and probes it against LDS marks of the
-// other.  Virtual rows 0..n-1 ("A side", row i) mark L_i and stream whole
-// rows L_j (pairs with len(L_j) <= p); virtual rows n..2n-1 ("B side", row
-// j) mark L_j and stream the prefix L_i[0, p) (pairs with len(L_j) > p).
+// streams one of the two, about the shorter, and probes it against LDS
+// marks of the other.  Virtual rows 0..n-1 ("A side", row i) mark L_i and
+// stream whole rows L_j; virtual rows n..2n-1 ("B side", row j) mark L_j
+// and stream the prefix L_i[0, p), for pairs whose L_j is more than twice
+// as long as the prefix (hub columns by their own rule, in the plan
+// builder).
 // Pairs with p = 0 or an empty L_j contribute nothing and are dropped.  An
 // entry packs the streamed segment as (offset << TC_PLAN_LEN_BITS) |
 // length.  The virtual rows are cut into items of up to 64 entries; an
