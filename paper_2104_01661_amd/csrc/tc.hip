@@ -126,14 +126,17 @@ __host__ __device__ __forceinline__ bool plan_hub_b(int64_t p, int64_t lj, int64
     return p < lj && p < words;
 }
 
-// Any other pair goes to B row j only when L_j is more than twice as long
-// as the prefix L_i[0, p): a pair whose sides are closer streams L_j from
-// row i, at most p more ids, and spares the fill a cursor atomic and a
+// Any other pair goes to B row j when L_j is longer than the prefix
+// L_i[0, p), and in a graph with hub columns only when L_j is more than
+// twice as long: there a pair whose sides are closer streams L_j from row
+// i, at most p more ids, and spares the fill a cursor atomic and a
 // scattered write in B row j (at 2^20: 1.0 million of the 6.1 million such
-// pairs, 14.8 million more streamed ids, the whole count 1.5% faster).
-__host__ __device__ __forceinline__ bool plan_cold_b(int64_t p, int64_t lj)
+// pairs, 14.8 million more streamed ids, the whole count 1.5% faster; in
+// graphs of 2^16 vertices or fewer the extra ids cost more than the fill
+// saves).
+__host__ __device__ __forceinline__ bool plan_cold_b(int64_t p, int64_t lj, int64_t nhub)
 {
-    return lj > 2 * p;
+    return nhub > 0 ? lj > 2 * p : lj > p;
 }
 
 // One pass over the entries of L, on the fill's partition (workgroup g
@@ -189,7 +192,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_hot(const int32_t *__restri
                 const unsigned m = hmeta[j];
                 const int64_t lj = (m & 0xFFFFu) != 0xFFFFu ? (int64_t)(m & 0xFFFFu) : (int64_t)(rowpk[j] & lmask);
                 if (lj > 0 && p > 0) {
-                    bool b_side = plan_cold_b(p, lj);
+                    bool b_side = plan_cold_b(p, lj, nhub);
                     if (j < nhub) b_side = plan_hub_b(p, lj, (m >> 16) != 0xFFFFu ? (int64_t)(m >> 16) : hubw[j]);
                     if (b_side) atomicAdd(&hot[j], 1u);
                 }
@@ -382,7 +385,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_plan_fill(const int32_t *__restr
                 aval[k] = lj <= words ? pj[k] : fb[k];
                 if (valid && !a_side[k]) bpos[k] = bstart + (int64_t)atomicAdd(&hot[j[k]], 1u);
             } else {
-                a_side[k] = valid && !plan_cold_b(p, lj);
+                a_side[k] = valid && !plan_cold_b(p, lj, nhub);
                 aval[k] = fb[k] ? fb[k] : pj[k];
                 if (valid && !a_side[k]) {
                     if (tc_bitmap_pair(j[k], p)) bval[k] = TC_PLAN_BITS | (uint64_t)bitoff[i[k]];
