@@ -131,9 +131,9 @@ __host__ __device__ __forceinline__ bool plan_hub_b(int64_t p, int64_t lj, int64
 // twice as long: there a pair whose sides are closer streams L_j from row
 // i, at most p more ids, and spares the fill a cursor atomic and a
 // scattered write in B row j (at 2^20: 1.0 million of the 6.1 million such
-// pairs, 14.8 million more streamed ids, the whole count 1.5% faster; in
-// graphs of 2^16 vertices or fewer the extra ids cost more than the fill
-// saves).
+// pairs, 14 million more ids and bitmap words read, the whole count 1.5%
+// faster; in graphs of 2^16 vertices or fewer the extra ids cost more than
+// the fill saves).
 __host__ __device__ __forceinline__ bool plan_cold_b(int64_t p, int64_t lj, int64_t nhub)
 {
     return nhub > 0 ? lj > 2 * p : lj > p;
