@@ -470,9 +470,11 @@ def test_tc_and_bfs_autotune_keep_results():
         L.lagr_bfs_autotune(G, [], c)
     assert e.value.code == L.INVALID_VALUE
     assert G.tuning() == (hubs, a, b)
-    # set by hand: a new hub count drops the operand, which is rebuilt
-    G.set_tuning(c, 0, 32, -1)
-    assert G.tuning() == (0, 32, b) and G.tc_lower() is None
+    # set by hand: a new hub count (other than the tuner's choice) drops the
+    # operand, which is rebuilt
+    other = 0 if hubs != 0 else min(n >> 8, 4096)
+    G.set_tuning(c, other, 32, -1)
+    assert G.tuning() == (other, 32, b) and G.tc_lower() is None
     assert L.lagr_tc(G, c) == want
     lv, _ = bfs_host(G, srcs[0])
     assert np.array_equal(lv, oracle.bfs(rp, ci, srcs[0])[0].astype(np.int64))
